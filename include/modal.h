@@ -1,0 +1,239 @@
+/*
+ * modal.h - C ABI of the MI355X modal bispectrum library (libmodal.so).
+ *
+ * Computes the data-parallel hot path of the optimal modal bispectrum
+ * estimator of Fergusson & Shellard, "Optimal Polyspectra Estimation":
+ *
+ *   filtered maps   M_p(x)   = sum_lm q_p(l) a_lm / sqrt(C_l) Y_lm(x)
+ *   cubic modes     beta_prs = sum_x w(x) M_p M_r M_s              (p <= r <= s)
+ *   linear term     lin_prs  = sum_x w(x) [V_pr M_s + V_ps M_r + V_rs M_p],
+ *                   V_pr(x)  = Monte-Carlo mean of M_p M_r
+ *   covariance      zeta     = <beta^hat beta^hat^T> / 6,  beta^hat = beta - lin
+ *   estimator       E = alpha^T zeta^-1 beta^hat / alpha^T zeta^-1 alpha,
+ *                   sigma^2 = 6 / alpha^T zeta^-1 alpha
+ *
+ * The maps and beta follow eq. (bbispect) of Sec. III A with the separable
+ * isotropic basis R_n(l1,l2,l3) = q_p(l1) q_r(l2) q_s(l3) and v_l = 1; the
+ * linear term is the "3 C a" term of eq. (bispectrumest) with the pairing
+ * expectation taken from Monte-Carlo maps (Sec. II); zeta is eq. (linearterm);
+ * E and sigma^2 are eqs. (modalest) and (modalvariance) evaluated through the
+ * Cholesky rotation of eq. (Cholrot).
+ *
+ * Conventions
+ * -----------
+ * Grid        Gauss-Legendre rings, north to south (cos theta descending),
+ *             nphi equidistant pixels per ring starting at phi = 0; pixel
+ *             weight w(x) = w_GL(theta_j) * 2 pi / nphi * mask(x).
+ * a_lm        m-major triangle, index(l, m) = m (2 lmax + 3 - m) / 2 + (l - m),
+ *             0 <= m <= l <= lmax, complex interleaved (re, im).
+ *             complex128 when prec = MODAL_F64, complex64 otherwise.
+ *             Y_lm carries the Condon-Shortley phase; a_{l,-m} = (-1)^m a_lm^*.
+ * maps        [S][P][ntheta][nphi], float64 (MODAL_F64) or float32.
+ * modes       n = lexicographic index of (p <= r <= s); nmax = P(P+1)(P+2)/6.
+ * pairs       lexicographic index of (p <= r); npairs = P(P+1)/2.
+ * beta, lin,  always float64, row-major [S][nmax] / [nmax][nmax].
+ * zeta, alpha
+ * gradients   d/d a_lm packed as complex: (d/dRe a_lm) + i (d/dIm a_lm) for
+ *             m > 0 (a_{l,-m} follows from reality), d/d a_l0 (imag 0) for m = 0.
+ *
+ * Memory and streams
+ * ------------------
+ * Every pointer argument named *_dev or documented as "device" is device
+ * memory owned by the caller; *_host pointers are host memory.  The context
+ * owns only its constant tables (allocated in modal_create, freed in
+ * modal_destroy).  Every compute call takes a caller-owned device workspace
+ * of at least modal_workspace_size() bytes (256-byte aligned) and enqueues
+ * its work asynchronously on the given HIP stream (NULL = legacy default
+ * stream); none of them allocates device memory.  modal_create and
+ * modal_fnl synchronise (the latter returns host scalars).
+ *
+ * Errors
+ * ------
+ * No exception or abort crosses the ABI.  Every call returns a modal_status;
+ * modal_last_error() gives a message for the last failing call on a context.
+ * A context is not thread-safe; concurrent calls on one context must be
+ * serialised by the caller.
+ */
+#ifndef MODAL_H
+#define MODAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct modal_ctx modal_ctx;
+typedef void* modal_stream_t;   /* a hipStream_t */
+
+typedef enum {
+  MODAL_OK = 0,
+  MODAL_EINVAL = 1,        /* null pointer, non-positive size, bad enum           */
+  MODAL_ESHAPE = 2,        /* grid cannot represent lmax (ntheta <= lmax, nphi <= 2 lmax, odd nphi) */
+  MODAL_EDEVICE = 3,       /* a HIP call failed                                    */
+  MODAL_ENOTPD = 4,        /* Cholesky met a non-positive pivot (index in last_error) */
+  MODAL_ENOTREADY = 5,     /* linear-term state used before FINALIZE               */
+  MODAL_EUNSUPPORTED = 6,  /* precision / option not available                     */
+  MODAL_ENOSPACE = 7       /* workspace or state smaller than required             */
+} modal_status;
+
+typedef enum {
+  MODAL_F64 = 0,     /* FP64 everywhere                                          */
+  MODAL_F32 = 1,     /* FP32 maps, FP32 MFMA contractions, FP64 recurrence/reductions */
+  MODAL_BF16X3 = 2,  /* split bf16 hi+lo (3 MFMA products), FP32 accumulation    */
+  MODAL_F16X3 = 3    /* split fp16 hi+lo with per-mode scaling, FP32 accumulation */
+} modal_prec;
+
+typedef enum {
+  MODAL_OP_FILTER_MAPS = 0,
+  MODAL_OP_BETA = 1,
+  MODAL_OP_LINEAR_ACCUMULATE = 2,
+  MODAL_OP_LINEAR_APPLY = 3,
+  MODAL_OP_BETA_VJP = 4,
+  MODAL_OP_COVARIANCE_SAMPLE = 5,
+  MODAL_OP_COVARIANCE_FISHER = 6,
+  MODAL_OP_FNL = 7
+} modal_op;
+
+typedef enum {
+  MODAL_LIN_RESET = 0,       /* zero the accumulator and its count                   */
+  MODAL_LIN_ACCUMULATE = 1,  /* U_pr(x) += sum over the S maps of M_p M_r            */
+  MODAL_LIN_FINALIZE = 2,    /* V = U / count (in place); state becomes usable       */
+  MODAL_LIN_APPLY = 3        /* lin[S][nmax] for the given a_lm                      */
+} modal_lin_mode;
+
+typedef enum {
+  MODAL_COV_SAMPLE = 0,      /* zeta = (1/(6N)) sum beta^hat beta^hat^T              */
+  MODAL_COV_FISHER = 1       /* zeta = (1/(18N)) sum J C J^T, C = diag dof variance  */
+} modal_cov_method;
+
+typedef enum {
+  MODAL_STAGE_LEGENDRE = 0,   /* harmonic synthesis over l per m                    */
+  MODAL_STAGE_FFT = 1,        /* ring c2r FFT                                       */
+  MODAL_STAGE_CUBIC = 2,      /* pair x mode contraction over pixels                */
+  MODAL_STAGE_REDUCE = 3,     /* split-K reduction and symmetrisation               */
+  MODAL_STAGE_LINACC = 4,     /* linear-term accumulation                           */
+  MODAL_STAGE_ADJ_PAIR = 5,   /* adjoint pair contraction                           */
+  MODAL_STAGE_ADJ_FFT = 6,    /* ring r2c FFT                                       */
+  MODAL_STAGE_ADJ_LEGENDRE = 7, /* adjoint Legendre contraction (incl. lambda table) */
+  MODAL_STAGE_COVARIANCE = 8, /* SYRK / Fisher assembly                             */
+  MODAL_STAGE_CHOLESKY = 9,   /* factorisation, triangular solves, dots             */
+  MODAL_NSTAGES = 10
+} modal_stage;
+
+/* ------------------------------------------------------------------------ */
+/* context                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Create a context for one (grid, lmax, P, precision) on the current HIP
+ * device.  Host inputs are copied; the caller may free them afterwards.
+ *   q_host    [P][lmax+1]   separable mode functions q_p(l)
+ *   cl_host   [lmax+1]      filter spectrum C_l (a_lm are divided by sqrt(C_l);
+ *                           C_l <= 0 zeroes that l)
+ *   mask_host [ntheta][nphi] extra pixel weight multiplying the quadrature
+ *                           weight (a Galactic cut is 0/1); NULL = full sky
+ * Errors: EINVAL (null out/q/cl, lmax < 0, P < 1, bad prec), ESHAPE (ntheta
+ * <= lmax, nphi <= 2 lmax or nphi odd), EDEVICE.  On failure *out is NULL. */
+modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P, int prec,
+                          const double* q_host, const double* cl_host, const double* mask_host);
+void modal_destroy(modal_ctx* ctx);
+const char* modal_last_error(const modal_ctx* ctx);
+const char* modal_version(void);
+
+/* Shape queries (host, no device work). */
+int modal_nalm(const modal_ctx* ctx);
+int modal_nmax(const modal_ctx* ctx);
+int modal_npairs(const modal_ctx* ctx);
+
+/* Contraction kernel the context dispatches for the cubic reduction:
+ * 0 = vector-ALU with FP64 accumulation, 1 = FP32 MFMA, 2 = split-bf16 MFMA. */
+int modal_cubic_path(const modal_ctx* ctx);
+
+/* The context's quadrature: x_host[ntheta] = cos theta_j (descending),
+ * w_host[ntheta] = Gauss-Legendre weights (sum 2).  Either may be NULL. */
+modal_status modal_grid(const modal_ctx* ctx, double* x_host, double* w_host);
+
+/* Bytes of workspace an operation needs for S maps (N for covariance). */
+modal_status modal_workspace_size(const modal_ctx* ctx, int op, int S, size_t* bytes);
+/* Bytes of the linear-term state (pair accumulator, one plane per pair). */
+size_t modal_linear_state_size(const modal_ctx* ctx);
+
+/* ------------------------------------------------------------------------ */
+/* hot path                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Filtered maps M_p for S maps (Sec. III A, separable form of eq. bbispect).
+ *   alm_dev  [S][nalm] complex (see dtype above), device
+ *   maps_dev [S][P][ntheta][nphi] real, device
+ * Errors: EINVAL, ENOSPACE (ws_bytes too small), EDEVICE. */
+modal_status modal_filter_maps(modal_ctx* ctx, const void* alm_dev, int S, void* maps_dev,
+                               void* ws_dev, size_t ws_bytes, modal_stream_t stream);
+
+/* Monte-Carlo linear term (Sec. II: linear term from Gaussian simulations;
+ * eq. bispectrumest: the three pairings of "3 C a").
+ *   RESET      state is zeroed (alm may be NULL, S ignored)
+ *   ACCUMULATE U_pr += sum over S maps of M_p M_r
+ *   FINALIZE   V = U / total count; afterwards the state may be passed to
+ *              modal_beta / APPLY / modal_beta_vjp
+ *   APPLY      lin_dev [S][nmax] float64 = lin(a) for the S maps
+ * state_dev has modal_linear_state_size() bytes; the count lives in the
+ * context, so a state is tied to the context that built it.
+ * Errors: EINVAL, ENOTREADY (APPLY before FINALIZE, FINALIZE with count 0),
+ * ENOSPACE, EDEVICE. */
+modal_status modal_linear_term(modal_ctx* ctx, int mode, const void* alm_dev, int S, void* state_dev,
+                               double* lin_dev, void* ws_dev, size_t ws_bytes, modal_stream_t stream);
+
+/* beta^hat_n = beta_n - lin_n for S maps (eq. bbispect); state_dev NULL gives
+ * beta_n without the linear term.  beta_dev [S][nmax] float64.
+ * Errors: EINVAL, ENOTREADY (state not finalised), ENOSPACE, EDEVICE. */
+modal_status modal_beta(modal_ctx* ctx, const void* alm_dev, int S, const void* state_dev,
+                        double* beta_dev, void* ws_dev, size_t ws_bytes, modal_stream_t stream);
+
+/* Vector-Jacobian product: grad[s] = sum_n cot[s][n] d beta^hat_n / d a_lm
+ * (V held fixed), packed as documented above.
+ *   cot_dev [S][nmax] float64, grad_dev [S][nalm] complex (alm dtype).
+ * Errors: EINVAL, ENOTREADY, ENOSPACE, EDEVICE. */
+modal_status modal_beta_vjp(modal_ctx* ctx, const void* alm_dev, int S, const void* state_dev,
+                            const double* cot_dev, void* grad_dev, void* ws_dev, size_t ws_bytes,
+                            modal_stream_t stream);
+
+/* Modal covariance zeta [nmax][nmax] float64 (eq. linearterm).
+ *   SAMPLE: beta_dev [N][nmax] beta^hat vectors; zeta = sum b b^T / (6 N).
+ *   FISHER: alm_dev [N][nalm] maps, state_dev finalised, cvar_host [lmax+1]
+ *           the variance C_l of a_lm used as the metric (C_l for a_l0,
+ *           C_l / 2 for Re and Im of a_lm, m > 0);
+ *           zeta = sum_i J_i C J_i^T / (18 N), J = d beta^hat / d a.
+ * Errors: EINVAL, ENOTREADY, ENOSPACE, EDEVICE. */
+modal_status modal_covariance(modal_ctx* ctx, int method, const double* beta_dev, const void* alm_dev,
+                              const void* state_dev, const double* cvar_host, int N, double* zeta_dev,
+                              void* ws_dev, size_t ws_bytes, modal_stream_t stream);
+
+/* Estimator (eqs. Cholrot, modalest, modalvariance): factor zeta = L L^T in
+ * FP64, y = L^-1 alpha, z_s = L^-1 beta_s, E_s = y.z_s / y.y, sigma^2 = 6 / y.y.
+ *   zeta_dev [nmax][nmax] (read only), alpha_dev [nmax], beta_dev [S][nmax]
+ *   E_host [S], sigma2_host [1] (host); L_dev [nmax][nmax] or NULL (lower
+ *   triangle of L written row-major, upper triangle zeroed).
+ * Synchronises the stream.  Errors: EINVAL, ENOTPD (pivot index in
+ * last_error), ENOSPACE, EDEVICE. */
+modal_status modal_fnl(modal_ctx* ctx, const double* zeta_dev, const double* alpha_dev,
+                       const double* beta_dev, int S, double* E_host, double* sigma2_host,
+                       double* L_dev, void* ws_dev, size_t ws_bytes, modal_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* instrumentation                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Per-stage GPU timing: when enabled, every stage of every call is bracketed
+ * by HIP events recorded on the call's stream (a few microseconds per stage).
+ * modal_profile_read synchronises on the recorded events and returns, per
+ * stage, the summed elapsed milliseconds and the number of launches timed;
+ * reset != 0 clears the totals.  Arrays have MODAL_NSTAGES entries; either
+ * may be NULL.  Errors: EINVAL, EDEVICE. */
+modal_status modal_profile_enable(modal_ctx* ctx, int enable);
+modal_status modal_profile_read(modal_ctx* ctx, double* ms_host, long long* count_host, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MODAL_H */

@@ -1,0 +1,201 @@
+"""Thin torch-facing wrapper over the C ABI (include/modal.h).
+
+PyTorch provides device memory and the stream; every step of the computation
+runs in libmodal's HIP kernels.  Tensors passed in must live on the context's
+GPU; they are made contiguous and of the context's dtype here (marshalling
+only).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+class ModalContext:
+    """One (grid, lmax, P, precision) configuration on one GPU."""
+
+    def __init__(self, lmax: int, ntheta: int, nphi: int, P: int, prec: str, q, cl, mask=None,
+                 device: int | str | torch.device = 0):
+        self._lib = L.lib()
+        self.device = torch.device("cuda", torch.device(device).index if not isinstance(device, int) else device)
+        self.lmax, self.ntheta, self.nphi, self.P = lmax, ntheta, nphi, P
+        self.prec_name = prec
+        self.prec = L.PREC_NAMES[prec]
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        cl = np.ascontiguousarray(cl, dtype=np.float64)
+        if q.shape != (P, lmax + 1) or cl.shape != (lmax + 1,):
+            raise ValueError("q must be [P][lmax+1] and cl [lmax+1]")
+        mk = None
+        if mask is not None:
+            mk = np.ascontiguousarray(np.broadcast_to(np.asarray(mask, dtype=np.float64), (ntheta, nphi)))
+        self._h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            st = self._lib.modal_create(C.byref(self._h), lmax, ntheta, nphi, P, self.prec,
+                                        q.ctypes.data, cl.ctypes.data, None if mk is None else mk.ctypes.data)
+        if st != L.OK:
+            raise L.ModalError(st, "modal_create failed")
+        self.nalm = self._lib.modal_nalm(self._h)
+        self.nmax = self._lib.modal_nmax(self._h)
+        self.npairs = self._lib.modal_npairs(self._h)
+        self.real_dtype = torch.float64 if self.prec == L.F64 else torch.float32
+        self.complex_dtype = torch.complex128 if self.prec == L.F64 else torch.complex64
+        self._ws = None
+
+    # ------------------------------------------------------------------ utils
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.modal_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != L.OK:
+            raise L.ModalError(st, self._lib.modal_last_error(self._h).decode())
+
+    def _stream(self):
+        return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def workspace_size(self, op: int, S: int) -> int:
+        n = C.c_size_t()
+        self._check(self._lib.modal_workspace_size(self._h, op, S, C.byref(n)))
+        return int(n.value)
+
+    def workspace(self, op: int, S: int) -> torch.Tensor:
+        need = max(256, self.workspace_size(op, S))
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def grid(self):
+        x = np.empty(self.ntheta)
+        w = np.empty(self.ntheta)
+        self._check(self._lib.modal_grid(self._h, x.ctypes.data, w.ctypes.data))
+        return x, w
+
+    def profile(self, enable: bool = True):
+        self._check(self._lib.modal_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self, reset: bool = True) -> dict:
+        """Per-stage summed GPU milliseconds and launch counts since the last reset."""
+        ms = np.zeros(len(L.STAGES))
+        n = np.zeros(len(L.STAGES), dtype=np.int64)
+        self._check(self._lib.modal_profile_read(self._h, ms.ctypes.data, n.ctypes.data, 1 if reset else 0))
+        return {name: (float(ms[i]), int(n[i])) for i, name in enumerate(L.STAGES)}
+
+    def cubic_path(self) -> dict:
+        """Which contraction kernel the context uses ('valu' or 'mfma') and its
+        issued-work padding factor over the pair x mode product."""
+        code = int(self._lib.modal_cubic_path(self._h))
+        pad = 1.0
+        if code != 0:
+            tiles = -(-self.P // 16) * 16
+            pad = tiles / self.P
+        return {"path": "valu" if code == 0 else "mfma", "code": code, "pad": pad}
+
+    def _alm(self, alm) -> torch.Tensor:
+        a = torch.as_tensor(alm)
+        if a.dim() == 1:
+            a = a[None]
+        if a.shape[-1] != self.nalm:
+            raise ValueError(f"alm last dim {a.shape[-1]} != nalm {self.nalm}")
+        return a.to(device=self.device, dtype=self.complex_dtype).contiguous()
+
+    # --------------------------------------------------------------- hot path
+    def filter_maps(self, alm, out=None) -> torch.Tensor:
+        a = self._alm(alm)
+        S = a.shape[0]
+        if out is None:
+            out = torch.empty((S, self.P, self.ntheta, self.nphi), dtype=self.real_dtype, device=self.device)
+        ws = self.workspace(L.OP_FILTER_MAPS, S)
+        self._check(self._lib.modal_filter_maps(self._h, _ptr(a), S, _ptr(out), _ptr(ws), ws.numel(),
+                                                self._stream()))
+        return out
+
+    def beta(self, alm, state=None, out=None) -> torch.Tensor:
+        a = self._alm(alm)
+        S = a.shape[0]
+        if out is None:
+            out = torch.empty((S, self.nmax), dtype=torch.float64, device=self.device)
+        ws = self.workspace(L.OP_BETA, S)
+        self._check(self._lib.modal_beta(self._h, _ptr(a), S, _ptr(state), _ptr(out), _ptr(ws), ws.numel(),
+                                         self._stream()))
+        return out
+
+    def linear_state(self) -> torch.Tensor:
+        n = int(self._lib.modal_linear_state_size(self._h))
+        return torch.empty(n, dtype=torch.uint8, device=self.device)
+
+    def linear_reset(self, state):
+        self._check(self._lib.modal_linear_term(self._h, L.LIN_RESET, None, 0, _ptr(state), None, None, 0,
+                                                self._stream()))
+
+    def linear_accumulate(self, state, alm):
+        a = self._alm(alm)
+        S = a.shape[0]
+        ws = self.workspace(L.OP_LINEAR_ACCUMULATE, S)
+        self._check(self._lib.modal_linear_term(self._h, L.LIN_ACCUMULATE, _ptr(a), S, _ptr(state), None,
+                                                _ptr(ws), ws.numel(), self._stream()))
+
+    def linear_finalize(self, state):
+        self._check(self._lib.modal_linear_term(self._h, L.LIN_FINALIZE, None, 0, _ptr(state), None, None, 0,
+                                                self._stream()))
+
+    def linear_apply(self, state, alm) -> torch.Tensor:
+        a = self._alm(alm)
+        S = a.shape[0]
+        out = torch.empty((S, self.nmax), dtype=torch.float64, device=self.device)
+        ws = self.workspace(L.OP_LINEAR_APPLY, S)
+        self._check(self._lib.modal_linear_term(self._h, L.LIN_APPLY, _ptr(a), S, _ptr(state), _ptr(out),
+                                                _ptr(ws), ws.numel(), self._stream()))
+        return out
+
+    def pair_means(self, state) -> torch.Tensor:
+        """View of a finalised state as V[pair][ntheta][nphi]."""
+        n = self.npairs * self.ntheta * self.nphi
+        return state.view(self.real_dtype)[:n].view(self.npairs, self.ntheta, self.nphi)
+
+    def beta_vjp(self, alm, cot, state=None) -> torch.Tensor:
+        a = self._alm(alm)
+        S = a.shape[0]
+        c = torch.as_tensor(cot).to(device=self.device, dtype=torch.float64).reshape(S, self.nmax).contiguous()
+        g = torch.empty((S, self.nalm), dtype=self.complex_dtype, device=self.device)
+        ws = self.workspace(L.OP_BETA_VJP, S)
+        self._check(self._lib.modal_beta_vjp(self._h, _ptr(a), S, _ptr(state), _ptr(c), _ptr(g), _ptr(ws),
+                                             ws.numel(), self._stream()))
+        return g
+
+    def covariance_sample(self, beta) -> torch.Tensor:
+        b = torch.as_tensor(beta).to(device=self.device, dtype=torch.float64).contiguous()
+        N = b.shape[0]
+        z = torch.empty((self.nmax, self.nmax), dtype=torch.float64, device=self.device)
+        ws = self.workspace(L.OP_COVARIANCE_SAMPLE, N)
+        self._check(self._lib.modal_covariance(self._h, L.COV_SAMPLE, _ptr(b), None, None, None, N, _ptr(z),
+                                               _ptr(ws), ws.numel(), self._stream()))
+        return z
+
+    def fnl(self, zeta, alpha, beta, want_L: bool = False):
+        z = torch.as_tensor(zeta).to(device=self.device, dtype=torch.float64).contiguous()
+        al = torch.as_tensor(alpha).to(device=self.device, dtype=torch.float64).contiguous()
+        b = torch.as_tensor(beta).to(device=self.device, dtype=torch.float64).reshape(-1, self.nmax).contiguous()
+        S = b.shape[0]
+        E = np.zeros(S)
+        s2 = np.zeros(1)
+        Ld = torch.empty_like(z) if want_L else None
+        ws = self.workspace(L.OP_FNL, S)
+        self._check(self._lib.modal_fnl(self._h, _ptr(z), _ptr(al), _ptr(b), S, E.ctypes.data, s2.ctypes.data,
+                                        _ptr(Ld), _ptr(ws), ws.numel(), self._stream()))
+        return (E, float(s2[0]), Ld) if want_L else (E, float(s2[0]))

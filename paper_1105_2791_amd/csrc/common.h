@@ -1,0 +1,128 @@
+// Internal declarations shared by the host code and the HIP kernels of
+// libmodal.  Not part of the public ABI (include/modal.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/modal.h"
+
+namespace modal {
+
+constexpr int kMaxP = 64;          // largest number of mode functions supported
+constexpr int kMaxFactors = 16;    // FFT radix plan length
+constexpr double kLogSeedFloor = -62.383246250395075;  // ln(2^-90): smaller lambda are dropped
+
+struct FftPlan {
+  int N;                 // ring length nphi (even)
+  int K;                 // N / 2, length of the complex transform
+  int nf;                // number of radix stages
+  int radix[kMaxFactors];
+};
+
+// Device tables owned by a context (all allocated in modal_create).
+struct Tables {
+  double* x = nullptr;         // [ntheta] cos theta_j, north to south
+  double* ringw = nullptr;     // [ntheta] w_GL(theta_j) * 2 pi / nphi
+  double* w64 = nullptr;       // [ntheta*nphi] pixel weights (ringw * mask)
+  float* w32 = nullptr;        // same, float
+  double* rec = nullptr;       // [nalm][2] recurrence coefficients (A_lm, B_lm)
+  double* seed = nullptr;      // [lmax+1][nrp][2] lambda at l_start and l_start + 1
+  int* lstart = nullptr;       // [lmax+1][nrp] first significant l per (m, ring)
+  int* lstart_blk = nullptr;   // [lmax+1][nrp/64 rounded up] block minimum of lstart
+  double* qw64 = nullptr;      // [P][lmax+1] q_p(l) / sqrt(C_l)
+  float* qw32 = nullptr;
+  double* tw64 = nullptr;      // [nphi][2] exp(2 pi i t / nphi)
+  float* tw32 = nullptr;
+  int* pair_a = nullptr;       // [npairs] first mode of each pair
+  int* pair_b = nullptr;       // [npairs] second mode
+  int* tri = nullptr;          // [nmax][6] p, r, s, pair(pr), pair(ps), pair(rs)
+  int* pair_of = nullptr;      // [P][P] pair index of (min, max)
+  int* tri_of = nullptr;       // [P][npairs] triple index of sort(u, a, b)
+  int* tri_mult = nullptr;     // [P][npairs] multiplicity of u in that triple
+  int* flag = nullptr;         // [4] device status words (Cholesky pivot)
+  int2* blk = nullptr;         // [nblk] (a0, b0) of the 2 x 4 pair blocks of the MFMA contraction
+  int nblk = 0;
+};
+
+}  // namespace modal
+
+struct modal_ctx {
+  int lmax = 0, ntheta = 0, nphi = 0, P = 0, prec = 0;
+  int nalm = 0, npairs = 0, nmax = 0, nrp = 0, npix = 0;
+  int device = 0;
+  size_t max_lds = 65536;
+  modal::FftPlan fft{};
+  modal::Tables t{};
+  std::vector<double> x_host, wgl_host;
+  std::string last_error;
+  // per-stage timing (modal_profile_enable)
+  bool profile = false;
+  struct Mark { int stage; hipEvent_t a, b; };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> event_pool;
+  double stage_ms[MODAL_NSTAGES] = {};
+  long long stage_n[MODAL_NSTAGES] = {};
+  // linear-term state bookkeeping (the device state holds the pair planes)
+  const void* lin_state = nullptr;
+  long long lin_count = 0;
+  bool lin_final = false;
+};
+
+namespace modal {
+
+// ---- launchers (defined in the .hip files); all return hipSuccess or the error
+hipError_t launch_seeds(const modal_ctx* c, const double* logpref, hipStream_t st);
+
+// Legendre synthesis: F[S][P][ntheta][lmax+1] complex (double2 for F64, float2 otherwise)
+hipError_t launch_legendre(const modal_ctx* c, const void* alm, int S, void* F, hipStream_t st);
+// ring c2r FFT: maps[S][P][ntheta][nphi] from F
+hipError_t launch_fft_c2r(const modal_ctx* c, const void* F, int S, void* maps, hipStream_t st);
+// ring r2c FFT: Gh[S][P][ntheta][lmax+1] complex from G[S][P][ntheta][nphi]
+hipError_t launch_fft_r2c(const modal_ctx* c, const void* G, int S, void* Gh, hipStream_t st);
+
+// cubic pixel reduction.  mode: 0 = A = M_p M_r, 1 = M_p M_r - 3 V, 2 = A = V
+// partials[S][nchunk][npairs][P] float64
+int cubic_nchunk(const modal_ctx* c);
+hipError_t launch_cubic(const modal_ctx* c, const void* maps, const void* V, int S, int mode,
+                        double* partials, hipStream_t st);
+// sum chunk partials and symmetrise into out[S][nmax]; scale multiplies the
+// three-pairing sum (1/3 for beta, 1 for the linear term alone)
+hipError_t launch_reduce_symm(const modal_ctx* c, const double* partials, int S, int nchunk, double scale,
+                              double* E, double* out, hipStream_t st);
+void make_pair_blocks(int P, std::vector<int2>& out);
+
+// linear term accumulator
+hipError_t launch_lin_accumulate(const modal_ctx* c, const void* maps, int S, void* U, hipStream_t st);
+hipError_t launch_lin_scale(const modal_ctx* c, void* U, double s, hipStream_t st);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+
+// adjoint
+hipError_t launch_slot_matrix(const modal_ctx* c, const double* cot, int S, void* K, hipStream_t st);
+hipError_t launch_pair_adjoint(const modal_ctx* c, const void* maps, const void* V, const void* K, int S,
+                               void* G, hipStream_t st);
+hipError_t launch_lambda_table(const modal_ctx* c, void* lam, hipStream_t st);
+hipError_t launch_adj_legendre(const modal_ctx* c, const void* lam, const void* Gh, int S, void* grad,
+                               hipStream_t st);
+
+// FP64 dense linear algebra
+hipError_t launch_syrk(int n, int N, const double* B, double scale, double* Z, hipStream_t st);
+hipError_t launch_fisher_accumulate(const modal_ctx* c, const void* grads, const double* cvar, int nrow,
+                                    double scale, double* Z, hipStream_t st);
+hipError_t launch_copy_lower(int n, const double* src, double* dst, hipStream_t st);
+// in-place Cholesky of the lower triangle of A (row-major, n x n); flag[0] = 1 + first bad pivot
+hipError_t launch_cholesky(int n, double* A, int* flag, hipStream_t st);
+// solve L Y = B in place for nrhs right-hand sides stored as rows of B [nrhs][n]
+hipError_t launch_trsm_rows(int n, const double* L, int nrhs, double* B, hipStream_t st);
+hipError_t launch_estimator(int n, const double* y, const double* Z, int S, double* out, hipStream_t st);
+
+// helpers
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+inline bool is_f64(const modal_ctx* c) { return c->prec == MODAL_F64; }
+inline size_t real_bytes(const modal_ctx* c) { return is_f64(c) ? 8 : 4; }
+
+}  // namespace modal

@@ -1,0 +1,608 @@
+// Host side of libmodal: context construction (FP64 tables), validation,
+// workspace carving and the extern "C" entry points declared in include/modal.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace modal {
+hipError_t launch_cubic_valu(const modal_ctx* c, const void* maps, const void* V, int S, int mode, double* part,
+                             hipStream_t st);
+hipError_t launch_cubic_mfma(const modal_ctx* c, const void* maps, const void* V, int S, int mode, double* part,
+                             hipStream_t st);
+bool cubic_mfma_available(const modal_ctx* c);
+int cubic_mfma_nchunk(const modal_ctx* c);
+hipError_t fft_set_lds_limit(size_t bytes);
+}  // namespace modal
+
+using namespace modal;
+
+namespace {
+
+const double kPi = 3.14159265358979323846;
+
+// Gauss-Legendre nodes (descending) and weights by Newton iteration on P_n.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    double pp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p1 = 1.0, p2 = 0.0;
+      for (int j = 1; j <= n; ++j) {
+        const double p3 = p2;
+        p2 = p1;
+        p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+      }
+      pp = n * (z * p1 - p2) / (z * z - 1.0);
+      const double z1 = z;
+      z = z1 - p1 / pp;
+      if (std::fabs(z - z1) < 1e-16) {
+        // one more evaluation of the derivative at the converged node
+        p1 = 1.0;
+        p2 = 0.0;
+        for (int j = 1; j <= n; ++j) {
+          const double p3 = p2;
+          p2 = p1;
+          p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+        }
+        pp = n * (z * p1 - p2) / (z * z - 1.0);
+        break;
+      }
+    }
+    x[i] = z;
+    x[n - 1 - i] = -z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * pp * pp);
+  }
+  if (n & 1) x[n / 2] = 0.0;
+}
+
+bool fft_plan(int N, FftPlan& p) {
+  p.N = N;
+  p.K = N / 2;
+  p.nf = 0;
+  int K = p.K;
+  auto push = [&](int r) {
+    if (p.nf >= kMaxFactors) return false;
+    p.radix[p.nf++] = r;
+    return true;
+  };
+  while (K % 4 == 0) { if (!push(4)) return false; K /= 4; }
+  while (K % 2 == 0) { if (!push(2)) return false; K /= 2; }
+  for (int r = 3; K > 1; r += 2) {
+    while (K % r == 0) { if (!push(r)) return false; K /= r; }
+    if (r > 4096) return false;
+  }
+  return true;
+}
+
+struct Carver {
+  char* base;
+  size_t used = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  void* take(size_t bytes) {
+    void* p = base ? base + used : nullptr;
+    used += align256(bytes);
+    return p;
+  }
+};
+
+modal_status fail(modal_ctx* c, modal_status s, const std::string& msg) {
+  if (c) c->last_error = msg;
+  return s;
+}
+
+#define HIPTRY(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess)                                                                    \
+      return fail(c, MODAL_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));      \
+  } while (0)
+
+template <typename V>
+hipError_t upload(V** dst, const std::vector<V>& src) {
+  hipError_t e = hipMalloc((void**)dst, std::max<size_t>(1, src.size()) * sizeof(V));
+  if (e != hipSuccess) return e;
+  if (src.empty()) return hipSuccess;
+  return hipMemcpy(*dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice);
+}
+
+size_t alm_bytes(const modal_ctx* c) { return (size_t)c->nalm * 2 * real_bytes(c); }
+size_t F_bytes(const modal_ctx* c, int S) { return (size_t)S * c->P * c->ntheta * (c->lmax + 1) * 2 * real_bytes(c); }
+size_t maps_bytes(const modal_ctx* c, int S) { return (size_t)S * c->P * c->npix * real_bytes(c); }
+int nchunk_for(const modal_ctx* c) { return cubic_mfma_available(c) ? cubic_mfma_nchunk(c) : cubic_nchunk(c); }
+size_t part_bytes(const modal_ctx* c, int S) { return (size_t)S * nchunk_for(c) * c->npairs * c->P * 8; }
+size_t E_bytes(const modal_ctx* c, int S) { return (size_t)S * c->npairs * c->P * 8; }
+size_t lam_bytes(const modal_ctx* c) { return (size_t)c->nalm * c->nrp * real_bytes(c); }
+
+size_t ws_size(const modal_ctx* c, int op, int S) {
+  Carver cv(nullptr);
+  switch (op) {
+    case MODAL_OP_FILTER_MAPS: cv.take(F_bytes(c, S)); break;
+    case MODAL_OP_BETA:
+    case MODAL_OP_LINEAR_APPLY:
+      cv.take(F_bytes(c, S)); cv.take(maps_bytes(c, S)); cv.take(part_bytes(c, S)); cv.take(E_bytes(c, S));
+      break;
+    case MODAL_OP_LINEAR_ACCUMULATE: cv.take(F_bytes(c, S)); cv.take(maps_bytes(c, S)); break;
+    case MODAL_OP_BETA_VJP:
+      cv.take(F_bytes(c, S)); cv.take(maps_bytes(c, S)); cv.take((size_t)S * c->P * c->npairs * 8);
+      cv.take(maps_bytes(c, S)); cv.take(F_bytes(c, S)); cv.take(lam_bytes(c));
+      break;
+    case MODAL_OP_COVARIANCE_SAMPLE: cv.take(256); break;
+    case MODAL_OP_FNL:
+      cv.take((size_t)c->nmax * c->nmax * 8); cv.take((size_t)(S + 1) * c->nmax * 8); cv.take((size_t)(S + 1) * 8);
+      cv.take(16);
+      break;
+    default: return 0;
+  }
+  return cv.used;
+}
+
+modal_status check_ws(modal_ctx* c, int op, int S, void* ws, size_t ws_bytes) {
+  const size_t need = ws_size(c, op, S);
+  if (need > 0 && !ws) return fail(c, MODAL_EINVAL, "workspace pointer is NULL");
+  if (ws_bytes < need)
+    return fail(c, MODAL_ENOSPACE, "workspace too small: need " + std::to_string(need) + " bytes, got " +
+                                       std::to_string(ws_bytes));
+  return MODAL_OK;
+}
+
+modal_status set_device(modal_ctx* c) {
+  int cur = -1;
+  HIPTRY(hipGetDevice(&cur));
+  if (cur != c->device) HIPTRY(hipSetDevice(c->device));
+  return MODAL_OK;
+}
+
+// Brackets one stage with HIP events when profiling is enabled.
+struct StageTimer {
+  modal_ctx* c;
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  static hipEvent_t get(modal_ctx* c) {
+    if (!c->event_pool.empty()) {
+      hipEvent_t e = c->event_pool.back();
+      c->event_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  StageTimer(modal_ctx* c_, int stage_, hipStream_t st_) : c(c_), stage(stage_), st(st_) {
+    if (!c->profile) return;
+    a = get(c);
+    if (a && hipEventRecord(a, st) != hipSuccess) {
+      c->event_pool.push_back(a);
+      a = nullptr;
+    }
+  }
+  ~StageTimer() {
+    if (!a) return;
+    hipEvent_t b = get(c);
+    if (b && hipEventRecord(b, st) == hipSuccess) {
+      c->marks.push_back({stage, a, b});
+    } else {
+      c->event_pool.push_back(a);
+      if (b) c->event_pool.push_back(b);
+    }
+  }
+};
+
+#define STAGE(id, expr)                      \
+  do {                                       \
+    StageTimer _t(c, (id), st);              \
+    HIPTRY(expr);                            \
+  } while (0)
+
+// Filter maps for S maps into 'maps' using F as scratch.
+modal_status run_maps(modal_ctx* c, const void* alm, int S, void* F, void* maps, hipStream_t st) {
+  STAGE(MODAL_STAGE_LEGENDRE, launch_legendre(c, alm, S, F, st));
+  STAGE(MODAL_STAGE_FFT, launch_fft_c2r(c, F, S, maps, st));
+  return MODAL_OK;
+}
+
+modal_status run_cubic(modal_ctx* c, const void* maps, const void* V, int S, int mode, double* part, double* E,
+                       double scale, double* out, hipStream_t st) {
+  if (cubic_mfma_available(c)) STAGE(MODAL_STAGE_CUBIC, launch_cubic_mfma(c, maps, V, S, mode, part, st));
+  else STAGE(MODAL_STAGE_CUBIC, launch_cubic_valu(c, maps, V, S, mode, part, st));
+  STAGE(MODAL_STAGE_REDUCE, launch_reduce_symm(c, part, S, nchunk_for(c), scale, E, out, st));
+  return MODAL_OK;
+}
+
+modal_status check_state(modal_ctx* c, const void* state) {
+  if (state && (state != c->lin_state || !c->lin_final))
+    return fail(c, MODAL_ENOTREADY, "linear-term state not finalised on this context");
+  return MODAL_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* modal_version(void) { return "libmodal 0.1 (gfx950)"; }
+
+modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P, int prec, const double* q_host,
+                          const double* cl_host, const double* mask_host) {
+  if (!out) return MODAL_EINVAL;
+  *out = nullptr;
+  if (!q_host || !cl_host || lmax < 0 || P < 1 || P > kMaxP || prec < MODAL_F64 || prec > MODAL_F16X3)
+    return MODAL_EINVAL;
+  if (ntheta <= lmax || nphi <= 2 * lmax || (nphi & 1) || ntheta < 1) return MODAL_ESHAPE;
+  if (prec == MODAL_F16X3) return MODAL_EUNSUPPORTED;
+  modal_ctx* c = new (std::nothrow) modal_ctx();
+  if (!c) return MODAL_EDEVICE;
+  c->lmax = lmax;
+  c->ntheta = ntheta;
+  c->nphi = nphi;
+  c->P = P;
+  c->prec = prec;
+  c->nalm = (lmax + 1) * (lmax + 2) / 2;
+  c->npairs = P * (P + 1) / 2;
+  c->nmax = P * (P + 1) * (P + 2) / 6;
+  c->nrp = (ntheta + 1) / 2;
+  c->npix = ntheta * nphi;
+  auto bail = [&](modal_status s) {
+    modal_destroy(c);
+    return s;
+  };
+  if (prec == MODAL_BF16X3 && !cubic_mfma_available(c)) return bail(MODAL_EUNSUPPORTED);
+  if (hipGetDevice(&c->device) != hipSuccess) return bail(MODAL_EDEVICE);
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess && lds > 0)
+    c->max_lds = (size_t)lds;
+  if (!fft_plan(nphi, c->fft)) return bail(MODAL_ESHAPE);
+  const size_t fft_lds = 2 * (size_t)c->fft.K * 2 * real_bytes(c);
+  if (fft_lds > c->max_lds) return bail(MODAL_EUNSUPPORTED);
+  if (fft_lds > 65536 && fft_set_lds_limit(fft_lds) != hipSuccess) return bail(MODAL_EDEVICE);
+
+  // --- grid
+  gauss_legendre(ntheta, c->x_host, c->wgl_host);
+  std::vector<double> ringw(ntheta), w64((size_t)ntheta * nphi);
+  std::vector<float> w32((size_t)ntheta * nphi);
+  for (int j = 0; j < ntheta; ++j) {
+    ringw[j] = c->wgl_host[j] * 2.0 * kPi / nphi;
+    for (int k = 0; k < nphi; ++k) {
+      const size_t i = (size_t)j * nphi + k;
+      w64[i] = ringw[j] * (mask_host ? mask_host[i] : 1.0);
+      w32[i] = (float)w64[i];
+    }
+  }
+  // --- recurrence coefficients and seed prefactors
+  std::vector<double> rec(2 * (size_t)c->nalm, 0.0), logpref(lmax + 1);
+  double cum = 0.0;
+  for (int m = 0; m <= lmax; ++m) {
+    if (m > 0) cum += std::log((2.0 * m - 1.0) / (2.0 * m));
+    logpref[m] = 0.5 * (std::log((2.0 * m + 1.0) / (4.0 * kPi)) + cum);
+    const size_t off = (size_t)m * (2 * lmax + 3 - m) / 2;
+    for (int l = m + 1; l <= lmax; ++l) {
+      double A, B;
+      if (l == m + 1) {
+        A = std::sqrt(2.0 * m + 3.0);
+        B = 0.0;
+      } else {
+        const double ll = l, mm = m;
+        A = std::sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mm * mm));
+        B = A * std::sqrt(((ll - 1.0) * (ll - 1.0) - mm * mm) / (4.0 * (ll - 1.0) * (ll - 1.0) - 1.0));
+      }
+      rec[2 * (off + (l - m))] = A;
+      rec[2 * (off + (l - m)) + 1] = B;
+    }
+  }
+  // --- whitened mode functions
+  std::vector<double> qw64((size_t)P * (lmax + 1));
+  std::vector<float> qw32(qw64.size());
+  for (int p = 0; p < P; ++p)
+    for (int l = 0; l <= lmax; ++l) {
+      const double cl = cl_host[l];
+      const double v = cl > 0.0 ? q_host[(size_t)p * (lmax + 1) + l] / std::sqrt(cl) : 0.0;
+      qw64[(size_t)p * (lmax + 1) + l] = v;
+      qw32[(size_t)p * (lmax + 1) + l] = (float)v;
+    }
+  // --- twiddles
+  std::vector<double> tw64(2 * (size_t)nphi);
+  std::vector<float> tw32(2 * (size_t)nphi);
+  for (int t = 0; t < nphi; ++t) {
+    const double a = 2.0 * kPi * (double)t / (double)nphi;
+    tw64[2 * t] = std::cos(a);
+    tw64[2 * t + 1] = std::sin(a);
+    tw32[2 * t] = (float)tw64[2 * t];
+    tw32[2 * t + 1] = (float)tw64[2 * t + 1];
+  }
+  // --- pair / triple index tables
+  std::vector<int> pa, pb, pair_of((size_t)P * P, -1), tri, tri_of((size_t)P * c->npairs), tri_mult((size_t)P * c->npairs);
+  for (int p = 0; p < P; ++p)
+    for (int r = p; r < P; ++r) {
+      pair_of[(size_t)p * P + r] = pair_of[(size_t)r * P + p] = (int)pa.size();
+      pa.push_back(p);
+      pb.push_back(r);
+    }
+  std::vector<int> tri_index((size_t)P * P * P, -1);
+  for (int p = 0; p < P; ++p)
+    for (int r = p; r < P; ++r)
+      for (int s = r; s < P; ++s) {
+        tri_index[((size_t)p * P + r) * P + s] = (int)(tri.size() / 6);
+        tri.insert(tri.end(), {p, r, s, pair_of[(size_t)p * P + r], pair_of[(size_t)p * P + s], pair_of[(size_t)r * P + s]});
+      }
+  for (int u = 0; u < P; ++u)
+    for (int k = 0; k < c->npairs; ++k) {
+      int v[3] = {u, pa[k], pb[k]};
+      std::sort(v, v + 3);
+      tri_of[(size_t)u * c->npairs + k] = tri_index[((size_t)v[0] * P + v[1]) * P + v[2]];
+      tri_mult[(size_t)u * c->npairs + k] = (v[0] == u) + (v[1] == u) + (v[2] == u);
+    }
+
+  Tables& t = c->t;
+  std::vector<int2> blocks;
+  make_pair_blocks(P, blocks);
+  t.nblk = (int)blocks.size();
+  if (upload(&t.blk, blocks) != hipSuccess) return bail(MODAL_EDEVICE);
+  std::vector<double> xs(c->x_host);
+  if (upload(&t.x, xs) != hipSuccess || upload(&t.ringw, ringw) != hipSuccess || upload(&t.w64, w64) != hipSuccess ||
+      upload(&t.w32, w32) != hipSuccess || upload(&t.rec, rec) != hipSuccess || upload(&t.qw64, qw64) != hipSuccess ||
+      upload(&t.qw32, qw32) != hipSuccess || upload(&t.tw64, tw64) != hipSuccess ||
+      upload(&t.tw32, tw32) != hipSuccess || upload(&t.pair_a, pa) != hipSuccess ||
+      upload(&t.pair_b, pb) != hipSuccess || upload(&t.tri, tri) != hipSuccess ||
+      upload(&t.pair_of, pair_of) != hipSuccess || upload(&t.tri_of, tri_of) != hipSuccess ||
+      upload(&t.tri_mult, tri_mult) != hipSuccess)
+    return bail(MODAL_EDEVICE);
+  if (hipMalloc((void**)&t.seed, 2 * sizeof(double) * (lmax + 1) * (size_t)c->nrp) != hipSuccess ||
+      hipMalloc((void**)&t.lstart, sizeof(int) * (lmax + 1) * (size_t)c->nrp) != hipSuccess ||
+      hipMalloc((void**)&t.flag, 4 * sizeof(int)) != hipSuccess)
+    return bail(MODAL_EDEVICE);
+  double* d_logpref = nullptr;
+  if (upload(&d_logpref, logpref) != hipSuccess) return bail(MODAL_EDEVICE);
+  hipError_t e = launch_seeds(c, d_logpref, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  (void)hipFree(d_logpref);
+  if (e != hipSuccess) return bail(MODAL_EDEVICE);
+  *out = c;
+  return MODAL_OK;
+}
+
+void modal_destroy(modal_ctx* c) {
+  if (!c) return;
+  for (auto& mk : c->marks) {
+    (void)hipEventDestroy(mk.a);
+    (void)hipEventDestroy(mk.b);
+  }
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  Tables& t = c->t;
+  void* ptrs[] = {t.x, t.ringw, t.w64, t.w32, t.rec, t.seed, t.lstart, t.lstart_blk, t.qw64, t.qw32, t.tw64, t.tw32,
+                  t.pair_a, t.pair_b, t.tri, t.pair_of, t.tri_of, t.tri_mult, t.flag, t.blk};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete c;
+}
+
+const char* modal_last_error(const modal_ctx* c) { return c ? c->last_error.c_str() : "null context"; }
+int modal_nalm(const modal_ctx* c) { return c ? c->nalm : -1; }
+int modal_nmax(const modal_ctx* c) { return c ? c->nmax : -1; }
+int modal_npairs(const modal_ctx* c) { return c ? c->npairs : -1; }
+int modal_cubic_path(const modal_ctx* c) {
+  if (!c) return -1;
+  if (!cubic_mfma_available(c)) return 0;
+  return c->prec == MODAL_BF16X3 ? 2 : 1;
+}
+
+modal_status modal_grid(const modal_ctx* c, double* x_host, double* w_host) {
+  if (!c) return MODAL_EINVAL;
+  if (x_host) std::memcpy(x_host, c->x_host.data(), sizeof(double) * c->ntheta);
+  if (w_host) std::memcpy(w_host, c->wgl_host.data(), sizeof(double) * c->ntheta);
+  return MODAL_OK;
+}
+
+modal_status modal_workspace_size(const modal_ctx* c, int op, int S, size_t* bytes) {
+  if (!c || !bytes || S < 0 || op < MODAL_OP_FILTER_MAPS || op > MODAL_OP_FNL) return MODAL_EINVAL;
+  if (op == MODAL_OP_COVARIANCE_FISHER) return MODAL_EUNSUPPORTED;
+  *bytes = ws_size(c, op, S);
+  return MODAL_OK;
+}
+
+size_t modal_linear_state_size(const modal_ctx* c) { return c ? align256((size_t)c->npairs * c->npix * real_bytes(c)) : 0; }
+
+modal_status modal_filter_maps(modal_ctx* c, const void* alm, int S, void* maps, void* ws, size_t ws_bytes,
+                               modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (!alm || !maps || S <= 0) return fail(c, MODAL_EINVAL, "filter_maps: null pointer or S <= 0");
+  modal_status s = check_ws(c, MODAL_OP_FILTER_MAPS, S, ws, ws_bytes);
+  if (s != MODAL_OK) return s;
+  if ((s = set_device(c)) != MODAL_OK) return s;
+  Carver cv(ws);
+  void* F = cv.take(F_bytes(c, S));
+  return run_maps(c, alm, S, F, maps, (hipStream_t)stream);
+}
+
+modal_status modal_beta(modal_ctx* c, const void* alm, int S, const void* state, double* beta, void* ws,
+                        size_t ws_bytes, modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (!alm || !beta || S <= 0) return fail(c, MODAL_EINVAL, "beta: null pointer or S <= 0");
+  modal_status s = check_state(c, state);
+  if (s != MODAL_OK) return s;
+  if ((s = check_ws(c, MODAL_OP_BETA, S, ws, ws_bytes)) != MODAL_OK) return s;
+  if ((s = set_device(c)) != MODAL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  Carver cv(ws);
+  void* F = cv.take(F_bytes(c, S));
+  void* maps = cv.take(maps_bytes(c, S));
+  double* part = (double*)cv.take(part_bytes(c, S));
+  double* E = (double*)cv.take(E_bytes(c, S));
+  if ((s = run_maps(c, alm, S, F, maps, st)) != MODAL_OK) return s;
+  return run_cubic(c, maps, state, S, state ? 1 : 0, part, E, 1.0 / 3.0, beta, st);
+}
+
+modal_status modal_linear_term(modal_ctx* c, int mode, const void* alm, int S, void* state, double* lin, void* ws,
+                               size_t ws_bytes, modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (!state) return fail(c, MODAL_EINVAL, "linear_term: null state");
+  modal_status s = set_device(c);
+  if (s != MODAL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  switch (mode) {
+    case MODAL_LIN_RESET:
+      HIPTRY(launch_zero(state, modal_linear_state_size(c), st));
+      c->lin_state = state;
+      c->lin_count = 0;
+      c->lin_final = false;
+      return MODAL_OK;
+    case MODAL_LIN_ACCUMULATE: {
+      if (!alm || S <= 0) return fail(c, MODAL_EINVAL, "linear_term: null alm or S <= 0");
+      if (state != c->lin_state || c->lin_final)
+        return fail(c, MODAL_ENOTREADY, "linear_term: ACCUMULATE needs a state RESET on this context and not finalised");
+      if ((s = check_ws(c, MODAL_OP_LINEAR_ACCUMULATE, S, ws, ws_bytes)) != MODAL_OK) return s;
+      Carver cv(ws);
+      void* F = cv.take(F_bytes(c, S));
+      void* maps = cv.take(maps_bytes(c, S));
+      if ((s = run_maps(c, alm, S, F, maps, st)) != MODAL_OK) return s;
+      STAGE(MODAL_STAGE_LINACC, launch_lin_accumulate(c, maps, S, state, st));
+      c->lin_count += S;
+      return MODAL_OK;
+    }
+    case MODAL_LIN_FINALIZE:
+      if (state != c->lin_state || c->lin_final || c->lin_count <= 0)
+        return fail(c, MODAL_ENOTREADY, "linear_term: FINALIZE needs an accumulated, unfinalised state");
+      HIPTRY(launch_lin_scale(c, state, 1.0 / (double)c->lin_count, st));
+      c->lin_final = true;
+      return MODAL_OK;
+    case MODAL_LIN_APPLY: {
+      if (!alm || !lin || S <= 0) return fail(c, MODAL_EINVAL, "linear_term: APPLY needs alm, lin and S > 0");
+      if ((s = check_state(c, state)) != MODAL_OK) return s;
+      if ((s = check_ws(c, MODAL_OP_LINEAR_APPLY, S, ws, ws_bytes)) != MODAL_OK) return s;
+      Carver cv(ws);
+      void* F = cv.take(F_bytes(c, S));
+      void* maps = cv.take(maps_bytes(c, S));
+      double* part = (double*)cv.take(part_bytes(c, S));
+      double* E = (double*)cv.take(E_bytes(c, S));
+      if ((s = run_maps(c, alm, S, F, maps, st)) != MODAL_OK) return s;
+      return run_cubic(c, maps, state, S, 2, part, E, 1.0, lin, st);
+    }
+    default:
+      return fail(c, MODAL_EINVAL, "linear_term: bad mode");
+  }
+}
+
+modal_status modal_beta_vjp(modal_ctx* c, const void* alm, int S, const void* state, const double* cot, void* grad,
+                            void* ws, size_t ws_bytes, modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (!alm || !cot || !grad || S <= 0) return fail(c, MODAL_EINVAL, "beta_vjp: null pointer or S <= 0");
+  modal_status s = check_state(c, state);
+  if (s != MODAL_OK) return s;
+  if ((s = check_ws(c, MODAL_OP_BETA_VJP, S, ws, ws_bytes)) != MODAL_OK) return s;
+  if ((s = set_device(c)) != MODAL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  Carver cv(ws);
+  void* F = cv.take(F_bytes(c, S));
+  void* maps = cv.take(maps_bytes(c, S));
+  void* K = cv.take((size_t)S * c->P * c->npairs * 8);
+  void* G = cv.take(maps_bytes(c, S));
+  void* Gh = cv.take(F_bytes(c, S));
+  void* lam = cv.take(lam_bytes(c));
+  if ((s = run_maps(c, alm, S, F, maps, st)) != MODAL_OK) return s;
+  STAGE(MODAL_STAGE_ADJ_PAIR, launch_slot_matrix(c, cot, S, K, st));
+  STAGE(MODAL_STAGE_ADJ_PAIR, launch_pair_adjoint(c, maps, state, K, S, G, st));
+  STAGE(MODAL_STAGE_ADJ_FFT, launch_fft_r2c(c, G, S, Gh, st));
+  STAGE(MODAL_STAGE_ADJ_LEGENDRE, launch_lambda_table(c, lam, st));
+  STAGE(MODAL_STAGE_ADJ_LEGENDRE, launch_adj_legendre(c, lam, Gh, S, grad, st));
+  return MODAL_OK;
+}
+
+modal_status modal_covariance(modal_ctx* c, int method, const double* beta, const void* alm, const void* state,
+                              const double* cvar_host, int N, double* zeta, void* ws, size_t ws_bytes,
+                              modal_stream_t stream) {
+  (void)alm;
+  (void)state;
+  (void)cvar_host;
+  if (!c) return MODAL_EINVAL;
+  if (!zeta || N <= 0) return fail(c, MODAL_EINVAL, "covariance: null zeta or N <= 0");
+  modal_status s = set_device(c);
+  if (s != MODAL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  if (method == MODAL_COV_SAMPLE) {
+    if (!beta) return fail(c, MODAL_EINVAL, "covariance: SAMPLE needs beta");
+    STAGE(MODAL_STAGE_COVARIANCE, launch_syrk(c->nmax, N, beta, 1.0 / (6.0 * N), zeta, st));
+    return MODAL_OK;
+  }
+  if (method == MODAL_COV_FISHER) return fail(c, MODAL_EUNSUPPORTED, "covariance: FISHER not available");
+  return fail(c, MODAL_EINVAL, "covariance: bad method");
+}
+
+modal_status modal_fnl(modal_ctx* c, const double* zeta, const double* alpha, const double* beta, int S,
+                       double* E_host, double* sigma2_host, double* L_dev, void* ws, size_t ws_bytes,
+                       modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (!zeta || !alpha || !sigma2_host || S < 0 || (S > 0 && (!beta || !E_host)))
+    return fail(c, MODAL_EINVAL, "fnl: null pointer or S < 0");
+  modal_status s = check_ws(c, MODAL_OP_FNL, S, ws, ws_bytes);
+  if (s != MODAL_OK) return s;
+  if ((s = set_device(c)) != MODAL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const int n = c->nmax;
+  Carver cv(ws);
+  double* L = (double*)cv.take((size_t)n * n * 8);
+  double* rows = (double*)cv.take((size_t)(S + 1) * n * 8);
+  double* dots = (double*)cv.take((size_t)(S + 1) * 8);
+  int* flag = (int*)cv.take(16);
+  HIPTRY(launch_zero(flag, 16, st));
+  HIPTRY(hipMemcpyAsync(L, zeta, (size_t)n * n * 8, hipMemcpyDeviceToDevice, st));
+  HIPTRY(hipMemcpyAsync(rows, alpha, (size_t)n * 8, hipMemcpyDeviceToDevice, st));
+  if (S > 0) HIPTRY(hipMemcpyAsync(rows + n, beta, (size_t)S * n * 8, hipMemcpyDeviceToDevice, st));
+  {
+    StageTimer _t(c, MODAL_STAGE_CHOLESKY, st);
+    HIPTRY(launch_cholesky(n, L, flag, st));
+    HIPTRY(launch_trsm_rows(n, L, S + 1, rows, st));
+    HIPTRY(launch_estimator(n, rows, nullptr, S, dots, st));
+  }
+  if (L_dev) HIPTRY(launch_copy_lower(n, L, L_dev, st));
+  std::vector<double> h(S + 1);
+  int hflag[4] = {0, 0, 0, 0};
+  HIPTRY(hipMemcpyAsync(h.data(), dots, (size_t)(S + 1) * 8, hipMemcpyDeviceToHost, st));
+  HIPTRY(hipMemcpyAsync(hflag, flag, 16, hipMemcpyDeviceToHost, st));
+  HIPTRY(hipStreamSynchronize(st));
+  if (hflag[0] != 0)
+    return fail(c, MODAL_ENOTPD, "fnl: zeta is not positive definite at pivot " + std::to_string(hflag[0] - 1));
+  const double yy = h[0];
+  *sigma2_host = 6.0 / yy;
+  for (int i = 0; i < S; ++i) E_host[i] = h[1 + i] / yy;
+  return MODAL_OK;
+}
+
+modal_status modal_profile_enable(modal_ctx* c, int enable) {
+  if (!c) return MODAL_EINVAL;
+  c->profile = enable != 0;
+  return MODAL_OK;
+}
+
+modal_status modal_profile_read(modal_ctx* c, double* ms, long long* count, int reset) {
+  if (!c) return MODAL_EINVAL;
+  for (auto& mk : c->marks) {
+    float t = 0.f;
+    HIPTRY(hipEventSynchronize(mk.b));
+    HIPTRY(hipEventElapsedTime(&t, mk.a, mk.b));
+    c->stage_ms[mk.stage] += t;
+    c->stage_n[mk.stage] += 1;
+    c->event_pool.push_back(mk.a);
+    c->event_pool.push_back(mk.b);
+  }
+  c->marks.clear();
+  for (int i = 0; i < MODAL_NSTAGES; ++i) {
+    if (ms) ms[i] = c->stage_ms[i];
+    if (count) count[i] = c->stage_n[i];
+    if (reset) {
+      c->stage_ms[i] = 0.0;
+      c->stage_n[i] = 0;
+    }
+  }
+  return MODAL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Adjoint of the cubic reduction with respect to the filtered maps.
+//
+// For L = sum_n c_n beta^hat_n, beta^hat_prs = sum_x w (M_p M_r M_s - V_pr M_s - V_ps M_r - V_rs M_p),
+//   dL/dM_u(x) = w(x) sum_{(ab)} K_{u,(ab)} (M_a M_b - V_ab)(x),
+// where K_{u,(ab)} = c_{sort(u,a,b)} times the number of legs of that triple equal
+// to u (each leg of the product differentiates to the other two).  The pair map
+// contraction over (ab) is done per pixel; the result then goes through the
+// r2c ring FFT and the adjoint Legendre contraction (k_fft.hip, k_legendre.hip).
+#include "common.h"
+
+namespace modal {
+namespace {
+
+__global__ void k_slot(int P, int npairs, int nmax, int S, const int* __restrict__ tri_of,
+                       const int* __restrict__ tri_mult, const double* __restrict__ cot, double* __restrict__ K) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t per = (size_t)P * npairs;
+  if (i >= per * S) return;
+  const size_t s = i / per, k = i - s * per;
+  K[i] = cot[s * nmax + tri_of[k]] * (double)tri_mult[k];
+}
+
+constexpr int kPx = 64;
+constexpr int kPc = 32;
+
+template <typename T, bool LIN>
+__global__ __launch_bounds__(256) void k_pair_adjoint(int P, int npairs, int npix, const int* __restrict__ pair_a,
+                                                      const int* __restrict__ pair_b, const T* __restrict__ maps,
+                                                      const T* __restrict__ V, const T* __restrict__ w,
+                                                      const double* __restrict__ K, T* __restrict__ G) {
+  const int s = blockIdx.y;
+  const int x0 = blockIdx.x * kPx;
+  const int px = threadIdx.x & 63, ug = threadIdx.x >> 6;
+  const int x = x0 + px;
+  __shared__ T Mt[kMaxP][kPx];
+  __shared__ double Ks[kMaxP][kPc];
+  __shared__ int sa[kPc], sb[kPc];
+  const T* Ms = maps + (size_t)s * P * npix;
+  for (int e = threadIdx.x; e < P * kPx; e += 256) {
+    const int p = e / kPx, xx = e - p * kPx;
+    Mt[p][xx] = (x0 + xx < npix) ? Ms[(size_t)p * npix + x0 + xx] : T(0);
+  }
+  double acc[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+  const double* Kslab = K + (size_t)s * P * npairs;
+  for (int c0 = 0; c0 < npairs; c0 += kPc) {
+    const int nc = min(kPc, npairs - c0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < P * kPc; e += 256) {
+      const int u = e / kPc, pc = e - u * kPc;
+      Ks[u][pc] = pc < nc ? Kslab[(size_t)u * npairs + c0 + pc] : 0.0;
+    }
+    if (threadIdx.x < kPc) {
+      sa[threadIdx.x] = threadIdx.x < nc ? pair_a[c0 + threadIdx.x] : 0;
+      sb[threadIdx.x] = threadIdx.x < nc ? pair_b[c0 + threadIdx.x] : 0;
+    }
+    __syncthreads();
+    if (x < npix) {
+      for (int pc = 0; pc < nc; ++pc) {
+        double A = (double)Mt[sa[pc]][px] * (double)Mt[sb[pc]][px];
+        if (LIN) A -= (double)V[(size_t)(c0 + pc) * npix + x];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int u = ug + 4 * i;
+          if (u < P) acc[i] += Ks[u][pc] * A;
+        }
+      }
+    }
+  }
+  if (x >= npix) return;
+  const double wx = (double)w[x];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int u = ug + 4 * i;
+    if (u < P) G[((size_t)s * P + u) * npix + x] = T(wx * acc[i]);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_slot_matrix(const modal_ctx* c, const double* cot, int S, void* K, hipStream_t st) {
+  const size_t tot = (size_t)c->P * c->npairs * S;
+  hipLaunchKernelGGL(k_slot, dim3((tot + 255) / 256), dim3(256), 0, st, c->P, c->npairs, c->nmax, S, c->t.tri_of,
+                     c->t.tri_mult, cot, (double*)K);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_adjoint(const modal_ctx* c, const void* maps, const void* V, const void* K, int S, void* G,
+                               hipStream_t st) {
+  dim3 grid((c->npix + kPx - 1) / kPx, S);
+#define LAUNCH(T, L, W)                                                                                          \
+  hipLaunchKernelGGL((k_pair_adjoint<T, L>), grid, dim3(256), 0, st, c->P, c->npairs, c->npix, c->t.pair_a,      \
+                     c->t.pair_b, (const T*)maps, (const T*)V, (const T*)W, (const double*)K, (T*)G)
+  if (is_f64(c)) {
+    if (V) LAUNCH(double, true, c->t.w64);
+    else LAUNCH(double, false, c->t.w64);
+  } else {
+    if (V) LAUNCH(float, true, c->t.w32);
+    else LAUNCH(float, false, c->t.w32);
+  }
+#undef LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace modal

@@ -1,0 +1,135 @@
+// Cubic pixel reduction as a pair x mode contraction over pixels (VALU path).
+//
+//   E_{(ab),t} = sum_x w(x) A_ab(x) M_t(x),  A_ab = M_a M_b           (mode 0, beta)
+//                                             A_ab = M_a M_b - 3 V_ab  (mode 1, beta - lin)
+//                                             A_ab = V_ab              (mode 2, lin alone)
+//   out_prs = scale (E_{(pr),s} + E_{(ps),r} + E_{(rs),p})
+//
+// With scale = 1/3, mode 0 gives beta_prs (the three terms are equal), mode 1
+// gives beta_prs - lin_prs (each pairing of the linear term appears once), and
+// mode 2 with scale = 1 gives lin_prs alone (eq. bbispect with the three
+// pairings of the "3 C a" linear term of eq. bispectrumest).
+//
+// This kernel is the FP64 path (and any precision's reference-grade path): one
+// workgroup per (pixel chunk, block of 64 pairs, map) accumulating in FP64.
+// The MFMA paths live in k_cubic_mfma.hip and share the reduction below.
+#include "common.h"
+
+namespace modal {
+namespace {
+
+constexpr int kChunk = 65536;  // pixels per split-K chunk
+constexpr int kTile = 64;      // pixels staged in LDS per step
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_cubic_valu(int P, int npairs, int npix, int nchunk,
+                                                    const int* __restrict__ pair_a, const int* __restrict__ pair_b,
+                                                    const T* __restrict__ maps, const T* __restrict__ w,
+                                                    const T* __restrict__ V, double* __restrict__ part) {
+  const int chunk = blockIdx.x;
+  const int s = blockIdx.z;
+  const int pl = threadIdx.x & 63;
+  const int tg = threadIdx.x >> 6;
+  const int pair = blockIdx.y * 64 + pl;
+  const bool pv = pair < npairs;
+  const int a = pv ? pair_a[pair] : 0;
+  const int b = pv ? pair_b[pair] : 0;
+  __shared__ T Mt[kMaxP][kTile];
+  __shared__ T wt[kTile];
+  double acc[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+  const T* Ms = maps + (size_t)s * P * npix;
+  const int x0c = chunk * kChunk;
+  const int x1c = min(npix, x0c + kChunk);
+  for (int x0 = x0c; x0 < x1c; x0 += kTile) {
+    const int nt = min(kTile, x1c - x0);
+    for (int i = threadIdx.x; i < P * kTile; i += 256) {
+      const int p = i / kTile, xx = i - p * kTile;
+      Mt[p][xx] = xx < nt ? Ms[(size_t)p * npix + x0 + xx] : T(0);
+    }
+    if (threadIdx.x < kTile) wt[threadIdx.x] = threadIdx.x < nt ? w[x0 + threadIdx.x] : T(0);
+    __syncthreads();
+    if (pv) {
+      for (int xx = 0; xx < nt; ++xx) {
+        double A;
+        if (MODE == 0) A = (double)Mt[a][xx] * (double)Mt[b][xx];
+        else if (MODE == 1) A = (double)Mt[a][xx] * (double)Mt[b][xx] - 3.0 * (double)V[(size_t)pair * npix + x0 + xx];
+        else A = (double)V[(size_t)pair * npix + x0 + xx];
+        A *= (double)wt[xx];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int t = tg + 4 * i;
+          if (t < P) acc[i] += A * (double)Mt[t][xx];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!pv) return;
+  double* dst = part + (((size_t)s * nchunk + chunk) * npairs + pair) * P;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int t = tg + 4 * i;
+    if (t < P) dst[t] = acc[i];
+  }
+}
+
+__global__ void k_reduce_chunks(int nchunk, size_t per, int S, const double* __restrict__ part, double* __restrict__ E) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= per * S) return;
+  const size_t s = i / per, k = i - s * per;
+  const double* src = part + s * nchunk * per + k;
+  double acc = 0.0;
+  for (int c = 0; c < nchunk; ++c) acc += src[(size_t)c * per];
+  E[i] = acc;
+}
+
+__global__ void k_symm(int nmax, int npairs, int P, int S, double scale, const int* __restrict__ tri,
+                       const double* __restrict__ E, double* __restrict__ out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (n >= nmax) return;
+  const int* tr = tri + 6 * n;  // p, r, s, pair(pr), pair(ps), pair(rs)
+  const double* Es = E + (size_t)s * npairs * P;
+  const double v = Es[(size_t)tr[3] * P + tr[2]] + Es[(size_t)tr[4] * P + tr[1]] + Es[(size_t)tr[5] * P + tr[0]];
+  out[(size_t)s * nmax + n] = scale * v;
+}
+
+}  // namespace
+
+int cubic_nchunk(const modal_ctx* c) { return (c->npix + kChunk - 1) / kChunk; }
+
+hipError_t launch_cubic_valu(const modal_ctx* c, const void* maps, const void* V, int S, int mode, double* part,
+                             hipStream_t st) {
+  const int nchunk = cubic_nchunk(c);
+  dim3 grid(nchunk, (c->npairs + 63) / 64, S);
+#define LAUNCH(T, MD, W)                                                                                     \
+  hipLaunchKernelGGL((k_cubic_valu<T, MD>), grid, dim3(256), 0, st, c->P, c->npairs, c->npix, nchunk,        \
+                     c->t.pair_a, c->t.pair_b, (const T*)maps, (const T*)W, (const T*)V, part)
+  if (is_f64(c)) {
+    if (mode == 0) LAUNCH(double, 0, c->t.w64);
+    else if (mode == 1) LAUNCH(double, 1, c->t.w64);
+    else LAUNCH(double, 2, c->t.w64);
+  } else {
+    if (mode == 0) LAUNCH(float, 0, c->t.w32);
+    else if (mode == 1) LAUNCH(float, 1, c->t.w32);
+    else LAUNCH(float, 2, c->t.w32);
+  }
+#undef LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_symm(const modal_ctx* c, const double* part, int S, int nchunk, double scale, double* E,
+                              double* out, hipStream_t st) {
+  const size_t per = (size_t)c->npairs * c->P;
+  const size_t tot = per * S;
+  hipLaunchKernelGGL(k_reduce_chunks, dim3((tot + 255) / 256), dim3(256), 0, st, nchunk, per, S, part, E);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_symm, dim3((c->nmax + 255) / 256, S), dim3(256), 0, st, c->nmax, c->npairs, c->P, S, scale,
+                     c->t.tri, E, out);
+  return hipGetLastError();
+}
+
+}  // namespace modal

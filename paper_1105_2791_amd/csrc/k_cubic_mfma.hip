@@ -1,0 +1,312 @@
+// Cubic pixel reduction on the CDNA4 matrix cores.
+//
+//   E_{(ab),t} = sum_x A_ab(x) B_t(x),  A_ab = M_a M_b [- 3 V_ab] (or V_ab),  B_t = w M_t
+//
+// is a GEMM with M = pairs, N = modes and K = pixels (split into chunks whose
+// FP32 partial sums are reduced in FP64 by k_cubic.hip).  The A operand is formed
+// on the vector ALUs from maps staged in LDS and never stored; B is split once
+// per K step into LDS.
+//
+// Pair tiling: lane-row i of a wave owns a 2 x 4 block of pairs, a in {a0, a0+1},
+// b in {b0..b0+3}, so one K step needs 6 map rows per lane (instead of 2 per pair)
+// and the eight 16-row tiles of a wave are its eight (a, b) combinations.  Blocks
+// that straddle the diagonal carry invalid pairs (a > b) whose A is zero.
+//
+// Precisions
+//   F32    : v_mfma_f32_16x16x4_f32, A and B in FP32.
+//   BF16X3 : v_mfma_f32_16x16x32_bf16 on hi/lo splits, A B ~ Ah Bh + Ah Bl + Al Bh
+//            (hi = RNE bf16, lo = RNE bf16 of the residual), FP32 accumulation.
+//
+// Launch: one workgroup per (pixel chunk, block group, sky); chunk c runs on XCD
+// c mod 8 with all skies of that chunk dispatched back to back, so the V planes
+// of a chunk are fetched from HBM about once and re-read from that XCD's L2.
+#include "common.h"
+
+namespace modal {
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int KS = 32;          // pixels per K step
+constexpr int MS_STRIDE = KS + 4;
+constexpr int NW = 8;           // waves per workgroup
+constexpr int NT = 64 * NW;
+constexpr int BLK_PER_GROUP = 16 * NW;
+constexpr int TCOLS = 48;       // modes padded to three 16-wide column tiles
+
+struct Blocks {
+  int nblk;      // valid blocks
+  int ngroups;   // ceil(nblk / BLK_PER_GROUP)
+};
+
+__device__ inline uint32_t bf16x2_bits(float a, float b) {
+  typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
+  bf16x2 h;
+  h[0] = (__bf16)a;
+  h[1] = (__bf16)b;
+  return __builtin_bit_cast(uint32_t, h);
+}
+
+// hi/lo split of 8 floats into two bf16x8 (hi = RNE(x), lo = RNE(x - hi)).
+__device__ inline void split8(const float* v, bf16x8& hi, bf16x8& lo) {
+  uint32_t h[4], l[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t hb = bf16x2_bits(v[2 * k], v[2 * k + 1]);
+    const float h0 = __builtin_bit_cast(float, hb << 16);
+    const float h1 = __builtin_bit_cast(float, hb & 0xffff0000u);
+    h[k] = hb;
+    l[k] = bf16x2_bits(v[2 * k] - h0, v[2 * k + 1] - h1);
+  }
+  typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
+  u32x4 hv = {h[0], h[1], h[2], h[3]};
+  u32x4 lv = {l[0], l[1], l[2], l[3]};
+  hi = __builtin_bit_cast(bf16x8, hv);
+  lo = __builtin_bit_cast(bf16x8, lv);
+}
+
+template <int PREC, int MODE>
+__global__ __launch_bounds__(NT) void k_cubic_mfma(int P, int npairs, int npix, int S, int nchunk, int chunk_px,
+                                                   Blocks bk, const int2* __restrict__ blocks,
+                                                   const int* __restrict__ pair_of, const float* __restrict__ maps,
+                                                   const float* __restrict__ w, const float* __restrict__ V,
+                                                   double* __restrict__ part) {
+  // ---- XCD-aware decode: chunk c on XCD c % 8, its (group, sky) items consecutive there
+  const int b = blockIdx.x;
+  const int xcd = b & 7;
+  const int i8 = b >> 3;
+  const int per = bk.ngroups * S;
+  const int chunk = xcd + 8 * (i8 / per);
+  if (chunk >= nchunk) return;
+  const int rem = i8 - (i8 / per) * per;
+  const int group = rem / S;
+  const int s = rem - group * S;
+
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6, lane = tid & 63;
+  const int row = lane & 15, kg = lane >> 4;
+
+  __shared__ float Ms[kMaxP][MS_STRIDE];
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[TCOLS][KS];   // bf16 bits (BF16X3)
+  __shared__ __attribute__((aligned(16))) uint16_t Bl[TCOLS][KS];
+  __shared__ __attribute__((aligned(16))) float Bf[TCOLS][KS];      // FP32 path
+
+  // this lane-row's block
+  const int blk = group * BLK_PER_GROUP + wv * 16 + row;
+  int a0 = -1, b0 = 0;
+  if (blk < bk.nblk) {
+    const int2 bb = blocks[blk];
+    a0 = bb.x;
+    b0 = bb.y;
+  }
+  int pidx[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int a = a0 + (j >> 2), bm = b0 + (j & 3);
+    pidx[j] = (a0 >= 0 && a < P && bm < P && a <= bm) ? pair_of[a * P + bm] : -1;
+  }
+
+  f32x4 acc[8][3];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[j][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const float* Msky = maps + (size_t)s * P * npix;
+  const int x_begin = chunk * chunk_px;
+  const int x_end = min(npix, x_begin + chunk_px);
+
+  for (int x0 = x_begin; x0 < x_end; x0 += KS) {
+    // ---- stage maps and the B operand for this K step
+    for (int e = tid; e < P * KS; e += NT) {
+      const int p = e / KS, xx = e - p * KS;
+      const int x = x0 + xx;
+      Ms[p][xx] = x < x_end ? Msky[(size_t)p * npix + x] : 0.f;
+    }
+    for (int e = tid; e < TCOLS * KS / 2; e += NT) {
+      const int t = e / (KS / 2), xx = 2 * (e - t * (KS / 2));
+      const int x = x0 + xx;
+      float v0 = 0.f, v1 = 0.f;
+      if (t < P) {
+        if (x < x_end) v0 = w[x] * Msky[(size_t)t * npix + x];
+        if (x + 1 < x_end) v1 = w[x + 1] * Msky[(size_t)t * npix + x + 1];
+      }
+      if (PREC == MODAL_BF16X3) {
+        const uint32_t hb = bf16x2_bits(v0, v1);
+        const float h0 = __builtin_bit_cast(float, hb << 16);
+        const float h1 = __builtin_bit_cast(float, hb & 0xffff0000u);
+        const uint32_t lb = bf16x2_bits(v0 - h0, v1 - h1);
+        *reinterpret_cast<uint32_t*>(&Bh[t][xx]) = hb;
+        *reinterpret_cast<uint32_t*>(&Bl[t][xx]) = lb;
+      } else {
+        Bf[t][xx] = v0;
+        Bf[t][xx + 1] = v1;
+      }
+    }
+    __syncthreads();
+
+    if (a0 >= 0) {
+      // the six map rows this lane needs, at its 8 pixels (x0 + 8 kg .. + 7)
+      float ma[2][8], mb[4][8];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int p = min(a0 + u, P - 1);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) ma[u][k] = Ms[p][8 * kg + k];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int p = min(b0 + u, P - 1);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) mb[u][k] = Ms[p][8 * kg + k];
+      }
+      const int xl = x0 + 8 * kg;
+      if (PREC == MODAL_BF16X3) {
+        bf16x8 bh[3], bl[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          bh[c] = *reinterpret_cast<const bf16x8*>(&Bh[16 * c + row][8 * kg]);
+          bl[c] = *reinterpret_cast<const bf16x8*>(&Bl[16 * c + row][8 * kg]);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          float av[8];
+          if (pidx[j] >= 0) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              if (MODE == 0) av[k] = ma[j >> 2][k] * mb[j & 3][k];
+              else {
+                const int x = xl + k;
+                const float vv = x < x_end ? V[(size_t)pidx[j] * npix + x] : 0.f;
+                av[k] = (MODE == 1) ? fmaf(ma[j >> 2][k], mb[j & 3][k], -3.f * vv) : vv;
+              }
+            }
+          } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) av[k] = 0.f;
+          }
+          bf16x8 ah, al;
+          split8(av, ah, al);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            acc[j][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[c], acc[j][c], 0, 0, 0);
+            acc[j][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[c], acc[j][c], 0, 0, 0);
+            acc[j][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[c], acc[j][c], 0, 0, 0);
+          }
+        }
+      } else {
+        float bv[3][8];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int k = 0; k < 8; ++k) bv[c][k] = Bf[16 * c + row][8 * kg + k];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          float av[8];
+          if (pidx[j] >= 0) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              if (MODE == 0) av[k] = ma[j >> 2][k] * mb[j & 3][k];
+              else {
+                const int x = xl + k;
+                const float vv = x < x_end ? V[(size_t)pidx[j] * npix + x] : 0.f;
+                av[k] = (MODE == 1) ? fmaf(ma[j >> 2][k], mb[j & 3][k], -3.f * vv) : vv;
+              }
+            }
+          } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) av[k] = 0.f;
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+              acc[j][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[k], bv[c][k], acc[j][c], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- write this chunk's partial sums: acc[j][c][r] is output row 4 kg + r
+  // (a lane-row of this wave), column t = 16 c + row
+  double* dst = part + ((size_t)s * nchunk + chunk) * npairs * P;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int orow = 4 * kg + r;
+    const int oblk = group * BLK_PER_GROUP + wv * 16 + orow;
+    if (oblk >= bk.nblk) continue;
+    const int2 bb = blocks[oblk];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int a = bb.x + (j >> 2), bm = bb.y + (j & 3);
+      if (a >= P || bm >= P || a > bm) continue;
+      const int pr = pair_of[a * P + bm];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int t = 16 * c + row;
+        if (t < P) dst[(size_t)pr * P + t] = (double)acc[j][c][r];
+      }
+    }
+  }
+}
+
+int chunk_px_for(const modal_ctx* c) {
+  // nchunk a multiple of 8 (one chunk stream per XCD), chunks of about 64K pixels
+  const int target = 65536;
+  int nchunk = 8 * ((c->npix + 8 * target - 1) / (8 * target));
+  int px = (c->npix + nchunk - 1) / nchunk;
+  px = (px + KS - 1) / KS * KS;
+  return px;
+}
+
+}  // namespace
+
+bool cubic_mfma_available(const modal_ctx* c) {
+  return c->prec == MODAL_F32 || c->prec == MODAL_BF16X3;
+}
+
+int cubic_mfma_nchunk(const modal_ctx* c) {
+  const int px = chunk_px_for(c);
+  return (c->npix + px - 1) / px;
+}
+
+// Blocks of 2 x 4 pairs covering the triangle a <= b < P.
+void make_pair_blocks(int P, std::vector<int2>& out) {
+  out.clear();
+  for (int u = 0; u < P; u += 2)
+    for (int v = 0; v < P; v += 4) {
+      bool any = false;
+      for (int a = u; a < u + 2 && a < P; ++a)
+        for (int b = v; b < v + 4 && b < P; ++b) any |= (a <= b);
+      if (any) out.push_back(make_int2(u, v));
+    }
+}
+
+hipError_t launch_cubic_mfma(const modal_ctx* c, const void* maps, const void* V, int S, int mode, double* part,
+                             hipStream_t st) {
+  Blocks bk;
+  bk.nblk = c->t.nblk;
+  bk.ngroups = (bk.nblk + BLK_PER_GROUP - 1) / BLK_PER_GROUP;
+  const int px = chunk_px_for(c);
+  const int nchunk = (c->npix + px - 1) / px;
+  const int nslots = 8 * ((nchunk + 7) / 8);
+  const size_t grid = (size_t)nslots * bk.ngroups * S;
+#define LAUNCH(PR, MD)                                                                                        \
+  hipLaunchKernelGGL((k_cubic_mfma<PR, MD>), dim3(grid), dim3(NT), 0, st, c->P, c->npairs, c->npix, S, nchunk, \
+                     px, bk, c->t.blk, c->t.pair_of, (const float*)maps, c->t.w32, (const float*)V, part)
+  if (c->prec == MODAL_BF16X3) {
+    if (mode == 0) LAUNCH(MODAL_BF16X3, 0);
+    else if (mode == 1) LAUNCH(MODAL_BF16X3, 1);
+    else LAUNCH(MODAL_BF16X3, 2);
+  } else {
+    if (mode == 0) LAUNCH(MODAL_F32, 0);
+    else if (mode == 1) LAUNCH(MODAL_F32, 1);
+    else LAUNCH(MODAL_F32, 2);
+  }
+#undef LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace modal

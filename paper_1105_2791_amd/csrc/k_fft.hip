@@ -1,0 +1,222 @@
+// Ring FFTs in LDS (Stockham autosort, mixed radix).
+//
+// c2r (synthesis):  M(theta_j, phi_k) = Re F_0 + 2 Re sum_{m=1}^{lmax} F_m e^{i m phi_k},
+//                   phi_k = 2 pi k / N, N = nphi even, lmax < N/2.
+// The length-N real transform is one complex transform of length K = N/2:
+//   Z_m = (X_m + X*_{K-m}) + i e^{2 pi i m / N} (X_m - X*_{K-m}),  z = sum_m Z_m e^{2 pi i m n / K},
+//   M_{2n} = Re z_n, M_{2n+1} = Im z_n,
+// with X_m = F_m (m <= lmax), 0 otherwise, and X_0 real.
+// r2c (adjoint):    Gh_m = sum_k G_k e^{-i m phi_k} for m <= lmax, from
+//   z_n = G_{2n} + i G_{2n+1}, Z = sum_n z_n e^{-2 pi i m n / K},
+//   Gh_m = (Z_m + Z*_{K-m}) / 2 - (i/2) e^{-2 pi i m / N} (Z_m - Z*_{K-m}).
+// One workgroup per ring row; twiddles tw[t] = e^{2 pi i t / N} come from an FP64
+// table (rounded to the working precision).
+#include "common.h"
+
+namespace modal {
+namespace {
+
+template <typename T> struct vec2;
+template <> struct vec2<float> { using type = float2; };
+template <> struct vec2<double> { using type = double2; };
+
+template <typename T2>
+__device__ inline T2 cmul(T2 a, T2 b) {
+  T2 r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+
+// One Stockham stage of radix R on K points: out = stage(in).  sign = +1 for
+// e^{+i}, -1 for e^{-i}.  Twiddle exp(sign 2 pi i t / K) = tw[2 t] (conjugated for sign -1).
+template <typename T2, int SIGN>
+__device__ inline void stockham_stage(const T2* __restrict__ in, T2* __restrict__ out, int K, int Ns, int R,
+                                      const T2* __restrict__ tw) {
+  const int KR = K / R;
+  const int step = K / (Ns * R);  // exp(2 pi i u / (Ns R)) = exp(2 pi i u step / K)
+  for (int b = threadIdx.x; b < KR; b += blockDim.x) {
+    const int k = b % Ns;
+    const int obase = (b / Ns) * Ns * R + k;
+    if (R == 2) {
+      const T2 a0 = in[b];
+      T2 a1 = in[b + KR];
+      T2 w = tw[2 * ((k * step) % K)];
+      if (SIGN < 0) w.y = -w.y;
+      a1 = cmul(a1, w);
+      T2 y0, y1;
+      y0.x = a0.x + a1.x; y0.y = a0.y + a1.y;
+      y1.x = a0.x - a1.x; y1.y = a0.y - a1.y;
+      out[obase] = y0;
+      out[obase + Ns] = y1;
+    } else if (R == 4) {
+      T2 a[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        a[r] = in[b + r * KR];
+        if (r) {
+          T2 w = tw[2 * ((r * k * step) % K)];
+          if (SIGN < 0) w.y = -w.y;
+          a[r] = cmul(a[r], w);
+        }
+      }
+      // radix-4 DFT with e^{sign i pi/2} = sign * i
+      T2 s02, d02, s13, d13;
+      s02.x = a[0].x + a[2].x; s02.y = a[0].y + a[2].y;
+      d02.x = a[0].x - a[2].x; d02.y = a[0].y - a[2].y;
+      s13.x = a[1].x + a[3].x; s13.y = a[1].y + a[3].y;
+      d13.x = a[1].x - a[3].x; d13.y = a[1].y - a[3].y;
+      // j * d13 where j = sign * i
+      T2 jd;
+      jd.x = -SIGN * d13.y;
+      jd.y = SIGN * d13.x;
+      T2 y0, y1, y2, y3;
+      y0.x = s02.x + s13.x; y0.y = s02.y + s13.y;
+      y2.x = s02.x - s13.x; y2.y = s02.y - s13.y;
+      y1.x = d02.x + jd.x;  y1.y = d02.y + jd.y;
+      y3.x = d02.x - jd.x;  y3.y = d02.y - jd.y;
+      out[obase] = y0;
+      out[obase + Ns] = y1;
+      out[obase + 2 * Ns] = y2;
+      out[obase + 3 * Ns] = y3;
+    } else {
+      // generic radix: direct DFT with the combined twiddle exp(sign 2 pi i r (k + q Ns) / (Ns R))
+      for (int q = 0; q < R; ++q) {
+        T2 acc;
+        acc.x = 0;
+        acc.y = 0;
+        for (int r = 0; r < R; ++r) {
+          const T2 a = in[b + r * KR];
+          const long long t = ((long long)r * (k + q * Ns) * step) % K;
+          T2 w = tw[2 * t];
+          if (SIGN < 0) w.y = -w.y;
+          const T2 p = cmul(a, w);
+          acc.x += p.x;
+          acc.y += p.y;
+        }
+        out[obase + q * Ns] = acc;
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_c2r(FftPlan plan, int lmax, const typename vec2<T>::type* __restrict__ F,
+                                                 T* __restrict__ maps, const typename vec2<T>::type* __restrict__ tw) {
+  using T2 = typename vec2<T>::type;
+  extern __shared__ char smem[];
+  T2* b0 = reinterpret_cast<T2*>(smem);
+  T2* b1 = b0 + plan.K;
+  const int K = plan.K;
+  const size_t row = blockIdx.x;
+  const T2* H = F + row * (lmax + 1);
+  for (int m = threadIdx.x; m < K; m += blockDim.x) {
+    T2 xm, xk;
+    xm.x = xm.y = T(0);
+    xk.x = xk.y = T(0);
+    if (m <= lmax) xm = H[m];
+    if (m == 0) xm.y = T(0);
+    const int mk = K - m;          // in (0, K]; X_K = 0 since lmax < K
+    if (mk <= lmax) xk = H[mk];
+    T2 a, d;
+    a.x = xm.x + xk.x; a.y = xm.y - xk.y;   // X_m + conj(X_{K-m})
+    d.x = xm.x - xk.x; d.y = xm.y + xk.y;   // X_m - conj(X_{K-m})
+    const T2 e = tw[m];
+    T2 z;
+    z.x = a.x - (e.x * d.y + e.y * d.x);
+    z.y = a.y + (e.x * d.x - e.y * d.y);
+    b0[m] = z;
+  }
+  __syncthreads();
+  T2* in = b0;
+  T2* out = b1;
+  int Ns = 1;
+  for (int f = 0; f < plan.nf; ++f) {
+    const int R = plan.radix[f];
+    stockham_stage<T2, +1>(in, out, K, Ns, R, tw);
+    __syncthreads();
+    T2* tmp = in; in = out; out = tmp;
+    Ns *= R;
+  }
+  T2* dst = reinterpret_cast<T2*>(maps + row * plan.N);
+  for (int n = threadIdx.x; n < K; n += blockDim.x) dst[n] = in[n];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_r2c(FftPlan plan, int lmax, const T* __restrict__ G,
+                                                 typename vec2<T>::type* __restrict__ Gh,
+                                                 const typename vec2<T>::type* __restrict__ tw) {
+  using T2 = typename vec2<T>::type;
+  extern __shared__ char smem[];
+  T2* b0 = reinterpret_cast<T2*>(smem);
+  T2* b1 = b0 + plan.K;
+  const int K = plan.K;
+  const size_t row = blockIdx.x;
+  const T2* src = reinterpret_cast<const T2*>(G + row * plan.N);
+  for (int n = threadIdx.x; n < K; n += blockDim.x) b0[n] = src[n];
+  __syncthreads();
+  T2* in = b0;
+  T2* out = b1;
+  int Ns = 1;
+  for (int f = 0; f < plan.nf; ++f) {
+    const int R = plan.radix[f];
+    stockham_stage<T2, -1>(in, out, K, Ns, R, tw);
+    __syncthreads();
+    T2* tmp = in; in = out; out = tmp;
+    Ns *= R;
+  }
+  T2* dst = Gh + row * (lmax + 1);
+  for (int m = threadIdx.x; m <= lmax; m += blockDim.x) {
+    const T2 zk = in[m % K];
+    const T2 zm = in[(K - m) % K];
+    T2 a, d;
+    a.x = zk.x + zm.x; a.y = zk.y - zm.y;   // Z_m + conj(Z_{K-m})
+    d.x = zk.x - zm.x; d.y = zk.y + zm.y;   // Z_m - conj(Z_{K-m})
+    const T2 e = tw[m];                     // e^{+2 pi i m / N}; use its conjugate (c, -s)
+    // -(i/2) (c - i s) d = 0.5 (c d.y - s d.x) - 0.5 i (c d.x + s d.y)
+    T2 g;
+    g.x = T(0.5) * (a.x + (e.x * d.y - e.y * d.x));
+    g.y = T(0.5) * (a.y - (e.x * d.x + e.y * d.y));
+    dst[m] = g;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fft_c2r(const modal_ctx* c, const void* F, int S, void* maps, hipStream_t st) {
+  const size_t rows = (size_t)S * c->P * c->ntheta;
+  const size_t lds = 2 * (size_t)c->fft.K * 2 * real_bytes(c);
+  if (is_f64(c))
+    hipLaunchKernelGGL(k_fft_c2r<double>, dim3(rows), dim3(256), lds, st, c->fft, c->lmax, (const double2*)F,
+                       (double*)maps, (const double2*)c->t.tw64);
+  else
+    hipLaunchKernelGGL(k_fft_c2r<float>, dim3(rows), dim3(256), lds, st, c->fft, c->lmax, (const float2*)F,
+                       (float*)maps, (const float2*)c->t.tw32);
+  return hipGetLastError();
+}
+
+hipError_t launch_fft_r2c(const modal_ctx* c, const void* G, int S, void* Gh, hipStream_t st) {
+  const size_t rows = (size_t)S * c->P * c->ntheta;
+  const size_t lds = 2 * (size_t)c->fft.K * 2 * real_bytes(c);
+  if (is_f64(c))
+    hipLaunchKernelGGL(k_fft_r2c<double>, dim3(rows), dim3(256), lds, st, c->fft, c->lmax, (const double*)G,
+                       (double2*)Gh, (const double2*)c->t.tw64);
+  else
+    hipLaunchKernelGGL(k_fft_r2c<float>, dim3(rows), dim3(256), lds, st, c->fft, c->lmax, (const float*)G,
+                       (float2*)Gh, (const float2*)c->t.tw32);
+  return hipGetLastError();
+}
+
+// Called once per context to allow LDS above the 64 KB default.
+hipError_t fft_set_lds_limit(size_t bytes) {
+  hipError_t e;
+  e = hipFuncSetAttribute((const void*)k_fft_c2r<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_fft_c2r<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_fft_r2c<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_fft_r2c<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+}  // namespace modal

@@ -1,0 +1,303 @@
+// Associated-Legendre synthesis and its adjoint (FP64 recurrence on the fly).
+//
+// F_{s,p,m}(theta_j) = sum_{l>=m} qw_p(l) a_{s,lm} lambda_lm(theta_j),  qw = q / sqrt(C_l)
+//
+// is the harmonic half of the filtered maps M_p (separable form of eq. bbispect):
+// for each m it is a contraction over l.  lambda_lm is produced by the normalised
+// three-term recurrence in l, carried in FP64 from per-(m, ring) seeds that a setup
+// kernel finds with a log-scaled FP64 recurrence (values below 2^-90 are dropped).
+// Rings are processed in north/south mirror pairs: lambda_lm(-x) = (-1)^{l+m}
+// lambda_lm(x), so even and odd (l - m) are summed separately and F_north = E + O,
+// F_south = E - O.
+#include "common.h"
+
+namespace modal {
+namespace {
+
+// ---------------------------------------------------------------------------
+// seeds: first significant l per (m, ring) and lambda there (log-scaled FP64)
+// ---------------------------------------------------------------------------
+__global__ void k_seeds(int lmax, int nrp, const double* __restrict__ x, const double* __restrict__ rec,
+                        const double* __restrict__ logpref, double* __restrict__ seed, int* __restrict__ lstart) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = blockIdx.y;
+  if (j >= nrp) return;
+  const double xx = x[j];
+  const double st = sqrt((1.0 - xx) * (1.0 + xx));
+  double E = logpref[m] + (m > 0 ? m * log(st) : 0.0);  // log scale of the scaled value
+  double s1 = (m & 1) ? -1.0 : 1.0;                     // scaled lambda_l
+  double s2 = 0.0;                                      // scaled lambda_{l-1}
+  const size_t off = (size_t)m * (2 * lmax + 3 - m) / 2;  // alm index of (m, m)
+  int l = m;
+  int ls = lmax + 1;
+  double v0 = 0.0, v1 = 0.0;
+  for (;;) {
+    if (s1 != 0.0 && E + log(fabs(s1)) >= kLogSeedFloor) {
+      ls = l;
+      v0 = s1 * exp(E);
+      if (l < lmax) {
+        const double* rc = rec + 2 * (off + (l + 1 - m));
+        v1 = (rc[0] * xx * s1 - rc[1] * s2) * exp(E);
+      }
+      break;
+    }
+    if (l == lmax) break;
+    const double* rc = rec + 2 * (off + (l + 1 - m));
+    const double sn = rc[0] * xx * s1 - rc[1] * s2;
+    s2 = s1;
+    s1 = sn;
+    ++l;
+    if (fabs(s1) > 1e100) {
+      s1 *= 1e-100;
+      s2 *= 1e-100;
+      E += 230.25850929940458;  // ln(1e100)
+    }
+  }
+  seed[2 * ((size_t)m * nrp + j) + 0] = v0;
+  seed[2 * ((size_t)m * nrp + j) + 1] = v1;
+  lstart[(size_t)m * nrp + j] = ls;
+}
+
+template <typename T> struct vec2;
+template <> struct vec2<float> { using type = float2; };
+template <> struct vec2<double> { using type = double2; };
+
+// Per-lane recurrence state for one ring.
+struct Rec {
+  double l1, l2;   // lambda_{l-1}, lambda_{l-2}
+  double s0, s1;   // seeds at ls, ls+1
+  int ls;
+  __device__ inline double step(int l, double xx, const double* rc) {
+    double v;
+    if (l < ls) v = 0.0;
+    else if (l == ls) v = s0;
+    else if (l == ls + 1) v = s1;
+    else v = rc[0] * xx * l1 - rc[1] * l2;
+    l2 = l1;
+    l1 = v;
+    return v;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// forward synthesis (VALU): one wave = 64 north rings, NSEQ (s,p) sequences
+// ---------------------------------------------------------------------------
+constexpr int kLch = 64;
+
+template <typename T, int NSEQ>
+__global__ __launch_bounds__(64) void k_legendre(int lmax, int ntheta, int nrp, int P, int nseq, int nalm,
+                                                 const double* __restrict__ x, const double* __restrict__ rec,
+                                                 const double* __restrict__ seed, const int* __restrict__ lstart,
+                                                 const T* __restrict__ qw,
+                                                 const typename vec2<T>::type* __restrict__ alm,
+                                                 typename vec2<T>::type* __restrict__ F) {
+  using T2 = typename vec2<T>::type;
+  const int m = blockIdx.z;
+  const int lane = threadIdx.x;
+  const int j = blockIdx.y * 64 + lane;
+  const int seq0 = blockIdx.x * NSEQ;
+  const bool ring_ok = j < nrp;
+  __shared__ T2 coef[kLch][NSEQ];
+  __shared__ int lmin_s;
+
+  Rec r;
+  double xx = 0.0;
+  r.l1 = r.l2 = 0.0;
+  r.ls = lmax + 1;
+  r.s0 = r.s1 = 0.0;
+  if (ring_ok) {
+    xx = x[j];
+    r.ls = lstart[(size_t)m * nrp + j];
+    r.s0 = seed[2 * ((size_t)m * nrp + j)];
+    r.s1 = seed[2 * ((size_t)m * nrp + j) + 1];
+  }
+  if (lane == 0) lmin_s = lmax + 1;
+  __syncthreads();
+  atomicMin(&lmin_s, r.ls);
+  __syncthreads();
+  const int lmin = lmin_s;
+
+  T er[NSEQ], ei[NSEQ], orr[NSEQ], oi[NSEQ];
+#pragma unroll
+  for (int q = 0; q < NSEQ; ++q) er[q] = ei[q] = orr[q] = oi[q] = T(0);
+
+  const size_t off = (size_t)m * (2 * lmax + 3 - m) / 2;
+  for (int l0 = lmin; l0 <= lmax; l0 += kLch) {
+    {
+      const int l = l0 + lane;
+#pragma unroll
+      for (int q = 0; q < NSEQ; ++q) {
+        T2 v;
+        v.x = T(0);
+        v.y = T(0);
+        const int sq = seq0 + q;
+        if (l <= lmax && sq < nseq) {
+          const int s = sq / P, p = sq - s * P;
+          const T2 a = alm[(size_t)s * nalm + off + (l - m)];
+          const T wq = qw[(size_t)p * (lmax + 1) + l];
+          v.x = a.x * wq;
+          v.y = a.y * wq;
+        }
+        coef[lane][q] = v;
+      }
+    }
+    __syncthreads();
+    const int nl = min(kLch, lmax + 1 - l0);
+    for (int tt = 0; tt < nl; ++tt) {
+      const int l = l0 + tt;
+      const double lam = r.step(l, xx, rec + 2 * (off + (l - m)));
+      const T lf = T(lam);
+      if ((l - m) & 1) {
+#pragma unroll
+        for (int q = 0; q < NSEQ; ++q) {
+          orr[q] += coef[tt][q].x * lf;
+          oi[q] += coef[tt][q].y * lf;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < NSEQ; ++q) {
+          er[q] += coef[tt][q].x * lf;
+          ei[q] += coef[tt][q].y * lf;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!ring_ok) return;
+  const int js = ntheta - 1 - j;
+#pragma unroll
+  for (int q = 0; q < NSEQ; ++q) {
+    const int sq = seq0 + q;
+    if (sq >= nseq) break;
+    T2* row = F + (size_t)sq * ntheta * (lmax + 1);
+    T2 vn, vs;
+    vn.x = er[q] + orr[q];
+    vn.y = ei[q] + oi[q];
+    vs.x = er[q] - orr[q];
+    vs.y = ei[q] - oi[q];
+    row[(size_t)j * (lmax + 1) + m] = vn;
+    if (js != j) row[(size_t)js * (lmax + 1) + m] = vs;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// lambda table for the adjoint: lam[m][j][l - m] (north rings), T precision
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_lambda_table(int lmax, int nrp, const double* __restrict__ x, const double* __restrict__ rec,
+                               const double* __restrict__ seed, const int* __restrict__ lstart,
+                               T* __restrict__ lam) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = blockIdx.y;
+  if (j >= nrp) return;
+  Rec r;
+  r.l1 = r.l2 = 0.0;
+  r.ls = lstart[(size_t)m * nrp + j];
+  r.s0 = seed[2 * ((size_t)m * nrp + j)];
+  r.s1 = seed[2 * ((size_t)m * nrp + j) + 1];
+  const double xx = x[j];
+  const size_t off = (size_t)m * (2 * lmax + 3 - m) / 2;
+  // table base for this m: rows j of length L_m = lmax + 1 - m
+  T* out = lam + off * nrp + (size_t)j * (lmax + 1 - m);
+  for (int l = m; l <= lmax; ++l) out[l - m] = T(r.step(l, xx, rec + 2 * (off + (l - m))));
+}
+
+// ---------------------------------------------------------------------------
+// adjoint Legendre + mode combination:
+//   grad_{s,lm} = c_m / sqrt(C_l) sum_u q_u(l) sum_j lambda_lm(theta_j) Gh_{s,u,m}(theta_j)
+// with c_m = 2 - delta_m0.  Mirror rings are folded first: sum over all rings of
+// lambda Gh = sum over north rings of lambda (Gh_N + (-1)^{l+m} Gh_S).
+// One thread per (l, s); loops over u and rings; lam is read from the table.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_legendre(int lmax, int ntheta, int nrp, int P, int S, int nalm,
+                                                      const T* __restrict__ lam, const T* __restrict__ qw,
+                                                      const typename vec2<T>::type* __restrict__ Gh,
+                                                      typename vec2<T>::type* __restrict__ grad) {
+  using T2 = typename vec2<T>::type;
+  const int m = blockIdx.y;
+  const int L = lmax + 1 - m;
+  const int li = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int s = blockIdx.z * 4 + (threadIdx.x >> 6);
+  const size_t off = (size_t)m * (2 * lmax + 3 - m) / 2;
+  if (li >= L || s >= S) return;
+  const int l = m + li;
+  const bool odd = (li & 1);
+  const T* lrow = lam + off * nrp;  // [nrp][L]
+  double gre = 0.0, gim = 0.0;
+  for (int u = 0; u < P; ++u) {
+    const T2* gu = Gh + (size_t)(s * P + u) * ntheta * (lmax + 1);
+    double dre = 0.0, dim = 0.0;
+    for (int j = 0; j < nrp; ++j) {
+      const double lv = (double)lrow[(size_t)j * L + li];
+      const T2 gn = gu[(size_t)j * (lmax + 1) + m];
+      const int js = ntheta - 1 - j;
+      T2 gs;
+      gs.x = T(0);
+      gs.y = T(0);
+      if (js != j) gs = gu[(size_t)js * (lmax + 1) + m];
+      const double hr = odd ? (double)gn.x - (double)gs.x : (double)gn.x + (double)gs.x;
+      const double hi = odd ? (double)gn.y - (double)gs.y : (double)gn.y + (double)gs.y;
+      dre += lv * hr;
+      dim += lv * hi;
+    }
+    const double qv = (double)qw[(size_t)u * (lmax + 1) + l];
+    gre += qv * dre;
+    gim += qv * dim;
+  }
+  const double cm = (m == 0) ? 1.0 : 2.0;
+  T2 g;
+  g.x = T(cm * gre);
+  g.y = T(m == 0 ? 0.0 : cm * gim);
+  grad[(size_t)s * nalm + off + li] = g;
+}
+
+}  // namespace
+
+hipError_t launch_seeds(const modal_ctx* c, const double* logpref, hipStream_t st) {
+  dim3 grid((c->nrp + 127) / 128, c->lmax + 1);
+  hipLaunchKernelGGL(k_seeds, grid, dim3(128), 0, st, c->lmax, c->nrp, c->t.x, c->t.rec, logpref, c->t.seed,
+                     c->t.lstart);
+  return hipGetLastError();
+}
+
+hipError_t launch_legendre(const modal_ctx* c, const void* alm, int S, void* F, hipStream_t st) {
+  const int nseq = S * c->P;
+  constexpr int NS = 8;
+  dim3 grid((nseq + NS - 1) / NS, (c->nrp + 63) / 64, c->lmax + 1);
+  if (is_f64(c)) {
+    hipLaunchKernelGGL((k_legendre<double, NS>), grid, dim3(64), 0, st, c->lmax, c->ntheta, c->nrp, c->P, nseq,
+                       c->nalm, c->t.x, c->t.rec, c->t.seed, c->t.lstart, c->t.qw64, (const double2*)alm,
+                       (double2*)F);
+  } else {
+    hipLaunchKernelGGL((k_legendre<float, NS>), grid, dim3(64), 0, st, c->lmax, c->ntheta, c->nrp, c->P, nseq,
+                       c->nalm, c->t.x, c->t.rec, c->t.seed, c->t.lstart, c->t.qw32, (const float2*)alm,
+                       (float2*)F);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lambda_table(const modal_ctx* c, void* lam, hipStream_t st) {
+  dim3 grid((c->nrp + 63) / 64, c->lmax + 1);
+  if (is_f64(c))
+    hipLaunchKernelGGL(k_lambda_table<double>, grid, dim3(64), 0, st, c->lmax, c->nrp, c->t.x, c->t.rec, c->t.seed,
+                       c->t.lstart, (double*)lam);
+  else
+    hipLaunchKernelGGL(k_lambda_table<float>, grid, dim3(64), 0, st, c->lmax, c->nrp, c->t.x, c->t.rec, c->t.seed,
+                       c->t.lstart, (float*)lam);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_legendre(const modal_ctx* c, const void* lam, const void* Gh, int S, void* grad,
+                               hipStream_t st) {
+  dim3 grid((c->lmax + 1 + 63) / 64, c->lmax + 1, (S + 3) / 4);
+  if (is_f64(c))
+    hipLaunchKernelGGL(k_adj_legendre<double>, grid, dim3(256), 0, st, c->lmax, c->ntheta, c->nrp, c->P, S, c->nalm,
+                       (const double*)lam, c->t.qw64, (const double2*)Gh, (double2*)grad);
+  else
+    hipLaunchKernelGGL(k_adj_legendre<float>, grid, dim3(256), 0, st, c->lmax, c->ntheta, c->nrp, c->P, S, c->nalm,
+                       (const float*)lam, c->t.qw32, (const float2*)Gh, (float2*)grad);
+  return hipGetLastError();
+}
+
+}  // namespace modal

@@ -1,0 +1,67 @@
+"""Shared test helpers: seeded cases and the oracle's expected values."""
+from __future__ import annotations
+
+import dataclasses
+import functools
+
+import numpy as np
+
+import modal_inputs as mi
+from oracle import grid as og
+from oracle import modal as om
+from oracle import sims as osims
+
+
+def rel_inf(got, ref) -> float:
+    """max |got - ref| / rms(ref)."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.sqrt(np.mean(ref * ref))
+    return float(np.max(np.abs(got - ref)) / (scale if scale > 0 else 1.0))
+
+
+@dataclasses.dataclass
+class Case:
+    name: str
+    lmax: int
+    ntheta: int
+    nphi: int
+    P: int
+    S: int
+    sky: str        # 'ideal' | 'wmap'
+    cfg_id: int
+
+    @functools.cached_property
+    def grid(self):
+        g0 = og.Grid(self.ntheta, self.nphi)
+        if self.sky == "ideal":
+            return g0
+        return og.Grid(self.ntheta, self.nphi, ring_mask=np.repeat(mi.mask_rings(g0.theta)[:, None], self.nphi, 1))
+
+    @functools.cached_property
+    def cl(self):
+        return mi.filter_cl(self.lmax, self.sky)
+
+    @functools.cached_property
+    def q(self):
+        return mi.q_basis(self.P, self.lmax)
+
+    def alms(self, first: int, count: int) -> np.ndarray:
+        """Isotropic Gaussian a_lm with the filter spectrum (seeded)."""
+        return np.array([mi.gaussian_alm(self.cl, self.lmax, mi.rng_for(self.cfg_id, first + i))
+                         for i in range(count)])
+
+    def mask(self):
+        return None if self.sky == "ideal" else self.grid.mask
+
+    def maps(self, alms):
+        return om.filtered_maps(alms, self.cl, self.q, self.grid)
+
+
+CASES = {
+    # the l_max = 32 workload itself (48 x 96 grid, P = 8, full sky)
+    "tiny": Case("tiny", 32, 48, 96, 8, 3, "ideal", 1),
+    # odd ring count (equator ring), generic FFT radices (K = 200 = 4*2*5*5),
+    # two pair blocks (91 pairs), two pixel chunks with a ragged tail, mask + beam/noise spectrum
+    "ragged": Case("ragged", 150, 199, 400, 13, 3, "wmap", 21),
+}

@@ -1,0 +1,237 @@
+"""GPU parity: libmodal (through the C ABI) against the FP64 oracle on the same
+seeded inputs.  Tolerances (max |diff| / rms(reference)): 1e-10 in FP64,
+1e-5 in FP32."""
+import numpy as np
+import pytest
+
+import modal_inputs as mi
+from oracle import closed_forms as cf
+from oracle import modal as om
+
+from helpers import CASES, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+# split-bf16 results carry the split error (about 2^-17 per product, a few 1e-6
+# of rms(beta) measured); 1e-4 is a sanity bound that catches layout or
+# operand mistakes, the measured error is logged per result
+TOL = {"f64": 1e-10, "f32": 1e-5, "bf16x3": 1e-4}
+MAP_TOL = {"f64": 1e-10, "f32": 1e-5, "bf16x3": 1e-5}   # maps are FP32 in both reduced precisions
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+_ctx_cache = {}
+
+
+def log_err(what, err):
+    """Append a measured error to $MODAL_ERR_LOG (informational)."""
+    import os
+    path = os.environ.get("MODAL_ERR_LOG")
+    print(f"[err] {what}: {err:.3e}", flush=True)
+    if path:
+        with open(path, "a") as f:
+            f.write(f"{what}\t{err:.6e}\n")
+
+
+def ctx_for(case, prec):
+    from paper_1105_2791_amd import ModalContext
+    key = (case.name, prec)
+    if key not in _ctx_cache:
+        print(f"[case] create {case.name} {prec}", flush=True)
+        _ctx_cache[key] = ModalContext(case.lmax, case.ntheta, case.nphi, case.P, prec, case.q, case.cl,
+                                       mask=case.mask())
+    return _ctx_cache[key]
+
+
+_oracle_cache = {}
+
+
+def oracle_for(case):
+    if case.name not in _oracle_cache:
+        alms = case.alms(0, case.S)
+        mc = case.alms(500, 4)
+        M = case.maps(alms)
+        Mmc = case.maps(mc)
+        V = om.pair_means(Mmc)
+        g = case.grid
+        beta = np.array([om.beta(M[i], g.w) for i in range(case.S)])
+        lin = np.array([om.linear_term(M[i], g.w, V) for i in range(case.S)])
+        _oracle_cache[case.name] = dict(alms=alms, mc=mc, M=M, V=V, beta=beta, lin=lin)
+    return _oracle_cache[case.name]
+
+
+CASE_PREC = [("tiny", "f64"), ("tiny", "f32"), ("tiny", "bf16x3"), ("ragged", "f64"), ("ragged", "f32"),
+             ("ragged", "bf16x3")]
+
+
+@pytest.mark.parametrize("name", ["tiny", "ragged"])
+def test_grid_matches_oracle(name):
+    case = CASES[name]
+    c = ctx_for(case, "f64")
+    x, w = c.grid()
+    assert np.max(np.abs(x - case.grid.x)) < 1e-14
+    assert np.max(np.abs(w - case.grid.wgl)) < 1e-14
+
+
+@pytest.mark.parametrize("name,prec", CASE_PREC)
+def test_filter_maps(name, prec):
+    case = CASES[name]
+    c = ctx_for(case, prec)
+    o = oracle_for(case)
+    print(f"[case] maps {name} {prec}", flush=True)
+    got = c.filter_maps(o["alms"]).cpu().numpy()
+    err = rel_inf(got, o["M"])
+    log_err(f"maps {name} {prec}", err)
+    assert err < MAP_TOL[prec]
+
+
+@pytest.mark.parametrize("name,prec", CASE_PREC)
+def test_beta_no_linear_term(name, prec):
+    case = CASES[name]
+    c = ctx_for(case, prec)
+    o = oracle_for(case)
+    print(f"[case] beta {name} {prec}", flush=True)
+    got = c.beta(o["alms"]).cpu().numpy()
+    err = max(rel_inf(got[i], o["beta"][i]) for i in range(case.S))
+    log_err(f"beta {name} {prec}", err)
+    assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("name,prec", CASE_PREC)
+def test_linear_term_and_beta_hat(name, prec):
+    case = CASES[name]
+    c = ctx_for(case, prec)
+    o = oracle_for(case)
+    print(f"[case] linear {name} {prec}", flush=True)
+    st = c.linear_state()
+    c.linear_reset(st)
+    c.linear_accumulate(st, o["mc"][:3])   # two batches of unequal size
+    c.linear_accumulate(st, o["mc"][3:])
+    c.linear_finalize(st)
+    V = c.pair_means(st).cpu().numpy()
+    # V_pr is a product of two maps: its error is bounded by the map error times
+    # rms(M_p) rms(M_r), i.e. twice the map tolerance in that norm
+    Mmc = case.maps(o["mc"])
+    rms = np.sqrt(np.mean(Mmc ** 2, axis=(0, 2, 3)))
+    pa = np.array([p for p, r in mi.pair_list(case.P)])
+    pb = np.array([r for p, r in mi.pair_list(case.P)])
+    errV = np.max(np.abs(V - o["V"]).reshape(len(pa), -1), axis=1) / (rms[pa] * rms[pb])
+    log_err(f"V {name} {prec}", float(errV.max()))
+    assert errV.max() < 2 * MAP_TOL[prec]
+    lin = c.linear_apply(st, o["alms"]).cpu().numpy()
+    bh = c.beta(o["alms"], state=st).cpu().numpy()
+    e_lin = max(rel_inf(lin[i], o["lin"][i]) for i in range(case.S))
+    e_bh = max(rel_inf(bh[i], o["beta"][i] - o["lin"][i]) for i in range(case.S))
+    log_err(f"lin {name} {prec}", e_lin)
+    log_err(f"beta_hat {name} {prec}", e_bh)
+    assert e_lin < TOL[prec] and e_bh < TOL[prec]
+
+
+@pytest.mark.parametrize("name,prec", CASE_PREC)
+def test_vjp_matches_oracle_gradient(name, prec):
+    case = CASES[name]
+    c = ctx_for(case, prec)
+    o = oracle_for(case)
+    print(f"[case] vjp {name} {prec}", flush=True)
+    st = c.linear_state()
+    c.linear_reset(st)
+    c.linear_accumulate(st, o["mc"])
+    c.linear_finalize(st)
+    rng = np.random.default_rng(17)
+    cot = rng.standard_normal((2, mi.ntriples(case.P)))
+    g = c.beta_vjp(o["alms"][:2], cot, state=st).cpu().numpy()
+    for i in range(2):
+        ref = om.vjp(o["alms"][i], case.cl, case.q, case.grid, o["V"], cot[i])[0]
+        err = np.linalg.norm(g[i] - ref) / np.linalg.norm(ref)
+        log_err(f"vjp {name} {prec} sim{i}", err)
+        assert err < MAP_TOL[prec], err
+
+
+def test_sample_covariance_and_estimator():
+    case = CASES["tiny"]
+    c = ctx_for(case, "f64")
+    rng = np.random.default_rng(3)
+    n = mi.ntriples(case.P)
+    B = rng.standard_normal((700, n)) * np.linspace(1.0, 3.0, n)
+    Z = c.covariance_sample(B).cpu().numpy()
+    Zo = om.covariance_sample(B)
+    assert np.linalg.norm(Z - Zo) / np.linalg.norm(Zo) < 1e-13
+    alpha = rng.standard_normal(n)
+    betas = rng.standard_normal((5, n))
+    E, s2, L = c.fnl(Zo, alpha, betas, want_L=True)
+    Eo, s2o, Lo = om.estimator(Zo, alpha, betas)
+    assert np.max(np.abs(E - Eo)) < 1e-10 * max(1.0, np.max(np.abs(Eo)))
+    assert abs(s2 - s2o) < 1e-12 * s2o
+    assert np.linalg.norm(L.cpu().numpy() - Lo) / np.linalg.norm(Lo) < 1e-12
+
+
+@pytest.mark.parametrize("n", [120, 455, 969])
+def test_cholesky_bivector_closed_form(n):
+    """Sec. III B: zeta = I + b b^T has a closed-form Cholesky factor and variance."""
+    case = CASES["tiny"]
+    c = ctx_for(case, "f64")
+    rng = np.random.default_rng(n)
+    bt = rng.standard_normal(n) * 0.3
+    Z = cf.bivector_zeta(bt)
+    alpha = rng.standard_normal(n)
+    # fnl works for any n: use a throwaway context whose nmax is n? the ABI ties n to P,
+    # so embed the problem in the context's nmax when it matches, else skip
+    if n != c.nmax:
+        P = {455: 13, 969: 17}.get(n)
+        if P is None:
+            pytest.skip("no P gives this nmax")
+        from paper_1105_2791_amd import ModalContext
+        c = ModalContext(8, 12, 24, P, "f64", np.ones((P, 9)), np.ones(9))
+    E, s2, L = c.fnl(Z, alpha, alpha[None, :], want_L=True)
+    assert abs(E[0] - 1.0) < 1e-12
+    assert abs(s2 - 6.0 * cf.bivector_variance(alpha, bt)) < 1e-12 * s2
+    Lc = cf.bivector_cholesky(bt)
+    assert np.max(np.abs(L.cpu().numpy() - Lc)) < 1e-12
+
+
+def test_fnl_reports_not_positive_definite():
+    from paper_1105_2791_amd import ModalError
+    case = CASES["tiny"]
+    c = ctx_for(case, "f64")
+    n = c.nmax
+    rng = np.random.default_rng(9)
+    B = rng.standard_normal((n // 2, n))          # rank n/2 < n: singular sample covariance
+    Z = c.covariance_sample(B)
+    with pytest.raises(ModalError) as ei:
+        c.fnl(Z, rng.standard_normal(n), rng.standard_normal((1, n)))
+    assert ei.value.status == 4
+
+
+def test_error_paths():
+    from paper_1105_2791_amd import ModalError
+    from paper_1105_2791_amd import _lib as L
+    case = CASES["tiny"]
+    c = ctx_for(case, "f64")
+    o = oracle_for(case)
+    st = c.linear_state()
+    c.linear_reset(st)
+    with pytest.raises(ModalError) as ei:          # state not finalised
+        c.beta(o["alms"][:1], state=st)
+    assert ei.value.status == L.ENOTREADY
+    with pytest.raises(ModalError) as ei:          # finalise with zero count
+        c.linear_finalize(st)
+    assert ei.value.status == L.ENOTREADY
+    a = torch.as_tensor(o["alms"][:1]).to("cuda", torch.complex128)
+    out = torch.empty((1, c.nmax), dtype=torch.float64, device="cuda")
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    import ctypes
+    stn = c._lib.modal_beta(c._h, a.data_ptr(), 1, None, out.data_ptr(), ws.data_ptr(), 16, None)
+    assert stn == L.ENOSPACE
+    stn = c._lib.modal_beta(c._h, None, 1, None, out.data_ptr(), ws.data_ptr(), 16, None)
+    assert stn == L.EINVAL
+    with pytest.raises(ModalError) as ei:
+        from paper_1105_2791_amd import ModalContext
+        ModalContext(32, 32, 96, 2, "f64", np.ones((2, 33)), np.ones(33))
+    assert ei.value.status == L.ESHAPE
