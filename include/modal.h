@@ -221,6 +221,28 @@ modal_status modal_fnl(modal_ctx* ctx, const double* zeta_dev, const double* alp
                        double* L_dev, void* ws_dev, size_t ws_bytes, modal_stream_t stream);
 
 /* ------------------------------------------------------------------------ */
+/* captured launches                                                         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct modal_graph modal_graph;
+
+/* Capture a sequence of modal_beta calls into one HIP graph (north-star
+ * batching: many Monte-Carlo maps, possibly of different l_max, replayed with
+ * one launch).  Call i uses ctxs[i], alms[i] ([S[i]][nalm_i] device),
+ * states[i] (finalised or NULL), betas[i] ([S[i]][nmax_i] device) and its own
+ * workspace ws[i] of ws_bytes[i] bytes; contexts must live on one device.
+ * Arguments are validated exactly as modal_beta does; the pointers are baked
+ * into the graph and must stay valid while it is used.  Capture runs on a
+ * private stream (nothing executes); replay with modal_graph_launch on any
+ * stream of that device.  Profiling is suspended during capture.
+ * Errors: EINVAL, ENOTREADY, ENOSPACE, EDEVICE (capture/instantiate failed). */
+modal_status modal_beta_graph_create(int n, modal_ctx* const* ctxs, const void* const* alms, const int* S,
+                                     const void* const* states, double* const* betas, void* const* ws,
+                                     const size_t* ws_bytes, modal_graph** out);
+modal_status modal_graph_launch(modal_graph* g, modal_stream_t stream);
+void modal_graph_destroy(modal_graph* g);
+
+/* ------------------------------------------------------------------------ */
 /* instrumentation                                                           */
 /* ------------------------------------------------------------------------ */
 

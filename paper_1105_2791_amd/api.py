@@ -187,6 +187,20 @@ class ModalContext:
                                                _ptr(ws), ws.numel(), self._stream()))
         return z
 
+    def covariance_fisher(self, alm, cvar, state=None) -> torch.Tensor:
+        """zeta_F = (1/(18N)) sum_i J_i C J_i^T for the N maps alm [N][nalm]; cvar[l] is the
+        variance C_l of a_lm (C_l for a_l0, C_l/2 for Re and Im of a_lm, m > 0)."""
+        a = self._alm(alm)
+        N = a.shape[0]
+        cv = np.ascontiguousarray(cvar, dtype=np.float64)
+        if cv.shape != (self.lmax + 1,):
+            raise ValueError("cvar must have lmax+1 entries")
+        z = torch.empty((self.nmax, self.nmax), dtype=torch.float64, device=self.device)
+        ws = self.workspace(L.OP_COVARIANCE_FISHER, N)
+        self._check(self._lib.modal_covariance(self._h, L.COV_FISHER, None, _ptr(a), _ptr(state), cv.ctypes.data,
+                                               N, _ptr(z), _ptr(ws), ws.numel(), self._stream()))
+        return z
+
     def fnl(self, zeta, alpha, beta, want_L: bool = False):
         z = torch.as_tensor(zeta).to(device=self.device, dtype=torch.float64).contiguous()
         al = torch.as_tensor(alpha).to(device=self.device, dtype=torch.float64).contiguous()
@@ -199,3 +213,51 @@ class ModalContext:
         self._check(self._lib.modal_fnl(self._h, _ptr(z), _ptr(al), _ptr(b), S, E.ctypes.data, s2.ctypes.data,
                                         _ptr(Ld), _ptr(ws), ws.numel(), self._stream()))
         return (E, float(s2[0]), Ld) if want_L else (E, float(s2[0]))
+
+
+class BetaGraph:
+    """A captured sequence of modal_beta calls (one per context, mixed l_max allowed),
+    replayed with a single graph launch.  Holds references to every tensor baked
+    into the graph."""
+
+    def __init__(self, calls):
+        """calls: list of (ModalContext, alm tensor [S][nalm], state or None)."""
+        self._lib = L.lib()
+        n = len(calls)
+        self.ctxs = [c for c, _, _ in calls]
+        self.alms = [c._alm(a) for c, a, _ in calls]
+        self.states = [st for _, _, st in calls]
+        self.betas = [torch.empty((a.shape[0], c.nmax), dtype=torch.float64, device=c.device)
+                      for (c, _, _), a in zip(calls, self.alms)]
+        self.ws = [torch.empty(max(256, c.workspace_size(L.OP_BETA, a.shape[0])), dtype=torch.uint8,
+                               device=c.device) for (c, _, _), a in zip(calls, self.alms)]
+        arr = lambda T, vals: (T * n)(*vals)
+        ctxs = arr(C.c_void_p, [c._h.value for c in self.ctxs])
+        alms = arr(C.c_void_p, [a.data_ptr() for a in self.alms])
+        Ss = arr(C.c_int, [a.shape[0] for a in self.alms])
+        sts = arr(C.c_void_p, [None if s is None else s.data_ptr() for s in self.states])
+        bts = arr(C.c_void_p, [b.data_ptr() for b in self.betas])
+        wss = arr(C.c_void_p, [w.data_ptr() for w in self.ws])
+        wsb = arr(C.c_size_t, [w.numel() for w in self.ws])
+        self._g = C.c_void_p()
+        st = self._lib.modal_beta_graph_create(n, ctxs, alms, Ss, sts, bts, wss, wsb, C.byref(self._g))
+        if st != L.OK:
+            raise L.ModalError(st, self._lib.modal_last_error(self.ctxs[0]._h).decode())
+
+    def launch(self):
+        dev = self.ctxs[0].device
+        st = self._lib.modal_graph_launch(self._g, C.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
+        if st != L.OK:
+            raise L.ModalError(st, "graph launch failed")
+        return self.betas
+
+    def close(self):
+        if getattr(self, "_g", None) is not None and self._g.value:
+            self._lib.modal_graph_destroy(self._g)
+            self._g = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -84,6 +84,14 @@ hipError_t launch_legendre(const modal_ctx* c, const void* alm, int S, void* F, 
 hipError_t launch_fft_c2r(const modal_ctx* c, const void* F, int S, void* maps, hipStream_t st);
 // ring r2c FFT: Gh[S][P][ntheta][lmax+1] complex from G[S][P][ntheta][nphi]
 hipError_t launch_fft_r2c(const modal_ctx* c, const void* G, int S, void* Gh, hipStream_t st);
+hipError_t launch_fft_r2c_rows(const modal_ctx* c, const void* G, size_t rows, void* Gh, hipStream_t st);
+
+// Fisher covariance from pair adjoints
+hipError_t launch_pair_maps(const modal_ctx* c, const void* maps, const void* V, void* G, hipStream_t st);
+hipError_t launch_adj_legendre_cols(const modal_ctx* c, const void* lam, const void* Gh, int ncol, void* Z,
+                                    hipStream_t st);
+hipError_t launch_cross_spectra(const modal_ctx* c, const void* Z, const double* cvar, double* X, hipStream_t st);
+hipError_t launch_fisher_assemble(const modal_ctx* c, const double* X, double scale, double* F, hipStream_t st);
 
 // cubic pixel reduction.  mode: 0 = A = M_p M_r, 1 = M_p M_r - 3 V, 2 = A = V
 // partials[S][nchunk][npairs][P] float64
@@ -111,8 +119,6 @@ hipError_t launch_adj_legendre(const modal_ctx* c, const void* lam, const void* 
 
 // FP64 dense linear algebra
 hipError_t launch_syrk(int n, int N, const double* B, double scale, double* Z, hipStream_t st);
-hipError_t launch_fisher_accumulate(const modal_ctx* c, const void* grads, const double* cvar, int nrow,
-                                    double scale, double* Z, hipStream_t st);
 hipError_t launch_copy_lower(int n, const double* src, double* dst, hipStream_t st);
 // in-place Cholesky of the lower triangle of A (row-major, n x n); flag[0] = 1 + first bad pivot
 hipError_t launch_cholesky(int n, double* A, int* flag, hipStream_t st);

@@ -137,6 +137,12 @@ size_t ws_size(const modal_ctx* c, int op, int S) {
       cv.take(maps_bytes(c, S)); cv.take(F_bytes(c, S)); cv.take(lam_bytes(c));
       break;
     case MODAL_OP_COVARIANCE_SAMPLE: cv.take(256); break;
+    case MODAL_OP_COVARIANCE_FISHER:
+      cv.take(F_bytes(c, 1)); cv.take(maps_bytes(c, 1)); cv.take((size_t)c->npairs * c->npix * real_bytes(c));
+      cv.take((size_t)c->npairs * c->ntheta * (c->lmax + 1) * 2 * real_bytes(c)); cv.take(lam_bytes(c));
+      cv.take((size_t)c->npairs * c->nalm * 2 * real_bytes(c));
+      cv.take((size_t)(c->lmax + 1) * c->npairs * c->npairs * 8); cv.take((size_t)(c->lmax + 1) * 8);
+      break;
     case MODAL_OP_FNL:
       cv.take((size_t)c->nmax * c->nmax * 8); cv.take((size_t)(S + 1) * c->nmax * 8); cv.take((size_t)(S + 1) * 8);
       cv.take(16);
@@ -404,7 +410,6 @@ modal_status modal_grid(const modal_ctx* c, double* x_host, double* w_host) {
 
 modal_status modal_workspace_size(const modal_ctx* c, int op, int S, size_t* bytes) {
   if (!c || !bytes || S < 0 || op < MODAL_OP_FILTER_MAPS || op > MODAL_OP_FNL) return MODAL_EINVAL;
-  if (op == MODAL_OP_COVARIANCE_FISHER) return MODAL_EUNSUPPORTED;
   *bytes = ws_size(c, op, S);
   return MODAL_OK;
 }
@@ -519,9 +524,6 @@ modal_status modal_beta_vjp(modal_ctx* c, const void* alm, int S, const void* st
 modal_status modal_covariance(modal_ctx* c, int method, const double* beta, const void* alm, const void* state,
                               const double* cvar_host, int N, double* zeta, void* ws, size_t ws_bytes,
                               modal_stream_t stream) {
-  (void)alm;
-  (void)state;
-  (void)cvar_host;
   if (!c) return MODAL_EINVAL;
   if (!zeta || N <= 0) return fail(c, MODAL_EINVAL, "covariance: null zeta or N <= 0");
   modal_status s = set_device(c);
@@ -532,7 +534,36 @@ modal_status modal_covariance(modal_ctx* c, int method, const double* beta, cons
     STAGE(MODAL_STAGE_COVARIANCE, launch_syrk(c->nmax, N, beta, 1.0 / (6.0 * N), zeta, st));
     return MODAL_OK;
   }
-  if (method == MODAL_COV_FISHER) return fail(c, MODAL_EUNSUPPORTED, "covariance: FISHER not available");
+  if (method == MODAL_COV_FISHER) {
+    if (!alm || !cvar_host) return fail(c, MODAL_EINVAL, "covariance: FISHER needs alm and cvar");
+    if ((s = check_state(c, state)) != MODAL_OK) return s;
+    if ((s = check_ws(c, MODAL_OP_COVARIANCE_FISHER, N, ws, ws_bytes)) != MODAL_OK) return s;
+    Carver cv(ws);
+    void* F = cv.take(F_bytes(c, 1));
+    void* maps = cv.take(maps_bytes(c, 1));
+    void* G = cv.take((size_t)c->npairs * c->npix * real_bytes(c));
+    void* Gh = cv.take((size_t)c->npairs * c->ntheta * (c->lmax + 1) * 2 * real_bytes(c));
+    void* lam = cv.take(lam_bytes(c));
+    void* Z = cv.take((size_t)c->npairs * c->nalm * 2 * real_bytes(c));
+    const size_t xbytes = (size_t)(c->lmax + 1) * c->npairs * c->npairs * 8;
+    double* X = (double*)cv.take(xbytes);
+    double* cvar = (double*)cv.take((size_t)(c->lmax + 1) * 8);
+    HIPTRY(hipMemcpyAsync(cvar, cvar_host, (size_t)(c->lmax + 1) * 8, hipMemcpyHostToDevice, st));
+    HIPTRY(hipStreamSynchronize(st));   // cvar_host may be released on return
+    HIPTRY(launch_zero(X, xbytes, st));
+    STAGE(MODAL_STAGE_ADJ_LEGENDRE, launch_lambda_table(c, lam, st));
+    const size_t abytes = alm_bytes(c);
+    for (int i = 0; i < N; ++i) {
+      const void* ai = (const char*)alm + (size_t)i * abytes;
+      if ((s = run_maps(c, ai, 1, F, maps, st)) != MODAL_OK) return s;
+      STAGE(MODAL_STAGE_ADJ_PAIR, launch_pair_maps(c, maps, state, G, st));
+      STAGE(MODAL_STAGE_ADJ_FFT, launch_fft_r2c_rows(c, G, (size_t)c->npairs * c->ntheta, Gh, st));
+      STAGE(MODAL_STAGE_ADJ_LEGENDRE, launch_adj_legendre_cols(c, lam, Gh, c->npairs, Z, st));
+      STAGE(MODAL_STAGE_COVARIANCE, launch_cross_spectra(c, Z, cvar, X, st));
+    }
+    STAGE(MODAL_STAGE_COVARIANCE, launch_fisher_assemble(c, X, 1.0 / (18.0 * N), zeta, st));
+    return MODAL_OK;
+  }
   return fail(c, MODAL_EINVAL, "covariance: bad method");
 }
 
@@ -574,6 +605,89 @@ modal_status modal_fnl(modal_ctx* c, const double* zeta, const double* alpha, co
   *sigma2_host = 6.0 / yy;
   for (int i = 0; i < S; ++i) E_host[i] = h[1 + i] / yy;
   return MODAL_OK;
+}
+
+}  // extern "C"
+
+struct modal_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = 0;
+};
+
+extern "C" {
+
+modal_status modal_beta_graph_create(int n, modal_ctx* const* ctxs, const void* const* alms, const int* S,
+                                     const void* const* states, double* const* betas, void* const* ws,
+                                     const size_t* ws_bytes, modal_graph** out) {
+  if (!out) return MODAL_EINVAL;
+  *out = nullptr;
+  if (n <= 0 || !ctxs || !alms || !S || !betas || !ws || !ws_bytes) return MODAL_EINVAL;
+  const int dev = ctxs[0] ? ctxs[0]->device : -1;
+  // validate everything before capturing
+  for (int i = 0; i < n; ++i) {
+    modal_ctx* c = ctxs[i];
+    if (!c || c->device != dev) return MODAL_EINVAL;
+    if (!alms[i] || !betas[i] || S[i] <= 0) return fail(c, MODAL_EINVAL, "graph: null pointer or S <= 0");
+    modal_status s = check_state(c, states ? states[i] : nullptr);
+    if (s != MODAL_OK) return s;
+    if ((s = check_ws(c, MODAL_OP_BETA, S[i], ws[i], ws_bytes[i])) != MODAL_OK) return s;
+  }
+  modal_ctx* c = ctxs[0];
+  modal_status s = set_device(c);
+  if (s != MODAL_OK) return s;
+  hipStream_t cap = nullptr;
+  HIPTRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  std::vector<bool> prof(n);
+  for (int i = 0; i < n; ++i) {
+    prof[i] = ctxs[i]->profile;
+    ctxs[i]->profile = false;
+  }
+  modal_status rs = MODAL_OK;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (int i = 0; i < n && rs == MODAL_OK; ++i)
+      rs = modal_beta(ctxs[i], alms[i], S[i], states ? states[i] : nullptr, betas[i], ws[i], ws_bytes[i], cap);
+    hipError_t e2 = hipStreamEndCapture(cap, &graph);
+    if (e == hipSuccess) e = e2;
+  }
+  for (int i = 0; i < n; ++i) ctxs[i]->profile = prof[i];
+  (void)hipStreamDestroy(cap);
+  if (rs != MODAL_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rs;
+  }
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(c, MODAL_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  modal_graph* g = new (std::nothrow) modal_graph();
+  if (!g) {
+    (void)hipGraphDestroy(graph);
+    return MODAL_EDEVICE;
+  }
+  g->graph = graph;
+  g->device = dev;
+  e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    modal_graph_destroy(g);
+    return fail(c, MODAL_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  }
+  *out = g;
+  return MODAL_OK;
+}
+
+modal_status modal_graph_launch(modal_graph* g, modal_stream_t stream) {
+  if (!g || !g->exec) return MODAL_EINVAL;
+  return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? MODAL_OK : MODAL_EDEVICE;
+}
+
+void modal_graph_destroy(modal_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
 }
 
 modal_status modal_profile_enable(modal_ctx* c, int enable) {

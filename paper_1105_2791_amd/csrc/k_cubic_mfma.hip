@@ -146,12 +146,14 @@ __global__ __launch_bounds__(NT) void k_cubic_mfma(int P, int npairs, int npix, 
     }
     __syncthreads();
 
-    if (a0 >= 0) {
+    {
+      // Every lane runs this block: an MFMA reads its operands from all 64 lanes,
+      // so no lane may skip it; lane-rows without a block contribute A = 0.
       // the six map rows this lane needs, at its 8 pixels (x0 + 8 kg .. + 7)
       float ma[2][8], mb[4][8];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int p = min(a0 + u, P - 1);
+        const int p = min(max(a0, 0) + u, P - 1);
 #pragma unroll
         for (int k = 0; k < 8; ++k) ma[u][k] = Ms[p][8 * kg + k];
       }
@@ -172,19 +174,17 @@ __global__ __launch_bounds__(NT) void k_cubic_mfma(int P, int npairs, int npix, 
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           float av[8];
-          if (pidx[j] >= 0) {
+          const bool pv = pidx[j] >= 0;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-              if (MODE == 0) av[k] = ma[j >> 2][k] * mb[j & 3][k];
-              else {
-                const int x = xl + k;
-                const float vv = x < x_end ? V[(size_t)pidx[j] * npix + x] : 0.f;
-                av[k] = (MODE == 1) ? fmaf(ma[j >> 2][k], mb[j & 3][k], -3.f * vv) : vv;
-              }
+          for (int k = 0; k < 8; ++k) {
+            float v;
+            if (MODE == 0) v = ma[j >> 2][k] * mb[j & 3][k];
+            else {
+              const int x = xl + k;
+              const float vv = (pv && x < x_end) ? V[(size_t)pidx[j] * npix + x] : 0.f;
+              v = (MODE == 1) ? fmaf(ma[j >> 2][k], mb[j & 3][k], -3.f * vv) : vv;
             }
-          } else {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) av[k] = 0.f;
+            av[k] = pv ? v : 0.f;
           }
           bf16x8 ah, al;
           split8(av, ah, al);
@@ -204,19 +204,17 @@ __global__ __launch_bounds__(NT) void k_cubic_mfma(int P, int npairs, int npix, 
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           float av[8];
-          if (pidx[j] >= 0) {
+          const bool pv = pidx[j] >= 0;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-              if (MODE == 0) av[k] = ma[j >> 2][k] * mb[j & 3][k];
-              else {
-                const int x = xl + k;
-                const float vv = x < x_end ? V[(size_t)pidx[j] * npix + x] : 0.f;
-                av[k] = (MODE == 1) ? fmaf(ma[j >> 2][k], mb[j & 3][k], -3.f * vv) : vv;
-              }
+          for (int k = 0; k < 8; ++k) {
+            float v;
+            if (MODE == 0) v = ma[j >> 2][k] * mb[j & 3][k];
+            else {
+              const int x = xl + k;
+              const float vv = (pv && x < x_end) ? V[(size_t)pidx[j] * npix + x] : 0.f;
+              v = (MODE == 1) ? fmaf(ma[j >> 2][k], mb[j & 3][k], -3.f * vv) : vv;
             }
-          } else {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) av[k] = 0.f;
+            av[k] = pv ? v : 0.f;
           }
 #pragma unroll
           for (int k = 0; k < 8; ++k)

@@ -196,7 +196,10 @@ hipError_t launch_fft_c2r(const modal_ctx* c, const void* F, int S, void* maps, 
 }
 
 hipError_t launch_fft_r2c(const modal_ctx* c, const void* G, int S, void* Gh, hipStream_t st) {
-  const size_t rows = (size_t)S * c->P * c->ntheta;
+  return launch_fft_r2c_rows(c, G, (size_t)S * c->P * c->ntheta, Gh, st);
+}
+
+hipError_t launch_fft_r2c_rows(const modal_ctx* c, const void* G, size_t rows, void* Gh, hipStream_t st) {
   const size_t lds = 2 * (size_t)c->fft.K * 2 * real_bytes(c);
   if (is_f64(c))
     hipLaunchKernelGGL(k_fft_r2c<double>, dim3(rows), dim3(256), lds, st, c->fft, c->lmax, (const double*)G,

@@ -1,0 +1,258 @@
+// Fisher estimate of the modal covariance from gradients.
+//
+// For Gaussian maps with exact pairing expectation in the linear term,
+// E[J C J^T] = 18 zeta (J = d beta^hat / d a over the real dof of a, C their
+// covariance), which follows from eq. (linearterm): beta^hat = T(aaa) - 3 T(C a)
+// so J = 3 T(aa - C, .) and the expectation counts 18 of the Wick pairings that
+// give 6 zeta in <beta^hat beta^hat^T>.  Hence zeta_F = (1/(18N)) sum_i J_i C J_i^T.
+//
+// J never needs forming: with qw = q / sqrt(C_l),
+//   J_{prs,lm} = qw_p(l) Z_{rs,lm} + qw_r(l) Z_{ps,lm} + qw_s(l) Z_{pr,lm},
+//   Z_{ab,lm}  = c_m sum_j lambda_lm(theta_j) sum_k w (M_a M_b - V_ab)(theta_j, phi_k) e^{-i m phi_k}
+// (c_m = 2 - delta_m0; Re/Im of Z are the derivatives with respect to Re/Im a_lm),
+// so J C J^T only needs, per l, the cross spectra of the pair adjoints
+//   X_l[a][b] = C_l [Re Z_a(l,0) Re Z_b(l,0) + 1/2 sum_{m>=1} (Re Z_a Re Z_b + Im Z_a Im Z_b)],
+// accumulated over maps, and the assembly
+//   F_{nn'} = (1/(18N)) sum over the 3 x 3 leg choices of sum_l qw_u(l) qw_u'(l) X_l[pair][pair'].
+#include "common.h"
+
+namespace modal {
+namespace {
+
+template <typename T> struct vec2;
+template <> struct vec2<float> { using type = float2; };
+template <> struct vec2<double> { using type = double2; };
+
+// G[pair][x] = w(x) (M_a M_b - V_ab)(x) for one map.
+template <typename T, bool LIN>
+__global__ __launch_bounds__(256) void k_pair_maps(int npairs, int npix, const int* __restrict__ pa,
+                                                   const int* __restrict__ pb, const T* __restrict__ maps,
+                                                   const T* __restrict__ V, const T* __restrict__ w,
+                                                   T* __restrict__ G) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  const int pair = blockIdx.y;
+  if (x >= npix) return;
+  const int a = pa[pair], b = pb[pair];
+  double v = (double)maps[(size_t)a * npix + x] * (double)maps[(size_t)b * npix + x];
+  if (LIN) v -= (double)V[(size_t)pair * npix + x];
+  G[(size_t)pair * npix + x] = T(v * (double)w[x]);
+}
+
+// Z[col][lm] = c_m sum_j lambda_lm(theta_j) (Gh_N +- Gh_S)(col, m), one thread per l,
+// NC columns per thread, ring values staged in LDS.
+constexpr int NC = 16;
+constexpr int RCH = 64;
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_adj_legendre_cols(int lmax, int ntheta, int nrp, int ncol, int nalm,
+                                                          const T* __restrict__ lam,
+                                                          const typename vec2<T>::type* __restrict__ Gh,
+                                                          typename vec2<T>::type* __restrict__ Z) {
+  using T2 = typename vec2<T>::type;
+  const int m = blockIdx.y;
+  const int L = lmax + 1 - m;
+  const int li = blockIdx.x * 64 + threadIdx.x;
+  const int c0 = blockIdx.z * NC;
+  const size_t off = (size_t)m * (2 * lmax + 3 - m) / 2;
+  const T* lrow = lam + off * nrp;
+  __shared__ T2 hn[RCH][NC];
+  __shared__ T2 hs[RCH][NC];
+  double ar[NC], ai[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) ar[q] = ai[q] = 0.0;
+  const bool odd = (li & 1);
+  for (int j0 = 0; j0 < nrp; j0 += RCH) {
+    const int nj = min(RCH, nrp - j0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < RCH * NC; e += 64) {
+      const int jj = e / NC, q = e - jj * NC;
+      T2 vn, vs;
+      vn.x = vn.y = vs.x = vs.y = T(0);
+      const int col = c0 + q, j = j0 + jj;
+      if (jj < nj && col < ncol) {
+        const T2* g = Gh + (size_t)col * ntheta * (lmax + 1);
+        vn = g[(size_t)j * (lmax + 1) + m];
+        const int js = ntheta - 1 - j;
+        if (js != j) vs = g[(size_t)js * (lmax + 1) + m];
+      }
+      hn[jj][q] = vn;
+      hs[jj][q] = vs;
+    }
+    __syncthreads();
+    if (li < L) {
+      for (int jj = 0; jj < nj; ++jj) {
+        const double lv = (double)lrow[(size_t)(j0 + jj) * L + li];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          const T2 n = hn[jj][q], s = hs[jj][q];
+          const double hr = odd ? (double)n.x - (double)s.x : (double)n.x + (double)s.x;
+          const double hi = odd ? (double)n.y - (double)s.y : (double)n.y + (double)s.y;
+          ar[q] += lv * hr;
+          ai[q] += lv * hi;
+        }
+      }
+    }
+  }
+  if (li >= L) return;
+  const double cm = (m == 0) ? 1.0 : 2.0;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const int col = c0 + q;
+    if (col >= ncol) break;
+    T2 z;
+    z.x = T(cm * ar[q]);
+    z.y = T(m == 0 ? 0.0 : cm * ai[q]);
+    Z[(size_t)col * nalm + off + li] = z;
+  }
+}
+
+// X[l][a][b] += C_l [Re Za Re Zb (m=0) + 1/2 sum_{m>=1} (Re Za Re Zb + Im Za Im Zb)], 64x64 tiles, lower tiles only.
+constexpr int XT = 64;
+constexpr int MC = 16;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cross_spectra(int lmax, int npairs, int nalm,
+                                                       const typename vec2<T>::type* __restrict__ Z,
+                                                       const double* __restrict__ cvar, double* __restrict__ X) {
+  using T2 = typename vec2<T>::type;
+  const int l = blockIdx.z;
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  if (bj > bi) return;
+  const int i0 = bi * XT, j0 = bj * XT;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  __shared__ double Zi[2 * MC][XT + 1];
+  __shared__ double Zj[2 * MC][XT + 1];
+  double acc[4][4] = {};
+  for (int m0 = 0; m0 <= l; m0 += MC) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < MC * XT; e += 256) {
+      const int mm = e / XT, r = e - mm * XT;
+      const int m = m0 + mm;
+      double ir = 0, ii = 0, jr = 0, jim = 0;
+      if (m <= l) {
+        const size_t idx = (size_t)m * (2 * lmax + 3 - m) / 2 + (l - m);
+        const double wgt = (m == 0) ? 1.0 : 0.7071067811865476;  // sqrt(1/2) per factor
+        if (i0 + r < npairs) {
+          const T2 z = Z[(size_t)(i0 + r) * nalm + idx];
+          ir = wgt * (double)z.x;
+          ii = (m == 0) ? 0.0 : wgt * (double)z.y;
+        }
+        if (j0 + r < npairs) {
+          const T2 z = Z[(size_t)(j0 + r) * nalm + idx];
+          jr = wgt * (double)z.x;
+          jim = (m == 0) ? 0.0 : wgt * (double)z.y;
+        }
+      }
+      Zi[2 * mm][r] = ir;
+      Zi[2 * mm + 1][r] = ii;
+      Zj[2 * mm][r] = jr;
+      Zj[2 * mm + 1][r] = jim;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < 2 * MC; ++k) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = Zi[k][ty * 4 + u];
+        b[u] = Zj[k][tx * 4 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+    }
+  }
+  const double cl = cvar[l];
+  double* Xl = X + (size_t)l * npairs * npairs;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + ty * 4 + u, j = j0 + tx * 4 + v;
+      if (i < npairs && j < npairs && j <= i) {
+        const double d = cl * acc[u][v];
+        Xl[(size_t)i * npairs + j] += d;
+        if (i != j) Xl[(size_t)j * npairs + i] += d;
+      }
+    }
+}
+
+// F[n][n'] = scale sum_{legs} sum_l qw_u(l) qw_u'(l) X_l[pair][pair'] (n <= n', mirrored).
+__global__ __launch_bounds__(256) void k_fisher_assemble(int nmax, int npairs, int lmax, const int* __restrict__ tri,
+                                                         const double* __restrict__ qw, const double* __restrict__ X,
+                                                         double scale, double* __restrict__ F) {
+  const int n = blockIdx.y;
+  const int np = blockIdx.x * 256 + threadIdx.x;
+  if (np >= nmax || np < n) return;
+  const int* t1 = tri + 6 * n;
+  const int* t2 = tri + 6 * np;
+  // legs: (u, complementary pair): (p, rs), (r, ps), (s, pr)
+  const int u1[3] = {t1[0], t1[1], t1[2]}, c1[3] = {t1[5], t1[4], t1[3]};
+  const int u2[3] = {t2[0], t2[1], t2[2]}, c2[3] = {t2[5], t2[4], t2[3]};
+  const size_t pp = (size_t)npairs * npairs;
+  double acc = 0.0;
+  for (int l = 0; l <= lmax; ++l) {
+    const double* Xl = X + l * pp;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double qa = qw[(size_t)u1[a] * (lmax + 1) + l];
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        acc += qa * qw[(size_t)u2[b] * (lmax + 1) + l] * Xl[(size_t)c1[a] * npairs + c2[b]];
+    }
+  }
+  F[(size_t)n * nmax + np] = scale * acc;
+  F[(size_t)np * nmax + n] = scale * acc;
+}
+
+}  // namespace
+
+hipError_t launch_pair_maps(const modal_ctx* c, const void* maps, const void* V, void* G, hipStream_t st) {
+  dim3 grid((c->npix + 255) / 256, c->npairs);
+#define LAUNCH(T, L, W)                                                                                     \
+  hipLaunchKernelGGL((k_pair_maps<T, L>), grid, dim3(256), 0, st, c->npairs, c->npix, c->t.pair_a,         \
+                     c->t.pair_b, (const T*)maps, (const T*)V, (const T*)W, (T*)G)
+  if (is_f64(c)) {
+    if (V) LAUNCH(double, true, c->t.w64);
+    else LAUNCH(double, false, c->t.w64);
+  } else {
+    if (V) LAUNCH(float, true, c->t.w32);
+    else LAUNCH(float, false, c->t.w32);
+  }
+#undef LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_legendre_cols(const modal_ctx* c, const void* lam, const void* Gh, int ncol, void* Z,
+                                    hipStream_t st) {
+  dim3 grid((c->lmax + 1 + 63) / 64, c->lmax + 1, (ncol + NC - 1) / NC);
+  if (is_f64(c))
+    hipLaunchKernelGGL(k_adj_legendre_cols<double>, grid, dim3(64), 0, st, c->lmax, c->ntheta, c->nrp, ncol, c->nalm,
+                       (const double*)lam, (const double2*)Gh, (double2*)Z);
+  else
+    hipLaunchKernelGGL(k_adj_legendre_cols<float>, grid, dim3(64), 0, st, c->lmax, c->ntheta, c->nrp, ncol, c->nalm,
+                       (const float*)lam, (const float2*)Gh, (float2*)Z);
+  return hipGetLastError();
+}
+
+hipError_t launch_cross_spectra(const modal_ctx* c, const void* Z, const double* cvar, double* X, hipStream_t st) {
+  const int nb = (c->npairs + XT - 1) / XT;
+  dim3 grid(nb, nb, c->lmax + 1);
+  if (is_f64(c))
+    hipLaunchKernelGGL(k_cross_spectra<double>, grid, dim3(256), 0, st, c->lmax, c->npairs, c->nalm,
+                       (const double2*)Z, cvar, X);
+  else
+    hipLaunchKernelGGL(k_cross_spectra<float>, grid, dim3(256), 0, st, c->lmax, c->npairs, c->nalm,
+                       (const float2*)Z, cvar, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_fisher_assemble(const modal_ctx* c, const double* X, double scale, double* F, hipStream_t st) {
+  dim3 grid((c->nmax + 255) / 256, c->nmax);
+  hipLaunchKernelGGL(k_fisher_assemble, grid, dim3(256), 0, st, c->nmax, c->npairs, c->lmax, c->t.tri, c->t.qw64, X,
+                     scale, F);
+  return hipGetLastError();
+}
+
+}  // namespace modal

@@ -235,3 +235,88 @@ def test_error_paths():
         from paper_1105_2791_amd import ModalContext
         ModalContext(32, 32, 96, 2, "f64", np.ones((2, 33)), np.ones(33))
     assert ei.value.status == L.ESHAPE
+
+
+@pytest.mark.parametrize("name,prec", [("tiny", "f64"), ("tiny", "f32"), ("ragged", "f64")])
+def test_fisher_covariance_matches_oracle(name, prec):
+    case = CASES[name]
+    c = ctx_for(case, prec)
+    o = oracle_for(case)
+    print(f"[case] fisher {name} {prec}", flush=True)
+    st = c.linear_state()
+    c.linear_reset(st)
+    c.linear_accumulate(st, o["mc"])
+    c.linear_finalize(st)
+    alms = o["alms"][:2]
+    Fg = c.covariance_fisher(alms, case.cl, state=st).cpu().numpy()
+    Fo = om.fisher(alms, case.cl, case.cl, case.q, case.grid, o["V"])
+    err = np.linalg.norm(Fg - Fo) / np.linalg.norm(Fo)
+    log_err(f"fisher {name} {prec}", err)
+    assert err < MAP_TOL[prec]
+
+
+def test_autograd_matches_finite_differences_and_oracle():
+    """Gradient of L = sum_n c_n beta^hat_n through torch.autograd: FP64 GPU forward
+    finite differences (4-point stencil, exact for a cubic) and the oracle VJP."""
+    from paper_1105_2791_amd.autograd import modal_beta
+    case = CASES["ragged"]
+    c = ctx_for(case, "f64")
+    o = oracle_for(case)
+    st = c.linear_state()
+    c.linear_reset(st)
+    c.linear_accumulate(st, o["mc"])
+    c.linear_finalize(st)
+    rng = np.random.default_rng(23)
+    cot = torch.as_tensor(rng.standard_normal(mi.ntriples(case.P)), device="cuda")
+    a = torch.as_tensor(o["alms"][0], device="cuda").clone().requires_grad_(True)
+    loss = (modal_beta(a, c, st) * cot).sum()
+    loss.backward()
+    g = a.grad.detach().cpu().numpy()
+    ref = om.vjp(o["alms"][0], case.cl, case.q, case.grid, o["V"], cot.cpu().numpy())[0]
+    assert np.linalg.norm(g - ref) / np.linalg.norm(ref) < 1e-10
+    # finite differences on 64 random real dof, batched as perturbed maps
+    l, m = mi.lm_arrays(case.lmax)
+    cand = np.where(l >= 2)[0]
+    idx = rng.choice(cand, 64, replace=False)
+    parts = [1.0 if m[k] == 0 or rng.random() < 0.5 else 1j for k in idx]
+    base = o["alms"][0]
+    pert = []
+    hs = []
+    for k, part in zip(idx, parts):
+        h = 1e-4 * max(abs(base[k]), np.sqrt(case.cl[l[k]] / 2))
+        hs.append(h)
+        for f in (1, -1, 2, -2):
+            e = base.copy()
+            e[k] += f * h * part
+            pert.append(e)
+    B = c.beta(np.array(pert), state=st).cpu().numpy() @ cot.cpu().numpy()
+    B = B.reshape(64, 4)
+    fd = (8 * (B[:, 0] - B[:, 1]) - (B[:, 2] - B[:, 3])) / (12 * np.array(hs))
+    got = np.array([g[k].real if p == 1.0 else g[k].imag for k, p in zip(idx, parts)])
+    err = np.max(np.abs(got - fd)) / np.sqrt(np.mean(fd ** 2))
+    log_err("autograd fd ragged f64", err)
+    assert err < 1e-7
+
+
+def test_graph_replay_mixed_lmax():
+    """Two contexts of different l_max captured into one graph; every replay (with
+    eager work and synchronisation in between) equals the eager result."""
+    from paper_1105_2791_amd.api import BetaGraph
+    ca, cb = CASES["tiny"], CASES["ragged"]
+    xa, xb = ctx_for(ca, "f32"), ctx_for(cb, "bf16x3")
+    oa, ob = oracle_for(ca), oracle_for(cb)
+    st = xb.linear_state()
+    xb.linear_reset(st)
+    xb.linear_accumulate(st, ob["mc"])
+    xb.linear_finalize(st)
+    ea = xa.beta(oa["alms"]).cpu().numpy()
+    eb = xb.beta(ob["alms"], state=st).cpu().numpy()
+    g = BetaGraph([(xa, oa["alms"], None), (xb, ob["alms"], st)])
+    for rep in range(3):
+        ba, bb = g.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(ba.cpu().numpy(), ea), rep
+        assert np.array_equal(bb.cpu().numpy(), eb), rep
+        xa.beta(oa["alms"][:1])          # eager work between replays
+        torch.cuda.synchronize()
+    g.close()
