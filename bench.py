@@ -93,6 +93,7 @@ def main():
     ap.add_argument("--mc", type=int, default=16, help="Monte-Carlo skies for the linear term")
     ap.add_argument("--cpu-rings", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -139,6 +140,10 @@ def main():
     torch.cuda.synchronize()
     log("bench: state ready")
 
+    tuned = None
+    if not args.no_autotune:
+        tuned = ctx.autotune(alm, state)
+        log(f"bench: autotuned {tuned}")
     for _ in range(args.warmup):
         ctx.beta(alm, state=state, out=out)
     torch.cuda.synchronize()
@@ -197,7 +202,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"metric1000: lmax={lmax} GL {nt}x{nphi} P={P} nmax={ctx.nmax}, "
                                f"beam+noise spectrum, |lat|<10deg cut, MC linear term ({args.mc} skies)",
-                   "batch": S, "prec": prec},
+                   "batch": S, "prec": prec, "tuned": tuned},
         "stages_ms": {k: v[0] / max(1, v[1]) for k, v in stages.items() if v[1]},
         "roofline": roof,
         "cpu_baseline": cpu,

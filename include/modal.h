@@ -81,8 +81,12 @@ typedef enum {
 typedef enum {
   MODAL_F64 = 0,     /* FP64 everywhere                                          */
   MODAL_F32 = 1,     /* FP32 maps, FP32 MFMA contractions, FP64 recurrence/reductions */
-  MODAL_BF16X3 = 2,  /* split bf16 hi+lo (3 MFMA products), FP32 accumulation    */
-  MODAL_F16X3 = 3    /* split fp16 hi+lo with per-mode scaling, FP32 accumulation */
+  MODAL_BF16X3 = 2,  /* split bf16 hi+lo on the matrix cores, FP32 accumulation:
+                        synthesis 4 products, cubic contraction 3 products       */
+  MODAL_F16X3 = 3    /* split fp16 hi+lo (22-bit operands, 3 products) in both
+                        contractions, exact power-of-two scaling of maps and
+                        weights in the cubic one, FP32 accumulation; needs
+                        |q_p(l) a_lm / sqrt(C_l)| < 6.5e4 (true for whitened data) */
 } modal_prec;
 
 typedef enum {
@@ -219,6 +223,17 @@ modal_status modal_covariance(modal_ctx* ctx, int method, const double* beta_dev
 modal_status modal_fnl(modal_ctx* ctx, const double* zeta_dev, const double* alpha_dev,
                        const double* beta_dev, int S, double* E_host, double* sigma2_host,
                        double* L_dev, void* ws_dev, size_t ws_bytes, modal_stream_t stream);
+
+/* Autotuner: times modal_beta on the caller's inputs (same arguments and
+ * workspace as modal_beta) for each candidate launch configuration - pixels
+ * per split-K chunk of the matrix-core contraction (16K..128K for the split
+ * precisions, 2K or 4K for FP32) and rings per FFT workgroup (4, 2, 1 as LDS
+ * allows) - and keeps the fastest in
+ * the context (reported through chunk_px / fft_rings when not NULL).  A
+ * workspace sized by modal_workspace_size stays valid for every candidate.
+ * Synchronises the stream.  Errors: as modal_beta. */
+modal_status modal_autotune(modal_ctx* ctx, const void* alm_dev, int S, const void* state_dev, double* beta_dev,
+                            void* ws_dev, size_t ws_bytes, modal_stream_t stream, int* chunk_px, int* fft_rings);
 
 /* ------------------------------------------------------------------------ */
 /* captured launches                                                         */

@@ -60,6 +60,7 @@ _SIGS = {
     "modal_beta_graph_create": (ip, [ip, vp, vp, vp, vp, vp, vp, vp, vp]),
     "modal_graph_launch": (ip, [vp, vp]),
     "modal_graph_destroy": (None, [vp]),
+    "modal_autotune": (ip, [vp, vp, ip, vp, vp, vp, sz, vp, vp, vp]),
     "modal_profile_read": (ip, [vp, vp, vp, ip]),
 }
 

@@ -135,6 +135,17 @@ class ModalContext:
                                          self._stream()))
         return out
 
+    def autotune(self, alm, state=None) -> dict:
+        """Pick the fastest launch configuration for modal_beta on these inputs."""
+        a = self._alm(alm)
+        S = a.shape[0]
+        out = torch.empty((S, self.nmax), dtype=torch.float64, device=self.device)
+        ws = self.workspace(L.OP_BETA, S)
+        ch, rr = C.c_int(), C.c_int()
+        self._check(self._lib.modal_autotune(self._h, _ptr(a), S, _ptr(state), _ptr(out), _ptr(ws), ws.numel(),
+                                             self._stream(), C.byref(ch), C.byref(rr)))
+        return {"chunk_px": ch.value, "fft_rings": rr.value}
+
     def linear_state(self) -> torch.Tensor:
         n = int(self._lib.modal_linear_state_size(self._h))
         return torch.empty(n, dtype=torch.uint8, device=self.device)

@@ -47,6 +47,7 @@ struct Tables {
   int* flag = nullptr;         // [4] device status words (Cholesky pivot)
   int2* blk = nullptr;         // [nblk] (a0, b0) of the 2 x 4 pair blocks of the MFMA contraction
   int nblk = 0;
+  float* mscale = nullptr;     // [P] exact powers of two ~ 1/sigma_p (split-fp16 contraction)
 };
 
 }  // namespace modal
@@ -56,6 +57,11 @@ struct modal_ctx {
   int nalm = 0, npairs = 0, nmax = 0, nrp = 0, npix = 0;
   int device = 0;
   size_t max_lds = 65536;
+  bool legendre_mfma = false;   // MFMA synthesis enabled (F32 / BF16X3 when the LDS fits)
+  // tuned launch parameters (modal_autotune); 0 = default
+  int tune_chunk_px = 0;        // pixels per split-K chunk of the MFMA contraction target
+  int tune_fft_rings = 0;       // rings per FFT workgroup
+  float wscale = 1.f;           // power of two ~ npix / 4pi (split-fp16 contraction)
   modal::FftPlan fft{};
   modal::Tables t{};
   std::vector<double> x_host, wgl_host;
@@ -78,13 +84,20 @@ namespace modal {
 // ---- launchers (defined in the .hip files); all return hipSuccess or the error
 hipError_t launch_seeds(const modal_ctx* c, const double* logpref, hipStream_t st);
 
-// Legendre synthesis: F[S][P][ntheta][lmax+1] complex (double2 for F64, float2 otherwise)
+// Legendre synthesis: F[S][P][lmax+1][ntheta] complex (rings contiguous; double2 for F64, float2 otherwise)
 hipError_t launch_legendre(const modal_ctx* c, const void* alm, int S, void* F, hipStream_t st);
+hipError_t launch_legendre_mfma(const modal_ctx* c, const void* alm, int S, void* F, hipStream_t st);
+size_t legendre_mfma_lds(const modal_ctx* c);
+hipError_t legendre_mfma_set_lds(size_t bytes);
 // ring c2r FFT: maps[S][P][ntheta][nphi] from F
 hipError_t launch_fft_c2r(const modal_ctx* c, const void* F, int S, void* maps, hipStream_t st);
-// ring r2c FFT: Gh[S][P][ntheta][lmax+1] complex from G[S][P][ntheta][nphi]
+// ring r2c FFT: Gh[S][P][lmax+1][ntheta] complex from G[S][P][ntheta][nphi]
 hipError_t launch_fft_r2c(const modal_ctx* c, const void* G, int S, void* Gh, hipStream_t st);
-hipError_t launch_fft_r2c_rows(const modal_ctx* c, const void* G, size_t rows, void* Gh, hipStream_t st);
+hipError_t launch_fft_r2c_rows(const modal_ctx* c, const void* G, size_t nseq, void* Gh, hipStream_t st);
+int fft_rings_per_block(const modal_ctx* c);
+int fft_rings_max(const modal_ctx* c);
+int chunk_target_default(const modal_ctx* c);
+int chunk_target_min(const modal_ctx* c);
 
 // Fisher covariance from pair adjoints
 hipError_t launch_pair_maps(const modal_ctx* c, const void* maps, const void* V, void* G, hipStream_t st);

@@ -19,6 +19,7 @@ hipError_t launch_cubic_mfma(const modal_ctx* c, const void* maps, const void* V
                              hipStream_t st);
 bool cubic_mfma_available(const modal_ctx* c);
 int cubic_mfma_nchunk(const modal_ctx* c);
+int cubic_mfma_nchunk_max(const modal_ctx* c);
 hipError_t fft_set_lds_limit(size_t bytes);
 }  // namespace modal
 
@@ -119,7 +120,11 @@ size_t alm_bytes(const modal_ctx* c) { return (size_t)c->nalm * 2 * real_bytes(c
 size_t F_bytes(const modal_ctx* c, int S) { return (size_t)S * c->P * c->ntheta * (c->lmax + 1) * 2 * real_bytes(c); }
 size_t maps_bytes(const modal_ctx* c, int S) { return (size_t)S * c->P * c->npix * real_bytes(c); }
 int nchunk_for(const modal_ctx* c) { return cubic_mfma_available(c) ? cubic_mfma_nchunk(c) : cubic_nchunk(c); }
-size_t part_bytes(const modal_ctx* c, int S) { return (size_t)S * nchunk_for(c) * c->npairs * c->P * 8; }
+// sized for the smallest chunk the autotuner may choose, so a workspace stays valid after tuning
+size_t part_bytes(const modal_ctx* c, int S) {
+  const int nc = cubic_mfma_available(c) ? cubic_mfma_nchunk_max(c) : cubic_nchunk(c);
+  return (size_t)S * nc * c->npairs * c->P * 8;
+}
 size_t E_bytes(const modal_ctx* c, int S) { return (size_t)S * c->npairs * c->P * 8; }
 size_t lam_bytes(const modal_ctx* c) { return (size_t)c->nalm * c->nrp * real_bytes(c); }
 
@@ -212,7 +217,8 @@ struct StageTimer {
 
 // Filter maps for S maps into 'maps' using F as scratch.
 modal_status run_maps(modal_ctx* c, const void* alm, int S, void* F, void* maps, hipStream_t st) {
-  STAGE(MODAL_STAGE_LEGENDRE, launch_legendre(c, alm, S, F, st));
+  if (c->legendre_mfma) STAGE(MODAL_STAGE_LEGENDRE, launch_legendre_mfma(c, alm, S, F, st));
+  else STAGE(MODAL_STAGE_LEGENDRE, launch_legendre(c, alm, S, F, st));
   STAGE(MODAL_STAGE_FFT, launch_fft_c2r(c, F, S, maps, st));
   return MODAL_OK;
 }
@@ -245,7 +251,6 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
   if (!q_host || !cl_host || lmax < 0 || P < 1 || P > kMaxP || prec < MODAL_F64 || prec > MODAL_F16X3)
     return MODAL_EINVAL;
   if (ntheta <= lmax || nphi <= 2 * lmax || (nphi & 1) || ntheta < 1) return MODAL_ESHAPE;
-  if (prec == MODAL_F16X3) return MODAL_EUNSUPPORTED;
   modal_ctx* c = new (std::nothrow) modal_ctx();
   if (!c) return MODAL_EDEVICE;
   c->lmax = lmax;
@@ -262,16 +267,23 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
     modal_destroy(c);
     return s;
   };
-  if (prec == MODAL_BF16X3 && !cubic_mfma_available(c)) return bail(MODAL_EUNSUPPORTED);
+  if ((prec == MODAL_BF16X3 || prec == MODAL_F16X3) && !cubic_mfma_available(c)) return bail(MODAL_EUNSUPPORTED);
   if (hipGetDevice(&c->device) != hipSuccess) return bail(MODAL_EDEVICE);
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess && lds > 0)
     c->max_lds = (size_t)lds;
   if (!fft_plan(nphi, c->fft)) return bail(MODAL_ESHAPE);
-  const size_t fft_lds = 2 * (size_t)c->fft.K * 2 * real_bytes(c);
+  const size_t fft_lds = (size_t)fft_rings_per_block(c) * 2 * c->fft.K * 2 * real_bytes(c);
   if (fft_lds > c->max_lds) return bail(MODAL_EUNSUPPORTED);
   if (fft_lds > 65536 && fft_set_lds_limit(fft_lds) != hipSuccess) return bail(MODAL_EDEVICE);
 
+  if (prec == MODAL_F32 || prec == MODAL_BF16X3 || prec == MODAL_F16X3) {
+    const size_t need = legendre_mfma_lds(c);
+    if (need <= c->max_lds) {
+      if (need > 65536 && legendre_mfma_set_lds(need) != hipSuccess) return bail(MODAL_EDEVICE);
+      c->legendre_mfma = true;
+    }
+  }
   // --- grid
   gauss_legendre(ntheta, c->x_host, c->wgl_host);
   std::vector<double> ringw(ntheta), w64((size_t)ntheta * nphi);
@@ -348,7 +360,19 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
       tri_mult[(size_t)u * c->npairs + k] = (v[0] == u) + (v[1] == u) + (v[2] == u);
     }
 
+  // exact power-of-two scales for the split-fp16 contraction: whitened maps have
+  // variance sigma_p^2 = sum_{C_l > 0} (2l+1)/(4 pi) q_p(l)^2
+  std::vector<float> mscale(P, 1.f);
+  for (int p = 0; p < P; ++p) {
+    double v = 0.0;
+    for (int l = 0; l <= lmax; ++l)
+      if (cl_host[l] > 0.0) v += (2.0 * l + 1.0) / (4.0 * kPi) * q_host[(size_t)p * (lmax + 1) + l] * q_host[(size_t)p * (lmax + 1) + l];
+    const int e = v > 0.0 ? (int)std::lround(0.5 * std::log2(v)) : 0;
+    mscale[p] = (float)std::ldexp(1.0, -e);
+  }
+  c->wscale = (float)std::ldexp(1.0, (int)std::lround(std::log2((double)c->npix / (4.0 * kPi))));
   Tables& t = c->t;
+  if (upload(&t.mscale, mscale) != hipSuccess) return bail(MODAL_EDEVICE);
   std::vector<int2> blocks;
   make_pair_blocks(P, blocks);
   t.nblk = (int)blocks.size();
@@ -385,7 +409,7 @@ void modal_destroy(modal_ctx* c) {
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   Tables& t = c->t;
   void* ptrs[] = {t.x, t.ringw, t.w64, t.w32, t.rec, t.seed, t.lstart, t.lstart_blk, t.qw64, t.qw32, t.tw64, t.tw32,
-                  t.pair_a, t.pair_b, t.tri, t.pair_of, t.tri_of, t.tri_mult, t.flag, t.blk};
+                  t.pair_a, t.pair_b, t.tri, t.pair_of, t.tri_of, t.tri_mult, t.flag, t.blk, t.mscale};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -398,7 +422,7 @@ int modal_npairs(const modal_ctx* c) { return c ? c->npairs : -1; }
 int modal_cubic_path(const modal_ctx* c) {
   if (!c) return -1;
   if (!cubic_mfma_available(c)) return 0;
-  return c->prec == MODAL_BF16X3 ? 2 : 1;
+  return c->prec == MODAL_F32 ? 1 : 2;
 }
 
 modal_status modal_grid(const modal_ctx* c, double* x_host, double* w_host) {
@@ -557,7 +581,7 @@ modal_status modal_covariance(modal_ctx* c, int method, const double* beta, cons
       const void* ai = (const char*)alm + (size_t)i * abytes;
       if ((s = run_maps(c, ai, 1, F, maps, st)) != MODAL_OK) return s;
       STAGE(MODAL_STAGE_ADJ_PAIR, launch_pair_maps(c, maps, state, G, st));
-      STAGE(MODAL_STAGE_ADJ_FFT, launch_fft_r2c_rows(c, G, (size_t)c->npairs * c->ntheta, Gh, st));
+      STAGE(MODAL_STAGE_ADJ_FFT, launch_fft_r2c_rows(c, G, (size_t)c->npairs, Gh, st));
       STAGE(MODAL_STAGE_ADJ_LEGENDRE, launch_adj_legendre_cols(c, lam, Gh, c->npairs, Z, st));
       STAGE(MODAL_STAGE_COVARIANCE, launch_cross_spectra(c, Z, cvar, X, st));
     }
@@ -688,6 +712,62 @@ void modal_graph_destroy(modal_graph* g) {
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
+}
+
+modal_status modal_autotune(modal_ctx* c, const void* alm, int S, const void* state, double* beta, void* ws,
+                            size_t ws_bytes, modal_stream_t stream, int* chunk_px, int* fft_rings) {
+  if (!c) return MODAL_EINVAL;
+  modal_status s = check_state(c, state);
+  if (s != MODAL_OK) return s;
+  if (!alm || !beta || S <= 0) return fail(c, MODAL_EINVAL, "autotune: null pointer or S <= 0");
+  if ((s = check_ws(c, MODAL_OP_BETA, S, ws, ws_bytes)) != MODAL_OK) return s;
+  if ((s = set_device(c)) != MODAL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPTRY(hipEventCreate(&a));
+  HIPTRY(hipEventCreate(&b));
+  const bool prof = c->profile;
+  c->profile = false;
+  auto time_beta = [&](float* ms) -> modal_status {
+    modal_status r = modal_beta(c, alm, S, state, beta, ws, ws_bytes, st);   // warm-up
+    if (r != MODAL_OK) return r;
+    if (hipEventRecord(a, st) != hipSuccess) return MODAL_EDEVICE;
+    for (int i = 0; i < 2 && r == MODAL_OK; ++i) r = modal_beta(c, alm, S, state, beta, ws, ws_bytes, st);
+    if (r != MODAL_OK) return r;
+    if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        hipEventElapsedTime(ms, a, b) != hipSuccess)
+      return MODAL_EDEVICE;
+    return MODAL_OK;
+  };
+  float best = 1e30f;
+  int best_chunk = 65536, best_r = fft_rings_max(c);
+  const int lo = chunk_target_min(c);
+  const int chunks[] = {lo, 2 * lo, 4 * lo, 8 * lo};
+  int best_chunk_init = chunk_target_default(c);
+  best_chunk = best_chunk_init;
+  for (int r = fft_rings_max(c); r >= 1 && s == MODAL_OK; r >>= 1)
+    for (int ch : chunks) {
+      if (c->prec == MODAL_F32 && ch > chunk_target_default(c)) continue;   // FP32 keeps short chunks
+      c->tune_chunk_px = ch;
+      c->tune_fft_rings = r;
+      float ms = 0.f;
+      if ((s = time_beta(&ms)) != MODAL_OK) break;
+      if (ms < best) {
+        best = ms;
+        best_chunk = ch;
+        best_r = r;
+      }
+      if (!cubic_mfma_available(c)) break;   // the chunk only matters for the MFMA contraction
+    }
+  c->tune_chunk_px = best_chunk;
+  c->tune_fft_rings = best_r;
+  c->profile = prof;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (s != MODAL_OK) return s;
+  if (chunk_px) *chunk_px = best_chunk;
+  if (fft_rings) *fft_rings = best_r;
+  return MODAL_OK;
 }
 
 modal_status modal_profile_enable(modal_ctx* c, int enable) {

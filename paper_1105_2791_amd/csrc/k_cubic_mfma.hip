@@ -13,9 +13,14 @@
 // that straddle the diagonal carry invalid pairs (a > b) whose A is zero.
 //
 // Precisions
-//   F32    : v_mfma_f32_16x16x4_f32, A and B in FP32.
+//   F32    : v_mfma_f32_16x16x4_f32, A and B in FP32 (short chunks: the FP32
+//            accumulation length sets this path's error).
 //   BF16X3 : v_mfma_f32_16x16x32_bf16 on hi/lo splits, A B ~ Ah Bh + Ah Bl + Al Bh
 //            (hi = RNE bf16, lo = RNE bf16 of the residual), FP32 accumulation.
+//   F16X3  : the same on fp16 hi/lo splits (22-bit operands).  Maps are staged
+//            scaled by exact powers of two s_p ~ 1/sigma_p and w by s_w ~ npix/4pi so
+//            that pair products and B stay inside the fp16 range; the partial sums
+//            are unscaled exactly (FP64) when written.
 //
 // Launch: one workgroup per (pixel chunk, block group, sky); chunk c runs on XCD
 // c mod 8 with all skies of that chunk dispatched back to back, so the V planes
@@ -26,18 +31,21 @@ namespace modal {
 namespace {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr int KS = 32;          // pixels per K step
 constexpr int MS_STRIDE = KS + 4;
-constexpr int NW = 8;           // waves per workgroup
-constexpr int NT = 64 * NW;
-constexpr int BLK_PER_GROUP = 16 * NW;
+// waves per workgroup: 8 for split-bf16 (two waves per SIMD to overlap the
+// vector-ALU operand formation with the matrix cores); 4 for FP32 (compensated
+// accumulation, twice the accumulator registers) and split-fp16 (scaling and the
+// per-step product chains), which then have up to 512 registers per lane
+template <int PREC> struct Waves { static constexpr int value = (PREC == MODAL_BF16X3) ? 8 : 4; };
 constexpr int TCOLS = 48;       // modes padded to three 16-wide column tiles
 
 struct Blocks {
   int nblk;      // valid blocks
-  int ngroups;   // ceil(nblk / BLK_PER_GROUP)
+  int ngroups;   // ceil(nblk / (16 * waves))
 };
 
 __device__ inline uint32_t bf16x2_bits(float a, float b) {
@@ -66,12 +74,26 @@ __device__ inline void split8(const float* v, bf16x8& hi, bf16x8& lo) {
   lo = __builtin_bit_cast(bf16x8, lv);
 }
 
+// fp16 hi/lo split of 8 floats (hi = RNE fp16(x), lo = RNE fp16(x - hi)).
+__device__ inline void split8h(const float* v, f16x8& hi, f16x8& lo) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const _Float16 h = (_Float16)v[k];
+    hi[k] = h;
+    lo[k] = (_Float16)(v[k] - (float)h);
+  }
+}
+
 template <int PREC, int MODE>
-__global__ __launch_bounds__(NT) void k_cubic_mfma(int P, int npairs, int npix, int S, int nchunk, int chunk_px,
+__global__ __launch_bounds__(64 * Waves<PREC>::value) void k_cubic_mfma(int P, int npairs, int npix, int S, int nchunk, int chunk_px,
                                                    Blocks bk, const int2* __restrict__ blocks,
                                                    const int* __restrict__ pair_of, const float* __restrict__ maps,
                                                    const float* __restrict__ w, const float* __restrict__ V,
+                                                   const float* __restrict__ mscale, float wscale,
                                                    double* __restrict__ part) {
+  constexpr bool SCALED = (PREC == MODAL_F16X3);
+  constexpr int NT = 64 * Waves<PREC>::value;
+  constexpr int BLK_PER_GROUP = 16 * Waves<PREC>::value;
   // ---- XCD-aware decode: chunk c on XCD c % 8, its (group, sky) items consecutive there
   const int b = blockIdx.x;
   const int xcd = b & 7;
@@ -88,8 +110,10 @@ __global__ __launch_bounds__(NT) void k_cubic_mfma(int P, int npairs, int npix, 
   const int row = lane & 15, kg = lane >> 4;
 
   __shared__ float Ms[kMaxP][MS_STRIDE];
-  __shared__ __attribute__((aligned(16))) uint16_t Bh[TCOLS][KS];   // bf16 bits (BF16X3)
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[TCOLS][KS];   // bf16 / fp16 bits
   __shared__ __attribute__((aligned(16))) uint16_t Bl[TCOLS][KS];
+  __shared__ float msc[kMaxP];
+  if (tid < kMaxP) msc[tid] = (SCALED && tid < P) ? mscale[tid] : 1.f;
   __shared__ __attribute__((aligned(16))) float Bf[TCOLS][KS];      // FP32 path
 
   // this lane-row's block
@@ -101,17 +125,27 @@ __global__ __launch_bounds__(NT) void k_cubic_mfma(int P, int npairs, int npix, 
     b0 = bb.y;
   }
   int pidx[8];
+  float vsc[8];   // -3 s_a s_b (MODE 1) or s_a s_b (MODE 2): scale of the V term
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int a = a0 + (j >> 2), bm = b0 + (j & 3);
-    pidx[j] = (a0 >= 0 && a < P && bm < P && a <= bm) ? pair_of[a * P + bm] : -1;
+    const bool ok = a0 >= 0 && a < P && bm < P && a <= bm;
+    pidx[j] = ok ? pair_of[a * P + bm] : -1;
+    const float sab = (SCALED && ok) ? mscale[a] * mscale[bm] : 1.f;
+    vsc[j] = (MODE == 1 ? -3.f : 1.f) * sab;
   }
+  __syncthreads();
 
   f32x4 acc[8][3];
+  f32x4 cmp[PREC == MODAL_F32 ? 8 : 1][3];   // FP32: running compensation of acc (Fast2Sum)
 #pragma unroll
   for (int j = 0; j < 8; ++j)
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[j][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int j = 0; j < (PREC == MODAL_F32 ? 8 : 1); ++j)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) cmp[j][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   const float* Msky = maps + (size_t)s * P * npix;
   const int x_begin = chunk * chunk_px;
@@ -122,17 +156,25 @@ __global__ __launch_bounds__(NT) void k_cubic_mfma(int P, int npairs, int npix, 
     for (int e = tid; e < P * KS; e += NT) {
       const int p = e / KS, xx = e - p * KS;
       const int x = x0 + xx;
-      Ms[p][xx] = x < x_end ? Msky[(size_t)p * npix + x] : 0.f;
+      Ms[p][xx] = x < x_end ? Msky[(size_t)p * npix + x] * msc[p] : 0.f;
     }
     for (int e = tid; e < TCOLS * KS / 2; e += NT) {
       const int t = e / (KS / 2), xx = 2 * (e - t * (KS / 2));
       const int x = x0 + xx;
       float v0 = 0.f, v1 = 0.f;
       if (t < P) {
-        if (x < x_end) v0 = w[x] * Msky[(size_t)t * npix + x];
-        if (x + 1 < x_end) v1 = w[x + 1] * Msky[(size_t)t * npix + x + 1];
+        const float sc = SCALED ? msc[t] * wscale : 1.f;
+        if (x < x_end) v0 = w[x] * sc * Msky[(size_t)t * npix + x];
+        if (x + 1 < x_end) v1 = w[x + 1] * sc * Msky[(size_t)t * npix + x + 1];
       }
-      if (PREC == MODAL_BF16X3) {
+      if (PREC == MODAL_F16X3) {
+        const _Float16 h0 = (_Float16)v0, h1 = (_Float16)v1;
+        const _Float16 l0 = (_Float16)(v0 - (float)h0), l1 = (_Float16)(v1 - (float)h1);
+        Bh[t][xx] = __builtin_bit_cast(uint16_t, h0);
+        Bh[t][xx + 1] = __builtin_bit_cast(uint16_t, h1);
+        Bl[t][xx] = __builtin_bit_cast(uint16_t, l0);
+        Bl[t][xx + 1] = __builtin_bit_cast(uint16_t, l1);
+      } else if (PREC == MODAL_BF16X3) {
         const uint32_t hb = bf16x2_bits(v0, v1);
         const float h0 = __builtin_bit_cast(float, hb << 16);
         const float h1 = __builtin_bit_cast(float, hb & 0xffff0000u);
@@ -182,7 +224,7 @@ __global__ __launch_bounds__(NT) void k_cubic_mfma(int P, int npairs, int npix, 
             else {
               const int x = xl + k;
               const float vv = (pv && x < x_end) ? V[(size_t)pidx[j] * npix + x] : 0.f;
-              v = (MODE == 1) ? fmaf(ma[j >> 2][k], mb[j & 3][k], -3.f * vv) : vv;
+              v = (MODE == 1) ? fmaf(ma[j >> 2][k], mb[j & 3][k], vsc[j] * vv) : vsc[j] * vv;
             }
             av[k] = pv ? v : 0.f;
           }
@@ -193,6 +235,41 @@ __global__ __launch_bounds__(NT) void k_cubic_mfma(int P, int npairs, int npix, 
             acc[j][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[c], acc[j][c], 0, 0, 0);
             acc[j][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[c], acc[j][c], 0, 0, 0);
             acc[j][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[c], acc[j][c], 0, 0, 0);
+          }
+        }
+      } else if (PREC == MODAL_F16X3) {
+        f16x8 bh[3], bl[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          bh[c] = *reinterpret_cast<const f16x8*>(&Bh[16 * c + row][8 * kg]);
+          bl[c] = *reinterpret_cast<const f16x8*>(&Bl[16 * c + row][8 * kg]);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          float av[8];
+          const bool pv = pidx[j] >= 0;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            float v;
+            if (MODE == 0) v = ma[j >> 2][k] * mb[j & 3][k];
+            else {
+              const int x = xl + k;
+              const float vv = (pv && x < x_end) ? V[(size_t)pidx[j] * npix + x] : 0.f;
+              v = (MODE == 1) ? fmaf(ma[j >> 2][k], mb[j & 3][k], vsc[j] * vv) : vsc[j] * vv;
+            }
+            av[k] = pv ? v : 0.f;
+          }
+          f16x8 ah, al;
+          split8h(av, ah, al);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            // the three products of one K step start from zero and join the running
+            // sum with a round-to-nearest vector add, so the long FP32 sum is not
+            // accumulated inside the matrix unit
+            f32x4 t = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[c], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            t = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[c], t, 0, 0, 0);
+            t = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[c], t, 0, 0, 0);
+            acc[j][c] += t;
           }
         }
       } else {
@@ -212,15 +289,27 @@ __global__ __launch_bounds__(NT) void k_cubic_mfma(int P, int npairs, int npix, 
             else {
               const int x = xl + k;
               const float vv = (pv && x < x_end) ? V[(size_t)pidx[j] * npix + x] : 0.f;
-              v = (MODE == 1) ? fmaf(ma[j >> 2][k], mb[j & 3][k], -3.f * vv) : vv;
+              v = (MODE == 1) ? fmaf(ma[j >> 2][k], mb[j & 3][k], vsc[j] * vv) : vsc[j] * vv;
             }
             av[k] = pv ? v : 0.f;
           }
 #pragma unroll
-          for (int k = 0; k < 8; ++k)
+          for (int c = 0; c < 3; ++c) {
+            // one K step (8 MFMAs of K = 4) from zero, then a round-to-nearest add
+            f32x4 t = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-              acc[j][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[k], bv[c][k], acc[j][c], 0, 0, 0);
+            for (int k = 0; k < 8; ++k) t = __builtin_amdgcn_mfma_f32_16x16x4f32(av[k], bv[c][k], t, 0, 0, 0);
+            // two-sum of the running total and this K step; the rounding error is kept
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const float a = acc[j][c][r], b = t[r];
+              const float sum = a + b;
+              const float bb = sum - a;
+              const float err = (a - (sum - bb)) + (b - bb);
+              acc[j][c][r] = sum;
+              cmp[(PREC == MODAL_F32) ? j : 0][c][r] += err;
+            }
+          }
         }
       }
     }
@@ -244,15 +333,19 @@ __global__ __launch_bounds__(NT) void k_cubic_mfma(int P, int npairs, int npix, 
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const int t = 16 * c + row;
-        if (t < P) dst[(size_t)pr * P + t] = (double)acc[j][c][r];
+        if (t < P) {
+          double v = (double)acc[j][c][r];
+          if (PREC == MODAL_F32) v += (double)cmp[(PREC == MODAL_F32) ? j : 0][c][r];
+          if (SCALED) v /= (double)msc[a] * (double)msc[bm] * (double)msc[t] * (double)wscale;
+          dst[(size_t)pr * P + t] = v;
+        }
       }
     }
   }
 }
 
-int chunk_px_for(const modal_ctx* c) {
-  // nchunk a multiple of 8 (one chunk stream per XCD), chunks of about 64K pixels
-  const int target = 65536;
+int chunk_px_for(const modal_ctx* c, int target) {
+  // nchunk a multiple of 8 (one chunk stream per XCD), chunks of about target pixels
   int nchunk = 8 * ((c->npix + 8 * target - 1) / (8 * target));
   int px = (c->npix + nchunk - 1) / nchunk;
   px = (px + KS - 1) / KS * KS;
@@ -261,12 +354,22 @@ int chunk_px_for(const modal_ctx* c) {
 
 }  // namespace
 
+// FP32 accumulates its exact products in FP32, so it uses short chunks; the split
+// precisions carry a larger operand error and use long chunks (fewer partials).
+int chunk_target_default(const modal_ctx* c) { return c->prec == MODAL_F32 ? 4096 : 65536; }
+int chunk_target_min(const modal_ctx* c) { return c->prec == MODAL_F32 ? 2048 : 16384; }
+
+int cubic_mfma_nchunk_max(const modal_ctx* c) {
+  const int px = chunk_px_for(c, chunk_target_min(c));
+  return (c->npix + px - 1) / px;
+}
+
 bool cubic_mfma_available(const modal_ctx* c) {
-  return c->prec == MODAL_F32 || c->prec == MODAL_BF16X3;
+  return c->prec == MODAL_F32 || c->prec == MODAL_BF16X3 || c->prec == MODAL_F16X3;
 }
 
 int cubic_mfma_nchunk(const modal_ctx* c) {
-  const int px = chunk_px_for(c);
+  const int px = chunk_px_for(c, c->tune_chunk_px > 0 ? c->tune_chunk_px : chunk_target_default(c));
   return (c->npix + px - 1) / px;
 }
 
@@ -286,15 +389,21 @@ hipError_t launch_cubic_mfma(const modal_ctx* c, const void* maps, const void* V
                              hipStream_t st) {
   Blocks bk;
   bk.nblk = c->t.nblk;
-  bk.ngroups = (bk.nblk + BLK_PER_GROUP - 1) / BLK_PER_GROUP;
-  const int px = chunk_px_for(c);
+  const int waves = (c->prec == MODAL_BF16X3) ? Waves<MODAL_BF16X3>::value : Waves<MODAL_F32>::value;
+  bk.ngroups = (bk.nblk + 16 * waves - 1) / (16 * waves);
+  const int px = chunk_px_for(c, c->tune_chunk_px > 0 ? c->tune_chunk_px : chunk_target_default(c));
   const int nchunk = (c->npix + px - 1) / px;
   const int nslots = 8 * ((nchunk + 7) / 8);
   const size_t grid = (size_t)nslots * bk.ngroups * S;
 #define LAUNCH(PR, MD)                                                                                        \
-  hipLaunchKernelGGL((k_cubic_mfma<PR, MD>), dim3(grid), dim3(NT), 0, st, c->P, c->npairs, c->npix, S, nchunk, \
-                     px, bk, c->t.blk, c->t.pair_of, (const float*)maps, c->t.w32, (const float*)V, part)
-  if (c->prec == MODAL_BF16X3) {
+  hipLaunchKernelGGL((k_cubic_mfma<PR, MD>), dim3(grid), dim3(64 * Waves<PR>::value), 0, st, c->P, c->npairs, c->npix, S, nchunk, \
+                     px, bk, c->t.blk, c->t.pair_of, (const float*)maps, c->t.w32, (const float*)V, c->t.mscale,   \
+                     c->wscale, part)
+  if (c->prec == MODAL_F16X3) {
+    if (mode == 0) LAUNCH(MODAL_F16X3, 0);
+    else if (mode == 1) LAUNCH(MODAL_F16X3, 1);
+    else LAUNCH(MODAL_F16X3, 2);
+  } else if (c->prec == MODAL_BF16X3) {
     if (mode == 0) LAUNCH(MODAL_BF16X3, 0);
     else if (mode == 1) LAUNCH(MODAL_BF16X3, 1);
     else LAUNCH(MODAL_BF16X3, 2);

@@ -100,113 +100,168 @@ __device__ inline void stockham_stage(const T2* __restrict__ in, T2* __restrict_
   }
 }
 
+// Stage over R independent transforms of length K stored back to back.
+template <typename T2, int SIGN>
+__device__ inline void stockham_stage_multi(const T2* __restrict__ in, T2* __restrict__ out, int K, int R, int Ns,
+                                            int Rf, const T2* __restrict__ tw) {
+  // each transform r uses the same butterfly set; run them as one flat index space
+  const int KR = K / Rf;
+  for (int r = 0; r < R; ++r) stockham_stage<T2, SIGN>(in + (size_t)r * K, out + (size_t)r * K, K, Ns, Rf, tw);
+  (void)KR;
+}
+
+// c2r: one workgroup per (sequence, block of R consecutive rings).  F layout is
+// [seq][m][ring] (rings contiguous), so a block reads R consecutive values per m.
 template <typename T>
-__global__ __launch_bounds__(256) void k_fft_c2r(FftPlan plan, int lmax, const typename vec2<T>::type* __restrict__ F,
+__global__ __launch_bounds__(256) void k_fft_c2r(FftPlan plan, int lmax, int ntheta, int R,
+                                                 const typename vec2<T>::type* __restrict__ F,
                                                  T* __restrict__ maps, const typename vec2<T>::type* __restrict__ tw) {
   using T2 = typename vec2<T>::type;
   extern __shared__ char smem[];
-  T2* b0 = reinterpret_cast<T2*>(smem);
-  T2* b1 = b0 + plan.K;
   const int K = plan.K;
-  const size_t row = blockIdx.x;
-  const T2* H = F + row * (lmax + 1);
-  for (int m = threadIdx.x; m < K; m += blockDim.x) {
-    T2 xm, xk;
-    xm.x = xm.y = T(0);
+  T2* b0 = reinterpret_cast<T2*>(smem);
+  T2* b1 = b0 + (size_t)R * K;
+  const int nrb = (ntheta + R - 1) / R;
+  const int seq = blockIdx.x / nrb;
+  const int j0 = (blockIdx.x - seq * nrb) * R;
+  const int nr = min(R, ntheta - j0);
+  const T2* H = F + (size_t)seq * (lmax + 1) * ntheta;
+  // X_m (zero beyond lmax, X_0 real) into b1, ring-major
+  for (int e = threadIdx.x; e < R * K; e += blockDim.x) {
+    const int m = e / R, r = e - m * R;
+    T2 x;
+    x.x = x.y = T(0);
+    if (m <= lmax && r < nr) x = H[(size_t)m * ntheta + j0 + r];
+    if (m == 0) x.y = T(0);
+    b1[(size_t)r * K + m] = x;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < R * K; e += blockDim.x) {
+    const int r = e / K, m = e - r * K;
+    const T2 xm = b1[(size_t)r * K + m];
+    T2 xk;
     xk.x = xk.y = T(0);
-    if (m <= lmax) xm = H[m];
-    if (m == 0) xm.y = T(0);
-    const int mk = K - m;          // in (0, K]; X_K = 0 since lmax < K
-    if (mk <= lmax) xk = H[mk];
+    if (m > 0) xk = b1[(size_t)r * K + (K - m)];   // X_K = 0 since lmax < K
     T2 a, d;
     a.x = xm.x + xk.x; a.y = xm.y - xk.y;   // X_m + conj(X_{K-m})
     d.x = xm.x - xk.x; d.y = xm.y + xk.y;   // X_m - conj(X_{K-m})
-    const T2 e = tw[m];
+    const T2 ew = tw[m];
     T2 z;
-    z.x = a.x - (e.x * d.y + e.y * d.x);
-    z.y = a.y + (e.x * d.x - e.y * d.y);
-    b0[m] = z;
+    z.x = a.x - (ew.x * d.y + ew.y * d.x);
+    z.y = a.y + (ew.x * d.x - ew.y * d.y);
+    b0[(size_t)r * K + m] = z;
   }
   __syncthreads();
   T2* in = b0;
   T2* out = b1;
   int Ns = 1;
   for (int f = 0; f < plan.nf; ++f) {
-    const int R = plan.radix[f];
-    stockham_stage<T2, +1>(in, out, K, Ns, R, tw);
+    const int Rf = plan.radix[f];
+    stockham_stage_multi<T2, +1>(in, out, K, R, Ns, Rf, tw);
     __syncthreads();
     T2* tmp = in; in = out; out = tmp;
-    Ns *= R;
+    Ns *= Rf;
   }
-  T2* dst = reinterpret_cast<T2*>(maps + row * plan.N);
-  for (int n = threadIdx.x; n < K; n += blockDim.x) dst[n] = in[n];
+  for (int r = 0; r < nr; ++r) {
+    T2* dst = reinterpret_cast<T2*>(maps + ((size_t)seq * ntheta + j0 + r) * plan.N);
+    for (int n = threadIdx.x; n < K; n += blockDim.x) dst[n] = in[(size_t)r * K + n];
+  }
 }
 
+// r2c: G rows [seq][ring][pixel] -> Gh [seq][m][ring], m <= lmax.
 template <typename T>
-__global__ __launch_bounds__(256) void k_fft_r2c(FftPlan plan, int lmax, const T* __restrict__ G,
+__global__ __launch_bounds__(256) void k_fft_r2c(FftPlan plan, int lmax, int ntheta, int R, const T* __restrict__ G,
                                                  typename vec2<T>::type* __restrict__ Gh,
                                                  const typename vec2<T>::type* __restrict__ tw) {
   using T2 = typename vec2<T>::type;
   extern __shared__ char smem[];
-  T2* b0 = reinterpret_cast<T2*>(smem);
-  T2* b1 = b0 + plan.K;
   const int K = plan.K;
-  const size_t row = blockIdx.x;
-  const T2* src = reinterpret_cast<const T2*>(G + row * plan.N);
-  for (int n = threadIdx.x; n < K; n += blockDim.x) b0[n] = src[n];
+  T2* b0 = reinterpret_cast<T2*>(smem);
+  T2* b1 = b0 + (size_t)R * K;
+  const int nrb = (ntheta + R - 1) / R;
+  const int seq = blockIdx.x / nrb;
+  const int j0 = (blockIdx.x - seq * nrb) * R;
+  const int nr = min(R, ntheta - j0);
+  for (int r = 0; r < R; ++r) {
+    const T2* src = reinterpret_cast<const T2*>(G + ((size_t)seq * ntheta + j0 + min(r, nr - 1)) * plan.N);
+    for (int n = threadIdx.x; n < K; n += blockDim.x) {
+      T2 v = src[n];
+      if (r >= nr) v.x = v.y = T(0);
+      b0[(size_t)r * K + n] = v;
+    }
+  }
   __syncthreads();
   T2* in = b0;
   T2* out = b1;
   int Ns = 1;
   for (int f = 0; f < plan.nf; ++f) {
-    const int R = plan.radix[f];
-    stockham_stage<T2, -1>(in, out, K, Ns, R, tw);
+    const int Rf = plan.radix[f];
+    stockham_stage_multi<T2, -1>(in, out, K, R, Ns, Rf, tw);
     __syncthreads();
     T2* tmp = in; in = out; out = tmp;
-    Ns *= R;
+    Ns *= Rf;
   }
-  T2* dst = Gh + row * (lmax + 1);
-  for (int m = threadIdx.x; m <= lmax; m += blockDim.x) {
-    const T2 zk = in[m % K];
-    const T2 zm = in[(K - m) % K];
+  T2* dst = Gh + (size_t)seq * (lmax + 1) * ntheta;
+  for (int e = threadIdx.x; e < (lmax + 1) * R; e += blockDim.x) {
+    const int m = e / R, r = e - m * R;
+    if (r >= nr) continue;
+    const T2 zk = in[(size_t)r * K + (m % K)];
+    const T2 zm = in[(size_t)r * K + ((K - m) % K)];
     T2 a, d;
     a.x = zk.x + zm.x; a.y = zk.y - zm.y;   // Z_m + conj(Z_{K-m})
     d.x = zk.x - zm.x; d.y = zk.y + zm.y;   // Z_m - conj(Z_{K-m})
-    const T2 e = tw[m];                     // e^{+2 pi i m / N}; use its conjugate (c, -s)
+    const T2 ew = tw[m];                    // e^{+2 pi i m / N}; use its conjugate (c, -s)
     // -(i/2) (c - i s) d = 0.5 (c d.y - s d.x) - 0.5 i (c d.x + s d.y)
     T2 g;
-    g.x = T(0.5) * (a.x + (e.x * d.y - e.y * d.x));
-    g.y = T(0.5) * (a.y - (e.x * d.x + e.y * d.y));
-    dst[m] = g;
+    g.x = T(0.5) * (a.x + (ew.x * d.y - ew.y * d.x));
+    g.y = T(0.5) * (a.y - (ew.x * d.x + ew.y * d.y));
+    dst[(size_t)m * ntheta + j0 + r] = g;
   }
 }
 
 }  // namespace
 
+int fft_rings_max(const modal_ctx* c) {
+  // as many rings per workgroup as fit in LDS (two buffers), at most 4
+  const size_t per = 2 * (size_t)c->fft.K * 2 * real_bytes(c);
+  int R = 4;
+  while (R > 1 && (size_t)R * per > c->max_lds) R >>= 1;
+  return R;
+}
+
+int fft_rings_per_block(const modal_ctx* c) {
+  const int R = fft_rings_max(c);
+  return (c->tune_fft_rings > 0 && c->tune_fft_rings <= R) ? c->tune_fft_rings : R;
+}
+
 hipError_t launch_fft_c2r(const modal_ctx* c, const void* F, int S, void* maps, hipStream_t st) {
-  const size_t rows = (size_t)S * c->P * c->ntheta;
-  const size_t lds = 2 * (size_t)c->fft.K * 2 * real_bytes(c);
+  const int R = fft_rings_per_block(c);
+  const size_t blocks = (size_t)S * c->P * ((c->ntheta + R - 1) / R);
+  const size_t lds = (size_t)R * 2 * c->fft.K * 2 * real_bytes(c);
   if (is_f64(c))
-    hipLaunchKernelGGL(k_fft_c2r<double>, dim3(rows), dim3(256), lds, st, c->fft, c->lmax, (const double2*)F,
-                       (double*)maps, (const double2*)c->t.tw64);
+    hipLaunchKernelGGL(k_fft_c2r<double>, dim3(blocks), dim3(256), lds, st, c->fft, c->lmax, c->ntheta, R,
+                       (const double2*)F, (double*)maps, (const double2*)c->t.tw64);
   else
-    hipLaunchKernelGGL(k_fft_c2r<float>, dim3(rows), dim3(256), lds, st, c->fft, c->lmax, (const float2*)F,
-                       (float*)maps, (const float2*)c->t.tw32);
+    hipLaunchKernelGGL(k_fft_c2r<float>, dim3(blocks), dim3(256), lds, st, c->fft, c->lmax, c->ntheta, R,
+                       (const float2*)F, (float*)maps, (const float2*)c->t.tw32);
   return hipGetLastError();
 }
 
 hipError_t launch_fft_r2c(const modal_ctx* c, const void* G, int S, void* Gh, hipStream_t st) {
-  return launch_fft_r2c_rows(c, G, (size_t)S * c->P * c->ntheta, Gh, st);
+  return launch_fft_r2c_rows(c, G, (size_t)S * c->P, Gh, st);
 }
 
-hipError_t launch_fft_r2c_rows(const modal_ctx* c, const void* G, size_t rows, void* Gh, hipStream_t st) {
-  const size_t lds = 2 * (size_t)c->fft.K * 2 * real_bytes(c);
+// nseq sequences of ntheta ring rows each
+hipError_t launch_fft_r2c_rows(const modal_ctx* c, const void* G, size_t nseq, void* Gh, hipStream_t st) {
+  const int R = fft_rings_per_block(c);
+  const size_t blocks = nseq * ((c->ntheta + R - 1) / R);
+  const size_t lds = (size_t)R * 2 * c->fft.K * 2 * real_bytes(c);
   if (is_f64(c))
-    hipLaunchKernelGGL(k_fft_r2c<double>, dim3(rows), dim3(256), lds, st, c->fft, c->lmax, (const double*)G,
-                       (double2*)Gh, (const double2*)c->t.tw64);
+    hipLaunchKernelGGL(k_fft_r2c<double>, dim3(blocks), dim3(256), lds, st, c->fft, c->lmax, c->ntheta, R,
+                       (const double*)G, (double2*)Gh, (const double2*)c->t.tw64);
   else
-    hipLaunchKernelGGL(k_fft_r2c<float>, dim3(rows), dim3(256), lds, st, c->fft, c->lmax, (const float*)G,
-                       (float2*)Gh, (const float2*)c->t.tw32);
+    hipLaunchKernelGGL(k_fft_r2c<float>, dim3(blocks), dim3(256), lds, st, c->fft, c->lmax, c->ntheta, R,
+                       (const float*)G, (float2*)Gh, (const float2*)c->t.tw32);
   return hipGetLastError();
 }
 

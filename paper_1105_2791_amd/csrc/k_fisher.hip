@@ -70,10 +70,10 @@ __global__ __launch_bounds__(64) void k_adj_legendre_cols(int lmax, int ntheta, 
       vn.x = vn.y = vs.x = vs.y = T(0);
       const int col = c0 + q, j = j0 + jj;
       if (jj < nj && col < ncol) {
-        const T2* g = Gh + (size_t)col * ntheta * (lmax + 1);
-        vn = g[(size_t)j * (lmax + 1) + m];
+        const T2* g = Gh + ((size_t)col * (lmax + 1) + m) * ntheta;   // Gh[col][m][ring]
+        vn = g[j];
         const int js = ntheta - 1 - j;
-        if (js != j) vs = g[(size_t)js * (lmax + 1) + m];
+        if (js != j) vs = g[js];
       }
       hn[jj][q] = vn;
       hs[jj][q] = vs;

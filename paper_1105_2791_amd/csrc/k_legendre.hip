@@ -169,14 +169,14 @@ __global__ __launch_bounds__(64) void k_legendre(int lmax, int ntheta, int nrp, 
   for (int q = 0; q < NSEQ; ++q) {
     const int sq = seq0 + q;
     if (sq >= nseq) break;
-    T2* row = F + (size_t)sq * ntheta * (lmax + 1);
+    T2* row = F + ((size_t)sq * (lmax + 1) + m) * ntheta;   // F[seq][m][ring]
     T2 vn, vs;
     vn.x = er[q] + orr[q];
     vn.y = ei[q] + oi[q];
     vs.x = er[q] - orr[q];
     vs.y = ei[q] - oi[q];
-    row[(size_t)j * (lmax + 1) + m] = vn;
-    if (js != j) row[(size_t)js * (lmax + 1) + m] = vs;
+    row[j] = vn;
+    if (js != j) row[js] = vs;
   }
 }
 
@@ -230,12 +230,13 @@ __global__ __launch_bounds__(256) void k_adj_legendre(int lmax, int ntheta, int 
     double dre = 0.0, dim = 0.0;
     for (int j = 0; j < nrp; ++j) {
       const double lv = (double)lrow[(size_t)j * L + li];
-      const T2 gn = gu[(size_t)j * (lmax + 1) + m];
+      const T2* gm = gu + (size_t)m * ntheta;   // Gh[seq][m][ring]
+      const T2 gn = gm[j];
       const int js = ntheta - 1 - j;
       T2 gs;
       gs.x = T(0);
       gs.y = T(0);
-      if (js != j) gs = gu[(size_t)js * (lmax + 1) + m];
+      if (js != j) gs = gm[js];
       const double hr = odd ? (double)gn.x - (double)gs.x : (double)gn.x + (double)gs.x;
       const double hi = odd ? (double)gn.y - (double)gs.y : (double)gn.y + (double)gs.y;
       dre += lv * hr;
