@@ -2,11 +2,13 @@
 """Throughput of the modal bispectrum hot path on one MI355X.
 
 One step = filtered maps (Legendre synthesis + ring FFT) and beta^hat = beta - lin
-(cubic pair x mode reduction with the Monte-Carlo linear term fused in, FP64
-split-K reduction and symmetrisation) for one batch of S synthetic skies at the
-metric shape: l_max = 1000, Gauss-Legendre 1536 x 3072 rings, P = 40 separable
-modes (n_max = 11480), beam/noise spectrum and a |lat| < 10 deg cut.  The
-linear-term state (Monte-Carlo <M_p M_r> planes) is built before timing.
+(cubic pair x mode contraction, the Monte-Carlo linear term as one GEMM over the
+batch, FP64 split-K reduction and symmetrisation) for one batch of S synthetic
+skies at l_max = 1000, Gauss-Legendre 1536 x 3072 rings, P = 40 separable modes
+(n_max = 11480), beam/noise spectrum and a |lat| < 10 deg cut.  The linear-term
+state (Monte-Carlo <M_p M_r> planes) is built before timing.  The headline path
+(split bf16 by default) is followed by a shorter run of the plain-FP32 path on the
+same GPU.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -79,39 +81,52 @@ def cpu_baseline(lmax, ntheta, nphi, P, rings, V_sims=2, cfg_id=6):
                       f"{t:.1f} s, scaled by {ntheta}/{rings}"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=8, help="skies per step (S)")
-    ap.add_argument("--prec", default="auto", choices=["auto", "bf16x3", "f32", "f64"])
-    ap.add_argument("--lmax", type=int, default=1000)
-    ap.add_argument("--ntheta", type=int, default=1536)
-    ap.add_argument("--nphi", type=int, default=3072)
-    ap.add_argument("--P", type=int, default=40)
-    ap.add_argument("--mc", type=int, default=16, help="Monte-Carlo skies for the linear term")
-    ap.add_argument("--cpu-rings", type=int, default=8)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        log("bench.py: only --gpus 1 is supported (single-GPU build)")
-        sys.exit(2)
+def kernel_rooflines(ctx, stages, prec, S):
+    """Algorithmic work per launch of each timed stage and its rate against the MI355X peak."""
+    lmax, nt, nphi, P = ctx.lmax, ctx.ntheta, ctx.nphi, ctx.P
+    npix = nt * nphi
+    split = prec in ("bf16x3", "f16x3")
+    mfma_peak = PEAK["bf16"] if split else (PEAK["f32_mfma"] if prec == "f32" else PEAK["f64_vec"])
+    mfma_bound = "mfma" if prec != "f64" else "alu"
+    cubic_bound = mfma_bound if ctx.cubic_path()["path"] != "valu" else "alu"
+    real = 8 if prec == "f64" else 4
+    # name: (work per launch, unit of work, bound, peak, products issued per algorithmic MAC)
+    work = {
+        # F[m][ring] = sum_l lambda_lm(ring) a_lm: one complex x real MAC per (l, m, ring, column)
+        "legendre": (2.0 * ctx.nalm * nt * P * S, "flop", mfma_bound, mfma_peak, 4 if prec == "bf16x3" else 3),
+        # read F (complex, m <= lmax per ring) and write the real rings
+        "fft": ((lmax + 1) * nt * P * S * 2 * real + npix * P * S * real, "byte", "hbm", PEAK["hbm"], None),
+        # E_(ab),t = sum_x (M_a M_b)(x) w(x) M_t(x): one MAC per (pair, mode, pixel)
+        "cubic": (2.0 * ctx.npairs * P * npix * S, "flop", cubic_bound,
+                  mfma_peak if cubic_bound == "mfma" else PEAK["f64_vec"], 3),
+        # L_(ab),(s,t) = sum_x V_ab(x) w(x) M^s_t(x): one MAC per (pair, column, pixel)
+        "lingemm": (2.0 * ctx.npairs * P * npix * S, "flop", mfma_bound, mfma_peak, 3),
+    }
+    out = {}
+    for name, (units, kind, bound, peak, issue) in work.items():
+        ms, n = stages.get(name, (0.0, 0))
+        if not n:
+            continue
+        avg = ms / n
+        rate = units / (avg * 1e-3)
+        r = {"bound": bound, "achieved": rate / (1e12 if kind == "flop" else 1e9),
+             "peak": peak / (1e12 if kind == "flop" else 1e9), "unit": "TFLOP/s" if kind == "flop" else "GB/s",
+             "frac": rate / peak, "traffic": None, "avg_ms": avg, "per_launch": units, "per_launch_unit": kind}
+        if split and issue and bound == "mfma":
+            r["mfma_issued_frac"] = issue * rate / peak
+        out[name] = r
+    return out
 
+
+def run_path(args, prec, steps, warmup, make_state=True):
+    """Build a context at the workload shape, time `steps` beta batches, return the figures."""
     import numpy as np
     import torch
     import modal_inputs as mi
     from paper_1105_2791_amd import ModalContext
-    from paper_1105_2791_amd import _lib as L
 
     dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
     lmax, nt, nphi, P, S = args.lmax, args.ntheta, args.nphi, args.P, args.batch
-    prec = args.prec
-    if prec == "auto":
-        prec = "bf16x3"
     cl = mi.filter_cl(lmax, "wmap")
     q = mi.q_basis(P, lmax)
     # the context's own quadrature gives the ring colatitudes for the mask
@@ -119,92 +134,114 @@ def main():
     x, _ = probe.grid()
     probe.close()
     mask = np.repeat(mi.mask_rings(np.arccos(x))[:, None], nphi, axis=1)
-    try:
-        ctx = ModalContext(lmax, nt, nphi, P, prec, q, cl, mask=mask, device=0)
-    except L.ModalError as e:
-        if prec != "bf16x3" or e.status != L.EUNSUPPORTED:
-            raise
-        log("bf16x3 unavailable, falling back to f32")
-        prec = "f32"
-        ctx = ModalContext(lmax, nt, nphi, P, prec, q, cl, mask=mask, device=0)
+    ctx = ModalContext(lmax, nt, nphi, P, prec, q, cl, mask=mask, device=0)
     log(f"bench: lmax={lmax} grid={nt}x{nphi} P={P} nmax={ctx.nmax} S={S} prec={prec}")
 
     # linear-term state from Monte-Carlo skies (not timed)
-    state = ctx.linear_state()
-    ctx.linear_reset(state)
-    for b0 in range(0, args.mc, S):
-        ctx.linear_accumulate(state, make_inputs(lmax, P, min(S, args.mc - b0), 1000 + b0))
-    ctx.linear_finalize(state)
+    state = None
+    if make_state:
+        state = ctx.linear_state()
+        ctx.linear_reset(state)
+        for b0 in range(0, args.mc, S):
+            ctx.linear_accumulate(state, make_inputs(lmax, P, min(S, args.mc - b0), 1000 + b0))
+        ctx.linear_finalize(state)
     alm = ctx._alm(make_inputs(lmax, P, S, 0))
     out = torch.empty((S, ctx.nmax), dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
-    log("bench: state ready")
+    log(f"bench[{prec}]: state ready")
 
     tuned = None
     if not args.no_autotune:
         tuned = ctx.autotune(alm, state)
-        log(f"bench: autotuned {tuned}")
-    for _ in range(args.warmup):
+        log(f"bench[{prec}]: autotuned {tuned}")
+    for _ in range(warmup):
         ctx.beta(alm, state=state, out=out)
     torch.cuda.synchronize()
     ctx.profile_read(reset=True)
     ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for _ in range(steps):
         ctx.beta(alm, state=state, out=out)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.profile(False)
     stages = ctx.profile_read(reset=True)
-    elapsed = t1 - t0
     assert torch.isfinite(out).all().item()
-    value = S * args.steps / elapsed
-    ms_step = 1e3 * elapsed / args.steps
-    log(f"bench: {value:.2f} maps/s, {ms_step:.2f} ms/step; stages: " +
-        ", ".join(f"{k}={v[0] / max(1, v[1]):.3f}ms x{v[1]}" for k, v in stages.items() if v[1]))
+    elapsed = t1 - t0
+    res = {"prec": prec, "value": S * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps, "tuned": tuned,
+           "stages_ms": {k: v[0] / max(1, v[1]) for k, v in stages.items() if v[1]},
+           "kernels": kernel_rooflines(ctx, stages, prec, S), "nmax": ctx.nmax}
+    log(f"bench[{prec}]: {res['value']:.2f} maps/s, {res['ms_per_step']:.2f} ms/step; stages: " +
+        ", ".join(f"{k}={v:.3f}ms" for k, v in res["stages_ms"].items()))
+    del state, alm, out
+    ctx.close()
+    torch.cuda.empty_cache()
+    return res
 
-    # roofline of the dominant kernel (the cubic contraction), timed on the library's stream
-    cub_ms, cub_n = stages["cubic"]
-    cub_avg = cub_ms / max(1, cub_n)
-    npix = nt * nphi
-    flops = 2.0 * ctx.npairs * P * npix * S          # pair x mode contraction, one pass
-    if prec == "bf16x3":
-        bound, peak, unit = "mfma", PEAK["bf16"], "TFLOP/s"
-    elif prec == "f32":
-        bound, peak, unit = "mfma", PEAK["f32_mfma"], "TFLOP/s"
-    else:
-        bound, peak, unit = "alu", PEAK["f64_vec"], "TFLOP/s"
-    kinfo = ctx.cubic_path()
-    if kinfo["path"] == "valu":   # FP64-accumulating vector-ALU contraction
-        bound, peak = "alu", PEAK["f64_vec"]
-    achieved = flops / (cub_avg * 1e-3)
-    roof = {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": unit,
-            "frac": achieved / peak, "traffic": None, "kernel": "cubic pair x mode contraction",
-            "avg_ms": cub_avg, "flop_per_launch": flops}
-    if prec == "bf16x3":
-        roof["mfma_issued_frac"] = 3.0 * achieved * kinfo.get("pad", 1.0) / peak
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=8, help="skies per step (S)")
+    ap.add_argument("--prec", default="bf16x3", choices=["bf16x3", "f16x3", "f32", "f64"])
+    ap.add_argument("--lmax", type=int, default=1000)
+    ap.add_argument("--ntheta", type=int, default=1536)
+    ap.add_argument("--nphi", type=int, default=3072)
+    ap.add_argument("--P", type=int, default=40)
+    ap.add_argument("--mc", type=int, default=16, help="Monte-Carlo skies for the linear term")
+    ap.add_argument("--cpu-rings", type=int, default=8)
+    ap.add_argument("--compare-steps", type=int, default=3, help="timed steps of the plain-FP32 comparison (0: skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-linear", action="store_true", help="beta without the linear term (diagnostic)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        log("bench.py: only --gpus 1 is supported (single-GPU build)")
+        sys.exit(2)
+
+    import torch
+    torch.cuda.set_device(torch.device("cuda", 0))
+    prec = args.prec
+    head = run_path(args, prec, args.steps, args.warmup, make_state=not args.no_linear)
+    fp32 = None
+    if args.compare_steps > 0 and prec != "f32":
+        fp32 = run_path(args, "f32", args.compare_steps, 1, make_state=not args.no_linear)
+
+    # the dominant kernel's roofline (by time per step)
+    dom = max(head["kernels"].items(), key=lambda kv: kv[1]["avg_ms"])
+    roof = dict(dom[1])
+    roof["kernel"] = dom[0]
 
     cpu = None
     if not args.no_cpu_baseline:
         try:
-            cpu = cpu_baseline(lmax, nt, nphi, P, args.cpu_rings)
+            cpu = cpu_baseline(args.lmax, args.ntheta, args.nphi, args.P, args.cpu_rings)
         except Exception as e:  # the baseline is reported, never the target
             log(f"cpu baseline failed: {e!r}")
 
     line = {
-        "metric": METRIC, "value": value, "unit": "maps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {"bf16x3": "bf16", "f32": "f32", "f64": "f64"}[prec],
-        "precision": {"bf16x3": "split bf16 hi+lo (3 MFMA products), fp32 accumulate, fp64 reduce",
-                      "f32": "fp32 maps and products, fp64 accumulate",
+        "metric": METRIC, "value": head["value"], "unit": "maps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"bf16x3": "bf16", "f16x3": "f16", "f32": "f32", "f64": "f64"}[prec],
+        "precision": {"bf16x3": "split bf16 hi+lo on the matrix cores, fp32 accumulate, fp64 reduce",
+                      "f16x3": "split fp16 hi+lo (scaled) on the matrix cores, fp32 accumulate, fp64 reduce",
+                      "f32": "fp32 maps and matrix-core products, compensated fp32 accumulate, fp64 reduce",
                       "f64": "fp64"}[prec],
         "data": "synthetic",
-        "config": {"workload": f"metric1000: lmax={lmax} GL {nt}x{nphi} P={P} nmax={ctx.nmax}, "
-                               f"beam+noise spectrum, |lat|<10deg cut, MC linear term ({args.mc} skies)",
-                   "batch": S, "prec": prec, "tuned": tuned},
-        "stages_ms": {k: v[0] / max(1, v[1]) for k, v in stages.items() if v[1]},
+        "config": {"workload": f"lmax={args.lmax} GL {args.ntheta}x{args.nphi} P={args.P} nmax={head['nmax']}, "
+                               f"beam+noise spectrum, |lat|<10deg cut, "
+                               + ("no linear term" if args.no_linear else f"MC linear term ({args.mc} skies)"),
+                   "batch": args.batch, "prec": prec, "tuned": head["tuned"]},
+        "stages_ms": head["stages_ms"],
         "roofline": roof,
+        "kernels": head["kernels"],
+        "fp32_compare": None if fp32 is None else {
+            "value": fp32["value"], "ms_per_step": fp32["ms_per_step"], "steps": args.compare_steps,
+            "stages_ms": fp32["stages_ms"], "speedup": head["value"] / fp32["value"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

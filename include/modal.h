@@ -123,7 +123,8 @@ typedef enum {
   MODAL_STAGE_ADJ_LEGENDRE = 7, /* adjoint Legendre contraction (incl. lambda table) */
   MODAL_STAGE_COVARIANCE = 8, /* SYRK / Fisher assembly                             */
   MODAL_STAGE_CHOLESKY = 9,   /* factorisation, triangular solves, dots             */
-  MODAL_NSTAGES = 10
+  MODAL_STAGE_LINGEMM = 10,   /* linear term as a batch GEMM against the pair means   */
+  MODAL_NSTAGES = 11
 } modal_stage;
 
 /* ------------------------------------------------------------------------ */

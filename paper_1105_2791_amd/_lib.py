@@ -65,7 +65,7 @@ _SIGS = {
 }
 
 STAGES = ["legendre", "fft", "cubic", "reduce", "linacc", "adj_pair", "adj_fft", "adj_legendre",
-          "covariance", "cholesky"]
+          "covariance", "cholesky", "lingemm"]
 
 
 def lib():

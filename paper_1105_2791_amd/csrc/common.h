@@ -115,7 +115,17 @@ hipError_t launch_cubic(const modal_ctx* c, const void* maps, const void* V, int
 // three-pairing sum (1/3 for beta, 1 for the linear term alone)
 hipError_t launch_reduce_symm(const modal_ctx* c, const double* partials, int S, int nchunk, double scale,
                               double* E, double* out, hipStream_t st);
+hipError_t launch_reduce_symm2(const modal_ctx* c, const double* part, int S, int nchunk, double scale, double* E,
+                               const double* part2, int nchunk2, double scale2, double* E2, double* out,
+                               hipStream_t st);
 void make_pair_blocks(int P, std::vector<int2>& out);
+// linear term as one GEMM over the batch (V read once per batch)
+hipError_t launch_lin_gemm(const modal_ctx* c, const void* maps, const void* V, int S, int nchunk, int chunk_px,
+                           double* part, hipStream_t st);
+size_t lin_gemm_lds(const modal_ctx* c);
+hipError_t lin_gemm_set_lds(size_t bytes);
+int lin_gemm_chunk_px(const modal_ctx* c);
+int lin_gemm_nchunk(const modal_ctx* c);
 
 // linear term accumulator
 hipError_t launch_lin_accumulate(const modal_ctx* c, const void* maps, int S, void* U, hipStream_t st);

@@ -126,6 +126,11 @@ size_t part_bytes(const modal_ctx* c, int S) {
   return (size_t)S * nc * c->npairs * c->P * 8;
 }
 size_t E_bytes(const modal_ctx* c, int S) { return (size_t)S * c->npairs * c->P * 8; }
+// the MFMA paths keep the linear term's partial sums apart (batch GEMM)
+size_t part2_bytes(const modal_ctx* c, int S) {
+  return cubic_mfma_available(c) ? (size_t)S * lin_gemm_nchunk(c) * c->npairs * c->P * 8 : 0;
+}
+size_t E2_bytes(const modal_ctx* c, int S) { return cubic_mfma_available(c) ? E_bytes(c, S) : 0; }
 size_t lam_bytes(const modal_ctx* c) { return (size_t)c->nalm * c->nrp * real_bytes(c); }
 
 size_t ws_size(const modal_ctx* c, int op, int S) {
@@ -135,6 +140,7 @@ size_t ws_size(const modal_ctx* c, int op, int S) {
     case MODAL_OP_BETA:
     case MODAL_OP_LINEAR_APPLY:
       cv.take(F_bytes(c, S)); cv.take(maps_bytes(c, S)); cv.take(part_bytes(c, S)); cv.take(E_bytes(c, S));
+      cv.take(part2_bytes(c, S)); cv.take(E2_bytes(c, S));
       break;
     case MODAL_OP_LINEAR_ACCUMULATE: cv.take(F_bytes(c, S)); cv.take(maps_bytes(c, S)); break;
     case MODAL_OP_BETA_VJP:
@@ -223,11 +229,26 @@ modal_status run_maps(modal_ctx* c, const void* alm, int S, void* F, void* maps,
   return MODAL_OK;
 }
 
+// mode 0: beta; 1: beta - lin; 2: lin alone.  The MFMA paths evaluate the linear
+// term as a separate GEMM over the whole batch (V read once per batch) and combine
+// the two partial sums in the reduction; the FP64 path fuses it into the contraction.
 modal_status run_cubic(modal_ctx* c, const void* maps, const void* V, int S, int mode, double* part, double* E,
-                       double scale, double* out, hipStream_t st) {
-  if (cubic_mfma_available(c)) STAGE(MODAL_STAGE_CUBIC, launch_cubic_mfma(c, maps, V, S, mode, part, st));
-  else STAGE(MODAL_STAGE_CUBIC, launch_cubic_valu(c, maps, V, S, mode, part, st));
-  STAGE(MODAL_STAGE_REDUCE, launch_reduce_symm(c, part, S, nchunk_for(c), scale, E, out, st));
+                       double* part2, double* E2, double* out, hipStream_t st) {
+  const int nchunk = nchunk_for(c);
+  if (!cubic_mfma_available(c)) {
+    STAGE(MODAL_STAGE_CUBIC, launch_cubic_valu(c, maps, V, S, mode, part, st));
+    STAGE(MODAL_STAGE_REDUCE, launch_reduce_symm(c, part, S, nchunk, mode == 2 ? 1.0 : 1.0 / 3.0, E, out, st));
+    return MODAL_OK;
+  }
+  if (mode != 2) STAGE(MODAL_STAGE_CUBIC, launch_cubic_mfma(c, maps, nullptr, S, 0, part, st));
+  const int nlin = lin_gemm_nchunk(c);
+  if (mode != 0)
+    STAGE(MODAL_STAGE_LINGEMM, launch_lin_gemm(c, maps, V, S, nlin, lin_gemm_chunk_px(c), part2, st));
+  if (mode == 0) STAGE(MODAL_STAGE_REDUCE, launch_reduce_symm(c, part, S, nchunk, 1.0 / 3.0, E, out, st));
+  else if (mode == 2) STAGE(MODAL_STAGE_REDUCE, launch_reduce_symm(c, part2, S, nlin, 1.0, E2, out, st));
+  else
+    STAGE(MODAL_STAGE_REDUCE,
+          launch_reduce_symm2(c, part, S, nchunk, 1.0 / 3.0, E, part2, nlin, -1.0, E2, out, st));
   return MODAL_OK;
 }
 
@@ -283,6 +304,9 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
       if (need > 65536 && legendre_mfma_set_lds(need) != hipSuccess) return bail(MODAL_EDEVICE);
       c->legendre_mfma = true;
     }
+    const size_t lneed = lin_gemm_lds(c);
+    if (lneed + 2048 > c->max_lds) return bail(MODAL_EUNSUPPORTED);   // + its static scale tables
+    if (lneed > 65536 && lin_gemm_set_lds(lneed) != hipSuccess) return bail(MODAL_EDEVICE);
   }
   // --- grid
   gauss_legendre(ntheta, c->x_host, c->wgl_host);
@@ -466,8 +490,10 @@ modal_status modal_beta(modal_ctx* c, const void* alm, int S, const void* state,
   void* maps = cv.take(maps_bytes(c, S));
   double* part = (double*)cv.take(part_bytes(c, S));
   double* E = (double*)cv.take(E_bytes(c, S));
+  double* part2 = (double*)cv.take(part2_bytes(c, S));
+  double* E2 = (double*)cv.take(E2_bytes(c, S));
   if ((s = run_maps(c, alm, S, F, maps, st)) != MODAL_OK) return s;
-  return run_cubic(c, maps, state, S, state ? 1 : 0, part, E, 1.0 / 3.0, beta, st);
+  return run_cubic(c, maps, state, S, state ? 1 : 0, part, E, part2, E2, beta, st);
 }
 
 modal_status modal_linear_term(modal_ctx* c, int mode, const void* alm, int S, void* state, double* lin, void* ws,
@@ -512,8 +538,10 @@ modal_status modal_linear_term(modal_ctx* c, int mode, const void* alm, int S, v
       void* maps = cv.take(maps_bytes(c, S));
       double* part = (double*)cv.take(part_bytes(c, S));
       double* E = (double*)cv.take(E_bytes(c, S));
+      double* part2 = (double*)cv.take(part2_bytes(c, S));
+      double* E2 = (double*)cv.take(E2_bytes(c, S));
       if ((s = run_maps(c, alm, S, F, maps, st)) != MODAL_OK) return s;
-      return run_cubic(c, maps, state, S, 2, part, E, 1.0, lin, st);
+      return run_cubic(c, maps, state, S, 2, part, E, part2, E2, lin, st);
     }
     default:
       return fail(c, MODAL_EINVAL, "linear_term: bad mode");

@@ -85,15 +85,19 @@ __global__ void k_reduce_chunks(int nchunk, size_t per, int S, const double* __r
   E[i] = acc;
 }
 
+// out_n = scale * (three pairings of E) + scale2 * (three pairings of E2) (E2 optional)
 __global__ void k_symm(int nmax, int npairs, int P, int S, double scale, const int* __restrict__ tri,
-                       const double* __restrict__ E, double* __restrict__ out) {
+                       const double* __restrict__ E, double scale2, const double* __restrict__ E2,
+                       double* __restrict__ out) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
   if (n >= nmax) return;
   const int* tr = tri + 6 * n;  // p, r, s, pair(pr), pair(ps), pair(rs)
-  const double* Es = E + (size_t)s * npairs * P;
-  const double v = Es[(size_t)tr[3] * P + tr[2]] + Es[(size_t)tr[4] * P + tr[1]] + Es[(size_t)tr[5] * P + tr[0]];
-  out[(size_t)s * nmax + n] = scale * v;
+  const size_t o = (size_t)s * npairs * P;
+  const size_t i1 = (size_t)tr[3] * P + tr[2], i2 = (size_t)tr[4] * P + tr[1], i3 = (size_t)tr[5] * P + tr[0];
+  double v = scale * (E[o + i1] + E[o + i2] + E[o + i3]);
+  if (E2) v += scale2 * (E2[o + i1] + E2[o + i2] + E2[o + i3]);
+  out[(size_t)s * nmax + n] = v;
 }
 
 }  // namespace
@@ -122,13 +126,23 @@ hipError_t launch_cubic_valu(const modal_ctx* c, const void* maps, const void* V
 
 hipError_t launch_reduce_symm(const modal_ctx* c, const double* part, int S, int nchunk, double scale, double* E,
                               double* out, hipStream_t st) {
+  return launch_reduce_symm2(c, part, S, nchunk, scale, E, nullptr, 0, 0.0, nullptr, out, st);
+}
+
+hipError_t launch_reduce_symm2(const modal_ctx* c, const double* part, int S, int nchunk, double scale, double* E,
+                               const double* part2, int nchunk2, double scale2, double* E2, double* out,
+                               hipStream_t st) {
   const size_t per = (size_t)c->npairs * c->P;
   const size_t tot = per * S;
   hipLaunchKernelGGL(k_reduce_chunks, dim3((tot + 255) / 256), dim3(256), 0, st, nchunk, per, S, part, E);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (part2) {
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((tot + 255) / 256), dim3(256), 0, st, nchunk2, per, S, part2, E2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_symm, dim3((c->nmax + 255) / 256, S), dim3(256), 0, st, c->nmax, c->npairs, c->P, S, scale,
-                     c->t.tri, E, out);
+                     c->t.tri, E, scale2, part2 ? E2 : nullptr, out);
   return hipGetLastError();
 }
 

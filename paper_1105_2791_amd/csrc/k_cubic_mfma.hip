@@ -359,6 +359,14 @@ int chunk_px_for(const modal_ctx* c, int target) {
 int chunk_target_default(const modal_ctx* c) { return c->prec == MODAL_F32 ? 4096 : 65536; }
 int chunk_target_min(const modal_ctx* c) { return c->prec == MODAL_F32 ? 2048 : 16384; }
 
+// The linear-term GEMM accumulates exact (split) or compensated (FP32) products and
+// always uses long chunks.
+int lin_gemm_chunk_px(const modal_ctx* c) { return chunk_px_for(c, 65536); }
+int lin_gemm_nchunk(const modal_ctx* c) {
+  const int px = lin_gemm_chunk_px(c);
+  return (c->npix + px - 1) / px;
+}
+
 int cubic_mfma_nchunk_max(const modal_ctx* c) {
   const int px = chunk_px_for(c, chunk_target_min(c));
   return (c->npix + px - 1) / px;
