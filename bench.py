@@ -2,8 +2,8 @@
 """Throughput of the modal bispectrum hot path on one MI355X.
 
 One step = filtered maps (Legendre synthesis + ring FFT) and beta^hat = beta - lin
-(cubic pair x mode contraction, the Monte-Carlo linear term as one GEMM over the
-batch, FP64 split-K reduction and symmetrisation) for one batch of S synthetic
+(cubic pair x mode contraction, the Monte-Carlo linear term from the harmonic
+transforms of the pair means, FP64 split-K reduction and symmetrisation) for one batch of S synthetic
 skies at l_max = 1000, Gauss-Legendre 1536 x 3072 rings, P = 40 separable modes
 (n_max = 11480), beam/noise spectrum and a |lat| < 10 deg cut.  The linear-term
 state (Monte-Carlo <M_p M_r> planes) is built before timing.  The headline path
@@ -99,8 +99,8 @@ def kernel_rooflines(ctx, stages, prec, S):
         # E_(ab),t = sum_x (M_a M_b)(x) w(x) M_t(x): one MAC per (pair, mode, pixel)
         "cubic": (2.0 * ctx.npairs * P * npix * S, "flop", cubic_bound,
                   mfma_peak if cubic_bound == "mfma" else PEAK["f64_vec"], 3),
-        # L_(ab),(s,t) = sum_x V_ab(x) w(x) M^s_t(x): one MAC per (pair, column, pixel)
-        "lingemm": (2.0 * ctx.npairs * P * npix * S, "flop", mfma_bound, mfma_peak, 3),
+        # linear term from the harmonic pair means: one pass over Z[npairs][nalm]
+        "linear": (ctx.npairs * ctx.nalm * 2 * real, "byte", "hbm", PEAK["hbm"], None),
     }
     out = {}
     for name, (units, kind, bound, peak, issue) in work.items():

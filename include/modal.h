@@ -97,13 +97,15 @@ typedef enum {
   MODAL_OP_BETA_VJP = 4,
   MODAL_OP_COVARIANCE_SAMPLE = 5,
   MODAL_OP_COVARIANCE_FISHER = 6,
-  MODAL_OP_FNL = 7
+  MODAL_OP_FNL = 7,
+  MODAL_OP_LINEAR_FINALIZE = 8
 } modal_op;
 
 typedef enum {
   MODAL_LIN_RESET = 0,       /* zero the accumulator and its count                   */
   MODAL_LIN_ACCUMULATE = 1,  /* U_pr(x) += sum over the S maps of M_p M_r            */
-  MODAL_LIN_FINALIZE = 2,    /* V = U / count (in place); state becomes usable       */
+  MODAL_LIN_FINALIZE = 2,    /* V = U / count (in place) and its harmonic transform Z;
+                                state becomes usable                                 */
   MODAL_LIN_APPLY = 3        /* lin[S][nmax] for the given a_lm                      */
 } modal_lin_mode;
 
@@ -123,7 +125,7 @@ typedef enum {
   MODAL_STAGE_ADJ_LEGENDRE = 7, /* adjoint Legendre contraction (incl. lambda table) */
   MODAL_STAGE_COVARIANCE = 8, /* SYRK / Fisher assembly                             */
   MODAL_STAGE_CHOLESKY = 9,   /* factorisation, triangular solves, dots             */
-  MODAL_STAGE_LINGEMM = 10,   /* linear term as a batch GEMM against the pair means   */
+  MODAL_STAGE_LINEAR = 10,    /* linear term from the harmonic pair means            */
   MODAL_NSTAGES = 11
 } modal_stage;
 
@@ -161,7 +163,9 @@ modal_status modal_grid(const modal_ctx* ctx, double* x_host, double* w_host);
 
 /* Bytes of workspace an operation needs for S maps (N for covariance). */
 modal_status modal_workspace_size(const modal_ctx* ctx, int op, int S, size_t* bytes);
-/* Bytes of the linear-term state (pair accumulator, one plane per pair). */
+/* Bytes of the linear-term state: the pair accumulator (one pixel plane per
+ * pair, [npairs][ntheta][nphi] real, at offset 0; after FINALIZE the pair means
+ * V), then, 256-byte aligned, Z[npairs][nalm] complex written by FINALIZE. */
 size_t modal_linear_state_size(const modal_ctx* ctx);
 
 /* ------------------------------------------------------------------------ */
@@ -179,8 +183,12 @@ modal_status modal_filter_maps(modal_ctx* ctx, const void* alm_dev, int S, void*
  * eq. bispectrumest: the three pairings of "3 C a").
  *   RESET      state is zeroed (alm may be NULL, S ignored)
  *   ACCUMULATE U_pr += sum over S maps of M_p M_r
- *   FINALIZE   V = U / total count; afterwards the state may be passed to
- *              modal_beta / APPLY / modal_beta_vjp
+ *   FINALIZE   V = U / total count, then Z_ab,lm = c_m sum_x w V_ab lambda_lm
+ *              e^{-i m phi} (c_m = 2 - delta_m0) for every pair; afterwards the
+ *              state may be passed to modal_beta / APPLY / modal_beta_vjp.
+ *              Workspace: modal_workspace_size(MODAL_OP_LINEAR_FINALIZE, 1).
+ *   The linear term is evaluated from Z as sum_l qw_t(l) sum_m Re(a_lm conj Z_ab,lm),
+ *   an exact rearrangement of sum_x w V_ab M_t (the maps are finite harmonic sums).
  *   APPLY      lin_dev [S][nmax] float64 = lin(a) for the S maps
  * state_dev has modal_linear_state_size() bytes; the count lives in the
  * context, so a state is tied to the context that built it.

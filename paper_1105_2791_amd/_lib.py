@@ -16,7 +16,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "modal.h")
 OK, EINVAL, ESHAPE, EDEVICE, ENOTPD, ENOTREADY, EUNSUPPORTED, ENOSPACE = range(8)
 F64, F32, BF16X3, F16X3 = range(4)
 OP_FILTER_MAPS, OP_BETA, OP_LINEAR_ACCUMULATE, OP_LINEAR_APPLY, OP_BETA_VJP, \
-    OP_COVARIANCE_SAMPLE, OP_COVARIANCE_FISHER, OP_FNL = range(8)
+    OP_COVARIANCE_SAMPLE, OP_COVARIANCE_FISHER, OP_FNL, OP_LINEAR_FINALIZE = range(9)
 LIN_RESET, LIN_ACCUMULATE, LIN_FINALIZE, LIN_APPLY = range(4)
 COV_SAMPLE, COV_FISHER = range(2)
 
@@ -65,7 +65,7 @@ _SIGS = {
 }
 
 STAGES = ["legendre", "fft", "cubic", "reduce", "linacc", "adj_pair", "adj_fft", "adj_legendre",
-          "covariance", "cholesky", "lingemm"]
+          "covariance", "cholesky", "linear"]
 
 
 def lib():

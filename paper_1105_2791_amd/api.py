@@ -162,8 +162,9 @@ class ModalContext:
                                                 _ptr(ws), ws.numel(), self._stream()))
 
     def linear_finalize(self, state):
-        self._check(self._lib.modal_linear_term(self._h, L.LIN_FINALIZE, None, 0, _ptr(state), None, None, 0,
-                                                self._stream()))
+        ws = self.workspace(L.OP_LINEAR_FINALIZE, 1)
+        self._check(self._lib.modal_linear_term(self._h, L.LIN_FINALIZE, None, 0, _ptr(state), None, _ptr(ws),
+                                                ws.numel(), self._stream()))
 
     def linear_apply(self, state, alm) -> torch.Tensor:
         a = self._alm(alm)

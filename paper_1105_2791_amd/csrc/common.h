@@ -106,26 +106,24 @@ hipError_t launch_adj_legendre_cols(const modal_ctx* c, const void* lam, const v
 hipError_t launch_cross_spectra(const modal_ctx* c, const void* Z, const double* cvar, double* X, hipStream_t st);
 hipError_t launch_fisher_assemble(const modal_ctx* c, const double* X, double scale, double* F, hipStream_t st);
 
-// cubic pixel reduction.  mode: 0 = A = M_p M_r, 1 = M_p M_r - 3 V, 2 = A = V
-// partials[S][nchunk][npairs][P] float64
+// cubic pixel reduction E_(ab),t = sum_x w M_a M_b M_t into
+// partials[S][nchunk][npairs][P] float64 (VALU FP64 path / matrix-core paths)
 int cubic_nchunk(const modal_ctx* c);
-hipError_t launch_cubic(const modal_ctx* c, const void* maps, const void* V, int S, int mode,
-                        double* partials, hipStream_t st);
-// sum chunk partials and symmetrise into out[S][nmax]; scale multiplies the
-// three-pairing sum (1/3 for beta, 1 for the linear term alone)
+hipError_t launch_cubic_valu(const modal_ctx* c, const void* maps, int S, double* partials, hipStream_t st);
+hipError_t launch_cubic_mfma(const modal_ctx* c, const void* maps, int S, double* partials, hipStream_t st);
+bool cubic_mfma_available(const modal_ctx* c);
+int cubic_mfma_nchunk(const modal_ctx* c);
+int cubic_mfma_nchunk_max(const modal_ctx* c);
+// out[S][nmax] = scale (three pairings of the chunk sum of partials) + scale2 (three
+// pairings of E2[S][npairs][P]); partials or E2 may be null
 hipError_t launch_reduce_symm(const modal_ctx* c, const double* partials, int S, int nchunk, double scale,
-                              double* E, double* out, hipStream_t st);
-hipError_t launch_reduce_symm2(const modal_ctx* c, const double* part, int S, int nchunk, double scale, double* E,
-                               const double* part2, int nchunk2, double scale2, double* E2, double* out,
-                               hipStream_t st);
+                              double* E, const double* E2, double scale2, double* out, hipStream_t st);
 void make_pair_blocks(int P, std::vector<int2>& out);
-// linear term as one GEMM over the batch (V read once per batch)
-hipError_t launch_lin_gemm(const modal_ctx* c, const void* maps, const void* V, int S, int nchunk, int chunk_px,
-                           double* part, hipStream_t st);
-size_t lin_gemm_lds(const modal_ctx* c);
-hipError_t lin_gemm_set_lds(size_t bytes);
-int lin_gemm_chunk_px(const modal_ctx* c);
-int lin_gemm_nchunk(const modal_ctx* c);
+// linear term from the harmonic pair means Z[npairs][nalm] (k_lin_harm.hip):
+// X[S][npairs][lmax+1] scratch, L[S][npairs][P] = sum_x w V_ab M^s_t
+hipError_t launch_weight_planes(const modal_ctx* c, const void* V, int nk, void* G, hipStream_t st);
+hipError_t launch_lin_harmonic(const modal_ctx* c, const void* Z, const void* alm, int S, double* X, double* L,
+                               hipStream_t st);
 
 // linear term accumulator
 hipError_t launch_lin_accumulate(const modal_ctx* c, const void* maps, int S, void* U, hipStream_t st);

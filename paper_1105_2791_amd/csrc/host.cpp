@@ -13,13 +13,6 @@
 #include "common.h"
 
 namespace modal {
-hipError_t launch_cubic_valu(const modal_ctx* c, const void* maps, const void* V, int S, int mode, double* part,
-                             hipStream_t st);
-hipError_t launch_cubic_mfma(const modal_ctx* c, const void* maps, const void* V, int S, int mode, double* part,
-                             hipStream_t st);
-bool cubic_mfma_available(const modal_ctx* c);
-int cubic_mfma_nchunk(const modal_ctx* c);
-int cubic_mfma_nchunk_max(const modal_ctx* c);
 hipError_t fft_set_lds_limit(size_t bytes);
 }  // namespace modal
 
@@ -126,21 +119,28 @@ size_t part_bytes(const modal_ctx* c, int S) {
   return (size_t)S * nc * c->npairs * c->P * 8;
 }
 size_t E_bytes(const modal_ctx* c, int S) { return (size_t)S * c->npairs * c->P * 8; }
-// the MFMA paths keep the linear term's partial sums apart (batch GEMM)
-size_t part2_bytes(const modal_ctx* c, int S) {
-  return cubic_mfma_available(c) ? (size_t)S * lin_gemm_nchunk(c) * c->npairs * c->P * 8 : 0;
-}
-size_t E2_bytes(const modal_ctx* c, int S) { return cubic_mfma_available(c) ? E_bytes(c, S) : 0; }
+size_t X_bytes(const modal_ctx* c, int S) { return (size_t)S * c->npairs * (c->lmax + 1) * 8; }
 size_t lam_bytes(const modal_ctx* c) { return (size_t)c->nalm * c->nrp * real_bytes(c); }
+// linear-term state: pixel pair means V[npairs][npix], then their weighted adjoint
+// transforms Z[npairs][nalm] (complex, alm dtype)
+size_t lin_V_bytes(const modal_ctx* c) { return align256((size_t)c->npairs * c->npix * real_bytes(c)); }
+size_t lin_Z_bytes(const modal_ctx* c) { return align256((size_t)c->npairs * c->nalm * 2 * real_bytes(c)); }
+const void* lin_Z(const modal_ctx* c, const void* state) { return (const char*)state + lin_V_bytes(c); }
+// pair planes transformed per pass when a state is finalised
+int fin_chunk(const modal_ctx* c) { return std::min(c->npairs, 64); }
 
 size_t ws_size(const modal_ctx* c, int op, int S) {
   Carver cv(nullptr);
   switch (op) {
     case MODAL_OP_FILTER_MAPS: cv.take(F_bytes(c, S)); break;
     case MODAL_OP_BETA:
-    case MODAL_OP_LINEAR_APPLY:
       cv.take(F_bytes(c, S)); cv.take(maps_bytes(c, S)); cv.take(part_bytes(c, S)); cv.take(E_bytes(c, S));
-      cv.take(part2_bytes(c, S)); cv.take(E2_bytes(c, S));
+      cv.take(X_bytes(c, S)); cv.take(E_bytes(c, S));
+      break;
+    case MODAL_OP_LINEAR_APPLY: cv.take(X_bytes(c, S)); cv.take(E_bytes(c, S)); break;
+    case MODAL_OP_LINEAR_FINALIZE:
+      cv.take(lam_bytes(c)); cv.take((size_t)fin_chunk(c) * c->npix * real_bytes(c));
+      cv.take((size_t)fin_chunk(c) * c->ntheta * (c->lmax + 1) * 2 * real_bytes(c));
       break;
     case MODAL_OP_LINEAR_ACCUMULATE: cv.take(F_bytes(c, S)); cv.take(maps_bytes(c, S)); break;
     case MODAL_OP_BETA_VJP:
@@ -229,26 +229,15 @@ modal_status run_maps(modal_ctx* c, const void* alm, int S, void* F, void* maps,
   return MODAL_OK;
 }
 
-// mode 0: beta; 1: beta - lin; 2: lin alone.  The MFMA paths evaluate the linear
-// term as a separate GEMM over the whole batch (V read once per batch) and combine
-// the two partial sums in the reduction; the FP64 path fuses it into the contraction.
-modal_status run_cubic(modal_ctx* c, const void* maps, const void* V, int S, int mode, double* part, double* E,
-                       double* part2, double* E2, double* out, hipStream_t st) {
-  const int nchunk = nchunk_for(c);
-  if (!cubic_mfma_available(c)) {
-    STAGE(MODAL_STAGE_CUBIC, launch_cubic_valu(c, maps, V, S, mode, part, st));
-    STAGE(MODAL_STAGE_REDUCE, launch_reduce_symm(c, part, S, nchunk, mode == 2 ? 1.0 : 1.0 / 3.0, E, out, st));
-    return MODAL_OK;
-  }
-  if (mode != 2) STAGE(MODAL_STAGE_CUBIC, launch_cubic_mfma(c, maps, nullptr, S, 0, part, st));
-  const int nlin = lin_gemm_nchunk(c);
-  if (mode != 0)
-    STAGE(MODAL_STAGE_LINGEMM, launch_lin_gemm(c, maps, V, S, nlin, lin_gemm_chunk_px(c), part2, st));
-  if (mode == 0) STAGE(MODAL_STAGE_REDUCE, launch_reduce_symm(c, part, S, nchunk, 1.0 / 3.0, E, out, st));
-  else if (mode == 2) STAGE(MODAL_STAGE_REDUCE, launch_reduce_symm(c, part2, S, nlin, 1.0, E2, out, st));
-  else
-    STAGE(MODAL_STAGE_REDUCE,
-          launch_reduce_symm2(c, part, S, nchunk, 1.0 / 3.0, E, part2, nlin, -1.0, E2, out, st));
+// beta (state == nullptr) or beta - lin for S maps: the cubic contraction over
+// pixels, and the linear term from the state's harmonic pair means.
+modal_status run_beta(modal_ctx* c, const void* maps, const void* alm, const void* state, int S, double* part,
+                      double* E, double* X, double* L, double* out, hipStream_t st) {
+  if (cubic_mfma_available(c)) STAGE(MODAL_STAGE_CUBIC, launch_cubic_mfma(c, maps, S, part, st));
+  else STAGE(MODAL_STAGE_CUBIC, launch_cubic_valu(c, maps, S, part, st));
+  if (state) STAGE(MODAL_STAGE_LINEAR, launch_lin_harmonic(c, lin_Z(c, state), alm, S, X, L, st));
+  STAGE(MODAL_STAGE_REDUCE,
+        launch_reduce_symm(c, part, S, nchunk_for(c), 1.0 / 3.0, E, state ? L : nullptr, -1.0, out, st));
   return MODAL_OK;
 }
 
@@ -304,9 +293,6 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
       if (need > 65536 && legendre_mfma_set_lds(need) != hipSuccess) return bail(MODAL_EDEVICE);
       c->legendre_mfma = true;
     }
-    const size_t lneed = lin_gemm_lds(c);
-    if (lneed + 2048 > c->max_lds) return bail(MODAL_EUNSUPPORTED);   // + its static scale tables
-    if (lneed > 65536 && lin_gemm_set_lds(lneed) != hipSuccess) return bail(MODAL_EDEVICE);
   }
   // --- grid
   gauss_legendre(ntheta, c->x_host, c->wgl_host);
@@ -457,12 +443,12 @@ modal_status modal_grid(const modal_ctx* c, double* x_host, double* w_host) {
 }
 
 modal_status modal_workspace_size(const modal_ctx* c, int op, int S, size_t* bytes) {
-  if (!c || !bytes || S < 0 || op < MODAL_OP_FILTER_MAPS || op > MODAL_OP_FNL) return MODAL_EINVAL;
+  if (!c || !bytes || S < 0 || op < MODAL_OP_FILTER_MAPS || op > MODAL_OP_LINEAR_FINALIZE) return MODAL_EINVAL;
   *bytes = ws_size(c, op, S);
   return MODAL_OK;
 }
 
-size_t modal_linear_state_size(const modal_ctx* c) { return c ? align256((size_t)c->npairs * c->npix * real_bytes(c)) : 0; }
+size_t modal_linear_state_size(const modal_ctx* c) { return c ? lin_V_bytes(c) + lin_Z_bytes(c) : 0; }
 
 modal_status modal_filter_maps(modal_ctx* c, const void* alm, int S, void* maps, void* ws, size_t ws_bytes,
                                modal_stream_t stream) {
@@ -490,10 +476,10 @@ modal_status modal_beta(modal_ctx* c, const void* alm, int S, const void* state,
   void* maps = cv.take(maps_bytes(c, S));
   double* part = (double*)cv.take(part_bytes(c, S));
   double* E = (double*)cv.take(E_bytes(c, S));
-  double* part2 = (double*)cv.take(part2_bytes(c, S));
-  double* E2 = (double*)cv.take(E2_bytes(c, S));
+  double* X = (double*)cv.take(X_bytes(c, S));
+  double* L = (double*)cv.take(E_bytes(c, S));
   if ((s = run_maps(c, alm, S, F, maps, st)) != MODAL_OK) return s;
-  return run_cubic(c, maps, state, S, state ? 1 : 0, part, E, part2, E2, beta, st);
+  return run_beta(c, maps, alm, state, S, part, E, X, L, beta, st);
 }
 
 modal_status modal_linear_term(modal_ctx* c, int mode, const void* alm, int S, void* state, double* lin, void* ws,
@@ -523,25 +509,40 @@ modal_status modal_linear_term(modal_ctx* c, int mode, const void* alm, int S, v
       c->lin_count += S;
       return MODAL_OK;
     }
-    case MODAL_LIN_FINALIZE:
+    case MODAL_LIN_FINALIZE: {
       if (state != c->lin_state || c->lin_final || c->lin_count <= 0)
         return fail(c, MODAL_ENOTREADY, "linear_term: FINALIZE needs an accumulated, unfinalised state");
+      if ((s = check_ws(c, MODAL_OP_LINEAR_FINALIZE, 1, ws, ws_bytes)) != MODAL_OK) return s;
       HIPTRY(launch_lin_scale(c, state, 1.0 / (double)c->lin_count, st));
+      // Z = c_m sum_j lambda_lm sum_k w V e^{-i m phi_k} for every pair plane
+      Carver cv(ws);
+      void* lam = cv.take(lam_bytes(c));
+      const int nch = fin_chunk(c);
+      void* G = cv.take((size_t)nch * c->npix * real_bytes(c));
+      void* Gh = cv.take((size_t)nch * c->ntheta * (c->lmax + 1) * 2 * real_bytes(c));
+      STAGE(MODAL_STAGE_ADJ_LEGENDRE, launch_lambda_table(c, lam, st));
+      char* Z = (char*)state + lin_V_bytes(c);
+      for (int p0 = 0; p0 < c->npairs; p0 += nch) {
+        const int nk = std::min(nch, c->npairs - p0);
+        const void* Vp = (const char*)state + (size_t)p0 * c->npix * real_bytes(c);
+        STAGE(MODAL_STAGE_ADJ_PAIR, launch_weight_planes(c, Vp, nk, G, st));
+        STAGE(MODAL_STAGE_ADJ_FFT, launch_fft_r2c_rows(c, G, (size_t)nk, Gh, st));
+        STAGE(MODAL_STAGE_ADJ_LEGENDRE,
+              launch_adj_legendre_cols(c, lam, Gh, nk, Z + (size_t)p0 * c->nalm * 2 * real_bytes(c), st));
+      }
       c->lin_final = true;
       return MODAL_OK;
+    }
     case MODAL_LIN_APPLY: {
       if (!alm || !lin || S <= 0) return fail(c, MODAL_EINVAL, "linear_term: APPLY needs alm, lin and S > 0");
       if ((s = check_state(c, state)) != MODAL_OK) return s;
       if ((s = check_ws(c, MODAL_OP_LINEAR_APPLY, S, ws, ws_bytes)) != MODAL_OK) return s;
       Carver cv(ws);
-      void* F = cv.take(F_bytes(c, S));
-      void* maps = cv.take(maps_bytes(c, S));
-      double* part = (double*)cv.take(part_bytes(c, S));
-      double* E = (double*)cv.take(E_bytes(c, S));
-      double* part2 = (double*)cv.take(part2_bytes(c, S));
-      double* E2 = (double*)cv.take(E2_bytes(c, S));
-      if ((s = run_maps(c, alm, S, F, maps, st)) != MODAL_OK) return s;
-      return run_cubic(c, maps, state, S, 2, part, E, part2, E2, lin, st);
+      double* X = (double*)cv.take(X_bytes(c, S));
+      double* L = (double*)cv.take(E_bytes(c, S));
+      STAGE(MODAL_STAGE_LINEAR, launch_lin_harmonic(c, lin_Z(c, state), alm, S, X, L, st));
+      STAGE(MODAL_STAGE_REDUCE, launch_reduce_symm(c, nullptr, S, 0, 0.0, nullptr, L, 1.0, lin, st));
+      return MODAL_OK;
     }
     default:
       return fail(c, MODAL_EINVAL, "linear_term: bad mode");

@@ -1,14 +1,12 @@
 // Cubic pixel reduction as a pair x mode contraction over pixels (VALU path).
 //
-//   E_{(ab),t} = sum_x w(x) A_ab(x) M_t(x),  A_ab = M_a M_b           (mode 0, beta)
-//                                             A_ab = M_a M_b - 3 V_ab  (mode 1, beta - lin)
-//                                             A_ab = V_ab              (mode 2, lin alone)
-//   out_prs = scale (E_{(pr),s} + E_{(ps),r} + E_{(rs),p})
+//   E_{(ab),t} = sum_x w(x) M_a(x) M_b(x) M_t(x)
+//   out_prs = scale (E_{(pr),s} + E_{(ps),r} + E_{(rs),p}) + scale2 (L_{(pr),s} + L_{(ps),r} + L_{(rs),p})
 //
-// With scale = 1/3, mode 0 gives beta_prs (the three terms are equal), mode 1
-// gives beta_prs - lin_prs (each pairing of the linear term appears once), and
-// mode 2 with scale = 1 gives lin_prs alone (eq. bbispect with the three
-// pairings of the "3 C a" linear term of eq. bispectrumest).
+// With scale = 1/3 the first term is beta_prs (the three pairings are equal); with
+// L the linear-term sums of k_lin_harm.hip and scale2 = -1 the second subtracts
+// lin_prs (eq. bbispect with the three pairings of the "3 C a" linear term of
+// eq. bispectrumest).
 //
 // This kernel is the FP64 path (and any precision's reference-grade path): one
 // workgroup per (pixel chunk, block of 64 pairs, map) accumulating in FP64.
@@ -21,11 +19,11 @@ namespace {
 constexpr int kChunk = 65536;  // pixels per split-K chunk
 constexpr int kTile = 64;      // pixels staged in LDS per step
 
-template <typename T, int MODE>
+template <typename T>
 __global__ __launch_bounds__(256) void k_cubic_valu(int P, int npairs, int npix, int nchunk,
                                                     const int* __restrict__ pair_a, const int* __restrict__ pair_b,
                                                     const T* __restrict__ maps, const T* __restrict__ w,
-                                                    const T* __restrict__ V, double* __restrict__ part) {
+                                                    double* __restrict__ part) {
   const int chunk = blockIdx.x;
   const int s = blockIdx.z;
   const int pl = threadIdx.x & 63;
@@ -52,11 +50,7 @@ __global__ __launch_bounds__(256) void k_cubic_valu(int P, int npairs, int npix,
     __syncthreads();
     if (pv) {
       for (int xx = 0; xx < nt; ++xx) {
-        double A;
-        if (MODE == 0) A = (double)Mt[a][xx] * (double)Mt[b][xx];
-        else if (MODE == 1) A = (double)Mt[a][xx] * (double)Mt[b][xx] - 3.0 * (double)V[(size_t)pair * npix + x0 + xx];
-        else A = (double)V[(size_t)pair * npix + x0 + xx];
-        A *= (double)wt[xx];
+        const double A = (double)Mt[a][xx] * (double)Mt[b][xx] * (double)wt[xx];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           const int t = tg + 4 * i;
@@ -85,7 +79,7 @@ __global__ void k_reduce_chunks(int nchunk, size_t per, int S, const double* __r
   E[i] = acc;
 }
 
-// out_n = scale * (three pairings of E) + scale2 * (three pairings of E2) (E2 optional)
+// out_n = scale * (three pairings of E) + scale2 * (three pairings of E2); either may be absent
 __global__ void k_symm(int nmax, int npairs, int P, int S, double scale, const int* __restrict__ tri,
                        const double* __restrict__ E, double scale2, const double* __restrict__ E2,
                        double* __restrict__ out) {
@@ -95,7 +89,8 @@ __global__ void k_symm(int nmax, int npairs, int P, int S, double scale, const i
   const int* tr = tri + 6 * n;  // p, r, s, pair(pr), pair(ps), pair(rs)
   const size_t o = (size_t)s * npairs * P;
   const size_t i1 = (size_t)tr[3] * P + tr[2], i2 = (size_t)tr[4] * P + tr[1], i3 = (size_t)tr[5] * P + tr[0];
-  double v = scale * (E[o + i1] + E[o + i2] + E[o + i3]);
+  double v = 0.0;
+  if (E) v = scale * (E[o + i1] + E[o + i2] + E[o + i3]);
   if (E2) v += scale2 * (E2[o + i1] + E2[o + i2] + E2[o + i3]);
   out[(size_t)s * nmax + n] = v;
 }
@@ -104,45 +99,31 @@ __global__ void k_symm(int nmax, int npairs, int P, int S, double scale, const i
 
 int cubic_nchunk(const modal_ctx* c) { return (c->npix + kChunk - 1) / kChunk; }
 
-hipError_t launch_cubic_valu(const modal_ctx* c, const void* maps, const void* V, int S, int mode, double* part,
-                             hipStream_t st) {
+hipError_t launch_cubic_valu(const modal_ctx* c, const void* maps, int S, double* part, hipStream_t st) {
   const int nchunk = cubic_nchunk(c);
   dim3 grid(nchunk, (c->npairs + 63) / 64, S);
-#define LAUNCH(T, MD, W)                                                                                     \
-  hipLaunchKernelGGL((k_cubic_valu<T, MD>), grid, dim3(256), 0, st, c->P, c->npairs, c->npix, nchunk,        \
-                     c->t.pair_a, c->t.pair_b, (const T*)maps, (const T*)W, (const T*)V, part)
-  if (is_f64(c)) {
-    if (mode == 0) LAUNCH(double, 0, c->t.w64);
-    else if (mode == 1) LAUNCH(double, 1, c->t.w64);
-    else LAUNCH(double, 2, c->t.w64);
-  } else {
-    if (mode == 0) LAUNCH(float, 0, c->t.w32);
-    else if (mode == 1) LAUNCH(float, 1, c->t.w32);
-    else LAUNCH(float, 2, c->t.w32);
-  }
-#undef LAUNCH
+  if (is_f64(c))
+    hipLaunchKernelGGL(k_cubic_valu<double>, grid, dim3(256), 0, st, c->P, c->npairs, c->npix, nchunk, c->t.pair_a,
+                       c->t.pair_b, (const double*)maps, c->t.w64, part);
+  else
+    hipLaunchKernelGGL(k_cubic_valu<float>, grid, dim3(256), 0, st, c->P, c->npairs, c->npix, nchunk, c->t.pair_a,
+                       c->t.pair_b, (const float*)maps, c->t.w32, part);
   return hipGetLastError();
 }
 
+// out = scale (three pairings of the chunk-reduced part) + scale2 (three pairings of E2);
+// part == nullptr leaves only the E2 term, E2 == nullptr only the first.
 hipError_t launch_reduce_symm(const modal_ctx* c, const double* part, int S, int nchunk, double scale, double* E,
-                              double* out, hipStream_t st) {
-  return launch_reduce_symm2(c, part, S, nchunk, scale, E, nullptr, 0, 0.0, nullptr, out, st);
-}
-
-hipError_t launch_reduce_symm2(const modal_ctx* c, const double* part, int S, int nchunk, double scale, double* E,
-                               const double* part2, int nchunk2, double scale2, double* E2, double* out,
-                               hipStream_t st) {
-  const size_t per = (size_t)c->npairs * c->P;
-  const size_t tot = per * S;
-  hipLaunchKernelGGL(k_reduce_chunks, dim3((tot + 255) / 256), dim3(256), 0, st, nchunk, per, S, part, E);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (part2) {
-    hipLaunchKernelGGL(k_reduce_chunks, dim3((tot + 255) / 256), dim3(256), 0, st, nchunk2, per, S, part2, E2);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+                              const double* E2, double scale2, double* out, hipStream_t st) {
+  if (part) {
+    const size_t per = (size_t)c->npairs * c->P;
+    const size_t tot = per * S;
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((tot + 255) / 256), dim3(256), 0, st, nchunk, per, S, part, E);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_symm, dim3((c->nmax + 255) / 256, S), dim3(256), 0, st, c->nmax, c->npairs, c->P, S, scale,
-                     c->t.tri, E, scale2, part2 ? E2 : nullptr, out);
+                     c->t.tri, part ? E : nullptr, scale2, E2, out);
   return hipGetLastError();
 }
 

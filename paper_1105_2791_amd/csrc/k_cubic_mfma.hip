@@ -1,6 +1,6 @@
 // Cubic pixel reduction on the CDNA4 matrix cores.
 //
-//   E_{(ab),t} = sum_x A_ab(x) B_t(x),  A_ab = M_a M_b [- 3 V_ab] (or V_ab),  B_t = w M_t
+//   E_{(ab),t} = sum_x A_ab(x) B_t(x),  A_ab = M_a M_b,  B_t = w M_t
 //
 // is a GEMM with M = pairs, N = modes and K = pixels (split into chunks whose
 // FP32 partial sums are reduced in FP64 by k_cubic.hip).  The A operand is formed
@@ -23,8 +23,7 @@
 //            are unscaled exactly (FP64) when written.
 //
 // Launch: one workgroup per (pixel chunk, block group, sky); chunk c runs on XCD
-// c mod 8 with all skies of that chunk dispatched back to back, so the V planes
-// of a chunk are fetched from HBM about once and re-read from that XCD's L2.
+// c mod 8 with all skies of that chunk dispatched back to back.
 #include "common.h"
 
 namespace modal {
@@ -48,6 +47,15 @@ struct Blocks {
   int ngroups;   // ceil(nblk / (16 * waves))
 };
 
+// The value a split starts from must be one rounded FP32 number: the backend may
+// otherwise fuse the producing multiply into the hi conversion (a mixed-precision
+// FMA rounding the exact product) in one place and not in another, so that hi and
+// lo no longer add up.  An empty asm statement makes the rounded product opaque.
+__device__ inline float rounded(float x) {
+  asm("" : "+v"(x));
+  return x;
+}
+
 __device__ inline uint32_t bf16x2_bits(float a, float b) {
   typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
   bf16x2 h;
@@ -61,11 +69,12 @@ __device__ inline void split8(const float* v, bf16x8& hi, bf16x8& lo) {
   uint32_t h[4], l[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const uint32_t hb = bf16x2_bits(v[2 * k], v[2 * k + 1]);
+    const float v0 = rounded(v[2 * k]), v1 = rounded(v[2 * k + 1]);
+    const uint32_t hb = bf16x2_bits(v0, v1);
     const float h0 = __builtin_bit_cast(float, hb << 16);
     const float h1 = __builtin_bit_cast(float, hb & 0xffff0000u);
     h[k] = hb;
-    l[k] = bf16x2_bits(v[2 * k] - h0, v[2 * k + 1] - h1);
+    l[k] = bf16x2_bits(v0 - h0, v1 - h1);
   }
   typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
   u32x4 hv = {h[0], h[1], h[2], h[3]};
@@ -78,19 +87,19 @@ __device__ inline void split8(const float* v, bf16x8& hi, bf16x8& lo) {
 __device__ inline void split8h(const float* v, f16x8& hi, f16x8& lo) {
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const _Float16 h = (_Float16)v[k];
+    const float x = rounded(v[k]);
+    const _Float16 h = (_Float16)x;
     hi[k] = h;
-    lo[k] = (_Float16)(v[k] - (float)h);
+    lo[k] = (_Float16)(x - (float)h);
   }
 }
 
-template <int PREC, int MODE>
+template <int PREC>
 __global__ __launch_bounds__(64 * Waves<PREC>::value) void k_cubic_mfma(int P, int npairs, int npix, int S, int nchunk, int chunk_px,
                                                    Blocks bk, const int2* __restrict__ blocks,
                                                    const int* __restrict__ pair_of, const float* __restrict__ maps,
-                                                   const float* __restrict__ w, const float* __restrict__ V,
-                                                   const float* __restrict__ mscale, float wscale,
-                                                   double* __restrict__ part) {
+                                                   const float* __restrict__ w, const float* __restrict__ mscale,
+                                                   float wscale, double* __restrict__ part) {
   constexpr bool SCALED = (PREC == MODAL_F16X3);
   constexpr int NT = 64 * Waves<PREC>::value;
   constexpr int BLK_PER_GROUP = 16 * Waves<PREC>::value;
@@ -123,16 +132,6 @@ __global__ __launch_bounds__(64 * Waves<PREC>::value) void k_cubic_mfma(int P, i
     const int2 bb = blocks[blk];
     a0 = bb.x;
     b0 = bb.y;
-  }
-  int pidx[8];
-  float vsc[8];   // -3 s_a s_b (MODE 1) or s_a s_b (MODE 2): scale of the V term
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int a = a0 + (j >> 2), bm = b0 + (j & 3);
-    const bool ok = a0 >= 0 && a < P && bm < P && a <= bm;
-    pidx[j] = ok ? pair_of[a * P + bm] : -1;
-    const float sab = (SCALED && ok) ? mscale[a] * mscale[bm] : 1.f;
-    vsc[j] = (MODE == 1 ? -3.f : 1.f) * sab;
   }
   __syncthreads();
 
@@ -167,6 +166,8 @@ __global__ __launch_bounds__(64 * Waves<PREC>::value) void k_cubic_mfma(int P, i
         if (x < x_end) v0 = w[x] * sc * Msky[(size_t)t * npix + x];
         if (x + 1 < x_end) v1 = w[x + 1] * sc * Msky[(size_t)t * npix + x + 1];
       }
+      v0 = rounded(v0);
+      v1 = rounded(v1);
       if (PREC == MODAL_F16X3) {
         const _Float16 h0 = (_Float16)v0, h1 = (_Float16)v1;
         const _Float16 l0 = (_Float16)(v0 - (float)h0), l1 = (_Float16)(v1 - (float)h1);
@@ -205,7 +206,6 @@ __global__ __launch_bounds__(64 * Waves<PREC>::value) void k_cubic_mfma(int P, i
 #pragma unroll
         for (int k = 0; k < 8; ++k) mb[u][k] = Ms[p][8 * kg + k];
       }
-      const int xl = x0 + 8 * kg;
       if (PREC == MODAL_BF16X3) {
         bf16x8 bh[3], bl[3];
 #pragma unroll
@@ -215,19 +215,11 @@ __global__ __launch_bounds__(64 * Waves<PREC>::value) void k_cubic_mfma(int P, i
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
+          // rows of pairs outside the triangle (or of lanes without a block) hold
+          // finite products that are never written out
           float av[8];
-          const bool pv = pidx[j] >= 0;
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            float v;
-            if (MODE == 0) v = ma[j >> 2][k] * mb[j & 3][k];
-            else {
-              const int x = xl + k;
-              const float vv = (pv && x < x_end) ? V[(size_t)pidx[j] * npix + x] : 0.f;
-              v = (MODE == 1) ? fmaf(ma[j >> 2][k], mb[j & 3][k], vsc[j] * vv) : vsc[j] * vv;
-            }
-            av[k] = pv ? v : 0.f;
-          }
+          for (int k = 0; k < 8; ++k) av[k] = ma[j >> 2][k] * mb[j & 3][k];
           bf16x8 ah, al;
           split8(av, ah, al);
 #pragma unroll
@@ -246,19 +238,11 @@ __global__ __launch_bounds__(64 * Waves<PREC>::value) void k_cubic_mfma(int P, i
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
+          // rows of pairs outside the triangle (or of lanes without a block) hold
+          // finite products that are never written out
           float av[8];
-          const bool pv = pidx[j] >= 0;
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            float v;
-            if (MODE == 0) v = ma[j >> 2][k] * mb[j & 3][k];
-            else {
-              const int x = xl + k;
-              const float vv = (pv && x < x_end) ? V[(size_t)pidx[j] * npix + x] : 0.f;
-              v = (MODE == 1) ? fmaf(ma[j >> 2][k], mb[j & 3][k], vsc[j] * vv) : vsc[j] * vv;
-            }
-            av[k] = pv ? v : 0.f;
-          }
+          for (int k = 0; k < 8; ++k) av[k] = ma[j >> 2][k] * mb[j & 3][k];
           f16x8 ah, al;
           split8h(av, ah, al);
 #pragma unroll
@@ -280,19 +264,11 @@ __global__ __launch_bounds__(64 * Waves<PREC>::value) void k_cubic_mfma(int P, i
           for (int k = 0; k < 8; ++k) bv[c][k] = Bf[16 * c + row][8 * kg + k];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
+          // rows of pairs outside the triangle (or of lanes without a block) hold
+          // finite products that are never written out
           float av[8];
-          const bool pv = pidx[j] >= 0;
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            float v;
-            if (MODE == 0) v = ma[j >> 2][k] * mb[j & 3][k];
-            else {
-              const int x = xl + k;
-              const float vv = (pv && x < x_end) ? V[(size_t)pidx[j] * npix + x] : 0.f;
-              v = (MODE == 1) ? fmaf(ma[j >> 2][k], mb[j & 3][k], vsc[j] * vv) : vsc[j] * vv;
-            }
-            av[k] = pv ? v : 0.f;
-          }
+          for (int k = 0; k < 8; ++k) av[k] = ma[j >> 2][k] * mb[j & 3][k];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             // one K step (8 MFMAs of K = 4) from zero, then a round-to-nearest add
@@ -359,14 +335,6 @@ int chunk_px_for(const modal_ctx* c, int target) {
 int chunk_target_default(const modal_ctx* c) { return c->prec == MODAL_F32 ? 4096 : 65536; }
 int chunk_target_min(const modal_ctx* c) { return c->prec == MODAL_F32 ? 2048 : 16384; }
 
-// The linear-term GEMM accumulates exact (split) or compensated (FP32) products and
-// always uses long chunks.
-int lin_gemm_chunk_px(const modal_ctx* c) { return chunk_px_for(c, 65536); }
-int lin_gemm_nchunk(const modal_ctx* c) {
-  const int px = lin_gemm_chunk_px(c);
-  return (c->npix + px - 1) / px;
-}
-
 int cubic_mfma_nchunk_max(const modal_ctx* c) {
   const int px = chunk_px_for(c, chunk_target_min(c));
   return (c->npix + px - 1) / px;
@@ -393,8 +361,7 @@ void make_pair_blocks(int P, std::vector<int2>& out) {
     }
 }
 
-hipError_t launch_cubic_mfma(const modal_ctx* c, const void* maps, const void* V, int S, int mode, double* part,
-                             hipStream_t st) {
+hipError_t launch_cubic_mfma(const modal_ctx* c, const void* maps, int S, double* part, hipStream_t st) {
   Blocks bk;
   bk.nblk = c->t.nblk;
   const int waves = (c->prec == MODAL_BF16X3) ? Waves<MODAL_BF16X3>::value : Waves<MODAL_F32>::value;
@@ -403,23 +370,13 @@ hipError_t launch_cubic_mfma(const modal_ctx* c, const void* maps, const void* V
   const int nchunk = (c->npix + px - 1) / px;
   const int nslots = 8 * ((nchunk + 7) / 8);
   const size_t grid = (size_t)nslots * bk.ngroups * S;
-#define LAUNCH(PR, MD)                                                                                        \
-  hipLaunchKernelGGL((k_cubic_mfma<PR, MD>), dim3(grid), dim3(64 * Waves<PR>::value), 0, st, c->P, c->npairs, c->npix, S, nchunk, \
-                     px, bk, c->t.blk, c->t.pair_of, (const float*)maps, c->t.w32, (const float*)V, c->t.mscale,   \
-                     c->wscale, part)
-  if (c->prec == MODAL_F16X3) {
-    if (mode == 0) LAUNCH(MODAL_F16X3, 0);
-    else if (mode == 1) LAUNCH(MODAL_F16X3, 1);
-    else LAUNCH(MODAL_F16X3, 2);
-  } else if (c->prec == MODAL_BF16X3) {
-    if (mode == 0) LAUNCH(MODAL_BF16X3, 0);
-    else if (mode == 1) LAUNCH(MODAL_BF16X3, 1);
-    else LAUNCH(MODAL_BF16X3, 2);
-  } else {
-    if (mode == 0) LAUNCH(MODAL_F32, 0);
-    else if (mode == 1) LAUNCH(MODAL_F32, 1);
-    else LAUNCH(MODAL_F32, 2);
-  }
+#define LAUNCH(PR)                                                                                            \
+  hipLaunchKernelGGL((k_cubic_mfma<PR>), dim3(grid), dim3(64 * Waves<PR>::value), 0, st, c->P, c->npairs,    \
+                     c->npix, S, nchunk, px, bk, c->t.blk, c->t.pair_of, (const float*)maps, c->t.w32,        \
+                     c->t.mscale, c->wscale, part)
+  if (c->prec == MODAL_F16X3) LAUNCH(MODAL_F16X3);
+  else if (c->prec == MODAL_BF16X3) LAUNCH(MODAL_BF16X3);
+  else LAUNCH(MODAL_F32);
 #undef LAUNCH
   return hipGetLastError();
 }

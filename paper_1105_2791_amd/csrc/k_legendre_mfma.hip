@@ -45,8 +45,13 @@ __device__ inline uint32_t bf2(float a, float b) {
 }
 
 // hi/lo split of one float into two 16-bit words (bf16 or fp16, RNE each).
+// The value a split starts from must be one rounded FP32 number: the backend may
+// otherwise fuse the producing multiply into the hi conversion (a mixed-precision
+// FMA rounding the exact product) in one place and not in another, so that hi and
+// lo no longer add up.  An empty asm statement makes the rounded value opaque.
 template <int PREC>
 __device__ inline void split1(float v, uint16_t& hi, uint16_t& lo) {
+  asm("" : "+v"(v));
   if (PREC == MODAL_F16X3) {
     const _Float16 h = (_Float16)v;
     const _Float16 l = (_Float16)(v - (float)h);

@@ -1,0 +1,141 @@
+// Linear term evaluated in harmonic space.
+//
+// The Monte-Carlo linear term needs, for every pair (ab), map s and mode t,
+//   L_{(ab),s,t} = sum_x w(x) V_ab(x) M^s_t(x)
+// (lin_prs = L_{(pr),s} + L_{(ps),r} + L_{(rs),p}, eq. bbispect with the three
+// pairings of the "3 C a" term of eq. bispectrumest).  The filtered map is itself a
+// finite harmonic sum on the grid, M^s_t(x) = sum_lm qw_t(l) a^s_lm Y_lm(x) with
+// qw = q / sqrt(C_l), so exchanging the two finite sums gives, exactly,
+//   L_{(ab),s,t} = sum_l qw_t(l) X_{s,(ab)}(l),
+//   X_{s,(ab)}(l) = sum_{m=0}^{l} (Re a^s_lm Re Z_ab,lm + Im a^s_lm Im Z_ab,lm),
+//   Z_ab,lm = c_m sum_j lambda_lm(theta_j) sum_k w V_ab (theta_j, phi_k) e^{-i m phi_k}
+// (c_m = 2 - delta_m0).  Z depends on the state only, so it is computed once when
+// the state is finalised (weighted planes -> ring r2c FFT -> per-column adjoint
+// Legendre), and each batch costs one pass over Z instead of a pixel-space
+// contraction of npairs planes against S P maps.  No band-limit or quadrature
+// property is used: it is a reordering of the same finite sums.
+#include "common.h"
+
+namespace modal {
+namespace {
+
+template <typename T> struct vec2;
+template <> struct vec2<float> { using type = float2; };
+template <> struct vec2<double> { using type = double2; };
+
+// G[k][x] = w(x) V[k][x] for nk consecutive pair planes.
+template <typename T>
+__global__ __launch_bounds__(256) void k_weight_planes(int npix, int nk, const T* __restrict__ V,
+                                                       const T* __restrict__ w, T* __restrict__ G) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const size_t n = (size_t)nk * npix;
+  if (i >= n) return;
+  const int x = (int)(i % (size_t)npix);
+  G[i] = T((double)V[i] * (double)w[x]);
+}
+
+// X[s][pair][l] = sum_{m <= l} (Re a Re Z + Im a Im Z) at index (l, m), FP64 sums.
+// One thread per l; a workgroup covers PT pairs x ST maps so that every Z and a_lm
+// element it loads feeds PT or ST products.
+constexpr int PT = 8;
+constexpr int ST = 8;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_lin_x(int lmax, int nalm, int npairs, int S,
+                                               const typename vec2<T>::type* __restrict__ Z,
+                                               const typename vec2<T>::type* __restrict__ alm,
+                                               double* __restrict__ X) {
+  using T2 = typename vec2<T>::type;
+  const int l = blockIdx.x * 256 + threadIdx.x;
+  const int p0 = blockIdx.y * PT, s0 = blockIdx.z * ST;
+  if (l > lmax) return;
+  double acc[PT][ST];
+#pragma unroll
+  for (int k = 0; k < PT; ++k)
+#pragma unroll
+    for (int q = 0; q < ST; ++q) acc[k][q] = 0.0;
+  const T2* zr[PT];
+  const T2* ar[ST];
+#pragma unroll
+  for (int k = 0; k < PT; ++k) zr[k] = Z + (size_t)min(p0 + k, npairs - 1) * nalm;
+#pragma unroll
+  for (int q = 0; q < ST; ++q) ar[q] = alm + (size_t)min(s0 + q, S - 1) * nalm;
+  for (int m = 0; m <= l; ++m) {
+    const size_t idx = (size_t)m * (2 * lmax + 3 - m) / 2 + (l - m);   // m-major packing
+    double zx[PT], zy[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      const T2 z = zr[k][idx];
+      zx[k] = (double)z.x;
+      zy[k] = (double)z.y;
+    }
+#pragma unroll
+    for (int q = 0; q < ST; ++q) {
+      const T2 a = ar[q][idx];
+      const double ax = (double)a.x, ay = (double)a.y;
+#pragma unroll
+      for (int k = 0; k < PT; ++k) acc[k][q] = fma(ax, zx[k], fma(ay, zy[k], acc[k][q]));
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < ST; ++q) {
+    if (s0 + q >= S) break;
+#pragma unroll
+    for (int k = 0; k < PT; ++k)
+      if (p0 + k < npairs) X[((size_t)(s0 + q) * npairs + p0 + k) * (lmax + 1) + l] = acc[k][q];
+  }
+}
+
+// L[s][pair][t] = sum_l qw_t(l) X[s][pair][l]; one workgroup per (map, pair), one
+// thread per mode, the X row staged in LDS.
+__global__ __launch_bounds__(64) void k_lin_l(int lmax, int npairs, int P, const double* __restrict__ qw,
+                                              const double* __restrict__ X, double* __restrict__ L) {
+  const int pair = blockIdx.x, s = blockIdx.y;
+  const int t = threadIdx.x;
+  __shared__ double xs[256];
+  const double* xrow = X + ((size_t)s * npairs + pair) * (lmax + 1);
+  double acc = 0.0;
+  for (int l0 = 0; l0 <= lmax; l0 += 256) {
+    const int n = min(256, lmax + 1 - l0);
+    __syncthreads();
+    for (int i = t; i < n; i += 64) xs[i] = xrow[l0 + i];
+    __syncthreads();
+    if (t < P) {
+      const double* q = qw + (size_t)t * (lmax + 1) + l0;
+      for (int i = 0; i < n; ++i) acc = fma(q[i], xs[i], acc);
+    }
+  }
+  if (t < P) L[((size_t)s * npairs + pair) * P + t] = acc;
+}
+
+}  // namespace
+
+hipError_t launch_weight_planes(const modal_ctx* c, const void* V, int nk, void* G, hipStream_t st) {
+  const size_t n = (size_t)nk * c->npix;
+  const size_t blocks = (n + 255) / 256;
+  if (is_f64(c))
+    hipLaunchKernelGGL(k_weight_planes<double>, dim3(blocks), dim3(256), 0, st, c->npix, nk, (const double*)V,
+                       c->t.w64, (double*)G);
+  else
+    hipLaunchKernelGGL(k_weight_planes<float>, dim3(blocks), dim3(256), 0, st, c->npix, nk, (const float*)V,
+                       c->t.w32, (float*)G);
+  return hipGetLastError();
+}
+
+hipError_t launch_lin_harmonic(const modal_ctx* c, const void* Z, const void* alm, int S, double* X, double* L,
+                               hipStream_t st) {
+  if (c->P > 64) return hipErrorInvalidValue;
+  dim3 gx((c->lmax + 1 + 255) / 256, (c->npairs + PT - 1) / PT, (S + ST - 1) / ST);
+  if (is_f64(c))
+    hipLaunchKernelGGL(k_lin_x<double>, gx, dim3(256), 0, st, c->lmax, c->nalm, c->npairs, S, (const double2*)Z,
+                       (const double2*)alm, X);
+  else
+    hipLaunchKernelGGL(k_lin_x<float>, gx, dim3(256), 0, st, c->lmax, c->nalm, c->npairs, S, (const float2*)Z,
+                       (const float2*)alm, X);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lin_l, dim3(c->npairs, S), dim3(64), 0, st, c->lmax, c->npairs, c->P, c->t.qw64, X, L);
+  return hipGetLastError();
+}
+
+}  // namespace modal

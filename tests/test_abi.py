@@ -42,6 +42,9 @@ def test_enums_match_binding():
     assert val("MODAL_F64") == _lib.F64 and val("MODAL_BF16X3") == _lib.BF16X3
     assert val("MODAL_OP_FNL") == _lib.OP_FNL and val("MODAL_LIN_APPLY") == _lib.LIN_APPLY
     assert val("MODAL_COV_FISHER") == _lib.COV_FISHER
+    assert val("MODAL_OP_LINEAR_FINALIZE") == _lib.OP_LINEAR_FINALIZE
+    assert val("MODAL_F16X3") == _lib.F16X3
+    assert _lib.STAGES[val("MODAL_STAGE_LINEAR")] == "linear" and len(_lib.STAGES) == val("MODAL_NSTAGES")
 
 
 def test_version_without_gpu(lib):
