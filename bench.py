@@ -90,15 +90,17 @@ def kernel_rooflines(ctx, stages, prec, S):
     mfma_bound = "mfma" if prec != "f64" else "alu"
     cubic_bound = mfma_bound if ctx.cubic_path()["path"] != "valu" else "alu"
     real = 8 if prec == "f64" else 4
-    # name: (work per launch, unit of work, bound, peak, products issued per algorithmic MAC)
+    # name: (work per launch, unit of work, bound, peak, issued MFMA flops per launch)
+    issued_cubic = 2.0 * ctx.cubic_path()["issued_macs_per_pixel"] * npix * S
     work = {
         # F[m][ring] = sum_l lambda_lm(ring) a_lm: one complex x real MAC per (l, m, ring, column)
-        "legendre": (2.0 * ctx.nalm * nt * P * S, "flop", mfma_bound, mfma_peak, 4 if prec == "bf16x3" else 3),
+        "legendre": (2.0 * ctx.nalm * nt * P * S, "flop", mfma_bound, mfma_peak,
+                     (4 if prec == "bf16x3" else 3) * 2.0 * ctx.nalm * nt * P * S if split else None),
         # read F (complex, m <= lmax per ring) and write the real rings
         "fft": ((lmax + 1) * nt * P * S * 2 * real + npix * P * S * real, "byte", "hbm", PEAK["hbm"], None),
-        # E_(ab),t = sum_x (M_a M_b)(x) w(x) M_t(x): one MAC per (pair, mode, pixel)
-        "cubic": (2.0 * ctx.npairs * P * npix * S, "flop", cubic_bound,
-                  mfma_peak if cubic_bound == "mfma" else PEAK["f64_vec"], 3),
+        # beta_prs = sum_x (M_p M_r)(x) w(x) M_s(x): one MAC per (triple p <= r <= s, pixel)
+        "cubic": (2.0 * ctx.nmax * npix * S, "flop", cubic_bound,
+                  mfma_peak if cubic_bound == "mfma" else PEAK["f64_vec"], issued_cubic),
         # linear term from the harmonic pair means: one pass over Z[npairs][nalm]
         "linear": (ctx.npairs * ctx.nalm * 2 * real, "byte", "hbm", PEAK["hbm"], None),
     }
@@ -112,8 +114,9 @@ def kernel_rooflines(ctx, stages, prec, S):
         r = {"bound": bound, "achieved": rate / (1e12 if kind == "flop" else 1e9),
              "peak": peak / (1e12 if kind == "flop" else 1e9), "unit": "TFLOP/s" if kind == "flop" else "GB/s",
              "frac": rate / peak, "traffic": None, "avg_ms": avg, "per_launch": units, "per_launch_unit": kind}
-        if split and issue and bound == "mfma":
-            r["mfma_issued_frac"] = issue * rate / peak
+        if issue and bound == "mfma":
+            r["issued_flop_per_launch"] = issue
+            r["mfma_issued_frac"] = issue / (avg * 1e-3) / peak
         out[name] = r
     return out
 

@@ -154,8 +154,12 @@ int modal_nmax(const modal_ctx* ctx);
 int modal_npairs(const modal_ctx* ctx);
 
 /* Contraction kernel the context dispatches for the cubic reduction:
- * 0 = vector-ALU with FP64 accumulation, 1 = FP32 MFMA, 2 = split-bf16 MFMA. */
+ * 0 = vector-ALU with FP64 accumulation, 1 = FP32 MFMA (16x16x4 tiles),
+ * 2 = split bf16/fp16 MFMA (32x32x16 tiles, modes t >= b only). */
 int modal_cubic_path(const modal_ctx* ctx);
+/* Multiply-adds the cubic contraction issues per pixel and map, counting tile
+ * padding and every product of a split (for roofline reports; host only). */
+double modal_cubic_issued_macs(const modal_ctx* ctx);
 
 /* The context's quadrature: x_host[ntheta] = cos theta_j (descending),
  * w_host[ntheta] = Gauss-Legendre weights (sum 2).  Either may be NULL. */

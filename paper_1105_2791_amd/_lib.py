@@ -57,6 +57,7 @@ _SIGS = {
     "modal_fnl": (ip, [vp, vp, vp, vp, ip, vp, vp, vp, vp, sz, vp]),
     "modal_profile_enable": (ip, [vp, ip]),
     "modal_cubic_path": (ip, [vp]),
+    "modal_cubic_issued_macs": (C.c_double, [vp]),
     "modal_beta_graph_create": (ip, [ip, vp, vp, vp, vp, vp, vp, vp, vp]),
     "modal_graph_launch": (ip, [vp, vp]),
     "modal_graph_destroy": (None, [vp]),

@@ -97,14 +97,12 @@ class ModalContext:
         return {name: (float(ms[i]), int(n[i])) for i, name in enumerate(L.STAGES)}
 
     def cubic_path(self) -> dict:
-        """Which contraction kernel the context uses ('valu' or 'mfma') and its
-        issued-work padding factor over the pair x mode product."""
+        """Which contraction kernel the context uses ('valu' or 'mfma') and the
+        multiply-adds it issues per pixel and map (tile padding and split products
+        included)."""
         code = int(self._lib.modal_cubic_path(self._h))
-        pad = 1.0
-        if code != 0:
-            tiles = -(-self.P // 16) * 16
-            pad = tiles / self.P
-        return {"path": "valu" if code == 0 else "mfma", "code": code, "pad": pad}
+        return {"path": "valu" if code == 0 else "mfma", "code": code,
+                "issued_macs_per_pixel": float(self._lib.modal_cubic_issued_macs(self._h))}
 
     def _alm(self, alm) -> torch.Tensor:
         a = torch.as_tensor(alm)

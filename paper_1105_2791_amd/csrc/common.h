@@ -47,6 +47,8 @@ struct Tables {
   int* flag = nullptr;         // [4] device status words (Cholesky pivot)
   int2* blk = nullptr;         // [nblk] (a0, b0) of the 2 x 4 pair blocks of the MFMA contraction
   int nblk = 0;
+  int2* items = nullptr;       // [nitems] (first block, mode tile) work items of the split contraction
+  int nitems = 0;
   float* mscale = nullptr;     // [P] exact powers of two ~ 1/sigma_p (split-fp16 contraction)
 };
 
@@ -119,6 +121,17 @@ int cubic_mfma_nchunk_max(const modal_ctx* c);
 hipError_t launch_reduce_symm(const modal_ctx* c, const double* partials, int S, int nchunk, double scale,
                               double* E, const double* E2, double scale2, double* out, hipStream_t st);
 void make_pair_blocks(int P, std::vector<int2>& out);
+// split-precision contraction on 32x32 tiles (k_cubic_split.hip): 2 x 2 pair blocks
+// sorted by b0; writes the partial sums of the needed modes t >= b only
+void make_pair_blocks22(int P, std::vector<int2>& blocks, std::vector<int2>& items);
+size_t cubic_split_lds();
+hipError_t cubic_split_set_lds(size_t bytes);
+hipError_t launch_cubic_split(const modal_ctx* c, const void* maps, int S, int nchunk, int chunk_px, double* part,
+                              hipStream_t st);
+int cubic_chunk_px(const modal_ctx* c);
+// out[S][nmax] = sum over chunks of part at (pair(pr), s) + scale2 (three pairings of E2)
+hipError_t launch_reduce_single(const modal_ctx* c, const double* part, int S, int nchunk, const double* E2,
+                                double scale2, double* out, hipStream_t st);
 // linear term from the harmonic pair means Z[npairs][nalm] (k_lin_harm.hip):
 // X[S][npairs][lmax+1] scratch, L[S][npairs][P] = sum_x w V_ab M^s_t
 hipError_t launch_weight_planes(const modal_ctx* c, const void* V, int nk, void* G, hipStream_t st);

@@ -233,11 +233,16 @@ modal_status run_maps(modal_ctx* c, const void* alm, int S, void* F, void* maps,
 // pixels, and the linear term from the state's harmonic pair means.
 modal_status run_beta(modal_ctx* c, const void* maps, const void* alm, const void* state, int S, double* part,
                       double* E, double* X, double* L, double* out, hipStream_t st) {
-  if (cubic_mfma_available(c)) STAGE(MODAL_STAGE_CUBIC, launch_cubic_mfma(c, maps, S, part, st));
+  const bool split = c->prec == MODAL_BF16X3 || c->prec == MODAL_F16X3;
+  if (split) STAGE(MODAL_STAGE_CUBIC, launch_cubic_split(c, maps, S, nchunk_for(c), cubic_chunk_px(c), part, st));
+  else if (cubic_mfma_available(c)) STAGE(MODAL_STAGE_CUBIC, launch_cubic_mfma(c, maps, S, part, st));
   else STAGE(MODAL_STAGE_CUBIC, launch_cubic_valu(c, maps, S, part, st));
   if (state) STAGE(MODAL_STAGE_LINEAR, launch_lin_harmonic(c, lin_Z(c, state), alm, S, X, L, st));
-  STAGE(MODAL_STAGE_REDUCE,
-        launch_reduce_symm(c, part, S, nchunk_for(c), 1.0 / 3.0, E, state ? L : nullptr, -1.0, out, st));
+  if (split)
+    STAGE(MODAL_STAGE_REDUCE, launch_reduce_single(c, part, S, nchunk_for(c), state ? L : nullptr, -1.0, out, st));
+  else
+    STAGE(MODAL_STAGE_REDUCE,
+          launch_reduce_symm(c, part, S, nchunk_for(c), 1.0 / 3.0, E, state ? L : nullptr, -1.0, out, st));
   return MODAL_OK;
 }
 
@@ -288,6 +293,11 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
   if (fft_lds > 65536 && fft_set_lds_limit(fft_lds) != hipSuccess) return bail(MODAL_EDEVICE);
 
   if (prec == MODAL_F32 || prec == MODAL_BF16X3 || prec == MODAL_F16X3) {
+    if (prec != MODAL_F32) {
+      const size_t cneed = cubic_split_lds();
+      if (cneed + 1024 > c->max_lds) return bail(MODAL_EUNSUPPORTED);
+      if (cneed > 65536 && cubic_split_set_lds(cneed) != hipSuccess) return bail(MODAL_EDEVICE);
+    }
     const size_t need = legendre_mfma_lds(c);
     if (need <= c->max_lds) {
       if (need > 65536 && legendre_mfma_set_lds(need) != hipSuccess) return bail(MODAL_EDEVICE);
@@ -383,10 +393,12 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
   c->wscale = (float)std::ldexp(1.0, (int)std::lround(std::log2((double)c->npix / (4.0 * kPi))));
   Tables& t = c->t;
   if (upload(&t.mscale, mscale) != hipSuccess) return bail(MODAL_EDEVICE);
-  std::vector<int2> blocks;
-  make_pair_blocks(P, blocks);
+  std::vector<int2> blocks, items;
+  if (prec == MODAL_BF16X3 || prec == MODAL_F16X3) make_pair_blocks22(P, blocks, items);
+  else make_pair_blocks(P, blocks);
   t.nblk = (int)blocks.size();
-  if (upload(&t.blk, blocks) != hipSuccess) return bail(MODAL_EDEVICE);
+  t.nitems = (int)items.size();
+  if (upload(&t.blk, blocks) != hipSuccess || upload(&t.items, items) != hipSuccess) return bail(MODAL_EDEVICE);
   std::vector<double> xs(c->x_host);
   if (upload(&t.x, xs) != hipSuccess || upload(&t.ringw, ringw) != hipSuccess || upload(&t.w64, w64) != hipSuccess ||
       upload(&t.w32, w32) != hipSuccess || upload(&t.rec, rec) != hipSuccess || upload(&t.qw64, qw64) != hipSuccess ||
@@ -419,7 +431,7 @@ void modal_destroy(modal_ctx* c) {
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   Tables& t = c->t;
   void* ptrs[] = {t.x, t.ringw, t.w64, t.w32, t.rec, t.seed, t.lstart, t.lstart_blk, t.qw64, t.qw32, t.tw64, t.tw32,
-                  t.pair_a, t.pair_b, t.tri, t.pair_of, t.tri_of, t.tri_mult, t.flag, t.blk, t.mscale};
+                  t.pair_a, t.pair_b, t.tri, t.pair_of, t.tri_of, t.tri_mult, t.flag, t.blk, t.items, t.mscale};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -433,6 +445,13 @@ int modal_cubic_path(const modal_ctx* c) {
   if (!c) return -1;
   if (!cubic_mfma_available(c)) return 0;
   return c->prec == MODAL_F32 ? 1 : 2;
+}
+
+double modal_cubic_issued_macs(const modal_ctx* c) {
+  if (!c) return 0.0;
+  if (c->prec == MODAL_BF16X3 || c->prec == MODAL_F16X3) return (double)c->t.nitems * 32 * 4 * 32 * 3;
+  if (c->prec == MODAL_F32) return (double)c->t.nblk * 8 * 48;
+  return (double)c->npairs * c->P;
 }
 
 modal_status modal_grid(const modal_ctx* c, double* x_host, double* w_host) {

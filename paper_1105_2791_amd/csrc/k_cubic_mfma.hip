@@ -335,6 +335,10 @@ int chunk_px_for(const modal_ctx* c, int target) {
 int chunk_target_default(const modal_ctx* c) { return c->prec == MODAL_F32 ? 4096 : 65536; }
 int chunk_target_min(const modal_ctx* c) { return c->prec == MODAL_F32 ? 2048 : 16384; }
 
+int cubic_chunk_px(const modal_ctx* c) {
+  return chunk_px_for(c, c->tune_chunk_px > 0 ? c->tune_chunk_px : chunk_target_default(c));
+}
+
 int cubic_mfma_nchunk_max(const modal_ctx* c) {
   const int px = chunk_px_for(c, chunk_target_min(c));
   return (c->npix + px - 1) / px;

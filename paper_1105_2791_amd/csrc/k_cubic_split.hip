@@ -1,0 +1,326 @@
+// Cubic pixel reduction on the matrix cores with split 16-bit operands, 32x32 tiles.
+//
+//   E_{(ab),t} = sum_x A_ab(x) B_t(x),  A_ab = M_a M_b,  B_t = w M_t,
+//
+// a GEMM with M = pairs, N = modes, K = pixels (chunked; FP32 partial sums are
+// reduced in FP64 by k_cubic.hip).  beta_prs = E_{(pr),s} for p <= r <= s, so only
+// the modes t >= b of a pair (a, b) are needed.
+//
+// Tiling (v_mfma_f32_32x32x16_{bf16,f16}; lane l holds A[l % 32][8 (l / 32) + i],
+// B[8 (l / 32) + i][l % 32], and accumulator register j is D[8 (j / 4) + 4 (l / 32)
+// + j % 4][l % 32]):
+//   * lane-row i of a wave owns a 2 x 2 block of pairs (a0, a0+1) x (b0, b0+1); the
+//     four 32-row tiles of a wave are the four positions in the block, so a K step
+//     reads 4 map rows per lane for 4 pair products;
+//   * blocks are sorted by b0 and taken 32 at a time; a work item is such a group of
+//     32 blocks with one 32-mode tile: the last 32 modes [P-32, P) always, and the
+//     32 before them only when the group's smallest b0 is below P - 32 (for P = 40
+//     that is one extra item; every wave runs one item);
+//   * maps and the split B operand of a 32-pixel step are staged in LDS, double
+//     buffered, with the next step's global loads issued before this step's MFMAs.
+// Precisions
+//   BF16X3: hi = RNE bf16, lo = RNE bf16 of the residual; Ah Bh + Ah Bl + Al Bh.
+//   F16X3 : maps scaled by exact powers of two (s_p ~ 1/sigma_p, s_w ~ npix/4pi);
+//           hi = f16(a b) and lo = f16(a b - hi) each from one fused mixed-precision
+//           FMA of the two map values (the residual is exact before its rounding),
+//           which costs two vector instructions per pair product.
+// Every K step's three products start from zero and join the running FP32 sum with
+// a round-to-nearest vector add (the matrix core drops addend bits below the largest
+// term, which against a long running sum would bias every step).
+#include "common.h"
+
+#include <type_traits>
+
+namespace modal {
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
+
+constexpr int KS = 32;             // pixels per staged step (two MFMA K = 16 substeps)
+constexpr int NW = 8;              // waves per workgroup
+constexpr int NT = 64 * NW;
+constexpr int BPW = 32;            // pair blocks per wave (one per lane-row)
+constexpr int MSS = KS + 4;        // map row stride in LDS (floats)
+constexpr int BSS = KS + 8;        // B row stride in LDS (16-bit)
+constexpr int BROWS = 64;          // B rows: row r <-> mode P - 64 + r (rows of negative modes are zero)
+constexpr int ESTEP = kMaxP * KS / NT;   // staged map values per thread per step (4)
+
+struct Lds {
+  float ms[2][kMaxP][MSS];
+  uint16_t bh[2][BROWS][BSS];
+  uint16_t bl[2][BROWS][BSS];
+};
+
+// The value a split starts from must be one rounded FP32 number (see the bf16 path).
+__device__ inline float rounded(float x) {
+  asm("" : "+v"(x));
+  return x;
+}
+
+__device__ inline uint32_t bf16x2_bits(float a, float b) {
+  typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
+  bf16x2 h;
+  h[0] = (__bf16)a;
+  h[1] = (__bf16)b;
+  return __builtin_bit_cast(uint32_t, h);
+}
+
+// bf16 hi/lo of the products x[k] y[k], k = 0..7.
+__device__ inline void split_bf16(const float* x, const float* y, bf16x8& hi, bf16x8& lo) {
+  u32x4 h, l;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float v0 = rounded(x[2 * k] * y[2 * k]), v1 = rounded(x[2 * k + 1] * y[2 * k + 1]);
+    const uint32_t hb = bf16x2_bits(v0, v1);
+    h[k] = hb;
+    l[k] = bf16x2_bits(v0 - __builtin_bit_cast(float, hb << 16), v1 - __builtin_bit_cast(float, hb & 0xffff0000u));
+  }
+  hi = __builtin_bit_cast(bf16x8, h);
+  lo = __builtin_bit_cast(bf16x8, l);
+}
+
+// fp16 hi/lo of the products x[k] y[k]: hi = f16(x y), lo = f16(x y - hi), both
+// from fused mixed-precision FMAs (inputs FP32, result written to one half).
+__device__ inline void split_f16(const float* x, const float* y, f16x8& hi, f16x8& lo) {
+  u32x4 h, l;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    uint32_t hh, ll;
+    asm("v_fma_mixlo_f16 %0, %2, %3, 0\n\t"
+        "v_fma_mixhi_f16 %0, %4, %5, 0\n\t"
+        "v_fma_mixlo_f16 %1, %2, %3, -%0 op_sel_hi:[0,0,1]\n\t"
+        "v_fma_mixhi_f16 %1, %4, %5, -%0 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
+        : "=&v"(hh), "=&v"(ll)
+        : "v"(x[2 * k]), "v"(y[2 * k]), "v"(x[2 * k + 1]), "v"(y[2 * k + 1]));
+    h[k] = hh;
+    l[k] = ll;
+  }
+  hi = __builtin_bit_cast(f16x8, h);
+  lo = __builtin_bit_cast(f16x8, l);
+}
+
+template <int PREC>
+__device__ inline void store_split(float v, uint16_t* hi, uint16_t* lo) {
+  v = rounded(v);
+  if (PREC == MODAL_F16X3) {
+    const _Float16 h = (_Float16)v;
+    *hi = __builtin_bit_cast(uint16_t, h);
+    *lo = __builtin_bit_cast(uint16_t, (_Float16)(v - (float)h));
+  } else {
+    const uint32_t hb = bf16x2_bits(v, 0.f);
+    *hi = (uint16_t)(hb & 0xffffu);
+    *lo = (uint16_t)(bf16x2_bits(v - __builtin_bit_cast(float, hb << 16), 0.f) & 0xffffu);
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix, int S, int nchunk, int chunk_px,
+                                                    int nblk, int nitems, int ngroups, const int2* __restrict__ blocks,
+                                                    const int2* __restrict__ items, const int* __restrict__ pair_of,
+                                                    const float* __restrict__ maps, const float* __restrict__ w,
+                                                    const float* __restrict__ mscale, float wscale,
+                                                    double* __restrict__ part) {
+  constexpr bool F16 = PREC == MODAL_F16X3;
+  typedef typename std::conditional<F16, f16x8, bf16x8>::type vec8;
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  Lds& L = *reinterpret_cast<Lds*>(lds_raw);
+  __shared__ float msc[kMaxP];
+
+  // XCD-aware decode: chunk c on XCD c % 8, its (group, sky) items consecutive there
+  const int bid = blockIdx.x;
+  const int xcd = bid & 7;
+  const int i8 = bid >> 3;
+  const int per = ngroups * S;
+  const int chunk = xcd + 8 * (i8 / per);
+  if (chunk >= nchunk) return;
+  const int rem = i8 - (i8 / per) * per;
+  const int group = rem / S;
+  const int s = rem - group * S;
+
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int lrow = lane & 31, kh = lane >> 5;
+
+  if (tid < kMaxP) msc[tid] = (F16 && tid < P) ? mscale[tid] : 1.f;
+  // rows of negative modes stay zero in both stages
+  for (int e = tid; e < 2 * BROWS * BSS; e += NT) {
+    const int st = e / (BROWS * BSS), r = (e / BSS) % BROWS, xx = e % BSS;
+    if (r < BROWS - P) {
+      L.bh[st][r][xx] = 0;
+      L.bl[st][r][xx] = 0;
+    }
+  }
+
+  // this wave's work item (wave-uniform): 32 blocks from wfirst, mode tile ct
+  const int item = group * NW + wv;
+  const bool wave_on = item < nitems;
+  int wfirst = 0, ct = 1;
+  if (wave_on) {
+    const int2 it = items[item];
+    wfirst = __builtin_amdgcn_readfirstlane(it.x);
+    ct = __builtin_amdgcn_readfirstlane(it.y);
+  }
+  const int myblk = wfirst + lrow;
+  int a0 = 0, b0 = 0;
+  if (myblk < nblk) {
+    const int2 bb = blocks[myblk];
+    a0 = bb.x;
+    b0 = bb.y;
+  }
+  const int ra[2] = {min(a0, P - 1), min(a0 + 1, P - 1)};
+  const int rb[2] = {min(b0, P - 1), min(b0 + 1, P - 1)};
+
+  const float* Msky = maps + (size_t)s * P * npix;
+  const int x_begin = chunk * chunk_px;
+  const int x_end = min(npix, x_begin + chunk_px);
+
+  // staging: thread owns map values e = tid + NT i -> (t = e / KS, xx = e % KS)
+  float pre[ESTEP];
+  float wpre;
+  const int sxx = tid % KS;
+  auto load_step = [&](int x0) {
+    const int x = x0 + sxx;
+    const bool in = x < x_end;
+    wpre = in ? w[x] : 0.f;
+#pragma unroll
+    for (int i = 0; i < ESTEP; ++i) {
+      const int t = (tid + NT * i) / KS;
+      pre[i] = (in && t < P) ? Msky[(size_t)t * npix + x] : 0.f;
+    }
+  };
+  auto store_step = [&](int st) {
+#pragma unroll
+    for (int i = 0; i < ESTEP; ++i) {
+      const int t = (tid + NT * i) / KS;
+      if (t < P) {
+        L.ms[st][t][sxx] = pre[i] * msc[t];
+        const float sc = F16 ? msc[t] * wscale : 1.f;
+        store_split<PREC>(wpre * sc * pre[i], &L.bh[st][BROWS - P + t][sxx], &L.bl[st][BROWS - P + t][sxx]);
+      }
+    }
+  };
+
+  f32x16 acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[j][r] = 0.f;
+  const int brow = 32 * ct + lrow;   // this lane's B row (mode P - 64 + brow)
+
+  __syncthreads();   // msc and the zero rows
+  load_step(x_begin);
+  store_step(0);
+  __syncthreads();
+  int st = 0;
+  for (int x0 = x_begin; x0 < x_end; x0 += KS) {
+    const bool more = x0 + KS < x_end;
+    if (more) load_step(x0 + KS);
+    if (wave_on) {
+#pragma unroll
+      for (int ks = 0; ks < KS / 16; ++ks) {
+        const int kx = 16 * ks + 8 * kh;
+        // the four map rows of this lane's block at its 8 pixels
+        float ma[2][8], mb[2][8];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const float4* pa = reinterpret_cast<const float4*>(&L.ms[st][ra[u]][kx]);
+          const float4* pb = reinterpret_cast<const float4*>(&L.ms[st][rb[u]][kx]);
+          const float4 a_lo = pa[0], a_hi = pa[1], b_lo = pb[0], b_hi = pb[1];
+          ma[u][0] = a_lo.x; ma[u][1] = a_lo.y; ma[u][2] = a_lo.z; ma[u][3] = a_lo.w;
+          ma[u][4] = a_hi.x; ma[u][5] = a_hi.y; ma[u][6] = a_hi.z; ma[u][7] = a_hi.w;
+          mb[u][0] = b_lo.x; mb[u][1] = b_lo.y; mb[u][2] = b_lo.z; mb[u][3] = b_lo.w;
+          mb[u][4] = b_hi.x; mb[u][5] = b_hi.y; mb[u][6] = b_hi.z; mb[u][7] = b_hi.w;
+        }
+        const vec8 bh = *reinterpret_cast<const vec8*>(&L.bh[st][brow][kx]);
+        const vec8 bl = *reinterpret_cast<const vec8*>(&L.bl[st][brow][kx]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          vec8 ah, al;
+          if (F16) split_f16(ma[j >> 1], mb[j & 1], *reinterpret_cast<f16x8*>(&ah), *reinterpret_cast<f16x8*>(&al));
+          else split_bf16(ma[j >> 1], mb[j & 1], *reinterpret_cast<bf16x8*>(&ah), *reinterpret_cast<bf16x8*>(&al));
+          f32x16 t;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) t[r] = 0.f;
+          if (F16) {
+            t = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, t, 0, 0, 0);
+            t = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, t, 0, 0, 0);
+            t = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, t, 0, 0, 0);
+          } else {
+            t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, t, 0, 0, 0);
+            t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, t, 0, 0, 0);
+            t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, t, 0, 0, 0);
+          }
+          acc[j] += t;
+        }
+      }
+    }
+    if (more) store_step(st ^ 1);
+    __syncthreads();
+    st ^= 1;
+  }
+  if (!wave_on) return;
+
+  // partial sums: acc[j][r] = E[pair j of block wfirst + 8 (r/4) + 4 kh + r % 4][mode P - 64 + brow]
+  const int t = P - 64 + brow;
+  double* dst = part + ((size_t)s * nchunk + chunk) * npairs * P;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int ob = wfirst + 8 * (r >> 2) + 4 * kh + (r & 3);
+    if (ob >= nblk) continue;
+    const int2 bb = blocks[ob];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int a = bb.x + (j >> 1), b = bb.y + (j & 1);
+      if (a >= P || b >= P || a > b || t < b) continue;   // needed modes only: t >= b (>= 0)
+      double v = (double)acc[j][r];
+      if (F16) v /= (double)mscale[a] * (double)mscale[b] * (double)mscale[t] * (double)wscale;
+      dst[(size_t)pair_of[a * P + b] * P + t] = v;
+    }
+  }
+}
+
+}  // namespace
+
+// 2 x 2 pair blocks (a0, b0 even, a0 <= b0) sorted by b0, then a0, and the work items
+// (first block of a group of 32, mode tile).
+void make_pair_blocks22(int P, std::vector<int2>& blocks, std::vector<int2>& items) {
+  blocks.clear();
+  items.clear();
+  for (int b = 0; b < P; b += 2)
+    for (int a = 0; a <= b; a += 2) blocks.push_back(make_int2(a, b));
+  for (int g = 0; g < (int)blocks.size(); g += BPW) {
+    items.push_back(make_int2(g, 1));
+    if (P - blocks[g].y > 32) items.push_back(make_int2(g, 0));
+  }
+}
+
+size_t cubic_split_lds() { return sizeof(Lds); }
+
+hipError_t cubic_split_set_lds(size_t bytes) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_cubic_split<MODAL_BF16X3>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_cubic_split<MODAL_F16X3>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+hipError_t launch_cubic_split(const modal_ctx* c, const void* maps, int S, int nchunk, int chunk_px, double* part,
+                              hipStream_t st) {
+  if (c->P > kMaxP || chunk_px % KS != 0 || (long long)nchunk * chunk_px < c->npix) return hipErrorInvalidValue;
+  const int ngroups = (c->t.nitems + NW - 1) / NW;
+  const int nslots = 8 * ((nchunk + 7) / 8);
+  const size_t grid = (size_t)nslots * ngroups * S;
+  const size_t lds = sizeof(Lds);
+#define LAUNCH(PR)                                                                                              \
+  hipLaunchKernelGGL((k_cubic_split<PR>), dim3(grid), dim3(NT), lds, st, c->P, c->npairs, c->npix, S, nchunk,     \
+                     chunk_px, c->t.nblk, c->t.nitems, ngroups, c->t.blk, c->t.items, c->t.pair_of,               \
+                     (const float*)maps, c->t.w32, c->t.mscale, c->wscale, part)
+  if (c->prec == MODAL_F16X3) LAUNCH(MODAL_F16X3);
+  else LAUNCH(MODAL_BF16X3);
+#undef LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace modal
