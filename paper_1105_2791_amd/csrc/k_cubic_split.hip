@@ -16,17 +16,19 @@
 //     32 blocks with one 32-mode tile: the last 32 modes [P-32, P) always, and the
 //     32 before them only when the group's smallest b0 is below P - 32 (for P = 40
 //     that is one extra item; every wave runs one item);
-//   * maps and the split B operand of a 32-pixel step are staged in LDS, double
-//     buffered, with the next step's global loads issued before this step's MFMAs.
+//   * maps and the split B operand of a 64-pixel step are staged in LDS, double
+//     buffered, with the next step's global loads issued before this step's MFMAs
+//     (a step is long enough to cover the load latency).
 // Precisions
 //   BF16X3: hi = RNE bf16, lo = RNE bf16 of the residual; Ah Bh + Ah Bl + Al Bh.
 //   F16X3 : maps scaled by exact powers of two (s_p ~ 1/sigma_p, s_w ~ npix/4pi);
 //           hi = f16(a b) and lo = f16(a b - hi) each from one fused mixed-precision
 //           FMA of the two map values (the residual is exact before its rounding),
 //           which costs two vector instructions per pair product.
-// Every K step's three products start from zero and join the running FP32 sum with
-// a round-to-nearest vector add (the matrix core drops addend bits below the largest
-// term, which against a long running sum would bias every step).
+// The matrix core drops addend bits below the largest term of an accumulation, which
+// against a long running sum biases every step; so the MFMAs accumulate a short
+// chain of CHAIN staged steps from zero, and each chain joins the running FP32 sum
+// with a round-to-nearest vector add.
 #include "common.h"
 
 #include <type_traits>
@@ -39,14 +41,15 @@ typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
 
-constexpr int KS = 32;             // pixels per staged step (two MFMA K = 16 substeps)
+constexpr int KS = 64;             // pixels per staged step (four MFMA K = 16 substeps)
 constexpr int NW = 8;              // waves per workgroup
 constexpr int NT = 64 * NW;
 constexpr int BPW = 32;            // pair blocks per wave (one per lane-row)
 constexpr int MSS = KS + 4;        // map row stride in LDS (floats)
 constexpr int BSS = KS + 8;        // B row stride in LDS (16-bit)
 constexpr int BROWS = 64;          // B rows: row r <-> mode P - 64 + r (rows of negative modes are zero)
-constexpr int ESTEP = kMaxP * KS / NT;   // staged map values per thread per step (4)
+constexpr int ESTEP = kMaxP * KS / NT;   // staged map values per thread per step (8)
+constexpr int CHAIN = 4;           // staged steps per MFMA accumulation chain (48 MFMAs per tile)
 
 struct Lds {
   float ms[2][kMaxP][MSS];
@@ -74,7 +77,8 @@ __device__ inline void split_bf16(const float* x, const float* y, bf16x8& hi, bf
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const float v0 = rounded(x[2 * k] * y[2 * k]), v1 = rounded(x[2 * k + 1] * y[2 * k + 1]);
-    const uint32_t hb = bf16x2_bits(v0, v1);
+    uint32_t hb = bf16x2_bits(v0, v1);
+    asm("" : "+v"(hb));   // extract the hi words from this one conversion
     h[k] = hb;
     l[k] = bf16x2_bits(v0 - __builtin_bit_cast(float, hb << 16), v1 - __builtin_bit_cast(float, hb & 0xffff0000u));
   }
@@ -169,25 +173,29 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
     a0 = bb.x;
     b0 = bb.y;
   }
-  const int ra[2] = {min(a0, P - 1), min(a0 + 1, P - 1)};
-  const int rb[2] = {min(b0, P - 1), min(b0 + 1, P - 1)};
+  // LDS offsets (floats within a stage) of this lane's four map rows at its k-half
+  const int oa[2] = {min(a0, P - 1) * MSS + 8 * kh, min(a0 + 1, P - 1) * MSS + 8 * kh};
+  const int ob_[2] = {min(b0, P - 1) * MSS + 8 * kh, min(b0 + 1, P - 1) * MSS + 8 * kh};
 
   const float* Msky = maps + (size_t)s * P * npix;
   const int x_begin = chunk * chunk_px;
   const int x_end = min(npix, x_begin + chunk_px);
 
-  // staging: thread owns map values e = tid + NT i -> (t = e / KS, xx = e % KS)
+  // staging: thread owns map values e = tid + NT i -> (t = e / KS, xx = e % KS).  Loads
+  // are clamped in range and unconditional; past the chunk end w = 0 makes B = 0, so
+  // whatever A holds there contributes nothing.
   float pre[ESTEP];
   float wpre;
   const int sxx = tid % KS;
   auto load_step = [&](int x0) {
     const int x = x0 + sxx;
-    const bool in = x < x_end;
-    wpre = in ? w[x] : 0.f;
+    const int xc = min(x, x_end - 1);
+    const float wv_ = w[xc];
+    wpre = x < x_end ? wv_ : 0.f;
 #pragma unroll
     for (int i = 0; i < ESTEP; ++i) {
-      const int t = (tid + NT * i) / KS;
-      pre[i] = (in && t < P) ? Msky[(size_t)t * npix + x] : 0.f;
+      const int t = min((tid + NT * i) / KS, P - 1);
+      pre[i] = Msky[(size_t)t * npix + xc];
     }
   };
   auto store_step = [&](int st) {
@@ -202,18 +210,18 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
     }
   };
 
-  f32x16 acc[4];
+  f32x16 acc[4], cha[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[j][r] = 0.f;
+    for (int r = 0; r < 16; ++r) acc[j][r] = cha[j][r] = 0.f;
   const int brow = 32 * ct + lrow;   // this lane's B row (mode P - 64 + brow)
 
   __syncthreads();   // msc and the zero rows
   load_step(x_begin);
   store_step(0);
   __syncthreads();
-  int st = 0;
+  int st = 0, link = 0;
   for (int x0 = x_begin; x0 < x_end; x0 += KS) {
     const bool more = x0 + KS < x_end;
     if (more) load_step(x0 + KS);
@@ -221,12 +229,13 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
 #pragma unroll
       for (int ks = 0; ks < KS / 16; ++ks) {
         const int kx = 16 * ks + 8 * kh;
+        const float* msb = &L.ms[st][0][0] + 16 * ks;
         // the four map rows of this lane's block at its 8 pixels
         float ma[2][8], mb[2][8];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-          const float4* pa = reinterpret_cast<const float4*>(&L.ms[st][ra[u]][kx]);
-          const float4* pb = reinterpret_cast<const float4*>(&L.ms[st][rb[u]][kx]);
+          const float4* pa = reinterpret_cast<const float4*>(msb + oa[u]);
+          const float4* pb = reinterpret_cast<const float4*>(msb + ob_[u]);
           const float4 a_lo = pa[0], a_hi = pa[1], b_lo = pb[0], b_hi = pb[1];
           ma[u][0] = a_lo.x; ma[u][1] = a_lo.y; ma[u][2] = a_lo.z; ma[u][3] = a_lo.w;
           ma[u][4] = a_hi.x; ma[u][5] = a_hi.y; ma[u][6] = a_hi.z; ma[u][7] = a_hi.w;
@@ -240,19 +249,24 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
           vec8 ah, al;
           if (F16) split_f16(ma[j >> 1], mb[j & 1], *reinterpret_cast<f16x8*>(&ah), *reinterpret_cast<f16x8*>(&al));
           else split_bf16(ma[j >> 1], mb[j & 1], *reinterpret_cast<bf16x8*>(&ah), *reinterpret_cast<bf16x8*>(&al));
-          f32x16 t;
-#pragma unroll
-          for (int r = 0; r < 16; ++r) t[r] = 0.f;
           if (F16) {
-            t = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, t, 0, 0, 0);
-            t = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, t, 0, 0, 0);
-            t = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, t, 0, 0, 0);
+            cha[j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, cha[j], 0, 0, 0);
+            cha[j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, cha[j], 0, 0, 0);
+            cha[j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, cha[j], 0, 0, 0);
           } else {
-            t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, t, 0, 0, 0);
-            t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, t, 0, 0, 0);
-            t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, t, 0, 0, 0);
+            cha[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, cha[j], 0, 0, 0);
+            cha[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, cha[j], 0, 0, 0);
+            cha[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, cha[j], 0, 0, 0);
           }
-          acc[j] += t;
+        }
+      }
+      if (++link == CHAIN || !more) {   // wave-uniform
+        link = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc[j] += cha[j];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) cha[j][r] = 0.f;
         }
       }
     }
@@ -275,7 +289,7 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
       const int a = bb.x + (j >> 1), b = bb.y + (j & 1);
       if (a >= P || b >= P || a > b || t < b) continue;   // needed modes only: t >= b (>= 0)
       double v = (double)acc[j][r];
-      if (F16) v /= (double)mscale[a] * (double)mscale[b] * (double)mscale[t] * (double)wscale;
+      if (F16) v *= 1.0 / ((double)mscale[a] * (double)mscale[b] * (double)mscale[t] * (double)wscale);   // powers of two
       dst[(size_t)pair_of[a * P + b] * P + t] = v;
     }
   }
