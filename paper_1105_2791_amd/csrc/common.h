@@ -89,6 +89,10 @@ hipError_t launch_seeds(const modal_ctx* c, const double* logpref, hipStream_t s
 // Legendre synthesis: F[S][P][lmax+1][ntheta] complex (rings contiguous; double2 for F64, float2 otherwise)
 hipError_t launch_legendre(const modal_ctx* c, const void* alm, int S, void* F, hipStream_t st);
 hipError_t launch_legendre_mfma(const modal_ctx* c, const void* alm, int S, void* F, hipStream_t st);
+// split bf16/fp16 synthesis on 32x32 tiles, lambda in registers (k_legendre_split.hip)
+hipError_t launch_legendre_split(const modal_ctx* c, const void* alm, int S, void* F, hipStream_t st);
+size_t legendre_split_lds();
+hipError_t legendre_split_set_lds(size_t bytes);
 size_t legendre_mfma_lds(const modal_ctx* c);
 hipError_t legendre_mfma_set_lds(size_t bytes);
 // ring c2r FFT: maps[S][P][ntheta][nphi] from F

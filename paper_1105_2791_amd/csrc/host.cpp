@@ -223,7 +223,9 @@ struct StageTimer {
 
 // Filter maps for S maps into 'maps' using F as scratch.
 modal_status run_maps(modal_ctx* c, const void* alm, int S, void* F, void* maps, hipStream_t st) {
-  if (c->legendre_mfma) STAGE(MODAL_STAGE_LEGENDRE, launch_legendre_mfma(c, alm, S, F, st));
+  if (c->prec == MODAL_BF16X3 || c->prec == MODAL_F16X3)
+    STAGE(MODAL_STAGE_LEGENDRE, launch_legendre_split(c, alm, S, F, st));
+  else if (c->legendre_mfma) STAGE(MODAL_STAGE_LEGENDRE, launch_legendre_mfma(c, alm, S, F, st));
   else STAGE(MODAL_STAGE_LEGENDRE, launch_legendre(c, alm, S, F, st));
   STAGE(MODAL_STAGE_FFT, launch_fft_c2r(c, F, S, maps, st));
   return MODAL_OK;
@@ -294,6 +296,9 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
 
   if (prec == MODAL_F32 || prec == MODAL_BF16X3 || prec == MODAL_F16X3) {
     if (prec != MODAL_F32) {
+      const size_t lneed = legendre_split_lds();
+      if (lneed + 1024 > c->max_lds) return bail(MODAL_EUNSUPPORTED);
+      if (lneed > 65536 && legendre_split_set_lds(lneed) != hipSuccess) return bail(MODAL_EDEVICE);
       const size_t cneed = cubic_split_lds();
       if (cneed + 1024 > c->max_lds) return bail(MODAL_EUNSUPPORTED);
       if (cneed > 65536 && cubic_split_set_lds(cneed) != hipSuccess) return bail(MODAL_EDEVICE);
