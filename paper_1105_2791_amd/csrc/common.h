@@ -65,6 +65,8 @@ struct modal_ctx {
   int tune_fft_rings = 0;       // rings per FFT workgroup
   float wscale = 1.f;           // power of two ~ npix / 4pi (split-fp16 contraction)
   modal::FftPlan fft{};
+  bool fft_rg = false;          // register-pass c2r kernel (float maps, radices 8/4/2/3/5)
+  modal::FftPlan fft_rg_plan{};
   modal::Tables t{};
   std::vector<double> x_host, wgl_host;
   std::string last_error;
@@ -83,10 +85,18 @@ struct modal_ctx {
 
 namespace modal {
 
+// Layout of the synthesis output F (complex per (sequence, ring, m)): rings are
+// grouped by eight, [seq][ring / 8][m][ring % 8], so that the ring FFT of a group
+// reads one contiguous block and the synthesis writes 64-byte runs of rings.
+__host__ __device__ inline int f_ring_blocks(int ntheta) { return (ntheta + 7) / 8; }
+__host__ __device__ inline size_t f_index(int seq, int ring, int m, int lmax, int nrb8) {
+  return (((size_t)seq * nrb8 + (ring >> 3)) * (size_t)(lmax + 1) + m) * 8 + (ring & 7);
+}
+
 // ---- launchers (defined in the .hip files); all return hipSuccess or the error
 hipError_t launch_seeds(const modal_ctx* c, const double* logpref, hipStream_t st);
 
-// Legendre synthesis: F[S][P][lmax+1][ntheta] complex (rings contiguous; double2 for F64, float2 otherwise)
+// Legendre synthesis: F (f_index layout) complex, double2 for F64, float2 otherwise
 hipError_t launch_legendre(const modal_ctx* c, const void* alm, int S, void* F, hipStream_t st);
 hipError_t launch_legendre_mfma(const modal_ctx* c, const void* alm, int S, void* F, hipStream_t st);
 // split bf16/fp16 synthesis on 32x32 tiles, lambda in registers (k_legendre_split.hip)
@@ -101,6 +111,9 @@ hipError_t launch_fft_c2r(const modal_ctx* c, const void* F, int S, void* maps, 
 hipError_t launch_fft_r2c(const modal_ctx* c, const void* G, int S, void* Gh, hipStream_t st);
 hipError_t launch_fft_r2c_rows(const modal_ctx* c, const void* G, size_t nseq, void* Gh, hipStream_t st);
 int fft_rings_per_block(const modal_ctx* c);
+bool fft_plan_rg(int N, FftPlan& p);
+size_t fft_rg_lds(const modal_ctx* c);
+hipError_t fft_rg_set_lds(size_t bytes);
 int fft_rings_max(const modal_ctx* c);
 int chunk_target_default(const modal_ctx* c);
 int chunk_target_min(const modal_ctx* c);

@@ -110,7 +110,10 @@ hipError_t upload(V** dst, const std::vector<V>& src) {
 }
 
 size_t alm_bytes(const modal_ctx* c) { return (size_t)c->nalm * 2 * real_bytes(c); }
-size_t F_bytes(const modal_ctx* c, int S) { return (size_t)S * c->P * c->ntheta * (c->lmax + 1) * 2 * real_bytes(c); }
+// synthesis output (f_index layout; also large enough for the adjoint's [S][P][lmax+1][ntheta])
+size_t F_bytes(const modal_ctx* c, int S) {
+  return (size_t)S * c->P * f_ring_blocks(c->ntheta) * 8 * (c->lmax + 1) * 2 * real_bytes(c);
+}
 size_t maps_bytes(const modal_ctx* c, int S) { return (size_t)S * c->P * c->npix * real_bytes(c); }
 int nchunk_for(const modal_ctx* c) { return cubic_mfma_available(c) ? cubic_mfma_nchunk(c) : cubic_nchunk(c); }
 // sized for the smallest chunk the autotuner may choose, so a workspace stays valid after tuning
@@ -293,6 +296,13 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
   const size_t fft_lds = (size_t)fft_rings_per_block(c) * 2 * c->fft.K * 2 * real_bytes(c);
   if (fft_lds > c->max_lds) return bail(MODAL_EUNSUPPORTED);
   if (fft_lds > 65536 && fft_set_lds_limit(fft_lds) != hipSuccess) return bail(MODAL_EDEVICE);
+  if (prec != MODAL_F64 && fft_plan_rg(nphi, c->fft_rg_plan)) {
+    const size_t rg = fft_rg_lds(c);
+    if (rg <= c->max_lds) {
+      if (rg > 65536 && fft_rg_set_lds(rg) != hipSuccess) return bail(MODAL_EDEVICE);
+      c->fft_rg = true;
+    }
+  }
 
   if (prec == MODAL_F32 || prec == MODAL_BF16X3 || prec == MODAL_F16X3) {
     if (prec != MODAL_F32) {

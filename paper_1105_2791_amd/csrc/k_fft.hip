@@ -13,6 +13,8 @@
 // table (rounded to the working precision).
 #include "common.h"
 
+#include <algorithm>
+
 namespace modal {
 namespace {
 
@@ -110,8 +112,9 @@ __device__ inline void stockham_stage_multi(const T2* __restrict__ in, T2* __res
   (void)KR;
 }
 
-// c2r: one workgroup per (sequence, block of R consecutive rings).  F layout is
-// [seq][m][ring] (rings contiguous), so a block reads R consecutive values per m.
+// c2r, generic radices: one workgroup per (sequence, block of R consecutive rings),
+// two LDS buffers (Stockham ping-pong).  Used for FP64 and for ring lengths whose
+// factors the register kernel below does not cover.
 template <typename T>
 __global__ __launch_bounds__(256) void k_fft_c2r(FftPlan plan, int lmax, int ntheta, int R,
                                                  const typename vec2<T>::type* __restrict__ F,
@@ -125,13 +128,13 @@ __global__ __launch_bounds__(256) void k_fft_c2r(FftPlan plan, int lmax, int nth
   const int seq = blockIdx.x / nrb;
   const int j0 = (blockIdx.x - seq * nrb) * R;
   const int nr = min(R, ntheta - j0);
-  const T2* H = F + (size_t)seq * (lmax + 1) * ntheta;
+  const int nrb8 = f_ring_blocks(ntheta);
   // X_m (zero beyond lmax, X_0 real) into b1, ring-major
   for (int e = threadIdx.x; e < R * K; e += blockDim.x) {
     const int m = e / R, r = e - m * R;
     T2 x;
     x.x = x.y = T(0);
-    if (m <= lmax && r < nr) x = H[(size_t)m * ntheta + j0 + r];
+    if (m <= lmax && r < nr) x = F[f_index(seq, j0 + r, m, lmax, nrb8)];
     if (m == 0) x.y = T(0);
     b1[(size_t)r * K + m] = x;
   }
@@ -219,6 +222,187 @@ __global__ __launch_bounds__(256) void k_fft_r2c(FftPlan plan, int lmax, int nth
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// c2r, register passes: one wave per ring, 4 rings per workgroup (half of one
+// f_index ring group).  The group's spectra are one contiguous block of F; the two
+// halves of a group run on the same XCD back to back (block b -> XCD b % 8), so a
+// cache line of F is fetched once.  Each pass of the mixed-radix (8, 4, 2, 3, 5)
+// Stockham transform reads all of a lane's butterfly inputs from the ring's LDS
+// buffer into registers, then writes the outputs in place: one wave owns the
+// buffer, and its LDS accesses complete in program order, so no barrier is needed
+// between passes.  LDS indices are padded by one element per 16 against bank
+// conflicts of the strided early passes.
+// ---------------------------------------------------------------------------
+constexpr int RG_RINGS = 4;            // rings (waves) per workgroup
+constexpr int RG_KMAX = 2048;          // longest complex transform of the register kernel
+
+__device__ inline int pad16(int i) { return i + (i >> 4); }
+
+__device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ inline float2 cmulf(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline float2 cmuli(float2 a) { return make_float2(-a.y, a.x); }            // i a
+__device__ inline float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// y_q = sum_r x_r e^{+2 pi i r q / R}, in place
+template <int R>
+__device__ inline void dft_plus(float2* x) {
+  if (R == 2) {
+    const float2 a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  } else if (R == 4) {
+    const float2 s02 = cadd(x[0], x[2]), d02 = csub(x[0], x[2]);
+    const float2 s13 = cadd(x[1], x[3]), d13 = cmuli(csub(x[1], x[3]));
+    x[0] = cadd(s02, s13);
+    x[2] = csub(s02, s13);
+    x[1] = cadd(d02, d13);
+    x[3] = csub(d02, d13);
+  } else if (R == 8) {
+    const float h = 0.70710678118654752f;
+    float2 a[4], b[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      a[r] = cadd(x[r], x[r + 4]);
+      b[r] = csub(x[r], x[r + 4]);
+    }
+    b[1] = make_float2(h * (b[1].x - b[1].y), h * (b[1].x + b[1].y));    // e^{i pi / 4}
+    b[2] = cmuli(b[2]);                                                  // e^{i pi / 2}
+    b[3] = make_float2(-h * (b[3].x + b[3].y), h * (b[3].x - b[3].y));   // e^{3 i pi / 4}
+    dft_plus<4>(a);
+    dft_plus<4>(b);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      x[2 * q] = a[q];
+      x[2 * q + 1] = b[q];
+    }
+  } else if (R == 3) {
+    const float s3 = 0.86602540378443865f;
+    const float2 t = cadd(x[1], x[2]), d = cscale(cmuli(csub(x[1], x[2])), s3);
+    const float2 m = csub(x[0], cscale(t, 0.5f));
+    x[0] = cadd(x[0], t);
+    x[1] = cadd(m, d);
+    x[2] = csub(m, d);
+  } else if (R == 5) {
+    const float c1 = 0.30901699437494742f, c2 = -0.80901699437494742f;
+    const float s1 = 0.95105651629515357f, s2 = 0.58778525229247313f;
+    const float2 t1 = cadd(x[1], x[4]), t2 = cadd(x[2], x[3]);
+    const float2 d1 = csub(x[1], x[4]), d2 = csub(x[2], x[3]);
+    const float2 a1 = cadd(x[0], cadd(cscale(t1, c1), cscale(t2, c2)));
+    const float2 a2 = cadd(x[0], cadd(cscale(t1, c2), cscale(t2, c1)));
+    const float2 b1 = cmuli(cadd(cscale(d1, s1), cscale(d2, s2)));
+    const float2 b2 = cmuli(csub(cscale(d1, s2), cscale(d2, s1)));
+    x[0] = cadd(x[0], cadd(t1, t2));
+    x[1] = cadd(a1, b1);
+    x[4] = csub(a1, b1);
+    x[2] = cadd(a2, b2);
+    x[3] = csub(a2, b2);
+  }
+}
+
+// one Stockham pass of radix R over the ring buffer b (length K, twiddle table tw of
+// the ring length N = 2 K: e^{2 pi i t / N})
+template <int R>
+__device__ inline void rg_pass(float2* b, int K, int Ns, int lane, const float2* tw) {
+  constexpr int NB = (RG_KMAX / R + 63) / 64;
+  const int KR = K / R;
+  const int step = K / (Ns * R);
+  float2 v[NB][R];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int bi = lane + 64 * i;
+    if (bi < KR) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[i][q] = b[pad16(bi + q * KR)];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int bi = lane + 64 * i;
+    if (bi < KR) {
+      const int k = bi % Ns;
+#pragma unroll
+      for (int q = 1; q < R; ++q) v[i][q] = cmulf(v[i][q], tw[2 * (q * k * step)]);
+      dft_plus<R>(v[i]);
+      const int ob = (bi / Ns) * Ns * R + k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) b[pad16(ob + q * Ns)] = v[i][q];
+    }
+  }
+}
+
+__global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int lmax, int ntheta, int nseq,
+                                                              const float2* __restrict__ F, float* __restrict__ maps,
+                                                              const float2* __restrict__ twg) {
+  extern __shared__ __attribute__((aligned(16))) float2 rbuf[];
+  const int K = plan.K, N = plan.N;
+  const int KP = pad16(K) + 1;
+  float2* tw = rbuf + RG_RINGS * KP;   // e^{2 pi i t / N}, t < N, shared by the workgroup's rings
+  const int nrb8 = f_ring_blocks(ntheta);
+  const int units = nseq * nrb8;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  for (int t = tid; t < N; t += 64 * RG_RINGS) tw[t] = twg[t];
+  // persistent: workgroups b and b + 8 (one XCD) take the two halves of the same ring
+  // groups, xcd + 8 (slot + k nslot), k = 0, 1, ...
+  const int b = blockIdx.x;
+  const int xcd = b & 7, half = (b >> 3) & 1, slot = b >> 4;
+  const int nslot = gridDim.x >> 4;
+  for (int unit = xcd + 8 * slot; unit < units; unit += 8 * nslot) {
+    const int seq = unit / nrb8, rb = unit - seq * nrb8;
+    __syncthreads();   // previous unit's buffers (and the twiddle table) are settled
+    // spectra of the four rings: F block of ring group rb, rings 4 half .. 4 half + 3
+    const float2* src = F + (size_t)unit * (lmax + 1) * 8 + RG_RINGS * half;
+    for (int e = tid; e < (lmax + 1) * RG_RINGS; e += 64 * RG_RINGS) {
+      const int m = e >> 2, r = e & 3;
+      float2 x = src[(size_t)m * 8 + r];
+      if (m == 0) x.y = 0.f;
+      rbuf[r * KP + pad16(m)] = x;
+    }
+    for (int e = tid; e < (K - lmax - 1) * RG_RINGS; e += 64 * RG_RINGS) {
+      const int r = e / (K - lmax - 1), m = lmax + 1 + e % (K - lmax - 1);
+      rbuf[r * KP + pad16(m)] = make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+
+    float2* bw = rbuf + w * KP;
+    // Z_m = (X_m + conj X_{K-m}) + i e^{2 pi i m / N} (X_m - conj X_{K-m}), X_K = 0;
+    // the lane that owns m also owns K - m, so the update is in place
+    for (int m = lane; m <= K / 2; m += 64) {
+      const int m2 = K - m;
+      const float2 xm = bw[pad16(m)];
+      const float2 xk = (m > 0) ? bw[pad16(m2 % K)] : make_float2(0.f, 0.f);
+      {
+        const float2 a = make_float2(xm.x + xk.x, xm.y - xk.y), d = make_float2(xm.x - xk.x, xm.y + xk.y);
+        const float2 ew = tw[m];
+        bw[pad16(m)] = make_float2(a.x - (ew.x * d.y + ew.y * d.x), a.y + (ew.x * d.x - ew.y * d.y));
+      }
+      if (m > 0 && m2 != m) {
+        const float2 a = make_float2(xk.x + xm.x, xk.y - xm.y), d = make_float2(xk.x - xm.x, xk.y + xm.y);
+        const float2 ew = tw[m2];
+        bw[pad16(m2)] = make_float2(a.x - (ew.x * d.y + ew.y * d.x), a.y + (ew.x * d.x - ew.y * d.y));
+      }
+    }
+    // z = sum_m Z_m e^{+2 pi i m n / K}
+    int Ns = 1;
+    for (int f = 0; f < plan.nf; ++f) {
+      const int R = plan.radix[f];
+      if (R == 8) rg_pass<8>(bw, K, Ns, lane, tw);
+      else if (R == 4) rg_pass<4>(bw, K, Ns, lane, tw);
+      else if (R == 2) rg_pass<2>(bw, K, Ns, lane, tw);
+      else if (R == 3) rg_pass<3>(bw, K, Ns, lane, tw);
+      else rg_pass<5>(bw, K, Ns, lane, tw);
+      Ns *= R;
+    }
+    // M_{2n} = Re z_n, M_{2n+1} = Im z_n
+    const int j = rb * 8 + RG_RINGS * half + w;
+    if (j < ntheta) {
+      float2* dst = reinterpret_cast<float2*>(maps + ((size_t)seq * ntheta + j) * plan.N);
+      for (int n = lane; n < K; n += 64) dst[n] = bw[pad16(n)];
+    }
+  }
+}
+
 }  // namespace
 
 int fft_rings_max(const modal_ctx* c) {
@@ -234,7 +418,43 @@ int fft_rings_per_block(const modal_ctx* c) {
   return (c->tune_fft_rings > 0 && c->tune_fft_rings <= R) ? c->tune_fft_rings : R;
 }
 
+// The register kernel's plan: radices 8, 4, 2, 3, 5 (largest first); false if the
+// ring length has other factors or exceeds the register kernel's size.
+bool fft_plan_rg(int N, FftPlan& p) {
+  p.N = N;
+  p.K = N / 2;
+  p.nf = 0;
+  if (p.K > RG_KMAX || p.K < 1) return false;
+  int K = p.K;
+  for (int r : {8, 4, 2, 3, 5})
+    while (K % r == 0) {
+      if (p.nf >= kMaxFactors) return false;
+      p.radix[p.nf++] = r;
+      K /= r;
+    }
+  return K == 1;
+}
+
+size_t fft_rg_lds(const modal_ctx* c) {
+  const int K = c->fft.K;
+  return ((size_t)RG_RINGS * (K + (K >> 4) + 1) + (size_t)2 * K) * sizeof(float2);
+}
+
+hipError_t fft_rg_set_lds(size_t bytes) {
+  return hipFuncSetAttribute((const void*)k_fft_c2r_rg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 hipError_t launch_fft_c2r(const modal_ctx* c, const void* F, int S, void* maps, hipStream_t st) {
+  if (c->fft_rg) {
+    // persistent: two workgroups per CU, in pairs (b, b + 8) per XCD
+    const int nseq = S * c->P;
+    const int units = nseq * f_ring_blocks(c->ntheta);
+    int blocks = 16 * ((units + 7) / 8);
+    blocks = std::min(blocks, 16 * 64);   // 1024 workgroups: 256 CUs x 4 rings x 2 x 2
+    hipLaunchKernelGGL(k_fft_c2r_rg, dim3(blocks), dim3(64 * RG_RINGS), fft_rg_lds(c), st, c->fft_rg_plan, c->lmax,
+                       c->ntheta, nseq, (const float2*)F, (float*)maps, (const float2*)c->t.tw32);
+    return hipGetLastError();
+  }
   const int R = fft_rings_per_block(c);
   const size_t blocks = (size_t)S * c->P * ((c->ntheta + R - 1) / R);
   const size_t lds = (size_t)R * 2 * c->fft.K * 2 * real_bytes(c);

@@ -169,14 +169,14 @@ __global__ __launch_bounds__(64) void k_legendre(int lmax, int ntheta, int nrp, 
   for (int q = 0; q < NSEQ; ++q) {
     const int sq = seq0 + q;
     if (sq >= nseq) break;
-    T2* row = F + ((size_t)sq * (lmax + 1) + m) * ntheta;   // F[seq][m][ring]
+    const int nrb8 = f_ring_blocks(ntheta);
     T2 vn, vs;
     vn.x = er[q] + orr[q];
     vn.y = ei[q] + oi[q];
     vs.x = er[q] - orr[q];
     vs.y = ei[q] - oi[q];
-    row[j] = vn;
-    if (js != j) row[js] = vs;
+    F[f_index(sq, j, m, lmax, nrb8)] = vn;
+    if (js != j) F[f_index(sq, js, m, lmax, nrb8)] = vs;
   }
 }
 

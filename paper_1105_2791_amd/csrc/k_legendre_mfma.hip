@@ -20,7 +20,7 @@
 //           coefficients are O(1), so no scaling is needed; lo parts that fall
 //           into fp16 subnormals carry absolute errors below 1e-7.
 //   F32   : v_mfma_f32_16x16x4_f32.
-// Output goes through LDS so that F[seq][m][ring] is written ring-contiguously.
+// Output goes through LDS so that F (f_index layout) is written in runs of rings.
 #include "common.h"
 
 namespace modal {
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(256) void k_legendre_mfma(int lmax, int ntheta, int
           float2 v;
           v.x = stg[lane * SS + cc];
           v.y = stg[lane * SS + cc + 1];
-          F[((size_t)(cg >> 1) * (lmax + 1) + m) * ntheta + jw] = v;
+          F[f_index(cg >> 1, jw, m, lmax, f_ring_blocks(ntheta))] = v;
         }
       }
     }

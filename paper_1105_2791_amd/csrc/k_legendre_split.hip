@@ -20,7 +20,7 @@
 //     2 K steps x (4 products for bf16: hi.hi + hi.lo + lo.hi + lo.lo, every map
 //     entering the cubic three times; 3 for fp16) from zero, added to the running
 //     FP32 sum on the VALU once per chunk.
-// Output goes through LDS so that F[seq][m][ring] is written ring-contiguously.
+// Output goes through LDS so that F (f_index layout) is written in runs of rings.
 #include "common.h"
 
 #include <type_traits>
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(256) void k_legendre_split(int lmax, int ntheta, in
           float2 v;
           v.x = stg[lane * SS + cc];
           v.y = stg[lane * SS + cc + 1];
-          F[((size_t)(cg >> 1) * (lmax + 1) + m) * ntheta + jw] = v;
+          F[f_index(cg >> 1, jw, m, lmax, f_ring_blocks(ntheta))] = v;
         }
       }
     }
