@@ -303,9 +303,10 @@ __device__ inline void dft_plus(float2* x) {
 
 // one Stockham pass of radix R over the ring buffer b (length K, twiddle table tw of
 // the ring length N = 2 K: e^{2 pi i t / N})
-template <int R>
+// PTS: the most points a lane holds in any pass of the plan (register budget)
+template <int R, int PTS>
 __device__ inline void rg_pass(float2* b, int K, int Ns, int lane, const float2* tw) {
-  constexpr int NB = (RG_KMAX / R + 63) / 64;
+  constexpr int NB = (PTS + R - 1) / R;
   const int KR = K / R;
   const int step = K / (Ns * R);
   float2 v[NB][R];
@@ -332,6 +333,7 @@ __device__ inline void rg_pass(float2* b, int K, int Ns, int lane, const float2*
   }
 }
 
+template <int PTS>
 __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int lmax, int ntheta, int nseq,
                                                               const float2* __restrict__ F, float* __restrict__ maps,
                                                               const float2* __restrict__ twg) {
@@ -352,12 +354,25 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int 
     const int seq = unit / nrb8, rb = unit - seq * nrb8;
     __syncthreads();   // previous unit's buffers (and the twiddle table) are settled
     // spectra of the four rings: F block of ring group rb, rings 4 half .. 4 half + 3
-    const float2* src = F + (size_t)unit * (lmax + 1) * 8 + RG_RINGS * half;
-    for (int e = tid; e < (lmax + 1) * RG_RINGS; e += 64 * RG_RINGS) {
-      const int m = e >> 2, r = e & 3;
-      float2 x = src[(size_t)m * 8 + r];
-      if (m == 0) x.y = 0.f;
-      rbuf[r * KP + pad16(m)] = x;
+    // float4 = rings (2 rp, 2 rp + 1) at one m; 8 loads in flight per thread per round
+    const float4* src = reinterpret_cast<const float4*>(F + (size_t)unit * (lmax + 1) * 8 + RG_RINGS * half);
+    const int nv = (lmax + 1) * 2;
+    for (int e0 = 0; e0 < nv; e0 += 8 * 64 * RG_RINGS) {
+      float4 x[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int e = e0 + tid + i * 64 * RG_RINGS;
+        if (e < nv) x[i] = src[(size_t)(e >> 1) * 4 + (e & 1)];
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int e = e0 + tid + i * 64 * RG_RINGS;
+        if (e < nv) {
+          const int m = e >> 1, r = 2 * (e & 1);
+          rbuf[r * KP + pad16(m)] = make_float2(x[i].x, m == 0 ? 0.f : x[i].y);
+          rbuf[(r + 1) * KP + pad16(m)] = make_float2(x[i].z, m == 0 ? 0.f : x[i].w);
+        }
+      }
     }
     for (int e = tid; e < (K - lmax - 1) * RG_RINGS; e += 64 * RG_RINGS) {
       const int r = e / (K - lmax - 1), m = lmax + 1 + e % (K - lmax - 1);
@@ -387,11 +402,11 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int 
     int Ns = 1;
     for (int f = 0; f < plan.nf; ++f) {
       const int R = plan.radix[f];
-      if (R == 8) rg_pass<8>(bw, K, Ns, lane, tw);
-      else if (R == 4) rg_pass<4>(bw, K, Ns, lane, tw);
-      else if (R == 2) rg_pass<2>(bw, K, Ns, lane, tw);
-      else if (R == 3) rg_pass<3>(bw, K, Ns, lane, tw);
-      else rg_pass<5>(bw, K, Ns, lane, tw);
+      if (R == 8) rg_pass<8, PTS>(bw, K, Ns, lane, tw);
+      else if (R == 4) rg_pass<4, PTS>(bw, K, Ns, lane, tw);
+      else if (R == 2) rg_pass<2, PTS>(bw, K, Ns, lane, tw);
+      else if (R == 3) rg_pass<3, PTS>(bw, K, Ns, lane, tw);
+      else rg_pass<5, PTS>(bw, K, Ns, lane, tw);
       Ns *= R;
     }
     // M_{2n} = Re z_n, M_{2n+1} = Im z_n
@@ -420,6 +435,8 @@ int fft_rings_per_block(const modal_ctx* c) {
 
 // The register kernel's plan: radices 8, 4, 2, 3, 5 (largest first); false if the
 // ring length has other factors or exceeds the register kernel's size.
+int fft_rg_points(const FftPlan& p);
+
 bool fft_plan_rg(int N, FftPlan& p) {
   p.N = N;
   p.K = N / 2;
@@ -432,7 +449,15 @@ bool fft_plan_rg(int N, FftPlan& p) {
       p.radix[p.nf++] = r;
       K /= r;
     }
-  return K == 1;
+  if (K != 1) return false;
+  return fft_rg_points(p) <= 48;
+}
+
+// the most points one lane holds in a pass: ceil(K / R / 64) R
+int fft_rg_points(const FftPlan& p) {
+  int pts = 0;
+  for (int f = 0; f < p.nf; ++f) pts = std::max(pts, (p.K / p.radix[f] + 63) / 64 * p.radix[f]);
+  return pts;
 }
 
 size_t fft_rg_lds(const modal_ctx* c) {
@@ -441,7 +466,11 @@ size_t fft_rg_lds(const modal_ctx* c) {
 }
 
 hipError_t fft_rg_set_lds(size_t bytes) {
-  return hipFuncSetAttribute((const void*)k_fft_c2r_rg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  hipError_t e = hipFuncSetAttribute((const void*)k_fft_c2r_rg<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_fft_c2r_rg<24>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_fft_c2r_rg<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_fft_c2r_rg<48>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  return e;
 }
 
 hipError_t launch_fft_c2r(const modal_ctx* c, const void* F, int S, void* maps, hipStream_t st) {
@@ -451,8 +480,15 @@ hipError_t launch_fft_c2r(const modal_ctx* c, const void* F, int S, void* maps, 
     const int units = nseq * f_ring_blocks(c->ntheta);
     int blocks = 16 * ((units + 7) / 8);
     blocks = std::min(blocks, 16 * 64);   // 1024 workgroups: 256 CUs x 4 rings x 2 x 2
-    hipLaunchKernelGGL(k_fft_c2r_rg, dim3(blocks), dim3(64 * RG_RINGS), fft_rg_lds(c), st, c->fft_rg_plan, c->lmax,
-                       c->ntheta, nseq, (const float2*)F, (float*)maps, (const float2*)c->t.tw32);
+    const int pts = fft_rg_points(c->fft_rg_plan);
+#define LAUNCH(PT)                                                                                                \
+  hipLaunchKernelGGL(k_fft_c2r_rg<PT>, dim3(blocks), dim3(64 * RG_RINGS), fft_rg_lds(c), st, c->fft_rg_plan,        \
+                     c->lmax, c->ntheta, nseq, (const float2*)F, (float*)maps, (const float2*)c->t.tw32)
+    if (pts <= 16) LAUNCH(16);
+    else if (pts <= 24) LAUNCH(24);
+    else if (pts <= 32) LAUNCH(32);
+    else LAUNCH(48);
+#undef LAUNCH
     return hipGetLastError();
   }
   const int R = fft_rings_per_block(c);
