@@ -154,7 +154,7 @@ def run_path(args, prec, steps, warmup, make_state=True):
     log(f"bench[{prec}]: state ready")
 
     tuned = None
-    if not args.no_autotune:
+    if args.autotune:
         tuned = ctx.autotune(alm, state)
         log(f"bench[{prec}]: autotuned {tuned}")
     for _ in range(warmup):
@@ -183,6 +183,48 @@ def run_path(args, prec, steps, warmup, make_state=True):
     return res
 
 
+KERNEL_SOURCES = {   # dominant-kernel name -> the source file its counters belong to
+    "cubic": "paper_1105_2791_amd/csrc/k_cubic_split.hip",
+    "legendre": "paper_1105_2791_amd/csrc/k_legendre_split.hip",
+    "fft": "paper_1105_2791_amd/csrc/k_fft.hip",
+    "linear": "paper_1105_2791_amd/csrc/k_lin_harm.hip",
+}
+
+
+def measured_traffic(kernel, prec):
+    """HBM bytes per launch from the committed counter record of this kernel, or None
+    when there is none or the kernel source changed since the counters were taken."""
+    import hashlib
+    rec_path = os.path.join(ROOT, "profiles", f"{kernel}_{prec}_traffic.json")
+    src = KERNEL_SOURCES.get(kernel)
+    if not src or not os.path.exists(rec_path):
+        return None
+    with open(rec_path) as f:
+        rec = json.load(f)
+    with open(os.path.join(ROOT, src), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 2 GiB, three times (the counter reference)."""
+    import torch
+    n = 2 << 30
+    a = torch.empty(n // 4, dtype=torch.float32, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 3
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 3,
+                      "GB_per_s_read_plus_write": 2 * n / dt / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,7 +240,10 @@ def main():
     ap.add_argument("--cpu-rings", type=int, default=8)
     ap.add_argument("--compare-steps", type=int, default=3, help="timed steps of the plain-FP32 comparison (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the chunk autotuner first (the defaults are its choice on MI355X)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of a known size (HBM counter calibration)")
     ap.add_argument("--no-linear", action="store_true", help="beta without the linear term (diagnostic)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -208,6 +253,9 @@ def main():
 
     import torch
     torch.cuda.set_device(torch.device("cuda", 0))
+    if args.copy_calibration:
+        copy_calibration()
+        return
     prec = args.prec
     head = run_path(args, prec, args.steps, args.warmup, make_state=not args.no_linear)
     fp32 = None
@@ -218,6 +266,7 @@ def main():
     dom = max(head["kernels"].items(), key=lambda kv: kv[1]["avg_ms"])
     roof = dict(dom[1])
     roof["kernel"] = dom[0]
+    roof["traffic"] = measured_traffic(dom[0], prec)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -808,7 +808,8 @@ modal_status modal_autotune(modal_ctx* c, const void* alm, int S, const void* st
   const int chunks[] = {lo, 2 * lo, 4 * lo, 8 * lo};
   int best_chunk_init = chunk_target_default(c);
   best_chunk = best_chunk_init;
-  for (int r = fft_rings_max(c); r >= 1 && s == MODAL_OK; r >>= 1)
+  // rings per FFT workgroup only matter for the LDS ping-pong FFT kernel
+  for (int r = c->fft_rg ? 1 : fft_rings_max(c); r >= 1 && s == MODAL_OK; r >>= 1)
     for (int ch : chunks) {
       if (c->prec == MODAL_F32 && ch > chunk_target_default(c)) continue;   // FP32 keeps short chunks
       c->tune_chunk_px = ch;

@@ -332,8 +332,9 @@ int chunk_px_for(const modal_ctx* c, int target) {
 
 // FP32 accumulates its exact products in FP32, so it uses short chunks; the split
 // precisions carry a larger operand error and use long chunks (fewer partials).
-int chunk_target_default(const modal_ctx* c) { return c->prec == MODAL_F32 ? 4096 : 65536; }
-int chunk_target_min(const modal_ctx* c) { return c->prec == MODAL_F32 ? 2048 : 16384; }
+// (defaults: the autotuner's choice at lmax 1000, P 40 on MI355X)
+int chunk_target_default(const modal_ctx* c) { return c->prec == MODAL_F32 ? 4096 : 16384; }
+int chunk_target_min(const modal_ctx* c) { return c->prec == MODAL_F32 ? 2048 : 8192; }
 
 int cubic_chunk_px(const modal_ctx* c) {
   return chunk_px_for(c, c->tune_chunk_px > 0 ? c->tune_chunk_px : chunk_target_default(c));
