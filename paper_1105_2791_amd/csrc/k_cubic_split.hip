@@ -51,6 +51,11 @@ constexpr int BROWS = 64;          // B rows: row r <-> mode P - 64 + r (rows of
 constexpr int ESTEP = kMaxP * KS / NT;   // staged map values per thread per step (8)
 constexpr int CHAIN = 4;           // staged steps per MFMA accumulation chain (48 MFMAs per tile)
 
+// LDS slot of map row r: even rows first, then odd rows.  The lane-rows of a wave
+// read rows a0 (even, consecutive blocks) and a0 + 1, so consecutive even rows land
+// in consecutive 16-byte bank groups (row stride MSS = 17 groups).
+__device__ inline int ms_slot(int r) { return (r >> 1) + (r & 1) * (kMaxP / 2); }
+
 struct Lds {
   float ms[2][kMaxP][MSS];
   uint16_t bh[2][BROWS][BSS];
@@ -174,8 +179,8 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
     b0 = bb.y;
   }
   // LDS offsets (floats within a stage) of this lane's four map rows at its k-half
-  const int oa[2] = {min(a0, P - 1) * MSS + 8 * kh, min(a0 + 1, P - 1) * MSS + 8 * kh};
-  const int ob_[2] = {min(b0, P - 1) * MSS + 8 * kh, min(b0 + 1, P - 1) * MSS + 8 * kh};
+  const int oa[2] = {ms_slot(min(a0, P - 1)) * MSS + 8 * kh, ms_slot(min(a0 + 1, P - 1)) * MSS + 8 * kh};
+  const int ob_[2] = {ms_slot(min(b0, P - 1)) * MSS + 8 * kh, ms_slot(min(b0 + 1, P - 1)) * MSS + 8 * kh};
 
   const float* Msky = maps + (size_t)s * P * npix;
   const int x_begin = chunk * chunk_px;
@@ -203,7 +208,7 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
     for (int i = 0; i < ESTEP; ++i) {
       const int t = (tid + NT * i) / KS;
       if (t < P) {
-        L.ms[st][t][sxx] = pre[i] * msc[t];
+        L.ms[st][ms_slot(t)][sxx] = pre[i] * msc[t];
         const float sc = F16 ? msc[t] * wscale : 1.f;
         store_split<PREC>(wpre * sc * pre[i], &L.bh[st][BROWS - P + t][sxx], &L.bl[st][BROWS - P + t][sxx]);
       }

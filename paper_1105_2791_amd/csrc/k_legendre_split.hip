@@ -73,8 +73,40 @@ __device__ inline void split2(float v0, float v1, uint32_t& hi, uint32_t& lo) {
   }
 }
 
+// 64 recurrence steps of one lane's ring from l0, split into hi/lo words: Lh/Ll
+// [par][ks][half][k] hold l-indices 16 ks + 8 half + 2 k and + 1 of parity par.
+// 16 steps at a time fill l-indices 8 g .. 8 g + 7 of both parities (ks = g / 2, half = g % 2).
+template <int PREC, bool FAST>
+__device__ inline void lambda_chunk(int l0, int m, int lmax, size_t off, const double* __restrict__ rec, double xx,
+                                    int ls, double s0, double s1, double& l1, double& l2, uint32_t (&Lh)[2][2][2][4],
+                                    uint32_t (&Ll)[2][2][2][4]) {
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    float lam[2][8];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int l = l0 + 16 * g + t;
+      const double* rc = rec + 2 * (off + (size_t)((FAST ? l : min(l, lmax)) - m));
+      double v = fma(rc[0] * xx, l1, -rc[1] * l2);
+      if (!FAST) {
+        v = (l < ls) ? 0.0 : v;
+        v = (l == ls) ? s0 : v;
+        v = (l == ls + 1) ? s1 : v;
+      }
+      l2 = l1;
+      l1 = v;
+      lam[t & 1][t >> 1] = (FAST || l <= lmax) ? (float)v : 0.f;
+    }
+#pragma unroll
+    for (int par = 0; par < 2; ++par)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        split2<PREC>(lam[par][2 * k], lam[par][2 * k + 1], Lh[par][g >> 1][g & 1][k], Ll[par][g >> 1][g & 1][k]);
+  }
+}
+
 template <int PREC>
-__global__ __launch_bounds__(256) void k_legendre_split(int lmax, int ntheta, int nrp, int P, int ncols, int nalm,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_legendre_split(int lmax, int ntheta, int nrp, int P, int ncols, int nalm,
                                                         const double* __restrict__ x, const double* __restrict__ rec,
                                                         const double* __restrict__ seed,
                                                         const int* __restrict__ lstart, const float* __restrict__ qw,
@@ -164,30 +196,12 @@ __global__ __launch_bounds__(256) void k_legendre_split(int lmax, int ntheta, in
     //      [par][ks][half][k] holds l-indices 16 ks + 8 half + 2 k, + 1
     uint32_t Lh[2][2][2][4], Ll[2][2][2][4];
     {
-      const bool fast = l0 > wls + 1;   // wave-uniform: every lane is past its seeds
-      // 16 steps at a time fill l-indices 8 g .. 8 g + 7 of both parities (ks = g / 2, half = g % 2)
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        float lam[2][8];
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-          const int l = l0 + 16 * g + t;
-          const double* rc = rec + 2 * (off + (size_t)(min(l, lmax) - m));
-          double v = fma(rc[0] * xx, l1, -rc[1] * l2);
-          if (!fast) {
-            v = (l < ls) ? 0.0 : v;
-            v = (l == ls) ? s0 : v;
-            v = (l == ls + 1) ? s1 : v;
-          }
-          l2 = l1;
-          l1 = v;
-          lam[t & 1][t >> 1] = (l <= lmax) ? (float)v : 0.f;
-        }
-#pragma unroll
-        for (int par = 0; par < 2; ++par)
-#pragma unroll
-          for (int k = 0; k < 4; ++k)
-            split2<PREC>(lam[par][2 * k], lam[par][2 * k + 1], Lh[par][g >> 1][g & 1][k], Ll[par][g >> 1][g & 1][k]);
+      // wave-uniform: every lane is past its seeds and the chunk ends inside l <= lmax,
+      // so the steps need no selects (the general form handles seeds and the tail)
+      if (l0 > wls + 1 && l0 + LCH - 1 <= lmax) {
+        lambda_chunk<PREC, true>(l0, m, lmax, off, rec, xx, ls, s0, s1, l1, l2, Lh, Ll);
+      } else {
+        lambda_chunk<PREC, false>(l0, m, lmax, off, rec, xx, ls, s0, s1, l1, l2, Lh, Ll);
       }
       // hand half 1 of lanes 0-31 and half 0 of lanes 32-63 across: afterwards
       // half 0 is the ring tile 0 operand and half 1 the ring tile 1 operand
