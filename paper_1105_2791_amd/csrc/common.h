@@ -15,6 +15,7 @@ namespace modal {
 
 constexpr int kMaxP = 64;          // largest number of mode functions supported
 constexpr int kMaxFactors = 16;    // FFT radix plan length
+constexpr int kRecPad = 64;       // zero recurrence entries after the last (l, m)
 constexpr double kLogSeedFloor = -62.383246250395075;  // ln(2^-90): smaller lambda are dropped
 
 struct FftPlan {
@@ -30,7 +31,7 @@ struct Tables {
   double* ringw = nullptr;     // [ntheta] w_GL(theta_j) * 2 pi / nphi
   double* w64 = nullptr;       // [ntheta*nphi] pixel weights (ringw * mask)
   float* w32 = nullptr;        // same, float
-  double* rec = nullptr;       // [nalm][2] recurrence coefficients (A_lm, B_lm)
+  double* rec = nullptr;       // [nalm + kRecPad][2] recurrence coefficients (A_lm, B_lm)
   double* seed = nullptr;      // [lmax+1][nrp][2] lambda at l_start and l_start + 1
   int* lstart = nullptr;       // [lmax+1][nrp] first significant l per (m, ring)
   int* lstart_blk = nullptr;   // [lmax+1][nrp/64 rounded up] block minimum of lstart

@@ -332,7 +332,8 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
     }
   }
   // --- recurrence coefficients and seed prefactors
-  std::vector<double> rec(2 * (size_t)c->nalm, 0.0), logpref(lmax + 1);
+  // zero entries past the last m let a 64-step chunk read past l = lmax without a clamp
+  std::vector<double> rec(2 * ((size_t)c->nalm + kRecPad), 0.0), logpref(lmax + 1);
   double cum = 0.0;
   for (int m = 0; m <= lmax; ++m) {
     if (m > 0) cum += std::log((2.0 * m - 1.0) / (2.0 * m));

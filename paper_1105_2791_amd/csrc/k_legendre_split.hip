@@ -77,17 +77,19 @@ __device__ inline void split2(float v0, float v1, uint32_t& hi, uint32_t& lo) {
 // [par][ks][half][k] hold l-indices 16 ks + 8 half + 2 k and + 1 of parity par.
 // 16 steps at a time fill l-indices 8 g .. 8 g + 7 of both parities (ks = g / 2, half = g % 2).
 template <int PREC, bool FAST>
-__device__ inline void lambda_chunk(int l0, int m, int lmax, size_t off, const double* __restrict__ rec, double xx,
-                                    int ls, double s0, double s1, double& l1, double& l2, uint32_t (&Lh)[2][2][2][4],
+__device__ inline void lambda_chunk(int l0, int m, int lmax, const double2* __restrict__ rc, double xx, int ls,
+                                    double s0, double s1, double& l1, double& l2, uint32_t (&Lh)[2][2][2][4],
                                     uint32_t (&Ll)[2][2][2][4]) {
+  // rc = (A, B) of l0 .. l0 + 63 for this m: wave-uniform, constant offsets, so the
+  // coefficients arrive as wide scalar loads (the table is padded past the last m)
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
     float lam[2][8];
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
       const int l = l0 + 16 * g + t;
-      const double* rc = rec + 2 * (off + (size_t)((FAST ? l : min(l, lmax)) - m));
-      double v = fma(rc[0] * xx, l1, -rc[1] * l2);
+      const double2 r = rc[16 * g + t];
+      double v = fma(r.x * xx, l1, -r.y * l2);
       if (!FAST) {
         v = (l < ls) ? 0.0 : v;
         v = (l == ls) ? s0 : v;
@@ -157,28 +159,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // chunks start at l = m + 64 k so that parity(l - m) = parity(l - l0)
   const int kfirst = (lmin > m) ? (lmin - m) / LCH : 0;
   for (int l0 = m + kfirst * LCH; l0 <= lmax; l0 += LCH) {
-    // ---- coefficient tile: thread (col, quarter) fills 16 consecutive l of one column
+    // ---- coefficient tile: thread (col, quarter) fills 16 consecutive l of one column.
+    //      All 16 pairs of loads are unconditional (index clamped, value selected after)
+    //      so that they are in flight together.
     __syncthreads();
     {
       const int col = tid >> 2, q = tid & 3;
-      const int cg = c0 + col;
+      const int cg = min(c0 + col, ncols - 1);
+      const int sq = cg >> 1, reim = cg & 1;
+      const int s = sq / P, p = sq - s * P;
+      const float* as = reinterpret_cast<const float*>(alm + (size_t)s * nalm + off) + reim;
+      const float* qp = qw + (size_t)p * (lmax + 1);
+      float va[16], vq[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int l = min(l0 + 16 * q + i, lmax);
+        va[i] = as[2 * (l - m)];
+        vq[i] = qp[l];
+      }
       float v[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = 0.f;
-      if (cg < ncols) {
-        const int sq = cg >> 1, reim = cg & 1;
-        const int s = sq / P, p = sq - s * P;
-        const float2* as = alm + (size_t)s * nalm + off;
-        const float* qp = qw + (size_t)p * (lmax + 1);
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int l = l0 + 16 * q + i;
-          if (l <= lmax) {
-            const float2 a = as[l - m];
-            v[i] = qp[l] * (reim ? a.y : a.x);
-          }
-        }
-      }
+      for (int i = 0; i < 16; ++i) v[i] = (c0 + col < ncols && l0 + 16 * q + i <= lmax) ? vq[i] * va[i] : 0.f;
       // l = l0 + 16 q + i has parity i & 1 and index 8 q + i / 2
       uint32_t h[2][4], lw[2][4];
 #pragma unroll
@@ -196,12 +197,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     //      [par][ks][half][k] holds l-indices 16 ks + 8 half + 2 k, + 1
     uint32_t Lh[2][2][2][4], Ll[2][2][2][4];
     {
+      const double2* rc = reinterpret_cast<const double2*>(rec) + off + (l0 - m);
       // wave-uniform: every lane is past its seeds and the chunk ends inside l <= lmax,
       // so the steps need no selects (the general form handles seeds and the tail)
       if (l0 > wls + 1 && l0 + LCH - 1 <= lmax) {
-        lambda_chunk<PREC, true>(l0, m, lmax, off, rec, xx, ls, s0, s1, l1, l2, Lh, Ll);
+        lambda_chunk<PREC, true>(l0, m, lmax, rc, xx, ls, s0, s1, l1, l2, Lh, Ll);
       } else {
-        lambda_chunk<PREC, false>(l0, m, lmax, off, rec, xx, ls, s0, s1, l1, l2, Lh, Ll);
+        lambda_chunk<PREC, false>(l0, m, lmax, rc, xx, ls, s0, s1, l1, l2, Lh, Ll);
       }
       // hand half 1 of lanes 0-31 and half 0 of lanes 32-63 across: afterwards
       // half 0 is the ring tile 0 operand and half 1 the ring tile 1 operand
