@@ -35,20 +35,28 @@ __global__ __launch_bounds__(256) void k_weight_planes(int npix, int nk, const T
 }
 
 // X[s][pair][l] = sum_{m <= l} (Re a Re Z + Im a Im Z) at index (l, m), FP64 sums.
-// One thread per l; a workgroup covers PT pairs x ST maps so that every Z and a_lm
-// element it loads feeds PT or ST products.
+// A workgroup covers LT consecutive l (one per lane) x PT pairs x ST maps, so that every
+// Z and a_lm element it loads feeds PT or ST products; its MW waves take the m of the
+// sum in turn (m = w, w + MW, ...) and their partial sums are added through LDS.  The
+// lanes of a wave read consecutive l of one m row of the m-major packing: coalesced.
 constexpr int PT = 8;
 constexpr int ST = 8;
+constexpr int LT = 64;
+constexpr int MW = 4;
+constexpr int RED = 16;   // accumulators per LDS reduction round
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_lin_x(int lmax, int nalm, int npairs, int S,
-                                               const typename vec2<T>::type* __restrict__ Z,
-                                               const typename vec2<T>::type* __restrict__ alm,
-                                               double* __restrict__ X) {
+__global__ __launch_bounds__(LT * MW) void k_lin_x(int lmax, int nalm, int npairs, int S,
+                                                   const typename vec2<T>::type* __restrict__ Z,
+                                                   const typename vec2<T>::type* __restrict__ alm,
+                                                   double* __restrict__ X) {
   using T2 = typename vec2<T>::type;
-  const int l = blockIdx.x * 256 + threadIdx.x;
+  __shared__ double red[MW - 1][RED][LT];
+  const int lane = threadIdx.x % LT, w = threadIdx.x / LT;
+  const int l = blockIdx.x * LT + lane;
+  const int lc = min(l, lmax);
+  const int mend = min((int)blockIdx.x * LT + LT - 1, lmax);   // largest l of the workgroup
   const int p0 = blockIdx.y * PT, s0 = blockIdx.z * ST;
-  if (l > lmax) return;
   double acc[PT][ST];
 #pragma unroll
   for (int k = 0; k < PT; ++k)
@@ -60,14 +68,17 @@ __global__ __launch_bounds__(256) void k_lin_x(int lmax, int nalm, int npairs, i
   for (int k = 0; k < PT; ++k) zr[k] = Z + (size_t)min(p0 + k, npairs - 1) * nalm;
 #pragma unroll
   for (int q = 0; q < ST; ++q) ar[q] = alm + (size_t)min(s0 + q, S - 1) * nalm;
-  for (int m = 0; m <= l; ++m) {
-    const size_t idx = (size_t)m * (2 * lmax + 3 - m) / 2 + (l - m);   // m-major packing
+#pragma unroll 2
+  for (int m = w; m <= mend; m += MW) {
+    // lanes with l < m (or past lmax) read a valid element of the row and add zero
+    const bool on = m <= l && l <= lmax;
+    const size_t idx = (size_t)m * (2 * lmax + 3 - m) / 2 + (max(lc, m) - m);   // m-major packing
     double zx[PT], zy[PT];
 #pragma unroll
     for (int k = 0; k < PT; ++k) {
       const T2 z = zr[k][idx];
-      zx[k] = (double)z.x;
-      zy[k] = (double)z.y;
+      zx[k] = on ? (double)z.x : 0.0;
+      zy[k] = on ? (double)z.y : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < ST; ++q) {
@@ -77,6 +88,23 @@ __global__ __launch_bounds__(256) void k_lin_x(int lmax, int nalm, int npairs, i
       for (int k = 0; k < PT; ++k) acc[k][q] = fma(ax, zx[k], fma(ay, zy[k], acc[k][q]));
     }
   }
+  // add the partial sums of waves 1 .. MW-1 into wave 0, RED accumulators at a time
+#pragma unroll
+  for (int r0 = 0; r0 < PT * ST; r0 += RED) {
+    __syncthreads();
+    if (w > 0) {
+#pragma unroll
+      for (int i = 0; i < RED; ++i) red[w - 1][i][lane] = acc[(r0 + i) / ST][(r0 + i) % ST];
+    }
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+      for (int i = 0; i < RED; ++i)
+#pragma unroll
+        for (int v = 0; v < MW - 1; ++v) acc[(r0 + i) / ST][(r0 + i) % ST] += red[v][i][lane];
+    }
+  }
+  if (w != 0 || l > lmax) return;
 #pragma unroll
   for (int q = 0; q < ST; ++q) {
     if (s0 + q >= S) break;
@@ -125,12 +153,12 @@ hipError_t launch_weight_planes(const modal_ctx* c, const void* V, int nk, void*
 hipError_t launch_lin_harmonic(const modal_ctx* c, const void* Z, const void* alm, int S, double* X, double* L,
                                hipStream_t st) {
   if (c->P > 64) return hipErrorInvalidValue;
-  dim3 gx((c->lmax + 1 + 255) / 256, (c->npairs + PT - 1) / PT, (S + ST - 1) / ST);
+  dim3 gx((c->lmax + LT) / LT, (c->npairs + PT - 1) / PT, (S + ST - 1) / ST);
   if (is_f64(c))
-    hipLaunchKernelGGL(k_lin_x<double>, gx, dim3(256), 0, st, c->lmax, c->nalm, c->npairs, S, (const double2*)Z,
+    hipLaunchKernelGGL(k_lin_x<double>, gx, dim3(LT * MW), 0, st, c->lmax, c->nalm, c->npairs, S, (const double2*)Z,
                        (const double2*)alm, X);
   else
-    hipLaunchKernelGGL(k_lin_x<float>, gx, dim3(256), 0, st, c->lmax, c->nalm, c->npairs, S, (const float2*)Z,
+    hipLaunchKernelGGL(k_lin_x<float>, gx, dim3(LT * MW), 0, st, c->lmax, c->nalm, c->npairs, S, (const float2*)Z,
                        (const float2*)alm, X);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
