@@ -39,6 +39,7 @@ struct Tables {
   float* qw32 = nullptr;
   double* tw64 = nullptr;      // [nphi][2] exp(2 pi i t / nphi)
   float* tw32 = nullptr;
+  float* twp32 = nullptr;      // [K - 1][2] per-pass twiddles of the register-pass ring FFT
   int* pair_a = nullptr;       // [npairs] first mode of each pair
   int* pair_b = nullptr;       // [npairs] second mode
   int* tri = nullptr;          // [nmax][6] p, r, s, pair(pr), pair(ps), pair(rs)
@@ -113,6 +114,7 @@ hipError_t launch_fft_r2c(const modal_ctx* c, const void* G, int S, void* Gh, hi
 hipError_t launch_fft_r2c_rows(const modal_ctx* c, const void* G, size_t nseq, void* Gh, hipStream_t st);
 int fft_rings_per_block(const modal_ctx* c);
 bool fft_plan_rg(int N, FftPlan& p);
+std::vector<float> fft_rg_twiddles(const FftPlan& p);
 size_t fft_rg_lds(const modal_ctx* c);
 hipError_t fft_rg_set_lds(size_t bytes);
 int fft_rings_max(const modal_ctx* c);

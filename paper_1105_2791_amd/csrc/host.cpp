@@ -415,6 +415,7 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
   t.nblk = (int)blocks.size();
   t.nitems = (int)items.size();
   if (upload(&t.blk, blocks) != hipSuccess || upload(&t.items, items) != hipSuccess) return bail(MODAL_EDEVICE);
+  if (c->fft_rg && upload(&t.twp32, fft_rg_twiddles(c->fft_rg_plan)) != hipSuccess) return bail(MODAL_EDEVICE);
   std::vector<double> xs(c->x_host);
   if (upload(&t.x, xs) != hipSuccess || upload(&t.ringw, ringw) != hipSuccess || upload(&t.w64, w64) != hipSuccess ||
       upload(&t.w32, w32) != hipSuccess || upload(&t.rec, rec) != hipSuccess || upload(&t.qw64, qw64) != hipSuccess ||
@@ -447,7 +448,8 @@ void modal_destroy(modal_ctx* c) {
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   Tables& t = c->t;
   void* ptrs[] = {t.x, t.ringw, t.w64, t.w32, t.rec, t.seed, t.lstart, t.lstart_blk, t.qw64, t.qw32, t.tw64, t.tw32,
-                  t.pair_a, t.pair_b, t.tri, t.pair_of, t.tri_of, t.tri_mult, t.flag, t.blk, t.items, t.mscale};
+                  t.pair_a, t.pair_b, t.tri, t.pair_of, t.tri_of, t.tri_mult, t.flag, t.blk, t.items, t.mscale,
+                  t.twp32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;

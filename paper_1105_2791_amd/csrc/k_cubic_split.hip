@@ -48,7 +48,7 @@ constexpr int BPW = 32;            // pair blocks per wave (one per lane-row)
 constexpr int MSS = KS + 4;        // map row stride in LDS (floats)
 constexpr int BSS = KS + 8;        // B row stride in LDS (16-bit)
 constexpr int BROWS = 64;          // B rows: row r <-> mode P - 64 + r (rows of negative modes are zero)
-constexpr int ESTEP = kMaxP * KS / NT;   // staged map values per thread per step (8)
+constexpr int QSTEP = kMaxP * KS / (4 * NT);   // staged pixel quads per thread per step (2)
 constexpr int CHAIN = 4;           // staged steps per MFMA accumulation chain (48 MFMAs per tile)
 
 // LDS slot of map row r: even rows first, then odd rows.  The lane-rows of a wave
@@ -111,17 +111,22 @@ __device__ inline void split_f16(const float* x, const float* y, f16x8& hi, f16x
   lo = __builtin_bit_cast(f16x8, l);
 }
 
+// hi/lo words of two B values (packed low half first); each split starts from one
+// rounded FP32 value
 template <int PREC>
-__device__ inline void store_split(float v, uint16_t* hi, uint16_t* lo) {
-  v = rounded(v);
+__device__ inline void split_pair(float v0, float v1, uint32_t& hi, uint32_t& lo) {
+  v0 = rounded(v0);
+  v1 = rounded(v1);
   if (PREC == MODAL_F16X3) {
-    const _Float16 h = (_Float16)v;
-    *hi = __builtin_bit_cast(uint16_t, h);
-    *lo = __builtin_bit_cast(uint16_t, (_Float16)(v - (float)h));
+    const _Float16 h0 = (_Float16)v0, h1 = (_Float16)v1;
+    const _Float16 r0 = (_Float16)(v0 - (float)h0), r1 = (_Float16)(v1 - (float)h1);
+    hi = (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+    lo = (uint32_t)__builtin_bit_cast(uint16_t, r0) | ((uint32_t)__builtin_bit_cast(uint16_t, r1) << 16);
   } else {
-    const uint32_t hb = bf16x2_bits(v, 0.f);
-    *hi = (uint16_t)(hb & 0xffffu);
-    *lo = (uint16_t)(bf16x2_bits(v - __builtin_bit_cast(float, hb << 16), 0.f) & 0xffffu);
+    uint32_t hb = bf16x2_bits(v0, v1);
+    asm("" : "+v"(hb));
+    hi = hb;
+    lo = bf16x2_bits(v0 - __builtin_bit_cast(float, hb << 16), v1 - __builtin_bit_cast(float, hb & 0xffff0000u));
   }
 }
 
@@ -130,7 +135,7 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
                                                     int nblk, int nitems, int ngroups, const int2* __restrict__ blocks,
                                                     const int2* __restrict__ items, const int* __restrict__ pair_of,
                                                     const float* __restrict__ maps, const float* __restrict__ w,
-                                                    const float* __restrict__ mscale, float wscale,
+                                                    const float* __restrict__ mscale, float wscale, int vec,
                                                     double* __restrict__ part) {
   constexpr bool F16 = PREC == MODAL_F16X3;
   typedef typename std::conditional<F16, f16x8, bf16x8>::type vec8;
@@ -186,31 +191,57 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
   const int x_begin = chunk * chunk_px;
   const int x_end = min(npix, x_begin + chunk_px);
 
-  // staging: thread owns map values e = tid + NT i -> (t = e / KS, xx = e % KS).  Loads
-  // are clamped in range and unconditional; past the chunk end w = 0 makes B = 0, so
-  // whatever A holds there contributes nothing.
-  float pre[ESTEP];
-  float wpre;
-  const int sxx = tid % KS;
+  // staging: thread owns quads e = tid + NT i -> (mode t = e / 16, pixels 4 (e % 16) .. + 3).
+  // Loads are float4 when rows are 16-byte aligned (npix % 4 == 0; chunks start at
+  // multiples of 64 pixels, so a quad is then wholly inside or wholly past the chunk
+  // end), element-wise otherwise; indices are clamped in range and the loads are
+  // unconditional.  Past the chunk end w = 0 makes B = 0, so whatever A holds there
+  // contributes nothing.  Rows t >= P (whole waves when P % 4 == 0) stage nothing.
+  float4 pre[QSTEP];
+  float4 wpre;
+  const int sq4 = 4 * (tid % 16);
   auto load_step = [&](int x0) {
-    const int x = x0 + sxx;
-    const int xc = min(x, x_end - 1);
-    const float wv_ = w[xc];
-    wpre = x < x_end ? wv_ : 0.f;
+    const int x = x0 + sq4;
+    if (vec) {
+      const int xc = min(x, x_end - 4);
+      const float4 wv_ = *reinterpret_cast<const float4*>(w + xc);
+      wpre = x < x_end ? wv_ : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-    for (int i = 0; i < ESTEP; ++i) {
-      const int t = min((tid + NT * i) / KS, P - 1);
-      pre[i] = Msky[(size_t)t * npix + xc];
+      for (int i = 0; i < QSTEP; ++i) {
+        const int t = min((tid + NT * i) / 16, P - 1);
+        pre[i] = *reinterpret_cast<const float4*>(Msky + (size_t)t * npix + xc);
+      }
+    } else {
+      float wq[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int xc = min(x + k, x_end - 1);
+        const float wv_ = w[xc];
+        wq[k] = x + k < x_end ? wv_ : 0.f;
+      }
+      wpre = make_float4(wq[0], wq[1], wq[2], wq[3]);
+#pragma unroll
+      for (int i = 0; i < QSTEP; ++i) {
+        const float* row = Msky + (size_t)min((tid + NT * i) / 16, P - 1) * npix;
+        pre[i] = make_float4(row[min(x, x_end - 1)], row[min(x + 1, x_end - 1)], row[min(x + 2, x_end - 1)],
+                             row[min(x + 3, x_end - 1)]);
+      }
     }
   };
   auto store_step = [&](int st) {
 #pragma unroll
-    for (int i = 0; i < ESTEP; ++i) {
-      const int t = (tid + NT * i) / KS;
+    for (int i = 0; i < QSTEP; ++i) {
+      const int t = (tid + NT * i) / 16;
       if (t < P) {
-        L.ms[st][ms_slot(t)][sxx] = pre[i] * msc[t];
-        const float sc = F16 ? msc[t] * wscale : 1.f;
-        store_split<PREC>(wpre * sc * pre[i], &L.bh[st][BROWS - P + t][sxx], &L.bl[st][BROWS - P + t][sxx]);
+        const float m = msc[t];
+        const float sc = F16 ? m * wscale : 1.f;
+        *reinterpret_cast<float4*>(&L.ms[st][ms_slot(t)][sq4]) =
+            make_float4(pre[i].x * m, pre[i].y * m, pre[i].z * m, pre[i].w * m);
+        uint32_t h0, l0, h1, l1;
+        split_pair<PREC>(wpre.x * sc * pre[i].x, wpre.y * sc * pre[i].y, h0, l0);
+        split_pair<PREC>(wpre.z * sc * pre[i].z, wpre.w * sc * pre[i].w, h1, l1);
+        *reinterpret_cast<uint2*>(&L.bh[st][BROWS - P + t][sq4]) = make_uint2(h0, h1);
+        *reinterpret_cast<uint2*>(&L.bl[st][BROWS - P + t][sq4]) = make_uint2(l0, l1);
       }
     }
   };
@@ -335,7 +366,7 @@ hipError_t launch_cubic_split(const modal_ctx* c, const void* maps, int S, int n
 #define LAUNCH(PR)                                                                                              \
   hipLaunchKernelGGL((k_cubic_split<PR>), dim3(grid), dim3(NT), lds, st, c->P, c->npairs, c->npix, S, nchunk,     \
                      chunk_px, c->t.nblk, c->t.nitems, ngroups, c->t.blk, c->t.items, c->t.pair_of,               \
-                     (const float*)maps, c->t.w32, c->t.mscale, c->wscale, part)
+                     (const float*)maps, c->t.w32, c->t.mscale, c->wscale, c->npix % 4 == 0 ? 1 : 0, part)
   if (c->prec == MODAL_F16X3) LAUNCH(MODAL_F16X3);
   else LAUNCH(MODAL_BF16X3);
 #undef LAUNCH

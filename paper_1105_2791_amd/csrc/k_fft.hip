@@ -14,6 +14,8 @@
 #include "common.h"
 
 #include <algorithm>
+#include <cmath>
+#include <vector>
 
 namespace modal {
 namespace {
@@ -301,14 +303,14 @@ __device__ inline void dft_plus(float2* x) {
   }
 }
 
-// one Stockham pass of radix R over the ring buffer b (length K, twiddle table tw of
-// the ring length N = 2 K: e^{2 pi i t / N})
+// one Stockham pass of radix R over the ring buffer b (length K); twp is this pass's
+// twiddle table, twp[(q - 1) Ns + k] = e^{2 pi i q k / (Ns R)}, laid out so that the
+// lanes of a wave (consecutive k) read consecutive entries
 // PTS: the most points a lane holds in any pass of the plan (register budget)
 template <int R, int PTS>
-__device__ inline void rg_pass(float2* b, int K, int Ns, int lane, const float2* tw) {
+__device__ inline void rg_pass(float2* b, int K, int Ns, int lane, const float2* twp) {
   constexpr int NB = (PTS + R - 1) / R;
   const int KR = K / R;
-  const int step = K / (Ns * R);
   float2 v[NB][R];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
@@ -324,7 +326,7 @@ __device__ inline void rg_pass(float2* b, int K, int Ns, int lane, const float2*
     if (bi < KR) {
       const int k = bi % Ns;
 #pragma unroll
-      for (int q = 1; q < R; ++q) v[i][q] = cmulf(v[i][q], tw[2 * (q * k * step)]);
+      for (int q = 1; q < R; ++q) v[i][q] = cmulf(v[i][q], twp[(q - 1) * Ns + k]);
       dft_plus<R>(v[i]);
       const int ob = (bi / Ns) * Ns * R + k;
 #pragma unroll
@@ -336,15 +338,18 @@ __device__ inline void rg_pass(float2* b, int K, int Ns, int lane, const float2*
 template <int PTS>
 __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int lmax, int ntheta, int nseq,
                                                               const float2* __restrict__ F, float* __restrict__ maps,
-                                                              const float2* __restrict__ twg) {
+                                                              const float2* __restrict__ twg,
+                                                              const float2* __restrict__ twpg) {
   extern __shared__ __attribute__((aligned(16))) float2 rbuf[];
   const int K = plan.K, N = plan.N;
   const int KP = pad16(K) + 1;
-  float2* tw = rbuf + RG_RINGS * KP;   // e^{2 pi i t / N}, t < N, shared by the workgroup's rings
+  float2* tw = rbuf + RG_RINGS * KP;   // e^{2 pi i t / N}, t < K, shared by the workgroup's rings
+  float2* twp = tw + K;                  // the passes' twiddle tables, K - 1 entries in all
   const int nrb8 = f_ring_blocks(ntheta);
   const int units = nseq * nrb8;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  for (int t = tid; t < N; t += 64 * RG_RINGS) tw[t] = twg[t];
+  for (int t = tid; t < K; t += 64 * RG_RINGS) tw[t] = twg[t];
+  for (int t = tid; t < K - 1; t += 64 * RG_RINGS) twp[t] = twpg[t];
   // persistent: workgroups b and b + 8 (one XCD) take the two halves of the same ring
   // groups, xcd + 8 (slot + k nslot), k = 0, 1, ...
   const int b = blockIdx.x;
@@ -400,13 +405,15 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int 
     }
     // z = sum_m Z_m e^{+2 pi i m n / K}
     int Ns = 1;
+    const float2* tf = twp;
     for (int f = 0; f < plan.nf; ++f) {
       const int R = plan.radix[f];
-      if (R == 8) rg_pass<8, PTS>(bw, K, Ns, lane, tw);
-      else if (R == 4) rg_pass<4, PTS>(bw, K, Ns, lane, tw);
-      else if (R == 2) rg_pass<2, PTS>(bw, K, Ns, lane, tw);
-      else if (R == 3) rg_pass<3, PTS>(bw, K, Ns, lane, tw);
-      else rg_pass<5, PTS>(bw, K, Ns, lane, tw);
+      if (R == 8) rg_pass<8, PTS>(bw, K, Ns, lane, tf);
+      else if (R == 4) rg_pass<4, PTS>(bw, K, Ns, lane, tf);
+      else if (R == 2) rg_pass<2, PTS>(bw, K, Ns, lane, tf);
+      else if (R == 3) rg_pass<3, PTS>(bw, K, Ns, lane, tf);
+      else rg_pass<5, PTS>(bw, K, Ns, lane, tf);
+      tf += (R - 1) * Ns;
       Ns *= R;
     }
     // M_{2n} = Re z_n, M_{2n+1} = Im z_n
@@ -453,6 +460,25 @@ bool fft_plan_rg(int N, FftPlan& p) {
   return fft_rg_points(p) <= 48;
 }
 
+// The register kernel's per-pass twiddles, in pass order: for the pass of radix R
+// after Ns points, e^{2 pi i q k / (Ns R)} at (q - 1) Ns + k, q = 1..R-1, k < Ns
+// (K - 1 entries in all: the (R - 1) Ns telescope to K - 1).
+std::vector<float> fft_rg_twiddles(const FftPlan& p) {
+  std::vector<float> out;
+  int Ns = 1;
+  for (int f = 0; f < p.nf; ++f) {
+    const int R = p.radix[f];
+    for (int q = 1; q < R; ++q)
+      for (int k = 0; k < Ns; ++k) {
+        const double a = 2.0 * 3.14159265358979323846 * (double)(q * k) / (double)(Ns * R);
+        out.push_back((float)std::cos(a));
+        out.push_back((float)std::sin(a));
+      }
+    Ns *= R;
+  }
+  return out;
+}
+
 // the most points one lane holds in a pass: ceil(K / R / 64) R
 int fft_rg_points(const FftPlan& p) {
   int pts = 0;
@@ -462,7 +488,7 @@ int fft_rg_points(const FftPlan& p) {
 
 size_t fft_rg_lds(const modal_ctx* c) {
   const int K = c->fft.K;
-  return ((size_t)RG_RINGS * (K + (K >> 4) + 1) + (size_t)2 * K) * sizeof(float2);
+  return ((size_t)RG_RINGS * (K + (K >> 4) + 1) + (size_t)2 * K - 1) * sizeof(float2);
 }
 
 hipError_t fft_rg_set_lds(size_t bytes) {
@@ -483,7 +509,8 @@ hipError_t launch_fft_c2r(const modal_ctx* c, const void* F, int S, void* maps, 
     const int pts = fft_rg_points(c->fft_rg_plan);
 #define LAUNCH(PT)                                                                                                \
   hipLaunchKernelGGL(k_fft_c2r_rg<PT>, dim3(blocks), dim3(64 * RG_RINGS), fft_rg_lds(c), st, c->fft_rg_plan,        \
-                     c->lmax, c->ntheta, nseq, (const float2*)F, (float*)maps, (const float2*)c->t.tw32)
+                     c->lmax, c->ntheta, nseq, (const float2*)F, (float*)maps, (const float2*)c->t.tw32,        \
+                     (const float2*)c->t.twp32)
     if (pts <= 16) LAUNCH(16);
     else if (pts <= 24) LAUNCH(24);
     else if (pts <= 32) LAUNCH(32);
