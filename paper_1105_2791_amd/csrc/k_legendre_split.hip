@@ -76,20 +76,28 @@ __device__ inline void split2(float v0, float v1, uint32_t& hi, uint32_t& lo) {
 // 64 recurrence steps of one lane's ring from l0, split into hi/lo words: Lh/Ll
 // [par][ks][half][k] hold l-indices 16 ks + 8 half + 2 k and + 1 of parity par.
 // 16 steps at a time fill l-indices 8 g .. 8 g + 7 of both parities (ks = g / 2, half = g % 2).
+// wave-uniform value of lane t of a register pair (lo, hi) as a double
+__device__ inline double lane_double(uint32_t lo, uint32_t hi, int t) {
+  const uint64_t v = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)lo, t) |
+                     ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)hi, t) << 32);
+  return __builtin_bit_cast(double, v);
+}
+
 template <int PREC, bool FAST>
-__device__ inline void lambda_chunk(int l0, int m, int lmax, const double2* __restrict__ rc, double xx, int ls,
+__device__ inline void lambda_chunk(int l0, int m, int lmax, const uint32_t (&rr)[4], double xx, int ls,
                                     double s0, double s1, double& l1, double& l2, uint32_t (&Lh)[2][2][2][4],
                                     uint32_t (&Ll)[2][2][2][4]) {
-  // rc = (A, B) of l0 .. l0 + 63 for this m: wave-uniform, constant offsets, so the
-  // coefficients arrive as wide scalar loads (the table is padded past the last m)
+  // rr: lane t holds (A, B) of l0 + t for this m (one vector load per lane per chunk,
+  // issued with the coefficient loads); each step reads its pair back as wave-uniform
+  // values, so the recurrence never waits on the scalar cache
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
     float lam[2][8];
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
       const int l = l0 + 16 * g + t;
-      const double2 r = rc[16 * g + t];
-      double v = fma(r.x * xx, l1, -r.y * l2);
+      const double A = lane_double(rr[0], rr[1], 16 * g + t), B = lane_double(rr[2], rr[3], 16 * g + t);
+      double v = fma(A * xx, l1, -B * l2);
       if (!FAST) {
         v = (l < ls) ? 0.0 : v;
         v = (l == ls) ? s0 : v;
@@ -156,30 +164,68 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[a][b][c][r] = 0.f;
 
+  // this thread's coefficient column (col, quarter q): pointers offset so that element l
+  // of the column is pa2[l] (a_{s,lm}, of which the column takes Re or Im) and pq[l]
+  // (qw_p(l)) for l = 16 q + i of a chunk starting at 0; a chunk at l0 adds l0
+  const int ccol = tid >> 2, cq = tid & 3;
+  const bool col_ok = c0 + ccol < ncols;
+  const float2* pa2;
+  const float* pq;
+  const int creim = min(c0 + ccol, ncols - 1) & 1;
+  {
+    const int sq = min(c0 + ccol, ncols - 1) >> 1;
+    const int s = sq / P, p = sq - s * P;
+    pa2 = alm + (size_t)s * nalm + off + 16 * cq - m;
+    pq = qw + (size_t)p * (lmax + 1) + 16 * cq;
+  }
+
   // chunks start at l = m + 64 k so that parity(l - m) = parity(l - l0)
   const int kfirst = (lmin > m) ? (lmin - m) / LCH : 0;
   for (int l0 = m + kfirst * LCH; l0 <= lmax; l0 += LCH) {
     // ---- coefficient tile: thread (col, quarter) fills 16 consecutive l of one column.
-    //      All 16 pairs of loads are unconditional (index clamped, value selected after)
-    //      so that they are in flight together.
+    //      All 16 pairs of loads are unconditional (index clamped in the last chunk, value
+    //      selected after) so that they are in flight together.
     __syncthreads();
+    // recurrence coefficients of this chunk, lane t <- (A, B) of l0 + t (the table is
+    // padded past the last m, so l0 + 63 may run past lmax)
+    uint32_t rr[4];
     {
-      const int col = tid >> 2, q = tid & 3;
-      const int cg = min(c0 + col, ncols - 1);
-      const int sq = cg >> 1, reim = cg & 1;
-      const int s = sq / P, p = sq - s * P;
-      const float* as = reinterpret_cast<const float*>(alm + (size_t)s * nalm + off) + reim;
-      const float* qp = qw + (size_t)p * (lmax + 1);
+      const uint4 r4 = *reinterpret_cast<const uint4*>(rec + 2 * (off + (size_t)(l0 - m + lane)));
+      rr[0] = r4.x;
+      rr[1] = r4.y;
+      rr[2] = r4.z;
+      rr[3] = r4.w;
+    }
+    {
+      const int col = ccol, q = cq;
       float va[16], vq[16];
+      if (l0 + LCH - 1 <= lmax) {   // wave-uniform: one base, immediate offsets
+        const float2* a = pa2 + l0;
+        const float* b = pq + l0;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int l = min(l0 + 16 * q + i, lmax);
-        va[i] = as[2 * (l - m)];
-        vq[i] = qp[l];
+        for (int i = 0; i < 16; ++i) {
+          const float2 av = a[i];
+          va[i] = creim ? av.y : av.x;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {   // 8-byte loads (4-byte aligned): pairs of qw
+          float2 qv;
+          __builtin_memcpy(&qv, b + 2 * j, sizeof(qv));
+          vq[2 * j] = qv.x;
+          vq[2 * j + 1] = qv.y;
+        }
+      } else {
+        const float* pa = reinterpret_cast<const float*>(pa2) + creim;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int li = min(l0 + 16 * q + i, lmax) - 16 * q;
+          va[i] = pa[2 * li];
+          vq[i] = pq[li];
+        }
       }
       float v[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = (c0 + col < ncols && l0 + 16 * q + i <= lmax) ? vq[i] * va[i] : 0.f;
+      for (int i = 0; i < 16; ++i) v[i] = (col_ok && l0 + 16 * q + i <= lmax) ? vq[i] * va[i] : 0.f;
       // l = l0 + 16 q + i has parity i & 1 and index 8 q + i / 2
       uint32_t h[2][4], lw[2][4];
 #pragma unroll
@@ -197,13 +243,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     //      [par][ks][half][k] holds l-indices 16 ks + 8 half + 2 k, + 1
     uint32_t Lh[2][2][2][4], Ll[2][2][2][4];
     {
-      const double2* rc = reinterpret_cast<const double2*>(rec) + off + (l0 - m);
       // wave-uniform: every lane is past its seeds and the chunk ends inside l <= lmax,
       // so the steps need no selects (the general form handles seeds and the tail)
       if (l0 > wls + 1 && l0 + LCH - 1 <= lmax) {
-        lambda_chunk<PREC, true>(l0, m, lmax, rc, xx, ls, s0, s1, l1, l2, Lh, Ll);
+        lambda_chunk<PREC, true>(l0, m, lmax, rr, xx, ls, s0, s1, l1, l2, Lh, Ll);
       } else {
-        lambda_chunk<PREC, false>(l0, m, lmax, rc, xx, ls, s0, s1, l1, l2, Lh, Ll);
+        lambda_chunk<PREC, false>(l0, m, lmax, rr, xx, ls, s0, s1, l1, l2, Lh, Ll);
       }
       // hand half 1 of lanes 0-31 and half 0 of lanes 32-63 across: afterwards
       // half 0 is the ring tile 0 operand and half 1 the ring tile 1 operand
@@ -236,9 +281,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
-          f32x16 t;
-#pragma unroll
-          for (int r = 0; r < 16; ++r) t[r] = 0.f;
+          f32x16& t = acc[par][rt][ct];
 #pragma unroll
           for (int ks = 0; ks < 2; ++ks) {
             const u32x4 hv = {Lh[par][ks][rt][0], Lh[par][ks][rt][1], Lh[par][ks][rt][2], Lh[par][ks][rt][3]};
@@ -255,7 +298,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
               t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[ks], t, 0, 0, 0);
             }
           }
-          acc[par][rt][ct] += t;
         }
       }
   }
