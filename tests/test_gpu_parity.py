@@ -18,10 +18,10 @@ pytestmark = pytest.mark.gpu
 # sanity bounds that catch layout or operand mistakes, the measured errors are
 # logged per result
 TOL = {"f64": 1e-10, "f32": 1e-5, "bf16x3": 1e-3, "f16x3": 1e-4}
-# maps: FP32 synthesis is held to 1e-5; the split-bf16 synthesis (3 products per
-# term, about 2^-16 relative per product) is held to the 1e-4 sanity bound and its
-# measured error is logged
-MAP_TOL = {"f64": 1e-10, "f32": 1e-5, "bf16x3": 1e-3, "f16x3": 1e-4}
+# maps, pair means and gradients (no cubic cancellation): FP32 synthesis is held to
+# 1e-5, split-fp16 (about 2^-22 per operand) to 1e-5 and split-bf16 (3 products per
+# term, about 2^-16 relative per product; 2-4e-5 measured) to 1e-4
+MAP_TOL = {"f64": 1e-10, "f32": 1e-5, "bf16x3": 1e-4, "f16x3": 1e-5}
 
 torch = pytest.importorskip("torch")
 
