@@ -75,7 +75,6 @@ __device__ inline void split2(float v0, float v1, uint32_t& hi, uint32_t& lo) {
 
 // 64 recurrence steps of one lane's ring from l0, split into hi/lo words: Lh/Ll
 // [par][ks][half][k] hold l-indices 16 ks + 8 half + 2 k and + 1 of parity par.
-// 16 steps at a time fill l-indices 8 g .. 8 g + 7 of both parities (ks = g / 2, half = g % 2).
 // wave-uniform value of lane t of a register pair (lo, hi) as a double
 __device__ inline double lane_double(uint32_t lo, uint32_t hi, int t) {
   const uint64_t v = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)lo, t) |
@@ -91,12 +90,14 @@ __device__ inline void lambda_chunk(int l0, int m, int lmax, const uint32_t (&rr
   // issued with the coefficient loads); each step reads its pair back as wave-uniform
   // values, so the recurrence never waits on the scalar cache
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    float lam[2][8];
+  for (int g = 0; g < 8; ++g) {
+    // 8 steps: l-indices 4 g .. 4 g + 3 of each parity, i.e. [ks = g / 4][half = (g / 2) % 2]
+    // at k = 2 (g % 2) and 2 (g % 2) + 1
+    float lam[2][4];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int l = l0 + 16 * g + t;
-      const double A = lane_double(rr[0], rr[1], 16 * g + t), B = lane_double(rr[2], rr[3], 16 * g + t);
+    for (int t = 0; t < 8; ++t) {
+      const int l = l0 + 8 * g + t;
+      const double A = lane_double(rr[0], rr[1], 8 * g + t), B = lane_double(rr[2], rr[3], 8 * g + t);
       double v = fma(A * xx, l1, -B * l2);
       if (!FAST) {
         v = (l < ls) ? 0.0 : v;
@@ -110,8 +111,9 @@ __device__ inline void lambda_chunk(int l0, int m, int lmax, const uint32_t (&rr
 #pragma unroll
     for (int par = 0; par < 2; ++par)
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        split2<PREC>(lam[par][2 * k], lam[par][2 * k + 1], Lh[par][g >> 1][g & 1][k], Ll[par][g >> 1][g & 1][k]);
+      for (int k = 0; k < 2; ++k)
+        split2<PREC>(lam[par][2 * k], lam[par][2 * k + 1], Lh[par][g >> 2][(g >> 1) & 1][2 * (g & 1) + k],
+                     Ll[par][g >> 2][(g >> 1) & 1][2 * (g & 1) + k]);
   }
 }
 
@@ -181,61 +183,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 
   // chunks start at l = m + 64 k so that parity(l - m) = parity(l - l0)
   const int kfirst = (lmin > m) ? (lmin - m) / LCH : 0;
+  // recurrence coefficients of a chunk, lane t <- (A, B) of l0 + t (the table is padded
+  // past the last m, so l0 + 63 may run past lmax); loaded one chunk ahead
+  uint32_t rr[4];
+  auto load_rr = [&](int l0n) {
+    const uint4 r4 = *reinterpret_cast<const uint4*>(rec + 2 * (off + (size_t)(l0n - m + lane)));
+    rr[0] = r4.x;
+    rr[1] = r4.y;
+    rr[2] = r4.z;
+    rr[3] = r4.w;
+  };
+  if (m + kfirst * LCH <= lmax) load_rr(m + kfirst * LCH);
+
   for (int l0 = m + kfirst * LCH; l0 <= lmax; l0 += LCH) {
-    // ---- coefficient tile: thread (col, quarter) fills 16 consecutive l of one column.
-    //      All 16 pairs of loads are unconditional (index clamped in the last chunk, value
-    //      selected after) so that they are in flight together.
     __syncthreads();
-    // recurrence coefficients of this chunk, lane t <- (A, B) of l0 + t (the table is
-    // padded past the last m, so l0 + 63 may run past lmax)
-    uint32_t rr[4];
-    {
-      const uint4 r4 = *reinterpret_cast<const uint4*>(rec + 2 * (off + (size_t)(l0 - m + lane)));
-      rr[0] = r4.x;
-      rr[1] = r4.y;
-      rr[2] = r4.z;
-      rr[3] = r4.w;
-    }
-    {
-      const int col = ccol, q = cq;
-      float va[16], vq[16];
-      if (l0 + LCH - 1 <= lmax) {   // wave-uniform: one base, immediate offsets
-        const float2* a = pa2 + l0;
-        const float* b = pq + l0;
+    // ---- coefficient loads: thread (col, quarter) takes 16 consecutive l of one column.
+    //      All 16 pairs are unconditional (index clamped in the last chunk, value selected
+    //      after) and in flight together while the recurrence below runs.
+    const int col = ccol, q = cq;
+    float va[16], vq[16];
+    const float* pa = reinterpret_cast<const float*>(pa2) + creim;
+    if (l0 + LCH - 1 <= lmax) {   // wave-uniform: one base, immediate offsets
+      const float* a = pa + 2 * l0;
+      const float* b = pq + l0;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const float2 av = a[i];
-          va[i] = creim ? av.y : av.x;
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {   // 8-byte loads (4-byte aligned): pairs of qw
-          float2 qv;
-          __builtin_memcpy(&qv, b + 2 * j, sizeof(qv));
-          vq[2 * j] = qv.x;
-          vq[2 * j + 1] = qv.y;
-        }
-      } else {
-        const float* pa = reinterpret_cast<const float*>(pa2) + creim;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int li = min(l0 + 16 * q + i, lmax) - 16 * q;
-          va[i] = pa[2 * li];
-          vq[i] = pq[li];
-        }
+      for (int i = 0; i < 16; ++i) {
+        va[i] = a[2 * i];
+        vq[i] = b[i];
       }
-      float v[16];
+    } else {
+      // the last chunk of an m: clamped indices, and the product is formed here (vq = 1),
+      // which also keeps this path from being merged with the one above
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = (col_ok && l0 + 16 * q + i <= lmax) ? vq[i] * va[i] : 0.f;
-      // l = l0 + 16 q + i has parity i & 1 and index 8 q + i / 2
-      uint32_t h[2][4], lw[2][4];
-#pragma unroll
-      for (int par = 0; par < 2; ++par)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) split2<PREC>(v[4 * k + par], v[4 * k + 2 + par], h[par][k], lw[par][k]);
-#pragma unroll
-      for (int par = 0; par < 2; ++par) {
-        *reinterpret_cast<u32x4*>(&C.h[par][col][8 * q]) = u32x4{h[par][0], h[par][1], h[par][2], h[par][3]};
-        *reinterpret_cast<u32x4*>(&C.l[par][col][8 * q]) = u32x4{lw[par][0], lw[par][1], lw[par][2], lw[par][3]};
+      for (int i = 0; i < 16; ++i) {
+        const int li = min(l0 + 16 * q + i, lmax) - 16 * q;
+        va[i] = pq[li] * pa[2 * li];
+        vq[i] = 1.f;
       }
     }
 
@@ -265,6 +248,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             Ll[par][ks][0][k] = sl[0];
             Ll[par][ks][1][k] = sl[1];
           }
+    }
+    if (l0 + LCH <= lmax) load_rr(l0 + LCH);
+
+    // ---- coefficient tile: qw_p(l) Re/Im a_lm, split, stored; l = l0 + 16 q + i has
+    //      parity i & 1 and index 8 q + i / 2 (zero past lmax and for padding columns)
+    {
+      float v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = (col_ok && l0 + 16 * q + i <= lmax) ? vq[i] * va[i] : 0.f;
+      uint32_t h[2][4], lw[2][4];
+#pragma unroll
+      for (int par = 0; par < 2; ++par)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) split2<PREC>(v[4 * k + par], v[4 * k + 2 + par], h[par][k], lw[par][k]);
+#pragma unroll
+      for (int par = 0; par < 2; ++par) {
+        *reinterpret_cast<u32x4*>(&C.h[par][col][8 * q]) = u32x4{h[par][0], h[par][1], h[par][2], h[par][3]};
+        *reinterpret_cast<u32x4*>(&C.l[par][col][8 * q]) = u32x4{lw[par][0], lw[par][1], lw[par][2], lw[par][3]};
+      }
     }
     __syncthreads();
 
