@@ -95,6 +95,12 @@ __host__ __device__ inline size_t f_index(int seq, int ring, int m, int lmax, in
   return (((size_t)seq * nrb8 + (ring >> 3)) * (size_t)(lmax + 1) + m) * 8 + (ring & 7);
 }
 
+// Workgroup barrier that orders LDS only: this wave's LDS operations complete, then all
+// waves meet.  Unlike __syncthreads() it does not wait for outstanding global stores,
+// for loops whose workgroup never reads back what it stored.  The memory clobber keeps
+// the compiler from moving memory operations across it.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // ---- launchers (defined in the .hip files); all return hipSuccess or the error
 hipError_t launch_seeds(const modal_ctx* c, const double* logpref, hipStream_t st);
 

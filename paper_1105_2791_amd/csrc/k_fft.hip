@@ -357,7 +357,9 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int 
   const int nslot = gridDim.x >> 4;
   for (int unit = xcd + 8 * slot; unit < units; unit += 8 * nslot) {
     const int seq = unit / nrb8, rb = unit - seq * nrb8;
-    __syncthreads();   // previous unit's buffers (and the twiddle table) are settled
+    // previous unit's buffers (and the twiddle table) are settled; its map stores stay in
+    // flight (the workgroup never reads them back)
+    lds_barrier();
     // spectra of the four rings: F block of ring group rb, rings 4 half .. 4 half + 3
     // float4 = rings (2 rp, 2 rp + 1) at one m; 8 loads in flight per thread per round
     const float4* src = reinterpret_cast<const float4*>(F + (size_t)unit * (lmax + 1) * 8 + RG_RINGS * half);
@@ -365,9 +367,9 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int 
     for (int e0 = 0; e0 < nv; e0 += 8 * 64 * RG_RINGS) {
       float4 x[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int e = e0 + tid + i * 64 * RG_RINGS;
-        if (e < nv) x[i] = src[(size_t)(e >> 1) * 4 + (e & 1)];
+      for (int i = 0; i < 8; ++i) {   // unconditional (index clamped): no load left pending
+        const int e = min(e0 + tid + i * 64 * RG_RINGS, nv - 1);
+        x[i] = src[(size_t)(e >> 1) * 4 + (e & 1)];
       }
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
