@@ -324,7 +324,7 @@ int chunk_px_for(const modal_ctx* c, int target) {
   // nchunk a multiple of 8 (one chunk stream per XCD), chunks of about target pixels
   int nchunk = 8 * ((c->npix + 8 * target - 1) / (8 * target));
   int px = (c->npix + nchunk - 1) / nchunk;
-  px = (px + 63) / 64 * 64;   // whole staged steps of both matrix-core kernels
+  px = (px + 127) / 128 * 128;   // whole staged steps of both matrix-core kernels (64, 128 pixels)
   return px;
 }
 

@@ -16,7 +16,7 @@
 //     32 blocks with one 32-mode tile: the last 32 modes [P-32, P) always, and the
 //     32 before them only when the group's smallest b0 is below P - 32 (for P = 40
 //     that is one extra item; every wave runs one item);
-//   * maps and the split B operand of a 64-pixel step are staged in LDS, double
+//   * maps and the split B operand of a 128-pixel step are staged in LDS, double
 //     buffered, with the next step's global loads issued before this step's MFMAs
 //     (a step is long enough to cover the load latency).
 // Precisions
@@ -41,15 +41,15 @@ typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
 
-constexpr int KS = 64;             // pixels per staged step (four MFMA K = 16 substeps)
+constexpr int KS = 128;            // pixels per staged step (eight MFMA K = 16 substeps)
 constexpr int NW = 8;              // waves per workgroup
 constexpr int NT = 64 * NW;
 constexpr int BPW = 32;            // pair blocks per wave (one per lane-row)
 constexpr int MSS = KS + 4;        // map row stride in LDS (floats)
 constexpr int BSS = KS + 8;        // B row stride in LDS (16-bit)
 constexpr int BROWS = 64;          // B rows: row r <-> mode P - 64 + r (rows of negative modes are zero)
-constexpr int QSTEP = kMaxP * KS / (4 * NT);   // staged pixel quads per thread per step (2)
-constexpr int CHAIN = 4;           // staged steps per MFMA accumulation chain (48 MFMAs per tile)
+constexpr int QSTEP = kMaxP * KS / (4 * NT);   // staged pixel quads per thread per step (4)
+constexpr int CHAIN = 2;           // staged steps per MFMA accumulation chain (48 MFMAs per tile)
 
 // LDS slot of map row r: even rows first, then odd rows.  The lane-rows of a wave
 // read rows a0 (even, consecutive blocks) and a0 + 1, so consecutive even rows land
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
   const int x_begin = chunk * chunk_px;
   const int x_end = min(npix, x_begin + chunk_px);
 
-  // staging: thread owns quads e = tid + NT i -> (mode t = e / 16, pixels 4 (e % 16) .. + 3).
+  // staging: thread owns quads e = tid + NT i -> (mode t = e / (KS / 4), pixels 4 (e % (KS / 4)) .. + 3).
   // Loads are float4 when rows are 16-byte aligned (npix % 4 == 0; chunks start at
   // multiples of 64 pixels, so a quad is then wholly inside or wholly past the chunk
   // end), element-wise otherwise; indices are clamped in range and the loads are
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
   // contributes nothing.  Rows t >= P (whole waves when P % 4 == 0) stage nothing.
   float4 pre[QSTEP];
   float4 wpre;
-  const int sq4 = 4 * (tid % 16);
+  const int sq4 = 4 * (tid % (KS / 4));
   auto load_step = [&](int x0) {
     const int x = x0 + sq4;
     if (vec) {
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
       wpre = x < x_end ? wv_ : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
       for (int i = 0; i < QSTEP; ++i) {
-        const int t = min((tid + NT * i) / 16, P - 1);
+        const int t = min((tid + NT * i) / (KS / 4), P - 1);
         pre[i] = *reinterpret_cast<const float4*>(Msky + (size_t)t * npix + xc);
       }
     } else {
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
       wpre = make_float4(wq[0], wq[1], wq[2], wq[3]);
 #pragma unroll
       for (int i = 0; i < QSTEP; ++i) {
-        const float* row = Msky + (size_t)min((tid + NT * i) / 16, P - 1) * npix;
+        const float* row = Msky + (size_t)min((tid + NT * i) / (KS / 4), P - 1) * npix;
         pre[i] = make_float4(row[min(x, x_end - 1)], row[min(x + 1, x_end - 1)], row[min(x + 2, x_end - 1)],
                              row[min(x + 3, x_end - 1)]);
       }
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
   auto store_step = [&](int st) {
 #pragma unroll
     for (int i = 0; i < QSTEP; ++i) {
-      const int t = (tid + NT * i) / 16;
+      const int t = (tid + NT * i) / (KS / 4);
       if (t < P) {
         const float m = msc[t];
         const float sc = F16 ? m * wscale : 1.f;
