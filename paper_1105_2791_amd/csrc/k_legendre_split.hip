@@ -16,10 +16,11 @@
 //     their last 8, and one v_permlane32_swap per register hands the other halves
 //     across, so lambda never goes through LDS;
 //   * the workgroup stages the coefficient tile (hi/lo, padded rows) in LDS;
-//   * each wave runs 2 parities x 2 ring tiles x 2 column tiles, each a chain of
-//     2 K steps x (4 products for bf16: hi.hi + hi.lo + lo.hi + lo.lo, every map
-//     entering the cubic three times; 3 for fp16) from zero, added to the running
-//     FP32 sum on the VALU once per chunk.
+//   * each wave runs 2 parities x 2 ring tiles x 2 column tiles, accumulating
+//     2 K steps x 3 products (hi.hi + hi.lo + lo.hi; lo.lo is below the operand
+//     split error) per chunk in place: an output takes at most about 130
+//     accumulations, so the matrix core's addend truncation stays far below the split
+//     error.
 // Output goes through LDS so that F (f_index layout) is written in runs of rings.
 #include "common.h"
 
@@ -294,7 +295,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
               t = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl[ks], t, 0, 0, 0);
               t = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh[ks], t, 0, 0, 0);
             } else {
-              t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bl[ks], t, 0, 0, 0);
               t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[ks], t, 0, 0, 0);
               t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[ks], t, 0, 0, 0);
               t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[ks], t, 0, 0, 0);
