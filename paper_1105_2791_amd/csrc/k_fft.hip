@@ -239,7 +239,10 @@ __global__ __launch_bounds__(256) void k_fft_r2c(FftPlan plan, int lmax, int nth
 constexpr int RG_RINGS = 4;            // rings (waves) per workgroup
 constexpr int RG_KMAX = 2048;          // longest complex transform of the register kernel
 
-__device__ inline int pad16(int i) { return i + (i >> 4); }
+// LDS padding of the register-pass ring buffers: one slot after every 8 points, so that
+// the strided writes of the early passes and the interleaved spectrum stores hit
+// distinct banks
+__device__ inline int padr(int i) { return i + (i >> 3); }
 
 __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -317,7 +320,7 @@ __device__ inline void rg_pass(float2* b, int K, int Ns, int lane, const float2*
     const int bi = lane + 64 * i;
     if (bi < KR) {
 #pragma unroll
-      for (int q = 0; q < R; ++q) v[i][q] = b[pad16(bi + q * KR)];
+      for (int q = 0; q < R; ++q) v[i][q] = b[padr(bi + q * KR)];
     }
   }
 #pragma unroll
@@ -330,7 +333,7 @@ __device__ inline void rg_pass(float2* b, int K, int Ns, int lane, const float2*
       dft_plus<R>(v[i]);
       const int ob = (bi / Ns) * Ns * R + k;
 #pragma unroll
-      for (int q = 0; q < R; ++q) b[pad16(ob + q * Ns)] = v[i][q];
+      for (int q = 0; q < R; ++q) b[padr(ob + q * Ns)] = v[i][q];
     }
   }
 }
@@ -342,13 +345,13 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int 
                                                               const float2* __restrict__ twpg) {
   extern __shared__ __attribute__((aligned(16))) float2 rbuf[];
   const int K = plan.K, N = plan.N;
-  const int KP = pad16(K) + 1;
-  float2* tw = rbuf + RG_RINGS * KP;   // e^{2 pi i t / N}, t < K, shared by the workgroup's rings
-  float2* twp = tw + K;                  // the passes' twiddle tables, K - 1 entries in all
+  const int KP = padr(K) + 1;
+  float2* tw = rbuf + RG_RINGS * KP;   // e^{2 pi i t / N}, t <= K / 2, shared by the workgroup's rings
+  float2* twp = tw + K / 2 + 1;          // the passes' twiddle tables, K - 1 entries in all
   const int nrb8 = f_ring_blocks(ntheta);
   const int units = nseq * nrb8;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  for (int t = tid; t < K; t += 64 * RG_RINGS) tw[t] = twg[t];
+  for (int t = tid; t <= K / 2; t += 64 * RG_RINGS) tw[t] = twg[t];
   for (int t = tid; t < K - 1; t += 64 * RG_RINGS) twp[t] = twpg[t];
   // persistent: workgroups b and b + 8 (one XCD) take the two halves of the same ring
   // groups, xcd + 8 (slot + k nslot), k = 0, 1, ...
@@ -376,14 +379,14 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int 
         const int e = e0 + tid + i * 64 * RG_RINGS;
         if (e < nv) {
           const int m = e >> 1, r = 2 * (e & 1);
-          rbuf[r * KP + pad16(m)] = make_float2(x[i].x, m == 0 ? 0.f : x[i].y);
-          rbuf[(r + 1) * KP + pad16(m)] = make_float2(x[i].z, m == 0 ? 0.f : x[i].w);
+          rbuf[r * KP + padr(m)] = make_float2(x[i].x, m == 0 ? 0.f : x[i].y);
+          rbuf[(r + 1) * KP + padr(m)] = make_float2(x[i].z, m == 0 ? 0.f : x[i].w);
         }
       }
     }
     for (int e = tid; e < (K - lmax - 1) * RG_RINGS; e += 64 * RG_RINGS) {
       const int r = e / (K - lmax - 1), m = lmax + 1 + e % (K - lmax - 1);
-      rbuf[r * KP + pad16(m)] = make_float2(0.f, 0.f);
+      rbuf[r * KP + padr(m)] = make_float2(0.f, 0.f);
     }
     __syncthreads();
 
@@ -392,17 +395,17 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int 
     // the lane that owns m also owns K - m, so the update is in place
     for (int m = lane; m <= K / 2; m += 64) {
       const int m2 = K - m;
-      const float2 xm = bw[pad16(m)];
-      const float2 xk = (m > 0) ? bw[pad16(m2 % K)] : make_float2(0.f, 0.f);
+      const float2 xm = bw[padr(m)];
+      const float2 xk = (m > 0) ? bw[padr(m2 % K)] : make_float2(0.f, 0.f);
       {
         const float2 a = make_float2(xm.x + xk.x, xm.y - xk.y), d = make_float2(xm.x - xk.x, xm.y + xk.y);
         const float2 ew = tw[m];
-        bw[pad16(m)] = make_float2(a.x - (ew.x * d.y + ew.y * d.x), a.y + (ew.x * d.x - ew.y * d.y));
+        bw[padr(m)] = make_float2(a.x - (ew.x * d.y + ew.y * d.x), a.y + (ew.x * d.x - ew.y * d.y));
       }
       if (m > 0 && m2 != m) {
         const float2 a = make_float2(xk.x + xm.x, xk.y - xm.y), d = make_float2(xk.x - xm.x, xk.y + xm.y);
-        const float2 ew = tw[m2];
-        bw[pad16(m2)] = make_float2(a.x - (ew.x * d.y + ew.y * d.x), a.y + (ew.x * d.x - ew.y * d.y));
+        const float2 ew = make_float2(-tw[m].x, tw[m].y);   // e^{2 pi i (K - m) / N} = -conj(tw[m])
+        bw[padr(m2)] = make_float2(a.x - (ew.x * d.y + ew.y * d.x), a.y + (ew.x * d.x - ew.y * d.y));
       }
     }
     // z = sum_m Z_m e^{+2 pi i m n / K}
@@ -422,7 +425,7 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int 
     const int j = rb * 8 + RG_RINGS * half + w;
     if (j < ntheta) {
       float2* dst = reinterpret_cast<float2*>(maps + ((size_t)seq * ntheta + j) * plan.N);
-      for (int n = lane; n < K; n += 64) dst[n] = bw[pad16(n)];
+      for (int n = lane; n < K; n += 64) dst[n] = bw[padr(n)];
     }
   }
 }
@@ -490,7 +493,7 @@ int fft_rg_points(const FftPlan& p) {
 
 size_t fft_rg_lds(const modal_ctx* c) {
   const int K = c->fft.K;
-  return ((size_t)RG_RINGS * (K + (K >> 4) + 1) + (size_t)2 * K - 1) * sizeof(float2);
+  return ((size_t)RG_RINGS * (K + (K >> 3) + 1) + (size_t)(K / 2 + 1) + (size_t)(K - 1)) * sizeof(float2);
 }
 
 hipError_t fft_rg_set_lds(size_t bytes) {
