@@ -303,6 +303,34 @@ __device__ inline void dft_plus(float2* x) {
     x[4] = csub(a1, b1);
     x[2] = cadd(a2, b2);
     x[3] = csub(a2, b2);
+  } else if (R == 24) {
+    // 24 = 3 x 8 (Cooley-Tukey): input index 8 n1 + n2, output index k1 + 3 k2;
+    //   y[k1][n2] = e^{2 pi i n2 k1 / 24} sum_n1 x[8 n1 + n2] e^{2 pi i n1 k1 / 3},
+    //   X[k1 + 3 k2] = sum_n2 y[k1][n2] e^{2 pi i n2 k2 / 8}.
+    // e^{i pi j / 12} = (cos 15 j deg, sin 15 j deg), j = n2 k1 <= 14
+    const float cw[15] = {1.f, 0.96592582628906829f, 0.86602540378443865f, 0.70710678118654752f, 0.5f,
+                          0.25881904510252076f, 0.f, -0.25881904510252076f, -0.5f, -0.70710678118654752f,
+                          -0.86602540378443865f, -0.96592582628906829f, -1.f, -0.96592582628906829f,
+                          -0.86602540378443865f};
+    const float sw[15] = {0.f, 0.25881904510252076f, 0.5f, 0.70710678118654752f, 0.86602540378443865f,
+                          0.96592582628906829f, 1.f, 0.96592582628906829f, 0.86602540378443865f,
+                          0.70710678118654752f, 0.5f, 0.25881904510252076f, 0.f, -0.25881904510252076f, -0.5f};
+    float2 y[3][8];
+#pragma unroll
+    for (int n2 = 0; n2 < 8; ++n2) {
+      float2 t[3] = {x[n2], x[8 + n2], x[16 + n2]};
+      dft_plus<3>(t);
+      y[0][n2] = t[0];
+#pragma unroll
+      for (int k1 = 1; k1 < 3; ++k1)
+        y[k1][n2] = (n2 == 0) ? t[k1] : cmulf(t[k1], make_float2(cw[n2 * k1], sw[n2 * k1]));
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      dft_plus<8>(y[k1]);
+#pragma unroll
+      for (int k2 = 0; k2 < 8; ++k2) x[k1 + 3 * k2] = y[k1][k2];
+    }
   }
 }
 
@@ -413,7 +441,8 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int 
     const float2* tf = twp;
     for (int f = 0; f < plan.nf; ++f) {
       const int R = plan.radix[f];
-      if (R == 8) rg_pass<8, PTS>(bw, K, Ns, lane, tf);
+      if (R == 24) rg_pass<24, PTS>(bw, K, Ns, lane, tf);
+      else if (R == 8) rg_pass<8, PTS>(bw, K, Ns, lane, tf);
       else if (R == 4) rg_pass<4, PTS>(bw, K, Ns, lane, tf);
       else if (R == 2) rg_pass<2, PTS>(bw, K, Ns, lane, tf);
       else if (R == 3) rg_pass<3, PTS>(bw, K, Ns, lane, tf);
@@ -445,8 +474,9 @@ int fft_rings_per_block(const modal_ctx* c) {
   return (c->tune_fft_rings > 0 && c->tune_fft_rings <= R) ? c->tune_fft_rings : R;
 }
 
-// The register kernel's plan: radices 8, 4, 2, 3, 5 (largest first); false if the
-// ring length has other factors or exceeds the register kernel's size.
+// The register kernel's plan: 24 first where it fits, then radices 8, 4, 2, 3, 5
+// (largest first); false if the ring length has other factors or exceeds the
+// register kernel's size.
 int fft_rg_points(const FftPlan& p);
 
 bool fft_plan_rg(int N, FftPlan& p) {
@@ -455,6 +485,12 @@ bool fft_plan_rg(int N, FftPlan& p) {
   p.nf = 0;
   if (p.K > RG_KMAX || p.K < 1) return false;
   int K = p.K;
+  // a first radix-24 pass (a 24-point DFT in registers) saves one LDS round trip when a
+  // pass of 24 points per lane still keeps every lane of the wave busy
+  if (K % 24 == 0 && K / 24 >= 64) {
+    p.radix[p.nf++] = 24;
+    K /= 24;
+  }
   for (int r : {8, 4, 2, 3, 5})
     while (K % r == 0) {
       if (p.nf >= kMaxFactors) return false;
