@@ -391,51 +391,46 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int 
     // previous unit's buffers (and the twiddle table) are settled; its map stores stay in
     // flight (the workgroup never reads them back)
     lds_barrier();
-    // spectra of the four rings: F block of ring group rb, rings 4 half .. 4 half + 3
-    // float4 = rings (2 rp, 2 rp + 1) at one m; 8 loads in flight per thread per round
+    // spectra of the four rings (F block of ring group rb, rings 4 half .. 4 half + 3;
+    // float4 = rings (2 rp, 2 rp + 1) at one m) go straight into the buffers as the input
+    // of the half-length complex transform:
+    //   Z_m = (X_m + conj X_{K-m}) + i e^{2 pi i m / N} (X_m - conj X_{K-m}),  m < K,
+    // with X_m = F_m for m <= lmax (X_0 real) and 0 otherwise.  Element e = (m, rp), both
+    // loads unconditional (index clamped, value selected after), ZE elements per thread
+    // per round.
     const float4* src = reinterpret_cast<const float4*>(F + (size_t)unit * (lmax + 1) * 8 + RG_RINGS * half);
-    const int nv = (lmax + 1) * 2;
-    for (int e0 = 0; e0 < nv; e0 += 8 * 64 * RG_RINGS) {
-      float4 x[8];
+    constexpr int ZE = 4;
+    for (int e0 = 0; e0 < 2 * K; e0 += ZE * 64 * RG_RINGS) {
+      float4 xa[ZE], xb[ZE];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {   // unconditional (index clamped): no load left pending
-        const int e = min(e0 + tid + i * 64 * RG_RINGS, nv - 1);
-        x[i] = src[(size_t)(e >> 1) * 4 + (e & 1)];
+      for (int i = 0; i < ZE; ++i) {
+        const int e = min(e0 + tid + i * 64 * RG_RINGS, 2 * K - 1);
+        const int m = e >> 1, rp = e & 1;
+        xa[i] = src[(size_t)min(m, lmax) * 4 + rp];
+        xb[i] = src[(size_t)min(K - m, lmax) * 4 + rp];
       }
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
+      for (int i = 0; i < ZE; ++i) {
         const int e = e0 + tid + i * 64 * RG_RINGS;
-        if (e < nv) {
-          const int m = e >> 1, r = 2 * (e & 1);
-          rbuf[r * KP + padr(m)] = make_float2(x[i].x, m == 0 ? 0.f : x[i].y);
-          rbuf[(r + 1) * KP + padr(m)] = make_float2(x[i].z, m == 0 ? 0.f : x[i].w);
+        if (e < 2 * K) {
+          const int m = e >> 1, rp = e & 1;
+          const bool ha = m <= lmax, hb = m > 0 && K - m <= lmax;
+          const float2 ew = (m <= K / 2) ? tw[m] : make_float2(-tw[K - m].x, tw[K - m].y);
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            float2 X = ha ? (j ? make_float2(xa[i].z, xa[i].w) : make_float2(xa[i].x, xa[i].y)) : make_float2(0.f, 0.f);
+            if (m == 0) X.y = 0.f;
+            const float2 Y = hb ? (j ? make_float2(xb[i].z, xb[i].w) : make_float2(xb[i].x, xb[i].y)) : make_float2(0.f, 0.f);
+            const float2 sa = make_float2(X.x + Y.x, X.y - Y.y), d = make_float2(X.x - Y.x, X.y + Y.y);
+            rbuf[(2 * rp + j) * KP + padr(m)] =
+                make_float2(sa.x - (ew.x * d.y + ew.y * d.x), sa.y + (ew.x * d.x - ew.y * d.y));
+          }
         }
       }
-    }
-    for (int e = tid; e < (K - lmax - 1) * RG_RINGS; e += 64 * RG_RINGS) {
-      const int r = e / (K - lmax - 1), m = lmax + 1 + e % (K - lmax - 1);
-      rbuf[r * KP + padr(m)] = make_float2(0.f, 0.f);
     }
     __syncthreads();
 
     float2* bw = rbuf + w * KP;
-    // Z_m = (X_m + conj X_{K-m}) + i e^{2 pi i m / N} (X_m - conj X_{K-m}), X_K = 0;
-    // the lane that owns m also owns K - m, so the update is in place
-    for (int m = lane; m <= K / 2; m += 64) {
-      const int m2 = K - m;
-      const float2 xm = bw[padr(m)];
-      const float2 xk = (m > 0) ? bw[padr(m2 % K)] : make_float2(0.f, 0.f);
-      {
-        const float2 a = make_float2(xm.x + xk.x, xm.y - xk.y), d = make_float2(xm.x - xk.x, xm.y + xk.y);
-        const float2 ew = tw[m];
-        bw[padr(m)] = make_float2(a.x - (ew.x * d.y + ew.y * d.x), a.y + (ew.x * d.x - ew.y * d.y));
-      }
-      if (m > 0 && m2 != m) {
-        const float2 a = make_float2(xk.x + xm.x, xk.y - xm.y), d = make_float2(xk.x - xm.x, xk.y + xm.y);
-        const float2 ew = make_float2(-tw[m].x, tw[m].y);   // e^{2 pi i (K - m) / N} = -conj(tw[m])
-        bw[padr(m2)] = make_float2(a.x - (ew.x * d.y + ew.y * d.x), a.y + (ew.x * d.x - ew.y * d.y));
-      }
-    }
     // z = sum_m Z_m e^{+2 pi i m n / K}
     int Ns = 1;
     const float2* tf = twp;
