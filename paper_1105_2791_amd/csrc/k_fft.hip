@@ -338,8 +338,10 @@ __device__ inline void dft_plus(float2* x) {
 // twiddle table, twp[(q - 1) Ns + k] = e^{2 pi i q k / (Ns R)}, laid out so that the
 // lanes of a wave (consecutive k) read consecutive entries
 // PTS: the most points a lane holds in any pass of the plan (register budget)
-template <int R, int PTS>
-__device__ inline void rg_pass(float2* b, int K, int Ns, int lane, const float2* twp) {
+// OUT: the last pass writes its (natural-order) output to the global row out instead
+// of back to b (nothing when out is null: a padding ring)
+template <int R, int PTS, bool OUT = false>
+__device__ inline void rg_pass(float2* b, int K, int Ns, int lane, const float2* twp, float2* out = nullptr) {
   constexpr int NB = (PTS + R - 1) / R;
   const int KR = K / R;
   float2 v[NB][R];
@@ -360,8 +362,15 @@ __device__ inline void rg_pass(float2* b, int K, int Ns, int lane, const float2*
       for (int q = 1; q < R; ++q) v[i][q] = cmulf(v[i][q], twp[(q - 1) * Ns + k]);
       dft_plus<R>(v[i]);
       const int ob = (bi / Ns) * Ns * R + k;
+      if (OUT) {
+        if (out) {
 #pragma unroll
-      for (int q = 0; q < R; ++q) b[padr(ob + q * Ns)] = v[i][q];
+          for (int q = 0; q < R; ++q) out[ob + q * Ns] = v[i][q];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < R; ++q) b[padr(ob + q * Ns)] = v[i][q];
+      }
     }
   }
 }
@@ -378,7 +387,8 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int 
   float2* twp = tw + K / 2 + 1;          // the passes' twiddle tables, K - 1 entries in all
   const int nrb8 = f_ring_blocks(ntheta);
   const int units = nseq * nrb8;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: the ring row base stays scalar
   for (int t = tid; t <= K / 2; t += 64 * RG_RINGS) tw[t] = twg[t];
   for (int t = tid; t < K - 1; t += 64 * RG_RINGS) twp[t] = twpg[t];
   // persistent: workgroups b and b + 8 (one XCD) take the two halves of the same ring
@@ -431,12 +441,19 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int 
     __syncthreads();
 
     float2* bw = rbuf + w * KP;
-    // z = sum_m Z_m e^{+2 pi i m n / K}
+    // z = sum_m Z_m e^{+2 pi i m n / K}; the last pass writes the map row directly:
+    // M_{2n} = Re z_n, M_{2n+1} = Im z_n
+    const int j = rb * 8 + RG_RINGS * half + w;
+    float2* dst = (j < ntheta) ? reinterpret_cast<float2*>(maps + ((size_t)seq * ntheta + j) * plan.N) : nullptr;
     int Ns = 1;
     const float2* tf = twp;
+    // (a last pass of radix 8, the common case, stores straight to the row; other plans
+    // finish in LDS and copy the row out)
+    const bool direct = plan.radix[plan.nf - 1] == 8;
     for (int f = 0; f < plan.nf; ++f) {
       const int R = plan.radix[f];
-      if (R == 24) rg_pass<24, PTS>(bw, K, Ns, lane, tf);
+      if (direct && f == plan.nf - 1) rg_pass<8, PTS, true>(bw, K, Ns, lane, tf, dst);
+      else if (R == 24) rg_pass<24, PTS>(bw, K, Ns, lane, tf);
       else if (R == 8) rg_pass<8, PTS>(bw, K, Ns, lane, tf);
       else if (R == 4) rg_pass<4, PTS>(bw, K, Ns, lane, tf);
       else if (R == 2) rg_pass<2, PTS>(bw, K, Ns, lane, tf);
@@ -445,10 +462,7 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int 
       tf += (R - 1) * Ns;
       Ns *= R;
     }
-    // M_{2n} = Re z_n, M_{2n+1} = Im z_n
-    const int j = rb * 8 + RG_RINGS * half + w;
-    if (j < ntheta) {
-      float2* dst = reinterpret_cast<float2*>(maps + ((size_t)seq * ntheta + j) * plan.N);
+    if (!direct && dst) {
       for (int n = lane; n < K; n += 64) dst[n] = bw[padr(n)];
     }
   }
