@@ -52,6 +52,8 @@ struct Tables {
   int2* items = nullptr;       // [nitems] (first block, mode tile) work items of the split contraction
   int nitems = 0;
   float* mscale = nullptr;     // [P] exact powers of two ~ 1/sigma_p (split-fp16 contraction)
+  uint4* lamtab = nullptr;     // split synthesis: lambda operand words per (m, wave of rings, chunk)
+  long long* lamtab_off = nullptr;   // [lmax+1] first record of each m
 };
 
 }  // namespace modal
@@ -111,6 +113,10 @@ hipError_t launch_legendre_mfma(const modal_ctx* c, const void* alm, int S, void
 hipError_t launch_legendre_split(const modal_ctx* c, const void* alm, int S, void* F, hipStream_t st);
 size_t legendre_split_lds();
 hipError_t legendre_split_set_lds(size_t bytes);
+// the split synthesis's lambda table (built once per context when it fits)
+size_t lambda_table_records(const modal_ctx* c, std::vector<long long>* off);
+size_t lambda_table_bytes(const modal_ctx* c);
+hipError_t build_lambda_table(modal_ctx* c, hipStream_t st);
 size_t legendre_mfma_lds(const modal_ctx* c);
 hipError_t legendre_mfma_set_lds(size_t bytes);
 // ring c2r FFT: maps[S][P][ntheta][nphi] from F

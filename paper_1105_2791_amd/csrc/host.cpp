@@ -435,6 +435,22 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
   if (e == hipSuccess) e = hipDeviceSynchronize();
   (void)hipFree(d_logpref);
   if (e != hipSuccess) return bail(MODAL_EDEVICE);
+  // split precisions: the synthesis reads lambda from a table computed here once (the
+  // recurrence is then not repeated for every block of columns), when the table takes
+  // at most a tenth of the device memory
+  if (prec == MODAL_BF16X3 || prec == MODAL_F16X3) {
+    size_t free_b = 0, total_b = 0;
+    const size_t bytes = lambda_table_bytes(c);
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && bytes <= total_b / 10 && bytes < free_b / 2) {
+      std::vector<long long> off;
+      lambda_table_records(c, &off);
+      if (upload(&t.lamtab_off, off) != hipSuccess || hipMalloc((void**)&t.lamtab, bytes) != hipSuccess)
+        return bail(MODAL_EDEVICE);
+      e = build_lambda_table(c, nullptr);
+      if (e == hipSuccess) e = hipDeviceSynchronize();
+      if (e != hipSuccess) return bail(MODAL_EDEVICE);
+    }
+  }
   *out = c;
   return MODAL_OK;
 }
@@ -449,7 +465,7 @@ void modal_destroy(modal_ctx* c) {
   Tables& t = c->t;
   void* ptrs[] = {t.x, t.ringw, t.w64, t.w32, t.rec, t.seed, t.lstart, t.lstart_blk, t.qw64, t.qw32, t.tw64, t.tw32,
                   t.pair_a, t.pair_b, t.tri, t.pair_of, t.tri_of, t.tri_mult, t.flag, t.blk, t.items, t.mscale,
-                  t.twp32};
+                  t.twp32, t.lamtab, t.lamtab_off};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;

@@ -118,12 +118,16 @@ __device__ inline void lambda_chunk(int l0, int m, int lmax, const uint32_t (&rr
   }
 }
 
-template <int PREC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_legendre_split(int lmax, int ntheta, int nrp, int P, int ncols, int nalm,
-                                                        const double* __restrict__ x, const double* __restrict__ rec,
-                                                        const double* __restrict__ seed,
-                                                        const int* __restrict__ lstart, const float* __restrict__ qw,
-                                                        const float2* __restrict__ alm, float2* __restrict__ F) {
+constexpr int RECUR = 0, BUILD = 1, TABLE = 2;
+
+// MODE: RECUR computes lambda in the kernel; BUILD only computes it and stores the
+// operand words in the context's lambda table; TABLE reads them from the table.
+template <int PREC, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_legendre_split(
+    int lmax, int ntheta, int nrp, int P, int ncols, int nalm, const double* __restrict__ x,
+    const double* __restrict__ rec, const double* __restrict__ seed, const int* __restrict__ lstart,
+    const float* __restrict__ qw, const float2* __restrict__ alm, float2* __restrict__ F, uint4* __restrict__ tab,
+    const long long* __restrict__ tab_off) {
   constexpr bool F16 = PREC == MODAL_F16X3;
   typedef typename std::conditional<F16, f16x8, bf16x8>::type vec8;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -131,11 +135,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   __shared__ int lmin_blk;
   __shared__ int lmax_ls_wave[NWAVE];
 
-  const int m = blockIdx.z;
-  const int c0 = blockIdx.x * NCOL;
+  int m, rbk, cbk;
+  if (MODE == TABLE) {
+    // 1-D grid, XCD-aware: unit (m, ring block) u goes to XCD u % 8, and its column blocks
+    // follow each other there, so they read its lambda records from the same L2
+    const int nrb = (nrp + NWAVE * RW - 1) / (NWAVE * RW), ncb = (ncols + NCOL - 1) / NCOL;
+    const int b = blockIdx.x, idx = b >> 3;
+    const int unit = (b & 7) + 8 * (idx / ncb);
+    if (unit >= nrb * (lmax + 1)) return;   // whole workgroup
+    cbk = idx - (idx / ncb) * ncb;
+    m = unit / nrb;
+    rbk = unit - m * nrb;
+  } else {
+    m = blockIdx.z;
+    rbk = blockIdx.y;
+    cbk = blockIdx.x;
+  }
+  const int c0 = cbk * NCOL;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int lrow = lane & 31, kh = lane >> 5;
-  const int jring = blockIdx.y * (NWAVE * RW) + wv * RW + lane;
+  const int jring = rbk * (NWAVE * RW) + wv * RW + lane;
+  // lambda records of this wave: one per chunk k (from l = m), 16 x 64 lanes x 16 bytes
+  const int nkm = (lmax + 1 - m + LCH - 1) / LCH;
+  const long long rec0 = (MODE == RECUR) ? 0 : tab_off[m] + (long long)(rbk * NWAVE + wv) * nkm;
   const bool ring_ok = jring < nrp;
   const size_t off = (size_t)m * (2 * lmax + 3 - m) / 2;
 
@@ -194,17 +216,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     rr[2] = r4.z;
     rr[3] = r4.w;
   };
-  if (m + kfirst * LCH <= lmax) load_rr(m + kfirst * LCH);
+  if (MODE != TABLE && m + kfirst * LCH <= lmax) load_rr(m + kfirst * LCH);
 
   for (int l0 = m + kfirst * LCH; l0 <= lmax; l0 += LCH) {
-    __syncthreads();
+    uint4* trec = tab + (size_t)(rec0 + (l0 - m) / LCH) * 16 * 64 + lane;
+    if (MODE != BUILD) __syncthreads();
     // ---- coefficient loads: thread (col, quarter) takes 16 consecutive l of one column.
     //      All 16 pairs are unconditional (index clamped in the last chunk, value selected
     //      after) and in flight together while the recurrence below runs.
     const int col = ccol, q = cq;
     float va[16], vq[16];
     const float* pa = reinterpret_cast<const float*>(pa2) + creim;
-    if (l0 + LCH - 1 <= lmax) {   // wave-uniform: one base, immediate offsets
+    if (MODE == BUILD) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) va[i] = vq[i] = 0.f;
+    } else if (l0 + LCH - 1 <= lmax) {   // wave-uniform: one base, immediate offsets
       const float* a = pa + 2 * l0;
       const float* b = pq + l0;
 #pragma unroll
@@ -226,7 +252,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     // ---- lambda for this lane's ring, l0 .. l0 + 63, as hi/lo words: lw index
     //      [par][ks][half][k] holds l-indices 16 ks + 8 half + 2 k, + 1
     uint32_t Lh[2][2][2][4], Ll[2][2][2][4];
-    {
+    if (MODE == TABLE) {
+      // record word i: Lh (i < 8) or Ll (i >= 8) at [par][ks][half] = i % 8
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const uint4 u = trec[i * 64];
+        uint32_t(&dst)[4] = (i < 8) ? Lh[(i >> 2) & 1][(i >> 1) & 1][i & 1] : Ll[(i >> 2) & 1][(i >> 1) & 1][i & 1];
+        dst[0] = u.x;
+        dst[1] = u.y;
+        dst[2] = u.z;
+        dst[3] = u.w;
+      }
+    } else {
       // wave-uniform: every lane is past its seeds and the chunk ends inside l <= lmax,
       // so the steps need no selects (the general form handles seeds and the tail)
       if (l0 > wls + 1 && l0 + LCH - 1 <= lmax) {
@@ -249,8 +286,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             Ll[par][ks][0][k] = sl[0];
             Ll[par][ks][1][k] = sl[1];
           }
+      if (l0 + LCH <= lmax) load_rr(l0 + LCH);
     }
-    if (l0 + LCH <= lmax) load_rr(l0 + LCH);
+    if (MODE == BUILD) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const uint32_t(&w)[4] = (i < 8) ? Lh[(i >> 2) & 1][(i >> 1) & 1][i & 1] : Ll[(i >> 2) & 1][(i >> 1) & 1][i & 1];
+        trec[i * 64] = make_uint4(w[0], w[1], w[2], w[3]);
+      }
+      continue;
+    }
 
     // ---- coefficient tile: qw_p(l) Re/Im a_lm, split, stored; l = l0 + 16 q + i has
     //      parity i & 1 and index 8 q + i / 2 (zero past lmax and for padding columns)
@@ -304,6 +349,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       }
   }
 
+  if (MODE == BUILD) return;
+
   // ---- output: stage N = E + O then S = E - O through LDS, one [RW][SS] slab per wave;
   // acc[par][rt][ct][j] is ring 32 rt + 8 (j / 4) + 4 kh + j % 4, column 32 ct + lrow
   __syncthreads();
@@ -342,19 +389,65 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 size_t legendre_split_lds() { return kLdsBytes; }
 
 hipError_t legendre_split_set_lds(size_t bytes) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_legendre_split<MODAL_BF16X3>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_legendre_split<MODAL_F16X3>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)bytes);
+#define SETLDS(PR, MD)                                                                                        \
+  {                                                                                                           \
+    hipError_t e = hipFuncSetAttribute((const void*)k_legendre_split<PR, MD>,                                 \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);              \
+    if (e != hipSuccess) return e;                                                                            \
+  }
+  SETLDS(MODAL_BF16X3, RECUR) SETLDS(MODAL_BF16X3, TABLE) SETLDS(MODAL_F16X3, RECUR) SETLDS(MODAL_F16X3, TABLE)
+#undef SETLDS
+  return hipSuccess;
+}
+
+// lambda table: per m, per wave of 64 north rings, per chunk of 64 l from l = m, one
+// record of 16 x 64 lanes x 16 bytes (the wave's hi/lo operand words of the chunk)
+static int lam_waves(const modal_ctx* c) { return 4 * ((c->nrp + 255) / 256); }
+
+size_t lambda_table_records(const modal_ctx* c, std::vector<long long>* off) {
+  long long n = 0;
+  if (off) off->resize(c->lmax + 1);
+  for (int m = 0; m <= c->lmax; ++m) {
+    if (off) (*off)[m] = n;
+    n += (long long)lam_waves(c) * ((c->lmax + 1 - m + LCH - 1) / LCH);
+  }
+  return (size_t)n;
+}
+
+size_t lambda_table_bytes(const modal_ctx* c) { return lambda_table_records(c, nullptr) * 16 * 64 * sizeof(uint4); }
+
+hipError_t build_lambda_table(modal_ctx* c, hipStream_t st) {
+  dim3 grid(1, (c->nrp + NWAVE * RW - 1) / (NWAVE * RW), c->lmax + 1);
+#define LAUNCH(PR)                                                                                                  \
+  hipLaunchKernelGGL((k_legendre_split<PR, BUILD>), grid, dim3(256), 0, st, c->lmax, c->ntheta, c->nrp, c->P, 0,      \
+                     c->nalm, c->t.x, c->t.rec, c->t.seed, c->t.lstart, c->t.qw32, (const float2*)nullptr,          \
+                     (float2*)nullptr, c->t.lamtab, c->t.lamtab_off)
+  if (c->prec == MODAL_F16X3) LAUNCH(MODAL_F16X3);
+  else LAUNCH(MODAL_BF16X3);
+#undef LAUNCH
+  return hipGetLastError();
 }
 
 hipError_t launch_legendre_split(const modal_ctx* c, const void* alm, int S, void* F, hipStream_t st) {
   const int ncols = 2 * S * c->P;
-  dim3 grid((ncols + NCOL - 1) / NCOL, (c->nrp + NWAVE * RW - 1) / (NWAVE * RW), c->lmax + 1);
-#define LAUNCH(PR)                                                                                                 \
-  hipLaunchKernelGGL(k_legendre_split<PR>, grid, dim3(256), kLdsBytes, st, c->lmax, c->ntheta, c->nrp, c->P, ncols, \
-                     c->nalm, c->t.x, c->t.rec, c->t.seed, c->t.lstart, c->t.qw32, (const float2*)alm, (float2*)F)
+  const int nrb = (c->nrp + NWAVE * RW - 1) / (NWAVE * RW), ncb = (ncols + NCOL - 1) / NCOL;
+  if (c->t.lamtab) {
+    const int nunits = nrb * (c->lmax + 1);
+    dim3 grid((unsigned)(8 * ((nunits + 7) / 8) * ncb));
+#define LAUNCH(PR)                                                                                                  \
+  hipLaunchKernelGGL((k_legendre_split<PR, TABLE>), grid, dim3(256), kLdsBytes, st, c->lmax, c->ntheta, c->nrp, c->P, \
+                     ncols, c->nalm, c->t.x, c->t.rec, c->t.seed, c->t.lstart, c->t.qw32, (const float2*)alm,         \
+                     (float2*)F, c->t.lamtab, c->t.lamtab_off)
+    if (c->prec == MODAL_F16X3) LAUNCH(MODAL_F16X3);
+    else LAUNCH(MODAL_BF16X3);
+#undef LAUNCH
+    return hipGetLastError();
+  }
+  dim3 grid(ncb, nrb, c->lmax + 1);
+#define LAUNCH(PR)                                                                                                  \
+  hipLaunchKernelGGL((k_legendre_split<PR, RECUR>), grid, dim3(256), kLdsBytes, st, c->lmax, c->ntheta, c->nrp, c->P, \
+                     ncols, c->nalm, c->t.x, c->t.rec, c->t.seed, c->t.lstart, c->t.qw32, (const float2*)alm,         \
+                     (float2*)F, (uint4*)nullptr, (const long long*)nullptr)
   if (c->prec == MODAL_F16X3) LAUNCH(MODAL_F16X3);
   else LAUNCH(MODAL_BF16X3);
 #undef LAUNCH
