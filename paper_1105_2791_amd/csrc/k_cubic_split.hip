@@ -280,6 +280,23 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
         }
         const vec8 bh = *reinterpret_cast<const vec8*>(&L.bh[st][brow][kx]);
         const vec8 bl = *reinterpret_cast<const vec8*>(&L.bl[st][brow][kx]);
+        if (!F16) {
+          // bf16: all four tiles' operands first, then the MFMAs product by product, so
+          // that consecutive MFMAs feed different accumulators (no dependent chain stalls
+          // the in-order issue behind them)
+          bf16x8 ahv[4], alv[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) split_bf16(ma[j >> 1], mb[j & 1], ahv[j], alv[j]);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            cha[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alv[j], *reinterpret_cast<const bf16x8*>(&bh), cha[j], 0, 0, 0);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            cha[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahv[j], *reinterpret_cast<const bf16x8*>(&bl), cha[j], 0, 0, 0);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            cha[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahv[j], *reinterpret_cast<const bf16x8*>(&bh), cha[j], 0, 0, 0);
+        } else
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           vec8 ah, al;
