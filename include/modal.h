@@ -141,7 +141,13 @@ typedef enum {
  *   mask_host [ntheta][nphi] extra pixel weight multiplying the quadrature
  *                           weight (a Galactic cut is 0/1); NULL = full sky
  * Errors: EINVAL (null out/q/cl, lmax < 0, P < 1, bad prec), ESHAPE (ntheta
- * <= lmax, nphi <= 2 lmax or nphi odd), EDEVICE.  On failure *out is NULL. */
+ * <= lmax, nphi <= 2 lmax or nphi odd), EDEVICE.  On failure *out is NULL.
+ * The split precisions (BF16X3, F16X3) also compute here, once, a table of the
+ * synthesis's lambda_lm(theta_j) operand words: 16 KB per (m, 64 north rings,
+ * 64 l), about 1.6 GB at lmax 1000 on 1536 rings.  It is built when it takes at
+ * most a tenth of the device memory and half of the free memory, and not at all
+ * when the environment variable MODAL_LAMBDA_TABLE is "0"; without it the
+ * synthesis runs the recurrence itself (same results, bit for bit). */
 modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P, int prec,
                           const double* q_host, const double* cl_host, const double* mask_host);
 void modal_destroy(modal_ctx* ctx);

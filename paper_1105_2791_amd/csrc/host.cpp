@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -438,7 +439,8 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
   // split precisions: the synthesis reads lambda from a table computed here once (the
   // recurrence is then not repeated for every block of columns), when the table takes
   // at most a tenth of the device memory
-  if (prec == MODAL_BF16X3 || prec == MODAL_F16X3) {
+  const char* lam_env = std::getenv("MODAL_LAMBDA_TABLE");   // "0": keep the in-kernel recurrence
+  if ((prec == MODAL_BF16X3 || prec == MODAL_F16X3) && !(lam_env && lam_env[0] == '0')) {
     size_t free_b = 0, total_b = 0;
     const size_t bytes = lambda_table_bytes(c);
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && bytes <= total_b / 10 && bytes < free_b / 2) {
