@@ -98,7 +98,9 @@ typedef enum {
   MODAL_OP_COVARIANCE_SAMPLE = 5,
   MODAL_OP_COVARIANCE_FISHER = 6,
   MODAL_OP_FNL = 7,
-  MODAL_OP_LINEAR_FINALIZE = 8
+  MODAL_OP_LINEAR_FINALIZE = 8,
+  MODAL_OP_NOISE_VECTORS = 9,   /* S is the number N of beta^hat vectors            */
+  MODAL_OP_FNL_LOWRANK = 10
 } modal_op;
 
 typedef enum {
@@ -242,6 +244,51 @@ modal_status modal_covariance(modal_ctx* ctx, int method, const double* beta_dev
 modal_status modal_fnl(modal_ctx* ctx, const double* zeta_dev, const double* alpha_dev,
                        const double* beta_dev, int S, double* E_host, double* sigma2_host,
                        double* L_dev, void* ws_dev, size_t ws_bytes, modal_stream_t stream);
+
+/* Low-rank covariance (Sec. III B, eq. ic_bivector): zeta ~= I + sum_j b_j b_j^T
+ * in a frame where the ideal covariance is the identity (for instance after
+ * modal_whiten with the Cholesky factor of the ideal covariance).  k = 1 is the
+ * paper's noise/mask "bivector"; k > 1 the principal-component form it announces.
+ *
+ * modal_noise_vectors: the k leading eigenpairs (mu_j, v_j) of the sample
+ * covariance sum_i beta_i beta_i^T / (6N) of the rows of beta_dev [N][nmax]
+ * float64, and b_j = sqrt(max(mu_j - 1, 0)) v_j (the best rank-k fit of zeta - I),
+ * each signed so that its entry of largest magnitude is positive.  Computed from
+ * the N x N Gram matrix by `iters` rounds of subspace iteration on a block of
+ * min(k + 4, 16, N, nmax) columns and a final Rayleigh-Ritz step; the error of the
+ * subspace shrinks like (mu_{kb+1} / mu_k)^iters.
+ *   bt_dev [k][nmax] float64 (written), mu_host [k] (written; the call
+ *   synchronises the stream).  1 <= k <= min(16, N, nmax), iters >= 1.
+ *   Workspace: modal_workspace_size(MODAL_OP_NOISE_VECTORS, N) (holds N^2 doubles).
+ * Errors: EINVAL, ENOSPACE, EDEVICE. */
+modal_status modal_noise_vectors(modal_ctx* ctx, const double* beta_dev, int N, int k, int iters, double* bt_dev,
+                                 double* mu_host, void* ws_dev, size_t ws_bytes, modal_stream_t stream);
+
+/* Estimator of eqs. (modalest, modalvariance) with zeta = I + sum_j b_j b_j^T for
+ * the k rows of bt_dev [k][nmax] (0 <= k <= 16; k = 0 is zeta = I), through the
+ * Woodbury identity (eq. ic_bivectorinv for k = 1):
+ *   alpha_dev [nmax], beta_dev [S][nmax] float64; E_host [S], sigma2_host [1].
+ * Synchronises the stream.  Workspace: modal_workspace_size(MODAL_OP_FNL_LOWRANK, S).
+ * Errors: EINVAL (also alpha^T zeta^-1 alpha <= 0), ENOSPACE, EDEVICE. */
+modal_status modal_fnl_lowrank(modal_ctx* ctx, const double* bt_dev, int k, const double* alpha_dev,
+                               const double* beta_dev, int S, double* E_host, double* sigma2_host, void* ws_dev,
+                               size_t ws_bytes, modal_stream_t stream);
+
+/* Rotation into the orthonormal frame of zeta = I + b b^T (Sec. III B, eq. Cholrot):
+ * y_r = lambda~^-1 x_r for the closed-form lower Cholesky factor lambda~ of
+ * I + b b^T, for R rows x_dev [R][nmax] -> y_dev [R][nmax] (float64; y may equal
+ * x).  In that frame E = alpha'.beta' / |alpha'|^2.  No workspace; asynchronous.
+ * Errors: EINVAL, EDEVICE. */
+modal_status modal_bivector_rotate(modal_ctx* ctx, const double* b_dev, const double* x_dev, int R, double* y_dev,
+                                   modal_stream_t stream);
+
+/* y_r = L^-1 x_r for R rows x_dev [R][nmax] -> y_dev [R][nmax] (float64, y may
+ * equal x), L the lower Cholesky factor returned by modal_fnl (only the lower
+ * triangle is read): the rotation of eq. (Cholrot), e.g. into the frame where a
+ * reference covariance is the identity.  No workspace; asynchronous.
+ * Errors: EINVAL, EDEVICE. */
+modal_status modal_whiten(modal_ctx* ctx, const double* L_dev, const double* x_dev, int R, double* y_dev,
+                          modal_stream_t stream);
 
 /* Autotuner: times modal_beta on the caller's inputs (same arguments and
  * workspace as modal_beta) for each candidate launch configuration - pixels

@@ -16,7 +16,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "modal.h")
 OK, EINVAL, ESHAPE, EDEVICE, ENOTPD, ENOTREADY, EUNSUPPORTED, ENOSPACE = range(8)
 F64, F32, BF16X3, F16X3 = range(4)
 OP_FILTER_MAPS, OP_BETA, OP_LINEAR_ACCUMULATE, OP_LINEAR_APPLY, OP_BETA_VJP, \
-    OP_COVARIANCE_SAMPLE, OP_COVARIANCE_FISHER, OP_FNL, OP_LINEAR_FINALIZE = range(9)
+    OP_COVARIANCE_SAMPLE, OP_COVARIANCE_FISHER, OP_FNL, OP_LINEAR_FINALIZE, OP_NOISE_VECTORS, OP_FNL_LOWRANK = range(11)
 LIN_RESET, LIN_ACCUMULATE, LIN_FINALIZE, LIN_APPLY = range(4)
 COV_SAMPLE, COV_FISHER = range(2)
 
@@ -63,6 +63,10 @@ _SIGS = {
     "modal_graph_destroy": (None, [vp]),
     "modal_autotune": (ip, [vp, vp, ip, vp, vp, vp, sz, vp, vp, vp]),
     "modal_profile_read": (ip, [vp, vp, vp, ip]),
+    "modal_noise_vectors": (ip, [vp, vp, ip, ip, ip, vp, vp, vp, sz, vp]),
+    "modal_fnl_lowrank": (ip, [vp, vp, ip, vp, vp, ip, vp, vp, vp, sz, vp]),
+    "modal_bivector_rotate": (ip, [vp, vp, vp, ip, vp, vp]),
+    "modal_whiten": (ip, [vp, vp, vp, ip, vp, vp]),
 }
 
 STAGES = ["legendre", "fft", "cubic", "reduce", "linacc", "adj_pair", "adj_fft", "adj_legendre",

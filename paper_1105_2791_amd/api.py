@@ -225,6 +225,51 @@ class ModalContext:
         return (E, float(s2[0]), Ld) if want_L else (E, float(s2[0]))
 
 
+    # -- low-rank covariance I + sum_j b_j b_j^T (Sec. III B) --------------------------
+
+    def noise_vectors(self, beta, k: int = 1, iters: int = 100):
+        """The k leading noise vectors b_j [k][nmax] of the sample covariance of the rows of
+        beta [N][nmax] (b_j = sqrt(max(mu_j - 1, 0)) v_j) and the eigenvalues mu_j."""
+        b = torch.as_tensor(beta).to(device=self.device, dtype=torch.float64).reshape(-1, self.nmax).contiguous()
+        N = b.shape[0]
+        bt = torch.empty((k, self.nmax), dtype=torch.float64, device=self.device)
+        mu = np.zeros(k)
+        ws = self.workspace(L.OP_NOISE_VECTORS, N)
+        self._check(self._lib.modal_noise_vectors(self._h, _ptr(b), N, k, iters, _ptr(bt), mu.ctypes.data, _ptr(ws),
+                                                  ws.numel(), self._stream()))
+        return bt, mu
+
+    def fnl_lowrank(self, bt, alpha, beta):
+        """E_s and sigma^2 with zeta = I + sum_j b_j b_j^T (rows of bt, possibly none)."""
+        v = torch.as_tensor(bt).to(device=self.device, dtype=torch.float64).reshape(-1, self.nmax).contiguous()
+        al = torch.as_tensor(alpha).to(device=self.device, dtype=torch.float64).contiguous()
+        b = torch.as_tensor(beta).to(device=self.device, dtype=torch.float64).reshape(-1, self.nmax).contiguous()
+        S, k = b.shape[0], v.shape[0]
+        E = np.zeros(S)
+        s2 = np.zeros(1)
+        ws = self.workspace(L.OP_FNL_LOWRANK, S)
+        self._check(self._lib.modal_fnl_lowrank(self._h, _ptr(v) if k else None, k, _ptr(al), _ptr(b), S,
+                                                E.ctypes.data, s2.ctypes.data, _ptr(ws), ws.numel(), self._stream()))
+        return E, float(s2[0])
+
+    def bivector_rotate(self, b, x) -> torch.Tensor:
+        """Rows of x rotated by the inverse closed-form Cholesky factor of I + b b^T."""
+        bv = torch.as_tensor(b).to(device=self.device, dtype=torch.float64).contiguous()
+        xv = torch.as_tensor(x).to(device=self.device, dtype=torch.float64).reshape(-1, self.nmax).contiguous()
+        y = torch.empty_like(xv)
+        self._check(self._lib.modal_bivector_rotate(self._h, _ptr(bv), _ptr(xv), xv.shape[0], _ptr(y),
+                                                    self._stream()))
+        return y
+
+    def whiten(self, Lfac, x) -> torch.Tensor:
+        """Rows of x multiplied by L^-1 (L lower triangular, as returned by fnl(want_L=True))."""
+        Lv = torch.as_tensor(Lfac).to(device=self.device, dtype=torch.float64).contiguous()
+        xv = torch.as_tensor(x).to(device=self.device, dtype=torch.float64).reshape(-1, self.nmax).contiguous()
+        y = torch.empty_like(xv)
+        self._check(self._lib.modal_whiten(self._h, _ptr(Lv), _ptr(xv), xv.shape[0], _ptr(y), self._stream()))
+        return y
+
+
 class BetaGraph:
     """A captured sequence of modal_beta calls (one per context, mixed l_max allowed),
     replayed with a single graph launch.  Holds references to every tensor baked

@@ -192,6 +192,16 @@ hipError_t launch_cholesky(int n, double* A, int* flag, hipStream_t st);
 hipError_t launch_trsm_rows(int n, const double* L, int nrhs, double* B, hipStream_t st);
 hipError_t launch_estimator(int n, const double* y, const double* Z, int S, double* out, hipStream_t st);
 
+// low-rank covariance I + sum b b^T: noise vectors, Woodbury estimator, closed-form rotation
+size_t noise_ws_bytes(int N);
+int noise_block_max();
+hipError_t launch_noise_vectors(int N, int n, int k, int iters, const double* B, double* bt, double* ws,
+                                double* mu_dev, hipStream_t st);
+size_t lowrank_ws_bytes(int S);
+hipError_t launch_fnl_lowrank(int n, int k, const double* bt, const double* alpha, const double* beta, int S,
+                              double* ws, double* out, hipStream_t st);
+hipError_t launch_bivector_rotate(int n, const double* b, const double* x, int R, double* y, hipStream_t st);
+
 // helpers
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 inline bool is_f64(const modal_ctx* c) { return c->prec == MODAL_F64; }

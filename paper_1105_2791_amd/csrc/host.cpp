@@ -162,6 +162,8 @@ size_t ws_size(const modal_ctx* c, int op, int S) {
       cv.take((size_t)c->nmax * c->nmax * 8); cv.take((size_t)(S + 1) * c->nmax * 8); cv.take((size_t)(S + 1) * 8);
       cv.take(16);
       break;
+    case MODAL_OP_NOISE_VECTORS: cv.take(noise_ws_bytes(S)); break;
+    case MODAL_OP_FNL_LOWRANK: cv.take(lowrank_ws_bytes(S)); break;
     default: return 0;
   }
   return cv.used;
@@ -498,7 +500,7 @@ modal_status modal_grid(const modal_ctx* c, double* x_host, double* w_host) {
 }
 
 modal_status modal_workspace_size(const modal_ctx* c, int op, int S, size_t* bytes) {
-  if (!c || !bytes || S < 0 || op < MODAL_OP_FILTER_MAPS || op > MODAL_OP_LINEAR_FINALIZE) return MODAL_EINVAL;
+  if (!c || !bytes || S < 0 || op < MODAL_OP_FILTER_MAPS || op > MODAL_OP_FNL_LOWRANK) return MODAL_EINVAL;
   *bytes = ws_size(c, op, S);
   return MODAL_OK;
 }
@@ -712,6 +714,77 @@ modal_status modal_fnl(modal_ctx* c, const double* zeta, const double* alpha, co
   const double yy = h[0];
   *sigma2_host = 6.0 / yy;
   for (int i = 0; i < S; ++i) E_host[i] = h[1 + i] / yy;
+  return MODAL_OK;
+}
+
+modal_status modal_noise_vectors(modal_ctx* c, const double* beta, int N, int k, int iters, double* bt,
+                                 double* mu_host, void* ws, size_t ws_bytes, modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (!beta || !bt || !mu_host) return fail(c, MODAL_EINVAL, "noise_vectors: null pointer");
+  const int n = c->nmax;
+  if (N < 1 || iters < 1 || k < 1 || k > noise_block_max() || k > N || k > n)
+    return fail(c, MODAL_EINVAL, "noise_vectors: need N >= 1, iters >= 1 and 1 <= k <= min(16, N, nmax)");
+  modal_status s = check_ws(c, MODAL_OP_NOISE_VECTORS, N, ws, ws_bytes);
+  if (s != MODAL_OK) return s;
+  if ((s = set_device(c)) != MODAL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  double* mu_dev = (double*)((char*)ws + noise_ws_bytes(N) - align256((size_t)noise_block_max() * 8));
+  {
+    StageTimer _t(c, MODAL_STAGE_COVARIANCE, st);
+    HIPTRY(launch_noise_vectors(N, n, k, iters, beta, bt, (double*)ws, mu_dev, st));
+  }
+  HIPTRY(hipMemcpyAsync(mu_host, mu_dev, (size_t)k * 8, hipMemcpyDeviceToHost, st));
+  HIPTRY(hipStreamSynchronize(st));
+  return MODAL_OK;
+}
+
+modal_status modal_fnl_lowrank(modal_ctx* c, const double* bt, int k, const double* alpha, const double* beta, int S,
+                               double* E_host, double* sigma2_host, void* ws, size_t ws_bytes,
+                               modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (!alpha || !sigma2_host || S < 0 || (S > 0 && (!beta || !E_host)) || (k > 0 && !bt))
+    return fail(c, MODAL_EINVAL, "fnl_lowrank: null pointer or S < 0");
+  if (k < 0 || k > noise_block_max()) return fail(c, MODAL_EINVAL, "fnl_lowrank: need 0 <= k <= 16");
+  modal_status s = check_ws(c, MODAL_OP_FNL_LOWRANK, S, ws, ws_bytes);
+  if (s != MODAL_OK) return s;
+  if ((s = set_device(c)) != MODAL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  double* out = (double*)((char*)ws + align256((size_t)(S + 1 + noise_block_max()) * (noise_block_max() + 1) * 8));
+  {
+    StageTimer _t(c, MODAL_STAGE_CHOLESKY, st);
+    HIPTRY(launch_fnl_lowrank(c->nmax, k, bt, alpha, beta, S, (double*)ws, out, st));
+  }
+  std::vector<double> h(S + 1);
+  HIPTRY(hipMemcpyAsync(h.data(), out, (size_t)(S + 1) * 8, hipMemcpyDeviceToHost, st));
+  HIPTRY(hipStreamSynchronize(st));
+  const double yy = h[0];
+  if (!(yy > 0.0)) return fail(c, MODAL_EINVAL, "fnl_lowrank: alpha^T zeta^-1 alpha is not positive");
+  *sigma2_host = 6.0 / yy;
+  for (int i = 0; i < S; ++i) E_host[i] = h[1 + i] / yy;
+  return MODAL_OK;
+}
+
+modal_status modal_bivector_rotate(modal_ctx* c, const double* b, const double* x, int R, double* y,
+                                   modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (R < 0 || (R > 0 && (!b || !x || !y))) return fail(c, MODAL_EINVAL, "bivector_rotate: null pointer or R < 0");
+  if (R == 0) return MODAL_OK;
+  modal_status s = set_device(c);
+  if (s != MODAL_OK) return s;
+  HIPTRY(launch_bivector_rotate(c->nmax, b, x, R, y, (hipStream_t)stream));
+  return MODAL_OK;
+}
+
+modal_status modal_whiten(modal_ctx* c, const double* L, const double* x, int R, double* y, modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (R < 0 || (R > 0 && (!L || !x || !y))) return fail(c, MODAL_EINVAL, "whiten: null pointer or R < 0");
+  if (R == 0) return MODAL_OK;
+  modal_status s = set_device(c);
+  if (s != MODAL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const int n = c->nmax;
+  if (y != x) HIPTRY(hipMemcpyAsync(y, x, (size_t)R * n * 8, hipMemcpyDeviceToDevice, st));
+  HIPTRY(launch_trsm_rows(n, L, R, y, st));
   return MODAL_OK;
 }
 

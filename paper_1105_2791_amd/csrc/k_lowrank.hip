@@ -1,0 +1,561 @@
+// Low-rank modal covariance, Sec. III B: zeta ~= I + sum_j b_j b_j^T (eq. ic_bivector
+// for one vector, the principal-component form for several).
+//
+// Noise vectors.  The k leading eigenpairs of the sample covariance
+// zeta = B^T B / (6N) (rows of B [N][n] are beta^hat_i, eq. linearterm) are found
+// without forming zeta: the N x N Gram matrix G = B B^T / (6N) has the same
+// nonzero eigenvalues, and G u = mu u gives zeta (B^T u) = mu (B^T u) with
+// |B^T u|^2 = 6 N mu.  A block of kb <= 16 columns is iterated, X <- orth(G X)
+// (Cholesky QR applied twice), then one Rayleigh-Ritz step diagonalises
+// H = X^T G X by cyclic Jacobi.  b_j = sqrt(max(mu_j - 1, 0)) B^T u_j / sqrt(6 N mu_j),
+// signed so that its entry of largest magnitude is positive.
+//
+// Estimator.  With K = [b_1 .. b_k] and M = I_k + K^T K, Woodbury gives
+// x^T zeta^-1 y = x.y - (K^T x)^T M^-1 (K^T y) (eq. ic_bivectorinv for k = 1);
+// E_s = alpha^T zeta^-1 beta_s / alpha^T zeta^-1 alpha (eq. modalest).
+//
+// Rotation by the closed-form Cholesky factor of I + b b^T (Sec. III B).  With
+// D_i = 1 + sum_{l <= i} b_l^2 (D_{-1} = 1) and U_i = sum_{j < i} b_j x_j, forward
+// substitution with that factor telescopes to
+//   y_i = (x_i - b_i U_i / D_{i-1}) sqrt(D_{i-1} / D_i),
+// so a rotation is two prefix sums, one workgroup per vector.
+//
+// All of it is FP64 on the vector ALUs; the Gram matrix (N^2 n / 2 FMAs) is the
+// only part with real work, the rest is latency-bound small kernels.
+#include "common.h"
+
+#include <cmath>
+
+namespace modal {
+namespace {
+
+constexpr int KB = 16;     // iterated block width (max noise vectors plus oversampling)
+constexpr int GT = 64;     // Gram output tile
+constexpr int GK = 16;     // Gram column chunk staged in LDS
+constexpr int GXR = 64;    // rows i of G X per workgroup
+constexpr int GXL = 256;   // rows l of G summed per workgroup
+constexpr int RC = 128;    // rows staged per chunk in the one-workgroup kernels
+
+// G[i][j] = scale * B_i . B_j over the rows of B [N][n]; lower tiles computed and mirrored.
+__global__ __launch_bounds__(256) void k_gram_rows(int N, int n, const double* __restrict__ B, double scale,
+                                                   double* __restrict__ G) {
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  if (bj > bi) return;
+  const int i0 = bi * GT, j0 = bj * GT;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  __shared__ double Bi[GK][GT + 1];
+  __shared__ double Bj[GK][GT + 1];
+  double acc[4][4] = {};
+  for (int c0 = 0; c0 < n; c0 += GK) {
+    for (int e = threadIdx.x; e < GK * GT; e += 256) {
+      const int r = e / GK, kk = e - r * GK, c = c0 + kk;
+      Bi[kk][r] = (i0 + r < N && c < n) ? B[(size_t)(i0 + r) * n + c] : 0.0;
+      Bj[kk][r] = (j0 + r < N && c < n) ? B[(size_t)(j0 + r) * n + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = Bi[kk][ty * 4 + u];
+        b[u] = Bj[kk][tx * 4 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + ty * 4 + u, j = j0 + tx * 4 + v;
+      if (i < N && j < N) {
+        G[(size_t)i * N + j] = scale * acc[u][v];
+        G[(size_t)j * N + i] = scale * acc[u][v];
+      }
+    }
+}
+
+// Starting block: a fixed hash of (i, j) mapped to [-1, 1), columns >= kb zero.
+__global__ void k_start_block(int N, int kb, double* __restrict__ X) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * KB) return;
+  const int j = e % KB;
+  uint64_t z = (uint64_t)e * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;   // SplitMix64 finaliser
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  X[e] = j < kb ? (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0 : 0.0;
+}
+
+// Yp[split][i][j] = sum over l in this split of G[l][i] X[l][j] (G symmetric, so the
+// reads G[l][i] are consecutive across the lanes).  X [N][KB].
+__global__ __launch_bounds__(256) void k_gx(int N, const double* __restrict__ G, const double* __restrict__ X,
+                                            double* __restrict__ Yp) {
+  __shared__ double xs[GXL][KB];
+  __shared__ double red[3][GXR][KB + 1];
+  const int i0 = blockIdx.x * GXR, l0 = blockIdx.y * GXL;
+  const int ri = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  const int lend = min(N, l0 + GXL);
+  for (int e = threadIdx.x; e < GXL * KB; e += 256) {
+    const int l = e / KB;
+    xs[l][e % KB] = l0 + l < N ? X[(size_t)l0 * KB + e] : 0.0;
+  }
+  __syncthreads();
+  const int i = i0 + ri;
+  double acc[KB];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) acc[j] = 0.0;
+  if (i < N)
+    for (int l = l0 + ph; l < lend; l += 4) {
+      const double g = G[(size_t)l * N + i];
+#pragma unroll
+      for (int j = 0; j < KB; ++j) acc[j] = fma(g, xs[l - l0][j], acc[j]);
+    }
+  if (ph > 0)
+#pragma unroll
+    for (int j = 0; j < KB; ++j) red[ph - 1][ri][j] = acc[j];
+  __syncthreads();
+  if (ph == 0 && i < N)
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+      Yp[((size_t)blockIdx.y * N + i) * KB + j] = acc[j] + red[0][ri][j] + red[1][ri][j] + red[2][ri][j];
+}
+
+// C[a][b] = sum_i X[i][a] X[i][b] (a, b < kb) for one workgroup; thread t < kb^2 owns (t / kb, t % kb).
+__device__ void block_gram(int N, int kb, const double* __restrict__ X, const double* __restrict__ Y,
+                           double (*xs)[KB + 1], double (*ys)[KB + 1], double (*C)[KB]) {
+  const int tid = threadIdx.x;
+  const int a = tid / kb, b = tid - (tid / kb) * kb;
+  double c = 0.0;
+  for (int r0 = 0; r0 < N; r0 += RC) {
+    for (int e = tid; e < RC * KB; e += 256) {
+      const int r = e / KB, j = e - r * KB;
+      xs[r][j] = r0 + r < N ? X[(size_t)(r0 + r) * KB + j] : 0.0;
+      ys[r][j] = r0 + r < N ? Y[(size_t)(r0 + r) * KB + j] : 0.0;
+    }
+    __syncthreads();
+    if (tid < kb * kb)
+      for (int r = 0; r < RC; ++r) c = fma(xs[r][a], ys[r][b], c);
+    __syncthreads();
+  }
+  if (tid < kb * kb) C[a][b] = c;
+  __syncthreads();
+}
+
+// One workgroup: X = sum of the nsplit partial blocks, then made orthonormal by two
+// rounds of Cholesky QR (C = X^T X = R^T R, X <- X R^-1).  A column whose pivot falls
+// below 1e-26 of the largest diagonal entry of C (numerically dependent) is set to zero.
+__global__ __launch_bounds__(256) void k_orth(int N, int kb, int nsplit, const double* __restrict__ Yp,
+                                              double* __restrict__ X) {
+  __shared__ double xs[RC][KB + 1];
+  __shared__ double ys[RC][KB + 1];
+  __shared__ double C[KB][KB];
+  __shared__ double R[KB][KB];
+  __shared__ double Ri[KB][KB];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < N * KB; e += 256) {
+    double s = 0.0;
+    if (e % KB < kb)
+      for (int p = 0; p < nsplit; ++p) s += Yp[(size_t)p * N * KB + e];
+    X[e] = s;
+  }
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    block_gram(N, kb, X, X, xs, ys, C);
+    if (tid == 0) {
+      double dmax = 0.0;
+      for (int j = 0; j < kb; ++j) dmax = fmax(dmax, C[j][j]);
+      unsigned drop = 0;   // bit j: column j dropped
+      for (int j = 0; j < kb; ++j) {
+        double d = C[j][j];
+        for (int p = 0; p < j; ++p) d -= R[p][j] * R[p][j];
+        const bool dj = !(d > 1e-26 * dmax);
+        drop |= (unsigned)dj << j;
+        const double rjj = dj ? 1.0 : sqrt(d);
+        R[j][j] = rjj;
+        for (int q = j + 1; q < kb; ++q) {
+          double s = C[j][q];
+          for (int p = 0; p < j; ++p) s -= R[p][j] * R[p][q];
+          R[j][q] = dj ? 0.0 : s / rjj;
+        }
+      }
+      for (int j = 0; j < kb; ++j) {
+        for (int i = 0; i < KB; ++i) Ri[i][j] = 0.0;
+        Ri[j][j] = 1.0 / R[j][j];
+        for (int i = j - 1; i >= 0; --i) {
+          double s = 0.0;
+          for (int p = i + 1; p <= j; ++p) s += R[i][p] * Ri[p][j];
+          Ri[i][j] = -s / R[i][i];
+        }
+      }
+      for (int j = 0; j < kb; ++j)
+        if ((drop >> j) & 1u)
+          for (int i = 0; i < KB; ++i) Ri[i][j] = 0.0;
+    }
+    __syncthreads();
+    for (int i = tid; i < N; i += 256) {
+      double x[KB];
+#pragma unroll
+      for (int j = 0; j < KB; ++j) x[j] = X[(size_t)i * KB + j];
+#pragma unroll
+      for (int j = 0; j < KB; ++j) {
+        if (j >= kb) break;
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a <= j; ++a) s = fma(x[a], Ri[a][j], s);
+        X[(size_t)i * KB + j] = s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Cyclic Jacobi for the symmetric kb x kb matrix A (destroyed): eigenvalues w and
+// eigenvectors V (columns), sorted by decreasing eigenvalue.  Single thread.
+__device__ void jacobi_eig(int kb, double (*A)[KB], double (*V)[KB], double* w) {
+  for (int i = 0; i < kb; ++i)
+    for (int j = 0; j < kb; ++j) V[i][j] = i == j ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < kb; ++i)
+      for (int j = 0; j < kb; ++j) {
+        tot += A[i][j] * A[i][j];
+        if (i != j) off += A[i][j] * A[i][j];
+      }
+    if (!(off > 1e-32 * tot)) break;
+    for (int p = 0; p < kb - 1; ++p)
+      for (int q = p + 1; q < kb; ++q) {
+        const double apq = A[p][q];
+        if (apq == 0.0) continue;
+        // rotation angle from the stable tangent formula (Rutishauser)
+        const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int r = 0; r < kb; ++r) {   // A <- A J (columns p, q)
+          const double arp = A[r][p], arq = A[r][q];
+          A[r][p] = c * arp - s * arq;
+          A[r][q] = s * arp + c * arq;
+        }
+        for (int r = 0; r < kb; ++r) {   // A <- J^T A (rows p, q)
+          const double apr = A[p][r], aqr = A[q][r];
+          A[p][r] = c * apr - s * aqr;
+          A[q][r] = s * apr + c * aqr;
+        }
+        for (int r = 0; r < kb; ++r) {   // V <- V J
+          const double vrp = V[r][p], vrq = V[r][q];
+          V[r][p] = c * vrp - s * vrq;
+          V[r][q] = s * vrp + c * vrq;
+        }
+      }
+  }
+  for (int i = 0; i < kb; ++i) w[i] = A[i][i];
+  for (int i = 0; i < kb; ++i) {   // selection sort, decreasing
+    int m = i;
+    for (int j = i + 1; j < kb; ++j)
+      if (w[j] > w[m]) m = j;
+    if (m != i) {
+      const double tw = w[i];
+      w[i] = w[m];
+      w[m] = tw;
+      for (int r = 0; r < kb; ++r) {
+        const double tv = V[r][i];
+        V[r][i] = V[r][m];
+        V[r][m] = tv;
+      }
+    }
+  }
+}
+
+// One workgroup: H = X^T (G X) (partials summed on the fly), symmetrised, diagonalised;
+// X <- X V, mu = eigenvalues (decreasing).
+__global__ __launch_bounds__(256) void k_rayleigh_ritz(int N, int kb, int nsplit, const double* __restrict__ Yp,
+                                                       double* __restrict__ Y, double* __restrict__ X,
+                                                       double* __restrict__ mu) {
+  __shared__ double xs[RC][KB + 1];
+  __shared__ double ys[RC][KB + 1];
+  __shared__ double H[KB][KB];
+  __shared__ double V[KB][KB];
+  __shared__ double w[KB];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < N * KB; e += 256) {
+    double s = 0.0;
+    for (int p = 0; p < nsplit; ++p) s += Yp[(size_t)p * N * KB + e];
+    Y[e] = s;
+  }
+  __syncthreads();
+  block_gram(N, kb, X, Y, xs, ys, H);
+  if (tid == 0) {
+    for (int i = 0; i < kb; ++i)
+      for (int j = i + 1; j < kb; ++j) H[i][j] = H[j][i] = 0.5 * (H[i][j] + H[j][i]);
+    jacobi_eig(kb, H, V, w);
+    for (int j = 0; j < kb; ++j) mu[j] = w[j];
+  }
+  __syncthreads();
+  for (int i = tid; i < N; i += 256) {
+    double x[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) x[j] = X[(size_t)i * KB + j];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      if (j >= kb) break;
+      double s = 0.0;
+#pragma unroll
+      for (int a = 0; a < KB; ++a)
+        if (a < kb) s = fma(x[a], V[a][j], s);
+      X[(size_t)i * KB + j] = s;
+    }
+  }
+}
+
+// bt[j][c] = sqrt(max(mu_j - 1, 0) / (6N mu_j)) sum_i B[i][c] X[i][j], j < k.
+__global__ __launch_bounds__(256) void k_noise_from_block(int N, int n, int k, const double* __restrict__ B,
+                                                          const double* __restrict__ X, const double* __restrict__ mu,
+                                                          double sixN, double* __restrict__ bt) {
+  __shared__ double xs[RC][KB];
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  double acc[KB];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) acc[j] = 0.0;
+  for (int r0 = 0; r0 < N; r0 += RC) {
+    for (int e = threadIdx.x; e < RC * KB; e += 256) {
+      const int r = e / KB;
+      xs[r][e % KB] = r0 + r < N ? X[(size_t)r0 * KB + e] : 0.0;
+    }
+    __syncthreads();
+    const int nr = min(RC, N - r0);
+    if (c < n)
+      for (int r = 0; r < nr; ++r) {
+        const double b = B[(size_t)(r0 + r) * n + c];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) acc[j] = fma(b, xs[r][j], acc[j]);
+      }
+    __syncthreads();
+  }
+  if (c >= n) return;
+  for (int j = 0; j < k; ++j) {
+    const double m = mu[j];
+    const double coef = m > 1.0 ? sqrt((m - 1.0) / (sixN * m)) : 0.0;
+    bt[(size_t)j * n + c] = coef * acc[j];
+  }
+}
+
+// Sign of vector j: its entry of largest magnitude (first one on ties) made positive.
+__global__ __launch_bounds__(256) void k_sign_fix(int n, double* __restrict__ bt) {
+  double* v = bt + (size_t)blockIdx.x * n;
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  for (int c = threadIdx.x; c < n; c += 256) {
+    const double a = fabs(v[c]);
+    if (a > best) {
+      best = a;
+      bi = c;
+    }
+  }
+  __shared__ double sb[256];
+  __shared__ int si[256];
+  sb[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      const double o = sb[threadIdx.x + s];
+      const int oi = si[threadIdx.x + s];
+      if (o > sb[threadIdx.x] || (o == sb[threadIdx.x] && oi < si[threadIdx.x])) {
+        sb[threadIdx.x] = o;
+        si[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const int im = si[0];
+  const bool flip = im < n && v[im] < 0.0;
+  __syncthreads();
+  if (flip)
+    for (int c = threadIdx.x; c < n; c += 256) v[c] = -v[c];
+}
+
+__device__ inline double block_sum(double v, double* red) {
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_down(v, d, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+// D[r][0] = v_r . alpha and D[r][1 + j] = v_r . b_j for the rows
+// v = (alpha, beta_1 .. beta_S, b_1 .. b_k), one workgroup per row.
+__global__ __launch_bounds__(256) void k_lowrank_dots(int n, int S, int k, const double* __restrict__ alpha,
+                                                      const double* __restrict__ beta, const double* __restrict__ bt,
+                                                      double* __restrict__ D) {
+  const int r = blockIdx.x;
+  const double* v = r == 0 ? alpha : (r <= S ? beta + (size_t)(r - 1) * n : bt + (size_t)(r - 1 - S) * n);
+  double acc[KB + 1];
+#pragma unroll
+  for (int j = 0; j <= KB; ++j) acc[j] = 0.0;
+  for (int c = threadIdx.x; c < n; c += 256) {
+    const double x = v[c];
+    acc[0] = fma(x, alpha[c], acc[0]);
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+      if (j < k) acc[1 + j] = fma(x, bt[(size_t)j * n + c], acc[1 + j]);
+  }
+  __shared__ double red[4];
+#pragma unroll
+  for (int j = 0; j <= KB; ++j)
+    if (j <= k) {   // uniform
+      const double s = block_sum(acc[j], red);
+      if (threadIdx.x == 0) D[(size_t)r * (KB + 1) + j] = s;
+    }
+}
+
+// out[r] = D[r][0] - w^T D[r][1..k] with w = (I + K^T K)^-1 K^T alpha: out[0] is
+// alpha^T zeta^-1 alpha and out[1 + s] is alpha^T zeta^-1 beta_s.  One workgroup.
+__global__ __launch_bounds__(256) void k_lowrank_finish(int S, int k, const double* __restrict__ D,
+                                                        double* __restrict__ out) {
+  __shared__ double w[KB];
+  if (threadIdx.x == 0) {
+    double M[KB][KB], Lc[KB][KB], y[KB];
+    for (int a = 0; a < k; ++a)
+      for (int b = 0; b < k; ++b) M[a][b] = (a == b ? 1.0 : 0.0) + D[(size_t)(S + 1 + a) * (KB + 1) + 1 + b];
+    for (int j = 0; j < k; ++j) {   // M = Lc Lc^T (M >= I, so the pivots are >= 1)
+      double d = M[j][j];
+      for (int p = 0; p < j; ++p) d -= Lc[j][p] * Lc[j][p];
+      Lc[j][j] = sqrt(d);
+      for (int i = j + 1; i < k; ++i) {
+        double s = M[i][j];
+        for (int p = 0; p < j; ++p) s -= Lc[i][p] * Lc[j][p];
+        Lc[i][j] = s / Lc[j][j];
+      }
+    }
+    for (int i = 0; i < k; ++i) {
+      double s = D[1 + i];
+      for (int p = 0; p < i; ++p) s -= Lc[i][p] * y[p];
+      y[i] = s / Lc[i][i];
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double s = y[i];
+      for (int p = i + 1; p < k; ++p) s -= Lc[p][i] * w[p];
+      w[i] = s / Lc[i][i];
+    }
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r <= S; r += 256) {
+    double q = D[(size_t)r * (KB + 1)];
+    for (int j = 0; j < k; ++j) q -= w[j] * D[(size_t)r * (KB + 1) + 1 + j];
+    out[r] = q;
+  }
+}
+
+// Inclusive scan of v over the 256 threads of the workgroup; total in *tot.
+__device__ inline double block_incl_scan(double v, double* sh, double* tot) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int d = 1; d < 64; d <<= 1) {
+    const double t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  __syncthreads();
+  if (lane == 63) sh[wv] = v;
+  __syncthreads();
+  double off = 0.0;
+  for (int u = 0; u < wv; ++u) off += sh[u];
+  *tot = sh[0] + sh[1] + sh[2] + sh[3];
+  return v + off;
+}
+
+// y = lambda~^-1 x for every row of x [R][n] (see the file comment); one workgroup per
+// row, 1024 entries per round, 4 consecutive per thread.
+__global__ __launch_bounds__(256) void k_bivector_rotate(int n, const double* __restrict__ b,
+                                                         const double* __restrict__ x, double* __restrict__ y) {
+  __shared__ double sh2[4], shu[4];
+  const double* xr = x + (size_t)blockIdx.x * n;
+  double* yr = y + (size_t)blockIdx.x * n;
+  double carryD = 1.0, carryU = 0.0;
+  for (int base = 0; base < n; base += 1024) {
+    const int i0 = base + 4 * threadIdx.x;
+    double bb[4], xx[4], s2 = 0.0, su = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const bool in = i0 + e < n;
+      bb[e] = in ? b[i0 + e] : 0.0;
+      xx[e] = in ? xr[i0 + e] : 0.0;
+      s2 = fma(bb[e], bb[e], s2);
+      su = fma(bb[e], xx[e], su);
+    }
+    double t2, tu;
+    const double i2 = block_incl_scan(s2, sh2, &t2);
+    const double iu = block_incl_scan(su, shu, &tu);
+    double D = carryD + (i2 - s2);   // D_{i0 - 1}
+    double U = carryU + (iu - su);   // U_{i0}
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const double Dn = fma(bb[e], bb[e], D);
+      if (i0 + e < n) yr[i0 + e] = (xx[e] - bb[e] * U / D) * sqrt(D / Dn);
+      D = Dn;
+      U = fma(bb[e], xx[e], U);
+    }
+    carryD += t2;
+    carryU += tu;
+  }
+}
+
+}  // namespace
+
+size_t noise_ws_bytes(int N) {
+  const size_t nsplit = (size_t)(N + GXL - 1) / GXL;
+  return align256((size_t)N * N * 8) + align256((size_t)N * KB * 8) * 2 + align256(nsplit * N * KB * 8) +
+         align256(KB * 8);
+}
+
+int noise_block_max() { return KB; }
+
+hipError_t launch_noise_vectors(int N, int n, int k, int iters, const double* B, double* bt, double* ws,
+                                double* mu_dev, hipStream_t st) {
+  const int kb = std::min(std::min(k + 4, KB), std::min(N, n));
+  const int nsplit = (N + GXL - 1) / GXL;
+  char* p = (char*)ws;
+  double* G = (double*)p;
+  p += align256((size_t)N * N * 8);
+  double* X = (double*)p;
+  p += align256((size_t)N * KB * 8);
+  double* Y = (double*)p;
+  p += align256((size_t)N * KB * 8);
+  double* Yp = (double*)p;
+  const int nt = (N + GT - 1) / GT;
+  hipLaunchKernelGGL(k_gram_rows, dim3(nt, nt), dim3(256), 0, st, N, n, B, 1.0 / (6.0 * N), G);
+  hipLaunchKernelGGL(k_start_block, dim3((N * KB + 255) / 256), dim3(256), 0, st, N, kb, Yp);
+  hipLaunchKernelGGL(k_orth, dim3(1), dim3(256), 0, st, N, kb, 1, Yp, X);
+  const dim3 ggx((N + GXR - 1) / GXR, nsplit);
+  for (int it = 0; it < iters; ++it) {
+    hipLaunchKernelGGL(k_gx, ggx, dim3(256), 0, st, N, G, X, Yp);
+    hipLaunchKernelGGL(k_orth, dim3(1), dim3(256), 0, st, N, kb, nsplit, Yp, X);
+  }
+  hipLaunchKernelGGL(k_gx, ggx, dim3(256), 0, st, N, G, X, Yp);
+  hipLaunchKernelGGL(k_rayleigh_ritz, dim3(1), dim3(256), 0, st, N, kb, nsplit, Yp, Y, X, mu_dev);
+  hipLaunchKernelGGL(k_noise_from_block, dim3((n + 255) / 256), dim3(256), 0, st, N, n, k, B, X, mu_dev,
+                     6.0 * N, bt);
+  hipLaunchKernelGGL(k_sign_fix, dim3(k), dim3(256), 0, st, n, bt);
+  return hipGetLastError();
+}
+
+size_t lowrank_ws_bytes(int S) { return align256((size_t)(S + 1 + KB) * (KB + 1) * 8) + align256((size_t)(S + 1) * 8); }
+
+hipError_t launch_fnl_lowrank(int n, int k, const double* bt, const double* alpha, const double* beta, int S,
+                              double* ws, double* out, hipStream_t st) {
+  double* D = ws;
+  hipLaunchKernelGGL(k_lowrank_dots, dim3(S + 1 + k), dim3(256), 0, st, n, S, k, alpha, beta, bt, D);
+  hipLaunchKernelGGL(k_lowrank_finish, dim3(1), dim3(256), 0, st, S, k, D, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_bivector_rotate(int n, const double* b, const double* x, int R, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_bivector_rotate, dim3(R), dim3(256), 0, st, n, b, x, y);
+  return hipGetLastError();
+}
+
+}  // namespace modal
