@@ -81,7 +81,7 @@ def cpu_baseline(lmax, ntheta, nphi, P, rings, V_sims=2, cfg_id=6):
                       f"{t:.1f} s, scaled by {ntheta}/{rings}"}
 
 
-def kernel_rooflines(ctx, stages, prec, S):
+def kernel_rooflines(ctx, stages, prec, S, op="beta"):
     """Algorithmic work per launch of each timed stage and its rate against the MI355X peak."""
     lmax, nt, nphi, P = ctx.lmax, ctx.ntheta, ctx.nphi, ctx.P
     npix = nt * nphi
@@ -104,6 +104,9 @@ def kernel_rooflines(ctx, stages, prec, S):
         # linear term from the harmonic pair means: one pass over Z[npairs][nalm]
         "linear": (ctx.npairs * ctx.nalm * 2 * real, "byte", "hbm", PEAK["hbm"], None),
     }
+    if op == "power":
+        # sum_x w M_p M_r: one read of the maps and of the weights per sky
+        work["cubic"] = ((P * npix + npix) * S * real, "byte", "hbm", PEAK["hbm"], None)
     out = {}
     for name, (units, kind, bound, peak, issue) in work.items():
         ms, n = stages.get(name, (0.0, 0))
@@ -121,8 +124,9 @@ def kernel_rooflines(ctx, stages, prec, S):
     return out
 
 
-def run_path(args, prec, steps, warmup, make_state=True):
-    """Build a context at the workload shape, time `steps` beta batches, return the figures."""
+def run_path(args, prec, steps, warmup, make_state=True, op="beta"):
+    """Build a context at the workload shape, time `steps` beta batches (or, op="power",
+    power-spectrum batches), return the figures."""
     import numpy as np
     import torch
     import modal_inputs as mi
@@ -149,7 +153,9 @@ def run_path(args, prec, steps, warmup, make_state=True):
             ctx.linear_accumulate(state, make_inputs(lmax, P, min(S, args.mc - b0), 1000 + b0))
         ctx.linear_finalize(state)
     alm = ctx._alm(make_inputs(lmax, P, S, 0))
-    out = torch.empty((S, ctx.nmax), dtype=torch.float64, device=dev)
+    out = torch.empty((S, ctx.nmax if op == "beta" else ctx.npairs), dtype=torch.float64, device=dev)
+    call = (lambda: ctx.beta(alm, state=state, out=out)) if op == "beta" else \
+        (lambda: ctx.power_beta(alm, state=state, out=out))
     torch.cuda.synchronize()
     log(f"bench[{prec}]: state ready")
 
@@ -158,14 +164,14 @@ def run_path(args, prec, steps, warmup, make_state=True):
         tuned = ctx.autotune(alm, state)
         log(f"bench[{prec}]: autotuned {tuned}")
     for _ in range(warmup):
-        ctx.beta(alm, state=state, out=out)
+        call()
     torch.cuda.synchronize()
     ctx.profile_read(reset=True)
     ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        ctx.beta(alm, state=state, out=out)
+        call()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.profile(False)
@@ -174,7 +180,7 @@ def run_path(args, prec, steps, warmup, make_state=True):
     elapsed = t1 - t0
     res = {"prec": prec, "value": S * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps, "tuned": tuned,
            "stages_ms": {k: v[0] / max(1, v[1]) for k, v in stages.items() if v[1]},
-           "kernels": kernel_rooflines(ctx, stages, prec, S), "nmax": ctx.nmax}
+           "kernels": kernel_rooflines(ctx, stages, prec, S, op), "nmax": ctx.nmax, "npairs": ctx.npairs}
     log(f"bench[{prec}]: {res['value']:.2f} maps/s, {res['ms_per_step']:.2f} ms/step; stages: " +
         ", ".join(f"{k}={v:.3f}ms" for k, v in res["stages_ms"].items()))
     del state, alm, out
@@ -225,6 +231,116 @@ def copy_calibration():
                       "GB_per_s_read_plus_write": 2 * n / dt / 1e9}), flush=True)
 
 
+def run_lowrank(args):
+    """Low-rank covariance (Sec. III B) at n_max(P): noise vectors from N beta^hat vectors,
+    the estimator for S skies, and the closed-form Cholesky rotation of S + 1 vectors.
+    The beta^hat rows are synthetic: unit Gaussian noise plus k spikes along fixed
+    orthonormal directions, scaled by sqrt(6) so that the ideal covariance is I."""
+    import numpy as np
+    import torch
+    from paper_1105_2791_amd import ModalContext
+    P, N, k, S, iters = args.P, args.lr_sims, args.lr_k, args.batch, args.lr_iters
+    ctx = ModalContext(8, 12, 24, P, "f64", np.ones((P, 9)), np.ones(9))   # only n_max(P) matters here
+    n = ctx.nmax
+    rng = np.random.default_rng(2011)
+    U, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    strengths = np.linspace(14.0, 7.0, k)
+    B = math.sqrt(6.0) * (rng.standard_normal((N, n)) + (rng.standard_normal((N, k)) * strengths) @ U.T)
+    B = torch.as_tensor(B, device="cuda")
+    alpha = torch.as_tensor(rng.standard_normal(n), device="cuda")
+    betas = torch.as_tensor(rng.standard_normal((S, n)), device="cuda")
+    X = torch.cat([alpha[None, :], betas])
+    calls = {
+        "noise_vectors": lambda: ctx.noise_vectors(B, k, iters),
+        "fnl_lowrank": lambda: ctx.fnl_lowrank(bt, alpha, betas),
+        "bivector_rotate": lambda: ctx.bivector_rotate(bt[0], X),
+    }
+    bt, mu = ctx.noise_vectors(B, k, iters)
+    times = {}
+    for name, f in calls.items():
+        for _ in range(args.warmup):
+            f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        times[name] = e0.elapsed_time(e1) / args.steps
+    gram_flop = float(N) * (N + 1) / 2 * n * 2          # lower triangle of B B^T
+    t = times["noise_vectors"] * 1e-3
+    line = {
+        "metric": "low-rank covariance (noise vectors from N beta^hat + estimator), ms per call", "unit": "ms",
+        "value": times["noise_vectors"] + times["fnl_lowrank"], "higher_is_better": False, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"n_max={n} (P={P}), N={N} beta^hat vectors, k={k} noise vectors, "
+                               f"{iters} block iterations, S={S} skies", "N": N, "k": k, "S": S, "iters": iters},
+        "ms": times, "mu": [float(m) for m in mu],
+        "roofline": {"bound": "alu", "kernel": "noise_vectors (Gram matrix dominant)", "per_launch": gram_flop,
+                     "per_launch_unit": "flop", "achieved": gram_flop / t / 1e12, "peak": PEAK["f64_vec"] / 1e12,
+                     "unit": "TFLOP/s", "frac": gram_flop / t / PEAK["f64_vec"], "traffic": None},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_power(args):
+    """Modal power-spectrum batches (Sec. IV): maps + sum_x w (M_p M_r - V_pr) for S skies."""
+    res = run_path(args, args.prec, args.steps, args.warmup, make_state=not args.no_linear, op="power")
+    pair = dict(res["kernels"]["cubic"])
+    pair["kernel"] = "pair sums (k_pair_sums + k_pair_reduce)"
+    line = {
+        "metric": "modal power spectrum: sim maps/sec (filter + pair sums) @lmax=1000,P=40", "unit": "maps/s",
+        "value": res["value"], "ms_per_step": res["ms_per_step"], "higher_is_better": True, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"bf16x3": "bf16", "f16x3": "f16", "f32": "f32", "f64": "f64"}[args.prec], "data": "synthetic",
+        "config": {"workload": f"lmax={args.lmax} GL {args.ntheta}x{args.nphi} P={args.P} npairs={res['npairs']}, "
+                               f"beam+noise spectrum, |lat|<10deg cut, MC pair means ({args.mc} skies)",
+                   "batch": args.batch, "prec": args.prec},
+        "stages_ms": res["stages_ms"], "roofline": pair, "kernels": res["kernels"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_shapes(args):
+    """Theory side at the workload shape: alpha_n of a three-term separable shape and the
+    ideal covariance zeta0 (n_max x n_max) of the separable modes."""
+    import numpy as np
+    import torch
+    import modal_inputs as mi
+    from paper_1105_2791_amd import ModalContext
+    lmax, P = args.lmax, args.P
+    cl = mi.filter_cl(lmax, "wmap")
+    ctx = ModalContext(lmax, args.ntheta, args.nphi, P, "f32", mi.q_basis(P, lmax), cl)
+    one = np.ones(lmax + 1)
+    terms = np.array([[2 * cl, cl, one], [2 * cl, one, cl], [2 * one, cl, cl]])
+    times = {}
+    for name, f in (("alpha_separable", lambda: ctx.alpha_separable(terms)), ("ideal_covariance", ctx.ideal_covariance)):
+        for _ in range(args.warmup):
+            f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            f()
+        torch.cuda.synchronize()
+        times[name] = 1e3 * (time.perf_counter() - t0) / args.steps
+    nmu = (3 * lmax + 2) // 2
+    n = ctx.nmax
+    flop = n * (n + 1) / 2 * nmu * 16.0     # 4 mul + 6 fma per (pair of modes, node)
+    t = times["ideal_covariance"] * 1e-3
+    line = {
+        "metric": "theory side: alpha_n (3 separable terms) and ideal covariance, ms per call", "unit": "ms",
+        "value": times["ideal_covariance"], "higher_is_better": False, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"lmax={lmax} P={P} nmax={n}, {nmu} Gauss-Legendre nodes in mu"},
+        "ms": times,
+        "roofline": {"bound": "alu", "kernel": "ideal_covariance (k_ideal_cov dominant)", "per_launch": flop,
+                     "per_launch_unit": "flop", "achieved": flop / t / 1e12, "peak": PEAK["f64_vec"] / 1e12,
+                     "unit": "TFLOP/s", "frac": flop / t / PEAK["f64_vec"], "traffic": None},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,6 +361,12 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of a known size (HBM counter calibration)")
     ap.add_argument("--no-linear", action="store_true", help="beta without the linear term (diagnostic)")
+    ap.add_argument("--workload", default="beta", choices=["beta", "lowrank", "power", "shapes"],
+                    help="beta: the hot path (default); lowrank: the low-rank covariance calls; "
+                         "power: the modal power spectrum; shapes: alpha_n and the ideal covariance")
+    ap.add_argument("--lr-sims", type=int, default=1000, help="lowrank: beta^hat vectors N")
+    ap.add_argument("--lr-k", type=int, default=4, help="lowrank: noise vectors k")
+    ap.add_argument("--lr-iters", type=int, default=100, help="lowrank: block iterations")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -255,6 +377,15 @@ def main():
     torch.cuda.set_device(torch.device("cuda", 0))
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "lowrank":
+        run_lowrank(args)
+        return
+    if args.workload == "power":
+        run_power(args)
+        return
+    if args.workload == "shapes":
+        run_shapes(args)
         return
     prec = args.prec
     head = run_path(args, prec, args.steps, args.warmup, make_state=not args.no_linear)

@@ -100,7 +100,13 @@ typedef enum {
   MODAL_OP_FNL = 7,
   MODAL_OP_LINEAR_FINALIZE = 8,
   MODAL_OP_NOISE_VECTORS = 9,   /* S is the number N of beta^hat vectors            */
-  MODAL_OP_FNL_LOWRANK = 10
+  MODAL_OP_FNL_LOWRANK = 10,
+  MODAL_OP_ALPHA_SEPARABLE = 11,   /* S is the number T of separable terms          */
+  MODAL_OP_IDEAL_COVARIANCE = 12,
+  MODAL_OP_POWER_BETA = 13,
+  MODAL_OP_POWER_ALPHA = 14,
+  MODAL_OP_POWER_COVARIANCE = 15,
+  MODAL_OP_POWER_FNL = 16
 } modal_op;
 
 typedef enum {
@@ -289,6 +295,66 @@ modal_status modal_bivector_rotate(modal_ctx* ctx, const double* b_dev, const do
  * Errors: EINVAL, EDEVICE. */
 modal_status modal_whiten(modal_ctx* ctx, const double* L_dev, const double* x_dev, int R, double* y_dev,
                           modal_stream_t stream);
+
+/* Theory mode coefficients alpha_n (eq. abispect, v_l = 1) of a separable reduced
+ * bispectrum b_{l1 l2 l3} = sum_t X_t(l1) Y_t(l2) Z_t(l3), symmetrised over the
+ * order of (l1, l2, l3), whitened by the context's C_l (terms with C_l = 0 drop):
+ *   alpha_prs = sum_{l1 l2 l3} h^2_{l1 l2 l3} bbar / sqrt(C_l1 C_l2 C_l3) q_p(l1) q_r(l2) q_s(l3),
+ * evaluated exactly through the Legendre triple integral on a Gauss-Legendre rule in
+ * mu with (3 lmax + 2) / 2 nodes.
+ *   terms_host [T][3][lmax+1] (host, X_t, Y_t, Z_t), 1 <= T <= 64; alpha_dev [nmax] float64.
+ * Synchronises the stream.  Workspace: modal_workspace_size(MODAL_OP_ALPHA_SEPARABLE, T).
+ * Errors: EINVAL, ENOSPACE, EDEVICE. */
+modal_status modal_alpha_separable(modal_ctx* ctx, const double* terms_host, int T, double* alpha_dev, void* ws_dev,
+                                   size_t ws_bytes, modal_stream_t stream);
+
+/* Ideal modal covariance: zeta0 = <beta beta^T> / 6 for full-sky isotropic Gaussian skies
+ * whose whitened coefficients have <|a~_lm|^2> = c_l (eq. cbispect with a diagonal
+ * covariance), i.e. the Gram matrix of the separable modes under h^2 c c c:
+ *   zeta0_nn' = (1/6) sum_{l1 l2 l3} h^2 c_l1 c_l2 c_l3 sum_{sigma in S3} Q_n(l) Q_n'(sigma l),
+ * Q_prs(l) = q_p(l1) q_r(l2) q_s(l3).  Its Cholesky factor orthonormalises the basis
+ * (Sec. II) and gives the frame where the ideal covariance is the identity
+ * (modal_fnl + modal_whiten).  c_host [lmax+1] (host) or NULL: c_l = 1 where C_l > 0.
+ *   zeta_dev [nmax][nmax] float64.  Synchronises the stream.
+ *   Workspace: modal_workspace_size(MODAL_OP_IDEAL_COVARIANCE, 0).
+ * Errors: EINVAL, ENOSPACE, EDEVICE. */
+modal_status modal_ideal_covariance(modal_ctx* ctx, const double* c_host, double* zeta_dev, void* ws_dev,
+                                    size_t ws_bytes, modal_stream_t stream);
+
+/* Modal power-spectrum estimator (Sec. IV, the quadratic analogue of the bispectrum
+ * one).
+ *
+ * modal_power_beta: for every pair p <= r (npairs = P (P + 1) / 2, ordered as for the
+ * linear-term state) beta_pr = sum_x w(x) (M_p M_r - V_pr) for S maps, with the
+ * filtered maps of modal_filter_maps and V the Monte-Carlo pair means of a finalised
+ * linear-term state (state_dev NULL: no subtraction).  The mean term is read from
+ * the state's harmonic transform (sum_x w V_pr = sqrt(4 pi) Re Z_pr,00), not from V.
+ *   beta_dev [S][npairs] float64.  Workspace: modal_workspace_size(MODAL_OP_POWER_BETA, S).
+ *   Errors: EINVAL, ENOTREADY, ENOSPACE, EUNSUPPORTED, EDEVICE.
+ * The estimator's modes are the paper's isotropic R_n(l) = q_0(l) q_n(l), n < P: the
+ * pairs (0, n), i.e. the first P entries of each row of beta (on the full sky the other
+ * pairs are linearly dependent on these and on each other).
+ * modal_power_alpha: alpha_n = sum_l (2l+1) q_0(l) q_n(l) dcl(l) / C_l for a spectral
+ *   deviation dcl_host [lmax+1] (host) = C~_l - C_l; alpha_dev [P].  Synchronises.
+ *   Workspace: modal_workspace_size(MODAL_OP_POWER_ALPHA, 0).
+ * modal_power_ideal_covariance: zeta = <beta beta^T> / 2 on those modes for full-sky
+ *   Gaussian skies with whitened spectrum c_l (c_host [lmax+1] or NULL: 1 where C_l > 0):
+ *   zeta_nn' = sum_l (2l+1) c_l^2 R_n(l) R_n'(l); zeta_dev [P][P].  Synchronises.
+ *   Workspace: modal_workspace_size(MODAL_OP_POWER_COVARIANCE, 0).
+ * modal_power_fnl: E_s = alpha^T zeta^-1 beta_s / alpha^T zeta^-1 alpha and
+ *   sigma^2 = 2 / alpha^T zeta^-1 alpha by FP64 Cholesky (as modal_fnl) on the P modes;
+ *   beta_dev is the [S][npairs] output of modal_power_beta (its first P columns are used).
+ *   Synchronises.  Workspace: modal_workspace_size(MODAL_OP_POWER_FNL, S).
+ *   Errors: EINVAL, ENOTPD, ENOSPACE, EDEVICE. */
+modal_status modal_power_beta(modal_ctx* ctx, const void* alm_dev, int S, const void* state_dev, double* beta_dev,
+                              void* ws_dev, size_t ws_bytes, modal_stream_t stream);
+modal_status modal_power_alpha(modal_ctx* ctx, const double* dcl_host, double* alpha_dev, void* ws_dev,
+                               size_t ws_bytes, modal_stream_t stream);
+modal_status modal_power_ideal_covariance(modal_ctx* ctx, const double* c_host, double* zeta_dev, void* ws_dev,
+                                          size_t ws_bytes, modal_stream_t stream);
+modal_status modal_power_fnl(modal_ctx* ctx, const double* zeta_dev, const double* alpha_dev, const double* beta_dev,
+                             int S, double* E_host, double* sigma2_host, void* ws_dev, size_t ws_bytes,
+                             modal_stream_t stream);
 
 /* Autotuner: times modal_beta on the caller's inputs (same arguments and
  * workspace as modal_beta) for each candidate launch configuration - pixels

@@ -16,7 +16,9 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "modal.h")
 OK, EINVAL, ESHAPE, EDEVICE, ENOTPD, ENOTREADY, EUNSUPPORTED, ENOSPACE = range(8)
 F64, F32, BF16X3, F16X3 = range(4)
 OP_FILTER_MAPS, OP_BETA, OP_LINEAR_ACCUMULATE, OP_LINEAR_APPLY, OP_BETA_VJP, \
-    OP_COVARIANCE_SAMPLE, OP_COVARIANCE_FISHER, OP_FNL, OP_LINEAR_FINALIZE, OP_NOISE_VECTORS, OP_FNL_LOWRANK = range(11)
+    OP_COVARIANCE_SAMPLE, OP_COVARIANCE_FISHER, OP_FNL, OP_LINEAR_FINALIZE, OP_NOISE_VECTORS, OP_FNL_LOWRANK, \
+    OP_ALPHA_SEPARABLE, OP_IDEAL_COVARIANCE, OP_POWER_BETA, OP_POWER_ALPHA, OP_POWER_COVARIANCE, \
+    OP_POWER_FNL = range(17)
 LIN_RESET, LIN_ACCUMULATE, LIN_FINALIZE, LIN_APPLY = range(4)
 COV_SAMPLE, COV_FISHER = range(2)
 
@@ -67,6 +69,12 @@ _SIGS = {
     "modal_fnl_lowrank": (ip, [vp, vp, ip, vp, vp, ip, vp, vp, vp, sz, vp]),
     "modal_bivector_rotate": (ip, [vp, vp, vp, ip, vp, vp]),
     "modal_whiten": (ip, [vp, vp, vp, ip, vp, vp]),
+    "modal_alpha_separable": (ip, [vp, vp, ip, vp, vp, sz, vp]),
+    "modal_ideal_covariance": (ip, [vp, vp, vp, vp, sz, vp]),
+    "modal_power_beta": (ip, [vp, vp, ip, vp, vp, vp, sz, vp]),
+    "modal_power_alpha": (ip, [vp, vp, vp, vp, sz, vp]),
+    "modal_power_ideal_covariance": (ip, [vp, vp, vp, vp, sz, vp]),
+    "modal_power_fnl": (ip, [vp, vp, vp, vp, ip, vp, vp, vp, sz, vp]),
 }
 
 STAGES = ["legendre", "fft", "cubic", "reduce", "linacc", "adj_pair", "adj_fft", "adj_legendre",

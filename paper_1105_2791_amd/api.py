@@ -261,6 +261,79 @@ class ModalContext:
                                                     self._stream()))
         return y
 
+    def alpha_separable(self, terms) -> torch.Tensor:
+        """alpha_n of b = sum_t X_t(l1) Y_t(l2) Z_t(l3) (terms [T][3][lmax+1], host array)."""
+        tm = np.ascontiguousarray(terms, dtype=np.float64)
+        if tm.ndim != 3 or tm.shape[1:] != (3, self.lmax + 1):
+            raise ValueError("terms must be [T][3][lmax+1]")
+        T = tm.shape[0]
+        a = torch.empty(self.nmax, dtype=torch.float64, device=self.device)
+        ws = self.workspace(L.OP_ALPHA_SEPARABLE, T)
+        self._check(self._lib.modal_alpha_separable(self._h, tm.ctypes.data, T, _ptr(a), _ptr(ws), ws.numel(),
+                                                    self._stream()))
+        return a
+
+    def ideal_covariance(self, c=None) -> torch.Tensor:
+        """zeta0 [nmax][nmax] for full-sky skies with <|a~_lm|^2> = c_l (default 1 where C_l > 0)."""
+        cv = None
+        if c is not None:
+            cv = np.ascontiguousarray(c, dtype=np.float64)
+            if cv.shape != (self.lmax + 1,):
+                raise ValueError("c must have lmax+1 entries")
+        z = torch.empty((self.nmax, self.nmax), dtype=torch.float64, device=self.device)
+        ws = self.workspace(L.OP_IDEAL_COVARIANCE, 0)
+        self._check(self._lib.modal_ideal_covariance(self._h, None if cv is None else cv.ctypes.data, _ptr(z),
+                                                     _ptr(ws), ws.numel(), self._stream()))
+        return z
+
+    # -- modal power spectrum (Sec. IV) ------------------------------------------------
+
+    def power_beta(self, alm, state=None, out=None) -> torch.Tensor:
+        """beta_pr = sum_x w (M_p M_r - V_pr) [S][npairs] (V from a finalised linear-term state)."""
+        a = self._alm(alm)
+        S = a.shape[0]
+        b = out if out is not None else torch.empty((S, self.npairs), dtype=torch.float64, device=self.device)
+        ws = self.workspace(L.OP_POWER_BETA, S)
+        self._check(self._lib.modal_power_beta(self._h, _ptr(a), S, _ptr(state), _ptr(b), _ptr(ws), ws.numel(),
+                                               self._stream()))
+        return b
+
+    def power_alpha(self, dcl) -> torch.Tensor:
+        """alpha_n [P] on the modes (0, n) for a spectral deviation dcl = C~_l - C_l."""
+        d = np.ascontiguousarray(dcl, dtype=np.float64)
+        if d.shape != (self.lmax + 1,):
+            raise ValueError("dcl must have lmax+1 entries")
+        a = torch.empty(self.P, dtype=torch.float64, device=self.device)
+        ws = self.workspace(L.OP_POWER_ALPHA, 0)
+        self._check(self._lib.modal_power_alpha(self._h, d.ctypes.data, _ptr(a), _ptr(ws), ws.numel(),
+                                                self._stream()))
+        return a
+
+    def power_ideal_covariance(self, c=None) -> torch.Tensor:
+        cv = None
+        if c is not None:
+            cv = np.ascontiguousarray(c, dtype=np.float64)
+            if cv.shape != (self.lmax + 1,):
+                raise ValueError("c must have lmax+1 entries")
+        z = torch.empty((self.P, self.P), dtype=torch.float64, device=self.device)
+        ws = self.workspace(L.OP_POWER_COVARIANCE, 0)
+        self._check(self._lib.modal_power_ideal_covariance(self._h, None if cv is None else cv.ctypes.data, _ptr(z),
+                                                           _ptr(ws), ws.numel(), self._stream()))
+        return z
+
+    def power_fnl(self, zeta, alpha, beta):
+        """E_s and sigma^2 on the modes (0, n); beta is the [S][npairs] output of power_beta."""
+        z = torch.as_tensor(zeta).to(device=self.device, dtype=torch.float64).contiguous()
+        al = torch.as_tensor(alpha).to(device=self.device, dtype=torch.float64).contiguous()
+        b = torch.as_tensor(beta).to(device=self.device, dtype=torch.float64).reshape(-1, self.npairs).contiguous()
+        S = b.shape[0]
+        E = np.zeros(S)
+        s2 = np.zeros(1)
+        ws = self.workspace(L.OP_POWER_FNL, S)
+        self._check(self._lib.modal_power_fnl(self._h, _ptr(z), _ptr(al), _ptr(b), S, E.ctypes.data, s2.ctypes.data,
+                                              _ptr(ws), ws.numel(), self._stream()))
+        return E, float(s2[0])
+
     def whiten(self, Lfac, x) -> torch.Tensor:
         """Rows of x multiplied by L^-1 (L lower triangular, as returned by fnl(want_L=True))."""
         Lv = torch.as_tensor(Lfac).to(device=self.device, dtype=torch.float64).contiguous()

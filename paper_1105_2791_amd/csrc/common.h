@@ -73,6 +73,7 @@ struct modal_ctx {
   modal::FftPlan fft_rg_plan{};
   modal::Tables t{};
   std::vector<double> x_host, wgl_host;
+  std::vector<double> q_host, cl_host;   // the mode functions and filter spectrum given at creation
   std::string last_error;
   // per-stage timing (modal_profile_enable)
   bool profile = false;
@@ -201,6 +202,25 @@ size_t lowrank_ws_bytes(int S);
 hipError_t launch_fnl_lowrank(int n, int k, const double* bt, const double* alpha, const double* beta, int S,
                               double* ws, double* out, hipStream_t st);
 hipError_t launch_bivector_rotate(int n, const double* b, const double* x, int R, double* y, hipStream_t st);
+
+// theory mode coefficients of separable shapes and the ideal covariance (1-D Legendre integrals)
+int shapes_nmu(int lmax);
+hipError_t launch_legendre_series(int L, int nmu, int P, int nf, const double* U, const double* B, const double* mu,
+                                  double* F, hipStream_t st);
+hipError_t launch_alpha_modes(int nmax, int P, int T, int nmu, const int* tri, const double* F, const double* wmu,
+                              double* alpha, hipStream_t st);
+hipError_t launch_ideal_cov(int nmax, int P, int nmu, const int* tri, const double* F, const double* wmu, double* Z,
+                            hipStream_t st);
+
+// modal power spectrum (quadratic pixel reduction)
+int power_chunk_px();
+size_t power_part_bytes(int P, int npix, int S);
+size_t power_lds(int P, bool f64);
+hipError_t power_set_lds();
+hipError_t launch_power_beta(const modal_ctx* c, const void* maps, int S, const void* zstate, double* part,
+                             double* beta, hipStream_t st);
+hipError_t launch_power_alpha(const modal_ctx* c, const double* dcl, double* alpha, hipStream_t st);
+hipError_t launch_power_rows(const modal_ctx* c, const double* q, const double* cw, double* X, hipStream_t st);
 
 // helpers
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }

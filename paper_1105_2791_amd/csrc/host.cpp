@@ -23,39 +23,44 @@ namespace {
 
 const double kPi = 3.14159265358979323846;
 
-// Gauss-Legendre nodes (descending) and weights by Newton iteration on P_n.
+// Gauss-Legendre nodes (descending) and weights by Newton iteration on P_n, carried out
+// in x87 extended precision: the weights 2 / ((1 - z^2) P_n'(z)^2) near the poles lose
+// about n^2 ulps when P_n' is evaluated at a node rounded to double (3.7e-11 relative
+// at n = 1501 in double, below the double rounding in extended precision).
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  typedef long double R;
   x.assign(n, 0.0);
   w.assign(n, 0.0);
+  const R pi = 3.141592653589793238462643383279502884L;
   for (int i = 0; i < (n + 1) / 2; ++i) {
-    double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
-    double pp = 1.0;
+    R z = std::cos(pi * (i + 0.75L) / (n + 0.5L));
+    R pp = 1.0L;
     for (int it = 0; it < 100; ++it) {
-      double p1 = 1.0, p2 = 0.0;
+      R p1 = 1.0L, p2 = 0.0L;
       for (int j = 1; j <= n; ++j) {
-        const double p3 = p2;
+        const R p3 = p2;
         p2 = p1;
-        p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+        p1 = ((2.0L * j - 1.0L) * z * p2 - (j - 1.0L) * p3) / j;
       }
-      pp = n * (z * p1 - p2) / (z * z - 1.0);
-      const double z1 = z;
+      pp = n * (z * p1 - p2) / (z * z - 1.0L);
+      const R z1 = z;
       z = z1 - p1 / pp;
-      if (std::fabs(z - z1) < 1e-16) {
+      if (std::fabs(z - z1) < 1e-19L) {
         // one more evaluation of the derivative at the converged node
-        p1 = 1.0;
-        p2 = 0.0;
+        p1 = 1.0L;
+        p2 = 0.0L;
         for (int j = 1; j <= n; ++j) {
-          const double p3 = p2;
+          const R p3 = p2;
           p2 = p1;
-          p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+          p1 = ((2.0L * j - 1.0L) * z * p2 - (j - 1.0L) * p3) / j;
         }
-        pp = n * (z * p1 - p2) / (z * z - 1.0);
+        pp = n * (z * p1 - p2) / (z * z - 1.0L);
         break;
       }
     }
-    x[i] = z;
-    x[n - 1 - i] = -z;
-    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * pp * pp);
+    x[i] = (double)z;
+    x[n - 1 - i] = -(double)z;
+    w[i] = w[n - 1 - i] = (double)(2.0L / ((1.0L - z * z) * pp * pp));
   }
   if (n & 1) x[n / 2] = 0.0;
 }
@@ -164,6 +169,29 @@ size_t ws_size(const modal_ctx* c, int op, int S) {
       break;
     case MODAL_OP_NOISE_VECTORS: cv.take(noise_ws_bytes(S)); break;
     case MODAL_OP_FNL_LOWRANK: cv.take(lowrank_ws_bytes(S)); break;
+    case MODAL_OP_ALPHA_SEPARABLE: {
+      const size_t nmu = shapes_nmu(c->lmax), L = c->lmax + 1;
+      cv.take(nmu * 8); cv.take(nmu * 8); cv.take(3 * (size_t)S * L * 8); cv.take(3 * (size_t)S * nmu * c->P * 8);
+      break;
+    }
+    case MODAL_OP_POWER_BETA:
+      cv.take(F_bytes(c, S)); cv.take(maps_bytes(c, S)); cv.take(power_part_bytes(c->P, c->npix, S));
+      break;
+    case MODAL_OP_POWER_ALPHA: cv.take((size_t)(c->lmax + 1) * 8); break;
+    case MODAL_OP_POWER_COVARIANCE:
+      cv.take((size_t)c->P * (c->lmax + 1) * 8); cv.take((size_t)(c->lmax + 1) * 8);
+      cv.take((size_t)(c->lmax + 1) * c->P * 8);
+      break;
+    case MODAL_OP_POWER_FNL:
+      cv.take((size_t)c->P * c->P * 8); cv.take((size_t)(S + 1) * c->P * 8); cv.take((size_t)(S + 1) * 8);
+      cv.take(16);
+      break;
+    case MODAL_OP_IDEAL_COVARIANCE: {
+      const size_t nmu = shapes_nmu(c->lmax), L = c->lmax + 1;
+      cv.take(nmu * 8); cv.take(nmu * 8); cv.take((size_t)c->P * L * 8); cv.take((size_t)c->P * L * 8);
+      cv.take((size_t)c->P * nmu * c->P * 8);
+      break;
+    }
     default: return 0;
   }
   return cv.used;
@@ -357,6 +385,8 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
     }
   }
   // --- whitened mode functions
+  c->q_host.assign(q_host, q_host + (size_t)P * (lmax + 1));
+  c->cl_host.assign(cl_host, cl_host + lmax + 1);
   std::vector<double> qw64((size_t)P * (lmax + 1));
   std::vector<float> qw32(qw64.size());
   for (int p = 0; p < P; ++p)
@@ -500,7 +530,7 @@ modal_status modal_grid(const modal_ctx* c, double* x_host, double* w_host) {
 }
 
 modal_status modal_workspace_size(const modal_ctx* c, int op, int S, size_t* bytes) {
-  if (!c || !bytes || S < 0 || op < MODAL_OP_FILTER_MAPS || op > MODAL_OP_FNL_LOWRANK) return MODAL_EINVAL;
+  if (!c || !bytes || S < 0 || op < MODAL_OP_FILTER_MAPS || op > MODAL_OP_POWER_FNL) return MODAL_EINVAL;
   *bytes = ws_size(c, op, S);
   return MODAL_OK;
 }
@@ -677,17 +707,16 @@ modal_status modal_covariance(modal_ctx* c, int method, const double* beta, cons
   return fail(c, MODAL_EINVAL, "covariance: bad method");
 }
 
-modal_status modal_fnl(modal_ctx* c, const double* zeta, const double* alpha, const double* beta, int S,
-                       double* E_host, double* sigma2_host, double* L_dev, void* ws, size_t ws_bytes,
-                       modal_stream_t stream) {
-  if (!c) return MODAL_EINVAL;
+// Cholesky estimator for n modes: E_s = y.z_s / y.y, sigma^2 = factor / y.y (factor = 3! or 2!,
+// the number of cross pairings of the legs).
+modal_status estimate(modal_ctx* c, int op, int n, double factor, const double* zeta, const double* alpha,
+                      const double* beta, int beta_stride, int S, double* E_host, double* sigma2_host, double* L_dev,
+                      void* ws, size_t ws_bytes, hipStream_t st) {
   if (!zeta || !alpha || !sigma2_host || S < 0 || (S > 0 && (!beta || !E_host)))
     return fail(c, MODAL_EINVAL, "fnl: null pointer or S < 0");
-  modal_status s = check_ws(c, MODAL_OP_FNL, S, ws, ws_bytes);
+  modal_status s = check_ws(c, op, S, ws, ws_bytes);
   if (s != MODAL_OK) return s;
   if ((s = set_device(c)) != MODAL_OK) return s;
-  hipStream_t st = (hipStream_t)stream;
-  const int n = c->nmax;
   Carver cv(ws);
   double* L = (double*)cv.take((size_t)n * n * 8);
   double* rows = (double*)cv.take((size_t)(S + 1) * n * 8);
@@ -696,7 +725,9 @@ modal_status modal_fnl(modal_ctx* c, const double* zeta, const double* alpha, co
   HIPTRY(launch_zero(flag, 16, st));
   HIPTRY(hipMemcpyAsync(L, zeta, (size_t)n * n * 8, hipMemcpyDeviceToDevice, st));
   HIPTRY(hipMemcpyAsync(rows, alpha, (size_t)n * 8, hipMemcpyDeviceToDevice, st));
-  if (S > 0) HIPTRY(hipMemcpyAsync(rows + n, beta, (size_t)S * n * 8, hipMemcpyDeviceToDevice, st));
+  if (S > 0)
+    HIPTRY(hipMemcpy2DAsync(rows + n, (size_t)n * 8, beta, (size_t)beta_stride * 8, (size_t)n * 8, S,
+                            hipMemcpyDeviceToDevice, st));
   {
     StageTimer _t(c, MODAL_STAGE_CHOLESKY, st);
     HIPTRY(launch_cholesky(n, L, flag, st));
@@ -712,9 +743,88 @@ modal_status modal_fnl(modal_ctx* c, const double* zeta, const double* alpha, co
   if (hflag[0] != 0)
     return fail(c, MODAL_ENOTPD, "fnl: zeta is not positive definite at pivot " + std::to_string(hflag[0] - 1));
   const double yy = h[0];
-  *sigma2_host = 6.0 / yy;
+  *sigma2_host = factor / yy;
   for (int i = 0; i < S; ++i) E_host[i] = h[1 + i] / yy;
   return MODAL_OK;
+}
+
+modal_status modal_fnl(modal_ctx* c, const double* zeta, const double* alpha, const double* beta, int S,
+                       double* E_host, double* sigma2_host, double* L_dev, void* ws, size_t ws_bytes,
+                       modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  return estimate(c, MODAL_OP_FNL, c->nmax, 6.0, zeta, alpha, beta, c->nmax, S, E_host, sigma2_host, L_dev, ws,
+                  ws_bytes, (hipStream_t)stream);
+}
+
+modal_status modal_power_beta(modal_ctx* c, const void* alm, int S, const void* state, double* beta, void* ws,
+                              size_t ws_bytes, modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (!alm || !beta || S <= 0) return fail(c, MODAL_EINVAL, "power_beta: null pointer or S <= 0");
+  modal_status s = check_state(c, state);
+  if (s != MODAL_OK) return s;
+  if ((s = check_ws(c, MODAL_OP_POWER_BETA, S, ws, ws_bytes)) != MODAL_OK) return s;
+  if ((s = set_device(c)) != MODAL_OK) return s;
+  if (power_lds(c->P, is_f64(c)) > c->max_lds) return fail(c, MODAL_EUNSUPPORTED, "power_beta: LDS too small");
+  HIPTRY(power_set_lds());
+  hipStream_t st = (hipStream_t)stream;
+  Carver cv(ws);
+  void* F = cv.take(F_bytes(c, S));
+  void* maps = cv.take(maps_bytes(c, S));
+  double* part = (double*)cv.take(power_part_bytes(c->P, c->npix, S));
+  if ((s = run_maps(c, alm, S, F, maps, st)) != MODAL_OK) return s;
+  {
+    StageTimer _t(c, MODAL_STAGE_CUBIC, st);
+    HIPTRY(launch_power_beta(c, maps, S, state ? lin_Z(c, state) : nullptr, part, beta, st));
+  }
+  return MODAL_OK;
+}
+
+modal_status modal_power_alpha(modal_ctx* c, const double* dcl, double* alpha, void* ws, size_t ws_bytes,
+                               modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (!dcl || !alpha) return fail(c, MODAL_EINVAL, "power_alpha: null pointer");
+  modal_status s = check_ws(c, MODAL_OP_POWER_ALPHA, 0, ws, ws_bytes);
+  if (s != MODAL_OK) return s;
+  if ((s = set_device(c)) != MODAL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  double* d = (double*)ws;
+  HIPTRY(hipMemcpyAsync(d, dcl, (size_t)(c->lmax + 1) * 8, hipMemcpyHostToDevice, st));
+  HIPTRY(launch_power_alpha(c, d, alpha, st));
+  HIPTRY(hipStreamSynchronize(st));
+  return MODAL_OK;
+}
+
+modal_status modal_power_ideal_covariance(modal_ctx* c, const double* c_host, double* zeta, void* ws, size_t ws_bytes,
+                                          modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (!zeta) return fail(c, MODAL_EINVAL, "power_ideal_covariance: null pointer");
+  modal_status s = check_ws(c, MODAL_OP_POWER_COVARIANCE, 0, ws, ws_bytes);
+  if (s != MODAL_OK) return s;
+  if ((s = set_device(c)) != MODAL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const int L = c->lmax + 1;
+  std::vector<double> cw(L);
+  for (int l = 0; l < L; ++l) cw[l] = c_host ? c_host[l] : (c->cl_host[l] > 0.0 ? 1.0 : 0.0);
+  Carver cv(ws);
+  double* q = (double*)cv.take((size_t)c->P * L * 8);
+  double* dc = (double*)cv.take((size_t)L * 8);
+  double* X = (double*)cv.take((size_t)L * c->P * 8);
+  HIPTRY(hipMemcpyAsync(q, c->q_host.data(), (size_t)c->P * L * 8, hipMemcpyHostToDevice, st));
+  HIPTRY(hipMemcpyAsync(dc, cw.data(), (size_t)L * 8, hipMemcpyHostToDevice, st));
+  {
+    StageTimer _t(c, MODAL_STAGE_COVARIANCE, st);
+    HIPTRY(launch_power_rows(c, q, dc, X, st));
+    HIPTRY(launch_syrk(c->P, L, X, 1.0, zeta, st));
+  }
+  HIPTRY(hipStreamSynchronize(st));
+  return MODAL_OK;
+}
+
+modal_status modal_power_fnl(modal_ctx* c, const double* zeta, const double* alpha, const double* beta, int S,
+                             double* E_host, double* sigma2_host, void* ws, size_t ws_bytes, modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  return estimate(c, MODAL_OP_POWER_FNL, c->P, 2.0, zeta, alpha, beta, c->npairs, S, E_host, sigma2_host, nullptr,
+                  ws, ws_bytes, (hipStream_t)stream);
 }
 
 modal_status modal_noise_vectors(modal_ctx* c, const double* beta, int N, int k, int iters, double* bt,
@@ -772,6 +882,71 @@ modal_status modal_bivector_rotate(modal_ctx* c, const double* b, const double* 
   modal_status s = set_device(c);
   if (s != MODAL_OK) return s;
   HIPTRY(launch_bivector_rotate(c->nmax, b, x, R, y, (hipStream_t)stream));
+  return MODAL_OK;
+}
+
+modal_status modal_alpha_separable(modal_ctx* c, const double* terms, int T, double* alpha, void* ws, size_t ws_bytes,
+                                   modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (!terms || !alpha || T < 1 || T > 64) return fail(c, MODAL_EINVAL, "alpha_separable: null pointer or T not in 1..64");
+  modal_status s = check_ws(c, MODAL_OP_ALPHA_SEPARABLE, T, ws, ws_bytes);
+  if (s != MODAL_OK) return s;
+  if ((s = set_device(c)) != MODAL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const int L = c->lmax + 1, nmu = shapes_nmu(c->lmax);
+  std::vector<double> mu, wmu;
+  gauss_legendre(nmu, mu, wmu);
+  Carver cv(ws);
+  double* dmu = (double*)cv.take((size_t)nmu * 8);
+  double* dw = (double*)cv.take((size_t)nmu * 8);
+  double* U = (double*)cv.take(3 * (size_t)T * L * 8);
+  double* F = (double*)cv.take(3 * (size_t)T * nmu * c->P * 8);
+  HIPTRY(hipMemcpyAsync(dmu, mu.data(), (size_t)nmu * 8, hipMemcpyHostToDevice, st));
+  HIPTRY(hipMemcpyAsync(dw, wmu.data(), (size_t)nmu * 8, hipMemcpyHostToDevice, st));
+  HIPTRY(hipMemcpyAsync(U, terms, 3 * (size_t)T * L * 8, hipMemcpyHostToDevice, st));
+  {
+    StageTimer _t(c, MODAL_STAGE_COVARIANCE, st);
+    HIPTRY(launch_legendre_series(L, nmu, c->P, 3 * T, U, c->t.qw64, dmu, F, st));
+    HIPTRY(launch_alpha_modes(c->nmax, c->P, T, nmu, c->t.tri, F, dw, alpha, st));
+  }
+  HIPTRY(hipStreamSynchronize(st));
+  return MODAL_OK;
+}
+
+modal_status modal_ideal_covariance(modal_ctx* c, const double* c_host, double* zeta, void* ws, size_t ws_bytes,
+                                    modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (!zeta) return fail(c, MODAL_EINVAL, "ideal_covariance: null pointer");
+  modal_status s = check_ws(c, MODAL_OP_IDEAL_COVARIANCE, 0, ws, ws_bytes);
+  if (s != MODAL_OK) return s;
+  if ((s = set_device(c)) != MODAL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const int L = c->lmax + 1, nmu = shapes_nmu(c->lmax), P = c->P;
+  std::vector<double> mu, wmu;
+  gauss_legendre(nmu, mu, wmu);
+  // U_b(l) = c_l q_b(l), B_a(l) = q_a(l): F[b][k][a] = Q_ab(mu_k)
+  std::vector<double> u((size_t)P * L);
+  for (int b = 0; b < P; ++b)
+    for (int l = 0; l < L; ++l) {
+      const double cw = c_host ? c_host[l] : (c->cl_host[l] > 0.0 ? 1.0 : 0.0);
+      u[(size_t)b * L + l] = cw * c->q_host[(size_t)b * L + l];
+    }
+  Carver cv(ws);
+  double* dmu = (double*)cv.take((size_t)nmu * 8);
+  double* dw = (double*)cv.take((size_t)nmu * 8);
+  double* U = (double*)cv.take((size_t)P * L * 8);
+  double* Bq = (double*)cv.take((size_t)P * L * 8);
+  double* F = (double*)cv.take((size_t)P * nmu * P * 8);
+  HIPTRY(hipMemcpyAsync(dmu, mu.data(), (size_t)nmu * 8, hipMemcpyHostToDevice, st));
+  HIPTRY(hipMemcpyAsync(dw, wmu.data(), (size_t)nmu * 8, hipMemcpyHostToDevice, st));
+  HIPTRY(hipMemcpyAsync(U, u.data(), (size_t)P * L * 8, hipMemcpyHostToDevice, st));
+  HIPTRY(hipMemcpyAsync(Bq, c->q_host.data(), (size_t)P * L * 8, hipMemcpyHostToDevice, st));
+  {
+    StageTimer _t(c, MODAL_STAGE_COVARIANCE, st);
+    HIPTRY(launch_legendre_series(L, nmu, P, P, U, Bq, dmu, F, st));
+    HIPTRY(launch_ideal_cov(c->nmax, P, nmu, c->t.tri, F, dw, zeta, st));
+  }
+  HIPTRY(hipStreamSynchronize(st));
   return MODAL_OK;
 }
 

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void k_gram_rows(int N, int n, const double* _
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = i0 + ty * 4 + u, j = j0 + tx * 4 + v;
-      if (i < N && j < N) {
+      if (i < N && j <= i) {   // one writer per symmetric pair
         G[(size_t)i * N + j] = scale * acc[u][v];
         G[(size_t)j * N + i] = scale * acc[u][v];
       }

@@ -1,0 +1,181 @@
+// Theory mode coefficients of separable bispectra, eq. (abispect), and the ideal
+// (full-sky, isotropic) covariance of the separable modes, eq. (cbispect) with a
+// diagonal covariance, which is also their Gram matrix: its Cholesky factor
+// orthonormalises the basis (Sec. II).
+//
+// Both are triple sums over (l1, l2, l3) weighted by
+//   h^2_{l1 l2 l3} = (2l1+1)(2l2+1)(2l3+1)/(8 pi) int_{-1}^{1} P_l1 P_l2 P_l3 dmu,
+// since the squared 3j symbol (l1 l2 l3; 0 0 0)^2 is half the Legendre triple
+// integral.  The sums then factor into one-dimensional Legendre series on a
+// Gauss-Legendre rule in mu with ceil((3 lmax + 1) / 2) nodes, exact because the
+// integrand has degree at most 3 lmax:
+//   F_{f,a}(mu_k) = sum_l (2l+1) U_f(l) B_a(l) P_l(mu_k)
+//   alpha_(pqr) = 1/(48 pi) sum_k w_k sum_t sum_{sigma in S3} F_{t,sigma1,p} F_{t,sigma2,q} F_{t,sigma3,r}
+//       U = (X_t, Y_t, Z_t) for b = sum_t X_t Y_t Z_t, B_a = q_a / sqrt(C)
+//   zeta0_(abc),(def) = 1/(48 pi) sum_k w_k sum_{sigma in S3} Q_{a,sigma d} Q_{b,sigma e} Q_{c,sigma f}
+//       Q_ab = F_{b,a} with U_b = c q_b, B_a = q_a (c_l = <|a~_lm|^2> of the whitened sky)
+// FP64 throughout.  The series are O(nf P nmu lmax); alpha is O(n_max nmu T); the
+// covariance, n_max^2 nmu / 2 sums of six triple products, is the only large one
+// and is tiled 64 x 64 with the Q(mu) slices staged in LDS.
+#include "common.h"
+
+#include <algorithm>
+
+namespace modal {
+namespace {
+
+constexpr int SL = 64;   // l per staged chunk of the series kernel
+
+// F[f][k][a] = sum_l (2l+1) U[f][l] B[a][l] P_l(mu_k), a < P <= NP; one thread per node.
+template <int NP>
+__global__ __launch_bounds__(64) void k_legendre_series(int L, int nmu, int P, const double* __restrict__ U,
+                                                        const double* __restrict__ B, const double* __restrict__ mu,
+                                                        double* __restrict__ F) {
+  __shared__ double bs[SL][NP];
+  __shared__ double us[SL];
+  const int f = blockIdx.y;
+  const int k = blockIdx.x * 64 + threadIdx.x;
+  const double x = k < nmu ? mu[k] : 0.0;
+  double acc[NP];
+#pragma unroll
+  for (int a = 0; a < NP; ++a) acc[a] = 0.0;
+  double pm = 0.0, pl = 1.0;   // P_{l-1}, P_l
+  for (int l0 = 0; l0 < L; l0 += SL) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < SL * NP; e += 64) {
+      const int i = e / NP, a = e - i * NP;
+      bs[i][a] = (a < P && l0 + i < L) ? B[(size_t)a * L + l0 + i] : 0.0;
+    }
+    us[threadIdx.x] = l0 + (int)threadIdx.x < L ? U[(size_t)f * L + l0 + threadIdx.x] : 0.0;
+    __syncthreads();
+    const int n = min(SL, L - l0);
+    for (int i = 0; i < n; ++i) {
+      const int l = l0 + i;
+      const double g = (2.0 * l + 1.0) * us[i] * pl;
+#pragma unroll
+      for (int a = 0; a < NP; ++a) acc[a] = fma(g, bs[i][a], acc[a]);
+      const double pn = ((2.0 * l + 1.0) * x * pl - l * pm) / (l + 1.0);   // Bonnet's recurrence
+      pm = pl;
+      pl = pn;
+    }
+  }
+  if (k >= nmu) return;
+  double* out = F + ((size_t)f * nmu + k) * P;
+#pragma unroll
+  for (int a = 0; a < NP; ++a)
+    if (a < P) out[a] = acc[a];
+}
+
+// alpha[n] = 1/(48 pi) sum_k w_k sum_t sum_sigma F[3t + sigma1][k][p] F[3t + sigma2][k][q] F[3t + sigma3][k][r]
+__global__ __launch_bounds__(256) void k_alpha_modes(int nmax, int P, int T, int nmu, const int* __restrict__ tri,
+                                                     const double* __restrict__ F, const double* __restrict__ wmu,
+                                                     double* __restrict__ alpha) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= nmax) return;
+  const int p = tri[6 * n], q = tri[6 * n + 1], r = tri[6 * n + 2];
+  double acc = 0.0;
+  for (int k = 0; k < nmu; ++k) {
+    double s = 0.0;
+    for (int t = 0; t < T; ++t) {
+      const double* X = F + ((size_t)(3 * t) * nmu + k) * P;
+      const double* Y = X + (size_t)nmu * P;
+      const double* Z = Y + (size_t)nmu * P;
+      const double xp = X[p], xq = X[q], xr = X[r], yp = Y[p], yq = Y[q], yr = Y[r], zp = Z[p], zq = Z[q], zr = Z[r];
+      s += xp * (yq * zr + zq * yr) + yp * (xq * zr + zq * xr) + zp * (xq * yr + yq * xr);
+    }
+    acc = fma(wmu[k], s, acc);
+  }
+  alpha[n] = acc * (1.0 / (48.0 * 3.14159265358979323846));
+}
+
+// zeta0 tile (bi, bj), bj <= bi, mirrored; Q slices [KC][P][P+1] staged in dynamic LDS.
+__global__ __launch_bounds__(256) void k_ideal_cov(int nmax, int P, int nmu, int KC, const int* __restrict__ tri,
+                                                   const double* __restrict__ F, const double* __restrict__ wmu,
+                                                   double* __restrict__ Z) {
+  extern __shared__ double qs_raw[];
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  if (bj > bi) return;
+  const int PP = P + 1;
+  double* wk = qs_raw + (size_t)KC * P * PP;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  int ra[4], rb[4], rc[4], cd[4], ce[4], cf[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = min(bi * 64 + ty * 4 + u, nmax - 1), j = min(bj * 64 + tx * 4 + u, nmax - 1);
+    ra[u] = tri[6 * i] * PP;
+    rb[u] = tri[6 * i + 1] * PP;
+    rc[u] = tri[6 * i + 2] * PP;
+    cd[u] = tri[6 * j];
+    ce[u] = tri[6 * j + 1];
+    cf[u] = tri[6 * j + 2];
+  }
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < nmu; k0 += KC) {
+    const int kn = min(KC, nmu - k0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kn * P * P; e += 256) {
+      const int kk = e / (P * P), rem = e - kk * P * P, b = rem / P, a = rem - b * P;
+      qs_raw[(size_t)kk * P * PP + a * PP + b] = F[((size_t)b * nmu + k0 + kk) * P + a];   // Q_ab(mu_k)
+    }
+    if ((int)threadIdx.x < kn) wk[threadIdx.x] = wmu[k0 + threadIdx.x];
+    __syncthreads();
+    for (int kk = 0; kk < kn; ++kk) {
+      const double* Q = qs_raw + (size_t)kk * P * PP;
+      const double w = wk[kk];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double* qa = Q + ra[u];
+          const double* qb = Q + rb[u];
+          const double* qc = Q + rc[u];
+          const int d = cd[v], e = ce[v], f = cf[v];
+          const double s = qa[d] * (qb[e] * qc[f] + qb[f] * qc[e]) + qa[e] * (qb[d] * qc[f] + qb[f] * qc[d]) +
+                           qa[f] * (qb[d] * qc[e] + qb[e] * qc[d]);
+          acc[u][v] = fma(w, s, acc[u][v]);
+        }
+    }
+  }
+  const double scale = 1.0 / (48.0 * 3.14159265358979323846);
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = bi * 64 + ty * 4 + u, j = bj * 64 + tx * 4 + v;
+      if (i < nmax && j <= i) {   // one writer per symmetric pair
+        Z[(size_t)i * nmax + j] = scale * acc[u][v];
+        Z[(size_t)j * nmax + i] = scale * acc[u][v];
+      }
+    }
+}
+
+}  // namespace
+
+int shapes_nmu(int lmax) { return (3 * lmax + 2) / 2; }
+
+hipError_t launch_legendre_series(int L, int nmu, int P, int nf, const double* U, const double* B, const double* mu,
+                                  double* F, hipStream_t st) {
+  const dim3 grid((nmu + 63) / 64, nf);
+  if (P <= 16) hipLaunchKernelGGL(k_legendre_series<16>, grid, dim3(64), 0, st, L, nmu, P, U, B, mu, F);
+  else if (P <= 32) hipLaunchKernelGGL(k_legendre_series<32>, grid, dim3(64), 0, st, L, nmu, P, U, B, mu, F);
+  else hipLaunchKernelGGL(k_legendre_series<64>, grid, dim3(64), 0, st, L, nmu, P, U, B, mu, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_alpha_modes(int nmax, int P, int T, int nmu, const int* tri, const double* F, const double* wmu,
+                              double* alpha, hipStream_t st) {
+  hipLaunchKernelGGL(k_alpha_modes, dim3((nmax + 255) / 256), dim3(256), 0, st, nmax, P, T, nmu, tri, F, wmu, alpha);
+  return hipGetLastError();
+}
+
+hipError_t launch_ideal_cov(int nmax, int P, int nmu, const int* tri, const double* F, const double* wmu, double* Z,
+                            hipStream_t st) {
+  const size_t slice = (size_t)P * (P + 1) * 8 + 8;
+  const int KC = (int)std::max<size_t>(1, std::min<size_t>(8, 65536 / slice));
+  const size_t lds = (size_t)KC * slice;
+  const int nt = (nmax + 63) / 64;
+  hipLaunchKernelGGL(k_ideal_cov, dim3(nt, nt), dim3(256), lds, st, nmax, P, nmu, KC, tri, F, wmu, Z);
+  return hipGetLastError();
+}
+
+}  // namespace modal
