@@ -14,9 +14,10 @@ Gaunt integral, brute-force triple sums, Parseval, finite differences and the
 bivector closed forms live in ``tests/test_oracle_*.py``; ``lowrank`` holds the
 low-rank (bivector / principal-component) covariance of Sec. III B, ``shapes``
 the theory mode coefficients of separable bispectra (eq. abispect), ``power``
-the modal power-spectrum estimator of Sec. IV.
+the modal power-spectrum estimator of Sec. IV, ``trispectrum`` the modal
+trispectrum estimator of Sec. IV.
 
 Functions whose parity is not pinned by anything but themselves say so in
 their docstring ("parity unpinned").
 """
-from . import grid, legendre, wigner, modal, closed_forms, sims, lowrank, shapes, power  # noqa: F401
+from . import grid, legendre, wigner, modal, closed_forms, sims, lowrank, shapes, power, trispectrum  # noqa: F401

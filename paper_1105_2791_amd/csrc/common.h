@@ -74,6 +74,7 @@ struct modal_ctx {
   modal::Tables t{};
   std::vector<double> x_host, wgl_host;
   std::vector<double> q_host, cl_host;   // the mode functions and filter spectrum given at creation
+  std::vector<double> mu_host, wmu_host; // Gauss-Legendre rule of the 1-D Legendre integrals (on first use)
   std::string last_error;
   // per-stage timing (modal_profile_enable)
   bool profile = false;

@@ -894,8 +894,9 @@ modal_status modal_alpha_separable(modal_ctx* c, const double* terms, int T, dou
   if ((s = set_device(c)) != MODAL_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   const int L = c->lmax + 1, nmu = shapes_nmu(c->lmax);
-  std::vector<double> mu, wmu;
-  gauss_legendre(nmu, mu, wmu);
+  if ((int)c->mu_host.size() != nmu) gauss_legendre(nmu, c->mu_host, c->wmu_host);
+  const std::vector<double>& mu = c->mu_host;
+  const std::vector<double>& wmu = c->wmu_host;
   Carver cv(ws);
   double* dmu = (double*)cv.take((size_t)nmu * 8);
   double* dw = (double*)cv.take((size_t)nmu * 8);
@@ -922,8 +923,9 @@ modal_status modal_ideal_covariance(modal_ctx* c, const double* c_host, double* 
   if ((s = set_device(c)) != MODAL_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   const int L = c->lmax + 1, nmu = shapes_nmu(c->lmax), P = c->P;
-  std::vector<double> mu, wmu;
-  gauss_legendre(nmu, mu, wmu);
+  if ((int)c->mu_host.size() != nmu) gauss_legendre(nmu, c->mu_host, c->wmu_host);
+  const std::vector<double>& mu = c->mu_host;
+  const std::vector<double>& wmu = c->wmu_host;
   // U_b(l) = c_l q_b(l), B_a(l) = q_a(l): F[b][k][a] = Q_ab(mu_k)
   std::vector<double> u((size_t)P * L);
   for (int b = 0; b < P; ++b)

@@ -34,7 +34,7 @@ constexpr int GT = 64;     // Gram output tile
 constexpr int GK = 16;     // Gram column chunk staged in LDS
 constexpr int GXR = 64;    // rows i of G X per workgroup
 constexpr int GXL = 256;   // rows l of G summed per workgroup
-constexpr int RC = 128;    // rows staged per chunk in the one-workgroup kernels
+constexpr int RC = 256;    // rows staged per chunk in the one-workgroup kernels
 
 // G[i][j] = scale * B_i . B_j over the rows of B [N][n]; lower tiles computed and mirrored.
 __global__ __launch_bounds__(256) void k_gram_rows(int N, int n, const double* __restrict__ B, double scale,
@@ -126,89 +126,110 @@ __global__ __launch_bounds__(256) void k_gx(int N, const double* __restrict__ G,
       Yp[((size_t)blockIdx.y * N + i) * KB + j] = acc[j] + red[0][ri][j] + red[1][ri][j] + red[2][ri][j];
 }
 
-// C[a][b] = sum_i X[i][a] X[i][b] (a, b < kb) for one workgroup; thread t < kb^2 owns (t / kb, t % kb).
+// C[a][b] = sum_i X[i][a] Y[i][b] (a, b < kb) for one workgroup (Y may be X: then only X
+// is staged).  Thread t owns the entry t % kb^2 for the rows of row group t / kb^2; the
+// groups' partial sums are added in LDS at the end.
+template <int RCT>
 __device__ void block_gram(int N, int kb, const double* __restrict__ X, const double* __restrict__ Y,
-                           double (*xs)[KB + 1], double (*ys)[KB + 1], double (*C)[KB]) {
+                           double (*xs)[KB + 1], double (*ys)[KB + 1], double (*C)[KB], double* part) {
   const int tid = threadIdx.x;
-  const int a = tid / kb, b = tid - (tid / kb) * kb;
+  const int kk = kb * kb, ng = 256 / kk;
+  const int grp = tid / kk, ent = tid - grp * kk;
+  const int a = ent / kb, b = ent - (ent / kb) * kb;
+  const bool same = X == Y;
   double c = 0.0;
-  for (int r0 = 0; r0 < N; r0 += RC) {
-    for (int e = tid; e < RC * KB; e += 256) {
+  for (int r0 = 0; r0 < N; r0 += RCT) {
+    for (int e = tid; e < RCT * KB; e += 256) {
       const int r = e / KB, j = e - r * KB;
       xs[r][j] = r0 + r < N ? X[(size_t)(r0 + r) * KB + j] : 0.0;
-      ys[r][j] = r0 + r < N ? Y[(size_t)(r0 + r) * KB + j] : 0.0;
+      if (!same) ys[r][j] = r0 + r < N ? Y[(size_t)(r0 + r) * KB + j] : 0.0;
     }
     __syncthreads();
-    if (tid < kb * kb)
-      for (int r = 0; r < RC; ++r) c = fma(xs[r][a], ys[r][b], c);
+    if (grp < ng) {
+      const double(*yy)[KB + 1] = same ? xs : ys;
+      for (int r = grp; r < RCT; r += ng) c = fma(xs[r][a], yy[r][b], c);
+    }
     __syncthreads();
   }
-  if (tid < kb * kb) C[a][b] = c;
+  if (grp < ng) part[tid] = c;
+  __syncthreads();
+  if (tid < kk) {
+    double s = 0.0;
+    for (int g = 0; g < ng; ++g) s += part[g * kk + tid];
+    C[a][b] = s;
+  }
   __syncthreads();
 }
 
+// Y[e] = sum over the nsplit partial blocks of Yp (columns >= kb zero), by one workgroup;
+// eight entries per thread at a time so that their loads are in flight together.
+__device__ void sum_partials(int N, int kb, int nsplit, const double* __restrict__ Yp, double* __restrict__ Y) {
+  const int tot = N * KB;
+  for (int e0 = threadIdx.x; e0 < tot; e0 += 256 * 8) {
+    double s[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] = 0.0;
+    for (int p = 0; p < nsplit; ++p)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 256 * u;
+        if (e < tot && e % KB < kb) s[u] += Yp[(size_t)p * tot + e];
+      }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + 256 * u;
+      if (e < tot) Y[e] = s[u];
+    }
+  }
+}
+
 // One workgroup: X = sum of the nsplit partial blocks, then made orthonormal by two
-// rounds of Cholesky QR (C = X^T X = R^T R, X <- X R^-1).  A column whose pivot falls
+// rounds of Cholesky QR (C = X^T X = R^T R, X <- X R^-1).  The Cholesky runs column by
+// column across the workgroup; each row then solves y R = x.  A column whose pivot falls
 // below 1e-26 of the largest diagonal entry of C (numerically dependent) is set to zero.
 __global__ __launch_bounds__(256) void k_orth(int N, int kb, int nsplit, const double* __restrict__ Yp,
                                               double* __restrict__ X) {
   __shared__ double xs[RC][KB + 1];
-  __shared__ double ys[RC][KB + 1];
   __shared__ double C[KB][KB];
   __shared__ double R[KB][KB];
-  __shared__ double Ri[KB][KB];
+  __shared__ double part[256];
+  __shared__ int drop[KB];
   const int tid = threadIdx.x;
-  for (int e = tid; e < N * KB; e += 256) {
-    double s = 0.0;
-    if (e % KB < kb)
-      for (int p = 0; p < nsplit; ++p) s += Yp[(size_t)p * N * KB + e];
-    X[e] = s;
-  }
+  sum_partials(N, kb, nsplit, Yp, X);
   __syncthreads();
   for (int pass = 0; pass < 2; ++pass) {
-    block_gram(N, kb, X, X, xs, ys, C);
-    if (tid == 0) {
-      double dmax = 0.0;
-      for (int j = 0; j < kb; ++j) dmax = fmax(dmax, C[j][j]);
-      unsigned drop = 0;   // bit j: column j dropped
-      for (int j = 0; j < kb; ++j) {
-        double d = C[j][j];
-        for (int p = 0; p < j; ++p) d -= R[p][j] * R[p][j];
-        const bool dj = !(d > 1e-26 * dmax);
-        drop |= (unsigned)dj << j;
-        const double rjj = dj ? 1.0 : sqrt(d);
+    block_gram<RC>(N, kb, X, X, xs, nullptr, C, part);
+    double dmax = 0.0;
+    for (int j = 0; j < kb; ++j) dmax = fmax(dmax, C[j][j]);
+    for (int j = 0; j < kb; ++j) {   // right-looking: row j of R, then the trailing update of C
+      const double d = C[j][j];
+      const bool dj = !(d > 1e-26 * dmax);
+      const double rjj = dj ? 1.0 : sqrt(d);
+      if (tid == j) {
         R[j][j] = rjj;
-        for (int q = j + 1; q < kb; ++q) {
-          double s = C[j][q];
-          for (int p = 0; p < j; ++p) s -= R[p][j] * R[p][q];
-          R[j][q] = dj ? 0.0 : s / rjj;
-        }
+        drop[j] = dj ? 1 : 0;
+      } else if (tid > j && tid < kb) {
+        R[j][tid] = dj ? 0.0 : C[j][tid] / rjj;
       }
-      for (int j = 0; j < kb; ++j) {
-        for (int i = 0; i < KB; ++i) Ri[i][j] = 0.0;
-        Ri[j][j] = 1.0 / R[j][j];
-        for (int i = j - 1; i >= 0; --i) {
-          double s = 0.0;
-          for (int p = i + 1; p <= j; ++p) s += R[i][p] * Ri[p][j];
-          Ri[i][j] = -s / R[i][i];
-        }
+      __syncthreads();
+      for (int e = tid; e < kb * kb; e += 256) {
+        const int a = e / kb, b = e - (e / kb) * kb;
+        if (a > j && b > j) C[a][b] -= R[j][a] * R[j][b];
       }
-      for (int j = 0; j < kb; ++j)
-        if ((drop >> j) & 1u)
-          for (int i = 0; i < KB; ++i) Ri[i][j] = 0.0;
+      __syncthreads();
     }
-    __syncthreads();
     for (int i = tid; i < N; i += 256) {
-      double x[KB];
+      double x[KB], y[KB];
 #pragma unroll
       for (int j = 0; j < KB; ++j) x[j] = X[(size_t)i * KB + j];
 #pragma unroll
       for (int j = 0; j < KB; ++j) {
         if (j >= kb) break;
-        double s = 0.0;
+        double s = x[j];
 #pragma unroll
-        for (int a = 0; a <= j; ++a) s = fma(x[a], Ri[a][j], s);
-        X[(size_t)i * KB + j] = s;
+        for (int p = 0; p < j; ++p) s -= y[p] * R[p][j];
+        y[j] = drop[j] ? 0.0 : s / R[j][j];
+        X[(size_t)i * KB + j] = y[j];
       }
     }
     __syncthreads();
@@ -276,19 +297,16 @@ __device__ void jacobi_eig(int kb, double (*A)[KB], double (*V)[KB], double* w) 
 __global__ __launch_bounds__(256) void k_rayleigh_ritz(int N, int kb, int nsplit, const double* __restrict__ Yp,
                                                        double* __restrict__ Y, double* __restrict__ X,
                                                        double* __restrict__ mu) {
-  __shared__ double xs[RC][KB + 1];
-  __shared__ double ys[RC][KB + 1];
+  __shared__ double xs[RC / 2][KB + 1];
+  __shared__ double ys[RC / 2][KB + 1];
   __shared__ double H[KB][KB];
   __shared__ double V[KB][KB];
   __shared__ double w[KB];
+  __shared__ double part[256];
   const int tid = threadIdx.x;
-  for (int e = tid; e < N * KB; e += 256) {
-    double s = 0.0;
-    for (int p = 0; p < nsplit; ++p) s += Yp[(size_t)p * N * KB + e];
-    Y[e] = s;
-  }
+  sum_partials(N, kb, nsplit, Yp, Y);
   __syncthreads();
-  block_gram(N, kb, X, Y, xs, ys, H);
+  block_gram<RC / 2>(N, kb, X, Y, xs, ys, H, part);
   if (tid == 0) {
     for (int i = 0; i < kb; ++i)
       for (int j = i + 1; j < kb; ++j) H[i][j] = H[j][i] = 0.5 * (H[i][j] + H[j][i]);

@@ -21,6 +21,11 @@ namespace {
 
 constexpr int PKC = 128;   // pixels per staged step (32 groups of 4)
 
+// LDS row stride in elements: 16 bytes of padding move consecutive rows to different
+// banks (the threads of a wave read different rows at the same pixel group)
+template <typename T>
+__host__ __device__ constexpr int pks() { return PKC + 16 / (int)sizeof(T); }
+
 // thread -> (phase, block (rb, cb), rb <= cb); nblk = nb (nb + 1) / 2
 __device__ inline void block_of(int b, int nb, int& rb, int& cb) {
   rb = 0;
@@ -34,14 +39,16 @@ __device__ inline void block_of(int b, int nb, int& rb, int& cb) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_pair_sums(int P, int npix, int chunk_px, int nchunk, const T* __restrict__ maps,
-                                                   const T* __restrict__ w, double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_pair_sums(int P, int npix, int chunk_px, int nchunk, int vec,
+                                                   const T* __restrict__ maps, const T* __restrict__ w,
+                                                   double* __restrict__ part) {
   typedef typename std::conditional<sizeof(T) == 4, float4, double4>::type T4;
   extern __shared__ __attribute__((aligned(16))) unsigned char praw[];
   const int nb = (P + 3) / 4, PR = 4 * nb, nblk = nb * (nb + 1) / 2;
   const int nph = max(1, 256 / nblk);
-  T* Ms = reinterpret_cast<T*>(praw);        // [PR][PKC]
-  T* Ws = Ms + (size_t)PR * PKC;              // [PR][PKC]  w * M
+  constexpr int PKS = pks<T>();
+  T* Ms = reinterpret_cast<T*>(praw);        // [PR][PKS]
+  T* Ws = Ms + (size_t)PR * PKS;              // [PR][PKS]  w * M
   const int chunk = blockIdx.x, s = blockIdx.y;
   const int tid = threadIdx.x;
   const int ph = tid / nblk, bk = tid - ph * nblk;
@@ -57,13 +64,36 @@ __global__ __launch_bounds__(256) void k_pair_sums(int P, int npix, int chunk_px
   const int x0 = chunk * chunk_px, x1 = min(npix, x0 + chunk_px);
   for (int xs = x0; xs < x1; xs += PKC) {
     __syncthreads();
-    for (int e = tid; e < PR * PKC; e += 256) {
-      const int r = e / PKC, i = e - r * PKC, x = xs + i;
-      const bool in = r < P && x < x1;
-      const T m = in ? Msky[(size_t)r * npix + x] : T(0);
-      const T ww = x < x1 ? w[x] : T(0);
-      Ms[e] = m;
-      Ws[e] = ww * m;
+    if (vec) {
+      // 4-pixel groups: chunks start at multiples of 4 and npix % 4 == 0, so a group is
+      // wholly inside or wholly past the chunk end; rows >= P stage zeros
+      for (int e = tid; e < PR * (PKC / 4); e += 256) {
+        const int r = e / (PKC / 4), g = e - r * (PKC / 4), x = xs + 4 * g;
+        T4 m, ww;
+        if (r < P && x < x1) {
+          m = *reinterpret_cast<const T4*>(Msky + (size_t)r * npix + x);
+          ww = *reinterpret_cast<const T4*>(w + x);
+        } else {
+          m.x = m.y = m.z = m.w = T(0);
+          ww = m;
+        }
+        *reinterpret_cast<T4*>(Ms + (size_t)r * PKS + 4 * g) = m;
+        T4 wm;
+        wm.x = ww.x * m.x;
+        wm.y = ww.y * m.y;
+        wm.z = ww.z * m.z;
+        wm.w = ww.w * m.w;
+        *reinterpret_cast<T4*>(Ws + (size_t)r * PKS + 4 * g) = wm;
+      }
+    } else {
+      for (int e = tid; e < PR * PKC; e += 256) {
+        const int r = e / PKC, i = e - r * PKC, x = xs + i;
+        const bool in = r < P && x < x1;
+        const T m = in ? Msky[(size_t)r * npix + x] : T(0);
+        const T ww = x < x1 ? w[x] : T(0);
+        Ms[(size_t)r * PKS + i] = m;
+        Ws[(size_t)r * PKS + i] = ww * m;
+      }
     }
     __syncthreads();
     if (on)
@@ -71,8 +101,8 @@ __global__ __launch_bounds__(256) void k_pair_sums(int P, int npix, int chunk_px
         T4 a[4], b[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          a[i] = *reinterpret_cast<const T4*>(Ms + (size_t)(4 * rb + i) * PKC + 4 * g);
-          b[i] = *reinterpret_cast<const T4*>(Ws + (size_t)(4 * cb + i) * PKC + 4 * g);
+          a[i] = *reinterpret_cast<const T4*>(Ms + (size_t)(4 * rb + i) * PKS + 4 * g);
+          b[i] = *reinterpret_cast<const T4*>(Ws + (size_t)(4 * cb + i) * PKS + 4 * g);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -156,7 +186,7 @@ size_t power_part_bytes(int P, int npix, int S) {
 
 size_t power_lds(int P, bool f64) {
   const int nb = (P + 3) / 4;
-  const size_t stage = (size_t)2 * 4 * nb * PKC * (f64 ? 8 : 4);
+  const size_t stage = f64 ? (size_t)2 * 4 * nb * pks<double>() * 8 : (size_t)2 * 4 * nb * pks<float>() * 4;
   const size_t red = (size_t)nb * (nb + 1) / 2 * 16 * 8;
   return stage > red ? stage : red;
 }
@@ -175,11 +205,12 @@ hipError_t launch_power_beta(const modal_ctx* c, const void* maps, int S, const 
   const int cpx = power_chunk_px();
   const int nchunk = (c->npix + cpx - 1) / cpx;
   const size_t lds = power_lds(c->P, f64);
+  const int vec = c->npix % 4 == 0 ? 1 : 0;
   if (f64)
-    hipLaunchKernelGGL(k_pair_sums<double>, dim3(nchunk, S), dim3(256), lds, st, c->P, c->npix, cpx, nchunk,
+    hipLaunchKernelGGL(k_pair_sums<double>, dim3(nchunk, S), dim3(256), lds, st, c->P, c->npix, cpx, nchunk, vec,
                        (const double*)maps, c->t.w64, part);
   else
-    hipLaunchKernelGGL(k_pair_sums<float>, dim3(nchunk, S), dim3(256), lds, st, c->P, c->npix, cpx, nchunk,
+    hipLaunchKernelGGL(k_pair_sums<float>, dim3(nchunk, S), dim3(256), lds, st, c->P, c->npix, cpx, nchunk, vec,
                        (const float*)maps, c->t.w32, part);
   const int tot = S * c->npairs;
   const size_t zstride = (size_t)c->nalm * 2;   // complex entries: real part of entry 0 of each pair row
