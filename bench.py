@@ -107,6 +107,13 @@ def kernel_rooflines(ctx, stages, prec, S, op="beta"):
     if op == "power":
         # sum_x w M_p M_r: one read of the maps and of the weights per sky
         work["cubic"] = ((P * npix + npix) * S * real, "byte", "hbm", PEAK["hbm"], None)
+    if op == "trispectrum":
+        # symmetric rank-npix update over the pairs: one MAC per (pair <= pair', pixel), per sky
+        # and once more for the pair means; issued: 128 x 128 tiles, three split products
+        R = ctx.npairs
+        nt = (R + 127) // 128
+        work["cubic"] = (2.0 * R * (R + 1) / 2 * npix * (S + 1), "flop", "mfma", PEAK["bf16"],
+                         2.0 * 3 * nt * (nt + 1) / 2 * 128 * 128 * npix * (S + 1))
     out = {}
     for name, (units, kind, bound, peak, issue) in work.items():
         ms, n = stages.get(name, (0.0, 0))
@@ -153,9 +160,11 @@ def run_path(args, prec, steps, warmup, make_state=True, op="beta"):
             ctx.linear_accumulate(state, make_inputs(lmax, P, min(S, args.mc - b0), 1000 + b0))
         ctx.linear_finalize(state)
     alm = ctx._alm(make_inputs(lmax, P, S, 0))
-    out = torch.empty((S, ctx.nmax if op == "beta" else ctx.npairs), dtype=torch.float64, device=dev)
-    call = (lambda: ctx.beta(alm, state=state, out=out)) if op == "beta" else \
-        (lambda: ctx.power_beta(alm, state=state, out=out))
+    ncol = {"beta": ctx.nmax, "power": ctx.npairs, "trispectrum": ctx.nquad}[op]
+    out = torch.empty((S, ncol), dtype=torch.float64, device=dev)
+    call = {"beta": lambda: ctx.beta(alm, state=state, out=out),
+            "power": lambda: ctx.power_beta(alm, state=state, out=out),
+            "trispectrum": lambda: ctx.trispectrum(alm, state=state, out=out)}[op]
     torch.cuda.synchronize()
     log(f"bench[{prec}]: state ready")
 
@@ -180,7 +189,8 @@ def run_path(args, prec, steps, warmup, make_state=True, op="beta"):
     elapsed = t1 - t0
     res = {"prec": prec, "value": S * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps, "tuned": tuned,
            "stages_ms": {k: v[0] / max(1, v[1]) for k, v in stages.items() if v[1]},
-           "kernels": kernel_rooflines(ctx, stages, prec, S, op), "nmax": ctx.nmax, "npairs": ctx.npairs}
+           "kernels": kernel_rooflines(ctx, stages, prec, S, op), "nmax": ctx.nmax, "npairs": ctx.npairs,
+           "ncol": ncol}
     log(f"bench[{prec}]: {res['value']:.2f} maps/s, {res['ms_per_step']:.2f} ms/step; stages: " +
         ", ".join(f"{k}={v:.3f}ms" for k, v in res["stages_ms"].items()))
     del state, alm, out
@@ -302,6 +312,24 @@ def run_power(args):
     print(json.dumps(line), flush=True)
 
 
+def run_trispectrum(args):
+    """Modal trispectrum batches (Sec. IV): maps + the pairs x pairs update + gather for S skies."""
+    res = run_path(args, args.prec, args.steps, args.warmup, make_state=not args.no_linear, op="trispectrum")
+    k = dict(res["kernels"]["cubic"])
+    k["kernel"] = "pairs x pairs update (k_quad_syrk + k_quad_reduce)"
+    line = {
+        "metric": "modal trispectrum: sim maps/sec (filter + quartic reduction) @lmax=1000,P=40", "unit": "maps/s",
+        "value": res["value"], "ms_per_step": res["ms_per_step"], "higher_is_better": True, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"bf16x3": "bf16", "f16x3": "f16", "f32": "f32", "f64": "f64"}[args.prec], "data": "synthetic",
+        "config": {"workload": f"lmax={args.lmax} GL {args.ntheta}x{args.nphi} P={args.P} npairs={res['npairs']} "
+                               f"modes={res['ncol']}, beam+noise spectrum, |lat|<10deg cut, MC pair means "
+                               f"({args.mc} skies)", "batch": args.batch, "prec": args.prec},
+        "stages_ms": res["stages_ms"], "roofline": k, "kernels": res["kernels"],
+    }
+    print(json.dumps(line), flush=True)
+
+
 def run_shapes(args):
     """Theory side at the workload shape: alpha_n of a three-term separable shape and the
     ideal covariance zeta0 (n_max x n_max) of the separable modes."""
@@ -361,9 +389,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of a known size (HBM counter calibration)")
     ap.add_argument("--no-linear", action="store_true", help="beta without the linear term (diagnostic)")
-    ap.add_argument("--workload", default="beta", choices=["beta", "lowrank", "power", "shapes"],
+    ap.add_argument("--workload", default="beta", choices=["beta", "lowrank", "power", "shapes", "trispectrum"],
                     help="beta: the hot path (default); lowrank: the low-rank covariance calls; "
-                         "power: the modal power spectrum; shapes: alpha_n and the ideal covariance")
+                         "power: the modal power spectrum; shapes: alpha_n and the ideal covariance; "
+                         "trispectrum: the modal trispectrum")
     ap.add_argument("--lr-sims", type=int, default=1000, help="lowrank: beta^hat vectors N")
     ap.add_argument("--lr-k", type=int, default=4, help="lowrank: noise vectors k")
     ap.add_argument("--lr-iters", type=int, default=100, help="lowrank: block iterations")
@@ -386,6 +415,9 @@ def main():
         return
     if args.workload == "shapes":
         run_shapes(args)
+        return
+    if args.workload == "trispectrum":
+        run_trispectrum(args)
         return
     prec = args.prec
     head = run_path(args, prec, args.steps, args.warmup, make_state=not args.no_linear)

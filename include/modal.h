@@ -106,7 +106,8 @@ typedef enum {
   MODAL_OP_POWER_BETA = 13,
   MODAL_OP_POWER_ALPHA = 14,
   MODAL_OP_POWER_COVARIANCE = 15,
-  MODAL_OP_POWER_FNL = 16
+  MODAL_OP_POWER_FNL = 16,
+  MODAL_OP_TRISPECTRUM = 17
 } modal_op;
 
 typedef enum {
@@ -355,6 +356,21 @@ modal_status modal_power_ideal_covariance(modal_ctx* ctx, const double* c_host, 
 modal_status modal_power_fnl(modal_ctx* ctx, const double* zeta_dev, const double* alpha_dev, const double* beta_dev,
                              int S, double* E_host, double* sigma2_host, void* ws_dev, size_t ws_bytes,
                              modal_stream_t stream);
+
+/* Modal trispectrum estimator (Sec. IV, the diagonal-free trispectrum): for the
+ * separable modes q_p q_r q_s q_u, p <= r <= s <= u (nquad = P(P+1)(P+2)(P+3)/24,
+ * lexicographic; modal_nquad),
+ *   tau_prsu = sum_x w [M_p M_r M_s M_u - (6 pairs) V_ab M_c M_d + (3 pairings) V_ab V_cd]
+ * with V the Monte-Carlo pair means of a finalised linear-term state (state_dev NULL:
+ * V = 0, the plain quartic sums).  Computed as the pairs x pairs symmetric update
+ * K = sum_x w A A^T - 6 sum_x w V V^T, A_ab = M_a M_b - 3 V_ab, tau = the mean of K over the
+ * three pairings; split-bf16 matrix cores for float contexts (all three float precisions),
+ * FP64 for MODAL_F64 (a reference path without pixel chunking).
+ *   tau_dev [S][nquad] float64.  Workspace: modal_workspace_size(MODAL_OP_TRISPECTRUM, S).
+ * Errors: EINVAL, ENOTREADY, ENOSPACE, EDEVICE. */
+modal_status modal_trispectrum(modal_ctx* ctx, const void* alm_dev, int S, const void* state_dev, double* tau_dev,
+                               void* ws_dev, size_t ws_bytes, modal_stream_t stream);
+int modal_nquad(const modal_ctx* ctx);
 
 /* Autotuner: times modal_beta on the caller's inputs (same arguments and
  * workspace as modal_beta) for each candidate launch configuration - pixels

@@ -18,7 +18,7 @@ F64, F32, BF16X3, F16X3 = range(4)
 OP_FILTER_MAPS, OP_BETA, OP_LINEAR_ACCUMULATE, OP_LINEAR_APPLY, OP_BETA_VJP, \
     OP_COVARIANCE_SAMPLE, OP_COVARIANCE_FISHER, OP_FNL, OP_LINEAR_FINALIZE, OP_NOISE_VECTORS, OP_FNL_LOWRANK, \
     OP_ALPHA_SEPARABLE, OP_IDEAL_COVARIANCE, OP_POWER_BETA, OP_POWER_ALPHA, OP_POWER_COVARIANCE, \
-    OP_POWER_FNL = range(17)
+    OP_POWER_FNL, OP_TRISPECTRUM = range(18)
 LIN_RESET, LIN_ACCUMULATE, LIN_FINALIZE, LIN_APPLY = range(4)
 COV_SAMPLE, COV_FISHER = range(2)
 
@@ -75,6 +75,8 @@ _SIGS = {
     "modal_power_alpha": (ip, [vp, vp, vp, vp, sz, vp]),
     "modal_power_ideal_covariance": (ip, [vp, vp, vp, vp, sz, vp]),
     "modal_power_fnl": (ip, [vp, vp, vp, vp, ip, vp, vp, vp, sz, vp]),
+    "modal_trispectrum": (ip, [vp, vp, ip, vp, vp, vp, sz, vp]),
+    "modal_nquad": (ip, [vp]),
 }
 
 STAGES = ["legendre", "fft", "cubic", "reduce", "linacc", "adj_pair", "adj_fft", "adj_legendre",

@@ -45,6 +45,7 @@ class ModalContext:
         self.nalm = self._lib.modal_nalm(self._h)
         self.nmax = self._lib.modal_nmax(self._h)
         self.npairs = self._lib.modal_npairs(self._h)
+        self.nquad = self._lib.modal_nquad(self._h)
         self.real_dtype = torch.float64 if self.prec == L.F64 else torch.float32
         self.complex_dtype = torch.complex128 if self.prec == L.F64 else torch.complex64
         self._ws = None
@@ -285,6 +286,19 @@ class ModalContext:
         self._check(self._lib.modal_ideal_covariance(self._h, None if cv is None else cv.ctypes.data, _ptr(z),
                                                      _ptr(ws), ws.numel(), self._stream()))
         return z
+
+    # -- modal trispectrum (Sec. IV) ---------------------------------------------------
+
+    def trispectrum(self, alm, state=None, out=None) -> torch.Tensor:
+        """tau [S][nquad] for quadruples p <= r <= s <= u (V from a finalised linear-term state)."""
+        a = self._alm(alm)
+        S = a.shape[0]
+        nq = self._lib.modal_nquad(self._h)
+        t = out if out is not None else torch.empty((S, nq), dtype=torch.float64, device=self.device)
+        ws = self.workspace(L.OP_TRISPECTRUM, S)
+        self._check(self._lib.modal_trispectrum(self._h, _ptr(a), S, _ptr(state), _ptr(t), _ptr(ws), ws.numel(),
+                                                self._stream()))
+        return t
 
     # -- modal power spectrum (Sec. IV) ------------------------------------------------
 

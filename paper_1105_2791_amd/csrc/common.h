@@ -43,6 +43,9 @@ struct Tables {
   int* pair_a = nullptr;       // [npairs] first mode of each pair
   int* pair_b = nullptr;       // [npairs] second mode
   int* tri = nullptr;          // [nmax][6] p, r, s, pair(pr), pair(ps), pair(rs)
+  int* quad = nullptr;         // [nquad][6] pair indices of the three pairings (pr|su), (ps|ru), (pu|rs)
+  int nquad = 0;
+  int2* qtiles = nullptr;      // tile pairs (ti <= tj) of the pairs x pairs update
   int* pair_of = nullptr;      // [P][P] pair index of (min, max)
   int* tri_of = nullptr;       // [P][npairs] triple index of sort(u, a, b)
   int* tri_mult = nullptr;     // [P][npairs] multiplicity of u in that triple
@@ -212,6 +215,15 @@ hipError_t launch_alpha_modes(int nmax, int P, int T, int nmu, const int* tri, c
                               double* alpha, hipStream_t st);
 hipError_t launch_ideal_cov(int nmax, int P, int nmu, const int* tri, const double* F, const double* wmu, double* Z,
                             hipStream_t st);
+
+// modal trispectrum (pairs x pairs update over pixels)
+int quad_chunks(int npix);
+int quad_ntile(int R);
+size_t quad_part_bytes(const modal_ctx* c, int S);
+hipError_t launch_quad_syrk(const modal_ctx* c, const void* maps, const void* V, int S, int vmode, const int2* tpairs,
+                            float* part, double* K, hipStream_t st);
+hipError_t launch_quad_gather(const modal_ctx* c, int nquad, int S, const int* quad, const double* K, const double* KVV,
+                              double* tau, hipStream_t st);
 
 // modal power spectrum (quadratic pixel reduction)
 int power_chunk_px();

@@ -178,6 +178,10 @@ size_t ws_size(const modal_ctx* c, int op, int S) {
       cv.take(F_bytes(c, S)); cv.take(maps_bytes(c, S)); cv.take(power_part_bytes(c->P, c->npix, S));
       break;
     case MODAL_OP_POWER_ALPHA: cv.take((size_t)(c->lmax + 1) * 8); break;
+    case MODAL_OP_TRISPECTRUM:
+      cv.take(F_bytes(c, S)); cv.take(maps_bytes(c, S)); cv.take(quad_part_bytes(c, S > 0 ? S : 1));
+      cv.take((size_t)S * c->npairs * c->npairs * 8); cv.take((size_t)c->npairs * c->npairs * 8);
+      break;
     case MODAL_OP_POWER_COVARIANCE:
       cv.take((size_t)c->P * (c->lmax + 1) * 8); cv.take((size_t)(c->lmax + 1) * 8);
       cv.take((size_t)(c->lmax + 1) * c->P * 8);
@@ -429,6 +433,24 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
       tri_mult[(size_t)u * c->npairs + k] = (v[0] == u) + (v[1] == u) + (v[2] == u);
     }
 
+  // trispectrum: quadruples p <= r <= s <= u with the pair indices of their three pairings,
+  // and the tile pairs of the pairs x pairs update
+  std::vector<int> quad;
+  for (int p = 0; p < P; ++p)
+    for (int r = p; r < P; ++r)
+      for (int s2 = r; s2 < P; ++s2)
+        for (int u = s2; u < P; ++u) {
+          auto pr = [&](int a, int b) { return pair_of[(size_t)std::min(a, b) * P + std::max(a, b)]; };
+          quad.insert(quad.end(), {pr(p, r), pr(s2, u), pr(p, s2), pr(r, u), pr(p, u), pr(r, s2)});
+        }
+  c->t.nquad = (int)(quad.size() / 6);
+  std::vector<int2> qtiles;
+  {
+    const int nt = quad_ntile(c->npairs);
+    for (int ti = 0; ti < nt; ++ti)
+      for (int tj = ti; tj < nt; ++tj) qtiles.push_back(make_int2(ti, tj));
+  }
+
   // exact power-of-two scales for the split-fp16 contraction: whitened maps have
   // variance sigma_p^2 = sum_{C_l > 0} (2l+1)/(4 pi) q_p(l)^2
   std::vector<float> mscale(P, 1.f);
@@ -456,7 +478,8 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
       upload(&t.tw32, tw32) != hipSuccess || upload(&t.pair_a, pa) != hipSuccess ||
       upload(&t.pair_b, pb) != hipSuccess || upload(&t.tri, tri) != hipSuccess ||
       upload(&t.pair_of, pair_of) != hipSuccess || upload(&t.tri_of, tri_of) != hipSuccess ||
-      upload(&t.tri_mult, tri_mult) != hipSuccess)
+      upload(&t.tri_mult, tri_mult) != hipSuccess || upload(&t.quad, quad) != hipSuccess ||
+      upload(&t.qtiles, qtiles) != hipSuccess)
     return bail(MODAL_EDEVICE);
   if (hipMalloc((void**)&t.seed, 2 * sizeof(double) * (lmax + 1) * (size_t)c->nrp) != hipSuccess ||
       hipMalloc((void**)&t.lstart, sizeof(int) * (lmax + 1) * (size_t)c->nrp) != hipSuccess ||
@@ -499,7 +522,7 @@ void modal_destroy(modal_ctx* c) {
   Tables& t = c->t;
   void* ptrs[] = {t.x, t.ringw, t.w64, t.w32, t.rec, t.seed, t.lstart, t.lstart_blk, t.qw64, t.qw32, t.tw64, t.tw32,
                   t.pair_a, t.pair_b, t.tri, t.pair_of, t.tri_of, t.tri_mult, t.flag, t.blk, t.items, t.mscale,
-                  t.twp32, t.lamtab, t.lamtab_off};
+                  t.twp32, t.lamtab, t.lamtab_off, t.quad, t.qtiles};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -508,6 +531,7 @@ void modal_destroy(modal_ctx* c) {
 const char* modal_last_error(const modal_ctx* c) { return c ? c->last_error.c_str() : "null context"; }
 int modal_nalm(const modal_ctx* c) { return c ? c->nalm : -1; }
 int modal_nmax(const modal_ctx* c) { return c ? c->nmax : -1; }
+int modal_nquad(const modal_ctx* c) { return c ? c->t.nquad : -1; }
 int modal_npairs(const modal_ctx* c) { return c ? c->npairs : -1; }
 int modal_cubic_path(const modal_ctx* c) {
   if (!c) return -1;
@@ -530,7 +554,7 @@ modal_status modal_grid(const modal_ctx* c, double* x_host, double* w_host) {
 }
 
 modal_status modal_workspace_size(const modal_ctx* c, int op, int S, size_t* bytes) {
-  if (!c || !bytes || S < 0 || op < MODAL_OP_FILTER_MAPS || op > MODAL_OP_POWER_FNL) return MODAL_EINVAL;
+  if (!c || !bytes || S < 0 || op < MODAL_OP_FILTER_MAPS || op > MODAL_OP_TRISPECTRUM) return MODAL_EINVAL;
   *bytes = ws_size(c, op, S);
   return MODAL_OK;
 }
@@ -775,6 +799,35 @@ modal_status modal_power_beta(modal_ctx* c, const void* alm, int S, const void* 
   {
     StageTimer _t(c, MODAL_STAGE_CUBIC, st);
     HIPTRY(launch_power_beta(c, maps, S, state ? lin_Z(c, state) : nullptr, part, beta, st));
+  }
+  return MODAL_OK;
+}
+
+modal_status modal_trispectrum(modal_ctx* c, const void* alm, int S, const void* state, double* tau, void* ws,
+                               size_t ws_bytes, modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (!alm || !tau || S <= 0) return fail(c, MODAL_EINVAL, "trispectrum: null pointer or S <= 0");
+  modal_status s = check_state(c, state);
+  if (s != MODAL_OK) return s;
+  if ((s = check_ws(c, MODAL_OP_TRISPECTRUM, S, ws, ws_bytes)) != MODAL_OK) return s;
+  if ((s = set_device(c)) != MODAL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t R2 = (size_t)c->npairs * c->npairs;
+  Carver cv(ws);
+  void* F = cv.take(F_bytes(c, S));
+  void* maps = cv.take(maps_bytes(c, S));
+  float* part = (float*)cv.take(quad_part_bytes(c, S));
+  double* K = (double*)cv.take((size_t)S * R2 * 8);
+  double* KVV = (double*)cv.take(R2 * 8);
+  if ((s = run_maps(c, alm, S, F, maps, st)) != MODAL_OK) return s;
+  {
+    StageTimer _t(c, MODAL_STAGE_CUBIC, st);
+    HIPTRY(launch_quad_syrk(c, maps, state, S, 0, c->t.qtiles, part, K, st));   // V planes lead the state
+    if (state) HIPTRY(launch_quad_syrk(c, nullptr, state, 1, 1, c->t.qtiles, part, KVV, st));
+  }
+  {
+    StageTimer _t(c, MODAL_STAGE_REDUCE, st);
+    HIPTRY(launch_quad_gather(c, c->t.nquad, S, c->t.quad, K, state ? KVV : nullptr, tau, st));
   }
   return MODAL_OK;
 }
