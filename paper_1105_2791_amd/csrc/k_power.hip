@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void k_power_rows(int lmax, int P, const doubl
 
 }  // namespace
 
-int power_chunk_px() { return 4096; }
+int power_chunk_px() { return 16384; }
 
 size_t power_part_bytes(int P, int npix, int S) {
   const int nb = (P + 3) / 4, nblk = nb * (nb + 1) / 2;
