@@ -27,7 +27,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
 
 constexpr int TT = 128;      // output tile of the MFMA kernel (rows = cols)
 constexpr int PXS = 32;      // pixels per staged step (two MFMA K = 16 steps)
-constexpr int OPS = PXS + 8; // operand row stride in LDS (bf16)
+constexpr int OPS = PXS;     // operand row stride in LDS (bf16; 16-byte fragments stay aligned)
 constexpr int MPS = PXS + 1; // map / pair-mean row stride in LDS (odd: the lanes read different rows)
 constexpr int CH = 16;       // staged steps per MFMA accumulation chain (96 MFMAs per tile)
 
@@ -56,7 +56,7 @@ __device__ inline void split2(float v0, float v1, uint32_t& hi, uint32_t& lo) {
 
 // Tile pair (ti, tj), ti <= tj, of the R x R result, pixel chunk c, sky s (vmode: operands
 // are the pair means themselves).  part[s][c][tp][TT][TT] FP32 sums of the chunk.
-__global__ __launch_bounds__(256) void k_quad_syrk(int P, int R, int npix, int nchunk, int chunk_px, int ntp,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_quad_syrk(int P, int R, int npix, int nchunk, int chunk_px, int ntp,
                                                    const int2* __restrict__ tpairs, const int* __restrict__ pair_a,
                                                    const int* __restrict__ pair_b, const float* __restrict__ maps,
                                                    const float* __restrict__ V, const float* __restrict__ w,
