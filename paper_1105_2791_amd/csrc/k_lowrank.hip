@@ -224,12 +224,14 @@ __global__ __launch_bounds__(256) void k_orth(int N, int kb, int nsplit, const d
       for (int j = 0; j < KB; ++j) x[j] = X[(size_t)i * KB + j];
 #pragma unroll
       for (int j = 0; j < KB; ++j) {
-        if (j >= kb) break;
-        double s = x[j];
+        y[j] = 0.0;
+        if (j < kb) {   // uniform
+          double s = x[j];
 #pragma unroll
-        for (int p = 0; p < j; ++p) s -= y[p] * R[p][j];
-        y[j] = drop[j] ? 0.0 : s / R[j][j];
-        X[(size_t)i * KB + j] = y[j];
+          for (int p = 0; p < j; ++p) s -= y[p] * R[p][j];
+          y[j] = drop[j] ? 0.0 : s / R[j][j];
+          X[(size_t)i * KB + j] = y[j];
+        }
       }
     }
     __syncthreads();
@@ -319,14 +321,14 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(int N, int kb, int nsplit
 #pragma unroll
     for (int j = 0; j < KB; ++j) x[j] = X[(size_t)i * KB + j];
 #pragma unroll
-    for (int j = 0; j < KB; ++j) {
-      if (j >= kb) break;
-      double s = 0.0;
+    for (int j = 0; j < KB; ++j)
+      if (j < kb) {   // uniform
+        double s = 0.0;
 #pragma unroll
-      for (int a = 0; a < KB; ++a)
-        if (a < kb) s = fma(x[a], V[a][j], s);
-      X[(size_t)i * KB + j] = s;
-    }
+        for (int a = 0; a < KB; ++a)
+          if (a < kb) s = fma(x[a], V[a][j], s);
+        X[(size_t)i * KB + j] = s;
+      }
   }
 }
 
