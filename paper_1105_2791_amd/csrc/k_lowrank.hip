@@ -161,26 +161,42 @@ __device__ void block_gram(int N, int kb, const double* __restrict__ X, const do
   __syncthreads();
 }
 
-// Y[e] = sum over the nsplit partial blocks of Yp (columns >= kb zero), by one workgroup;
-// eight entries per thread at a time so that their loads are in flight together.
-__device__ void sum_partials(int N, int kb, int nsplit, const double* __restrict__ Yp, double* __restrict__ Y) {
+// Sum over the nsplit partial blocks of Yp (columns >= kb zero), by one workgroup; each
+// entry e < N KB is handed to put(e, value).  EU entries of four blocks per thread are
+// loaded at a time, unconditionally (clamped indices, values selected afterwards), so
+// that 4 EU loads are in flight per wait instead of one.
+template <int EU, typename F>
+__device__ void sum_partials_with(int N, int kb, int nsplit, const double* __restrict__ Yp, F put) {
+  constexpr int PU = 4;
   const int tot = N * KB;
-  for (int e0 = threadIdx.x; e0 < tot; e0 += 256 * 8) {
-    double s[8];
+  for (int e0 = threadIdx.x; e0 < tot; e0 += 256 * EU) {
+    double sv[EU];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s[u] = 0.0;
-    for (int p = 0; p < nsplit; ++p)
+    for (int u = 0; u < EU; ++u) sv[u] = 0.0;
+    for (int p0 = 0; p0 < nsplit; p0 += PU) {
+      double v[PU][EU];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + 256 * u;
-        if (e < tot && e % KB < kb) s[u] += Yp[(size_t)p * tot + e];
+      for (int q = 0; q < PU; ++q) {
+        const size_t base = (size_t)min(p0 + q, nsplit - 1) * tot;
+#pragma unroll
+        for (int u = 0; u < EU; ++u) v[q][u] = Yp[base + min(e0 + 256 * u, tot - 1)];
       }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+      for (int q = 0; q < PU; ++q)
+#pragma unroll
+        for (int u = 0; u < EU; ++u) sv[u] += p0 + q < nsplit ? v[q][u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < EU; ++u) {
       const int e = e0 + 256 * u;
-      if (e < tot) Y[e] = s[u];
+      if (e < tot) put(e, e % KB < kb ? sv[u] : 0.0);
     }
   }
+}
+
+template <int EU>
+__device__ void sum_partials(int N, int kb, int nsplit, const double* __restrict__ Yp, double* __restrict__ Y) {
+  sum_partials_with<EU>(N, kb, nsplit, Yp, [&](int e, double v) { Y[e] = v; });
 }
 
 // One workgroup: X = sum of the nsplit partial blocks, then made orthonormal by two
@@ -195,7 +211,7 @@ __global__ __launch_bounds__(256) void k_orth(int N, int kb, int nsplit, const d
   __shared__ double part[256];
   __shared__ int drop[KB];
   const int tid = threadIdx.x;
-  sum_partials(N, kb, nsplit, Yp, X);
+  sum_partials<8>(N, kb, nsplit, Yp, X);
   __syncthreads();
   for (int pass = 0; pass < 2; ++pass) {
     block_gram<RC>(N, kb, X, X, xs, nullptr, C, part);
@@ -236,6 +252,86 @@ __global__ __launch_bounds__(256) void k_orth(int N, int kb, int nsplit, const d
     }
     __syncthreads();
   }
+}
+
+constexpr int ORN = 1024;   // largest N whose block k_orth_res keeps resident in LDS
+
+// k_orth with the whole N x KB block resident in LDS (N <= ORN, N (KB + 1) doubles of
+// dynamic LDS): the partial blocks are summed straight into LDS, both Cholesky QR rounds
+// read and write LDS only, and X goes to HBM once at the end.  Same arithmetic as
+// k_orth (the Gram sums run over the rows in another order).
+__global__ __launch_bounds__(256) void k_orth_res(int N, int kb, int nsplit, const double* __restrict__ Yp,
+                                                  double* __restrict__ X) {
+  extern __shared__ __attribute__((aligned(16))) double ores[];
+  double(*xs)[KB + 1] = reinterpret_cast<double(*)[KB + 1]>(ores);   // [N][KB + 1]
+  __shared__ double C[KB][KB];
+  __shared__ double R[KB][KB];
+  __shared__ double part[256];
+  __shared__ int drop[KB];
+  const int tid = threadIdx.x;
+  const int tot = N * KB;
+  sum_partials_with<16>(N, kb, nsplit, Yp, [&](int e, double v) { xs[e / KB][e % KB] = v; });
+  __syncthreads();
+  const int kk = kb * kb, ng = 256 / kk;
+  const int grp = tid / kk, ent = tid - grp * kk;
+  const int a = ent / kb, b = ent - (ent / kb) * kb;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (grp < ng) {
+      // four independent chains so that the LDS reads are in flight together
+      double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+      int r = grp;
+      for (; r + 3 * ng < N; r += 4 * ng) {
+        c0 = fma(xs[r][a], xs[r][b], c0);
+        c1 = fma(xs[r + ng][a], xs[r + ng][b], c1);
+        c2 = fma(xs[r + 2 * ng][a], xs[r + 2 * ng][b], c2);
+        c3 = fma(xs[r + 3 * ng][a], xs[r + 3 * ng][b], c3);
+      }
+      for (; r < N; r += ng) c0 = fma(xs[r][a], xs[r][b], c0);
+      part[tid] = (c0 + c1) + (c2 + c3);
+    }
+    __syncthreads();
+    if (tid < kk) {
+      double sm = 0.0;
+      for (int g = 0; g < ng; ++g) sm += part[g * kk + tid];
+      C[a][b] = sm;
+    }
+    __syncthreads();
+    double dmax = 0.0;
+    for (int j = 0; j < kb; ++j) dmax = fmax(dmax, C[j][j]);
+    for (int j = 0; j < kb; ++j) {   // right-looking: row j of R, then the trailing update of C
+      const double d = C[j][j];
+      const bool dj = !(d > 1e-26 * dmax);
+      const double rjj = dj ? 1.0 : sqrt(d);
+      if (tid == j) {
+        R[j][j] = rjj;
+        drop[j] = dj ? 1 : 0;
+      } else if (tid > j && tid < kb) {
+        R[j][tid] = dj ? 0.0 : C[j][tid] / rjj;
+      }
+      __syncthreads();
+      for (int e = tid; e < kk; e += 256) {
+        const int ea = e / kb, eb = e - (e / kb) * kb;
+        if (ea > j && eb > j) C[ea][eb] -= R[j][ea] * R[j][eb];
+      }
+      __syncthreads();
+    }
+    for (int i = tid; i < N; i += 256) {
+      double y[KB];
+#pragma unroll
+      for (int j = 0; j < KB; ++j) {
+        y[j] = 0.0;
+        if (j < kb) {   // uniform
+          double sm = xs[i][j];
+#pragma unroll
+          for (int p = 0; p < j; ++p) sm -= y[p] * R[p][j];
+          y[j] = drop[j] ? 0.0 : sm / R[j][j];
+          xs[i][j] = y[j];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < tot; e += 256) X[e] = xs[e / KB][e % KB];
 }
 
 // Cyclic Jacobi for the symmetric kb x kb matrix A (destroyed): eigenvalues w and
@@ -306,7 +402,7 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(int N, int kb, int nsplit
   __shared__ double w[KB];
   __shared__ double part[256];
   const int tid = threadIdx.x;
-  sum_partials(N, kb, nsplit, Yp, Y);
+  sum_partials<4>(N, kb, nsplit, Yp, Y);
   __syncthreads();
   block_gram<RC / 2>(N, kb, X, Y, xs, ys, H, part);
   if (tid == 0) {
@@ -549,11 +645,25 @@ hipError_t launch_noise_vectors(int N, int n, int k, int iters, const double* B,
   const int nt = (N + GT - 1) / GT;
   hipLaunchKernelGGL(k_gram_rows, dim3(nt, nt), dim3(256), 0, st, N, n, B, 1.0 / (6.0 * N), G);
   hipLaunchKernelGGL(k_start_block, dim3((N * KB + 255) / 256), dim3(256), 0, st, N, kb, Yp);
-  hipLaunchKernelGGL(k_orth, dim3(1), dim3(256), 0, st, N, kb, 1, Yp, X);
+  // the block stays in LDS through the orthonormalisation when it fits
+  const bool res = N <= ORN;
+  const size_t res_lds = (size_t)N * (KB + 1) * 8;
+  if (res) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_orth_res, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)((size_t)ORN * (KB + 1) * 8));
+    if (e != hipSuccess) return e;
+  }
+  auto orth = [&](int ns) {
+    if (res)
+      hipLaunchKernelGGL(k_orth_res, dim3(1), dim3(256), res_lds, st, N, kb, ns, Yp, X);
+    else
+      hipLaunchKernelGGL(k_orth, dim3(1), dim3(256), 0, st, N, kb, ns, Yp, X);
+  };
+  orth(1);
   const dim3 ggx((N + GXR - 1) / GXR, nsplit);
   for (int it = 0; it < iters; ++it) {
     hipLaunchKernelGGL(k_gx, ggx, dim3(256), 0, st, N, G, X, Yp);
-    hipLaunchKernelGGL(k_orth, dim3(1), dim3(256), 0, st, N, kb, nsplit, Yp, X);
+    orth(nsplit);
   }
   hipLaunchKernelGGL(k_gx, ggx, dim3(256), 0, st, N, G, X, Yp);
   hipLaunchKernelGGL(k_rayleigh_ritz, dim3(1), dim3(256), 0, st, N, kb, nsplit, Yp, Y, X, mu_dev);

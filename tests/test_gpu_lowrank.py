@@ -47,7 +47,7 @@ def spiked_betas(rng, N, n, strengths):
     return math.sqrt(6.0) * (Z + (G * np.asarray(strengths)) @ U.T)
 
 
-@pytest.mark.parametrize("P,N,k", [(8, 300, 1), (8, 300, 4), (6, 257, 3), (7, 5, 5), (6, 3, 2)])
+@pytest.mark.parametrize("P,N,k", [(8, 300, 1), (8, 300, 4), (6, 257, 3), (7, 5, 5), (6, 3, 2), (6, 1100, 2)])
 def test_noise_vectors_match_oracle(P, N, k):
     c = ctx_P(P)
     n = c.nmax
