@@ -354,7 +354,9 @@ def run_shapes(args):
         times[name] = 1e3 * (time.perf_counter() - t0) / args.steps
     nmu = (3 * lmax + 2) // 2
     n = ctx.nmax
-    flop = n * (n + 1) / 2 * nmu * 16.0     # 4 mul + 6 fma per (pair of modes, node)
+    # the 3 x 3 permanent expanded along its third row, its 2 x 2 permanents shared
+    # across the rows of a group: 1 mul + 2 fma, then the weighted fma, per (pair of modes, node)
+    flop = n * (n + 1) / 2 * nmu * 7.0
     t = times["ideal_covariance"] * 1e-3
     line = {
         "metric": "theory side: alpha_n (3 separable terms) and ideal covariance, ms per call", "unit": "ms",

@@ -46,6 +46,8 @@ struct Tables {
   int* quad = nullptr;         // [nquad][6] pair indices of the three pairings (pr|su), (ps|ru), (pu|rs)
   int nquad = 0;
   int2* qtiles = nullptr;      // tile pairs (ti <= tj) of the pairs x pairs update
+  int4* zrows = nullptr;       // [nzrows] ideal-covariance rows: (p, r, s, mode), runs of equal (p, r)
+  int nzrows = 0;              //   padded to multiples of 4 with (p, r, r, -1)
   int* pair_of = nullptr;      // [P][P] pair index of (min, max)
   int* tri_of = nullptr;       // [P][npairs] triple index of sort(u, a, b)
   int* tri_mult = nullptr;     // [P][npairs] multiplicity of u in that triple
@@ -213,8 +215,8 @@ hipError_t launch_legendre_series(int L, int nmu, int P, int nf, const double* U
                                   double* F, hipStream_t st);
 hipError_t launch_alpha_modes(int nmax, int P, int T, int nmu, const int* tri, const double* F, const double* wmu,
                               double* alpha, hipStream_t st);
-hipError_t launch_ideal_cov(int nmax, int P, int nmu, const int* tri, const double* F, const double* wmu, double* Z,
-                            hipStream_t st);
+hipError_t launch_ideal_cov(int nmax, int P, int nmu, int nrows, const int4* zrows, const double* F,
+                            const double* wmu, double* Z, hipStream_t st);
 
 // modal trispectrum (pairs x pairs update over pixels)
 int quad_chunks(int npix);

@@ -444,6 +444,15 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
           quad.insert(quad.end(), {pr(p, r), pr(s2, u), pr(p, s2), pr(r, u), pr(p, u), pr(r, s2)});
         }
   c->t.nquad = (int)(quad.size() / 6);
+  // ideal-covariance rows: the modes in their order, each run of equal (p, r) padded to a
+  // multiple of 4, so that every aligned group of four rows shares (p, r)
+  std::vector<int4> zrows;
+  for (int p = 0; p < P; ++p)
+    for (int r = p; r < P; ++r) {
+      for (int s = r; s < P; ++s) zrows.push_back(make_int4(p, r, s, tri_index[((size_t)p * P + r) * P + s]));
+      while (zrows.size() % 4) zrows.push_back(make_int4(p, r, r, -1));
+    }
+  c->t.nzrows = (int)zrows.size();
   std::vector<int2> qtiles;
   {
     const int nt = quad_ntile(c->npairs);
@@ -479,7 +488,7 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
       upload(&t.pair_b, pb) != hipSuccess || upload(&t.tri, tri) != hipSuccess ||
       upload(&t.pair_of, pair_of) != hipSuccess || upload(&t.tri_of, tri_of) != hipSuccess ||
       upload(&t.tri_mult, tri_mult) != hipSuccess || upload(&t.quad, quad) != hipSuccess ||
-      upload(&t.qtiles, qtiles) != hipSuccess)
+      upload(&t.qtiles, qtiles) != hipSuccess || upload(&t.zrows, zrows) != hipSuccess)
     return bail(MODAL_EDEVICE);
   if (hipMalloc((void**)&t.seed, 2 * sizeof(double) * (lmax + 1) * (size_t)c->nrp) != hipSuccess ||
       hipMalloc((void**)&t.lstart, sizeof(int) * (lmax + 1) * (size_t)c->nrp) != hipSuccess ||
@@ -522,7 +531,7 @@ void modal_destroy(modal_ctx* c) {
   Tables& t = c->t;
   void* ptrs[] = {t.x, t.ringw, t.w64, t.w32, t.rec, t.seed, t.lstart, t.lstart_blk, t.qw64, t.qw32, t.tw64, t.tw32,
                   t.pair_a, t.pair_b, t.tri, t.pair_of, t.tri_of, t.tri_mult, t.flag, t.blk, t.items, t.mscale,
-                  t.twp32, t.lamtab, t.lamtab_off, t.quad, t.qtiles};
+                  t.twp32, t.lamtab, t.lamtab_off, t.quad, t.qtiles, t.zrows};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -999,7 +1008,7 @@ modal_status modal_ideal_covariance(modal_ctx* c, const double* c_host, double* 
   {
     StageTimer _t(c, MODAL_STAGE_COVARIANCE, st);
     HIPTRY(launch_legendre_series(L, nmu, P, P, U, Bq, dmu, F, st));
-    HIPTRY(launch_ideal_cov(c->nmax, P, nmu, c->t.tri, F, dw, zeta, st));
+    HIPTRY(launch_ideal_cov(c->nmax, P, nmu, c->t.nzrows, c->t.zrows, F, dw, zeta, st));
   }
   HIPTRY(hipStreamSynchronize(st));
   return MODAL_OK;

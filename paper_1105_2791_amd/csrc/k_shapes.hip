@@ -88,33 +88,43 @@ __global__ __launch_bounds__(256) void k_alpha_modes(int nmax, int P, int T, int
   alpha[n] = acc * (1.0 / (48.0 * 3.14159265358979323846));
 }
 
-// zeta0 tile (bi, bj), bj <= bi, mirrored; Q slices [KC][P][P+1] staged in dynamic LDS.
-__global__ __launch_bounds__(256) void k_ideal_cov(int nmax, int P, int nmu, int KC, const int* __restrict__ tri,
-                                                   const double* __restrict__ F, const double* __restrict__ wmu,
-                                                   double* __restrict__ Z) {
+// zeta0 over the padded row order (runs of equal (p, r), each a multiple of 4 rows):
+// tile (bi, bj), bj <= bi, mirrored; Q slices [KC][P][P+1] staged in dynamic LDS.
+// Each thread owns 4 rows (a, b, c_u) and 4 columns (d, e, f_v) of one aligned group, so
+// the permanent of the 3 x 3 block, expanded along its third row,
+//   perm = Q_cf (Q_ad Q_be + Q_ae Q_bd) + Q_ce (Q_ad Q_bf + Q_af Q_bd) + Q_cd (Q_ae Q_bf + Q_af Q_be),
+// shares its 2 x 2 permanents across the thread's rows: 36 LDS reads per node for the
+// 16 entries instead of 144.
+__global__ __launch_bounds__(256) void k_ideal_cov(int nmax, int P, int nmu, int KC, int nrows,
+                                                   const int4* __restrict__ zrows, const double* __restrict__ F,
+                                                   const double* __restrict__ wmu, double* __restrict__ Z) {
   extern __shared__ double qs_raw[];
   const int bi = blockIdx.y, bj = blockIdx.x;
   if (bj > bi) return;
   const int PP = P + 1;
   double* wk = qs_raw + (size_t)KC * P * PP;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  int ra[4], rb[4], rc[4], cd[4], ce[4], cf[4];
+  // groups past the table (whole groups: nrows % 4 == 0) take a dummy row of mode -1
+  int4 rr[4], cc[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int i = min(bi * 64 + ty * 4 + u, nmax - 1), j = min(bj * 64 + tx * 4 + u, nmax - 1);
-    ra[u] = tri[6 * i] * PP;
-    rb[u] = tri[6 * i + 1] * PP;
-    rc[u] = tri[6 * i + 2] * PP;
-    cd[u] = tri[6 * j];
-    ce[u] = tri[6 * j + 1];
-    cf[u] = tri[6 * j + 2];
+    const int i = bi * 64 + ty * 4 + u, j = bj * 64 + tx * 4 + u;
+    rr[u] = i < nrows ? zrows[i] : make_int4(0, 0, 0, -1);
+    cc[u] = j < nrows ? zrows[j] : make_int4(0, 0, 0, -1);
+  }
+  const int ra = rr[0].x * PP, rb = rr[0].y * PP, d = cc[0].x, e = cc[0].y;
+  int rc[4], cf[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    rc[u] = rr[u].z * PP;
+    cf[u] = cc[u].z;
   }
   double acc[4][4] = {};
   for (int k0 = 0; k0 < nmu; k0 += KC) {
     const int kn = min(KC, nmu - k0);
     __syncthreads();
-    for (int e = threadIdx.x; e < kn * P * P; e += 256) {
-      const int kk = e / (P * P), rem = e - kk * P * P, b = rem / P, a = rem - b * P;
+    for (int x = threadIdx.x; x < kn * P * P; x += 256) {
+      const int kk = x / (P * P), rem = x - kk * P * P, b = rem / P, a = rem - b * P;
       qs_raw[(size_t)kk * P * PP + a * PP + b] = F[((size_t)b * nmu + k0 + kk) * P + a];   // Q_ab(mu_k)
     }
     if ((int)threadIdx.x < kn) wk[threadIdx.x] = wmu[k0 + threadIdx.x];
@@ -122,18 +132,24 @@ __global__ __launch_bounds__(256) void k_ideal_cov(int nmax, int P, int nmu, int
     for (int kk = 0; kk < kn; ++kk) {
       const double* Q = qs_raw + (size_t)kk * P * PP;
       const double w = wk[kk];
+      const double qad = Q[ra + d], qae = Q[ra + e], qbd = Q[rb + d], qbe = Q[rb + e];
+      const double t0 = qad * qbe + qae * qbd;
+      double t1[4], t2[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int v = 0; v < 4; ++v) {
+        const double qaf = Q[ra + cf[v]], qbf = Q[rb + cf[v]];
+        t1[v] = qad * qbf + qaf * qbd;
+        t2[v] = qae * qbf + qaf * qbe;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double qcd = Q[rc[u] + d], qce = Q[rc[u] + e];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const double* qa = Q + ra[u];
-          const double* qb = Q + rb[u];
-          const double* qc = Q + rc[u];
-          const int d = cd[v], e = ce[v], f = cf[v];
-          const double s = qa[d] * (qb[e] * qc[f] + qb[f] * qc[e]) + qa[e] * (qb[d] * qc[f] + qb[f] * qc[d]) +
-                           qa[f] * (qb[d] * qc[e] + qb[e] * qc[d]);
+          const double s = Q[rc[u] + cf[v]] * t0 + qce * t1[v] + qcd * t2[v];
           acc[u][v] = fma(w, s, acc[u][v]);
         }
+      }
     }
   }
   const double scale = 1.0 / (48.0 * 3.14159265358979323846);
@@ -141,10 +157,10 @@ __global__ __launch_bounds__(256) void k_ideal_cov(int nmax, int P, int nmu, int
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int i = bi * 64 + ty * 4 + u, j = bj * 64 + tx * 4 + v;
-      if (i < nmax && j <= i) {   // one writer per symmetric pair
-        Z[(size_t)i * nmax + j] = scale * acc[u][v];
-        Z[(size_t)j * nmax + i] = scale * acc[u][v];
+      const int n = rr[u].w, m = cc[v].w;
+      if (n >= 0 && m >= 0 && m <= n) {   // one writer per symmetric pair
+        Z[(size_t)n * nmax + m] = scale * acc[u][v];
+        Z[(size_t)m * nmax + n] = scale * acc[u][v];
       }
     }
 }
@@ -168,13 +184,13 @@ hipError_t launch_alpha_modes(int nmax, int P, int T, int nmu, const int* tri, c
   return hipGetLastError();
 }
 
-hipError_t launch_ideal_cov(int nmax, int P, int nmu, const int* tri, const double* F, const double* wmu, double* Z,
-                            hipStream_t st) {
+hipError_t launch_ideal_cov(int nmax, int P, int nmu, int nrows, const int4* zrows, const double* F,
+                            const double* wmu, double* Z, hipStream_t st) {
   const size_t slice = (size_t)P * (P + 1) * 8 + 8;
   const int KC = (int)std::max<size_t>(1, std::min<size_t>(8, 65536 / slice));
   const size_t lds = (size_t)KC * slice;
-  const int nt = (nmax + 63) / 64;
-  hipLaunchKernelGGL(k_ideal_cov, dim3(nt, nt), dim3(256), lds, st, nmax, P, nmu, KC, tri, F, wmu, Z);
+  const int nt = (nrows + 63) / 64;
+  hipLaunchKernelGGL(k_ideal_cov, dim3(nt, nt), dim3(256), lds, st, nmax, P, nmu, KC, nrows, zrows, F, wmu, Z);
   return hipGetLastError();
 }
 
