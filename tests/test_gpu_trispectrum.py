@@ -45,7 +45,7 @@ def ctx_case(case, prec):
     return _ctx[key]
 
 
-def oracle_case(case, S=2):
+def oracle_case(case, S=3):
     if case.name not in _or:
         alms = case.alms(0, S)
         mc = case.alms(500, 4)
