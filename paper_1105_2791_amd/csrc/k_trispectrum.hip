@@ -28,13 +28,15 @@ typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
 constexpr int TT = 128;      // output tile of the MFMA kernel (rows = cols)
 constexpr int PXS = 32;      // pixels per staged step (two MFMA K = 16 steps)
 constexpr int OPS = PXS;     // operand row stride in LDS (bf16; 16-byte fragments stay aligned)
-constexpr int MPS = PXS + 1; // map / pair-mean row stride in LDS (odd: the lanes read different rows)
+constexpr int MPS = PXS + 4; // map row stride in LDS (floats; rows stay 16-byte aligned)
 constexpr int CH = 16;       // staged steps per MFMA accumulation chain (96 MFMAs per tile)
+constexpr int GPR = PXS / 4; // 4-pixel groups per row
+constexpr int RPT = 2 * TT * GPR / 256;   // operand rows per thread (8)
 
 struct TriLds {
   float ms[kMaxP][MPS];
-  float vs[2 * TT][MPS];   // pair means of the operand rows for the step
-  float sw[PXS];
+  float4 vs[RPT][256];     // each thread's own pair means of the step (thread-private)
+  float4 sw[256];          // each thread's sqrt(w) of its 4 pixels (thread-private)
   uint16_t oh[2 * TT][OPS];
   uint16_t ol[2 * TT][OPS];
 };
@@ -56,6 +58,10 @@ __device__ inline void split2(float v0, float v1, uint32_t& hi, uint32_t& lo) {
 
 // Tile pair (ti, tj), ti <= tj, of the R x R result, pixel chunk c, sky s (vmode: operands
 // are the pair means themselves).  part[s][c][tp][TT][TT] FP32 sums of the chunk.
+// Thread t forms the operands of the 4 pixels 4 (t % 8) .. + 3 of the rows t / 8 + 32 j,
+// j < 8 (rows 0..127 of tile ti, then 128..255 of tile tj): its pair-mean and weight loads
+// are float4 and coalesced along each row, its map reads and operand writes are 16- and
+// 8-byte LDS accesses.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_quad_syrk(int P, int R, int npix, int nchunk, int chunk_px, int ntp,
                                                    const int2* __restrict__ tpairs, const int* __restrict__ pair_a,
                                                    const int* __restrict__ pair_b, const float* __restrict__ maps,
@@ -67,10 +73,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int2 tt = tpairs[tp];
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int wi = wv >> 1, wj = wv & 1;
-  // this thread's operand row: rows 0..127 of tile ti, then 128..255 of tile tj
-  const int orow = (tid < TT ? tt.x : tt.y) * TT + (tid & (TT - 1));
-  const bool rok = orow < R;
-  const int pa = rok ? pair_a[orow] : 0, pb = rok ? pair_b[orow] : 0;
+  const int g = tid & (GPR - 1), rsub = tid / GPR;
+  // this thread's operand rows r = rsub + 32 j (j < 4 in tile ti, j >= 4 in tile tj):
+  // pair index rowp(j); its two modes, 8 bits each, packed two rows to a word
+  const int rb0 = tt.x * TT + rsub, rb1 = tt.y * TT + rsub - TT;
+  auto rowp = [&](int j) { return (j < RPT / 2 ? rb0 : rb1) + 32 * j; };
+  uint32_t pab[RPT / 2] = {};
+  unsigned rokm = 0;
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const int orow = rowp(j);
+    const bool ok = orow < R;
+    const uint32_t ab = ok ? (uint32_t)(pair_a[orow] | (pair_b[orow] << 8)) : 0u;
+    pab[j >> 1] |= ab << (16 * (j & 1));
+    rokm |= ok ? (1u << j) : 0u;
+  }
   const bool hasV = V != nullptr;   // no state: V = 0 (never read); vmode always has V
   const float* Msky = maps + (size_t)s * P * npix;
   const int x0 = chunk * chunk_px, x1 = min(npix, x0 + chunk_px);
@@ -83,91 +100,101 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = cha[a][b][r] = 0.f;
   int link = 0;
-  // the workgroup's operand rows (tile ti then tile tj) for the staging of V
-  const int vrow0 = tt.x * TT, vrow1 = tt.y * TT;
-  // Staging of maps and pair means in 4-pixel groups (float4, coalesced along each row;
-  // npix % 4 == 0 and 32-pixel chunk starts keep a group wholly inside or wholly past the
-  // chunk end).  The next step's loads are issued into registers before this step's
-  // operand formation and MFMAs, so their latency is hidden behind that work.
-  constexpr int GPR = PXS / 4;                          // groups per row
-  constexpr int NVL = 2 * TT * GPR / 256;               // V groups per thread (8)
+  // Staging in 4-pixel groups (float4; npix % 4 == 0 and 32-pixel chunk starts keep a
+  // group wholly inside or wholly past the chunk end).  The next step's loads are issued
+  // into registers before this step's operand formation and MFMAs, so their latency is
+  // hidden behind that work.
   constexpr int NML = (kMaxP * GPR + 255) / 256;        // map groups per thread (2)
-  float4 pv[NVL], pm[NML];
+  float4 pv[RPT], pm[NML], pw;
   auto load_step = [&](int xs) {
 #pragma unroll
     for (int k = 0; k < NML; ++k) {
-      const int e = tid + 256 * k, r = e / GPR, g = e - r * GPR, x = xs + 4 * g;
+      const int e = tid + 256 * k, r = e / GPR, gg = e - r * GPR, x = xs + 4 * gg;
       pm[k] = make_float4(0.f, 0.f, 0.f, 0.f);
       if (!vmode && r < P && x < x1) pm[k] = *reinterpret_cast<const float4*>(Msky + (size_t)r * npix + x);
     }
+    const int x = xs + 4 * g;
 #pragma unroll
-    for (int k = 0; k < NVL; ++k) {
-      const int e = tid + 256 * k, r = e / GPR, g = e - r * GPR, x = xs + 4 * g;
-      const int row = (r < TT ? vrow0 : vrow1 - TT) + r;
-      pv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (hasV && x < x1 && row < R) pv[k] = *reinterpret_cast<const float4*>(V + (size_t)row * npix + x);
+    for (int j = 0; j < RPT; ++j) {
+      pv[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (hasV && x < x1 && ((rokm >> j) & 1u)) pv[j] = *reinterpret_cast<const float4*>(V + (size_t)rowp(j) * npix + x);
     }
+    pw = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (x < x1) pw = *reinterpret_cast<const float4*>(w + x);
   };
   auto store_step = [&]() {
 #pragma unroll
     for (int k = 0; k < NML; ++k) {
-      const int e = tid + 256 * k, r = e / GPR, g = e - r * GPR;
-      if (r < kMaxP) {
-        float* d = &L.ms[r][4 * g];
-        d[0] = pm[k].x; d[1] = pm[k].y; d[2] = pm[k].z; d[3] = pm[k].w;
-      }
+      const int e = tid + 256 * k, r = e / GPR, gg = e - r * GPR;
+      if (r < kMaxP) *reinterpret_cast<float4*>(&L.ms[r][4 * gg]) = pm[k];
     }
 #pragma unroll
-    for (int k = 0; k < NVL; ++k) {
-      const int e = tid + 256 * k, r = e / GPR, g = e - r * GPR;
-      float* d = &L.vs[r][4 * g];
-      d[0] = pv[k].x; d[1] = pv[k].y; d[2] = pv[k].z; d[3] = pv[k].w;
+    for (int j = 0; j < RPT; ++j) L.vs[j][tid] = pv[j];
+    L.sw[tid] = make_float4(sqrtf(pw.x), sqrtf(pw.y), sqrtf(pw.z), sqrtf(pw.w));
+  };
+  // element-wise staging (npix % 4 != 0): the same layout, scalar loads
+  auto stage_scalar = [&](int xs) {
+    if (!vmode)
+      for (int e = tid; e < P * PXS; e += 256) {
+        const int r = e / PXS, i = e - r * PXS, x = xs + i;
+        L.ms[r][i] = x < x1 ? Msky[(size_t)r * npix + x] : 0.f;
+      }
+    float q[4], sq[4];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int x = xs + 4 * g + k;
+        q[k] = (hasV && x < x1 && ((rokm >> j) & 1u)) ? V[(size_t)rowp(j) * npix + x] : 0.f;
+      }
+      L.vs[j][tid] = make_float4(q[0], q[1], q[2], q[3]);
     }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int x = xs + 4 * g + k;
+      sq[k] = x < x1 ? sqrtf(w[x]) : 0.f;
+    }
+    L.sw[tid] = make_float4(sq[0], sq[1], sq[2], sq[3]);
   };
   if (vec) load_step(x0);
   for (int xs = x0; xs < x1; xs += PXS) {
     __syncthreads();
-    if (vec) {
-      store_step();
-    } else {
-      if (!vmode)
-        for (int e = tid; e < P * PXS; e += 256) {
-          const int r = e / PXS, i = e - r * PXS, x = xs + i;
-          L.ms[r][i] = x < x1 ? Msky[(size_t)r * npix + x] : 0.f;
-        }
-      if (hasV)
-        for (int e = tid; e < 2 * TT * PXS; e += 256) {
-          const int r = e / PXS, i = e - r * PXS, x = xs + i;
-          const int row = (r < TT ? vrow0 : vrow1 - TT) + r;
-          L.vs[r][i] = (x < x1 && row < R) ? V[(size_t)row * npix + x] : 0.f;
-        }
-    }
-    if (tid < PXS) {
-      const int x = xs + tid;
-      L.sw[tid] = x < x1 ? sqrtf(w[x]) : 0.f;
-    }
+    if (vec) store_step();
+    else stage_scalar(xs);
     __syncthreads();
     if (vec && xs + PXS < x1) load_step(xs + PXS);
-    // operands sqrt(w) (M_a M_b - 3 V_ab), or sqrt(w) V_ab, split hi/lo
-#pragma unroll 4
-    for (int i = 0; i < PXS; i += 2) {
-      float v0 = 0.f, v1 = 0.f;
-      if (rok) {
-        const float V0 = hasV ? L.vs[tid][i] : 0.f, V1 = hasV ? L.vs[tid][i + 1] : 0.f;
-        if (vmode) {
-          v0 = V0;
-          v1 = V1;
-        } else {
-          v0 = fmaf(L.ms[pa][i], L.ms[pb][i], -3.f * V0);
-          v1 = fmaf(L.ms[pa][i + 1], L.ms[pb][i + 1], -3.f * V1);
+    // operands sqrt(w) (M_a M_b - 3 V_ab), or sqrt(w) V_ab, split hi/lo, 4 pixels x 8 rows
+    {
+      const float4 sq = L.sw[tid];
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        const int r = rsub + 32 * j;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if ((rokm >> j) & 1u) {
+          const float4 vv = hasV ? L.vs[j][tid] : make_float4(0.f, 0.f, 0.f, 0.f);
+          if (vmode) {
+            v = vv;
+          } else {
+            const uint32_t ab = pab[j >> 1] >> (16 * (j & 1));
+            const float4 ma = *reinterpret_cast<const float4*>(&L.ms[ab & 0xff][4 * g]);
+            const float4 mb = *reinterpret_cast<const float4*>(&L.ms[(ab >> 8) & 0xff][4 * g]);
+            v.x = fmaf(ma.x, mb.x, -3.f * vv.x);
+            v.y = fmaf(ma.y, mb.y, -3.f * vv.y);
+            v.z = fmaf(ma.z, mb.z, -3.f * vv.z);
+            v.w = fmaf(ma.w, mb.w, -3.f * vv.w);
+          }
+          v.x *= sq.x;
+          v.y *= sq.y;
+          v.z *= sq.z;
+          v.w *= sq.w;
         }
-        v0 *= L.sw[i];
-        v1 *= L.sw[i + 1];
+        uint32_t h0, l0, h1, l1;
+        split2(v.x, v.y, h0, l0);
+        split2(v.z, v.w, h1, l1);
+        *reinterpret_cast<uint2*>(&L.oh[r][4 * g]) = make_uint2(h0, h1);
+        *reinterpret_cast<uint2*>(&L.ol[r][4 * g]) = make_uint2(l0, l1);
+        if (j & 1) __builtin_amdgcn_sched_barrier(0);   // two rows in flight at a time (registers)
       }
-      uint32_t h, l;
-      split2(v0, v1, h, l);
-      *reinterpret_cast<uint32_t*>(&L.oh[tid][i]) = h;
-      *reinterpret_cast<uint32_t*>(&L.ol[tid][i]) = l;
     }
     __syncthreads();
 #pragma unroll
