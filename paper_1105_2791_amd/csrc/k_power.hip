@@ -62,28 +62,40 @@ __global__ __launch_bounds__(256) void k_pair_sums(int P, int npix, int chunk_px
     for (int j = 0; j < 4; ++j) acc[i][j] = 0;
   const T* Msky = maps + (size_t)s * P * npix;
   const int x0 = chunk * chunk_px, x1 = min(npix, x0 + chunk_px);
+  // 4-pixel groups: chunks start at multiples of 4 and npix % 4 == 0, so a group is
+  // wholly inside or wholly past the chunk end; rows >= P stage zeros.  The next step's
+  // groups are loaded into registers before this step's products, so that their latency
+  // is hidden behind them.
+  // (the group e = tid + 256 k has pixel group tid % 32 for every k: one weight group)
+  constexpr int NPF = kMaxP * (PKC / 4) / 256;   // groups per thread at most (8)
+  T4 pm[NPF], pw;
+  auto load_step = [&](int xs) {
+    const int x = xs + 4 * (tid % (PKC / 4));
+    pw.x = pw.y = pw.z = pw.w = T(0);
+    if (x < x1) pw = *reinterpret_cast<const T4*>(w + x);
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) {
+      const int r = (tid + 256 * k) / (PKC / 4);
+      pm[k].x = pm[k].y = pm[k].z = pm[k].w = T(0);
+      if (r < P && x < x1) pm[k] = *reinterpret_cast<const T4*>(Msky + (size_t)r * npix + x);
+    }
+  };
+  if (vec) load_step(x0);
   for (int xs = x0; xs < x1; xs += PKC) {
     __syncthreads();
     if (vec) {
-      // 4-pixel groups: chunks start at multiples of 4 and npix % 4 == 0, so a group is
-      // wholly inside or wholly past the chunk end; rows >= P stage zeros
-      for (int e = tid; e < PR * (PKC / 4); e += 256) {
-        const int r = e / (PKC / 4), g = e - r * (PKC / 4), x = xs + 4 * g;
-        T4 m, ww;
-        if (r < P && x < x1) {
-          m = *reinterpret_cast<const T4*>(Msky + (size_t)r * npix + x);
-          ww = *reinterpret_cast<const T4*>(w + x);
-        } else {
-          m.x = m.y = m.z = m.w = T(0);
-          ww = m;
+#pragma unroll
+      for (int k = 0; k < NPF; ++k) {
+        const int e = tid + 256 * k, r = e / (PKC / 4), g = e - r * (PKC / 4);
+        if (r < PR) {
+          *reinterpret_cast<T4*>(Ms + (size_t)r * PKS + 4 * g) = pm[k];
+          T4 wm;
+          wm.x = pw.x * pm[k].x;
+          wm.y = pw.y * pm[k].y;
+          wm.z = pw.z * pm[k].z;
+          wm.w = pw.w * pm[k].w;
+          *reinterpret_cast<T4*>(Ws + (size_t)r * PKS + 4 * g) = wm;
         }
-        *reinterpret_cast<T4*>(Ms + (size_t)r * PKS + 4 * g) = m;
-        T4 wm;
-        wm.x = ww.x * m.x;
-        wm.y = ww.y * m.y;
-        wm.z = ww.z * m.z;
-        wm.w = ww.w * m.w;
-        *reinterpret_cast<T4*>(Ws + (size_t)r * PKS + 4 * g) = wm;
       }
     } else {
       for (int e = tid; e < PR * PKC; e += 256) {
@@ -96,6 +108,7 @@ __global__ __launch_bounds__(256) void k_pair_sums(int P, int npix, int chunk_px
       }
     }
     __syncthreads();
+    if (vec && xs + PKC < x1) load_step(xs + PKC);
     if (on)
       for (int g = ph; g < PKC / 4; g += nph) {
         T4 a[4], b[4];
