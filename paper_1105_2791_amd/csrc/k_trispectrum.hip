@@ -32,13 +32,15 @@ constexpr int MPS = PXS + 4; // map row stride in LDS (floats; rows stay 16-byte
 constexpr int CH = 16;       // staged steps per MFMA accumulation chain (96 MFMAs per tile)
 constexpr int GPR = PXS / 4; // 4-pixel groups per row
 constexpr int RPT = 2 * TT * GPR / 256;   // operand rows per thread (8)
+constexpr int SKW = 2;       // skies per workgroup, one per half: the pair means are loaded once
+constexpr int NTQ = 256 * SKW;
 
 struct TriLds {
-  float ms[kMaxP][MPS];
-  float4 vs[RPT][256];     // each thread's own pair means of the step (thread-private)
-  float4 sw[256];          // each thread's sqrt(w) of its 4 pixels (thread-private)
-  uint16_t oh[2 * TT][OPS];
-  uint16_t ol[2 * TT][OPS];
+  float ms[SKW][kMaxP][MPS];
+  float4 vs[RPT][256];     // pair means of thread t's rows and pixels (read by t of both halves)
+  float4 sw[256];          // sqrt(w) of thread t's 4 pixels
+  uint16_t oh[SKW][2 * TT][OPS];
+  uint16_t ol[SKW][2 * TT][OPS];
 };
 
 __device__ inline uint32_t bf16_pair(float a, float b) {
@@ -56,24 +58,30 @@ __device__ inline void split2(float v0, float v1, uint32_t& hi, uint32_t& lo) {
   lo = bf16_pair(v0 - __builtin_bit_cast(float, hi << 16), v1 - __builtin_bit_cast(float, hi & 0xffff0000u));
 }
 
-// Tile pair (ti, tj), ti <= tj, of the R x R result, pixel chunk c, sky s (vmode: operands
-// are the pair means themselves).  part[s][c][tp][TT][TT] FP32 sums of the chunk.
-// Thread t forms the operands of the 4 pixels 4 (t % 8) .. + 3 of the rows t / 8 + 32 j,
-// j < 8 (rows 0..127 of tile ti, then 128..255 of tile tj): its pair-mean and weight loads
-// are float4 and coalesced along each row, its map reads and operand writes are 16- and
-// 8-byte LDS accesses.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_quad_syrk(int P, int R, int npix, int nchunk, int chunk_px, int ntp,
+// Tile pair (ti, tj), ti <= tj, of the R x R result, pixel chunk c, skies SKW z + h for the
+// two halves h of the workgroup (vmode: operands are the pair means themselves, one
+// "sky").  part[s][c][tp][TT][TT] FP32 sums of the chunk.
+// Thread t of a half forms the operands of the 4 pixels 4 (t % 8) .. + 3 of the rows
+// t / 8 + 32 j, j < 8 (rows 0..127 of tile ti, then 128..255 of tile tj): its pair-mean and
+// weight loads are float4 and coalesced along each row, its map reads and operand writes
+// are 16- and 8-byte LDS accesses.  The pair means of a step are the same for both skies:
+// half h loads the rows j = 4 h .. 4 h + 3 and both halves read all eight, so each pair
+// mean is read from HBM once per two skies.
+__global__ __launch_bounds__(NTQ) __attribute__((amdgpu_waves_per_eu(2))) void k_quad_syrk(int P, int R, int npix, int S, int nchunk, int chunk_px, int ntp,
                                                    const int2* __restrict__ tpairs, const int* __restrict__ pair_a,
                                                    const int* __restrict__ pair_b, const float* __restrict__ maps,
                                                    const float* __restrict__ V, const float* __restrict__ w,
                                                    int vmode, int vec, float* __restrict__ part) {
   extern __shared__ __attribute__((aligned(16))) unsigned char traw[];
   TriLds& L = *reinterpret_cast<TriLds*>(traw);
-  const int tp = blockIdx.x, chunk = blockIdx.y, s = blockIdx.z;
+  const int tp = blockIdx.x, chunk = blockIdx.y;
   const int2 tt = tpairs[tp];
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  const int wi = wv >> 1, wj = wv & 1;
-  const int g = tid & (GPR - 1), rsub = tid / GPR;
+  const int h = tid >> 8, t = tid & 255;           // sky half, thread within the half
+  const int s = SKW * blockIdx.z + h;
+  const bool skyok = s < S;                        // uniform over the half's four waves
+  const int wq = wv & 3, wi = wq >> 1, wj = wq & 1;
+  const int g = t & (GPR - 1), rsub = t / GPR;
   // this thread's operand rows r = rsub + 32 j (j < 4 in tile ti, j >= 4 in tile tj):
   // pair index rowp(j); its two modes, 8 bits each, packed two rows to a word
   const int rb0 = tt.x * TT + rsub, rb1 = tt.y * TT + rsub - TT;
@@ -89,7 +97,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     rokm |= ok ? (1u << j) : 0u;
   }
   const bool hasV = V != nullptr;   // no state: V = 0 (never read); vmode always has V
-  const float* Msky = maps + (size_t)s * P * npix;
+  const float* Msky = maps + (size_t)min(s, S - 1) * P * npix;
   const int x0 = chunk * chunk_px, x1 = min(npix, x0 + chunk_px);
 
   f32x16 acc[2][2], cha[2][2];
@@ -105,56 +113,63 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // into registers before this step's operand formation and MFMAs, so their latency is
   // hidden behind that work.
   constexpr int NML = (kMaxP * GPR + 255) / 256;        // map groups per thread (2)
-  float4 pv[RPT], pm[NML], pw;
+  constexpr int RPH = RPT / SKW;                        // pair-mean rows loaded per thread (4)
+  const int vbase = h == 0 ? rb0 : rb1;                 // rows of this half's j range
+  float4 pv[RPH], pm[NML], pw;
   auto load_step = [&](int xs) {
 #pragma unroll
     for (int k = 0; k < NML; ++k) {
-      const int e = tid + 256 * k, r = e / GPR, gg = e - r * GPR, x = xs + 4 * gg;
+      const int e = t + 256 * k, r = e / GPR, gg = e - r * GPR, x = xs + 4 * gg;
       pm[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (!vmode && r < P && x < x1) pm[k] = *reinterpret_cast<const float4*>(Msky + (size_t)r * npix + x);
+      if (!vmode && skyok && r < P && x < x1) pm[k] = *reinterpret_cast<const float4*>(Msky + (size_t)r * npix + x);
     }
     const int x = xs + 4 * g;
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-      pv[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (hasV && x < x1 && ((rokm >> j) & 1u)) pv[j] = *reinterpret_cast<const float4*>(V + (size_t)rowp(j) * npix + x);
+    for (int jj = 0; jj < RPH; ++jj) {
+      const int j = RPH * h + jj;
+      pv[jj] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (hasV && x < x1 && ((rokm >> j) & 1u))
+        pv[jj] = *reinterpret_cast<const float4*>(V + (size_t)(vbase + 32 * j) * npix + x);
     }
     pw = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (x < x1) pw = *reinterpret_cast<const float4*>(w + x);
+    if (h == 0 && x < x1) pw = *reinterpret_cast<const float4*>(w + x);
   };
   auto store_step = [&]() {
 #pragma unroll
     for (int k = 0; k < NML; ++k) {
-      const int e = tid + 256 * k, r = e / GPR, gg = e - r * GPR;
-      if (r < kMaxP) *reinterpret_cast<float4*>(&L.ms[r][4 * gg]) = pm[k];
+      const int e = t + 256 * k, r = e / GPR, gg = e - r * GPR;
+      if (r < kMaxP) *reinterpret_cast<float4*>(&L.ms[h][r][4 * gg]) = pm[k];
     }
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) L.vs[j][tid] = pv[j];
-    L.sw[tid] = make_float4(sqrtf(pw.x), sqrtf(pw.y), sqrtf(pw.z), sqrtf(pw.w));
+    for (int jj = 0; jj < RPH; ++jj) L.vs[RPH * h + jj][t] = pv[jj];
+    if (h == 0) L.sw[t] = make_float4(sqrtf(pw.x), sqrtf(pw.y), sqrtf(pw.z), sqrtf(pw.w));
   };
   // element-wise staging (npix % 4 != 0): the same layout, scalar loads
   auto stage_scalar = [&](int xs) {
     if (!vmode)
-      for (int e = tid; e < P * PXS; e += 256) {
+      for (int e = t; e < P * PXS; e += 256) {
         const int r = e / PXS, i = e - r * PXS, x = xs + i;
-        L.ms[r][i] = x < x1 ? Msky[(size_t)r * npix + x] : 0.f;
+        L.ms[h][r][i] = (skyok && x < x1) ? Msky[(size_t)r * npix + x] : 0.f;
       }
     float q[4], sq[4];
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
+    for (int jj = 0; jj < RPH; ++jj) {
+      const int j = RPH * h + jj;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int x = xs + 4 * g + k;
-        q[k] = (hasV && x < x1 && ((rokm >> j) & 1u)) ? V[(size_t)rowp(j) * npix + x] : 0.f;
+        q[k] = (hasV && x < x1 && ((rokm >> j) & 1u)) ? V[(size_t)(vbase + 32 * j) * npix + x] : 0.f;
       }
-      L.vs[j][tid] = make_float4(q[0], q[1], q[2], q[3]);
+      L.vs[j][t] = make_float4(q[0], q[1], q[2], q[3]);
     }
+    if (h == 0) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int x = xs + 4 * g + k;
-      sq[k] = x < x1 ? sqrtf(w[x]) : 0.f;
+      for (int k = 0; k < 4; ++k) {
+        const int x = xs + 4 * g + k;
+        sq[k] = x < x1 ? sqrtf(w[x]) : 0.f;
+      }
+      L.sw[t] = make_float4(sq[0], sq[1], sq[2], sq[3]);
     }
-    L.sw[tid] = make_float4(sq[0], sq[1], sq[2], sq[3]);
   };
   if (vec) load_step(x0);
   for (int xs = x0; xs < x1; xs += PXS) {
@@ -164,20 +179,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     __syncthreads();
     if (vec && xs + PXS < x1) load_step(xs + PXS);
     // operands sqrt(w) (M_a M_b - 3 V_ab), or sqrt(w) V_ab, split hi/lo, 4 pixels x 8 rows
-    {
-      const float4 sq = L.sw[tid];
+    if (skyok) {
+      const float4 sq = L.sw[t];
 #pragma unroll
       for (int j = 0; j < RPT; ++j) {
         const int r = rsub + 32 * j;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if ((rokm >> j) & 1u) {
-          const float4 vv = hasV ? L.vs[j][tid] : make_float4(0.f, 0.f, 0.f, 0.f);
+          const float4 vv = hasV ? L.vs[j][t] : make_float4(0.f, 0.f, 0.f, 0.f);
           if (vmode) {
             v = vv;
           } else {
             const uint32_t ab = pab[j >> 1] >> (16 * (j & 1));
-            const float4 ma = *reinterpret_cast<const float4*>(&L.ms[ab & 0xff][4 * g]);
-            const float4 mb = *reinterpret_cast<const float4*>(&L.ms[(ab >> 8) & 0xff][4 * g]);
+            const float4 ma = *reinterpret_cast<const float4*>(&L.ms[h][ab & 0xff][4 * g]);
+            const float4 mb = *reinterpret_cast<const float4*>(&L.ms[h][(ab >> 8) & 0xff][4 * g]);
             v.x = fmaf(ma.x, mb.x, -3.f * vv.x);
             v.y = fmaf(ma.y, mb.y, -3.f * vv.y);
             v.z = fmaf(ma.z, mb.z, -3.f * vv.z);
@@ -191,50 +206,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         uint32_t h0, l0, h1, l1;
         split2(v.x, v.y, h0, l0);
         split2(v.z, v.w, h1, l1);
-        *reinterpret_cast<uint2*>(&L.oh[r][4 * g]) = make_uint2(h0, h1);
-        *reinterpret_cast<uint2*>(&L.ol[r][4 * g]) = make_uint2(l0, l1);
+        *reinterpret_cast<uint2*>(&L.oh[h][r][4 * g]) = make_uint2(h0, h1);
+        *reinterpret_cast<uint2*>(&L.ol[h][r][4 * g]) = make_uint2(l0, l1);
         if (j & 1) __builtin_amdgcn_sched_barrier(0);   // two rows in flight at a time (registers)
       }
     }
     __syncthreads();
+    if (skyok) {
 #pragma unroll
-    for (int ks = 0; ks < PXS / 16; ++ks) {
-      const int kx = 16 * ks + 8 * (lane >> 5);
-      bf16x8 ah[2], al[2], bh[2], bl[2];
+      for (int ks = 0; ks < PXS / 16; ++ks) {
+        const int kx = 16 * ks + 8 * (lane >> 5);
+        bf16x8 ah[2], al[2], bh[2], bl[2];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int ra = 64 * wi + 32 * t + (lane & 31);
-        const int rb = TT + 64 * wj + 32 * t + (lane & 31);
-        ah[t] = *reinterpret_cast<const bf16x8*>(&L.oh[ra][kx]);
-        al[t] = *reinterpret_cast<const bf16x8*>(&L.ol[ra][kx]);
-        bh[t] = *reinterpret_cast<const bf16x8*>(&L.oh[rb][kx]);
-        bl[t] = *reinterpret_cast<const bf16x8*>(&L.ol[rb][kx]);
-      }
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) cha[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], cha[a][b], 0, 0, 0);
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) cha[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], cha[a][b], 0, 0, 0);
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) cha[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], cha[a][b], 0, 0, 0);
-    }
-    if (++link == CH || xs + PXS >= x1) {   // uniform
-      link = 0;
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          acc[a][b] += cha[a][b];
-#pragma unroll
-          for (int r = 0; r < 16; ++r) cha[a][b][r] = 0.f;
+        for (int u = 0; u < 2; ++u) {
+          const int ra = 64 * wi + 32 * u + (lane & 31);
+          const int rb = TT + 64 * wj + 32 * u + (lane & 31);
+          ah[u] = *reinterpret_cast<const bf16x8*>(&L.oh[h][ra][kx]);
+          al[u] = *reinterpret_cast<const bf16x8*>(&L.ol[h][ra][kx]);
+          bh[u] = *reinterpret_cast<const bf16x8*>(&L.oh[h][rb][kx]);
+          bl[u] = *reinterpret_cast<const bf16x8*>(&L.ol[h][rb][kx]);
         }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) cha[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], cha[a][b], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) cha[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], cha[a][b], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) cha[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], cha[a][b], 0, 0, 0);
+      }
+      if (++link == CH || xs + PXS >= x1) {   // uniform
+        link = 0;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            acc[a][b] += cha[a][b];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) cha[a][b][r] = 0.f;
+          }
+      }
     }
   }
+  if (!skyok) return;
   // acc[a][b][r] = D[64 wi + 32 a + 8 (r / 4) + 4 (lane / 32) + r % 4][64 wj + 32 b + lane % 32]
   float* dst = part + (((size_t)s * nchunk + chunk) * ntp + tp) * TT * TT;
 #pragma unroll
@@ -364,8 +382,8 @@ hipError_t launch_quad_syrk(const modal_ctx* c, const void* maps, const void* V,
   hipError_t e = quad_set_lds();
   if (e != hipSuccess) return e;
   const int vec = c->npix % 4 == 0 ? 1 : 0;
-  hipLaunchKernelGGL(k_quad_syrk, dim3(ntp, nchunk, S), dim3(256), sizeof(TriLds), st, c->P, R, c->npix, nchunk,
-                     chunk_px, ntp, tpairs, c->t.pair_a, c->t.pair_b, (const float*)maps, (const float*)V, c->t.w32,
+  hipLaunchKernelGGL(k_quad_syrk, dim3(ntp, nchunk, (S + SKW - 1) / SKW), dim3(NTQ), sizeof(TriLds), st, c->P, R,
+                     c->npix, S, nchunk, chunk_px, ntp, tpairs, c->t.pair_a, c->t.pair_b, (const float*)maps, (const float*)V, c->t.w32,
                      vmode, vec, part);
   const size_t tot = (size_t)R * R;
   hipLaunchKernelGGL(k_quad_reduce, dim3((tot + 255) / 256, S), dim3(256), 0, st, R, nchunk, ntp, ntile, part, K);
