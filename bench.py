@@ -427,6 +427,8 @@ def main():
     if args.compare_steps > 0 and prec != "f32":
         fp32 = run_path(args, "f32", args.compare_steps, 1, make_state=not args.no_linear)
 
+    for k, v in head["kernels"].items():
+        v["traffic"] = measured_traffic(k, prec)
     # the dominant kernel's roofline (by time per step)
     dom = max(head["kernels"].items(), key=lambda kv: kv[1]["avg_ms"])
     roof = dict(dom[1])
