@@ -43,8 +43,17 @@ def make_inputs(lmax, P, S, first, cfg_id=6):
     return alms
 
 
-def cpu_baseline(lmax, ntheta, nphi, P, rings, V_sims=2, cfg_id=6):
-    """FP64 oracle timed on host cores for one sky on a subset of rings (maps, beta, linear term)."""
+def _host_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([d.get("num_threads", 1) for d in threadpool_info()] + [1]))
+    except Exception:
+        return os.cpu_count()
+
+
+def _ring_sample(lmax, ntheta, nphi, P, rings, V_sims, cfg_id):
+    """The oracle's inputs on a subset of rings of the workload grid: the sampled rings as
+    a grid, one sky's a_lm, the Monte-Carlo pair means on those rings."""
     import numpy as np
     import modal_inputs as mi
     from oracle import grid as og
@@ -65,20 +74,73 @@ def cpu_baseline(lmax, ntheta, nphi, P, rings, V_sims=2, cfg_id=6):
     mc = make_inputs(lmax, P, V_sims, 10_000, cfg_id)
     V = om.pair_means(om.filtered_maps(mc, cl, q, sub))
     a = make_inputs(lmax, P, 1, 20_000, cfg_id)[0]
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    except Exception:
-        threads = os.cpu_count()
+    return sub, cl, q, V, a
+
+
+def cpu_baseline(lmax, ntheta, nphi, P, rings, V_sims=2, cfg_id=6, op="beta"):
+    """FP64 oracle timed on host cores for one sky on a subset of rings: maps, then beta
+    and the linear term (op "beta"), the pair sums (op "power") or the quartic sums
+    (op "trispectrum")."""
+    import numpy as np
+    from oracle import modal as om
+    from oracle import power as opw
+    from oracle import trispectrum as otr
+    sub, cl, q, V, a = _ring_sample(lmax, ntheta, nphi, P, rings, V_sims, cfg_id)
+    reduce_, what = {"beta": (om.beta_hat, "beta+linear term"), "power": (opw.power_beta, "pair sums"),
+                     "trispectrum": (otr.tau, "quartic sums")}[op]
     t0 = time.perf_counter()
     M = om.filtered_maps(a, cl, q, sub)
-    bh = om.beta_hat(M, sub.w, V)
+    out = reduce_(M, sub.w, V)
     t = time.perf_counter() - t0
-    assert np.all(np.isfinite(bh))
+    assert np.all(np.isfinite(out))
     frac = rings / ntheta
-    return {"value": frac / t, "unit": "maps/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one sky, {rings} of {ntheta} rings (every ~{ntheta // rings}th), maps+beta+linear term, "
+    return {"value": frac / t, "unit": "maps/s", "cores": _host_threads(), "kind": "oracle",
+            "sample": f"one sky, {rings} of {ntheta} rings (every ~{ntheta // rings}th), maps+{what}, "
                       f"{t:.1f} s, scaled by {ntheta}/{rings}"}
+
+
+def _baseline(args, f):
+    """A workload's oracle baseline, or None when switched off or when it fails (it is
+    reported, never the target)."""
+    if args.no_cpu_baseline:
+        return None
+    try:
+        return f()
+    except Exception as e:
+        log(f"cpu baseline failed: {e!r}")
+        return None
+
+
+def cpu_baseline_lowrank(B, k):
+    """The oracle's noise vectors (sample covariance, its eigendecomposition) for the same
+    N x n_max rows, timed whole on host cores."""
+    from oracle import lowrank as olr
+    t0 = time.perf_counter()
+    olr.noise_vectors(B, k)
+    t = time.perf_counter() - t0
+    return {"value": 1e3 * t, "unit": "ms", "cores": _host_threads(), "kind": "oracle",
+            "sample": f"the whole call: {B.shape[0]} x {B.shape[1]} rows, k = {k}, {t:.1f} s"}
+
+
+def cpu_baseline_shapes(lmax, P, P_sample=16):
+    """The oracle's full-sky ideal covariance (mu integral, one entry at a time) for the
+    first P_sample modes of the basis at the same l_max, scaled by the entry count of n_max(P)."""
+    import numpy as np
+    import modal_inputs as mi
+    from oracle import closed_forms as cf
+    cl = mi.filter_cl(lmax, "wmap")
+    q = mi.q_basis(P_sample, lmax)
+    c = (cl > 0).astype(float)
+    t0 = time.perf_counter()
+    Z = cf.zeta_ideal(q, c)
+    t = time.perf_counter() - t0
+    assert np.all(np.isfinite(Z))
+    n_s = Z.shape[0]
+    n = P * (P + 1) * (P + 2) // 6
+    scale = (n * (n + 1) / 2) / (n_s * (n_s + 1) / 2)
+    return {"value": 1e3 * t * scale, "unit": "ms", "cores": _host_threads(), "kind": "oracle",
+            "sample": f"ideal covariance of the first {P_sample} modes ({n_s} x {n_s}, l_max {lmax}), {t:.1f} s, "
+                      f"scaled by the entry count {n} x {n} / {n_s} x {n_s}"}
 
 
 def kernel_rooflines(ctx, stages, prec, S, op="beta"):
@@ -255,8 +317,8 @@ def run_lowrank(args):
     rng = np.random.default_rng(2011)
     U, _ = np.linalg.qr(rng.standard_normal((n, k)))
     strengths = np.linspace(14.0, 7.0, k)
-    B = math.sqrt(6.0) * (rng.standard_normal((N, n)) + (rng.standard_normal((N, k)) * strengths) @ U.T)
-    B = torch.as_tensor(B, device="cuda")
+    B_host = math.sqrt(6.0) * (rng.standard_normal((N, n)) + (rng.standard_normal((N, k)) * strengths) @ U.T)
+    B = torch.as_tensor(B_host, device="cuda")
     alpha = torch.as_tensor(rng.standard_normal(n), device="cuda")
     betas = torch.as_tensor(rng.standard_normal((S, n)), device="cuda")
     X = torch.cat([alpha[None, :], betas])
@@ -290,6 +352,7 @@ def run_lowrank(args):
         "roofline": {"bound": "alu", "kernel": "noise_vectors (Gram matrix dominant)", "per_launch": gram_flop,
                      "per_launch_unit": "flop", "achieved": gram_flop / t / 1e12, "peak": PEAK["f64_vec"] / 1e12,
                      "unit": "TFLOP/s", "frac": gram_flop / t / PEAK["f64_vec"], "traffic": None},
+        "cpu_baseline": _baseline(args, lambda: cpu_baseline_lowrank(B_host, k)),
     }
     print(json.dumps(line), flush=True)
 
@@ -308,6 +371,8 @@ def run_power(args):
                                f"beam+noise spectrum, |lat|<10deg cut, MC pair means ({args.mc} skies)",
                    "batch": args.batch, "prec": args.prec},
         "stages_ms": res["stages_ms"], "roofline": pair, "kernels": res["kernels"],
+        "cpu_baseline": _baseline(args, lambda: cpu_baseline(args.lmax, args.ntheta, args.nphi, args.P,
+                                                             args.cpu_rings, op="power")),
     }
     print(json.dumps(line), flush=True)
 
@@ -326,6 +391,9 @@ def run_trispectrum(args):
                                f"modes={res['ncol']}, beam+noise spectrum, |lat|<10deg cut, MC pair means "
                                f"({args.mc} skies)", "batch": args.batch, "prec": args.prec},
         "stages_ms": res["stages_ms"], "roofline": k, "kernels": res["kernels"],
+        # few rings: the oracle's quartic sums loop over the 123,410 modes
+        "cpu_baseline": _baseline(args, lambda: cpu_baseline(args.lmax, args.ntheta, args.nphi, args.P,
+                                                             max(1, args.cpu_rings // 8), op="trispectrum")),
     }
     print(json.dumps(line), flush=True)
 
@@ -367,6 +435,8 @@ def run_shapes(args):
         "roofline": {"bound": "alu", "kernel": "ideal_covariance (k_ideal_cov dominant)", "per_launch": flop,
                      "per_launch_unit": "flop", "achieved": flop / t / 1e12, "peak": PEAK["f64_vec"] / 1e12,
                      "unit": "TFLOP/s", "frac": flop / t / PEAK["f64_vec"], "traffic": None},
+        # the ideal covariance only: the oracle's alpha is a triple sum over an l_max^3 table
+        "cpu_baseline": _baseline(args, lambda: cpu_baseline_shapes(lmax, P)),
     }
     print(json.dumps(line), flush=True)
 
@@ -383,7 +453,7 @@ def main():
     ap.add_argument("--nphi", type=int, default=3072)
     ap.add_argument("--P", type=int, default=40)
     ap.add_argument("--mc", type=int, default=16, help="Monte-Carlo skies for the linear term")
-    ap.add_argument("--cpu-rings", type=int, default=8)
+    ap.add_argument("--cpu-rings", type=int, default=24)
     ap.add_argument("--compare-steps", type=int, default=3, help="timed steps of the plain-FP32 comparison (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
