@@ -349,7 +349,8 @@ def run_lowrank(args):
         "config": {"workload": f"n_max={n} (P={P}), N={N} beta^hat vectors, k={k} noise vectors, "
                                f"{iters} block iterations, S={S} skies", "N": N, "k": k, "S": S, "iters": iters},
         "ms": times, "mu": [float(m) for m in mu],
-        "roofline": {"bound": "alu", "kernel": "noise_vectors (Gram matrix dominant)", "per_launch": gram_flop,
+        # the Gram matrix's flops over the whole call (its one-workgroup steps are latency)
+        "roofline": {"bound": "alu", "kernel": "noise_vectors (whole call, Gram flops)", "per_launch": gram_flop,
                      "per_launch_unit": "flop", "achieved": gram_flop / t / 1e12, "peak": PEAK["f64_vec"] / 1e12,
                      "unit": "TFLOP/s", "frac": gram_flop / t / PEAK["f64_vec"], "traffic": None},
         "cpu_baseline": _baseline(args, lambda: cpu_baseline_lowrank(B_host, k)),

@@ -36,23 +36,45 @@ constexpr int GXR = 64;    // rows i of G X per workgroup
 constexpr int GXL = 256;   // rows l of G summed per workgroup
 constexpr int RC = 256;    // rows staged per chunk in the one-workgroup kernels
 
-// G[i][j] = scale * B_i . B_j over the rows of B [N][n]; lower tiles computed and mirrored.
-__global__ __launch_bounds__(256) void k_gram_rows(int N, int n, const double* __restrict__ B, double scale,
-                                                   double* __restrict__ G) {
-  const int bi = blockIdx.y, bj = blockIdx.x;
-  if (bj > bi) return;
+constexpr int GKS = 16;    // most column splits of the Gram matrix
+
+// Partial Gram tiles: Gp[ks][tp][64][64] = B_i . B_j over the columns of split ks, for the
+// lower tile pair tp = bi (bi + 1) / 2 + bj (bj <= bi).  Splitting the columns gives the
+// N = 1000 case (136 tile pairs) about a thousand workgroups; the next chunk's loads are
+// issued into registers before this chunk's products.
+__global__ __launch_bounds__(256) void k_gram_part(int N, int n, int kc, int ntp, const double* __restrict__ B,
+                                                   double* __restrict__ Gp) {
+  const int tp = blockIdx.x, ks = blockIdx.y;
+  int bi = 0;
+  while ((bi + 1) * (bi + 2) / 2 <= tp) ++bi;
+  const int bj = tp - bi * (bi + 1) / 2;
   const int i0 = bi * GT, j0 = bj * GT;
+  const int c_begin = ks * kc, c_end = min(n, c_begin + kc);
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   __shared__ double Bi[GK][GT + 1];
   __shared__ double Bj[GK][GT + 1];
+  constexpr int NL = GK * GT / 256;   // elements of each tile chunk per thread (4)
+  double pa[NL], pb[NL];
+  auto load = [&](int c0) {
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int e = threadIdx.x + 256 * u, r = e / GK, c = c0 + (e - r * GK);
+      pa[u] = (i0 + r < N && c < c_end) ? B[(size_t)(i0 + r) * n + c] : 0.0;
+      pb[u] = (j0 + r < N && c < c_end) ? B[(size_t)(j0 + r) * n + c] : 0.0;
+    }
+  };
   double acc[4][4] = {};
-  for (int c0 = 0; c0 < n; c0 += GK) {
-    for (int e = threadIdx.x; e < GK * GT; e += 256) {
-      const int r = e / GK, kk = e - r * GK, c = c0 + kk;
-      Bi[kk][r] = (i0 + r < N && c < n) ? B[(size_t)(i0 + r) * n + c] : 0.0;
-      Bj[kk][r] = (j0 + r < N && c < n) ? B[(size_t)(j0 + r) * n + c] : 0.0;
+  if (c_begin < c_end) load(c_begin);
+  for (int c0 = c_begin; c0 < c_end; c0 += GK) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int e = threadIdx.x + 256 * u, r = e / GK, kk = e - r * GK;
+      Bi[kk][r] = pa[u];
+      Bj[kk][r] = pb[u];
     }
     __syncthreads();
+    if (c0 + GK < c_end) load(c0 + GK);
 #pragma unroll
     for (int kk = 0; kk < GK; ++kk) {
       double a[4], b[4];
@@ -66,19 +88,37 @@ __global__ __launch_bounds__(256) void k_gram_rows(int N, int n, const double* _
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
     }
-    __syncthreads();
   }
+  double* dst = Gp + ((size_t)ks * ntp + tp) * GT * GT;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = i0 + ty * 4 + u, j = j0 + tx * 4 + v;
-      if (i < N && j <= i) {   // one writer per symmetric pair
-        G[(size_t)i * N + j] = scale * acc[u][v];
-        G[(size_t)j * N + i] = scale * acc[u][v];
-      }
-    }
+    for (int v = 0; v < 4; ++v) dst[(ty * 4 + u) * GT + tx * 4 + v] = acc[u][v];
 }
+
+// G[i][j] = G[j][i] = scale * (sum over the splits of the partial tiles), j <= i, in a
+// fixed order (deterministic).
+__global__ __launch_bounds__(256) void k_gram_reduce(int N, int ntp, int nks, const double* __restrict__ Gp,
+                                                     double scale, double* __restrict__ G) {
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (size_t)N * N) return;
+  const int i = (int)(e / N), j = (int)(e - (size_t)i * N);
+  if (j > i) return;
+  const int bi = i / GT, bj = j / GT, tp = bi * (bi + 1) / 2 + bj;
+  const size_t o = (size_t)tp * GT * GT + (size_t)(i - bi * GT) * GT + (j - bj * GT);
+  double sum = 0.0;
+  for (int k = 0; k < nks; ++k) sum += Gp[(size_t)k * ntp * GT * GT + o];
+  G[(size_t)i * N + j] = scale * sum;
+  G[(size_t)j * N + i] = scale * sum;
+}
+
+// column splits of the Gram matrix: about a thousand workgroups, at most GKS, at least one
+// GK-column chunk each
+int gram_splits_max(int N) {
+  const int nt = (N + GT - 1) / GT, ntp = nt * (nt + 1) / 2;
+  return std::max(1, std::min(GKS, (1024 + ntp - 1) / ntp));
+}
+int gram_splits(int N, int n) { return std::max(1, std::min(gram_splits_max(N), (n + GK - 1) / GK)); }
 
 // Starting block: a fixed hash of (i, j) mapped to [-1, 1), columns >= kb zero.
 __global__ void k_start_block(int N, int kb, double* __restrict__ X) {
@@ -624,8 +664,9 @@ __global__ __launch_bounds__(256) void k_bivector_rotate(int n, const double* __
 
 size_t noise_ws_bytes(int N) {
   const size_t nsplit = (size_t)(N + GXL - 1) / GXL;
+  const size_t nt = (N + GT - 1) / GT, ntp = nt * (nt + 1) / 2;
   return align256((size_t)N * N * 8) + align256((size_t)N * KB * 8) * 2 + align256(nsplit * N * KB * 8) +
-         align256(KB * 8);
+         align256((size_t)gram_splits_max(N) * ntp * GT * GT * 8) + align256(KB * 8);
 }
 
 int noise_block_max() { return KB; }
@@ -642,8 +683,14 @@ hipError_t launch_noise_vectors(int N, int n, int k, int iters, const double* B,
   double* Y = (double*)p;
   p += align256((size_t)N * KB * 8);
   double* Yp = (double*)p;
-  const int nt = (N + GT - 1) / GT;
-  hipLaunchKernelGGL(k_gram_rows, dim3(nt, nt), dim3(256), 0, st, N, n, B, 1.0 / (6.0 * N), G);
+  p += align256((size_t)nsplit * N * KB * 8);
+  double* Gp = (double*)p;   // partial Gram tiles, before the final slot (the eigenvalues)
+  const int nt = (N + GT - 1) / GT, ntp = nt * (nt + 1) / 2;
+  const int nks = gram_splits(N, n);
+  const int kc = ((n + nks - 1) / nks + GK - 1) / GK * GK;
+  hipLaunchKernelGGL(k_gram_part, dim3(ntp, nks), dim3(256), 0, st, N, n, kc, ntp, B, Gp);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)(((size_t)N * N + 255) / 256)), dim3(256), 0, st, N, ntp, nks, Gp,
+                     1.0 / (6.0 * N), G);
   hipLaunchKernelGGL(k_start_block, dim3((N * KB + 255) / 256), dim3(256), 0, st, N, kb, Yp);
   // the block stays in LDS through the orthonormalisation when it fits
   const bool res = N <= ORN;
