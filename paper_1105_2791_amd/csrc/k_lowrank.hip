@@ -307,7 +307,7 @@ __global__ __launch_bounds__(256) void k_orth_res(int N, int kb, int nsplit, con
   __shared__ double C[KB][KB];
   __shared__ double R[KB][KB];
   __shared__ double part[256];
-  __shared__ int drop[KB];
+  __shared__ double rinv[KB];   // 1 / R[j][j], 0 for a dropped column
   const int tid = threadIdx.x;
   const int tot = N * KB;
   sum_partials_with<16>(N, kb, nsplit, Yp, [&](int e, double v) { xs[e / KB][e % KB] = v; });
@@ -344,7 +344,7 @@ __global__ __launch_bounds__(256) void k_orth_res(int N, int kb, int nsplit, con
       const double rjj = dj ? 1.0 : sqrt(d);
       if (tid == j) {
         R[j][j] = rjj;
-        drop[j] = dj ? 1 : 0;
+        rinv[j] = dj ? 0.0 : 1.0 / rjj;
       } else if (tid > j && tid < kb) {
         R[j][tid] = dj ? 0.0 : C[j][tid] / rjj;
       }
@@ -355,17 +355,24 @@ __global__ __launch_bounds__(256) void k_orth_res(int N, int kb, int nsplit, con
       }
       __syncthreads();
     }
-    for (int i = tid; i < N; i += 256) {
-      double y[KB];
+    {
+      // y R = x for the thread's rows tid + 256 r (N <= 1024: all of them), the four
+      // substitutions interleaved
+      constexpr int NR = ORN / 256;
+      double y[NR][KB];
 #pragma unroll
       for (int j = 0; j < KB; ++j) {
-        y[j] = 0.0;
         if (j < kb) {   // uniform
-          double sm = xs[i][j];
+          const double rj = rinv[j];
 #pragma unroll
-          for (int p = 0; p < j; ++p) sm -= y[p] * R[p][j];
-          y[j] = drop[j] ? 0.0 : sm / R[j][j];
-          xs[i][j] = y[j];
+          for (int r = 0; r < NR; ++r) {
+            const int i = tid + 256 * r;
+            double sm = i < N ? xs[i][j] : 0.0;
+#pragma unroll
+            for (int p = 0; p < j; ++p) sm -= y[r][p] * R[p][j];
+            y[r][j] = sm * rj;
+            if (i < N) xs[i][j] = y[r][j];
+          }
         }
       }
     }
