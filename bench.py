@@ -394,7 +394,7 @@ def run_trispectrum(args):
         "stages_ms": res["stages_ms"], "roofline": k, "kernels": res["kernels"],
         # few rings: the oracle's quartic sums loop over the 123,410 modes
         "cpu_baseline": _baseline(args, lambda: cpu_baseline(args.lmax, args.ntheta, args.nphi, args.P,
-                                                             max(1, args.cpu_rings // 8), op="trispectrum")),
+                                                             max(1, args.cpu_rings // 32), op="trispectrum")),
     }
     print(json.dumps(line), flush=True)
 
@@ -454,7 +454,7 @@ def main():
     ap.add_argument("--nphi", type=int, default=3072)
     ap.add_argument("--P", type=int, default=40)
     ap.add_argument("--mc", type=int, default=16, help="Monte-Carlo skies for the linear term")
-    ap.add_argument("--cpu-rings", type=int, default=24)
+    ap.add_argument("--cpu-rings", type=int, default=64)
     ap.add_argument("--compare-steps", type=int, default=3, help="timed steps of the plain-FP32 comparison (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
