@@ -366,7 +366,9 @@ modal_status modal_power_fnl(modal_ctx* ctx, const double* zeta_dev, const doubl
  * K = sum_x w A A^T - 6 sum_x w V V^T, A_ab = M_a M_b - 3 V_ab, tau = the mean of K over the
  * three pairings; split-bf16 matrix cores for float contexts (all three float precisions),
  * FP64 for MODAL_F64 (a reference path without pixel chunking).
- *   tau_dev [S][nquad] float64.  Workspace: modal_workspace_size(MODAL_OP_TRISPECTRUM, S).
+ *   tau_dev [S][nquad] float64.  Workspace: modal_workspace_size(MODAL_OP_TRISPECTRUM, S);
+ * for float contexts it includes a pixel-block-major copy of the pair means (npairs x
+ * npix floats, rounded up to 32-pixel blocks), made at each call with a state.
  * Errors: EINVAL, ENOTREADY, ENOSPACE, EDEVICE. */
 modal_status modal_trispectrum(modal_ctx* ctx, const void* alm_dev, int S, const void* state_dev, double* tau_dev,
                                void* ws_dev, size_t ws_bytes, modal_stream_t stream);

@@ -222,6 +222,8 @@ hipError_t launch_ideal_cov(int nmax, int P, int nmu, int nrows, const int4* zro
 int quad_chunks(int npix);
 int quad_ntile(int R);
 size_t quad_part_bytes(const modal_ctx* c, int S);
+size_t quad_vtile_bytes(const modal_ctx* c);
+hipError_t launch_quad_vtile(const modal_ctx* c, const void* V, float* Vt, hipStream_t st);
 hipError_t launch_quad_syrk(const modal_ctx* c, const void* maps, const void* V, int S, int vmode, const int2* tpairs,
                             float* part, double* K, hipStream_t st);
 hipError_t launch_quad_gather(const modal_ctx* c, int nquad, int S, const int* quad, const double* K, const double* KVV,

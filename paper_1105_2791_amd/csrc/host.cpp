@@ -181,6 +181,7 @@ size_t ws_size(const modal_ctx* c, int op, int S) {
     case MODAL_OP_TRISPECTRUM:
       cv.take(F_bytes(c, S)); cv.take(maps_bytes(c, S)); cv.take(quad_part_bytes(c, S > 0 ? S : 1));
       cv.take((size_t)S * c->npairs * c->npairs * 8); cv.take((size_t)c->npairs * c->npairs * 8);
+      cv.take(quad_vtile_bytes(c));
       break;
     case MODAL_OP_POWER_COVARIANCE:
       cv.take((size_t)c->P * (c->lmax + 1) * 8); cv.take((size_t)(c->lmax + 1) * 8);
@@ -828,11 +829,18 @@ modal_status modal_trispectrum(modal_ctx* c, const void* alm, int S, const void*
   float* part = (float*)cv.take(quad_part_bytes(c, S));
   double* K = (double*)cv.take((size_t)S * R2 * 8);
   double* KVV = (double*)cv.take(R2 * 8);
+  float* Vt = (float*)cv.take(quad_vtile_bytes(c));
   if ((s = run_maps(c, alm, S, F, maps, st)) != MODAL_OK) return s;
   {
     StageTimer _t(c, MODAL_STAGE_CUBIC, st);
-    HIPTRY(launch_quad_syrk(c, maps, state, S, 0, c->t.qtiles, part, K, st));   // V planes lead the state
-    if (state) HIPTRY(launch_quad_syrk(c, nullptr, state, 1, 1, c->t.qtiles, part, KVV, st));
+    // the V planes lead the state; float contexts read them through a pixel-block-major copy
+    const void* V = state;
+    if (state && c->prec != MODAL_F64) {
+      HIPTRY(launch_quad_vtile(c, state, Vt, st));
+      V = Vt;
+    }
+    HIPTRY(launch_quad_syrk(c, maps, V, S, 0, c->t.qtiles, part, K, st));
+    if (state) HIPTRY(launch_quad_syrk(c, nullptr, V, 1, 1, c->t.qtiles, part, KVV, st));
   }
   {
     StageTimer _t(c, MODAL_STAGE_REDUCE, st);

@@ -66,7 +66,8 @@ __device__ inline void split2(float v0, float v1, uint32_t& hi, uint32_t& lo) {
 // weight loads are float4 and coalesced along each row, its map reads and operand writes
 // are 16- and 8-byte LDS accesses.  The pair means of a step are the same for both skies:
 // half h loads the rows j = 4 h .. 4 h + 3 and both halves read all eight, so each pair
-// mean is read from HBM once per two skies.
+// mean is read from HBM once per two skies.  V is the pixel-block-major copy made by
+// k_quad_vtile, so the 256 rows of a step are two contiguous 16 KB runs.
 __global__ __launch_bounds__(NTQ) __attribute__((amdgpu_waves_per_eu(2))) void k_quad_syrk(int P, int R, int npix, int S, int nchunk, int chunk_px, int ntp,
                                                    const int2* __restrict__ tpairs, const int* __restrict__ pair_a,
                                                    const int* __restrict__ pair_b, const float* __restrict__ maps,
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(NTQ) __attribute__((amdgpu_waves_per_eu(2))) void k
       const int j = RPH * h + jj;
       pv[jj] = make_float4(0.f, 0.f, 0.f, 0.f);
       if (hasV && x < x1 && ((rokm >> j) & 1u))
-        pv[jj] = *reinterpret_cast<const float4*>(V + (size_t)(vbase + 32 * j) * npix + x);
+        pv[jj] = *reinterpret_cast<const float4*>(V + ((size_t)(x >> 5) * R + vbase + 32 * j) * PXS + (x & 31));
     }
     pw = make_float4(0.f, 0.f, 0.f, 0.f);
     if (h == 0 && x < x1) pw = *reinterpret_cast<const float4*>(w + x);
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(NTQ) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int x = xs + 4 * g + k;
-        q[k] = (hasV && x < x1 && ((rokm >> j) & 1u)) ? V[(size_t)(vbase + 32 * j) * npix + x] : 0.f;
+        q[k] = (hasV && x < x1 && ((rokm >> j) & 1u)) ? V[((size_t)(x >> 5) * R + vbase + 32 * j) * PXS + (x & 31)] : 0.f;
       }
       L.vs[j][t] = make_float4(q[0], q[1], q[2], q[3]);
     }
@@ -267,6 +268,33 @@ __global__ __launch_bounds__(NTQ) __attribute__((amdgpu_waves_per_eu(2))) void k
       }
 }
 
+// Pixel-block-major copy of the pair means: Vt[b][pair][i] = V[pair][32 b + i] (zero past
+// npix).  The update reads, per 32-pixel step, 256 rows of one block: contiguous here,
+// 256 separate 128-byte pieces of the pair-major planes otherwise.  A workgroup copies
+// 32 rows x 8 blocks; each row is read as 1 KB runs, each block written as 4 KB runs.
+__global__ __launch_bounds__(256) void k_quad_vtile(int R, int npix, int nblk, int vec, const float* __restrict__ V,
+                                                    float* __restrict__ Vt) {
+  const int row = blockIdx.y * 32 + (threadIdx.x >> 3), g = threadIdx.x & 7;
+  if (row >= R) return;
+  const float* src = V + (size_t)row * npix;
+#pragma unroll
+  for (int b8 = 0; b8 < 8; ++b8) {
+    const int blk = blockIdx.x * 8 + b8;
+    if (blk >= nblk) break;
+    const int x = blk * PXS + 4 * g;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (vec && x < npix) {
+      v = *reinterpret_cast<const float4*>(src + x);   // npix % 4 == 0: the group is inside
+    } else if (!vec) {
+      v.x = x < npix ? src[x] : 0.f;
+      v.y = x + 1 < npix ? src[x + 1] : 0.f;
+      v.z = x + 2 < npix ? src[x + 2] : 0.f;
+      v.w = x + 3 < npix ? src[x + 3] : 0.f;
+    }
+    *reinterpret_cast<float4*>(Vt + ((size_t)blk * R + row) * PXS + 4 * g) = v;
+  }
+}
+
 // K[s][i][j] (i, j < R, FP64, both triangles) = sum over chunks of the tile partials.
 __global__ __launch_bounds__(256) void k_quad_reduce(int R, int nchunk, int ntp, int ntile, const float* __restrict__ part,
                                                      double* __restrict__ K) {
@@ -366,7 +394,9 @@ hipError_t quad_set_lds() {
   return hipFuncSetAttribute((const void*)k_quad_syrk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(TriLds));
 }
 
-// K [S][R][R] FP64 for the S skies' maps (vmode 0) or for V itself (vmode 1, S = 1).
+// K [S][R][R] FP64 for the S skies' maps (vmode 0) or for V itself (vmode 1, S = 1).  For
+// the float contexts V is the pixel-block-major copy (launch_quad_vtile), for FP64 the
+// pair-major planes of the state.
 hipError_t launch_quad_syrk(const modal_ctx* c, const void* maps, const void* V, int S, int vmode, const int2* tpairs,
                             float* part, double* K, hipStream_t st) {
   const int R = c->npairs;
@@ -394,6 +424,18 @@ hipError_t launch_quad_gather(const modal_ctx* c, int nquad, int S, const int* q
                               double* tau, hipStream_t st) {
   hipLaunchKernelGGL(k_quad_gather, dim3((S * nquad + 255) / 256), dim3(256), 0, st, c->npairs, nquad, S, quad, K, KVV,
                      tau);
+  return hipGetLastError();
+}
+
+size_t quad_vtile_bytes(const modal_ctx* c) {
+  if (c->prec == MODAL_F64) return 0;
+  return (size_t)((c->npix + PXS - 1) / PXS) * c->npairs * PXS * 4;
+}
+
+hipError_t launch_quad_vtile(const modal_ctx* c, const void* V, float* Vt, hipStream_t st) {
+  const int nblk = (c->npix + PXS - 1) / PXS;
+  hipLaunchKernelGGL(k_quad_vtile, dim3((nblk + 7) / 8, (c->npairs + 31) / 32), dim3(256), 0, st, c->npairs, c->npix,
+                     nblk, c->npix % 4 == 0 ? 1 : 0, (const float*)V, Vt);
   return hipGetLastError();
 }
 
