@@ -367,8 +367,9 @@ modal_status modal_power_fnl(modal_ctx* ctx, const double* zeta_dev, const doubl
  * three pairings; split-bf16 matrix cores for float contexts (all three float precisions),
  * FP64 for MODAL_F64 (a reference path without pixel chunking).
  *   tau_dev [S][nquad] float64.  Workspace: modal_workspace_size(MODAL_OP_TRISPECTRUM, S);
- * for float contexts it includes a pixel-block-major copy of the pair means (npairs x
- * npix floats, rounded up to 32-pixel blocks), made at each call with a state.
+ * for float contexts it includes pixel-block-major copies of the pair means (npairs x
+ * npix floats, rounded up to 32-pixel blocks; with a state) and of the S skies' maps,
+ * made at each call.
  * Errors: EINVAL, ENOTREADY, ENOSPACE, EDEVICE. */
 modal_status modal_trispectrum(modal_ctx* ctx, const void* alm_dev, int S, const void* state_dev, double* tau_dev,
                                void* ws_dev, size_t ws_bytes, modal_stream_t stream);

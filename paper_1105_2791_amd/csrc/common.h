@@ -223,7 +223,8 @@ int quad_chunks(int npix);
 int quad_ntile(int R);
 size_t quad_part_bytes(const modal_ctx* c, int S);
 size_t quad_vtile_bytes(const modal_ctx* c);
-hipError_t launch_quad_vtile(const modal_ctx* c, const void* V, float* Vt, hipStream_t st);
+hipError_t launch_quad_vtile(const modal_ctx* c, const void* V, int rows, int batch, float* Vt, hipStream_t st);
+size_t quad_mtile_bytes(const modal_ctx* c, int S);
 hipError_t launch_quad_syrk(const modal_ctx* c, const void* maps, const void* V, int S, int vmode, const int2* tpairs,
                             float* part, double* K, hipStream_t st);
 hipError_t launch_quad_gather(const modal_ctx* c, int nquad, int S, const int* quad, const double* K, const double* KVV,

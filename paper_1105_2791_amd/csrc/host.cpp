@@ -181,7 +181,7 @@ size_t ws_size(const modal_ctx* c, int op, int S) {
     case MODAL_OP_TRISPECTRUM:
       cv.take(F_bytes(c, S)); cv.take(maps_bytes(c, S)); cv.take(quad_part_bytes(c, S > 0 ? S : 1));
       cv.take((size_t)S * c->npairs * c->npairs * 8); cv.take((size_t)c->npairs * c->npairs * 8);
-      cv.take(quad_vtile_bytes(c));
+      cv.take(quad_vtile_bytes(c)); cv.take(quad_mtile_bytes(c, S));
       break;
     case MODAL_OP_POWER_COVARIANCE:
       cv.take((size_t)c->P * (c->lmax + 1) * 8); cv.take((size_t)(c->lmax + 1) * 8);
@@ -830,16 +830,23 @@ modal_status modal_trispectrum(modal_ctx* c, const void* alm, int S, const void*
   double* K = (double*)cv.take((size_t)S * R2 * 8);
   double* KVV = (double*)cv.take(R2 * 8);
   float* Vt = (float*)cv.take(quad_vtile_bytes(c));
+  float* Mt = (float*)cv.take(quad_mtile_bytes(c, S));
   if ((s = run_maps(c, alm, S, F, maps, st)) != MODAL_OK) return s;
   {
     StageTimer _t(c, MODAL_STAGE_CUBIC, st);
-    // the V planes lead the state; float contexts read them through a pixel-block-major copy
+    // the V planes lead the state; float contexts read them and the maps through
+    // pixel-block-major copies
     const void* V = state;
-    if (state && c->prec != MODAL_F64) {
-      HIPTRY(launch_quad_vtile(c, state, Vt, st));
-      V = Vt;
+    const void* M = maps;
+    if (c->prec != MODAL_F64) {
+      if (state) {
+        HIPTRY(launch_quad_vtile(c, state, c->npairs, 1, Vt, st));
+        V = Vt;
+      }
+      HIPTRY(launch_quad_vtile(c, maps, c->P, S, Mt, st));
+      M = Mt;
     }
-    HIPTRY(launch_quad_syrk(c, maps, V, S, 0, c->t.qtiles, part, K, st));
+    HIPTRY(launch_quad_syrk(c, M, V, S, 0, c->t.qtiles, part, K, st));
     if (state) HIPTRY(launch_quad_syrk(c, nullptr, V, 1, 1, c->t.qtiles, part, KVV, st));
   }
   {

@@ -66,8 +66,8 @@ __device__ inline void split2(float v0, float v1, uint32_t& hi, uint32_t& lo) {
 // weight loads are float4 and coalesced along each row, its map reads and operand writes
 // are 16- and 8-byte LDS accesses.  The pair means of a step are the same for both skies:
 // half h loads the rows j = 4 h .. 4 h + 3 and both halves read all eight, so each pair
-// mean is read from HBM once per two skies.  V is the pixel-block-major copy made by
-// k_quad_vtile, so the 256 rows of a step are two contiguous 16 KB runs.
+// mean is read from HBM once per two skies.  V and the maps are pixel-block-major copies
+// made by k_quad_vtile, so the rows of a step are contiguous runs.
 __global__ __launch_bounds__(NTQ) __attribute__((amdgpu_waves_per_eu(2))) void k_quad_syrk(int P, int R, int npix, int S, int nchunk, int chunk_px, int ntp,
                                                    const int2* __restrict__ tpairs, const int* __restrict__ pair_a,
                                                    const int* __restrict__ pair_b, const float* __restrict__ maps,
@@ -98,7 +98,8 @@ __global__ __launch_bounds__(NTQ) __attribute__((amdgpu_waves_per_eu(2))) void k
     rokm |= ok ? (1u << j) : 0u;
   }
   const bool hasV = V != nullptr;   // no state: V = 0 (never read); vmode always has V
-  const float* Msky = maps + (size_t)min(s, S - 1) * P * npix;
+  const int nblk = (npix + PXS - 1) / PXS;
+  const float* Msky = maps + (size_t)min(s, S - 1) * nblk * P * PXS;   // block-major copy of the maps
   const int x0 = chunk * chunk_px, x1 = min(npix, x0 + chunk_px);
 
   f32x16 acc[2][2], cha[2][2];
@@ -122,7 +123,8 @@ __global__ __launch_bounds__(NTQ) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int k = 0; k < NML; ++k) {
       const int e = t + 256 * k, r = e / GPR, gg = e - r * GPR, x = xs + 4 * gg;
       pm[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (!vmode && skyok && r < P && x < x1) pm[k] = *reinterpret_cast<const float4*>(Msky + (size_t)r * npix + x);
+      if (!vmode && skyok && r < P && x < x1)
+        pm[k] = *reinterpret_cast<const float4*>(Msky + ((size_t)(x >> 5) * P + r) * PXS + (x & 31));
     }
     const int x = xs + 4 * g;
 #pragma unroll
@@ -150,7 +152,7 @@ __global__ __launch_bounds__(NTQ) __attribute__((amdgpu_waves_per_eu(2))) void k
     if (!vmode)
       for (int e = t; e < P * PXS; e += 256) {
         const int r = e / PXS, i = e - r * PXS, x = xs + i;
-        L.ms[h][r][i] = (skyok && x < x1) ? Msky[(size_t)r * npix + x] : 0.f;
+        L.ms[h][r][i] = (skyok && x < x1) ? Msky[((size_t)(x >> 5) * P + r) * PXS + (x & 31)] : 0.f;
       }
     float q[4], sq[4];
 #pragma unroll
@@ -276,6 +278,8 @@ __global__ __launch_bounds__(256) void k_quad_vtile(int R, int npix, int nblk, i
                                                     float* __restrict__ Vt) {
   const int row = blockIdx.y * 32 + (threadIdx.x >> 3), g = threadIdx.x & 7;
   if (row >= R) return;
+  V += (size_t)blockIdx.z * R * npix;   // batch z: R rows of npix -> nblk blocks of R x 32
+  Vt += (size_t)blockIdx.z * nblk * R * PXS;
   const float* src = V + (size_t)row * npix;
 #pragma unroll
   for (int b8 = 0; b8 < 8; ++b8) {
@@ -395,8 +399,8 @@ hipError_t quad_set_lds() {
 }
 
 // K [S][R][R] FP64 for the S skies' maps (vmode 0) or for V itself (vmode 1, S = 1).  For
-// the float contexts V is the pixel-block-major copy (launch_quad_vtile), for FP64 the
-// pair-major planes of the state.
+// the float contexts the maps and V are pixel-block-major copies (launch_quad_vtile), for
+// FP64 the maps and the pair-major planes of the state.
 hipError_t launch_quad_syrk(const modal_ctx* c, const void* maps, const void* V, int S, int vmode, const int2* tpairs,
                             float* part, double* K, hipStream_t st) {
   const int R = c->npairs;
@@ -432,11 +436,16 @@ size_t quad_vtile_bytes(const modal_ctx* c) {
   return (size_t)((c->npix + PXS - 1) / PXS) * c->npairs * PXS * 4;
 }
 
-hipError_t launch_quad_vtile(const modal_ctx* c, const void* V, float* Vt, hipStream_t st) {
+hipError_t launch_quad_vtile(const modal_ctx* c, const void* V, int rows, int batch, float* Vt, hipStream_t st) {
   const int nblk = (c->npix + PXS - 1) / PXS;
-  hipLaunchKernelGGL(k_quad_vtile, dim3((nblk + 7) / 8, (c->npairs + 31) / 32), dim3(256), 0, st, c->npairs, c->npix,
+  hipLaunchKernelGGL(k_quad_vtile, dim3((nblk + 7) / 8, (rows + 31) / 32, batch), dim3(256), 0, st, rows, c->npix,
                      nblk, c->npix % 4 == 0 ? 1 : 0, (const float*)V, Vt);
   return hipGetLastError();
+}
+
+size_t quad_mtile_bytes(const modal_ctx* c, int S) {
+  if (c->prec == MODAL_F64) return 0;
+  return (size_t)S * ((c->npix + PXS - 1) / PXS) * c->P * PXS * 4;
 }
 
 size_t quad_part_bytes(const modal_ctx* c, int S) {
