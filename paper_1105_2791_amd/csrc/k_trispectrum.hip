@@ -116,7 +116,6 @@ __global__ __launch_bounds__(NTQ) __attribute__((amdgpu_waves_per_eu(2))) void k
   // hidden behind that work.
   constexpr int NML = (kMaxP * GPR + 255) / 256;        // map groups per thread (2)
   constexpr int RPH = RPT / SKW;                        // pair-mean rows loaded per thread (4)
-  const int vbase = h == 0 ? rb0 : rb1;                 // rows of this half's j range
   float4 pv[RPH], pm[NML], pw;
   auto load_step = [&](int xs) {
 #pragma unroll
@@ -132,7 +131,7 @@ __global__ __launch_bounds__(NTQ) __attribute__((amdgpu_waves_per_eu(2))) void k
       const int j = RPH * h + jj;
       pv[jj] = make_float4(0.f, 0.f, 0.f, 0.f);
       if (hasV && x < x1 && ((rokm >> j) & 1u))
-        pv[jj] = *reinterpret_cast<const float4*>(V + ((size_t)(x >> 5) * R + vbase + 32 * j) * PXS + (x & 31));
+        pv[jj] = *reinterpret_cast<const float4*>(V + ((size_t)(x >> 5) * R + rowp(j)) * PXS + (x & 31));
     }
     pw = make_float4(0.f, 0.f, 0.f, 0.f);
     if (h == 0 && x < x1) pw = *reinterpret_cast<const float4*>(w + x);
@@ -161,7 +160,7 @@ __global__ __launch_bounds__(NTQ) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int x = xs + 4 * g + k;
-        q[k] = (hasV && x < x1 && ((rokm >> j) & 1u)) ? V[((size_t)(x >> 5) * R + vbase + 32 * j) * PXS + (x & 31)] : 0.f;
+        q[k] = (hasV && x < x1 && ((rokm >> j) & 1u)) ? V[((size_t)(x >> 5) * R + rowp(j)) * PXS + (x & 31)] : 0.f;
       }
       L.vs[j][t] = make_float4(q[0], q[1], q[2], q[3]);
     }
