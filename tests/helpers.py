@@ -64,4 +64,7 @@ CASES = {
     # odd ring count (equator ring), generic FFT radices (K = 200 = 4*2*5*5),
     # two pair blocks (91 pairs), two pixel chunks with a ragged tail, mask + beam/noise spectrum
     "ragged": Case("ragged", 150, 199, 400, 13, 3, "wmap", 21),
+    # npix = 1250, not a multiple of 4: the element-wise staging paths of the float kernels
+    # (half-length FFT of 25 = 5 x 5), mask + beam/noise spectrum
+    "odd": Case("odd", 16, 25, 50, 5, 3, "wmap", 31),
 }

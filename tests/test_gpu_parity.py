@@ -73,7 +73,8 @@ def oracle_for(case):
 
 
 CASE_PREC = [("tiny", "f64"), ("tiny", "f32"), ("tiny", "bf16x3"), ("tiny", "f16x3"), ("ragged", "f64"),
-             ("ragged", "f32"), ("ragged", "bf16x3"), ("ragged", "f16x3")]
+             ("ragged", "f32"), ("ragged", "bf16x3"), ("ragged", "f16x3"), ("odd", "f64"), ("odd", "f32"),
+             ("odd", "bf16x3"), ("odd", "f16x3")]
 
 
 @pytest.mark.parametrize("name", ["tiny", "ragged"])

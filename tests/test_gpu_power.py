@@ -61,7 +61,7 @@ def oracle_case(case):
 
 
 @pytest.mark.parametrize("name,prec", [("tiny", "f64"), ("tiny", "f32"), ("tiny", "bf16x3"), ("ragged", "f64"),
-                                       ("ragged", "bf16x3"), ("ragged", "f16x3")])
+                                       ("ragged", "bf16x3"), ("ragged", "f16x3"), ("odd", "f32"), ("odd", "bf16x3")])
 def test_power_beta_matches_oracle(name, prec):
     case = CASES[name]
     c = ctx_case(case, prec)

@@ -59,7 +59,8 @@ def oracle_case(case, S=3):
 
 
 @pytest.mark.parametrize("name,prec", [("tiny", "f64"), ("tiny", "bf16x3"), ("tiny", "f32"), ("ragged", "f64"),
-                                       ("ragged", "bf16x3"), ("ragged", "f16x3")])
+                                       ("ragged", "bf16x3"), ("ragged", "f16x3"), ("odd", "bf16x3"),
+                                       ("odd", "f16x3")])
 def test_trispectrum_matches_oracle(name, prec):
     case = CASES[name]
     c = ctx_case(case, prec)
