@@ -141,3 +141,26 @@ def test_power_estimator_recovers_amplitude():
     assert abs(E0.mean()) < 4 * se
     assert abs(E0.var(ddof=1) / s2 - 1.0) < 4 * math.sqrt(2.0 / (N - 1))
     assert abs(E1.mean() - 0.04) < 4 * se * 1.1
+
+
+def test_power_and_trispectrum_error_paths():
+    """Host-side argument checks of the C ABI (no kernel runs): short workspace, null
+    a_lm, no skies, a state that is not finalised."""
+    from paper_1105_2791_amd import ModalError
+    from paper_1105_2791_amd import _lib as L
+    case = CASES["tiny"]
+    c = ctx_case(case, "bf16x3")
+    a = torch.as_tensor(case.alms(0, 1)).to("cuda", torch.complex64)
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    nq = c._lib.modal_nquad(c._h)
+    for fn, width in ((c._lib.modal_power_beta, c.npairs), (c._lib.modal_trispectrum, nq)):
+        out = torch.empty((1, width), dtype=torch.float64, device="cuda")
+        assert fn(c._h, a.data_ptr(), 1, None, out.data_ptr(), ws.data_ptr(), 16, None) == L.ENOSPACE
+        assert fn(c._h, None, 1, None, out.data_ptr(), ws.data_ptr(), 16, None) == L.EINVAL
+        assert fn(c._h, a.data_ptr(), 0, None, out.data_ptr(), ws.data_ptr(), 16, None) == L.EINVAL
+    st = c.linear_state()
+    c.linear_reset(st)
+    for call in (c.power_beta, c.trispectrum):
+        with pytest.raises(ModalError) as ei:
+            call(case.alms(0, 1), st)
+        assert ei.value.status == L.ENOTREADY
