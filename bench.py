@@ -266,6 +266,8 @@ KERNEL_SOURCES = {   # dominant-kernel name -> the source file its counters belo
     "legendre": "paper_1105_2791_amd/csrc/k_legendre_split.hip",
     "fft": "paper_1105_2791_amd/csrc/k_fft.hip",
     "linear": "paper_1105_2791_amd/csrc/k_lin_harm.hip",
+    "pair_sums": "paper_1105_2791_amd/csrc/k_power.hip",       # power spectrum: pair sums + reduce
+    "quad": "paper_1105_2791_amd/csrc/k_trispectrum.hip",      # trispectrum: copies, update, reduce
 }
 
 
@@ -363,6 +365,7 @@ def run_power(args):
     res = run_path(args, args.prec, args.steps, args.warmup, make_state=not args.no_linear, op="power")
     pair = dict(res["kernels"]["cubic"])
     pair["kernel"] = "pair sums (k_pair_sums + k_pair_reduce)"
+    pair["traffic"] = measured_traffic("pair_sums", args.prec)
     line = {
         "metric": "modal power spectrum: sim maps/sec (filter + pair sums) @lmax=1000,P=40", "unit": "maps/s",
         "value": res["value"], "ms_per_step": res["ms_per_step"], "higher_is_better": True, "n_gpus": 1,
@@ -382,7 +385,8 @@ def run_trispectrum(args):
     """Modal trispectrum batches (Sec. IV): maps + the pairs x pairs update + gather for S skies."""
     res = run_path(args, args.prec, args.steps, args.warmup, make_state=not args.no_linear, op="trispectrum")
     k = dict(res["kernels"]["cubic"])
-    k["kernel"] = "pairs x pairs update (k_quad_syrk + k_quad_reduce)"
+    k["kernel"] = "pairs x pairs update (k_quad_vtile + k_quad_syrk + k_quad_reduce)"
+    k["traffic"] = measured_traffic("quad", args.prec)
     line = {
         "metric": "modal trispectrum: sim maps/sec (filter + quartic reduction) @lmax=1000,P=40", "unit": "maps/s",
         "value": res["value"], "ms_per_step": res["ms_per_step"], "higher_is_better": True, "n_gpus": 1,
