@@ -10,9 +10,11 @@
 // The update is a pairs x pairs SYRK with K = pixels.  Operands sqrt(w) A are formed on
 // the fly (w >= 0 splits evenly over both sides), never stored in HBM:
 //   * float maps (bf16x3 / f16x3 / f32 contexts): split-bf16 MFMA 32x32x16 with three
-//     products, 128 x 128 output tiles per workgroup (64 x 64 per wave), operands of a
-//     32-pixel step formed once per workgroup into LDS (one thread per operand row),
-//     FP32 chains of CH steps joined in FP32, FP64 partial sums per pixel chunk;
+//     products, 128 x 128 output tiles, two skies per workgroup (one per half, 64 x 64
+//     per wave), operands of a 32-pixel step formed once per half into LDS (each thread
+//     4 pixels of 8 operand rows), maps and pair means read from pixel-block-major copies
+//     (k_quad_vtile), FP32 chains of CH steps joined in FP32, FP32 partial sums per pixel
+//     chunk reduced in FP64;
 //   * double maps (f64 contexts): FP64 on the vector ALUs, 64 x 64 tiles, 4 x 4 per thread.
 #include "common.h"
 
