@@ -205,11 +205,11 @@ __device__ void block_gram(int N, int kb, const double* __restrict__ X, const do
 // entry e < N KB is handed to put(e, value).  EU entries of four blocks per thread are
 // loaded at a time, unconditionally (clamped indices, values selected afterwards), so
 // that 4 EU loads are in flight per wait instead of one.
-template <int EU, typename F>
+template <int EU, typename F, int NB = 256>
 __device__ void sum_partials_with(int N, int kb, int nsplit, const double* __restrict__ Yp, F put) {
   constexpr int PU = 4;
   const int tot = N * KB;
-  for (int e0 = threadIdx.x; e0 < tot; e0 += 256 * EU) {
+  for (int e0 = threadIdx.x; e0 < tot; e0 += NB * EU) {
     double sv[EU];
 #pragma unroll
     for (int u = 0; u < EU; ++u) sv[u] = 0.0;
@@ -219,7 +219,7 @@ __device__ void sum_partials_with(int N, int kb, int nsplit, const double* __res
       for (int q = 0; q < PU; ++q) {
         const size_t base = (size_t)min(p0 + q, nsplit - 1) * tot;
 #pragma unroll
-        for (int u = 0; u < EU; ++u) v[q][u] = Yp[base + min(e0 + 256 * u, tot - 1)];
+        for (int u = 0; u < EU; ++u) v[q][u] = Yp[base + min(e0 + NB * u, tot - 1)];
       }
 #pragma unroll
       for (int q = 0; q < PU; ++q)
@@ -228,7 +228,7 @@ __device__ void sum_partials_with(int N, int kb, int nsplit, const double* __res
     }
 #pragma unroll
     for (int u = 0; u < EU; ++u) {
-      const int e = e0 + 256 * u;
+      const int e = e0 + NB * u;
       if (e < tot) put(e, e % KB < kb ? sv[u] : 0.0);
     }
   }
@@ -295,24 +295,26 @@ __global__ __launch_bounds__(256) void k_orth(int N, int kb, int nsplit, const d
 }
 
 constexpr int ORN = 1024;   // largest N whose block k_orth_res keeps resident in LDS
+constexpr int ORT = 1024;   // threads of k_orth_res: one row each
 
 // k_orth with the whole N x KB block resident in LDS (N <= ORN, N (KB + 1) doubles of
 // dynamic LDS): the partial blocks are summed straight into LDS, both Cholesky QR rounds
 // read and write LDS only, and X goes to HBM once at the end.  Same arithmetic as
 // k_orth (the Gram sums run over the rows in another order).
-__global__ __launch_bounds__(256) void k_orth_res(int N, int kb, int nsplit, const double* __restrict__ Yp,
+__global__ __launch_bounds__(ORT) void k_orth_res(int N, int kb, int nsplit, const double* __restrict__ Yp,
                                                   double* __restrict__ X) {
   extern __shared__ __attribute__((aligned(16))) double ores[];
   double(*xs)[KB + 1] = reinterpret_cast<double(*)[KB + 1]>(ores);   // [N][KB + 1]
   __shared__ double C[KB][KB];
   __shared__ double R[KB][KB];
-  __shared__ double part[256];
+  __shared__ double part[ORT];
   __shared__ double rinv[KB];   // 1 / R[j][j], 0 for a dropped column
   const int tid = threadIdx.x;
   const int tot = N * KB;
-  sum_partials_with<16>(N, kb, nsplit, Yp, [&](int e, double v) { xs[e / KB][e % KB] = v; });
+  auto put_x = [&](int e, double v) { xs[e / KB][e % KB] = v; };
+  sum_partials_with<4, decltype(put_x), ORT>(N, kb, nsplit, Yp, put_x);
   __syncthreads();
-  const int kk = kb * kb, ng = 256 / kk;
+  const int kk = kb * kb, ng = ORT / kk;
   const int grp = tid / kk, ent = tid - grp * kk;
   const int a = ent / kb, b = ent - (ent / kb) * kb;
   for (int pass = 0; pass < 2; ++pass) {
@@ -349,16 +351,15 @@ __global__ __launch_bounds__(256) void k_orth_res(int N, int kb, int nsplit, con
         R[j][tid] = dj ? 0.0 : C[j][tid] / rjj;
       }
       __syncthreads();
-      for (int e = tid; e < kk; e += 256) {
+      for (int e = tid; e < kk; e += ORT) {
         const int ea = e / kb, eb = e - (e / kb) * kb;
         if (ea > j && eb > j) C[ea][eb] -= R[j][ea] * R[j][eb];
       }
       __syncthreads();
     }
     {
-      // y R = x for the thread's rows tid + 256 r (N <= 1024: all of them), the four
-      // substitutions interleaved
-      constexpr int NR = ORN / 256;
+      // y R = x for the thread's rows tid + ORT r (N <= ORN: all of them)
+      constexpr int NR = ORN / ORT;
       double y[NR][KB];
 #pragma unroll
       for (int j = 0; j < KB; ++j) {
@@ -366,7 +367,7 @@ __global__ __launch_bounds__(256) void k_orth_res(int N, int kb, int nsplit, con
           const double rj = rinv[j];
 #pragma unroll
           for (int r = 0; r < NR; ++r) {
-            const int i = tid + 256 * r;
+            const int i = tid + ORT * r;
             double sm = i < N ? xs[i][j] : 0.0;
 #pragma unroll
             for (int p = 0; p < j; ++p) sm -= y[r][p] * R[p][j];
@@ -378,7 +379,7 @@ __global__ __launch_bounds__(256) void k_orth_res(int N, int kb, int nsplit, con
     }
     __syncthreads();
   }
-  for (int e = tid; e < tot; e += 256) X[e] = xs[e / KB][e % KB];
+  for (int e = tid; e < tot; e += ORT) X[e] = xs[e / KB][e % KB];
 }
 
 // Cyclic Jacobi for the symmetric kb x kb matrix A (destroyed): eigenvalues w and
@@ -709,7 +710,7 @@ hipError_t launch_noise_vectors(int N, int n, int k, int iters, const double* B,
   }
   auto orth = [&](int ns) {
     if (res)
-      hipLaunchKernelGGL(k_orth_res, dim3(1), dim3(256), res_lds, st, N, kb, ns, Yp, X);
+      hipLaunchKernelGGL(k_orth_res, dim3(1), dim3(ORT), res_lds, st, N, kb, ns, Yp, X);
     else
       hipLaunchKernelGGL(k_orth, dim3(1), dim3(256), 0, st, N, kb, ns, Yp, X);
   };
