@@ -32,7 +32,8 @@ namespace {
 constexpr int KB = 16;     // iterated block width (max noise vectors plus oversampling)
 constexpr int GT = 64;     // Gram output tile
 constexpr int GK = 16;     // Gram column chunk staged in LDS
-constexpr int GXR = 64;    // rows i of G X per workgroup
+constexpr int GXR = 16;    // rows i of G X per workgroup (N = 1000: 63 x 4 workgroups)
+constexpr int GXP = 256 / GXR;   // phases over the rows l of G in a workgroup
 constexpr int GXL = 256;   // rows l of G summed per workgroup
 constexpr int RC = 256;    // rows staged per chunk in the one-workgroup kernels
 
@@ -137,9 +138,9 @@ __global__ void k_start_block(int N, int kb, double* __restrict__ X) {
 __global__ __launch_bounds__(256) void k_gx(int N, const double* __restrict__ G, const double* __restrict__ X,
                                             double* __restrict__ Yp) {
   __shared__ double xs[GXL][KB];
-  __shared__ double red[3][GXR][KB + 1];
+  __shared__ double red[GXP][GXR][KB + 1];
   const int i0 = blockIdx.x * GXR, l0 = blockIdx.y * GXL;
-  const int ri = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  const int ri = threadIdx.x % GXR, ph = threadIdx.x / GXR;
   const int lend = min(N, l0 + GXL);
   for (int e = threadIdx.x; e < GXL * KB; e += 256) {
     const int l = e / KB;
@@ -151,19 +152,22 @@ __global__ __launch_bounds__(256) void k_gx(int N, const double* __restrict__ G,
 #pragma unroll
   for (int j = 0; j < KB; ++j) acc[j] = 0.0;
   if (i < N)
-    for (int l = l0 + ph; l < lend; l += 4) {
+    for (int l = l0 + ph; l < lend; l += GXP) {
       const double g = G[(size_t)l * N + i];
 #pragma unroll
       for (int j = 0; j < KB; ++j) acc[j] = fma(g, xs[l - l0][j], acc[j]);
     }
-  if (ph > 0)
 #pragma unroll
-    for (int j = 0; j < KB; ++j) red[ph - 1][ri][j] = acc[j];
+  for (int j = 0; j < KB; ++j) red[ph][ri][j] = acc[j];
   __syncthreads();
-  if (ph == 0 && i < N)
-#pragma unroll
-    for (int j = 0; j < KB; ++j)
-      Yp[((size_t)blockIdx.y * N + i) * KB + j] = acc[j] + red[0][ri][j] + red[1][ri][j] + red[2][ri][j];
+  // one thread per (row, column) of the block: the phases added in a fixed order
+  const int orow = threadIdx.x / KB, oj = threadIdx.x % KB;
+  const int oi = i0 + orow;
+  if (orow < GXR && oi < N) {
+    double sm = 0.0;
+    for (int p = 0; p < GXP; ++p) sm += red[p][orow][oj];
+    Yp[((size_t)blockIdx.y * N + oi) * KB + oj] = sm;
+  }
 }
 
 // C[a][b] = sum_i X[i][a] Y[i][b] (a, b < kb) for one workgroup (Y may be X: then only X
