@@ -316,7 +316,7 @@ __global__ __launch_bounds__(ORT) void k_orth_res(int N, int kb, int nsplit, con
   const int tid = threadIdx.x;
   const int tot = N * KB;
   auto put_x = [&](int e, double v) { xs[e / KB][e % KB] = v; };
-  sum_partials_with<4, decltype(put_x), ORT>(N, kb, nsplit, Yp, put_x);
+  sum_partials_with<8, decltype(put_x), ORT>(N, kb, nsplit, Yp, put_x);
   __syncthreads();
   const int kk = kb * kb, ng = ORT / kk;
   const int grp = tid / kk, ent = tid - grp * kk;
