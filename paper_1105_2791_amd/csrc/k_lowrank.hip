@@ -480,12 +480,17 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(int N, int kb, int nsplit
   }
 }
 
+constexpr int NBC = 32;            // columns of B per workgroup of k_noise_from_block
+constexpr int NBP = 256 / NBC;     // row phases per workgroup (8)
+
 // bt[j][c] = sqrt(max(mu_j - 1, 0) / (6N mu_j)) sum_i B[i][c] X[i][j], j < k.
 __global__ __launch_bounds__(256) void k_noise_from_block(int N, int n, int k, const double* __restrict__ B,
                                                           const double* __restrict__ X, const double* __restrict__ mu,
                                                           double sixN, double* __restrict__ bt) {
   __shared__ double xs[RC][KB];
-  const int c = blockIdx.x * 256 + threadIdx.x;
+  __shared__ double red[NBP][NBC][KB + 1];
+  const int cl = threadIdx.x % NBC, ph = threadIdx.x / NBC;
+  const int c = blockIdx.x * NBC + cl;
   double acc[KB];
 #pragma unroll
   for (int j = 0; j < KB; ++j) acc[j] = 0.0;
@@ -497,18 +502,26 @@ __global__ __launch_bounds__(256) void k_noise_from_block(int N, int n, int k, c
     __syncthreads();
     const int nr = min(RC, N - r0);
     if (c < n)
-      for (int r = 0; r < nr; ++r) {
+      for (int r = ph; r < nr; r += NBP) {
         const double b = B[(size_t)(r0 + r) * n + c];
 #pragma unroll
         for (int j = 0; j < KB; ++j) acc[j] = fma(b, xs[r][j], acc[j]);
       }
     __syncthreads();
   }
-  if (c >= n) return;
-  for (int j = 0; j < k; ++j) {
-    const double m = mu[j];
-    const double coef = m > 1.0 ? sqrt((m - 1.0) / (sixN * m)) : 0.0;
-    bt[(size_t)j * n + c] = coef * acc[j];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) red[ph][cl][j] = acc[j];
+  __syncthreads();
+  // one thread per (vector j, column): the row phases added in a fixed order
+  for (int e = threadIdx.x; e < KB * NBC; e += 256) {
+    const int j = e / NBC, oc = e - j * NBC, cc = blockIdx.x * NBC + oc;
+    if (j < k && cc < n) {
+      double sm = 0.0;
+      for (int p = 0; p < NBP; ++p) sm += red[p][oc][j];
+      const double m = mu[j];
+      const double coef = m > 1.0 ? sqrt((m - 1.0) / (sixN * m)) : 0.0;
+      bt[(size_t)j * n + cc] = coef * sm;
+    }
   }
 }
 
@@ -726,7 +739,7 @@ hipError_t launch_noise_vectors(int N, int n, int k, int iters, const double* B,
   }
   hipLaunchKernelGGL(k_gx, ggx, dim3(256), 0, st, N, G, X, Yp);
   hipLaunchKernelGGL(k_rayleigh_ritz, dim3(1), dim3(256), 0, st, N, kb, nsplit, Yp, Y, X, mu_dev);
-  hipLaunchKernelGGL(k_noise_from_block, dim3((n + 255) / 256), dim3(256), 0, st, N, n, k, B, X, mu_dev,
+  hipLaunchKernelGGL(k_noise_from_block, dim3((n + NBC - 1) / NBC), dim3(256), 0, st, N, n, k, B, X, mu_dev,
                      6.0 * N, bt);
   hipLaunchKernelGGL(k_sign_fix, dim3(k), dim3(256), 0, st, n, bt);
   return hipGetLastError();
