@@ -67,25 +67,39 @@ __global__ __launch_bounds__(64) void k_legendre_series(int L, int nmu, int P, c
 }
 
 // alpha[n] = 1/(48 pi) sum_k w_k sum_t sum_sigma F[3t + sigma1][k][p] F[3t + sigma2][k][q] F[3t + sigma3][k][r]
+// A workgroup takes AMC modes, its threads AMP phases of the nodes k; the phases are added
+// in a fixed order through LDS.
+constexpr int AMC = 32;
+constexpr int AMP = 256 / AMC;
+
 __global__ __launch_bounds__(256) void k_alpha_modes(int nmax, int P, int T, int nmu, const int* __restrict__ tri,
                                                      const double* __restrict__ F, const double* __restrict__ wmu,
                                                      double* __restrict__ alpha) {
-  const int n = blockIdx.x * 256 + threadIdx.x;
-  if (n >= nmax) return;
-  const int p = tri[6 * n], q = tri[6 * n + 1], r = tri[6 * n + 2];
+  __shared__ double red[AMP][AMC];
+  const int ml = threadIdx.x % AMC, ph = threadIdx.x / AMC;
+  const int n = blockIdx.x * AMC + ml;
   double acc = 0.0;
-  for (int k = 0; k < nmu; ++k) {
-    double s = 0.0;
-    for (int t = 0; t < T; ++t) {
-      const double* X = F + ((size_t)(3 * t) * nmu + k) * P;
-      const double* Y = X + (size_t)nmu * P;
-      const double* Z = Y + (size_t)nmu * P;
-      const double xp = X[p], xq = X[q], xr = X[r], yp = Y[p], yq = Y[q], yr = Y[r], zp = Z[p], zq = Z[q], zr = Z[r];
-      s += xp * (yq * zr + zq * yr) + yp * (xq * zr + zq * xr) + zp * (xq * yr + yq * xr);
+  if (n < nmax) {
+    const int p = tri[6 * n], q = tri[6 * n + 1], r = tri[6 * n + 2];
+    for (int k = ph; k < nmu; k += AMP) {
+      double sm = 0.0;
+      for (int t = 0; t < T; ++t) {
+        const double* X = F + ((size_t)(3 * t) * nmu + k) * P;
+        const double* Y = X + (size_t)nmu * P;
+        const double* Z = Y + (size_t)nmu * P;
+        const double xp = X[p], xq = X[q], xr = X[r], yp = Y[p], yq = Y[q], yr = Y[r], zp = Z[p], zq = Z[q], zr = Z[r];
+        sm += xp * (yq * zr + zq * yr) + yp * (xq * zr + zq * xr) + zp * (xq * yr + yq * xr);
+      }
+      acc = fma(wmu[k], sm, acc);
     }
-    acc = fma(wmu[k], s, acc);
   }
-  alpha[n] = acc * (1.0 / (48.0 * 3.14159265358979323846));
+  red[ph][ml] = acc;
+  __syncthreads();
+  if (ph == 0 && n < nmax) {
+    double s = 0.0;
+    for (int i = 0; i < AMP; ++i) s += red[i][ml];
+    alpha[n] = s * (1.0 / (48.0 * 3.14159265358979323846));
+  }
 }
 
 // zeta0 over the padded row order (runs of equal (p, r), each a multiple of 4 rows):
@@ -180,7 +194,7 @@ hipError_t launch_legendre_series(int L, int nmu, int P, int nf, const double* U
 
 hipError_t launch_alpha_modes(int nmax, int P, int T, int nmu, const int* tri, const double* F, const double* wmu,
                               double* alpha, hipStream_t st) {
-  hipLaunchKernelGGL(k_alpha_modes, dim3((nmax + 255) / 256), dim3(256), 0, st, nmax, P, T, nmu, tri, F, wmu, alpha);
+  hipLaunchKernelGGL(k_alpha_modes, dim3((nmax + AMC - 1) / AMC), dim3(256), 0, st, nmax, P, T, nmu, tri, F, wmu, alpha);
   return hipGetLastError();
 }
 
