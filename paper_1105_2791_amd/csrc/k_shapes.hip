@@ -26,14 +26,15 @@ namespace {
 
 constexpr int SL = 64;   // l per staged chunk of the series kernel
 
-// F[f][k][a] = sum_l (2l+1) U[f][l] B[a][l] P_l(mu_k), a < P <= NP; one thread per node.
+// F[f][k][a] = sum_l (2l+1) U[f][l] B[a][l] P_l(mu_k); one thread per node for the modes
+// a0 .. a0 + NP - 1, a0 = NP blockIdx.z (each group of modes repeats the cheap recurrence).
 template <int NP>
 __global__ __launch_bounds__(64) void k_legendre_series(int L, int nmu, int P, const double* __restrict__ U,
                                                         const double* __restrict__ B, const double* __restrict__ mu,
                                                         double* __restrict__ F) {
   __shared__ double bs[SL][NP];
   __shared__ double us[SL];
-  const int f = blockIdx.y;
+  const int f = blockIdx.y, a0 = blockIdx.z * NP;
   const int k = blockIdx.x * 64 + threadIdx.x;
   const double x = k < nmu ? mu[k] : 0.0;
   double acc[NP];
@@ -44,7 +45,7 @@ __global__ __launch_bounds__(64) void k_legendre_series(int L, int nmu, int P, c
     __syncthreads();
     for (int e = threadIdx.x; e < SL * NP; e += 64) {
       const int i = e / NP, a = e - i * NP;
-      bs[i][a] = (a < P && l0 + i < L) ? B[(size_t)a * L + l0 + i] : 0.0;
+      bs[i][a] = (a0 + a < P && l0 + i < L) ? B[(size_t)(a0 + a) * L + l0 + i] : 0.0;
     }
     us[threadIdx.x] = l0 + (int)threadIdx.x < L ? U[(size_t)f * L + l0 + threadIdx.x] : 0.0;
     __syncthreads();
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(64) void k_legendre_series(int L, int nmu, int P, c
   double* out = F + ((size_t)f * nmu + k) * P;
 #pragma unroll
   for (int a = 0; a < NP; ++a)
-    if (a < P) out[a] = acc[a];
+    if (a0 + a < P) out[a0 + a] = acc[a];
 }
 
 // alpha[n] = 1/(48 pi) sum_k w_k sum_t sum_sigma F[3t + sigma1][k][p] F[3t + sigma2][k][q] F[3t + sigma3][k][r]
@@ -185,10 +186,9 @@ int shapes_nmu(int lmax) { return (3 * lmax + 2) / 2; }
 
 hipError_t launch_legendre_series(int L, int nmu, int P, int nf, const double* U, const double* B, const double* mu,
                                   double* F, hipStream_t st) {
-  const dim3 grid((nmu + 63) / 64, nf);
-  if (P <= 16) hipLaunchKernelGGL(k_legendre_series<16>, grid, dim3(64), 0, st, L, nmu, P, U, B, mu, F);
-  else if (P <= 32) hipLaunchKernelGGL(k_legendre_series<32>, grid, dim3(64), 0, st, L, nmu, P, U, B, mu, F);
-  else hipLaunchKernelGGL(k_legendre_series<64>, grid, dim3(64), 0, st, L, nmu, P, U, B, mu, F);
+  constexpr int NG = 16;   // modes per thread
+  const dim3 grid((nmu + 63) / 64, nf, (P + NG - 1) / NG);
+  hipLaunchKernelGGL(k_legendre_series<NG>, grid, dim3(64), 0, st, L, nmu, P, U, B, mu, F);
   return hipGetLastError();
 }
 
