@@ -446,6 +446,110 @@ def run_shapes(args):
     print(json.dumps(line), flush=True)
 
 
+def _time_ms(f, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        f()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / steps
+
+
+def _roof(flop, ms, bound, peak):
+    rate = flop / (ms * 1e-3)
+    return {"bound": bound, "per_launch": flop, "per_launch_unit": "flop", "achieved": rate / 1e12,
+            "peak": peak / 1e12, "unit": "TFLOP/s", "frac": rate / peak, "traffic": None}
+
+
+def run_estimator(args):
+    """The estimator and gradient rows, each timed whole (host clock around synchronised
+    calls): the adjoint (VJP) of beta^hat for S skies at the workload shape, the sample
+    covariance of N = 200 beta^hat rows and the FP64 Cholesky estimator at n_max(P), the
+    Fisher covariance at l_max 500, GL 768 x 1536, P 30 in FP32, and the replay of one graph
+    holding beta calls of two contexts (l_max 500 and the workload's) against eager calls."""
+    import numpy as np
+    import torch
+    import modal_inputs as mi
+    from paper_1105_2791_amd import ModalContext
+    from paper_1105_2791_amd.api import BetaGraph
+    lmax, nt, nphi, P, S, prec = args.lmax, args.ntheta, args.nphi, args.P, args.batch, args.prec
+    split = prec in ("bf16x3", "f16x3")
+    mpeak = PEAK["bf16"] if split else (PEAK["f32_mfma"] if prec == "f32" else PEAK["f64_vec"])
+    rng = np.random.default_rng(2012)
+    items = {}
+    cl = mi.filter_cl(lmax, "wmap")
+    ctx = ModalContext(lmax, nt, nphi, P, prec, mi.q_basis(P, lmax), cl)
+    n = ctx.nmax
+    st = ctx.linear_state()
+    ctx.linear_reset(st)
+    ctx.linear_accumulate(st, make_inputs(lmax, P, S, 1000))
+    ctx.linear_finalize(st)
+    alm = ctx._alm(make_inputs(lmax, P, S, 0))
+    cot = torch.as_tensor(rng.standard_normal((S, n)), device="cuda")
+    log("estimator: vjp")
+    t = _time_ms(lambda: ctx.beta_vjp(alm, cot, st), args.steps, 1)
+    # adjoint Legendre (the synthesis transposed) + the cotangent contraction over the
+    # triples (the cubic's count); the r2c FFT is HBM work on top
+    flop = 2.0 * ctx.nalm * nt * P * S + 2.0 * n * nt * nphi * S
+    items["vjp"] = {"row": "A9", "shape": f"lmax={lmax} GL {nt}x{nphi} P={P} S={S} {prec}, with the linear-term state",
+                    "ms": t, "gradients_per_s": S / (t * 1e-3), "roofline": _roof(flop, t, "mfma", mpeak)}
+    N = 200
+    B = torch.as_tensor(rng.standard_normal((N, n)), device="cuda")
+    log("estimator: sample covariance")
+    t = _time_ms(lambda: ctx.covariance_sample(B), args.steps, 1)
+    items["covariance_sample"] = {"row": "A7", "shape": f"N={N} rows of n_max={n}", "ms": t,
+                                  "roofline": _roof(float(N) * n * (n + 1), t, "alu", PEAK["f64_vec"])}
+    Z = ctx.covariance_sample(B) + torch.eye(n, dtype=torch.float64, device="cuda")
+    alpha = torch.as_tensor(rng.standard_normal(n), device="cuda")
+    betas = torch.as_tensor(rng.standard_normal((S, n)), device="cuda")
+    log("estimator: Cholesky estimator")
+    t = _time_ms(lambda: ctx.fnl(Z, alpha, betas), max(1, args.steps // 2), 1)
+    items["fnl"] = {"row": "A8", "shape": f"n_max={n}, S={S} (zeta = sample covariance + I)", "ms": t,
+                    "roofline": _roof(2.0 * n ** 3 / 3.0 + 2.0 * (S + 1) * n * n, t, "alu", PEAK["f64_vec"])}
+    del Z, B
+    # graph replay: one graph with the beta calls of two contexts against eager calls
+    l2, nt2, nphi2 = 500, 768, 1536
+    cl2 = mi.filter_cl(l2, "wmap")
+    c2 = ModalContext(l2, nt2, nphi2, P, prec, mi.q_basis(P, l2), cl2)
+    a2 = c2._alm(make_inputs(l2, P, S, 0))
+    g = BetaGraph([(c2, a2, None), (ctx, alm, None)])
+    o1 = torch.empty((S, c2.nmax), dtype=torch.float64, device="cuda")
+    o2 = torch.empty((S, n), dtype=torch.float64, device="cuda")
+    log("estimator: graph replay")
+    tg = _time_ms(g.launch, args.steps, 1)
+    te = _time_ms(lambda: (c2.beta(a2, out=o1), ctx.beta(alm, out=o2)), args.steps, 1)
+    items["graph"] = {"row": "A11", "shape": f"beta of S={S} at lmax 500 (GL 768x1536) and lmax {lmax}, P={P}, {prec}",
+                      "graph_ms": tg, "eager_ms": te}
+    g.close()
+    c2.close()
+    ctx.close()
+    # Fisher covariance at the l_max 500, P 30 FP32 shape (every pair adjoint per sky)
+    lf, Pf, Nf = 500, 30, 2
+    clf = mi.filter_cl(lf, "wmap")
+    cf_ = ModalContext(lf, 768, 1536, Pf, "f32", mi.q_basis(Pf, lf), clf)
+    stf = cf_.linear_state()
+    cf_.linear_reset(stf)
+    cf_.linear_accumulate(stf, make_inputs(lf, Pf, 4, 1000))
+    cf_.linear_finalize(stf)
+    af = cf_._alm(make_inputs(lf, Pf, Nf, 0))
+    log("estimator: Fisher covariance")
+    t = _time_ms(lambda: cf_.covariance_fisher(af, clf, stf), 1, 1)
+    items["fisher"] = {"row": "A10", "shape": f"lmax={lf} GL 768x1536 P={Pf} (nmax={cf_.nmax}, {cf_.npairs} pair adjoints "
+                                              f"per sky) f32, N={Nf} skies", "ms": t, "ms_per_sky": t / Nf}
+    cf_.close()
+    line = {
+        "metric": "estimator and gradient rows: adjoint, covariance, Cholesky estimator, Fisher, graph replay",
+        "unit": "ms", "value": items["vjp"]["ms"], "higher_is_better": False, "n_gpus": 1, "steps": args.steps,
+        "dtype": {"bf16x3": "bf16", "f16x3": "f16", "f32": "f32", "f64": "f64"}[prec], "data": "synthetic",
+        "config": {"workload": f"lmax={lmax} GL {nt}x{nphi} P={P} n_max={n} S={S} (value: the VJP of S skies)"},
+        "items": items,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -466,10 +570,12 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of a known size (HBM counter calibration)")
     ap.add_argument("--no-linear", action="store_true", help="beta without the linear term (diagnostic)")
-    ap.add_argument("--workload", default="beta", choices=["beta", "lowrank", "power", "shapes", "trispectrum"],
+    ap.add_argument("--workload", default="beta",
+                    choices=["beta", "lowrank", "power", "shapes", "trispectrum", "estimator"],
                     help="beta: the hot path (default); lowrank: the low-rank covariance calls; "
                          "power: the modal power spectrum; shapes: alpha_n and the ideal covariance; "
-                         "trispectrum: the modal trispectrum")
+                         "trispectrum: the modal trispectrum; estimator: adjoint, covariance, Cholesky "
+                         "estimator, Fisher and graph replay")
     ap.add_argument("--lr-sims", type=int, default=1000, help="lowrank: beta^hat vectors N")
     ap.add_argument("--lr-k", type=int, default=4, help="lowrank: noise vectors k")
     ap.add_argument("--lr-iters", type=int, default=100, help="lowrank: block iterations")
@@ -495,6 +601,9 @@ def main():
         return
     if args.workload == "trispectrum":
         run_trispectrum(args)
+        return
+    if args.workload == "estimator":
+        run_estimator(args)
         return
     prec = args.prec
     head = run_path(args, prec, args.steps, args.warmup, make_state=not args.no_linear)

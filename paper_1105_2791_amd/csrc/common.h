@@ -187,8 +187,7 @@ hipError_t launch_slot_matrix(const modal_ctx* c, const double* cot, int S, void
 hipError_t launch_pair_adjoint(const modal_ctx* c, const void* maps, const void* V, const void* K, int S,
                                void* G, hipStream_t st);
 hipError_t launch_lambda_table(const modal_ctx* c, void* lam, hipStream_t st);
-hipError_t launch_adj_legendre(const modal_ctx* c, const void* lam, const void* Gh, int S, void* grad,
-                               hipStream_t st);
+hipError_t launch_adj_combine(const modal_ctx* c, const void* Z, int S, void* grad, hipStream_t st);
 
 // FP64 dense linear algebra
 hipError_t launch_syrk(int n, int N, const double* B, double scale, double* Z, hipStream_t st);

@@ -203,54 +203,33 @@ __global__ void k_lambda_table(int lmax, int nrp, const double* __restrict__ x, 
 }
 
 // ---------------------------------------------------------------------------
-// adjoint Legendre + mode combination:
-//   grad_{s,lm} = c_m / sqrt(C_l) sum_u q_u(l) sum_j lambda_lm(theta_j) Gh_{s,u,m}(theta_j)
-// with c_m = 2 - delta_m0.  Mirror rings are folded first: sum over all rings of
-// lambda Gh = sum over north rings of lambda (Gh_N + (-1)^{l+m} Gh_S).
-// One thread per (l, s); loops over u and rings; lam is read from the table.
+// mode combination after the adjoint Legendre contraction of every (sky, mode) column
+// (k_adj_legendre_cols: Z[s P + u][lm] = c_m sum_j lambda_lm(theta_j) Gh_{s,u,m}(theta_j),
+// mirror rings folded, imaginary part zero at m = 0):
+//   grad_{s,lm} = sum_u q_u(l) / sqrt(C_l) Z[s P + u][lm].
+// One thread per (l, s) of one m; the column reads are coalesced along l.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_adj_legendre(int lmax, int ntheta, int nrp, int P, int S, int nalm,
-                                                      const T* __restrict__ lam, const T* __restrict__ qw,
-                                                      const typename vec2<T>::type* __restrict__ Gh,
-                                                      typename vec2<T>::type* __restrict__ grad) {
+__global__ __launch_bounds__(256) void k_adj_combine(int lmax, int P, int S, int nalm, const T* __restrict__ qw,
+                                                     const typename vec2<T>::type* __restrict__ Z,
+                                                     typename vec2<T>::type* __restrict__ grad) {
   using T2 = typename vec2<T>::type;
-  const int m = blockIdx.y;
-  const int L = lmax + 1 - m;
-  const int li = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int s = blockIdx.z * 4 + (threadIdx.x >> 6);
-  const size_t off = (size_t)m * (2 * lmax + 3 - m) / 2;
-  if (li >= L || s >= S) return;
+  const int m = blockIdx.y, s = blockIdx.z;
+  const int li = blockIdx.x * 256 + threadIdx.x;
+  if (li > lmax - m) return;
   const int l = m + li;
-  const bool odd = (li & 1);
-  const T* lrow = lam + off * nrp;  // [nrp][L]
-  double gre = 0.0, gim = 0.0;
+  const size_t o = (size_t)m * (2 * lmax + 3 - m) / 2 + li;
+  double gr = 0.0, gi = 0.0;
   for (int u = 0; u < P; ++u) {
-    const T2* gu = Gh + (size_t)(s * P + u) * ntheta * (lmax + 1);
-    double dre = 0.0, dim = 0.0;
-    for (int j = 0; j < nrp; ++j) {
-      const double lv = (double)lrow[(size_t)j * L + li];
-      const T2* gm = gu + (size_t)m * ntheta;   // Gh[seq][m][ring]
-      const T2 gn = gm[j];
-      const int js = ntheta - 1 - j;
-      T2 gs;
-      gs.x = T(0);
-      gs.y = T(0);
-      if (js != j) gs = gm[js];
-      const double hr = odd ? (double)gn.x - (double)gs.x : (double)gn.x + (double)gs.x;
-      const double hi = odd ? (double)gn.y - (double)gs.y : (double)gn.y + (double)gs.y;
-      dre += lv * hr;
-      dim += lv * hi;
-    }
-    const double qv = (double)qw[(size_t)u * (lmax + 1) + l];
-    gre += qv * dre;
-    gim += qv * dim;
+    const double q = (double)qw[(size_t)u * (lmax + 1) + l];
+    const T2 z = Z[((size_t)s * P + u) * nalm + o];
+    gr += q * (double)z.x;
+    gi += q * (double)z.y;
   }
-  const double cm = (m == 0) ? 1.0 : 2.0;
   T2 g;
-  g.x = T(cm * gre);
-  g.y = T(m == 0 ? 0.0 : cm * gim);
-  grad[(size_t)s * nalm + off + li] = g;
+  g.x = T(gr);
+  g.y = T(gi);
+  grad[(size_t)s * nalm + o] = g;
 }
 
 }  // namespace
@@ -289,15 +268,14 @@ hipError_t launch_lambda_table(const modal_ctx* c, void* lam, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_adj_legendre(const modal_ctx* c, const void* lam, const void* Gh, int S, void* grad,
-                               hipStream_t st) {
-  dim3 grid((c->lmax + 1 + 63) / 64, c->lmax + 1, (S + 3) / 4);
+hipError_t launch_adj_combine(const modal_ctx* c, const void* Z, int S, void* grad, hipStream_t st) {
+  dim3 grid((c->lmax + 1 + 255) / 256, c->lmax + 1, S);
   if (is_f64(c))
-    hipLaunchKernelGGL(k_adj_legendre<double>, grid, dim3(256), 0, st, c->lmax, c->ntheta, c->nrp, c->P, S, c->nalm,
-                       (const double*)lam, c->t.qw64, (const double2*)Gh, (double2*)grad);
+    hipLaunchKernelGGL(k_adj_combine<double>, grid, dim3(256), 0, st, c->lmax, c->P, S, c->nalm, c->t.qw64,
+                       (const double2*)Z, (double2*)grad);
   else
-    hipLaunchKernelGGL(k_adj_legendre<float>, grid, dim3(256), 0, st, c->lmax, c->ntheta, c->nrp, c->P, S, c->nalm,
-                       (const float*)lam, c->t.qw32, (const float2*)Gh, (float2*)grad);
+    hipLaunchKernelGGL(k_adj_combine<float>, grid, dim3(256), 0, st, c->lmax, c->P, S, c->nalm, c->t.qw32,
+                       (const float2*)Z, (float2*)grad);
   return hipGetLastError();
 }
 
