@@ -21,36 +21,48 @@ __global__ void k_slot(int P, int npairs, int nmax, int S, const int* __restrict
 }
 
 constexpr int kPx = 64;
-constexpr int kPc = 32;
+constexpr int kPc = 16;
 
-template <typename T, bool LIN>
-__global__ __launch_bounds__(256) void k_pair_adjoint(int P, int npairs, int npix, const int* __restrict__ pair_a,
-                                                      const int* __restrict__ pair_b, const T* __restrict__ maps,
-                                                      const T* __restrict__ V, const T* __restrict__ w,
-                                                      const double* __restrict__ K, T* __restrict__ G) {
-  const int s = blockIdx.y;
+// One workgroup: 64 pixels of SK skies (SK = 2 for float maps, 1 for double); the pair
+// means of each 16-pair chunk are staged in LDS once for the SK skies with coalesced loads,
+// so the inner loop reads LDS only.  Thread (px, ug) accumulates the modes u = ug + 4 i.
+template <typename T, bool LIN, int SK>
+__global__ __launch_bounds__(256) void k_pair_adjoint(int P, int npairs, int npix, int S,
+                                                      const int* __restrict__ pair_a, const int* __restrict__ pair_b,
+                                                      const T* __restrict__ maps, const T* __restrict__ V,
+                                                      const T* __restrict__ w, const double* __restrict__ K,
+                                                      T* __restrict__ G) {
+  const int s0 = blockIdx.y * SK;
   const int x0 = blockIdx.x * kPx;
   const int px = threadIdx.x & 63, ug = threadIdx.x >> 6;
   const int x = x0 + px;
-  __shared__ T Mt[kMaxP][kPx];
-  __shared__ double Ks[kMaxP][kPc];
+  __shared__ T Mt[SK][kMaxP][kPx];
+  __shared__ double Ks[SK][kMaxP][kPc];
+  __shared__ T Vs[kPc][kPx];
   __shared__ int sa[kPc], sb[kPc];
-  const T* Ms = maps + (size_t)s * P * npix;
-  for (int e = threadIdx.x; e < P * kPx; e += 256) {
-    const int p = e / kPx, xx = e - p * kPx;
-    Mt[p][xx] = (x0 + xx < npix) ? Ms[(size_t)p * npix + x0 + xx] : T(0);
+  for (int e = threadIdx.x; e < SK * P * kPx; e += 256) {
+    const int sk = e / (P * kPx), rem = e - sk * P * kPx, p = rem / kPx, xx = rem - p * kPx;
+    const int s = s0 + sk;
+    Mt[sk][p][xx] = (s < S && x0 + xx < npix) ? maps[((size_t)s * P + p) * npix + x0 + xx] : T(0);
   }
-  double acc[16];
+  double acc[SK][16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] = 0.0;
-  const double* Kslab = K + (size_t)s * P * npairs;
+  for (int sk = 0; sk < SK; ++sk)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[sk][i] = 0.0;
   for (int c0 = 0; c0 < npairs; c0 += kPc) {
     const int nc = min(kPc, npairs - c0);
     __syncthreads();
-    for (int e = threadIdx.x; e < P * kPc; e += 256) {
-      const int u = e / kPc, pc = e - u * kPc;
-      Ks[u][pc] = pc < nc ? Kslab[(size_t)u * npairs + c0 + pc] : 0.0;
+    for (int e = threadIdx.x; e < SK * P * kPc; e += 256) {
+      const int sk = e / (P * kPc), rem = e - sk * P * kPc, u = rem / kPc, pc = rem - u * kPc;
+      const int s = s0 + sk;
+      Ks[sk][u][pc] = (s < S && pc < nc) ? K[((size_t)s * P + u) * npairs + c0 + pc] : 0.0;
     }
+    if (LIN)
+      for (int e = threadIdx.x; e < kPc * kPx; e += 256) {
+        const int pc = e / kPx, xx = e - pc * kPx;
+        Vs[pc][xx] = (pc < nc && x0 + xx < npix) ? V[(size_t)(c0 + pc) * npix + x0 + xx] : T(0);
+      }
     if (threadIdx.x < kPc) {
       sa[threadIdx.x] = threadIdx.x < nc ? pair_a[c0 + threadIdx.x] : 0;
       sb[threadIdx.x] = threadIdx.x < nc ? pair_b[c0 + threadIdx.x] : 0;
@@ -58,12 +70,16 @@ __global__ __launch_bounds__(256) void k_pair_adjoint(int P, int npairs, int npi
     __syncthreads();
     if (x < npix) {
       for (int pc = 0; pc < nc; ++pc) {
-        double A = (double)Mt[sa[pc]][px] * (double)Mt[sb[pc]][px];
-        if (LIN) A -= (double)V[(size_t)(c0 + pc) * npix + x];
+        const double v = LIN ? (double)Vs[pc][px] : 0.0;
+        const int a = sa[pc], b = sb[pc];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int u = ug + 4 * i;
-          if (u < P) acc[i] += Ks[u][pc] * A;
+        for (int sk = 0; sk < SK; ++sk) {
+          const double A = (double)Mt[sk][a][px] * (double)Mt[sk][b][px] - v;
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int u = ug + 4 * i;
+            if (u < P) acc[sk][i] += Ks[sk][u][pc] * A;
+          }
         }
       }
     }
@@ -71,9 +87,14 @@ __global__ __launch_bounds__(256) void k_pair_adjoint(int P, int npairs, int npi
   if (x >= npix) return;
   const double wx = (double)w[x];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int u = ug + 4 * i;
-    if (u < P) G[((size_t)s * P + u) * npix + x] = T(wx * acc[i]);
+  for (int sk = 0; sk < SK; ++sk) {
+    const int s = s0 + sk;
+    if (s >= S) break;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int u = ug + 4 * i;
+      if (u < P) G[((size_t)s * P + u) * npix + x] = T(wx * acc[sk][i]);
+    }
   }
 }
 
@@ -88,16 +109,16 @@ hipError_t launch_slot_matrix(const modal_ctx* c, const double* cot, int S, void
 
 hipError_t launch_pair_adjoint(const modal_ctx* c, const void* maps, const void* V, const void* K, int S, void* G,
                                hipStream_t st) {
-  dim3 grid((c->npix + kPx - 1) / kPx, S);
-#define LAUNCH(T, L, W)                                                                                          \
-  hipLaunchKernelGGL((k_pair_adjoint<T, L>), grid, dim3(256), 0, st, c->P, c->npairs, c->npix, c->t.pair_a,      \
-                     c->t.pair_b, (const T*)maps, (const T*)V, (const T*)W, (const double*)K, (T*)G)
+#define LAUNCH(T, L, SKN, W)                                                                                     \
+  hipLaunchKernelGGL((k_pair_adjoint<T, L, SKN>), dim3((c->npix + kPx - 1) / kPx, (S + SKN - 1) / SKN), dim3(256), \
+                     0, st, c->P, c->npairs, c->npix, S, c->t.pair_a, c->t.pair_b, (const T*)maps, (const T*)V,   \
+                     (const T*)W, (const double*)K, (T*)G)
   if (is_f64(c)) {
-    if (V) LAUNCH(double, true, c->t.w64);
-    else LAUNCH(double, false, c->t.w64);
+    if (V) LAUNCH(double, true, 1, c->t.w64);
+    else LAUNCH(double, false, 1, c->t.w64);
   } else {
-    if (V) LAUNCH(float, true, c->t.w32);
-    else LAUNCH(float, false, c->t.w32);
+    if (V) LAUNCH(float, true, 2, c->t.w32);
+    else LAUNCH(float, false, 2, c->t.w32);
   }
 #undef LAUNCH
   return hipGetLastError();
