@@ -98,6 +98,84 @@ __global__ __launch_bounds__(256) void k_pair_adjoint(int P, int npairs, int npi
   }
 }
 
+// Float maps, P <= 48: the same contraction on the matrix cores in FP32,
+//   G[u][x] = w(x) sum_pairs K[u][pair] (M_a M_b - V_ab)(x),
+// a GEMM with rows = modes u (three 16-row tiles), columns = pixels, inner index = pairs,
+// on v_mfma_f32_16x16x4_f32 (lane l holds A[l % 16][l / 16], B[l / 16][l % 16], and
+// accumulator register r is D[4 (l / 16) + r][l % 16]).  A = K of a 64-pair chunk (FP32,
+// in LDS), B = the pair product of the lane's pixel and pair, formed on the fly.  Each
+// chunk is a chain of 16 MFMAs from zero, added to the running sums with a vector add.
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+constexpr int kMx = 64;   // pixels per workgroup (16 per wave)
+constexpr int kMc = 64;   // pairs per staged chunk (16 MFMA steps of 4)
+constexpr int kMt = 3;    // 16-mode tiles (P <= 48)
+
+template <bool LIN>
+__global__ __launch_bounds__(256) void k_pair_adjoint_mfma(int P, int npairs, int npix,
+                                                           const int* __restrict__ pair_a,
+                                                           const int* __restrict__ pair_b,
+                                                           const float* __restrict__ maps,
+                                                           const float* __restrict__ V, const float* __restrict__ w,
+                                                           const double* __restrict__ K, float* __restrict__ G) {
+  const int s = blockIdx.y, x0 = blockIdx.x * kMx;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int xl = wv * 16 + l16;   // this lane's pixel within the block
+  __shared__ float Mt[kMaxP][kMx];
+  __shared__ float Ks[kMt * 16][kMc + 1];
+  __shared__ float Vs[kMc][kMx];
+  __shared__ int sab[kMc];        // a | b << 8 of each pair of the chunk
+  const float* Ms = maps + (size_t)s * P * npix;
+  for (int e = tid; e < P * kMx; e += 256) {
+    const int p = e / kMx, xx = e - p * kMx;
+    Mt[p][xx] = x0 + xx < npix ? Ms[(size_t)p * npix + x0 + xx] : 0.f;
+  }
+  f32x4 acc[kMt];
+#pragma unroll
+  for (int t = 0; t < kMt; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const double* Kslab = K + (size_t)s * P * npairs;
+  for (int c0 = 0; c0 < npairs; c0 += kMc) {
+    const int nc = min(kMc, npairs - c0);
+    __syncthreads();
+    for (int e = tid; e < kMt * 16 * kMc; e += 256) {
+      const int u = e / kMc, pc = e - u * kMc;
+      Ks[u][pc] = (u < P && pc < nc) ? (float)Kslab[(size_t)u * npairs + c0 + pc] : 0.f;
+    }
+    if (LIN)
+      for (int e = tid; e < kMc * kMx; e += 256) {
+        const int pc = e / kMx, xx = e - pc * kMx;
+        Vs[pc][xx] = (pc < nc && x0 + xx < npix) ? V[(size_t)(c0 + pc) * npix + x0 + xx] : 0.f;
+      }
+    if (tid < kMc) sab[tid] = tid < nc ? (pair_a[c0 + tid] | (pair_b[c0 + tid] << 8)) : 0;
+    __syncthreads();
+    // pairs past nc have zero K columns: whatever their product is contributes nothing
+    f32x4 ch[kMt];
+#pragma unroll
+    for (int t = 0; t < kMt; ++t) ch[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int ks = 0; ks < kMc / 4; ++ks) {
+      const int pc = 4 * ks + kq;
+      const int ab = sab[pc];
+      float b = Mt[ab & 0xff][xl] * Mt[(ab >> 8) & 0xff][xl];
+      if (LIN) b -= Vs[pc][xl];
+#pragma unroll
+      for (int t = 0; t < kMt; ++t) ch[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ks[16 * t + l16][pc], b, ch[t], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < kMt; ++t) acc[t] += ch[t];
+  }
+  const int x = x0 + xl;
+  if (x >= npix) return;
+  const float wx = w[x];
+#pragma unroll
+  for (int t = 0; t < kMt; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int u = 16 * t + 4 * kq + r;
+      if (u < P) G[((size_t)s * P + u) * npix + x] = wx * acc[t][r];
+    }
+}
+
 }  // namespace
 
 hipError_t launch_slot_matrix(const modal_ctx* c, const double* cot, int S, void* K, hipStream_t st) {
@@ -116,6 +194,14 @@ hipError_t launch_pair_adjoint(const modal_ctx* c, const void* maps, const void*
   if (is_f64(c)) {
     if (V) LAUNCH(double, true, 1, c->t.w64);
     else LAUNCH(double, false, 1, c->t.w64);
+  } else if (c->P <= kMt * 16) {
+    const dim3 grid((c->npix + kMx - 1) / kMx, S);
+    if (V)
+      hipLaunchKernelGGL(k_pair_adjoint_mfma<true>, grid, dim3(256), 0, st, c->P, c->npairs, c->npix, c->t.pair_a,
+                         c->t.pair_b, (const float*)maps, (const float*)V, c->t.w32, (const double*)K, (float*)G);
+    else
+      hipLaunchKernelGGL(k_pair_adjoint_mfma<false>, grid, dim3(256), 0, st, c->P, c->npairs, c->npix, c->t.pair_a,
+                         c->t.pair_b, (const float*)maps, (const float*)V, c->t.w32, (const double*)K, (float*)G);
   } else {
     if (V) LAUNCH(float, true, 2, c->t.w32);
     else LAUNCH(float, false, 2, c->t.w32);
