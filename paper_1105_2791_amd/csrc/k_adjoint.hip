@@ -134,20 +134,42 @@ __global__ __launch_bounds__(256) void k_pair_adjoint_mfma(int P, int npairs, in
 #pragma unroll
   for (int t = 0; t < kMt; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
   const double* Kslab = K + (size_t)s * P * npairs;
-  for (int c0 = 0; c0 < npairs; c0 += kMc) {
+  // the next chunk's K, pair means and pair modes are loaded into registers before this
+  // chunk's MFMAs, so that their latency is hidden behind them
+  constexpr int NK = kMt * 16 * kMc / 256, NV = kMc * kMx / 256;
+  double pk[NK];
+  float pv[NV];
+  int pab = 0;
+  auto load_chunk = [&](int c0) {
     const int nc = min(kMc, npairs - c0);
-    __syncthreads();
-    for (int e = tid; e < kMt * 16 * kMc; e += 256) {
-      const int u = e / kMc, pc = e - u * kMc;
-      Ks[u][pc] = (u < P && pc < nc) ? (float)Kslab[(size_t)u * npairs + c0 + pc] : 0.f;
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+      const int e = tid + 256 * i, u = e / kMc, pc = e - u * kMc;
+      pk[i] = (u < P && pc < nc) ? Kslab[(size_t)u * npairs + c0 + pc] : 0.0;
     }
-    if (LIN)
-      for (int e = tid; e < kMc * kMx; e += 256) {
-        const int pc = e / kMx, xx = e - pc * kMx;
-        Vs[pc][xx] = (pc < nc && x0 + xx < npix) ? V[(size_t)(c0 + pc) * npix + x0 + xx] : 0.f;
-      }
-    if (tid < kMc) sab[tid] = tid < nc ? (pair_a[c0 + tid] | (pair_b[c0 + tid] << 8)) : 0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int e = tid + 256 * i, pc = e / kMx, xx = e - pc * kMx;
+      pv[i] = (LIN && pc < nc && x0 + xx < npix) ? V[(size_t)(c0 + pc) * npix + x0 + xx] : 0.f;
+    }
+    if (tid < kMc) pab = tid < nc ? (pair_a[c0 + tid] | (pair_b[c0 + tid] << 8)) : 0;
+  };
+  load_chunk(0);
+  for (int c0 = 0; c0 < npairs; c0 += kMc) {
     __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+      const int e = tid + 256 * i, u = e / kMc, pc = e - u * kMc;
+      Ks[u][pc] = (float)pk[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int e = tid + 256 * i, pc = e / kMx, xx = e - pc * kMx;
+      Vs[pc][xx] = pv[i];
+    }
+    if (tid < kMc) sab[tid] = pab;
+    __syncthreads();
+    if (c0 + kMc < npairs) load_chunk(c0 + kMc);
     // pairs past nc have zero K columns: whatever their product is contributes nothing
     f32x4 ch[kMt];
 #pragma unroll
