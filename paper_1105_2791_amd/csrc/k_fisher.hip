@@ -39,9 +39,10 @@ __global__ __launch_bounds__(256) void k_pair_maps(int npairs, int npix, const i
 }
 
 // Z[col][lm] = c_m sum_j lambda_lm(theta_j) (Gh_N +- Gh_S)(col, m), one thread per l,
-// NC columns per thread, ring values staged in LDS.
+// NC columns per thread; the ring values are staged in LDS already folded, Gh_N + Gh_S
+// and Gh_N - Gh_S in FP64, so that each thread reads the one its parity of l - m needs.
 constexpr int NC = 16;
-constexpr int RCH = 64;
+constexpr int RCH = 32;
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_adj_legendre_cols(int lmax, int ntheta, int nrp, int ncol, int nalm,
@@ -55,8 +56,8 @@ __global__ __launch_bounds__(64) void k_adj_legendre_cols(int lmax, int ntheta, 
   const int c0 = blockIdx.z * NC;
   const size_t off = (size_t)m * (2 * lmax + 3 - m) / 2;
   const T* lrow = lam + off * nrp;
-  __shared__ T2 hn[RCH][NC];
-  __shared__ T2 hs[RCH][NC];
+  __shared__ double2 hp[RCH][NC];   // Gh_N + Gh_S (even l - m)
+  __shared__ double2 hm[RCH][NC];   // Gh_N - Gh_S (odd l - m)
   double ar[NC], ai[NC];
 #pragma unroll
   for (int q = 0; q < NC; ++q) ar[q] = ai[q] = 0.0;
@@ -75,20 +76,19 @@ __global__ __launch_bounds__(64) void k_adj_legendre_cols(int lmax, int ntheta, 
         const int js = ntheta - 1 - j;
         if (js != j) vs = g[js];
       }
-      hn[jj][q] = vn;
-      hs[jj][q] = vs;
+      hp[jj][q] = make_double2((double)vn.x + (double)vs.x, (double)vn.y + (double)vs.y);
+      hm[jj][q] = make_double2((double)vn.x - (double)vs.x, (double)vn.y - (double)vs.y);
     }
     __syncthreads();
     if (li < L) {
+      const double2(*h)[NC] = odd ? hm : hp;
       for (int jj = 0; jj < nj; ++jj) {
         const double lv = (double)lrow[(size_t)(j0 + jj) * L + li];
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
-          const T2 n = hn[jj][q], s = hs[jj][q];
-          const double hr = odd ? (double)n.x - (double)s.x : (double)n.x + (double)s.x;
-          const double hi = odd ? (double)n.y - (double)s.y : (double)n.y + (double)s.y;
-          ar[q] += lv * hr;
-          ai[q] += lv * hi;
+          const double2 v = h[jj][q];
+          ar[q] += lv * v.x;
+          ai[q] += lv * v.y;
         }
       }
     }
