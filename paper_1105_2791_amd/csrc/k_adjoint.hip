@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void k_pair_adjoint(int P, int npairs, int npi
 // in LDS), B = the pair product of the lane's pixel and pair, formed on the fly.  Each
 // chunk is a chain of 16 MFMAs from zero, added to the running sums with a vector add.
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
-constexpr int kMx = 64;   // pixels per workgroup (16 per wave)
+constexpr int kMx = 128;  // pixels per workgroup (32 per wave: two 16-column tiles)
 constexpr int kMc = 64;   // pairs per staged chunk (16 MFMA steps of 4)
 constexpr int kMt = 3;    // 16-mode tiles (P <= 48)
 
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void k_pair_adjoint_mfma(int P, int npairs, in
   const int s = blockIdx.y, x0 = blockIdx.x * kMx;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int l16 = lane & 15, kq = lane >> 4;
-  const int xl = wv * 16 + l16;   // this lane's pixel within the block
+  const int xl0 = wv * 32 + l16, xl1 = xl0 + 16;   // this lane's pixels within the block
   __shared__ float Mt[kMaxP][kMx];
   __shared__ float Ks[kMt * 16][kMc + 1];
   __shared__ float Vs[kMc][kMx];
@@ -130,9 +130,11 @@ __global__ __launch_bounds__(256) void k_pair_adjoint_mfma(int P, int npairs, in
     const int p = e / kMx, xx = e - p * kMx;
     Mt[p][xx] = x0 + xx < npix ? Ms[(size_t)p * npix + x0 + xx] : 0.f;
   }
-  f32x4 acc[kMt];
+  f32x4 acc[2][kMt];
 #pragma unroll
-  for (int t = 0; t < kMt; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int t = 0; t < kMt; ++t) acc[c][t] = f32x4{0.f, 0.f, 0.f, 0.f};
   const double* Kslab = K + (size_t)s * P * npairs;
   // the next chunk's K, pair means and pair modes are loaded into registers before this
   // chunk's MFMAs, so that their latency is hidden behind them
@@ -171,31 +173,45 @@ __global__ __launch_bounds__(256) void k_pair_adjoint_mfma(int P, int npairs, in
     __syncthreads();
     if (c0 + kMc < npairs) load_chunk(c0 + kMc);
     // pairs past nc have zero K columns: whatever their product is contributes nothing
-    f32x4 ch[kMt];
+    f32x4 ch[2][kMt];
 #pragma unroll
-    for (int t = 0; t < kMt; ++t) ch[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int t = 0; t < kMt; ++t) ch[c][t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 4
     for (int ks = 0; ks < kMc / 4; ++ks) {
       const int pc = 4 * ks + kq;
-      const int ab = sab[pc];
-      float b = Mt[ab & 0xff][xl] * Mt[(ab >> 8) & 0xff][xl];
-      if (LIN) b -= Vs[pc][xl];
+      const int ab = sab[pc], a = ab & 0xff, b2 = (ab >> 8) & 0xff;
+      float b0 = Mt[a][xl0] * Mt[b2][xl0], b1 = Mt[a][xl1] * Mt[b2][xl1];
+      if (LIN) {
+        b0 -= Vs[pc][xl0];
+        b1 -= Vs[pc][xl1];
+      }
 #pragma unroll
-      for (int t = 0; t < kMt; ++t) ch[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ks[16 * t + l16][pc], b, ch[t], 0, 0, 0);
+      for (int t = 0; t < kMt; ++t) {
+        const float av = Ks[16 * t + l16][pc];
+        ch[0][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b0, ch[0][t], 0, 0, 0);
+        ch[1][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b1, ch[1][t], 0, 0, 0);
+      }
     }
 #pragma unroll
-    for (int t = 0; t < kMt; ++t) acc[t] += ch[t];
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int t = 0; t < kMt; ++t) acc[c][t] += ch[c][t];
   }
-  const int x = x0 + xl;
-  if (x >= npix) return;
-  const float wx = w[x];
 #pragma unroll
-  for (int t = 0; t < kMt; ++t)
+  for (int c = 0; c < 2; ++c) {
+    const int x = x0 + (c ? xl1 : xl0);
+    if (x >= npix) continue;
+    const float wx = w[x];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int u = 16 * t + 4 * kq + r;
-      if (u < P) G[((size_t)s * P + u) * npix + x] = wx * acc[t][r];
-    }
+    for (int t = 0; t < kMt; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int u = 16 * t + 4 * kq + r;
+        if (u < P) G[((size_t)s * P + u) * npix + x] = wx * acc[c][t][r];
+      }
+  }
 }
 
 }  // namespace
