@@ -392,9 +392,8 @@ modal_status modal_autotune(modal_ctx* ctx, const void* alm_dev, int S, const vo
 
 typedef struct modal_graph modal_graph;
 
-/* Capture a sequence of modal_beta calls into one HIP graph (north-star
- * batching: many Monte-Carlo maps, possibly of different l_max, replayed with
- * one launch).  Call i uses ctxs[i], alms[i] ([S[i]][nalm_i] device),
+/* Capture a sequence of modal_beta calls into one HIP graph (batching: many
+ * Monte-Carlo maps, possibly of different l_max, replayed with one launch).  Call i uses ctxs[i], alms[i] ([S[i]][nalm_i] device),
  * states[i] (finalised or NULL), betas[i] ([S[i]][nmax_i] device) and its own
  * workspace ws[i] of ws_bytes[i] bytes; contexts must live on one device.
  * Arguments are validated exactly as modal_beta does; the pointers are baked
