@@ -494,8 +494,16 @@ def run_estimator(args):
     # adjoint Legendre (the synthesis transposed) + the cotangent contraction over the
     # triples (the cubic's count); the r2c FFT is HBM work on top
     flop = 2.0 * ctx.nalm * nt * P * S + 2.0 * n * nt * nphi * S
+    # stage times of one more call from the library's own events
+    ctx.profile_read(reset=True)
+    ctx.profile(True)
+    ctx.beta_vjp(alm, cot, st)
+    torch.cuda.synchronize()
+    ctx.profile(False)
+    vst = {k: v[0] for k, v in ctx.profile_read(reset=True).items() if v[1] > 0}
     items["vjp"] = {"row": "A9", "shape": f"lmax={lmax} GL {nt}x{nphi} P={P} S={S} {prec}, with the linear-term state",
-                    "ms": t, "gradients_per_s": S / (t * 1e-3), "roofline": _roof(flop, t, "mfma", mpeak)}
+                    "ms": t, "gradients_per_s": S / (t * 1e-3), "stages_ms": vst,
+                    "roofline": _roof(flop, t, "mfma", mpeak)}
     N = 200
     B = torch.as_tensor(rng.standard_normal((N, n)), device="cuda")
     log("estimator: sample covariance")
