@@ -213,6 +213,22 @@ modal_status modal_filter_maps(modal_ctx* ctx, const void* alm_dev, int S, void*
  * context, so a state is tied to the context that built it.
  * Errors: EINVAL, ENOTREADY (APPLY before FINALIZE, FINALIZE with count 0),
  * ENOSPACE, EDEVICE. */
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): modal_beta with its
+ * workspace taken from a fixed device array inside the library instead of a
+ * caller buffer.  The array holds MODAL_NOALLOC_SCRATCH_BYTES (64 MiB) on every
+ * GPU the library runs on, until the process ends; the call allocates nothing.
+ * Arguments, results and errors are those of modal_beta (same kernels, same
+ * results), plus ENOSPACE when modal_workspace_size(MODAL_OP_BETA, S) exceeds
+ * the array (small shapes only: for instance lmax 150 on 199 x 400 rings, P 13,
+ * S 3 needs about 25 MB; full-resolution shapes need modal_beta).  Nothing in
+ * the array has to start at zero.  All calls on one GPU share its array: calls
+ * that overlap on one GPU (two streams, two host threads, graphs replayed
+ * concurrently) race and must be serialised by the caller. */
+#define MODAL_NOALLOC_SCRATCH_BYTES (64u << 20)
+modal_status modal_beta_noalloc(modal_ctx* ctx, const void* alm_dev, int S, const void* state_dev,
+                                double* beta_dev, modal_stream_t stream);
+
 modal_status modal_linear_term(modal_ctx* ctx, int mode, const void* alm_dev, int S, void* state_dev,
                                double* lin_dev, void* ws_dev, size_t ws_bytes, modal_stream_t stream);
 

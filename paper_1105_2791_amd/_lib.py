@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libmodal.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "modal.h")
 
 OK, EINVAL, ESHAPE, EDEVICE, ENOTPD, ENOTREADY, EUNSUPPORTED, ENOSPACE = range(8)
+NOALLOC_SCRATCH_BYTES = 64 << 20   # MODAL_NOALLOC_SCRATCH_BYTES
 F64, F32, BF16X3, F16X3 = range(4)
 OP_FILTER_MAPS, OP_BETA, OP_LINEAR_ACCUMULATE, OP_LINEAR_APPLY, OP_BETA_VJP, \
     OP_COVARIANCE_SAMPLE, OP_COVARIANCE_FISHER, OP_FNL, OP_LINEAR_FINALIZE, OP_NOISE_VECTORS, OP_FNL_LOWRANK, \
@@ -54,6 +55,7 @@ _SIGS = {
     "modal_filter_maps": (ip, [vp, vp, ip, vp, vp, sz, vp]),
     "modal_linear_term": (ip, [vp, ip, vp, ip, vp, vp, vp, sz, vp]),
     "modal_beta": (ip, [vp, vp, ip, vp, vp, vp, sz, vp]),
+    "modal_beta_noalloc": (ip, [vp, vp, ip, vp, vp, vp]),
     "modal_beta_vjp": (ip, [vp, vp, ip, vp, vp, vp, vp, sz, vp]),
     "modal_covariance": (ip, [vp, ip, vp, vp, vp, vp, ip, vp, vp, sz, vp]),
     "modal_fnl": (ip, [vp, vp, vp, vp, ip, vp, vp, vp, vp, sz, vp]),

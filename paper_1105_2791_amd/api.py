@@ -134,6 +134,15 @@ class ModalContext:
                                          self._stream()))
         return out
 
+    def beta_noalloc(self, alm, state=None, out=None) -> torch.Tensor:
+        """modal_beta_noalloc: beta with the library's fixed device scratch as workspace."""
+        a = self._alm(alm)
+        S = a.shape[0]
+        if out is None:
+            out = torch.empty((S, self.nmax), dtype=torch.float64, device=self.device)
+        self._check(self._lib.modal_beta_noalloc(self._h, _ptr(a), S, _ptr(state), _ptr(out), self._stream()))
+        return out
+
     def autotune(self, alm, state=None) -> dict:
         """Pick the fastest launch configuration for modal_beta on these inputs."""
         a = self._alm(alm)

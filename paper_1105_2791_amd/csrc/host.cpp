@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -16,6 +17,36 @@
 namespace modal {
 hipError_t fft_set_lds_limit(size_t bytes);
 }  // namespace modal
+
+// Workspace of modal_beta_noalloc: a fixed device array (one copy per GPU, alive until
+// the process ends).  In host code the symbol is only a stand-in, never a device
+// address: its address on each device comes from hipGetSymbolAddress, resolved once
+// per device with that device current (modal_create), and only that address is used.
+static __device__ __align__(256) unsigned char scratch[MODAL_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of the scratch array (resolved on first use).
+hipError_t scratch_resolve(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[dev] = p;
+  return hipSuccess;
+}
+
+void* scratch_ptr(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[dev];
+}
+}  // namespace
 
 using namespace modal;
 
@@ -326,6 +357,7 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
   };
   if ((prec == MODAL_BF16X3 || prec == MODAL_F16X3) && !cubic_mfma_available(c)) return bail(MODAL_EUNSUPPORTED);
   if (hipGetDevice(&c->device) != hipSuccess) return bail(MODAL_EDEVICE);
+  if (scratch_resolve(c->device) != hipSuccess) return bail(MODAL_EDEVICE);
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess && lds > 0)
     c->max_lds = (size_t)lds;
@@ -602,6 +634,29 @@ modal_status modal_beta(modal_ctx* c, const void* alm, int S, const void* state,
   double* L = (double*)cv.take(E_bytes(c, S));
   if ((s = run_maps(c, alm, S, F, maps, st)) != MODAL_OK) return s;
   return run_beta(c, maps, alm, state, S, part, E, X, L, beta, st);
+}
+
+modal_status modal_beta_noalloc(modal_ctx* c, const void* alm, int S, const void* state, double* beta,
+                                modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (!alm || !beta || S <= 0) return fail(c, MODAL_EINVAL, "beta_noalloc: null pointer or S <= 0");
+  modal_status s = check_state(c, state);
+  if (s != MODAL_OK) return s;
+  const size_t need = ws_size(c, MODAL_OP_BETA, S);
+  if (need > (size_t)MODAL_NOALLOC_SCRATCH_BYTES)
+    return fail(c, MODAL_ENOSPACE, "beta_noalloc: these shapes need " + std::to_string(need) +
+                                       " bytes of workspace, the fixed scratch holds " +
+                                       std::to_string((size_t)MODAL_NOALLOC_SCRATCH_BYTES) +
+                                       " (call modal_beta with a caller workspace)");
+  if ((s = set_device(c)) != MODAL_OK) return s;
+  void* ws = scratch_ptr(c->device);
+  if (!ws) return fail(c, MODAL_EDEVICE, "beta_noalloc: scratch address not resolved on this device");
+  // stage timing would create events; it stays off for this call
+  const bool prof = c->profile;
+  c->profile = false;
+  s = modal_beta(c, alm, S, state, beta, ws, (size_t)MODAL_NOALLOC_SCRATCH_BYTES, stream);
+  c->profile = prof;
+  return s;
 }
 
 modal_status modal_linear_term(modal_ctx* c, int mode, const void* alm, int S, void* state, double* lin, void* ws,
