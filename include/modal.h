@@ -380,13 +380,14 @@ modal_status modal_power_fnl(modal_ctx* ctx, const double* zeta_dev, const doubl
  * with V the Monte-Carlo pair means of a finalised linear-term state (state_dev NULL:
  * V = 0, the plain quartic sums).  Computed as the pairs x pairs symmetric update
  * K = sum_x w A A^T - 6 sum_x w V V^T, A_ab = M_a M_b - 3 V_ab, tau = the mean of K over the
- * three pairings; split-bf16 matrix cores for float contexts (all three float precisions),
- * FP64 for MODAL_F64 (a reference path without pixel chunking).
+ * three pairings; split-bf16 matrix cores for MODAL_BF16X3 and MODAL_F16X3 contexts,
+ * FP64 for MODAL_F64 (a reference path without pixel chunking).  MODAL_F32 contexts get
+ * EUNSUPPORTED: there is no FP32 update, and a split one would not keep the FP32 bound.
  *   tau_dev [S][nquad] float64.  Workspace: modal_workspace_size(MODAL_OP_TRISPECTRUM, S);
  * for float contexts it includes pixel-block-major copies of the pair means (npairs x
  * npix floats, rounded up to 32-pixel blocks; with a state) and of the S skies' maps,
  * made at each call.
- * Errors: EINVAL, ENOTREADY, ENOSPACE, EDEVICE. */
+ * Errors: EINVAL, ENOTREADY, ENOSPACE, EUNSUPPORTED (MODAL_F32), EDEVICE. */
 modal_status modal_trispectrum(modal_ctx* ctx, const void* alm_dev, int S, const void* state_dev, double* tau_dev,
                                void* ws_dev, size_t ws_bytes, modal_stream_t stream);
 int modal_nquad(const modal_ctx* ctx);

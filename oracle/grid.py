@@ -37,3 +37,26 @@ class Grid:
     @property
     def npix(self) -> int:
         return self.ntheta * self.nphi
+
+
+class RingSubset:
+    """The rings ``idx`` of a grid (same nodes, same nphi, same weights): the pixel sums of
+    the estimator split over rings, since sum_x = sum over ring groups of sum over their
+    pixels."""
+
+    def __init__(self, grid: Grid, idx):
+        idx = np.asarray(idx, dtype=np.int64)
+        self.idx = idx
+        self.ntheta = int(idx.size)
+        self.nphi = grid.nphi
+        self.x = grid.x[idx]
+        self.wgl = grid.wgl[idx]
+        self.theta = grid.theta[idx]
+        self.phi = grid.phi
+        self.mask = grid.mask[idx]
+        self.area = grid.area[idx]
+        self.w = grid.w[idx]
+
+    @property
+    def npix(self) -> int:
+        return self.ntheta * self.nphi

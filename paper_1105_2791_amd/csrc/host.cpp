@@ -875,6 +875,10 @@ modal_status modal_trispectrum(modal_ctx* c, const void* alm, int S, const void*
                                size_t ws_bytes, modal_stream_t stream) {
   if (!c) return MODAL_EINVAL;
   if (!alm || !tau || S <= 0) return fail(c, MODAL_EINVAL, "trispectrum: null pointer or S <= 0");
+  if (c->prec == MODAL_F32)
+    return fail(c, MODAL_EUNSUPPORTED,
+                "trispectrum: no FP32 update (the float update is split-bf16 or split-fp16); use a MODAL_F64, "
+                "MODAL_BF16X3 or MODAL_F16X3 context");
   modal_status s = check_state(c, state);
   if (s != MODAL_OK) return s;
   if ((s = check_ws(c, MODAL_OP_TRISPECTRUM, S, ws, ws_bytes)) != MODAL_OK) return s;

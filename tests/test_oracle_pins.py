@@ -349,3 +349,28 @@ def test_p9_pair_mean_fullsky_matches_parseval_expectation():
     l = np.arange(lmax + 1)
     alt = np.array([np.sum(q[p] * q[r] * (2 * l + 1) * c) / (4 * math.pi) for p, r in mi.pair_list(P)])
     assert np.max(np.abs(ref - alt)) < 1e-14
+
+
+def test_ring_chunked_beta_and_linear_term_equal_whole_grid():
+    """beta and lin are pixel sums and V a per-pixel mean, so summing the definitions over
+    ring groups (7 rings, a ragged last group, a masked grid) gives the whole-grid values."""
+    import modal_inputs as mi
+    from oracle import grid as og
+    from oracle import modal as om
+    lmax, nt, nphi, P = 16, 25, 50, 5
+    g0 = og.Grid(nt, nphi)
+    g = og.Grid(nt, nphi, ring_mask=np.repeat(mi.mask_rings(g0.theta)[:, None], nphi, 1))
+    cl = mi.filter_cl(lmax, "wmap")
+    q = mi.q_basis(P, lmax)
+    alms = np.array([mi.gaussian_alm(cl, lmax, mi.rng_for(77, i)) for i in range(2)])
+    mc = np.array([mi.gaussian_alm(cl, lmax, mi.rng_for(77, 10 + i)) for i in range(3)])
+    b, lin = om.beta_and_linear_by_rings(alms, mc, cl, q, g, rings_per_chunk=7)
+    M = om.filtered_maps(alms, cl, q, g)
+    V = om.pair_means(om.filtered_maps(mc, cl, q, g))
+    for s in range(2):
+        ref_b = om.beta(M[s], g.w)
+        ref_l = om.linear_term(M[s], g.w, V)
+        assert np.max(np.abs(b[s] - ref_b)) < 1e-12 * np.sqrt(np.mean(ref_b ** 2))
+        assert np.max(np.abs(lin[s] - ref_l)) < 1e-12 * np.sqrt(np.mean(ref_l ** 2))
+    b2, none = om.beta_and_linear_by_rings(alms, None, cl, q, g, rings_per_chunk=25)
+    assert none is None and np.allclose(b2, b, rtol=0, atol=1e-12 * np.abs(b).max())
