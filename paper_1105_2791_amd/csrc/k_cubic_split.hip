@@ -20,11 +20,20 @@
 //     buffered, with the next step's global loads issued before this step's MFMAs
 //     (a step is long enough to cover the load latency).
 // Precisions
-//   BF16X3: hi = RNE bf16, lo = RNE bf16 of the residual; Ah Bh + Ah Bl + Al Bh.
-//   F16X3 : maps scaled by exact powers of two (s_p ~ 1/sigma_p, s_w ~ npix/4pi);
-//           hi = f16(a b) and lo = f16(a b - hi) each from one fused mixed-precision
-//           FMA of the two map values (the residual is exact before its rounding),
-//           which costs two vector instructions per pair product.
+//   BF16X3: maps staged in FP32; A = M_a M_b in FP32 split as hi = RNE bf16, lo = RNE bf16
+//           of the exact residual; Ah Bh + Ah Bl + Al Bh.
+//   F16X3 : maps scaled by exact powers of two (s_p ~ 1/sigma_p, s_w ~ npix/4pi) and staged
+//           as fp16 pairs m = h + l (h = f16(m), l = f16(m - h)).  A pair product is formed
+//           with packed fp16 arithmetic, two pixels per instruction:
+//             H = h_a h_b (rounded), r = fma(h_a, h_b, -H) (exact: the residual of a 22-bit
+//             product fits in fp16), L = fma(l_a, h_b, fma(h_a, l_b, r)),
+//           so A = H + L carries about 21 bits (the l_a l_b term, 2^-22, is dropped): four
+//           packed instructions per two products.
+// For F16X3 the substeps of 16 pixels are software-pipelined: the next substep's map rows
+// are read and its pair products split while this substep's MFMAs run, so that the vector
+// work issues between matrix-core instructions instead of after them (8.7 -> 8.0 ms per
+// 8-sky batch at l_max 1000, P 40 with the packed products; the same order made the bf16
+// split, twice the vector work, 3% slower, so bf16 keeps split-then-MFMA per substep).
 // The matrix core drops addend bits below the largest term of an accumulation, which
 // against a long running sum biases every step; so the MFMAs accumulate a short
 // chain of CHAIN staged steps from zero, and each chain joins the running FP32 sum
@@ -91,21 +100,29 @@ __device__ inline void split_bf16(const float* x, const float* y, bf16x8& hi, bf
   lo = __builtin_bit_cast(bf16x8, l);
 }
 
-// fp16 hi/lo of the products x[k] y[k]: hi = f16(x y), lo = f16(x y - hi), both
-// from fused mixed-precision FMAs (inputs FP32, result written to one half).
-__device__ inline void split_f16(const float* x, const float* y, f16x8& hi, f16x8& lo) {
+typedef __attribute__((__vector_size__(2 * sizeof(_Float16)))) _Float16 f16x2;
+
+// fp16 hi/lo of the products (ha + la)(hb + lb) of eight pixels, two per packed instruction
+__device__ inline void prod_f16(const u32x4& ha, const u32x4& la, const u32x4& hb, const u32x4& lb, f16x8& hi,
+                                f16x8& lo) {
   u32x4 h, l;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    uint32_t hh, ll;
-    asm("v_fma_mixlo_f16 %0, %2, %3, 0\n\t"
-        "v_fma_mixhi_f16 %0, %4, %5, 0\n\t"
-        "v_fma_mixlo_f16 %1, %2, %3, -%0 op_sel_hi:[0,0,1]\n\t"
-        "v_fma_mixhi_f16 %1, %4, %5, -%0 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
-        : "=&v"(hh), "=&v"(ll)
-        : "v"(x[2 * k]), "v"(y[2 * k]), "v"(x[2 * k + 1]), "v"(y[2 * k + 1]));
-    h[k] = hh;
-    l[k] = ll;
+    // vector elements go through scalars first: a bit_cast of the element itself is dropped
+    // by the compiler
+    const uint32_t wa = ha[k], va = la[k], wb = hb[k], vb = lb[k];
+    const f16x2 xa = __builtin_bit_cast(f16x2, wa), ya = __builtin_bit_cast(f16x2, va);
+    const f16x2 xb = __builtin_bit_cast(f16x2, wb), yb = __builtin_bit_cast(f16x2, vb);
+    f16x2 H = xa * xb;
+    uint32_t Hb = __builtin_bit_cast(uint32_t, H);
+    asm("" : "+v"(Hb));   // H is one rounded product, used as is below
+    H = __builtin_bit_cast(f16x2, Hb);
+    f16x2 r = __builtin_elementwise_fma(xa, xb, -H);
+    r = __builtin_elementwise_fma(xa, yb, r);
+    r = __builtin_elementwise_fma(ya, xb, r);
+    const uint32_t rb = __builtin_bit_cast(uint32_t, r);
+    h[k] = Hb;
+    l[k] = rb;
   }
   hi = __builtin_bit_cast(f16x8, h);
   lo = __builtin_bit_cast(f16x8, l);
@@ -128,6 +145,15 @@ __device__ inline void split_pair(float v0, float v1, uint32_t& hi, uint32_t& lo
     hi = hb;
     lo = bf16x2_bits(v0 - __builtin_bit_cast(float, hb << 16), v1 - __builtin_bit_cast(float, hb & 0xffff0000u));
   }
+}
+
+template <int PREC, typename V>
+__device__ inline f32x16 mfma32(const V& a, const V& b, const f32x16& c) {
+  if constexpr (PREC == MODAL_F16X3)
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0, 0,
+                                                   0);
 }
 
 template <int PREC>
@@ -235,9 +261,17 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
       if (t < P) {
         const float m = msc[t];
         const float sc = F16 ? m * wscale : 1.f;
-        *reinterpret_cast<float4*>(&L.ms[st][ms_slot(t)][sq4]) =
-            make_float4(pre[i].x * m, pre[i].y * m, pre[i].z * m, pre[i].w * m);
         uint32_t h0, l0, h1, l1;
+        if (F16) {
+          // the row as halves: hi words at [0, KS), lo words at [KS, 2 KS)
+          uint16_t* row = reinterpret_cast<uint16_t*>(&L.ms[st][ms_slot(t)][0]);
+          split_pair<PREC>(pre[i].x * m, pre[i].y * m, h0, l0);
+          split_pair<PREC>(pre[i].z * m, pre[i].w * m, h1, l1);
+          *reinterpret_cast<uint2*>(row + sq4) = make_uint2(h0, h1);
+          *reinterpret_cast<uint2*>(row + KS + sq4) = make_uint2(l0, l1);
+        } else {
+          *reinterpret_cast<float4*>(&L.ms[st][ms_slot(t)][sq4]) = pre[i];
+        }
         split_pair<PREC>(wpre.x * sc * pre[i].x, wpre.y * sc * pre[i].y, h0, l0);
         split_pair<PREC>(wpre.z * sc * pre[i].z, wpre.w * sc * pre[i].w, h1, l1);
         *reinterpret_cast<uint2*>(&L.bh[st][BROWS - P + t][sq4]) = make_uint2(h0, h1);
@@ -262,56 +296,88 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
     const bool more = x0 + KS < x_end;
     if (more) load_step(x0 + KS);
     if (wave_on) {
+      // The lane's four map rows at its 8 pixels of substep ks (F16X3: fp16 hi and lo words;
+      // BF16X3: FP32 values), and the split pair product of tile j = (a row j / 2, b row j % 2).
+      struct Rows {
+        u32x4 h[4], l[4];   // F16X3
+        float v[4][8];      // BF16X3
+      };
+      auto load_rows = [&](int ks, Rows& R) {
+        if constexpr (F16) {
+          const uint16_t* rows = reinterpret_cast<const uint16_t*>(&L.ms[st][0][0]);
+          // row offsets in halves: the slot's row start doubles (two halves per float of the
+          // row), the lane's pixel offset 8 kh does not (one half per pixel)
+          const int o[4] = {2 * oa[0] - 8 * kh, 2 * oa[1] - 8 * kh, 2 * ob_[0] - 8 * kh, 2 * ob_[1] - 8 * kh};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            R.h[u] = *reinterpret_cast<const u32x4*>(rows + o[u] + 16 * ks);
+            R.l[u] = *reinterpret_cast<const u32x4*>(rows + o[u] + KS + 16 * ks);
+          }
+        } else {
+          const float* msb = &L.ms[st][0][0] + 16 * ks;
+          const int o[4] = {oa[0], oa[1], ob_[0], ob_[1]};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float4 lo4 = reinterpret_cast<const float4*>(msb + o[u])[0];
+            const float4 hi4 = reinterpret_cast<const float4*>(msb + o[u])[1];
+            R.v[u][0] = lo4.x; R.v[u][1] = lo4.y; R.v[u][2] = lo4.z; R.v[u][3] = lo4.w;
+            R.v[u][4] = hi4.x; R.v[u][5] = hi4.y; R.v[u][6] = hi4.z; R.v[u][7] = hi4.w;
+          }
+        }
+      };
+      auto split_tile = [&](const Rows& R, int j, vec8& ah, vec8& al) {
+        if constexpr (F16)
+          prod_f16(R.h[j >> 1], R.l[j >> 1], R.h[2 + (j & 1)], R.l[2 + (j & 1)], *reinterpret_cast<f16x8*>(&ah),
+                   *reinterpret_cast<f16x8*>(&al));
+        else
+          split_bf16(R.v[j >> 1], R.v[2 + (j & 1)], *reinterpret_cast<bf16x8*>(&ah), *reinterpret_cast<bf16x8*>(&al));
+      };
+      if constexpr (!F16) {
+        // bf16: per substep, all four tiles' operands first, then the MFMAs product by product,
+        // so that consecutive MFMAs feed different accumulators (measured faster than the
+        // pipelined order for bf16, whose split is twice the vector work of the fp16 one)
+#pragma unroll
+        for (int ks = 0; ks < KS / 16; ++ks) {
+          const int kx = 16 * ks + 8 * kh;
+          const vec8 bh = *reinterpret_cast<const vec8*>(&L.bh[st][brow][kx]);
+          const vec8 bl = *reinterpret_cast<const vec8*>(&L.bl[st][brow][kx]);
+          Rows R;
+          load_rows(ks, R);
+          vec8 ah[4], al[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) split_tile(R, j, ah[j], al[j]);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) cha[j] = mfma32<PREC>(al[j], bh, cha[j]);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) cha[j] = mfma32<PREC>(ah[j], bl, cha[j]);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) cha[j] = mfma32<PREC>(ah[j], bh, cha[j]);
+        }
+      } else {
+      vec8 ah[4], al[4];
+      {
+        Rows R0;
+        load_rows(0, R0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) split_tile(R0, j, ah[j], al[j]);
+      }
 #pragma unroll
       for (int ks = 0; ks < KS / 16; ++ks) {
         const int kx = 16 * ks + 8 * kh;
-        const float* msb = &L.ms[st][0][0] + 16 * ks;
-        // the four map rows of this lane's block at its 8 pixels
-        float ma[2][8], mb[2][8];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const float4* pa = reinterpret_cast<const float4*>(msb + oa[u]);
-          const float4* pb = reinterpret_cast<const float4*>(msb + ob_[u]);
-          const float4 a_lo = pa[0], a_hi = pa[1], b_lo = pb[0], b_hi = pb[1];
-          ma[u][0] = a_lo.x; ma[u][1] = a_lo.y; ma[u][2] = a_lo.z; ma[u][3] = a_lo.w;
-          ma[u][4] = a_hi.x; ma[u][5] = a_hi.y; ma[u][6] = a_hi.z; ma[u][7] = a_hi.w;
-          mb[u][0] = b_lo.x; mb[u][1] = b_lo.y; mb[u][2] = b_lo.z; mb[u][3] = b_lo.w;
-          mb[u][4] = b_hi.x; mb[u][5] = b_hi.y; mb[u][6] = b_hi.z; mb[u][7] = b_hi.w;
-        }
         const vec8 bh = *reinterpret_cast<const vec8*>(&L.bh[st][brow][kx]);
         const vec8 bl = *reinterpret_cast<const vec8*>(&L.bl[st][brow][kx]);
-        if (!F16) {
-          // bf16: all four tiles' operands first, then the MFMAs product by product, so
-          // that consecutive MFMAs feed different accumulators (no dependent chain stalls
-          // the in-order issue behind them)
-          bf16x8 ahv[4], alv[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) split_bf16(ma[j >> 1], mb[j & 1], ahv[j], alv[j]);
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            cha[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alv[j], *reinterpret_cast<const bf16x8*>(&bh), cha[j], 0, 0, 0);
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            cha[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahv[j], *reinterpret_cast<const bf16x8*>(&bl), cha[j], 0, 0, 0);
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            cha[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahv[j], *reinterpret_cast<const bf16x8*>(&bh), cha[j], 0, 0, 0);
-        } else
+        Rows Rn;
+        if (ks + 1 < KS / 16) load_rows(ks + 1, Rn);
+        // tile by tile: its three products, then the next substep's split of the same tile
+        // into the registers they have just read (issued among the following MFMAs)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          vec8 ah, al;
-          if (F16) split_f16(ma[j >> 1], mb[j & 1], *reinterpret_cast<f16x8*>(&ah), *reinterpret_cast<f16x8*>(&al));
-          else split_bf16(ma[j >> 1], mb[j & 1], *reinterpret_cast<bf16x8*>(&ah), *reinterpret_cast<bf16x8*>(&al));
-          if (F16) {
-            cha[j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, cha[j], 0, 0, 0);
-            cha[j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, cha[j], 0, 0, 0);
-            cha[j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, cha[j], 0, 0, 0);
-          } else {
-            cha[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, cha[j], 0, 0, 0);
-            cha[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, cha[j], 0, 0, 0);
-            cha[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, cha[j], 0, 0, 0);
-          }
+          cha[j] = mfma32<PREC>(al[j], bh, cha[j]);
+          cha[j] = mfma32<PREC>(ah[j], bl, cha[j]);
+          cha[j] = mfma32<PREC>(ah[j], bh, cha[j]);
+          if (ks + 1 < KS / 16) split_tile(Rn, j, ah[j], al[j]);
         }
+      }
       }
       if (++link == CHAIN || !more) {   // wave-uniform
         link = 0;
