@@ -32,11 +32,73 @@ __device__ inline T2 cmul(T2 a, T2 b) {
   return r;
 }
 
+// One Stockham stage of an odd prime radix R known at compile time, float data.  Each
+// butterfly's R inputs are twiddled once into registers (stage twiddle index kept
+// incrementally, no division), then the R-point DFT pairs r with R - r:
+//   out_q = a_0 + sum_{j=1}^{(R-1)/2} [(a_j + a_{R-j}) Re w^{jq} + i (a_j - a_{R-j}) Im w^{jq}],
+// w = exp(sign 2 pi i / R), whose powers are held in registers (the indices j q mod R are
+// compile-time).  R^2 / 2 complex multiply-adds per butterfly, no LDS re-reads.
+template <typename T2, int SIGN, int R>
+__device__ inline void prime_stage(const T2* __restrict__ in, T2* __restrict__ out, int K, int Ns,
+                                   const T2* __restrict__ tw) {
+  constexpr int H = (R - 1) / 2;
+  const int KR = K / R;
+  const int step = K / (Ns * R);
+  T2 wr[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    wr[m] = tw[2 * m * KR];                 // exp(2 pi i m / R) = exp(2 pi i m KR / K)
+    if (SIGN < 0) wr[m].y = -wr[m].y;
+  }
+  for (int b = threadIdx.x; b < KR; b += blockDim.x) {
+    const int k = b % Ns;
+    const int obase = (b / Ns) * Ns * R + k;
+    const int dt = k * step;                // < K: the stage twiddle of input r is exp(2 pi i r dt / K)
+    const T2 a0 = in[b];
+    T2 s[H], d[H], hi[H];
+    int t = 0;
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      t += dt;
+      if (t >= K) t -= K;
+      T2 w = tw[2 * t];
+      if (SIGN < 0) w.y = -w.y;
+      const T2 a = cmul(in[b + r * KR], w);
+      if (r <= H) {
+        hi[r - 1] = a;
+      } else {
+        const T2 lo = hi[R - r - 1];       // a_{R-r}, R - r <= H
+        s[R - r - 1].x = lo.x + a.x; s[R - r - 1].y = lo.y + a.y;
+        d[R - r - 1].x = lo.x - a.x; d[R - r - 1].y = lo.y - a.y;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      T2 acc = a0;
+#pragma unroll
+      for (int j = 1; j <= H; ++j) {
+        const T2 w = wr[(j * q) % R];
+        acc.x += s[j - 1].x * w.x - d[j - 1].y * w.y;
+        acc.y += s[j - 1].y * w.x + d[j - 1].x * w.y;
+      }
+      out[obase + q * Ns] = acc;
+    }
+  }
+}
+
 // One Stockham stage of radix R on K points: out = stage(in).  sign = +1 for
 // e^{+i}, -1 for e^{-i}.  Twiddle exp(sign 2 pi i t / K) = tw[2 t] (conjugated for sign -1).
-template <typename T2, int SIGN>
+// PR: a large prime radix with its own compiled stage (0: none).
+template <typename T2, int SIGN, int PR>
 __device__ inline void stockham_stage(const T2* __restrict__ in, T2* __restrict__ out, int K, int Ns, int R,
                                       const T2* __restrict__ tw) {
+  if constexpr (sizeof(T2) == 8) {   // float data: compiled odd-prime stages
+    if (R == 3) return prime_stage<T2, SIGN, 3>(in, out, K, Ns, tw);
+    if (R == 5) return prime_stage<T2, SIGN, 5>(in, out, K, Ns, tw);
+    if (R == 7) return prime_stage<T2, SIGN, 7>(in, out, K, Ns, tw);
+    if constexpr (PR > 7)
+      if (R == PR) return prime_stage<T2, SIGN, PR>(in, out, K, Ns, tw);
+  }
   const int KR = K / R;
   const int step = K / (Ns * R);  // exp(2 pi i u / (Ns R)) = exp(2 pi i u step / K)
   for (int b = threadIdx.x; b < KR; b += blockDim.x) {
@@ -84,19 +146,23 @@ __device__ inline void stockham_stage(const T2* __restrict__ in, T2* __restrict_
       out[obase + 2 * Ns] = y2;
       out[obase + 3 * Ns] = y3;
     } else {
-      // generic radix: direct DFT with the combined twiddle exp(sign 2 pi i r (k + q Ns) / (Ns R))
+      // generic radix: direct DFT with the combined twiddle exp(sign 2 pi i r (k + q Ns) / (Ns R)),
+      // its index r (k + q Ns) step mod K advanced incrementally over r
       for (int q = 0; q < R; ++q) {
         T2 acc;
         acc.x = 0;
         acc.y = 0;
+        const int dt = (int)(((long long)(k + q * Ns) * step) % K);
+        int t = 0;
         for (int r = 0; r < R; ++r) {
           const T2 a = in[b + r * KR];
-          const long long t = ((long long)r * (k + q * Ns) * step) % K;
           T2 w = tw[2 * t];
           if (SIGN < 0) w.y = -w.y;
           const T2 p = cmul(a, w);
           acc.x += p.x;
           acc.y += p.y;
+          t += dt;
+          if (t >= K) t -= K;
         }
         out[obase + q * Ns] = acc;
       }
@@ -105,19 +171,16 @@ __device__ inline void stockham_stage(const T2* __restrict__ in, T2* __restrict_
 }
 
 // Stage over R independent transforms of length K stored back to back.
-template <typename T2, int SIGN>
+template <typename T2, int SIGN, int PR>
 __device__ inline void stockham_stage_multi(const T2* __restrict__ in, T2* __restrict__ out, int K, int R, int Ns,
                                             int Rf, const T2* __restrict__ tw) {
-  // each transform r uses the same butterfly set; run them as one flat index space
-  const int KR = K / Rf;
-  for (int r = 0; r < R; ++r) stockham_stage<T2, SIGN>(in + (size_t)r * K, out + (size_t)r * K, K, Ns, Rf, tw);
-  (void)KR;
+  for (int r = 0; r < R; ++r) stockham_stage<T2, SIGN, PR>(in + (size_t)r * K, out + (size_t)r * K, K, Ns, Rf, tw);
 }
 
 // c2r, generic radices: one workgroup per (sequence, block of R consecutive rings),
 // two LDS buffers (Stockham ping-pong).  Used for FP64 and for ring lengths whose
 // factors the register kernel below does not cover.
-template <typename T>
+template <typename T, int PR>
 __global__ __launch_bounds__(256) void k_fft_c2r(FftPlan plan, int lmax, int ntheta, int R,
                                                  const typename vec2<T>::type* __restrict__ F,
                                                  T* __restrict__ maps, const typename vec2<T>::type* __restrict__ tw) {
@@ -162,7 +225,7 @@ __global__ __launch_bounds__(256) void k_fft_c2r(FftPlan plan, int lmax, int nth
   int Ns = 1;
   for (int f = 0; f < plan.nf; ++f) {
     const int Rf = plan.radix[f];
-    stockham_stage_multi<T2, +1>(in, out, K, R, Ns, Rf, tw);
+    stockham_stage_multi<T2, +1, PR>(in, out, K, R, Ns, Rf, tw);
     __syncthreads();
     T2* tmp = in; in = out; out = tmp;
     Ns *= Rf;
@@ -174,7 +237,7 @@ __global__ __launch_bounds__(256) void k_fft_c2r(FftPlan plan, int lmax, int nth
 }
 
 // r2c: G rows [seq][ring][pixel] -> Gh [seq][m][ring], m <= lmax.
-template <typename T>
+template <typename T, int PR>
 __global__ __launch_bounds__(256) void k_fft_r2c(FftPlan plan, int lmax, int ntheta, int R, const T* __restrict__ G,
                                                  typename vec2<T>::type* __restrict__ Gh,
                                                  const typename vec2<T>::type* __restrict__ tw) {
@@ -201,7 +264,7 @@ __global__ __launch_bounds__(256) void k_fft_r2c(FftPlan plan, int lmax, int nth
   int Ns = 1;
   for (int f = 0; f < plan.nf; ++f) {
     const int Rf = plan.radix[f];
-    stockham_stage_multi<T2, -1>(in, out, K, R, Ns, Rf, tw);
+    stockham_stage_multi<T2, -1, PR>(in, out, K, R, Ns, Rf, tw);
     __syncthreads();
     T2* tmp = in; in = out; out = tmp;
     Ns *= Rf;
@@ -381,7 +444,7 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int 
                                                               const float2* __restrict__ twg,
                                                               const float2* __restrict__ twpg) {
   extern __shared__ __attribute__((aligned(16))) float2 rbuf[];
-  const int K = plan.K, N = plan.N;
+  const int K = plan.K;
   const int KP = padr(K) + 1;
   float2* tw = rbuf + RG_RINGS * KP;   // e^{2 pi i t / N}, t <= K / 2, shared by the workgroup's rings
   float2* twp = tw + K / 2 + 1;          // the passes' twiddle tables, K - 1 entries in all
@@ -549,6 +612,14 @@ hipError_t fft_rg_set_lds(size_t bytes) {
   return e;
 }
 
+namespace {
+bool plan_has_radix(const FftPlan& p, int r) {
+  for (int f = 0; f < p.nf; ++f)
+    if (p.radix[f] == r) return true;
+  return false;
+}
+}  // namespace
+
 hipError_t launch_fft_c2r(const modal_ctx* c, const void* F, int S, void* maps, hipStream_t st) {
   if (c->fft_rg) {
     // persistent: two workgroups per CU, in pairs (b, b + 8) per XCD
@@ -572,10 +643,13 @@ hipError_t launch_fft_c2r(const modal_ctx* c, const void* F, int S, void* maps, 
   const size_t blocks = (size_t)S * c->P * ((c->ntheta + R - 1) / R);
   const size_t lds = (size_t)R * 2 * c->fft.K * 2 * real_bytes(c);
   if (is_f64(c))
-    hipLaunchKernelGGL(k_fft_c2r<double>, dim3(blocks), dim3(256), lds, st, c->fft, c->lmax, c->ntheta, R,
+    hipLaunchKernelGGL((k_fft_c2r<double, 0>), dim3(blocks), dim3(256), lds, st, c->fft, c->lmax, c->ntheta, R,
                        (const double2*)F, (double*)maps, (const double2*)c->t.tw64);
+  else if (plan_has_radix(c->fft, 47))
+    hipLaunchKernelGGL((k_fft_c2r<float, 47>), dim3(blocks), dim3(256), lds, st, c->fft, c->lmax, c->ntheta, R,
+                       (const float2*)F, (float*)maps, (const float2*)c->t.tw32);
   else
-    hipLaunchKernelGGL(k_fft_c2r<float>, dim3(blocks), dim3(256), lds, st, c->fft, c->lmax, c->ntheta, R,
+    hipLaunchKernelGGL((k_fft_c2r<float, 0>), dim3(blocks), dim3(256), lds, st, c->fft, c->lmax, c->ntheta, R,
                        (const float2*)F, (float*)maps, (const float2*)c->t.tw32);
   return hipGetLastError();
 }
@@ -590,24 +664,27 @@ hipError_t launch_fft_r2c_rows(const modal_ctx* c, const void* G, size_t nseq, v
   const size_t blocks = nseq * ((c->ntheta + R - 1) / R);
   const size_t lds = (size_t)R * 2 * c->fft.K * 2 * real_bytes(c);
   if (is_f64(c))
-    hipLaunchKernelGGL(k_fft_r2c<double>, dim3(blocks), dim3(256), lds, st, c->fft, c->lmax, c->ntheta, R,
+    hipLaunchKernelGGL((k_fft_r2c<double, 0>), dim3(blocks), dim3(256), lds, st, c->fft, c->lmax, c->ntheta, R,
                        (const double*)G, (double2*)Gh, (const double2*)c->t.tw64);
+  else if (plan_has_radix(c->fft, 47))
+    hipLaunchKernelGGL((k_fft_r2c<float, 47>), dim3(blocks), dim3(256), lds, st, c->fft, c->lmax, c->ntheta, R,
+                       (const float*)G, (float2*)Gh, (const float2*)c->t.tw32);
   else
-    hipLaunchKernelGGL(k_fft_r2c<float>, dim3(blocks), dim3(256), lds, st, c->fft, c->lmax, c->ntheta, R,
+    hipLaunchKernelGGL((k_fft_r2c<float, 0>), dim3(blocks), dim3(256), lds, st, c->fft, c->lmax, c->ntheta, R,
                        (const float*)G, (float2*)Gh, (const float2*)c->t.tw32);
   return hipGetLastError();
 }
 
 // Called once per context to allow LDS above the 64 KB default.
 hipError_t fft_set_lds_limit(size_t bytes) {
-  hipError_t e;
-  e = hipFuncSetAttribute((const void*)k_fft_c2r<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_fft_c2r<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_fft_r2c<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_fft_r2c<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  const void* fns[] = {(const void*)k_fft_c2r<double, 0>, (const void*)k_fft_c2r<float, 0>,
+                       (const void*)k_fft_c2r<float, 47>, (const void*)k_fft_r2c<double, 0>,
+                       (const void*)k_fft_r2c<float, 0>, (const void*)k_fft_r2c<float, 47>};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace modal

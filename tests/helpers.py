@@ -67,4 +67,7 @@ CASES = {
     # npix = 1250, not a multiple of 4: the element-wise staging paths of the float kernels
     # (half-length FFT of 25 = 5 x 5), mask + beam/noise spectrum
     "odd": Case("odd", 16, 25, 50, 5, 3, "wmap", 31),
+    # nphi = 94: a prime half-length ring transform (K = 47), the radix that the l_max 2000
+    # grid (nphi 6016 = 128 x 47) needs, in the generic transform kernels (c2r and r2c)
+    "prime": Case("prime", 32, 48, 94, 8, 2, "wmap", 41),
 }

@@ -74,7 +74,7 @@ def oracle_for(case):
 
 CASE_PREC = [("tiny", "f64"), ("tiny", "f32"), ("tiny", "bf16x3"), ("tiny", "f16x3"), ("ragged", "f64"),
              ("ragged", "f32"), ("ragged", "bf16x3"), ("ragged", "f16x3"), ("odd", "f64"), ("odd", "f32"),
-             ("odd", "bf16x3"), ("odd", "f16x3")]
+             ("odd", "bf16x3"), ("odd", "f16x3"), ("prime", "f64"), ("prime", "f32"), ("prime", "bf16x3")]
 
 
 @pytest.mark.parametrize("name", ["tiny", "ragged"])
@@ -317,15 +317,69 @@ def test_graph_replay_mixed_lmax():
     xb.linear_finalize(st)
     ea = xa.beta(oa["alms"]).cpu().numpy()
     eb = xb.beta(ob["alms"], state=st).cpu().numpy()
+    # the eager results themselves against the oracle (beta, and beta - lin with the state)
+    assert max(rel_inf(ea[i], oa["beta"][i]) for i in range(ca.S)) < TOL["f32"]
+    assert max(rel_inf(eb[i], ob["beta"][i] - ob["lin"][i]) for i in range(cb.S)) < TOL["bf16x3"]
     g = BetaGraph([(xa, oa["alms"], None), (xb, ob["alms"], st)])
     for rep in range(3):
         ba, bb = g.launch()
         torch.cuda.synchronize()
-        assert np.array_equal(ba.cpu().numpy(), ea), rep
-        assert np.array_equal(bb.cpu().numpy(), eb), rep
+        ga, gb = ba.cpu().numpy(), bb.cpu().numpy()
+        assert np.array_equal(ga, ea), rep
+        assert np.array_equal(gb, eb), rep
+        ra = max(rel_inf(ga[i], oa["beta"][i]) for i in range(ca.S))
+        rb = max(rel_inf(gb[i], ob["beta"][i] - ob["lin"][i]) for i in range(cb.S))
+        log_err(f"graph replay {rep} vs oracle: tiny f32 beta / ragged bf16x3 beta_hat", max(ra, rb))
+        assert ra < TOL["f32"] and rb < TOL["bf16x3"], rep
         xa.beta(oa["alms"][:1])          # eager work between replays
         torch.cuda.synchronize()
     g.close()
+
+
+def test_graph_create_reports_the_failing_call():
+    """A graph whose second call has a bad argument names that call's error."""
+    from paper_1105_2791_amd import _lib as L
+    from paper_1105_2791_amd.api import BetaGraph
+    ca, cb = CASES["tiny"], CASES["ragged"]
+    xa, xb = ctx_for(ca, "f32"), ctx_for(cb, "f32")
+    st_other = xa.linear_state()   # a state never reset on xb: ENOTREADY for the second call
+    with pytest.raises(L.ModalError) as e:
+        BetaGraph([(xa, oracle_for(ca)["alms"], None), (xb, oracle_for(cb)["alms"], st_other)])
+    assert e.value.status == L.ENOTREADY and "call 1" in str(e.value) and "not finalised" in str(e.value)
+
+
+def test_autotune_choice_matches_oracle_and_is_not_slower():
+    """The autotuner times modal_beta over its candidate launch shapes and keeps the fastest:
+    the tuned context still matches the oracle, and is no slower than the default shapes
+    (medians of 15 calls, 10 % for timing noise)."""
+    import time
+    from paper_1105_2791_amd import ModalContext
+    case = CASES["ragged"]
+    o = oracle_for(case)
+    c = ModalContext(case.lmax, case.ntheta, case.nphi, case.P, "bf16x3", case.q, case.cl, mask=case.mask())
+    alms = c._alm(np.concatenate([o["alms"]] * 4))   # 12 skies: calls of about a millisecond
+
+    def med_ms():
+        ts = []
+        for _ in range(15):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c.beta(alms)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return 1e3 * float(np.median(ts))
+    med_ms()
+    t_default = med_ms()
+    tuned = c.autotune(alms)
+    t_tuned = med_ms()
+    print(f"[autotune] ragged bf16x3 S=12: default {t_default:.3f} ms, tuned {tuned} {t_tuned:.3f} ms", flush=True)
+    got = c.beta(o["alms"]).cpu().numpy()
+    err = max(rel_inf(got[i], o["beta"][i]) for i in range(case.S))
+    log_err("autotuned beta ragged bf16x3", err)
+    c.close()
+    assert tuned["chunk_px"] > 0 and tuned["fft_rings"] >= 1
+    assert err < TOL["bf16x3"]
+    assert t_tuned <= 1.10 * t_default
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "f16x3"])
