@@ -148,7 +148,7 @@ def beta_hat(M, w, V=None) -> np.ndarray:
     return b if V is None else b - linear_term(M, w, V)
 
 
-def beta_and_linear_by_rings(alms, mc_alms, cl, q, grid, rings_per_chunk: int = 128):
+def beta_and_linear_by_rings(alms, mc_alms, cl, q, grid, rings_per_chunk: int = 128, with_abs: bool = False):
     """beta and lin of every sky in ``alms`` [S, nalm] over the whole grid, with the pair
     means V taken from the Monte-Carlo skies ``mc_alms`` [N, nalm] (None: no linear term).
 
@@ -156,23 +156,32 @@ def beta_and_linear_by_rings(alms, mc_alms, cl, q, grid, rings_per_chunk: int = 
     "3 C a"), and V(x) is a per-pixel mean, so both are accumulated over groups of rings
     with the definitions above applied to each group: memory stays bounded at full
     resolution (a ring group's maps, pair products and pair means only).
-    Returns (beta [S, nmax], lin [S, nmax] or None)."""
+    with_abs: also the sums of the terms' magnitudes, sum_x w |M_p M_r M_s| and
+    sum_x w (|V_pr M_s| + |V_ps M_r| + |V_rs M_p|) (w >= 0): the scale that rounding in the
+    maps and in the summation is relative to (forward error of a sum).
+    Returns (beta [S, nmax], lin [S, nmax] or None), plus (beta_abs, lin_abs) with_abs."""
     from .grid import RingSubset
     alms = np.atleast_2d(alms)
     P = q.shape[0]
     n = len(triple_list(P))
     b = np.zeros((alms.shape[0], n))
     lin = None if mc_alms is None else np.zeros((alms.shape[0], n))
+    b_abs = np.zeros_like(b) if with_abs else None
+    lin_abs = None if (mc_alms is None or not with_abs) else np.zeros_like(b)
     for j0 in range(0, grid.ntheta, rings_per_chunk):
         sub = RingSubset(grid, np.arange(j0, min(grid.ntheta, j0 + rings_per_chunk)))
         M = filtered_maps(alms, cl, q, sub)
         V = None if mc_alms is None else pair_means(filtered_maps(np.atleast_2d(mc_alms), cl, q, sub))
         for s in range(alms.shape[0]):
             b[s] += beta(M[s], sub.w)
+            if with_abs:
+                b_abs[s] += beta(np.abs(M[s]), sub.w)
             if V is not None:
                 lin[s] += linear_term(M[s], sub.w, V)
+                if with_abs:
+                    lin_abs[s] += linear_term(np.abs(M[s]), sub.w, np.abs(V))
         del M, V
-    return b, lin
+    return (b, lin, b_abs, lin_abs) if with_abs else (b, lin)
 
 
 # ---------------------------------------------------------------------------

@@ -8,7 +8,8 @@ inputs).  The sky recipe is the benchmark's: isotropic Gaussian a_lm drawn with 
 WMAP-like filter spectrum f_sky (b_l^2 C_l + N_l) (13 arcmin beam, white noise equal
 to the signal at l = 400), whitened by that spectrum, the |lat| < 10 deg cut in the
 pixel weights, and the linear term's pair means from four further Monte-Carlo skies
-of the same recipe.
+of the same recipe.  It also writes the sums of the terms' magnitudes (the scale of
+rounding errors in a sum, for the condition-scaled error of the test).
 
 Usage: python tests/golden/make_fullsize_golden.py [metric1000|precision1024 ...]
 Writes tests/golden/fullsize_<name>.npz (about 0.6 MB each); takes minutes per shape.
@@ -49,9 +50,10 @@ def make(name: str) -> str:
     alms = np.array([mi.gaussian_alm(cl, lmax, mi.rng_for(cfg.cfg_id, i)) for i in SKY_IDS])
     mc = np.array([mi.gaussian_alm(cl, lmax, mi.rng_for(cfg.cfg_id, i)) for i in MC_IDS])
     t0 = time.time()
-    beta, lin = om.beta_and_linear_by_rings(alms, mc, cl, q, grid, RINGS_PER_CHUNK)
+    beta, lin, beta_abs, lin_abs = om.beta_and_linear_by_rings(alms, mc, cl, q, grid, RINGS_PER_CHUNK, with_abs=True)
     out = golden_path(name)
-    np.savez_compressed(out, beta=beta, lin=lin, beta_hat=beta - lin, lmax=lmax, ntheta=nt, nphi=nphi, P=P,
+    np.savez_compressed(out, beta=beta, lin=lin, beta_hat=beta - lin, beta_abs=beta_abs, lin_abs=lin_abs,
+                        lmax=lmax, ntheta=nt, nphi=nphi, P=P,
                         cfg_id=cfg.cfg_id, sky_ids=np.array(SKY_IDS), mc_ids=np.array(MC_IDS))
     print(f"{name}: lmax={lmax} grid={nt}x{nphi} P={P}: {time.time() - t0:.0f} s -> {out}", flush=True)
     return out
