@@ -43,6 +43,24 @@ def make_inputs(lmax, P, S, first, cfg_id=6):
     return alms
 
 
+def _host_info():
+    """nproc (CPUs this process may run on) and the CPU model of the host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return {"nproc": nproc, "cpu_model": model}
+
+
 def _host_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -77,7 +95,7 @@ def _ring_sample(lmax, ntheta, nphi, P, rings, V_sims, cfg_id):
     return sub, cl, q, V, a
 
 
-def cpu_baseline(lmax, ntheta, nphi, P, rings, V_sims=2, cfg_id=6, op="beta"):
+def cpu_baseline(lmax, ntheta, nphi, P, rings, V_sims=2, cfg_id=6, op="beta", one_thread_rings=0):
     """FP64 oracle timed on host cores for one sky on a subset of rings: maps, then beta
     and the linear term (op "beta"), the pair sums (op "power") or the quartic sums
     (op "trispectrum")."""
@@ -94,9 +112,22 @@ def cpu_baseline(lmax, ntheta, nphi, P, rings, V_sims=2, cfg_id=6, op="beta"):
     t = time.perf_counter() - t0
     assert np.all(np.isfinite(out))
     frac = rings / ntheta
-    return {"value": frac / t, "unit": "maps/s", "cores": _host_threads(), "kind": "oracle",
-            "sample": f"one sky, {rings} of {ntheta} rings (every ~{ntheta // rings}th), maps+{what}, "
-                      f"{t:.1f} s, scaled by {ntheta}/{rings}"}
+    res = {"value": frac / t, "unit": "maps/s", "cores": _host_threads(), "kind": "oracle",
+           "sample": f"one sky, {rings} of {ntheta} rings (every ~{ntheta // rings}th), maps+{what}, "
+                     f"{t:.1f} s, scaled by {ntheta}/{rings}", "host": _host_info()}
+    if one_thread_rings:
+        # the same oracle on one thread (BLAS limited to one), on fewer rings
+        from threadpoolctl import threadpool_limits
+        sub1, cl1, q1, V1, a1 = _ring_sample(lmax, ntheta, nphi, P, one_thread_rings, V_sims, cfg_id)
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            out1 = reduce_(om.filtered_maps(a1, cl1, q1, sub1), sub1.w, V1)
+            t1 = time.perf_counter() - t0
+        assert np.all(np.isfinite(out1))
+        res["one_thread"] = {"value": one_thread_rings / ntheta / t1, "unit": "maps/s", "cores": 1,
+                             "sample": f"one sky, {one_thread_rings} of {ntheta} rings, {t1:.1f} s, "
+                                       f"scaled by {ntheta}/{one_thread_rings}"}
+    return res
 
 
 def _baseline(args, f):
@@ -193,9 +224,10 @@ def kernel_rooflines(ctx, stages, prec, S, op="beta"):
     return out
 
 
-def run_path(args, prec, steps, warmup, make_state=True, op="beta"):
+def run_path(args, prec, steps, warmup, make_state=True, op="beta", lambda_table=None, autotune=None):
     """Build a context at the workload shape, time `steps` beta batches (or, op="power",
-    power-spectrum batches), return the figures."""
+    power-spectrum batches), return the figures.  lambda_table=False: the synthesis runs its
+    recurrence on the fly (no precomputed lambda table)."""
     import numpy as np
     import torch
     import modal_inputs as mi
@@ -210,7 +242,7 @@ def run_path(args, prec, steps, warmup, make_state=True, op="beta"):
     x, _ = probe.grid()
     probe.close()
     mask = np.repeat(mi.mask_rings(np.arccos(x))[:, None], nphi, axis=1)
-    ctx = ModalContext(lmax, nt, nphi, P, prec, q, cl, mask=mask, device=0)
+    ctx = ModalContext(lmax, nt, nphi, P, prec, q, cl, mask=mask, device=0, lambda_table=lambda_table)
     log(f"bench: lmax={lmax} grid={nt}x{nphi} P={P} nmax={ctx.nmax} S={S} prec={prec}")
 
     # linear-term state from Monte-Carlo skies (not timed)
@@ -231,7 +263,7 @@ def run_path(args, prec, steps, warmup, make_state=True, op="beta"):
     log(f"bench[{prec}]: state ready")
 
     tuned = None
-    if args.autotune:
+    if (args.autotune if autotune is None else autotune):
         tuned = ctx.autotune(alm, state)
         log(f"bench[{prec}]: autotuned {tuned}")
     for _ in range(warmup):
@@ -250,6 +282,7 @@ def run_path(args, prec, steps, warmup, make_state=True, op="beta"):
     assert torch.isfinite(out).all().item()
     elapsed = t1 - t0
     res = {"prec": prec, "value": S * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps, "tuned": tuned,
+           "lambda_table": ctx.lambda_table,
            "stages_ms": {k: v[0] / max(1, v[1]) for k, v in stages.items() if v[1]},
            "kernels": kernel_rooflines(ctx, stages, prec, S, op), "nmax": ctx.nmax, "npairs": ctx.npairs,
            "ncol": ncol}
@@ -558,6 +591,83 @@ def run_estimator(args):
     print(json.dumps(line), flush=True)
 
 
+def run_batch(args):
+    """Mixed-resolution Monte-Carlo batch on one GPU: 512 skies, sky i at l_max
+    [500, 1000, 2000][i mod 3] on Gauss-Legendre 768 x 1536, 1536 x 3072 and 3008 x 6016 rings,
+    P = 50 separable modes (n_max = 22,100), split bf16, beta of every sky.  Each context is
+    autotuned first; the calls (S skies each) are captured into one HIP graph and replayed."""
+    import numpy as np
+    import torch
+    import modal_inputs as mi
+    from paper_1105_2791_amd import ModalContext
+    from paper_1105_2791_amd.api import BetaGraph
+    P, S, nsims, prec = args.batch_P, args.batch, args.batch_sims, args.prec
+    shapes = [(500, 768, 1536), (1000, 1536, 3072), (2000, 3008, 6016)]
+    ctxs, tuned = [], []
+    for lmax, nt, nphi in shapes:
+        cl = mi.filter_cl(lmax, "wmap")
+        probe = ModalContext(lmax, nt, nphi, 1, "f32", mi.q_basis(1, lmax), cl)
+        x, _ = probe.grid()
+        probe.close()
+        mask = np.repeat(mi.mask_rings(np.arccos(x))[:, None], nphi, axis=1)
+        c = ModalContext(lmax, nt, nphi, P, prec, mi.q_basis(P, lmax), cl, mask=mask)
+        log(f"batch: context lmax={lmax} grid={nt}x{nphi} P={P} nmax={c.nmax} lambda_table={c.lambda_table}")
+        a = c._alm(make_inputs(lmax, P, S, 0, cfg_id=5))
+        tuned.append(c.autotune(a))
+        ctxs.append(c)
+    # sky i -> context i mod 3; consecutive skies of a context form calls of S skies
+    per = [len(range(k, nsims, 3)) for k in range(3)]
+    calls = []
+    for k, c in enumerate(ctxs):
+        lmax = shapes[k][0]
+        for b0 in range(0, per[k], S):
+            n = min(S, per[k] - b0)
+            calls.append((c, make_inputs(lmax, P, n, 3 * b0 + k, cfg_id=5), None))
+    log(f"batch: {len(calls)} calls, skies per l_max {per}; capturing")
+    g = BetaGraph(calls)
+    for _ in range(args.warmup):
+        g.launch()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        g.launch()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    t = float(np.median(times))
+    outs = g.betas
+    assert all(torch.isfinite(o).all().item() for o in outs)
+    # per-context eager time of one call of S skies (stage split)
+    per_ctx = {}
+    for k, c in enumerate(ctxs):
+        a = c._alm(make_inputs(shapes[k][0], P, S, 0, cfg_id=5))
+        out = torch.empty((S, c.nmax), dtype=torch.float64, device="cuda")
+        c.beta(a, out=out)
+        c.profile_read(reset=True)
+        c.profile(True)
+        c.beta(a, out=out)
+        torch.cuda.synchronize()
+        c.profile(False)
+        st = {kk: v[0] for kk, v in c.profile_read(reset=True).items() if v[1]}
+        per_ctx[f"lmax{shapes[k][0]}"] = {"grid": f"{shapes[k][1]}x{shapes[k][2]}", "ms_per_call": sum(st.values()),
+                                          "stages_ms": st, "tuned": tuned[k]}
+    g.close()
+    for c in ctxs:
+        c.close()
+    line = {
+        "metric": "mixed-resolution Monte-Carlo batch: sims/sec (filter + beta_n), graph replay", "unit": "sims/s",
+        "value": nsims / t, "ms_per_batch": 1e3 * t, "higher_is_better": True, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "dtype": {"bf16x3": "bf16", "f16x3": "f16", "f32": "f32", "f64": "f64"}[prec],
+        "data": "synthetic",
+        "config": {"workload": f"{nsims} skies, l_max 500/1000/2000 (sky i -> [500,1000,2000][i mod 3]) on GL "
+                               f"768x1536 / 1536x3072 / 3008x6016, P={P} (n_max={ctxs[0].nmax}), beam+noise "
+                               f"spectrum, |lat|<10deg cut, {len(calls)} calls of up to {S} skies in one HIP graph",
+                   "skies_per_lmax": per, "batch": S},
+        "per_context": per_ctx,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -571,19 +681,25 @@ def main():
     ap.add_argument("--P", type=int, default=40)
     ap.add_argument("--mc", type=int, default=16, help="Monte-Carlo skies for the linear term")
     ap.add_argument("--cpu-rings", type=int, default=64)
+    ap.add_argument("--cpu-rings-1t", type=int, default=8, help="rings of the one-thread oracle run (0: skip)")
     ap.add_argument("--compare-steps", type=int, default=3, help="timed steps of the plain-FP32 comparison (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--autotune", action="store_true",
-                    help="run the chunk autotuner first (the defaults are its choice on MI355X)")
+    ap.add_argument("--autotune", action=argparse.BooleanOptionalAction, default=True,
+                    help="run the launch-shape autotuner before timing the headline path (default on)")
+    ap.add_argument("--otf-steps", type=int, default=3,
+                    help="timed steps of the headline path with the recurrence on the fly (no lambda table; 0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of a known size (HBM counter calibration)")
     ap.add_argument("--no-linear", action="store_true", help="beta without the linear term (diagnostic)")
     ap.add_argument("--workload", default="beta",
-                    choices=["beta", "lowrank", "power", "shapes", "trispectrum", "estimator"],
+                    choices=["beta", "lowrank", "power", "shapes", "trispectrum", "estimator", "batch"],
                     help="beta: the hot path (default); lowrank: the low-rank covariance calls; "
                          "power: the modal power spectrum; shapes: alpha_n and the ideal covariance; "
                          "trispectrum: the modal trispectrum; estimator: adjoint, covariance, Cholesky "
-                         "estimator, Fisher and graph replay")
+                         "estimator, Fisher and graph replay; batch: 512 skies of mixed l_max 500/1000/2000 "
+                         "at P 50 in one graph")
+    ap.add_argument("--batch-sims", type=int, default=512, help="batch: Monte-Carlo skies")
+    ap.add_argument("--batch-P", type=int, default=50, help="batch: separable modes")
     ap.add_argument("--lr-sims", type=int, default=1000, help="lowrank: beta^hat vectors N")
     ap.add_argument("--lr-k", type=int, default=4, help="lowrank: noise vectors k")
     ap.add_argument("--lr-iters", type=int, default=100, help="lowrank: block iterations")
@@ -613,11 +729,18 @@ def main():
     if args.workload == "estimator":
         run_estimator(args)
         return
+    if args.workload == "batch":
+        run_batch(args)
+        return
     prec = args.prec
     head = run_path(args, prec, args.steps, args.warmup, make_state=not args.no_linear)
     fp32 = None
     if args.compare_steps > 0 and prec != "f32":
-        fp32 = run_path(args, "f32", args.compare_steps, 1, make_state=not args.no_linear)
+        fp32 = run_path(args, "f32", args.compare_steps, 1, make_state=not args.no_linear, autotune=False)
+    otf = None
+    if args.otf_steps > 0 and prec in ("bf16x3", "f16x3"):
+        otf = run_path(args, prec, args.otf_steps, 1, make_state=not args.no_linear, lambda_table=False,
+                       autotune=False)
 
     for k, v in head["kernels"].items():
         v["traffic"] = measured_traffic(k, prec)
@@ -630,7 +753,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         try:
-            cpu = cpu_baseline(args.lmax, args.ntheta, args.nphi, args.P, args.cpu_rings)
+            cpu = cpu_baseline(args.lmax, args.ntheta, args.nphi, args.P, args.cpu_rings,
+                               one_thread_rings=args.cpu_rings_1t)
         except Exception as e:  # the baseline is reported, never the target
             log(f"cpu baseline failed: {e!r}")
 
@@ -652,7 +776,15 @@ def main():
         "kernels": head["kernels"],
         "fp32_compare": None if fp32 is None else {
             "value": fp32["value"], "ms_per_step": fp32["ms_per_step"], "steps": args.compare_steps,
-            "stages_ms": fp32["stages_ms"], "speedup": head["value"] / fp32["value"]},
+            "stages_ms": fp32["stages_ms"], "speedup": head["value"] / fp32["value"],
+            # the FP32 contraction against the FP32 matrix-core peak (157.3 TF), algorithmic
+            # and issued (every pair x all modes, padded tiles)
+            "cubic_roofline": {k: fp32["kernels"]["cubic"].get(k) for k in
+                               ("achieved", "peak", "unit", "frac", "mfma_issued_frac", "avg_ms")}},
+        "recurrence_on_the_fly": None if otf is None else {
+            "value": otf["value"], "ms_per_step": otf["ms_per_step"], "steps": args.otf_steps,
+            "stages_ms": otf["stages_ms"], "lambda_table": otf["lambda_table"],
+            "note": "same path with the synthesis's recurrence computed on the fly (no precomputed lambda table)"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

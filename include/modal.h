@@ -39,9 +39,9 @@
  * Memory and streams
  * ------------------
  * Every pointer argument named *_dev or documented as "device" is device
- * memory owned by the caller; *_host pointers are host memory.  The context
- * owns only its constant tables (allocated in modal_create, freed in
- * modal_destroy).  Every compute call takes a caller-owned device workspace
+ * memory owned by the caller; *_host pointers are host memory.  The library
+ * allocates no device memory: a context's constant tables live in a caller
+ * buffer sized by modal_ctx_bytes.  Every compute call takes a caller-owned device workspace
  * of at least modal_workspace_size() bytes (256-byte aligned) and enqueues
  * its work asynchronously on the given HIP stream (NULL = legacy default
  * stream); none of them allocates device memory.  modal_create and
@@ -107,7 +107,9 @@ typedef enum {
   MODAL_OP_POWER_ALPHA = 14,
   MODAL_OP_POWER_COVARIANCE = 15,
   MODAL_OP_POWER_FNL = 16,
-  MODAL_OP_TRISPECTRUM = 17
+  MODAL_OP_TRISPECTRUM = 17,
+  MODAL_OP_FRAME = 18,          /* S ignored                                              */
+  MODAL_OP_FNL_FRAME = 19
 } modal_op;
 
 typedef enum {
@@ -142,23 +144,44 @@ typedef enum {
 /* context                                                                   */
 /* ------------------------------------------------------------------------ */
 
-/* Create a context for one (grid, lmax, P, precision) on the current HIP
- * device.  Host inputs are copied; the caller may free them afterwards.
+/* Context tables and ownership.  A context's constant tables (quadrature, pixel weights,
+ * recurrence coefficients and seeds, whitened mode functions, twiddles, index tables and,
+ * optionally, the lambda table) live in ONE device buffer that the caller allocates and
+ * owns: the library allocates no device memory anywhere.
+ *
+ * MODAL_CTX_LAMBDA_TABLE (split precisions only; ignored otherwise): also keep a table of
+ * the synthesis's lambda_lm(theta_j) operand words, 16 KB per (m, 64 north rings, 64 l),
+ * about 1.6 GB at lmax 1000 on 1536 rings, so that the synthesis reads lambda instead of
+ * running the recurrence for each block of columns (same results, bit for bit).  Without
+ * it the synthesis runs the recurrence on the fly. */
+#define MODAL_CTX_LAMBDA_TABLE 1u
+
+/* Device bytes of the tables of a context with these arguments (as modal_create takes
+ * them), 256-byte granular.  Host only, no device call.  Returns 0 for arguments that
+ * modal_create would reject (EINVAL, ESHAPE, EUNSUPPORTED). */
+size_t modal_ctx_bytes(int lmax, int ntheta, int nphi, int P, int prec, unsigned flags);
+
+/* Create a context for one (grid, lmax, P, precision) on the current HIP device.  Host
+ * inputs are copied; the caller may free them afterwards.  Synchronous.
  *   q_host    [P][lmax+1]   separable mode functions q_p(l)
  *   cl_host   [lmax+1]      filter spectrum C_l (a_lm are divided by sqrt(C_l);
  *                           C_l <= 0 zeroes that l)
  *   mask_host [ntheta][nphi] extra pixel weight multiplying the quadrature
- *                           weight (a Galactic cut is 0/1); NULL = full sky
- * Errors: EINVAL (null out/q/cl, lmax < 0, P < 1, bad prec), ESHAPE (ntheta
- * <= lmax, nphi <= 2 lmax or nphi odd), EDEVICE.  On failure *out is NULL.
- * The split precisions (BF16X3, F16X3) also compute here, once, a table of the
- * synthesis's lambda_lm(theta_j) operand words: 16 KB per (m, 64 north rings,
- * 64 l), about 1.6 GB at lmax 1000 on 1536 rings.  It is built when it takes at
- * most a tenth of the device memory and half of the free memory, and not at all
- * when the environment variable MODAL_LAMBDA_TABLE is "0"; without it the
- * synthesis runs the recurrence itself (same results, bit for bit). */
-modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P, int prec,
-                          const double* q_host, const double* cl_host, const double* mask_host);
+ *                           weight (a Galactic cut is 0/1); NULL = full sky.  The
+ *                           library forms w(x) = w_GL(theta_j) 2 pi / nphi mask(x)
+ *                           itself, from the Gauss-Legendre rule it computes.
+ *   flags     0 or MODAL_CTX_LAMBDA_TABLE
+ *   tables_dev, table_bytes  caller-owned device buffer, 256-byte aligned, of at least
+ *                           modal_ctx_bytes(lmax, ntheta, nphi, P, prec, flags) bytes; it
+ *                           must stay allocated and untouched until modal_destroy.
+ * Errors: EINVAL (null out/q/cl/tables, lmax < 0, P < 1 or > 64, bad prec or flags, a
+ * misaligned buffer), ESHAPE (ntheta <= lmax, nphi <= 2 lmax or nphi odd), ENOSPACE
+ * (table_bytes too small; checked before any device call), EUNSUPPORTED, EDEVICE.
+ * On failure *out is NULL. */
+modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P, int prec, unsigned flags,
+                          const double* q_host, const double* cl_host, const double* mask_host, void* tables_dev,
+                          size_t table_bytes);
+/* Destroys the host-side context (the caller then frees its table buffer). */
 void modal_destroy(modal_ctx* ctx);
 const char* modal_last_error(const modal_ctx* ctx);
 const char* modal_version(void);
@@ -313,6 +336,37 @@ modal_status modal_bivector_rotate(modal_ctx* ctx, const double* b_dev, const do
 modal_status modal_whiten(modal_ctx* ctx, const double* L_dev, const double* x_dev, int R, double* y_dev,
                           modal_stream_t stream);
 
+/* Truncated orthonormal frame of the modes (Sec. II: an orthonormal basis truncated to
+ * the modes that span the space of interest; eq. Cholrot: re-orthonormalisation by a
+ * Cholesky factor).  The separable q-product modes are linearly dependent in floating
+ * point once P is large (their ideal covariance zeta0 is singular to FP64 at lmax 1000,
+ * P 40), so the factor is pivoted and truncated:
+ *   Pi^T zeta0 Pi ~= L L^T,  L = [L11; L21] (nmax x k),
+ * taking at each step the mode with the largest remaining diagonal and stopping once that
+ * diagonal is <= tol * max(diag zeta0).  The k kept modes perm[0..k) span, to that
+ * tolerance, what all nmax modes span; T = L11^-1 [I_k 0] Pi^T is orthonormal under zeta0.
+ *
+ * modal_frame: zeta0_dev [nmax][nmax] symmetric positive semi-definite (read only; e.g.
+ *   modal_ideal_covariance), 0 <= tol < 1; writes *k_host, perm_dev [nmax] int (first k
+ *   used) and L11_dev [nmax * nmax] double (the k x k lower triangle, row-major with
+ *   leading dimension k, upper part zeroed).  FP64, one column per step (left-looking).
+ *   Synchronises.  Workspace: modal_workspace_size(MODAL_OP_FRAME, 0) (holds nmax^2 doubles).
+ * modal_frame_rotate: y_dev [R][k] = L11^-1 x[perm] for rows x_dev [R][nmax] (the frame
+ *   coordinates, eq. Cholrot on the kept modes); asynchronous, no workspace.
+ * modal_fnl_frame: E_s, sigma^2 of eqs. (modalest, modalvariance) on the k kept modes, with
+ *   zeta_dev [nmax][nmax] any covariance of the modes (zeta0 itself gives E = a'.b' / |a'|^2
+ *   in the frame); alpha_dev [nmax], beta_dev [S][nmax].  Synchronises.
+ *   Workspace: modal_workspace_size(MODAL_OP_FNL_FRAME, S).
+ * Errors: EINVAL (null pointer, tol outside [0, 1), k outside 1..nmax), ENOTPD (fnl_frame:
+ *   zeta restricted to the kept modes not positive definite), ENOSPACE, EDEVICE. */
+modal_status modal_frame(modal_ctx* ctx, const double* zeta0_dev, double tol, int* k_host, int* perm_dev,
+                         double* L11_dev, void* ws_dev, size_t ws_bytes, modal_stream_t stream);
+modal_status modal_frame_rotate(modal_ctx* ctx, int k, const int* perm_dev, const double* L11_dev,
+                                const double* x_dev, int R, double* y_dev, modal_stream_t stream);
+modal_status modal_fnl_frame(modal_ctx* ctx, const double* zeta_dev, int k, const int* perm_dev,
+                             const double* alpha_dev, const double* beta_dev, int S, double* E_host,
+                             double* sigma2_host, void* ws_dev, size_t ws_bytes, modal_stream_t stream);
+
 /* Theory mode coefficients alpha_n (eq. abispect, v_l = 1) of a separable reduced
  * bispectrum b_{l1 l2 l3} = sum_t X_t(l1) Y_t(l2) Z_t(l3), symmetrised over the
  * order of (l1, l2, l3), whitened by the context's C_l (terms with C_l = 0 drop):
@@ -393,12 +447,14 @@ modal_status modal_trispectrum(modal_ctx* ctx, const void* alm_dev, int S, const
 int modal_nquad(const modal_ctx* ctx);
 
 /* Autotuner: times modal_beta on the caller's inputs (same arguments and
- * workspace as modal_beta) for each candidate launch configuration - pixels
- * per split-K chunk of the matrix-core contraction (16K..128K for the split
- * precisions, 2K or 4K for FP32) and rings per FFT workgroup (4, 2, 1 as LDS
- * allows) - and keeps the fastest in
- * the context (reported through chunk_px / fft_rings when not NULL).  A
- * workspace sized by modal_workspace_size stays valid for every candidate.
+ * workspace as modal_beta; one warm-up and two timed calls per candidate) for
+ * each candidate launch configuration - pixels per split-K chunk of the
+ * matrix-core contraction (8K, 16K, 32K or 64K for the split precisions, 2K or
+ * 4K for FP32; rounded to whole staged steps and to a multiple of 8 chunks) and,
+ * for the LDS ping-pong ring FFT only, rings per FFT workgroup (4, 2, 1 as LDS
+ * allows; the register-pass FFT of float maps has one shape) - and keeps the
+ * fastest in the context (reported through chunk_px / fft_rings when not NULL).
+ * A workspace sized by modal_workspace_size stays valid for every candidate.
  * Synchronises the stream.  Errors: as modal_beta. */
 modal_status modal_autotune(modal_ctx* ctx, const void* alm_dev, int S, const void* state_dev, double* beta_dev,
                             void* ws_dev, size_t ws_bytes, modal_stream_t stream, int* chunk_px, int* fft_rings);
@@ -417,7 +473,8 @@ typedef struct modal_graph modal_graph;
  * into the graph and must stay valid while it is used.  Capture runs on a
  * private stream (nothing executes); replay with modal_graph_launch on any
  * stream of that device.  Profiling is suspended during capture.
- * Errors: EINVAL, ENOTREADY, ENOSPACE, EDEVICE (capture/instantiate failed). */
+ * Errors: EINVAL, ENOTREADY, ENOSPACE, EDEVICE (capture/instantiate failed); the failing
+ * call's context records the error, prefixed with "graph call <i>: ". */
 modal_status modal_beta_graph_create(int n, modal_ctx* const* ctxs, const void* const* alms, const int* S,
                                      const void* const* states, double* const* betas, void* const* ws,
                                      const size_t* ws_bytes, modal_graph** out);

@@ -20,4 +20,4 @@ trispectrum estimator of Sec. IV.
 Functions whose parity is not pinned by anything but themselves say so in
 their docstring ("parity unpinned").
 """
-from . import grid, legendre, wigner, modal, closed_forms, sims, lowrank, shapes, power, trispectrum  # noqa: F401
+from . import grid, legendre, wigner, modal, closed_forms, sims, lowrank, shapes, power, trispectrum, frame  # noqa: F401

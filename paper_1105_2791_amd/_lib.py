@@ -15,11 +15,12 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "modal.h")
 
 OK, EINVAL, ESHAPE, EDEVICE, ENOTPD, ENOTREADY, EUNSUPPORTED, ENOSPACE = range(8)
 NOALLOC_SCRATCH_BYTES = 64 << 20   # MODAL_NOALLOC_SCRATCH_BYTES
+CTX_LAMBDA_TABLE = 1              # MODAL_CTX_LAMBDA_TABLE
 F64, F32, BF16X3, F16X3 = range(4)
 OP_FILTER_MAPS, OP_BETA, OP_LINEAR_ACCUMULATE, OP_LINEAR_APPLY, OP_BETA_VJP, \
     OP_COVARIANCE_SAMPLE, OP_COVARIANCE_FISHER, OP_FNL, OP_LINEAR_FINALIZE, OP_NOISE_VECTORS, OP_FNL_LOWRANK, \
     OP_ALPHA_SEPARABLE, OP_IDEAL_COVARIANCE, OP_POWER_BETA, OP_POWER_ALPHA, OP_POWER_COVARIANCE, \
-    OP_POWER_FNL, OP_TRISPECTRUM = range(18)
+    OP_POWER_FNL, OP_TRISPECTRUM, OP_FRAME, OP_FNL_FRAME = range(20)
 LIN_RESET, LIN_ACCUMULATE, LIN_FINALIZE, LIN_APPLY = range(4)
 COV_SAMPLE, COV_FISHER = range(2)
 
@@ -42,7 +43,8 @@ sz = C.c_size_t
 dp = C.POINTER(C.c_double)
 
 _SIGS = {
-    "modal_create": (ip, [C.POINTER(vp), ip, ip, ip, ip, ip, vp, vp, vp]),
+    "modal_ctx_bytes": (sz, [ip, ip, ip, ip, ip, C.c_uint]),
+    "modal_create": (ip, [C.POINTER(vp), ip, ip, ip, ip, ip, C.c_uint, vp, vp, vp, vp, sz]),
     "modal_destroy": (None, [vp]),
     "modal_last_error": (C.c_char_p, [vp]),
     "modal_version": (C.c_char_p, []),
@@ -79,6 +81,9 @@ _SIGS = {
     "modal_power_fnl": (ip, [vp, vp, vp, vp, ip, vp, vp, vp, sz, vp]),
     "modal_trispectrum": (ip, [vp, vp, ip, vp, vp, vp, sz, vp]),
     "modal_nquad": (ip, [vp]),
+    "modal_frame": (ip, [vp, vp, C.c_double, vp, vp, vp, vp, sz, vp]),
+    "modal_frame_rotate": (ip, [vp, ip, vp, vp, vp, ip, vp, vp]),
+    "modal_fnl_frame": (ip, [vp, vp, ip, vp, vp, vp, ip, vp, vp, vp, sz, vp]),
 }
 
 STAGES = ["legendre", "fft", "cubic", "reduce", "linacc", "adj_pair", "adj_fft", "adj_legendre",

@@ -8,6 +8,7 @@ only).
 from __future__ import annotations
 
 import ctypes as C
+import os
 
 import numpy as np
 import torch
@@ -23,7 +24,7 @@ class ModalContext:
     """One (grid, lmax, P, precision) configuration on one GPU."""
 
     def __init__(self, lmax: int, ntheta: int, nphi: int, P: int, prec: str, q, cl, mask=None,
-                 device: int | str | torch.device = 0):
+                 device: int | str | torch.device = 0, lambda_table: bool | None = None):
         self._lib = L.lib()
         self.device = torch.device("cuda", torch.device(device).index if not isinstance(device, int) else device)
         self.lmax, self.ntheta, self.nphi, self.P = lmax, ntheta, nphi, P
@@ -37,10 +38,31 @@ class ModalContext:
         if mask is not None:
             mk = np.ascontiguousarray(np.broadcast_to(np.asarray(mask, dtype=np.float64), (ntheta, nphi)))
         self._h = C.c_void_p()
+        # the context's tables: one caller-owned device buffer sized by modal_ctx_bytes; the
+        # split precisions keep the synthesis's lambda table when it fits (a tenth of the
+        # device, half of the free memory) unless lambda_table=False (default: unless the
+        # environment sets MODAL_LAMBDA_TABLE=0)
+        flags = 0
+        want = os.environ.get("MODAL_LAMBDA_TABLE", "1") != "0" if lambda_table is None else bool(lambda_table)
+        if self.prec in (L.BF16X3, L.F16X3) and want:
+            extra = (self._lib.modal_ctx_bytes(lmax, ntheta, nphi, P, self.prec, L.CTX_LAMBDA_TABLE)
+                     - self._lib.modal_ctx_bytes(lmax, ntheta, nphi, P, self.prec, 0))
+            free, total = torch.cuda.mem_get_info(self.device)
+            if extra <= total // 10 and extra < free // 2:
+                flags = L.CTX_LAMBDA_TABLE
+        nbytes = self._lib.modal_ctx_bytes(lmax, ntheta, nphi, P, self.prec, flags)
+        if nbytes == 0:   # rejected arguments: modal_create names the reason (before any device call)
+            st = self._lib.modal_create(C.byref(self._h), lmax, ntheta, nphi, P, self.prec, flags, q.ctypes.data,
+                                        cl.ctypes.data, None, None, 0)
+            raise L.ModalError(st, "modal_create rejected the arguments")
+        self.lambda_table = bool(flags & L.CTX_LAMBDA_TABLE)
+        self._tables = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         with torch.cuda.device(self.device):
-            st = self._lib.modal_create(C.byref(self._h), lmax, ntheta, nphi, P, self.prec,
-                                        q.ctypes.data, cl.ctypes.data, None if mk is None else mk.ctypes.data)
+            st = self._lib.modal_create(C.byref(self._h), lmax, ntheta, nphi, P, self.prec, flags,
+                                        q.ctypes.data, cl.ctypes.data, None if mk is None else mk.ctypes.data,
+                                        self._tables.data_ptr(), nbytes)
         if st != L.OK:
+            self._tables = None
             raise L.ModalError(st, "modal_create failed")
         self.nalm = self._lib.modal_nalm(self._h)
         self.nmax = self._lib.modal_nmax(self._h)
@@ -55,6 +77,7 @@ class ModalContext:
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.modal_destroy(self._h)
             self._h = C.c_void_p()
+        self._tables = None
 
     def __del__(self):
         try:
@@ -235,6 +258,48 @@ class ModalContext:
         return (E, float(s2[0]), Ld) if want_L else (E, float(s2[0]))
 
 
+    # -- truncated orthonormal frame (Sec. II, eq. Cholrot) -----------------------------
+
+    def frame(self, zeta0, tol: float = 1e-10):
+        """Pivoted, truncated Cholesky of zeta0: (k, perm [k] int32, L11 [k][k]) with the
+        k kept modes perm and the lower factor L11 of zeta0 restricted to them."""
+        z = torch.as_tensor(zeta0).to(device=self.device, dtype=torch.float64).contiguous()
+        perm = torch.empty(self.nmax, dtype=torch.int32, device=self.device)
+        L11 = torch.empty(self.nmax * self.nmax, dtype=torch.float64, device=self.device)
+        k = C.c_int()
+        ws = self.workspace(L.OP_FRAME, 0)
+        self._check(self._lib.modal_frame(self._h, _ptr(z), float(tol), C.byref(k), _ptr(perm), _ptr(L11),
+                                          _ptr(ws), ws.numel(), self._stream()))
+        k = k.value
+        return k, perm[:k].clone(), L11[:k * k].reshape(k, k).clone()
+
+    def frame_rotate(self, perm, L11, x):
+        """Rows x [R][nmax] -> L11^-1 x[perm] [R][k] (the coordinates in the frame)."""
+        k = int(L11.shape[0])
+        p = torch.zeros(self.nmax, dtype=torch.int32, device=self.device)
+        p[:k] = perm
+        xx = torch.as_tensor(x).to(device=self.device, dtype=torch.float64).reshape(-1, self.nmax).contiguous()
+        y = torch.empty((xx.shape[0], k), dtype=torch.float64, device=self.device)
+        self._check(self._lib.modal_frame_rotate(self._h, k, _ptr(p), _ptr(L11.contiguous()), _ptr(xx), xx.shape[0],
+                                                 _ptr(y), self._stream()))
+        return y
+
+    def fnl_frame(self, zeta, perm, alpha, beta):
+        """E [S] and sigma^2 of the estimator on the kept modes perm [k] (zeta any covariance)."""
+        k = int(perm.shape[0])
+        p = torch.zeros(self.nmax, dtype=torch.int32, device=self.device)
+        p[:k] = perm
+        z = torch.as_tensor(zeta).to(device=self.device, dtype=torch.float64).contiguous()
+        al = torch.as_tensor(alpha).to(device=self.device, dtype=torch.float64).contiguous()
+        b = torch.as_tensor(beta).to(device=self.device, dtype=torch.float64).reshape(-1, self.nmax).contiguous()
+        S = b.shape[0]
+        E = np.zeros(S)
+        s2 = np.zeros(1)
+        ws = self.workspace(L.OP_FNL_FRAME, S)
+        self._check(self._lib.modal_fnl_frame(self._h, _ptr(z), k, _ptr(p), _ptr(al), _ptr(b), S, E.ctypes.data,
+                                              s2.ctypes.data, _ptr(ws), ws.numel(), self._stream()))
+        return E, float(s2[0])
+
     # -- low-rank covariance I + sum_j b_j b_j^T (Sec. III B) --------------------------
 
     def noise_vectors(self, beta, k: int = 1, iters: int = 100):
@@ -372,7 +437,8 @@ class BetaGraph:
     into the graph."""
 
     def __init__(self, calls):
-        """calls: list of (ModalContext, alm tensor [S][nalm], state or None)."""
+        """calls: list of (ModalContext, alm tensor [S][nalm], state or None); calls on one
+        context share its workspace."""
         self._lib = L.lib()
         n = len(calls)
         self.ctxs = [c for c, _, _ in calls]
@@ -380,8 +446,13 @@ class BetaGraph:
         self.states = [st for _, _, st in calls]
         self.betas = [torch.empty((a.shape[0], c.nmax), dtype=torch.float64, device=c.device)
                       for (c, _, _), a in zip(calls, self.alms)]
-        self.ws = [torch.empty(max(256, c.workspace_size(L.OP_BETA, a.shape[0])), dtype=torch.uint8,
-                               device=c.device) for (c, _, _), a in zip(calls, self.alms)]
+        # the calls run one after another on one stream, so calls on the same context share
+        # one workspace, sized for the largest S among them
+        need = {}
+        for (c, _, _), a in zip(calls, self.alms):
+            need[id(c)] = max(need.get(id(c), 256), c.workspace_size(L.OP_BETA, a.shape[0]))
+        shared = {k: torch.empty(v, dtype=torch.uint8, device=self.ctxs[0].device) for k, v in need.items()}
+        self.ws = [shared[id(c)] for c, _, _ in calls]
         arr = lambda T, vals: (T * n)(*vals)
         ctxs = arr(C.c_void_p, [c._h.value for c in self.ctxs])
         alms = arr(C.c_void_p, [a.data_ptr() for a in self.alms])
@@ -391,9 +462,16 @@ class BetaGraph:
         wss = arr(C.c_void_p, [w.data_ptr() for w in self.ws])
         wsb = arr(C.c_size_t, [w.numel() for w in self.ws])
         self._g = C.c_void_p()
+        before = [self._lib.modal_last_error(c._h) for c in self.ctxs]
         st = self._lib.modal_beta_graph_create(n, ctxs, alms, Ss, sts, bts, wss, wsb, C.byref(self._g))
         if st != L.OK:
-            raise L.ModalError(st, self._lib.modal_last_error(self.ctxs[0]._h).decode())
+            # a failing call records its error on its own context
+            msgs = [self._lib.modal_last_error(c._h).decode() for i, c in enumerate(self.ctxs)
+                    if self._lib.modal_last_error(c._h) != before[i]]
+            if not msgs:
+                msgs = [m.decode() for m in (self._lib.modal_last_error(c._h) for c in self.ctxs)
+                        if m.startswith(b"graph call")]
+            raise L.ModalError(st, "; ".join(msgs) or "graph capture failed")
 
     def launch(self):
         dev = self.ctxs[0].device

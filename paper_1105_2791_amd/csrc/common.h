@@ -217,6 +217,13 @@ hipError_t launch_alpha_modes(int nmax, int P, int T, int nmu, const int* tri, c
 hipError_t launch_ideal_cov(int nmax, int P, int nmu, int nrows, const int4* zrows, const double* F,
                             const double* wmu, double* Z, hipStream_t st);
 
+// truncated orthonormal frame: pivoted, truncated Cholesky (k_frame.hip)
+size_t frame_ws_bytes(int n);
+hipError_t launch_frame(int n, const double* Z, double tol, int* perm, double* L11, int* k_host, void* ws,
+                        hipStream_t st);
+hipError_t launch_gather_cols(int n, int k, int R, const double* x, const int* perm, double* y, hipStream_t st);
+hipError_t launch_gather_sym(int n, int k, const double* Z, const int* perm, double* Zk, hipStream_t st);
+
 // modal trispectrum (pairs x pairs update over pixels)
 int quad_chunks(int npix);
 int quad_ntile(int R);

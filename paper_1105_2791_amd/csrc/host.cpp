@@ -138,14 +138,6 @@ modal_status fail(modal_ctx* c, modal_status s, const std::string& msg) {
       return fail(c, MODAL_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));      \
   } while (0)
 
-template <typename V>
-hipError_t upload(V** dst, const std::vector<V>& src) {
-  hipError_t e = hipMalloc((void**)dst, std::max<size_t>(1, src.size()) * sizeof(V));
-  if (e != hipSuccess) return e;
-  if (src.empty()) return hipSuccess;
-  return hipMemcpy(*dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice);
-}
-
 size_t alm_bytes(const modal_ctx* c) { return (size_t)c->nalm * 2 * real_bytes(c); }
 // synthesis output (f_index layout; also large enough for the adjoint's [S][P][lmax+1][ntheta])
 size_t F_bytes(const modal_ctx* c, int S) {
@@ -221,6 +213,12 @@ size_t ws_size(const modal_ctx* c, int op, int S) {
       break;
     case MODAL_OP_POWER_FNL:
       cv.take((size_t)c->P * c->P * 8); cv.take((size_t)(S + 1) * c->P * 8); cv.take((size_t)(S + 1) * 8);
+      cv.take(16);
+      break;
+    case MODAL_OP_FRAME: cv.take(frame_ws_bytes(c->nmax)); break;
+    case MODAL_OP_FNL_FRAME:
+      cv.take((size_t)c->nmax * c->nmax * 8); cv.take((size_t)(S + 1) * c->nmax * 8);
+      cv.take((size_t)c->nmax * c->nmax * 8); cv.take((size_t)(S + 1) * c->nmax * 8); cv.take((size_t)(S + 1) * 8);
       cv.take(16);
       break;
     case MODAL_OP_IDEAL_COVARIANCE: {
@@ -325,22 +323,55 @@ modal_status check_state(modal_ctx* c, const void* state) {
   return MODAL_OK;
 }
 
-}  // namespace
+// Places every constant table of a context in the caller's device buffer (live) or only
+// adds up its aligned size (dry: no HIP call at all).  Both modes run the same code, so the
+// size query and the placement cannot disagree.
+struct Placer {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  bool dry = true;
+  template <typename V>
+  hipError_t put(V** dst, const std::vector<V>& src) {   // device copy of a host vector
+    const size_t bytes = align256(std::max<size_t>(1, src.size()) * sizeof(V));
+    if (!dry) {
+      if (used + bytes > cap) return hipErrorOutOfMemory;
+      *dst = reinterpret_cast<V*>(base + used);
+      if (!src.empty()) {
+        const hipError_t e = hipMemcpy(*dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return e;
+      }
+    }
+    used += bytes;
+    return hipSuccess;
+  }
+  template <typename V>
+  hipError_t take(V** dst, size_t count) {   // uninitialised region
+    const size_t bytes = align256(std::max<size_t>(1, count) * sizeof(V));
+    if (!dry) {
+      if (used + bytes > cap) return hipErrorOutOfMemory;
+      *dst = reinterpret_cast<V*>(base + used);
+    }
+    used += bytes;
+    return hipSuccess;
+  }
+};
 
-// ---------------------------------------------------------------------------
-extern "C" {
+// LDS per workgroup assumed by the size query (gfx950); a live context uses the device's value.
+constexpr size_t kGfx950Lds = 163840;
 
-const char* modal_version(void) { return "libmodal 0.1 (gfx950)"; }
+bool valid_shape_args(int lmax, int ntheta, int nphi, int P, int prec, modal_status* st) {
+  if (lmax < 0 || P < 1 || P > kMaxP || prec < MODAL_F64 || prec > MODAL_F16X3) {
+    *st = MODAL_EINVAL;
+    return false;
+  }
+  if (ntheta <= lmax || nphi <= 2 * lmax || (nphi & 1) || ntheta < 1) {
+    *st = MODAL_ESHAPE;
+    return false;
+  }
+  return true;
+}
 
-modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P, int prec, const double* q_host,
-                          const double* cl_host, const double* mask_host) {
-  if (!out) return MODAL_EINVAL;
-  *out = nullptr;
-  if (!q_host || !cl_host || lmax < 0 || P < 1 || P > kMaxP || prec < MODAL_F64 || prec > MODAL_F16X3)
-    return MODAL_EINVAL;
-  if (ntheta <= lmax || nphi <= 2 * lmax || (nphi & 1) || ntheta < 1) return MODAL_ESHAPE;
-  modal_ctx* c = new (std::nothrow) modal_ctx();
-  if (!c) return MODAL_EDEVICE;
+void init_shapes(modal_ctx* c, int lmax, int ntheta, int nphi, int P, int prec) {
   c->lmax = lmax;
   c->ntheta = ntheta;
   c->nphi = nphi;
@@ -351,43 +382,51 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
   c->nmax = P * (P + 1) * (P + 2) / 6;
   c->nrp = (ntheta + 1) / 2;
   c->npix = ntheta * nphi;
-  auto bail = [&](modal_status s) {
-    modal_destroy(c);
-    return s;
-  };
-  if ((prec == MODAL_BF16X3 || prec == MODAL_F16X3) && !cubic_mfma_available(c)) return bail(MODAL_EUNSUPPORTED);
-  if (hipGetDevice(&c->device) != hipSuccess) return bail(MODAL_EDEVICE);
-  if (scratch_resolve(c->device) != hipSuccess) return bail(MODAL_EDEVICE);
-  int lds = 0;
-  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess && lds > 0)
-    c->max_lds = (size_t)lds;
-  if (!fft_plan(nphi, c->fft)) return bail(MODAL_ESHAPE);
+}
+
+// Kernel variants the context's shapes allow (host decisions from the LDS size); live also
+// raises the kernels' dynamic-LDS limits.
+modal_status choose_kernels(modal_ctx* c, bool live) {
+  const int prec = c->prec;
+  if ((prec == MODAL_BF16X3 || prec == MODAL_F16X3) && !cubic_mfma_available(c)) return MODAL_EUNSUPPORTED;
+  if (!fft_plan(c->nphi, c->fft)) return MODAL_ESHAPE;
   const size_t fft_lds = (size_t)fft_rings_per_block(c) * 2 * c->fft.K * 2 * real_bytes(c);
-  if (fft_lds > c->max_lds) return bail(MODAL_EUNSUPPORTED);
-  if (fft_lds > 65536 && fft_set_lds_limit(fft_lds) != hipSuccess) return bail(MODAL_EDEVICE);
-  if (prec != MODAL_F64 && fft_plan_rg(nphi, c->fft_rg_plan)) {
+  if (fft_lds > c->max_lds) return MODAL_EUNSUPPORTED;
+  if (live && fft_lds > 65536 && fft_set_lds_limit(fft_lds) != hipSuccess) return MODAL_EDEVICE;
+  c->fft_rg = false;
+  if (prec != MODAL_F64 && fft_plan_rg(c->nphi, c->fft_rg_plan)) {
     const size_t rg = fft_rg_lds(c);
     if (rg <= c->max_lds) {
-      if (rg > 65536 && fft_rg_set_lds(rg) != hipSuccess) return bail(MODAL_EDEVICE);
+      if (live && rg > 65536 && fft_rg_set_lds(rg) != hipSuccess) return MODAL_EDEVICE;
       c->fft_rg = true;
     }
   }
-
+  c->legendre_mfma = false;
   if (prec == MODAL_F32 || prec == MODAL_BF16X3 || prec == MODAL_F16X3) {
     if (prec != MODAL_F32) {
       const size_t lneed = legendre_split_lds();
-      if (lneed + 1024 > c->max_lds) return bail(MODAL_EUNSUPPORTED);
-      if (lneed > 65536 && legendre_split_set_lds(lneed) != hipSuccess) return bail(MODAL_EDEVICE);
+      if (lneed + 1024 > c->max_lds) return MODAL_EUNSUPPORTED;
+      if (live && lneed > 65536 && legendre_split_set_lds(lneed) != hipSuccess) return MODAL_EDEVICE;
       const size_t cneed = cubic_split_lds();
-      if (cneed + 1024 > c->max_lds) return bail(MODAL_EUNSUPPORTED);
-      if (cneed > 65536 && cubic_split_set_lds(cneed) != hipSuccess) return bail(MODAL_EDEVICE);
+      if (cneed + 1024 > c->max_lds) return MODAL_EUNSUPPORTED;
+      if (live && cneed > 65536 && cubic_split_set_lds(cneed) != hipSuccess) return MODAL_EDEVICE;
     }
     const size_t need = legendre_mfma_lds(c);
     if (need <= c->max_lds) {
-      if (need > 65536 && legendre_mfma_set_lds(need) != hipSuccess) return bail(MODAL_EDEVICE);
+      if (live && need > 65536 && legendre_mfma_set_lds(need) != hipSuccess) return MODAL_EDEVICE;
       c->legendre_mfma = true;
     }
   }
+  return MODAL_OK;
+}
+
+// Host construction of every table and its placement (dry: sizes only).  Live, it also
+// computes the recurrence seeds and, with MODAL_CTX_LAMBDA_TABLE, the lambda table.
+modal_status place_tables(modal_ctx* c, const double* q_host, const double* cl_host, const double* mask_host,
+                          unsigned flags, Placer& pl) {
+  const int lmax = c->lmax, ntheta = c->ntheta, nphi = c->nphi, P = c->P, prec = c->prec;
+  const bool live = !pl.dry;
+  auto ok = [](hipError_t e) { return e == hipSuccess; };
   // --- grid
   gauss_legendre(ntheta, c->x_host, c->wgl_host);
   std::vector<double> ringw(ntheta), w64((size_t)ntheta * nphi);
@@ -506,51 +545,101 @@ modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P
   }
   c->wscale = (float)std::ldexp(1.0, (int)std::lround(std::log2((double)c->npix / (4.0 * kPi))));
   Tables& t = c->t;
-  if (upload(&t.mscale, mscale) != hipSuccess) return bail(MODAL_EDEVICE);
+  if (!ok(pl.put(&t.mscale, mscale))) return MODAL_EDEVICE;
   std::vector<int2> blocks, items;
   if (prec == MODAL_BF16X3 || prec == MODAL_F16X3) make_pair_blocks22(P, blocks, items);
   else make_pair_blocks(P, blocks);
   t.nblk = (int)blocks.size();
   t.nitems = (int)items.size();
-  if (upload(&t.blk, blocks) != hipSuccess || upload(&t.items, items) != hipSuccess) return bail(MODAL_EDEVICE);
-  if (c->fft_rg && upload(&t.twp32, fft_rg_twiddles(c->fft_rg_plan)) != hipSuccess) return bail(MODAL_EDEVICE);
+  if (!ok(pl.put(&t.blk, blocks)) || !ok(pl.put(&t.items, items))) return MODAL_EDEVICE;
+  if (c->fft_rg && !ok(pl.put(&t.twp32, fft_rg_twiddles(c->fft_rg_plan)))) return MODAL_EDEVICE;
   std::vector<double> xs(c->x_host);
-  if (upload(&t.x, xs) != hipSuccess || upload(&t.ringw, ringw) != hipSuccess || upload(&t.w64, w64) != hipSuccess ||
-      upload(&t.w32, w32) != hipSuccess || upload(&t.rec, rec) != hipSuccess || upload(&t.qw64, qw64) != hipSuccess ||
-      upload(&t.qw32, qw32) != hipSuccess || upload(&t.tw64, tw64) != hipSuccess ||
-      upload(&t.tw32, tw32) != hipSuccess || upload(&t.pair_a, pa) != hipSuccess ||
-      upload(&t.pair_b, pb) != hipSuccess || upload(&t.tri, tri) != hipSuccess ||
-      upload(&t.pair_of, pair_of) != hipSuccess || upload(&t.tri_of, tri_of) != hipSuccess ||
-      upload(&t.tri_mult, tri_mult) != hipSuccess || upload(&t.quad, quad) != hipSuccess ||
-      upload(&t.qtiles, qtiles) != hipSuccess || upload(&t.zrows, zrows) != hipSuccess)
-    return bail(MODAL_EDEVICE);
-  if (hipMalloc((void**)&t.seed, 2 * sizeof(double) * (lmax + 1) * (size_t)c->nrp) != hipSuccess ||
-      hipMalloc((void**)&t.lstart, sizeof(int) * (lmax + 1) * (size_t)c->nrp) != hipSuccess ||
-      hipMalloc((void**)&t.flag, 4 * sizeof(int)) != hipSuccess)
-    return bail(MODAL_EDEVICE);
+  if (!ok(pl.put(&t.x, xs)) || !ok(pl.put(&t.ringw, ringw)) || !ok(pl.put(&t.w64, w64)) || !ok(pl.put(&t.w32, w32)) ||
+      !ok(pl.put(&t.rec, rec)) || !ok(pl.put(&t.qw64, qw64)) || !ok(pl.put(&t.qw32, qw32)) ||
+      !ok(pl.put(&t.tw64, tw64)) || !ok(pl.put(&t.tw32, tw32)) || !ok(pl.put(&t.pair_a, pa)) ||
+      !ok(pl.put(&t.pair_b, pb)) || !ok(pl.put(&t.tri, tri)) || !ok(pl.put(&t.pair_of, pair_of)) ||
+      !ok(pl.put(&t.tri_of, tri_of)) || !ok(pl.put(&t.tri_mult, tri_mult)) || !ok(pl.put(&t.quad, quad)) ||
+      !ok(pl.put(&t.qtiles, qtiles)) || !ok(pl.put(&t.zrows, zrows)))
+    return MODAL_EDEVICE;
+  if (!ok(pl.take(&t.seed, 2 * (size_t)(lmax + 1) * c->nrp)) || !ok(pl.take(&t.lstart, (size_t)(lmax + 1) * c->nrp)) ||
+      !ok(pl.take(&t.flag, 4)))
+    return MODAL_EDEVICE;
   double* d_logpref = nullptr;
-  if (upload(&d_logpref, logpref) != hipSuccess) return bail(MODAL_EDEVICE);
-  hipError_t e = launch_seeds(c, d_logpref, nullptr);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
-  (void)hipFree(d_logpref);
-  if (e != hipSuccess) return bail(MODAL_EDEVICE);
-  // split precisions: the synthesis reads lambda from a table computed here once (the
-  // recurrence is then not repeated for every block of columns), when the table takes
-  // at most a tenth of the device memory
-  const char* lam_env = std::getenv("MODAL_LAMBDA_TABLE");   // "0": keep the in-kernel recurrence
-  if ((prec == MODAL_BF16X3 || prec == MODAL_F16X3) && !(lam_env && lam_env[0] == '0')) {
-    size_t free_b = 0, total_b = 0;
-    const size_t bytes = lambda_table_bytes(c);
-    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && bytes <= total_b / 10 && bytes < free_b / 2) {
-      std::vector<long long> off;
-      lambda_table_records(c, &off);
-      if (upload(&t.lamtab_off, off) != hipSuccess || hipMalloc((void**)&t.lamtab, bytes) != hipSuccess)
-        return bail(MODAL_EDEVICE);
-      e = build_lambda_table(c, nullptr);
+  if (!ok(pl.put(&d_logpref, logpref))) return MODAL_EDEVICE;
+  if (live) {
+    hipError_t e = launch_seeds(c, d_logpref, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return MODAL_EDEVICE;
+  }
+  // split precisions: with MODAL_CTX_LAMBDA_TABLE the synthesis reads lambda from a table
+  // computed here once, instead of running the recurrence for every block of columns
+  if ((prec == MODAL_BF16X3 || prec == MODAL_F16X3) && (flags & MODAL_CTX_LAMBDA_TABLE)) {
+    std::vector<long long> off;
+    lambda_table_records(c, &off);
+    if (!ok(pl.put(&t.lamtab_off, off)) || !ok(pl.take(&t.lamtab, lambda_table_bytes(c) / sizeof(uint4))))
+      return MODAL_EDEVICE;
+    if (live) {
+      hipError_t e = build_lambda_table(c, nullptr);
       if (e == hipSuccess) e = hipDeviceSynchronize();
-      if (e != hipSuccess) return bail(MODAL_EDEVICE);
+      if (e != hipSuccess) return MODAL_EDEVICE;
     }
   }
+  return MODAL_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* modal_version(void) { return "libmodal 0.2 (gfx950)"; }
+
+size_t modal_ctx_bytes(int lmax, int ntheta, int nphi, int P, int prec, unsigned flags) {
+  modal_status st = MODAL_OK;
+  if (!valid_shape_args(lmax, ntheta, nphi, P, prec, &st)) return 0;
+  modal_ctx c;
+  init_shapes(&c, lmax, ntheta, nphi, P, prec);
+  c.max_lds = kGfx950Lds;
+  if (choose_kernels(&c, false) != MODAL_OK) return 0;
+  std::vector<double> q((size_t)P * (lmax + 1), 1.0), cl(lmax + 1, 1.0);
+  Placer pl;
+  if (place_tables(&c, q.data(), cl.data(), nullptr, flags, pl) != MODAL_OK) return 0;
+  return pl.used;
+}
+
+modal_status modal_create(modal_ctx** out, int lmax, int ntheta, int nphi, int P, int prec, unsigned flags,
+                          const double* q_host, const double* cl_host, const double* mask_host, void* tables_dev,
+                          size_t table_bytes) {
+  if (!out) return MODAL_EINVAL;
+  *out = nullptr;
+  modal_status st = MODAL_OK;
+  if (!q_host || !cl_host) return MODAL_EINVAL;
+  if (!valid_shape_args(lmax, ntheta, nphi, P, prec, &st)) return st;
+  if (flags & ~(unsigned)MODAL_CTX_LAMBDA_TABLE) return MODAL_EINVAL;
+  // the size the query reports for these arguments, checked before any device call
+  const size_t need = modal_ctx_bytes(lmax, ntheta, nphi, P, prec, flags);
+  if (need == 0) return MODAL_EUNSUPPORTED;
+  if (!tables_dev) return MODAL_EINVAL;
+  if (table_bytes < need) return MODAL_ENOSPACE;
+  if (reinterpret_cast<uintptr_t>(tables_dev) % 256 != 0) return MODAL_EINVAL;
+  modal_ctx* c = new (std::nothrow) modal_ctx();
+  if (!c) return MODAL_EDEVICE;
+  init_shapes(c, lmax, ntheta, nphi, P, prec);
+  auto bail = [&](modal_status s) {
+    modal_destroy(c);
+    return s;
+  };
+  if (hipGetDevice(&c->device) != hipSuccess) return bail(MODAL_EDEVICE);
+  if (scratch_resolve(c->device) != hipSuccess) return bail(MODAL_EDEVICE);
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess && lds > 0)
+    c->max_lds = (size_t)lds;
+  if ((st = choose_kernels(c, true)) != MODAL_OK) return bail(st);
+  Placer pl;
+  pl.dry = false;
+  pl.base = static_cast<char*>(tables_dev);
+  pl.cap = table_bytes;
+  if ((st = place_tables(c, q_host, cl_host, mask_host, flags, pl)) != MODAL_OK) return bail(st);
   *out = c;
   return MODAL_OK;
 }
@@ -562,13 +651,7 @@ void modal_destroy(modal_ctx* c) {
     (void)hipEventDestroy(mk.b);
   }
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
-  Tables& t = c->t;
-  void* ptrs[] = {t.x, t.ringw, t.w64, t.w32, t.rec, t.seed, t.lstart, t.lstart_blk, t.qw64, t.qw32, t.tw64, t.tw32,
-                  t.pair_a, t.pair_b, t.tri, t.pair_of, t.tri_of, t.tri_mult, t.flag, t.blk, t.items, t.mscale,
-                  t.twp32, t.lamtab, t.lamtab_off, t.quad, t.qtiles, t.zrows};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
-  delete c;
+  delete c;   // the tables live in the caller's buffer
 }
 
 const char* modal_last_error(const modal_ctx* c) { return c ? c->last_error.c_str() : "null context"; }
@@ -597,7 +680,7 @@ modal_status modal_grid(const modal_ctx* c, double* x_host, double* w_host) {
 }
 
 modal_status modal_workspace_size(const modal_ctx* c, int op, int S, size_t* bytes) {
-  if (!c || !bytes || S < 0 || op < MODAL_OP_FILTER_MAPS || op > MODAL_OP_TRISPECTRUM) return MODAL_EINVAL;
+  if (!c || !bytes || S < 0 || op < MODAL_OP_FILTER_MAPS || op > MODAL_OP_FNL_FRAME) return MODAL_EINVAL;
   *bytes = ws_size(c, op, S);
   return MODAL_OK;
 }
@@ -1091,6 +1174,62 @@ modal_status modal_ideal_covariance(modal_ctx* c, const double* c_host, double* 
   return MODAL_OK;
 }
 
+modal_status modal_frame(modal_ctx* c, const double* zeta0, double tol, int* k_host, int* perm, double* L11, void* ws,
+                         size_t ws_bytes, modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (!zeta0 || !k_host || !perm || !L11) return fail(c, MODAL_EINVAL, "frame: null pointer");
+  if (!(tol >= 0.0 && tol < 1.0)) return fail(c, MODAL_EINVAL, "frame: tol outside [0, 1)");
+  modal_status s = check_ws(c, MODAL_OP_FRAME, 0, ws, ws_bytes);
+  if (s != MODAL_OK) return s;
+  if ((s = set_device(c)) != MODAL_OK) return s;
+  int k = 0;
+  {
+    StageTimer _t(c, MODAL_STAGE_CHOLESKY, (hipStream_t)stream);
+    HIPTRY(launch_frame(c->nmax, zeta0, tol, perm, L11, &k, ws, (hipStream_t)stream));
+  }
+  *k_host = k;
+  if (k == 0) return fail(c, MODAL_ENOTPD, "frame: no positive pivot");
+  return MODAL_OK;
+}
+
+modal_status modal_frame_rotate(modal_ctx* c, int k, const int* perm, const double* L11, const double* x, int R,
+                                double* y, modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (R < 0 || (R > 0 && (!perm || !L11 || !x || !y))) return fail(c, MODAL_EINVAL, "frame_rotate: null pointer or R < 0");
+  if (k < 1 || k > c->nmax) return fail(c, MODAL_EINVAL, "frame_rotate: k outside 1..nmax");
+  if (R == 0) return MODAL_OK;
+  modal_status s = set_device(c);
+  if (s != MODAL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  HIPTRY(launch_gather_cols(c->nmax, k, R, x, perm, y, st));
+  HIPTRY(launch_trsm_rows(k, L11, R, y, st));
+  return MODAL_OK;
+}
+
+modal_status modal_fnl_frame(modal_ctx* c, const double* zeta, int k, const int* perm, const double* alpha,
+                             const double* beta, int S, double* E_host, double* sigma2_host, void* ws,
+                             size_t ws_bytes, modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (!zeta || !perm || !alpha || !sigma2_host || S < 0 || (S > 0 && (!beta || !E_host)))
+    return fail(c, MODAL_EINVAL, "fnl_frame: null pointer or S < 0");
+  if (k < 1 || k > c->nmax) return fail(c, MODAL_EINVAL, "fnl_frame: k outside 1..nmax");
+  modal_status s = check_ws(c, MODAL_OP_FNL_FRAME, S, ws, ws_bytes);
+  if (s != MODAL_OK) return s;
+  if ((s = set_device(c)) != MODAL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const int n = c->nmax;
+  Carver cv(ws);
+  double* Zk = (double*)cv.take((size_t)n * n * 8);
+  double* rows = (double*)cv.take((size_t)(S + 1) * n * 8);
+  HIPTRY(launch_gather_sym(n, k, zeta, perm, Zk, st));
+  HIPTRY(launch_gather_cols(n, k, 1, alpha, perm, rows, st));
+  if (S > 0) HIPTRY(launch_gather_cols(n, k, S, beta, perm, rows + k, st));
+  // the estimator on k modes, its own workspace after the gathered arrays
+  void* ws2 = (char*)ws + cv.used;
+  return estimate(c, MODAL_OP_FNL, k, 6.0, Zk, rows, rows + k, k, S, E_host, sigma2_host, nullptr, ws2,
+                  ws_bytes - cv.used, st);
+}
+
 modal_status modal_whiten(modal_ctx* c, const double* L, const double* x, int R, double* y, modal_stream_t stream) {
   if (!c) return MODAL_EINVAL;
   if (R < 0 || (R > 0 && (!L || !x || !y))) return fail(c, MODAL_EINVAL, "whiten: null pointer or R < 0");
@@ -1125,10 +1264,11 @@ modal_status modal_beta_graph_create(int n, modal_ctx* const* ctxs, const void* 
   for (int i = 0; i < n; ++i) {
     modal_ctx* c = ctxs[i];
     if (!c || c->device != dev) return MODAL_EINVAL;
-    if (!alms[i] || !betas[i] || S[i] <= 0) return fail(c, MODAL_EINVAL, "graph: null pointer or S <= 0");
+    const std::string tag = "graph call " + std::to_string(i) + ": ";
+    if (!alms[i] || !betas[i] || S[i] <= 0) return fail(c, MODAL_EINVAL, tag + "null pointer or S <= 0");
     modal_status s = check_state(c, states ? states[i] : nullptr);
-    if (s != MODAL_OK) return s;
-    if ((s = check_ws(c, MODAL_OP_BETA, S[i], ws[i], ws_bytes[i])) != MODAL_OK) return s;
+    if (s == MODAL_OK) s = check_ws(c, MODAL_OP_BETA, S[i], ws[i], ws_bytes[i]);
+    if (s != MODAL_OK) return fail(c, s, tag + c->last_error);
   }
   modal_ctx* c = ctxs[0];
   modal_status s = set_device(c);
@@ -1144,8 +1284,10 @@ modal_status modal_beta_graph_create(int n, modal_ctx* const* ctxs, const void* 
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    for (int i = 0; i < n && rs == MODAL_OK; ++i)
+    for (int i = 0; i < n && rs == MODAL_OK; ++i) {
       rs = modal_beta(ctxs[i], alms[i], S[i], states ? states[i] : nullptr, betas[i], ws[i], ws_bytes[i], cap);
+      if (rs != MODAL_OK) ctxs[i]->last_error = "graph call " + std::to_string(i) + ": " + ctxs[i]->last_error;
+    }
     hipError_t e2 = hipStreamEndCapture(cap, &graph);
     if (e == hipSuccess) e = e2;
   }

@@ -53,20 +53,45 @@ def test_version_without_gpu(lib):
 
 
 def test_create_rejects_bad_arguments_before_touching_the_device(lib):
-    """Argument validation happens before any HIP call, so it runs on the CPU."""
+    """Argument validation, the table-size check included, happens before any HIP call, so
+    it runs on the CPU."""
     import numpy as np
-    lib.modal_create.restype = ctypes.c_int
+    from paper_1105_2791_amd import _lib as L
+    L.lib()   # signatures
     h = ctypes.c_void_p()
     q = np.ones((2, 9))
     cl = np.ones(9)
-    # null q -> EINVAL; ntheta <= lmax -> ESHAPE; odd nphi -> ESHAPE; P < 1 -> EINVAL
-    assert lib.modal_create(ctypes.byref(h), 8, 12, 24, 2, 0, None, cl.ctypes.data_as(ctypes.c_void_p), None) == 1
-    assert lib.modal_create(ctypes.byref(h), 8, 8, 24, 2, 0, q.ctypes.data_as(ctypes.c_void_p),
-                            cl.ctypes.data_as(ctypes.c_void_p), None) == 2
-    assert lib.modal_create(ctypes.byref(h), 8, 12, 25, 2, 0, q.ctypes.data_as(ctypes.c_void_p),
-                            cl.ctypes.data_as(ctypes.c_void_p), None) == 2
-    assert lib.modal_create(ctypes.byref(h), 8, 12, 16, 2, 0, q.ctypes.data_as(ctypes.c_void_p),
-                            cl.ctypes.data_as(ctypes.c_void_p), None) == 2
-    assert lib.modal_create(ctypes.byref(h), 8, 12, 24, 0, 0, q.ctypes.data_as(ctypes.c_void_p),
-                            cl.ctypes.data_as(ctypes.c_void_p), None) == 1
+    qp, cp = q.ctypes.data_as(ctypes.c_void_p), cl.ctypes.data_as(ctypes.c_void_p)
+    fake = ctypes.c_void_p(1 << 20)   # never dereferenced: every call below fails first
+    need = L.lib().modal_ctx_bytes(8, 12, 24, 2, L.F64, 0)
+
+    def create(lmax, nt, nphi, P, prec, flags, q_, tables, nbytes):
+        return L.lib().modal_create(ctypes.byref(h), lmax, nt, nphi, P, prec, flags, q_, cp, None, tables, nbytes)
+    # null q or null tables -> EINVAL; ntheta <= lmax -> ESHAPE; odd nphi -> ESHAPE;
+    # nphi <= 2 lmax -> ESHAPE; P < 1 -> EINVAL; unknown flag -> EINVAL
+    assert create(8, 12, 24, 2, L.F64, 0, None, fake, need) == L.EINVAL
+    assert create(8, 12, 24, 2, L.F64, 0, qp, None, need) == L.EINVAL
+    assert create(8, 8, 24, 2, L.F64, 0, qp, fake, need) == L.ESHAPE
+    assert create(8, 12, 25, 2, L.F64, 0, qp, fake, need) == L.ESHAPE
+    assert create(8, 12, 16, 2, L.F64, 0, qp, fake, need) == L.ESHAPE
+    assert create(8, 12, 24, 0, L.F64, 0, qp, fake, need) == L.EINVAL
+    assert create(8, 12, 24, 2, L.F64, 4, qp, fake, need) == L.EINVAL
+    # a buffer one byte short of the size query -> ENOSPACE
+    assert create(8, 12, 24, 2, L.F64, 0, qp, fake, need - 1) == L.ENOSPACE
     assert h.value is None
+
+
+def test_ctx_bytes_size_query(lib):
+    """modal_ctx_bytes: host only, 256-byte granular, 0 for rejected arguments, and it grows
+    by the lambda table (split precisions only) and with the grid."""
+    from paper_1105_2791_amd import _lib as L
+    f = L.lib().modal_ctx_bytes
+    assert f(8, 8, 24, 2, L.F64, 0) == 0 and f(8, 12, 24, 0, L.F64, 0) == 0 and f(8, 12, 25, 2, L.F64, 0) == 0
+    small = f(32, 48, 96, 8, L.BF16X3, 0)
+    big = f(32, 48, 96, 8, L.BF16X3, L.CTX_LAMBDA_TABLE)
+    assert small > 0 and small % 256 == 0 and big % 256 == 0
+    assert big - small >= 33 * 16384   # at least one 16 KB record per m
+    assert f(32, 48, 96, 8, L.F64, L.CTX_LAMBDA_TABLE) == f(32, 48, 96, 8, L.F64, 0)   # ignored for FP64
+    # the pixel weights alone: FP64 and FP32 planes of npix values
+    assert f(1000, 1536, 3072, 40, L.BF16X3, 0) > 12 * 1536 * 3072
+    assert f(150, 199, 400, 13, L.F32, 0) < f(150, 399, 800, 13, L.F32, 0)
