@@ -81,3 +81,9 @@ def ylm(l: int, m: int, theta, phi) -> np.ndarray:
     if m < 0:
         y = ((-1) ** am) * np.conj(y)
     return y
+
+
+def lambda_table(lmax: int, x):
+    """[lambda_m(m, lmax, x) for m = 0..lmax]: every lambda_lm on the points x, computed once
+    (for repeated transforms on one grid)."""
+    return [lambda_m(m, lmax, x) for m in range(lmax + 1)]

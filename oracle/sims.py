@@ -22,19 +22,28 @@ from .legendre import lambda_m
 from .modal import ring_coefficients, maps_from_ring_coefficients
 
 
-def synth_scalar(alm: np.ndarray, lmax: int, grid: Grid) -> np.ndarray:
-    """f(x) = sum_lm a_lm Y_lm(x) for a real field stored as m >= 0."""
-    F = ring_coefficients(np.atleast_2d(alm), np.ones((1, lmax + 1)), lmax, grid.x)
+def synth_scalar(alm: np.ndarray, lmax: int, grid: Grid, lam=None) -> np.ndarray:
+    """f(x) = sum_lm a_lm Y_lm(x) for a real field stored as m >= 0.  lam: optional
+    ``legendre.lambda_table(lmax, grid.x)`` (the same lambda_lm, computed once)."""
+    if lam is None:
+        F = ring_coefficients(np.atleast_2d(alm), np.ones((1, lmax + 1)), lmax, grid.x)
+        return maps_from_ring_coefficients(F, grid.nphi)[0, 0]
+    F = np.zeros((1, 1, grid.x.size, lmax + 1), dtype=np.complex128)
+    for m in range(lmax + 1):
+        a = alm[mi.alm_index(np.arange(m, lmax + 1), m, lmax)]
+        F[0, 0, :, m] = (a.real @ lam[m]) + 1j * (a.imag @ lam[m])
     return maps_from_ring_coefficients(F, grid.nphi)[0, 0]
 
 
-def analysis(f: np.ndarray, lmax: int, grid: Grid) -> np.ndarray:
-    """a_lm = sum_x dA(x) f(x) Y*_lm(x) with the full-sky quadrature weights."""
+def analysis(f: np.ndarray, lmax: int, grid: Grid, lam=None) -> np.ndarray:
+    """a_lm = sum_x dA(x) f(x) Y*_lm(x) with the full-sky quadrature weights.  lam: optional
+    ``legendre.lambda_table(lmax, grid.x)``."""
     fh = np.fft.rfft(f, axis=-1)[:, :lmax + 1] * (2.0 * math.pi / grid.nphi)   # [nt, L]
     out = np.zeros(mi.nalm(lmax), dtype=np.complex128)
     for m in range(lmax + 1):
-        lam = lambda_m(m, lmax, grid.x)                     # [L_m, nt]
-        out[mi.alm_index(np.arange(m, lmax + 1), m, lmax)] = lam @ (grid.wgl * fh[:, m])
+        lm = lambda_m(m, lmax, grid.x) if lam is None else lam[m]   # [L_m, nt]
+        v = grid.wgl * fh[:, m]
+        out[mi.alm_index(np.arange(m, lmax + 1), m, lmax)] = (lm @ v.real) + 1j * (lm @ v.imag)
     l, m = mi.lm_arrays(lmax)
     out[m == 0] = out[m == 0].real
     return out

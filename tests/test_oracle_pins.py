@@ -374,3 +374,18 @@ def test_ring_chunked_beta_and_linear_term_equal_whole_grid():
         assert np.max(np.abs(lin[s] - ref_l)) < 1e-12 * np.sqrt(np.mean(ref_l ** 2))
     b2, none = om.beta_and_linear_by_rings(alms, None, cl, q, g, rings_per_chunk=25)
     assert none is None and np.allclose(b2, b, rtol=0, atol=1e-12 * np.abs(b).max())
+
+
+def test_sims_cached_lambda_table_is_the_same_transform():
+    """Synthesis and analysis with a lambda table computed once give the same numbers as the
+    per-call recurrence, and the analysis inverts the synthesis on an exact grid."""
+    from oracle import legendre as ol
+    lmax = 16
+    g = og.Grid(26, 52)
+    lam = ol.lambda_table(lmax, g.x)
+    a = mi.gaussian_alm(mi.cl_signal(lmax), lmax, mi.rng_for(9, 0))
+    f1 = osims.synth_scalar(a, lmax, g)
+    f2 = osims.synth_scalar(a, lmax, g, lam)
+    assert np.max(np.abs(f1 - f2)) < 1e-14
+    assert np.max(np.abs(osims.analysis(f1, lmax, g) - osims.analysis(f1, lmax, g, lam))) < 1e-14
+    assert np.max(np.abs(osims.analysis(f2, lmax, g, lam) - a)) < 1e-13
