@@ -109,7 +109,9 @@ typedef enum {
   MODAL_OP_POWER_FNL = 16,
   MODAL_OP_TRISPECTRUM = 17,
   MODAL_OP_FRAME = 18,          /* S ignored                                              */
-  MODAL_OP_FNL_FRAME = 19
+  MODAL_OP_FNL_FRAME = 19,
+  MODAL_OP_COVARIANCE_CENTERED = 20,   /* S is the number N of beta^hat vectors          */
+  MODAL_OP_BETA_LOO = 21
 } modal_op;
 
 typedef enum {
@@ -122,7 +124,8 @@ typedef enum {
 
 typedef enum {
   MODAL_COV_SAMPLE = 0,      /* zeta = (1/(6N)) sum beta^hat beta^hat^T              */
-  MODAL_COV_FISHER = 1       /* zeta = (1/(18N)) sum J C J^T, C = diag dof variance  */
+  MODAL_COV_FISHER = 1,      /* zeta = (1/(18N)) sum J C J^T, C = diag dof variance  */
+  MODAL_COV_SAMPLE_CENTERED = 2   /* zeta = (1/(6(N-1))) sum (b - mean)(b - mean)^T  */
 } modal_cov_method;
 
 typedef enum {
@@ -261,6 +264,21 @@ modal_status modal_linear_term(modal_ctx* ctx, int mode, const void* alm_dev, in
 modal_status modal_beta(modal_ctx* ctx, const void* alm_dev, int S, const void* state_dev,
                         double* beta_dev, void* ws_dev, size_t ws_bytes, modal_stream_t stream);
 
+/* beta^hat of skies that are themselves among the Monte-Carlo skies of the linear
+ * term, with each sky's own maps left out of the pair means it is corrected with
+ * (Sec. II: linear term from simulations; the self-inclusion bias is O(1/N)):
+ *   V^(-i) = (N V - M^i_p M^i_r) / (N - 1),  beta^hat^(-i) = beta_i - lin(a_i; V^(-i))
+ *          = ((N + 2) beta_i - N lin(a_i; V)) / (N - 1),
+ * since the three pairings of M^i_p M^i_r M^i_s sum to 3 beta_i.  N is the number of
+ * skies accumulated into the state.  Every one of the S skies must have been
+ * accumulated exactly once, with these a_lm (the library cannot check this; for other
+ * skies the result is not a leave-one-out term).  Arguments as modal_beta; state_dev
+ * must be finalised.  Workspace: modal_workspace_size(MODAL_OP_BETA_LOO, S).
+ * Errors: EINVAL (null state), ENOTREADY (state not finalised, or N < 2), ENOSPACE,
+ * EDEVICE. */
+modal_status modal_beta_loo(modal_ctx* ctx, const void* alm_dev, int S, const void* state_dev,
+                            double* beta_dev, void* ws_dev, size_t ws_bytes, modal_stream_t stream);
+
 /* Vector-Jacobian product: grad[s] = sum_n cot[s][n] d beta^hat_n / d a_lm
  * (V held fixed), packed as documented above.
  *   cot_dev [S][nmax] float64, grad_dev [S][nalm] complex (alm dtype).
@@ -270,7 +288,11 @@ modal_status modal_beta_vjp(modal_ctx* ctx, const void* alm_dev, int S, const vo
                             modal_stream_t stream);
 
 /* Modal covariance zeta [nmax][nmax] float64 (eq. linearterm).
- *   SAMPLE: beta_dev [N][nmax] beta^hat vectors; zeta = sum b b^T / (6 N).
+ *   SAMPLE: beta_dev [N][nmax] beta^hat vectors; zeta = sum b b^T / (6 N) (no mean
+ *           subtracted: beta^hat has zero mean for Gaussian skies).  No workspace.
+ *   SAMPLE_CENTERED: zeta = sum (b - m)(b - m)^T / (6 (N - 1)), m the mean of the N
+ *           rows (the unbiased estimate when the mean is not known); N >= 2.
+ *           Workspace: modal_workspace_size(MODAL_OP_COVARIANCE_CENTERED, N).
  *   FISHER: alm_dev [N][nalm] maps, state_dev finalised, cvar_host [lmax+1]
  *           the variance C_l of a_lm used as the metric (C_l for a_l0,
  *           C_l / 2 for Re and Im of a_lm, m > 0);

@@ -188,10 +188,27 @@ def beta_and_linear_by_rings(alms, mc_alms, cl, q, grid, rings_per_chunk: int = 
 # covariance and estimator
 # ---------------------------------------------------------------------------
 
-def covariance_sample(beta_hats: np.ndarray) -> np.ndarray:
-    """zeta = (1/(6N)) sum_i beta^hat_i beta^hat_i^T  (eq. linearterm, <beta beta^T> = 6 zeta)."""
+def covariance_sample(beta_hats: np.ndarray, centered: bool = False) -> np.ndarray:
+    """zeta = (1/(6N)) sum_i beta^hat_i beta^hat_i^T  (eq. linearterm, <beta beta^T> = 6 zeta).
+
+    centered: the mean m = (1/N) sum_i beta^hat_i is subtracted first and the sum divided
+    by 6 (N - 1) instead (the unbiased sample covariance when the mean is not known)."""
     B = np.atleast_2d(beta_hats)
-    return B.T @ B / (6.0 * B.shape[0])
+    N = B.shape[0]
+    if not centered:
+        return B.T @ B / (6.0 * N)
+    m = B.sum(axis=0) / N
+    D = B - m[None, :]
+    return D.T @ D / (6.0 * (N - 1))
+
+
+def beta_hat_leave_one_out(Ms: np.ndarray, w: np.ndarray, i: int) -> np.ndarray:
+    """beta^hat of Monte-Carlo sky i with the pair means taken over the other N - 1 skies
+    of ``Ms`` [N, P, ...] (the linear term from simulations, Sec. II, without the sky's own
+    maps): beta(M_i) - lin(M_i; V over j != i)."""
+    Ms = np.asarray(Ms)
+    others = np.concatenate([Ms[:i], Ms[i + 1:]], axis=0)
+    return beta(Ms[i], w) - linear_term(Ms[i], w, pair_means(others))
 
 
 def estimator(zeta: np.ndarray, alpha: np.ndarray, betas: np.ndarray):

@@ -49,6 +49,15 @@ def analysis(f: np.ndarray, lmax: int, grid: Grid, lam=None) -> np.ndarray:
     return out
 
 
+def noise_pixel_variance(grid: Grid, nl: float) -> np.ndarray:
+    """Variance of the white noise in each pixel, sigma^2(theta) Omega_bar / dA(x) with
+    Omega_bar = 4 pi / n_pix (Appendix A: the noise as a pixel-variance map at the
+    mean pixel area; dividing by the pixel's own quadrature area keeps the harmonic
+    noise power at Omega_bar <sigma^2> = nl on unequal-area rings).  Shape [ntheta, nphi]."""
+    sig2 = mi.noise_sigma2(grid.theta, grid.npix, nl)[:, None]
+    return sig2 * (4.0 * math.pi / grid.npix) / grid.area
+
+
 def wmap_like_grid(cfg: mi.Config) -> Grid:
     g0 = Grid(cfg.ntheta, cfg.nphi)
     if cfg.sky == "ideal":
@@ -66,7 +75,6 @@ def sky_sim(cfg: mi.Config, sim_id: int, grid: Grid, lmax: int | None = None) ->
     b = mi.beam(lmax)
     a_sig = mi.gaussian_alm(cl * b * b, lmax, rng)
     f = synth_scalar(a_sig, lmax, grid)
-    nl = mi.noise_level(lmax)
-    var = mi.noise_sigma2(grid.theta, grid.npix, nl)[:, None] * (4.0 * math.pi / grid.npix) / grid.area
+    var = noise_pixel_variance(grid, mi.noise_level(lmax))
     f = f + rng.standard_normal(f.shape) * np.sqrt(var)
     return analysis(f * grid.mask, lmax, grid)

@@ -20,9 +20,9 @@ F64, F32, BF16X3, F16X3 = range(4)
 OP_FILTER_MAPS, OP_BETA, OP_LINEAR_ACCUMULATE, OP_LINEAR_APPLY, OP_BETA_VJP, \
     OP_COVARIANCE_SAMPLE, OP_COVARIANCE_FISHER, OP_FNL, OP_LINEAR_FINALIZE, OP_NOISE_VECTORS, OP_FNL_LOWRANK, \
     OP_ALPHA_SEPARABLE, OP_IDEAL_COVARIANCE, OP_POWER_BETA, OP_POWER_ALPHA, OP_POWER_COVARIANCE, \
-    OP_POWER_FNL, OP_TRISPECTRUM, OP_FRAME, OP_FNL_FRAME = range(20)
+    OP_POWER_FNL, OP_TRISPECTRUM, OP_FRAME, OP_FNL_FRAME, OP_COVARIANCE_CENTERED, OP_BETA_LOO = range(22)
 LIN_RESET, LIN_ACCUMULATE, LIN_FINALIZE, LIN_APPLY = range(4)
-COV_SAMPLE, COV_FISHER = range(2)
+COV_SAMPLE, COV_FISHER, COV_SAMPLE_CENTERED = range(3)
 
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ESHAPE: "ESHAPE", EDEVICE: "EDEVICE", ENOTPD: "ENOTPD",
                 ENOTREADY: "ENOTREADY", EUNSUPPORTED: "EUNSUPPORTED", ENOSPACE: "ENOSPACE"}
@@ -57,6 +57,7 @@ _SIGS = {
     "modal_filter_maps": (ip, [vp, vp, ip, vp, vp, sz, vp]),
     "modal_linear_term": (ip, [vp, ip, vp, ip, vp, vp, vp, sz, vp]),
     "modal_beta": (ip, [vp, vp, ip, vp, vp, vp, sz, vp]),
+    "modal_beta_loo": (ip, [vp, vp, ip, vp, vp, vp, sz, vp]),
     "modal_beta_noalloc": (ip, [vp, vp, ip, vp, vp, vp]),
     "modal_beta_vjp": (ip, [vp, vp, ip, vp, vp, vp, vp, sz, vp]),
     "modal_covariance": (ip, [vp, ip, vp, vp, vp, vp, ip, vp, vp, sz, vp]),

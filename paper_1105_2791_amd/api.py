@@ -157,6 +157,18 @@ class ModalContext:
                                          self._stream()))
         return out
 
+    def beta_loo(self, alm, state, out=None) -> torch.Tensor:
+        """modal_beta_loo: beta^hat of skies that were accumulated into ``state``, each with
+        its own maps left out of the Monte-Carlo pair means."""
+        a = self._alm(alm)
+        S = a.shape[0]
+        if out is None:
+            out = torch.empty((S, self.nmax), dtype=torch.float64, device=self.device)
+        ws = self.workspace(L.OP_BETA_LOO, S)
+        self._check(self._lib.modal_beta_loo(self._h, _ptr(a), S, _ptr(state), _ptr(out), _ptr(ws), ws.numel(),
+                                             self._stream()))
+        return out
+
     def beta_noalloc(self, alm, state=None, out=None) -> torch.Tensor:
         """modal_beta_noalloc: beta with the library's fixed device scratch as workspace."""
         a = self._alm(alm)
@@ -221,12 +233,16 @@ class ModalContext:
                                              ws.numel(), self._stream()))
         return g
 
-    def covariance_sample(self, beta) -> torch.Tensor:
+    def covariance_sample(self, beta, centered: bool = False) -> torch.Tensor:
+        """zeta from beta^hat rows: sum b b^T / (6N), or with the mean subtracted and
+        1 / (6 (N - 1)) when ``centered``."""
         b = torch.as_tensor(beta).to(device=self.device, dtype=torch.float64).contiguous()
         N = b.shape[0]
         z = torch.empty((self.nmax, self.nmax), dtype=torch.float64, device=self.device)
-        ws = self.workspace(L.OP_COVARIANCE_SAMPLE, N)
-        self._check(self._lib.modal_covariance(self._h, L.COV_SAMPLE, _ptr(b), None, None, None, N, _ptr(z),
+        op, method = (L.OP_COVARIANCE_CENTERED, L.COV_SAMPLE_CENTERED) if centered else \
+            (L.OP_COVARIANCE_SAMPLE, L.COV_SAMPLE)
+        ws = self.workspace(op, N)
+        self._check(self._lib.modal_covariance(self._h, method, _ptr(b), None, None, None, N, _ptr(z),
                                                _ptr(ws), ws.numel(), self._stream()))
         return z
 

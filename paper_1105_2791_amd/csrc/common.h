@@ -169,8 +169,8 @@ hipError_t launch_cubic_split(const modal_ctx* c, const void* maps, int S, int n
                               hipStream_t st);
 int cubic_chunk_px(const modal_ctx* c);
 // out[S][nmax] = sum over chunks of part at (pair(pr), s) + scale2 (three pairings of E2)
-hipError_t launch_reduce_single(const modal_ctx* c, const double* part, int S, int nchunk, const double* E2,
-                                double scale2, double* out, hipStream_t st);
+hipError_t launch_reduce_single(const modal_ctx* c, const double* part, int S, int nchunk, double scale,
+                                const double* E2, double scale2, double* out, hipStream_t st);
 // linear term from the harmonic pair means Z[npairs][nalm] (k_lin_harm.hip):
 // X[S][npairs][lmax+1] scratch, L[S][npairs][P] = sum_x w V_ab M^s_t
 hipError_t launch_weight_planes(const modal_ctx* c, const void* V, int nk, void* G, hipStream_t st);
@@ -191,6 +191,7 @@ hipError_t launch_adj_combine(const modal_ctx* c, const void* Z, int S, void* gr
 
 // FP64 dense linear algebra
 hipError_t launch_syrk(int n, int N, const double* B, double scale, double* Z, hipStream_t st);
+hipError_t launch_center_rows(int n, int N, const double* B, double* C, hipStream_t st);
 hipError_t launch_copy_lower(int n, const double* src, double* dst, hipStream_t st);
 // in-place Cholesky of the lower triangle of A (row-major, n x n); flag[0] = 1 + first bad pivot
 hipError_t launch_cholesky(int n, double* A, int* flag, hipStream_t st);

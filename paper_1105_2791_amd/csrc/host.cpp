@@ -166,6 +166,7 @@ size_t ws_size(const modal_ctx* c, int op, int S) {
   switch (op) {
     case MODAL_OP_FILTER_MAPS: cv.take(F_bytes(c, S)); break;
     case MODAL_OP_BETA:
+    case MODAL_OP_BETA_LOO:
       cv.take(F_bytes(c, S)); cv.take(maps_bytes(c, S)); cv.take(part_bytes(c, S)); cv.take(E_bytes(c, S));
       cv.take(X_bytes(c, S)); cv.take(E_bytes(c, S));
       break;
@@ -181,6 +182,7 @@ size_t ws_size(const modal_ctx* c, int op, int S) {
       cv.take((size_t)S * c->P * alm_bytes(c));
       break;
     case MODAL_OP_COVARIANCE_SAMPLE: cv.take(256); break;
+    case MODAL_OP_COVARIANCE_CENTERED: cv.take((size_t)S * c->nmax * 8); break;
     case MODAL_OP_COVARIANCE_FISHER:
       cv.take(F_bytes(c, 1)); cv.take(maps_bytes(c, 1)); cv.take((size_t)c->npairs * c->npix * real_bytes(c));
       cv.take((size_t)c->npairs * c->ntheta * (c->lmax + 1) * 2 * real_bytes(c)); cv.take(lam_bytes(c));
@@ -302,18 +304,20 @@ modal_status run_maps(modal_ctx* c, const void* alm, int S, void* F, void* maps,
 
 // beta (state == nullptr) or beta - lin for S maps: the cubic contraction over
 // pixels, and the linear term from the state's harmonic pair means.
+// out = sb beta + sl lin (lin from the state; sl = -1, sb = 1 gives beta^hat)
 modal_status run_beta(modal_ctx* c, const void* maps, const void* alm, const void* state, int S, double* part,
-                      double* E, double* X, double* L, double* out, hipStream_t st) {
+                      double* E, double* X, double* L, double* out, hipStream_t st, double sb = 1.0,
+                      double sl = -1.0) {
   const bool split = c->prec == MODAL_BF16X3 || c->prec == MODAL_F16X3;
   if (split) STAGE(MODAL_STAGE_CUBIC, launch_cubic_split(c, maps, S, nchunk_for(c), cubic_chunk_px(c), part, st));
   else if (cubic_mfma_available(c)) STAGE(MODAL_STAGE_CUBIC, launch_cubic_mfma(c, maps, S, part, st));
   else STAGE(MODAL_STAGE_CUBIC, launch_cubic_valu(c, maps, S, part, st));
   if (state) STAGE(MODAL_STAGE_LINEAR, launch_lin_harmonic(c, lin_Z(c, state), alm, S, X, L, st));
   if (split)
-    STAGE(MODAL_STAGE_REDUCE, launch_reduce_single(c, part, S, nchunk_for(c), state ? L : nullptr, -1.0, out, st));
+    STAGE(MODAL_STAGE_REDUCE, launch_reduce_single(c, part, S, nchunk_for(c), sb, state ? L : nullptr, sl, out, st));
   else
     STAGE(MODAL_STAGE_REDUCE,
-          launch_reduce_symm(c, part, S, nchunk_for(c), 1.0 / 3.0, E, state ? L : nullptr, -1.0, out, st));
+          launch_reduce_symm(c, part, S, nchunk_for(c), sb / 3.0, E, state ? L : nullptr, sl, out, st));
   return MODAL_OK;
 }
 
@@ -680,7 +684,7 @@ modal_status modal_grid(const modal_ctx* c, double* x_host, double* w_host) {
 }
 
 modal_status modal_workspace_size(const modal_ctx* c, int op, int S, size_t* bytes) {
-  if (!c || !bytes || S < 0 || op < MODAL_OP_FILTER_MAPS || op > MODAL_OP_FNL_FRAME) return MODAL_EINVAL;
+  if (!c || !bytes || S < 0 || op < MODAL_OP_FILTER_MAPS || op > MODAL_OP_BETA_LOO) return MODAL_EINVAL;
   *bytes = ws_size(c, op, S);
   return MODAL_OK;
 }
@@ -717,6 +721,30 @@ modal_status modal_beta(modal_ctx* c, const void* alm, int S, const void* state,
   double* L = (double*)cv.take(E_bytes(c, S));
   if ((s = run_maps(c, alm, S, F, maps, st)) != MODAL_OK) return s;
   return run_beta(c, maps, alm, state, S, part, E, X, L, beta, st);
+}
+
+modal_status modal_beta_loo(modal_ctx* c, const void* alm, int S, const void* state, double* beta, void* ws,
+                            size_t ws_bytes, modal_stream_t stream) {
+  if (!c) return MODAL_EINVAL;
+  if (!alm || !beta || S <= 0) return fail(c, MODAL_EINVAL, "beta_loo: null pointer or S <= 0");
+  if (!state) return fail(c, MODAL_EINVAL, "beta_loo: needs the linear-term state");
+  modal_status s = check_state(c, state);
+  if (s != MODAL_OK) return s;
+  const double N = (double)c->lin_count;
+  if (c->lin_count < 2) return fail(c, MODAL_ENOTREADY, "beta_loo: the state holds fewer than 2 skies");
+  if ((s = check_ws(c, MODAL_OP_BETA_LOO, S, ws, ws_bytes)) != MODAL_OK) return s;
+  if ((s = set_device(c)) != MODAL_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  Carver cv(ws);
+  void* F = cv.take(F_bytes(c, S));
+  void* maps = cv.take(maps_bytes(c, S));
+  double* part = (double*)cv.take(part_bytes(c, S));
+  double* E = (double*)cv.take(E_bytes(c, S));
+  double* X = (double*)cv.take(X_bytes(c, S));
+  double* L = (double*)cv.take(E_bytes(c, S));
+  if ((s = run_maps(c, alm, S, F, maps, st)) != MODAL_OK) return s;
+  // beta - (N lin - 3 beta) / (N - 1): the sky's own pair products removed from the mean
+  return run_beta(c, maps, alm, state, S, part, E, X, L, beta, st, (N + 2.0) / (N - 1.0), -N / (N - 1.0));
 }
 
 modal_status modal_beta_noalloc(modal_ctx* c, const void* alm, int S, const void* state, double* beta,
@@ -847,6 +875,15 @@ modal_status modal_covariance(modal_ctx* c, int method, const double* beta, cons
   if (method == MODAL_COV_SAMPLE) {
     if (!beta) return fail(c, MODAL_EINVAL, "covariance: SAMPLE needs beta");
     STAGE(MODAL_STAGE_COVARIANCE, launch_syrk(c->nmax, N, beta, 1.0 / (6.0 * N), zeta, st));
+    return MODAL_OK;
+  }
+  if (method == MODAL_COV_SAMPLE_CENTERED) {
+    if (!beta) return fail(c, MODAL_EINVAL, "covariance: SAMPLE_CENTERED needs beta");
+    if (N < 2) return fail(c, MODAL_EINVAL, "covariance: SAMPLE_CENTERED needs N >= 2");
+    if ((s = check_ws(c, MODAL_OP_COVARIANCE_CENTERED, N, ws, ws_bytes)) != MODAL_OK) return s;
+    double* B = (double*)ws;
+    STAGE(MODAL_STAGE_COVARIANCE, launch_center_rows(c->nmax, N, beta, B, st));
+    STAGE(MODAL_STAGE_COVARIANCE, launch_syrk(c->nmax, N, B, 1.0 / (6.0 * (N - 1)), zeta, st));
     return MODAL_OK;
   }
   if (method == MODAL_COV_FISHER) {

@@ -95,11 +95,11 @@ __global__ void k_symm(int nmax, int npairs, int P, int S, double scale, const i
   out[(size_t)s * nmax + n] = v;
 }
 
-// out_n = sum_c part[s][c][pair(pr)][s] + scale2 * (three pairings of E2): beta_prs is
-// the single pairing E_{(pr),s} (the contraction writes the modes t >= b only)
+// out_n = scale * sum_c part[s][c][pair(pr)][s] + scale2 * (three pairings of E2): beta_prs
+// is the single pairing E_{(pr),s} (the contraction writes the modes t >= b only)
 __global__ void k_reduce_single(int nmax, int npairs, int P, int nchunk, const int* __restrict__ tri,
-                                const double* __restrict__ part, double scale2, const double* __restrict__ E2,
-                                double* __restrict__ out) {
+                                const double* __restrict__ part, double scale, double scale2,
+                                const double* __restrict__ E2, double* __restrict__ out) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
   if (n >= nmax) return;
@@ -109,6 +109,7 @@ __global__ void k_reduce_single(int nmax, int npairs, int P, int nchunk, const i
   const double* src = part + (size_t)s * nchunk * per + i1;
   double v = 0.0;
   for (int c = 0; c < nchunk; ++c) v += src[(size_t)c * per];
+  v *= scale;
   if (E2) {
     const size_t o = (size_t)s * per;
     v += scale2 * (E2[o + i1] + E2[o + (size_t)tr[4] * P + tr[1]] + E2[o + (size_t)tr[5] * P + tr[0]]);
@@ -118,10 +119,10 @@ __global__ void k_reduce_single(int nmax, int npairs, int P, int nchunk, const i
 
 }  // namespace
 
-hipError_t launch_reduce_single(const modal_ctx* c, const double* part, int S, int nchunk, const double* E2,
-                                double scale2, double* out, hipStream_t st) {
+hipError_t launch_reduce_single(const modal_ctx* c, const double* part, int S, int nchunk, double scale,
+                                const double* E2, double scale2, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_reduce_single, dim3((c->nmax + 255) / 256, S), dim3(256), 0, st, c->nmax, c->npairs, c->P,
-                     nchunk, c->t.tri, part, scale2, E2, out);
+                     nchunk, c->t.tri, part, scale, scale2, E2, out);
   return hipGetLastError();
 }
 

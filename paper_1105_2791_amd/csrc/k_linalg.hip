@@ -240,6 +240,22 @@ __global__ void k_copy_lower(int n, const double* __restrict__ src, double* __re
 
 }  // namespace
 
+// C[i][k] = B[i][k] - (1/N) sum_j B[j][k] (rows of B [N][n]); one thread per column
+__global__ __launch_bounds__(256) void k_center_rows(int n, int N, const double* __restrict__ B,
+                                                     double* __restrict__ C) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double m = 0.0;
+  for (int i = 0; i < N; ++i) m += B[(size_t)i * n + k];
+  m /= N;
+  for (int i = 0; i < N; ++i) C[(size_t)i * n + k] = B[(size_t)i * n + k] - m;
+}
+
+hipError_t launch_center_rows(int n, int N, const double* B, double* C, hipStream_t st) {
+  hipLaunchKernelGGL(k_center_rows, dim3((n + 255) / 256), dim3(256), 0, st, n, N, B, C);
+  return hipGetLastError();
+}
+
 hipError_t launch_syrk(int n, int N, const double* B, double scale, double* Z, hipStream_t st) {
   const int nb = (n + NB - 1) / NB;
   hipLaunchKernelGGL(k_syrk_t, dim3(nb, nb), dim3(256), 0, st, n, N, B, scale, Z);

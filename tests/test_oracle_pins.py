@@ -338,17 +338,92 @@ def test_sims_analysis_inverts_synthesis():
     assert np.max(np.abs(a - b)) < 1e-13
 
 
-def test_p9_pair_mean_fullsky_matches_parseval_expectation():
-    # <M_p M_r> = sum_l (2l+1)/(4 pi) c q_p q_r, checked against the exact average
-    # of sum_x w M_p M_r / (4 pi) over the Gaussian ensemble (Parseval + <|a|^2> = C)
-    lmax, P = 16, 3
+def test_p9_pair_mean_fullsky_is_the_addition_theorem():
+    """<M_p(x) M_r(x)> over isotropic skies with <|a~_lm|^2> = c_l is
+    sum_l c_l q_p q_r sum_m |Y_lm(x)|^2 at every point x.  The m-sum is taken from the
+    oracle's own lambda_lm recurrence (sum over -l..l = lambda_l0^2 + 2 sum_{m>0}
+    lambda_lm^2), so the closed form's (2l+1)/(4 pi) is checked against the harmonics
+    the maps are built from, at several colatitudes."""
+    lmax, P = 24, 4
     q = mi.q_basis(P, lmax)
-    c = (mi.cl_signal(lmax) > 0).astype(float)
+    c = mi.cl_signal(lmax) * (1.0 + np.arange(lmax + 1) % 3)       # any spectrum
     ref = cf.pair_mean_fullsky(q, c)
-    # expectation of Parseval's right-hand side: sum_l q_p q_r (2l+1) c / (4 pi)
-    l = np.arange(lmax + 1)
-    alt = np.array([np.sum(q[p] * q[r] * (2 * l + 1) * c) / (4 * math.pi) for p, r in mi.pair_list(P)])
-    assert np.max(np.abs(ref - alt)) < 1e-14
+    x = np.cos(np.array([0.05, 0.7, 1.3, 1.5707963, 2.4, 3.1]))
+    msum = np.zeros((lmax + 1, x.size))
+    for m in range(lmax + 1):
+        lam = ol.lambda_m(m, lmax, x)                                  # [lmax + 1 - m, nx]
+        msum[m:] += (1.0 if m == 0 else 2.0) * lam ** 2
+    for j in range(x.size):
+        got = np.array([np.sum(c * q[p] * q[r] * msum[:, j]) for p, r in mi.pair_list(P)])
+        assert np.max(np.abs(got - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
+def test_c12_noise_power_of_the_sim_generator():
+    """The generator's pixel noise (variance sigma^2(theta) Omega_bar / dA per pixel,
+    independent pixels) analysed on an unmasked grid has the harmonic power nl at every l:
+    E|a_lm|^2 = sum_x var_x |d a_lm / d f_x|^2, with d a_lm / d f_x the oracle's analysis of
+    a unit impulse (the same on every pixel of a ring up to a phase); the m-average
+    (|a_l0|^2 + 2 sum_{m>0} |a_lm|^2) / (2l + 1) must be nl = Omega_bar <sigma^2>."""
+    lmax = 20
+    g = og.Grid(40, 80)
+    nl = 3.7e-6
+    var = osims.noise_pixel_variance(g, nl)
+    E = np.zeros(mi.nalm(lmax))
+    for j in range(g.x.size):
+        f = np.zeros((g.x.size, g.nphi))
+        f[j, 0] = 1.0
+        E += g.nphi * var[j, 0] * np.abs(osims.analysis(f, lmax, g)) ** 2
+    l, m = mi.lm_arrays(lmax)
+    for ll in range(lmax + 1):
+        per_l = (E[(l == ll) & (m == 0)].sum() + 2.0 * E[(l == ll) & (m > 0)].sum()) / (2 * ll + 1)
+        assert abs(per_l / nl - 1.0) < 1e-12, (ll, per_l / nl)
+    # a Monte-Carlo draw of the same noise agrees within its scatter
+    rng = np.random.default_rng(3)
+    acc = np.zeros(mi.nalm(lmax))
+    n = 40
+    for _ in range(n):
+        acc += np.abs(osims.analysis(rng.standard_normal(var.shape) * np.sqrt(var), lmax, g)) ** 2
+    assert abs(np.sum(acc / n) / np.sum(E) - 1.0) < 0.05
+
+
+def test_centered_sample_covariance():
+    """The mean-subtracted sample covariance: numpy's own unbiased covariance / 6; for
+    N = 2 it is (b1 - b2)(b1 - b2)^T / 12; a common shift of all rows changes nothing; for
+    rows of zero sample mean it is N / (N - 1) times the uncentered covariance."""
+    rng = np.random.default_rng(11)
+    B = rng.standard_normal((7, 5))
+    Z = om.covariance_sample(B, centered=True)
+    assert np.max(np.abs(Z - np.cov(B, rowvar=False, ddof=1) / 6.0)) < 1e-15
+    d = B[0] - B[1]
+    assert np.max(np.abs(om.covariance_sample(B[:2], centered=True) - np.outer(d, d) / 12.0)) < 1e-15
+    shift = rng.standard_normal(5) * 10
+    assert np.max(np.abs(om.covariance_sample(B + shift, centered=True) - Z)) < 1e-13
+    B0 = B - B.mean(axis=0)
+    assert np.max(np.abs(om.covariance_sample(B0, centered=True) * 6 / 7 - om.covariance_sample(B0))) < 1e-15
+
+
+def test_leave_one_out_beta_hat():
+    """beta^hat with sky i's own maps left out of the pair means equals
+    ((N + 2) beta_i - N lin_i(V over all N)) / (N - 1): V^(-i) = (N V - M_p M_r) / (N - 1)
+    and the three pairings of M_p M_r M_s sum to 3 beta.  For N = 2 the other sky alone
+    makes the pair means."""
+    lmax, nt, nphi, P = 12, 20, 40, 4
+    g = og.Grid(nt, nphi)
+    cl = mi.filter_cl(lmax, "wmap")
+    q = mi.q_basis(P, lmax)
+    alms = np.array([mi.gaussian_alm(cl, lmax, mi.rng_for(5, i)) for i in range(4)])
+    Ms = om.filtered_maps(alms, cl, q, g)
+    N = Ms.shape[0]
+    V = om.pair_means(Ms)
+    for i in range(N):
+        loo = om.beta_hat_leave_one_out(Ms, g.w, i)
+        b = om.beta(Ms[i], g.w)
+        lin = om.linear_term(Ms[i], g.w, V)
+        alt = ((N + 2) * b - N * lin) / (N - 1)
+        assert np.max(np.abs(loo - alt)) < 1e-12 * np.max(np.abs(b))
+    two = om.beta_hat_leave_one_out(Ms[:2], g.w, 0)
+    ref = om.beta(Ms[0], g.w) - om.linear_term(Ms[0], g.w, om.pair_means(Ms[1:2]))
+    assert np.max(np.abs(two - ref)) < 1e-13 * np.max(np.abs(ref))
 
 
 def test_ring_chunked_beta_and_linear_term_equal_whole_grid():
