@@ -106,6 +106,92 @@ __global__ __launch_bounds__(64) void k_adj_legendre_cols(int lmax, int ntheta, 
   }
 }
 
+// The same sums on the matrix cores for FP32 operands: per m a GEMM
+//   Z[l][c] = sum_j lambda[m][j][l] H_{(l - m) mod 2}[j][c],  H_0 = Gh_N + Gh_S, H_1 = Gh_N - Gh_S,
+// with K = the northern rings and the real and imaginary parts of the columns as
+// separate GEMM columns.  v_mfma_f32_32x32x2f32 (lane l holds A[l % 32][l / 32],
+// B[l / 32][l % 32]; accumulator register r is D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]).
+// A workgroup owns 64 consecutive l - m (32 even and 32 odd: one tile each) of one m and
+// 64 complex columns; wave w owns the columns [16 w, 16 w + 16) as 32 GEMM columns.  A
+// lane reads the even and odd lambda of its row from the table row of its ring; the
+// folded ring values of 32 rings are staged in LDS for all four waves.  The MFMAs of a
+// staged chunk accumulate from zero and the chunk joins the running FP32 sum with a
+// round-to-nearest add.
+constexpr int AL_RC = 32;   // rings per staged chunk
+constexpr int AL_NC = 64;   // complex columns per workgroup
+
+__global__ __launch_bounds__(256) void k_adj_legendre_mfma(int lmax, int ntheta, int nrp, int ncol, int nalm,
+                                                           const float* __restrict__ lam, const float2* __restrict__ Gh,
+                                                           float* __restrict__ Z) {
+  typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+  const int m = blockIdx.y;
+  const int L = lmax + 1 - m;
+  const int ib = blockIdx.x * 32;   // row i of a tile is l - m = 2 (ib + i) + parity
+  if (2 * ib >= L) return;          // whole workgroup: no barrier reached
+  const int c0 = blockIdx.z * AL_NC;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int row = lane & 31, kh = lane >> 5;
+  const size_t off = (size_t)m * (2 * lmax + 3 - m) / 2;
+  const float* lrow = lam + off * nrp;
+  __shared__ float2 hp[AL_RC][AL_NC + 1], hm[AL_RC][AL_NC + 1];
+  f32x16 acc[2], cha[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[t][r] = cha[t][r] = 0.f;
+  const int li = 2 * (ib + row);             // this lane's even A row; the odd one is li + 1
+  const bool ok0 = li < L, ok1 = li + 1 < L;
+  const int bc = 16 * wv + (row >> 1);       // this lane's B (and D) column: complex column, part
+  const int part = row & 1;
+  for (int j0 = 0; j0 < nrp; j0 += AL_RC) {
+    const int nj = min(AL_RC, nrp - j0);
+    __syncthreads();
+    for (int e = tid; e < AL_RC * AL_NC; e += 256) {   // consecutive threads: consecutive rings
+      const int jj = e % AL_RC, q = e / AL_RC;
+      float2 vn = make_float2(0.f, 0.f), vs = make_float2(0.f, 0.f);
+      const int col = c0 + q, j = j0 + jj;
+      if (jj < nj && col < ncol) {
+        const float2* g = Gh + ((size_t)col * (lmax + 1) + m) * ntheta;   // Gh[col][m][ring]
+        vn = g[j];
+        const int js = ntheta - 1 - j;
+        if (js != j) vs = g[js];
+      }
+      hp[jj][q] = make_float2(vn.x + vs.x, vn.y + vs.y);
+      hm[jj][q] = make_float2(vn.x - vs.x, vn.y - vs.y);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k2 = 0; k2 < AL_RC / 2; ++k2) {
+      const int jj = 2 * k2 + kh;
+      float a0 = 0.f, a1 = 0.f;
+      if (jj < nj) {
+        const float* lp = lrow + (size_t)(j0 + jj) * L + li;
+        if (ok0) a0 = lp[0];
+        if (ok1) a1 = lp[1];
+      }
+      const float2 he = hp[jj][bc], ho = hm[jj][bc];
+      cha[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, part ? he.y : he.x, cha[0], 0, 0, 0);
+      cha[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, part ? ho.y : ho.x, cha[1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      acc[t] += cha[t];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) cha[t][r] = 0.f;
+    }
+  }
+  const int col = c0 + bc;
+  if (col >= ncol) return;
+  const float cm = (m == 0) ? 1.f : 2.f;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int lr = 2 * (ib + 8 * (r >> 2) + 4 * kh + (r & 3)) + t;
+      if (lr < L) Z[((size_t)col * nalm + off + lr) * 2 + part] = (m == 0 && part) ? 0.f : cm * acc[t][r];
+    }
+}
+
 // X[l][a][b] += C_l [Re Za Re Zb (m=0) + 1/2 sum_{m>=1} (Re Za Re Zb + Im Za Im Zb)], 64x64 tiles, lower tiles only.
 constexpr int XT = 64;
 constexpr int MC = 16;
@@ -226,13 +312,15 @@ hipError_t launch_pair_maps(const modal_ctx* c, const void* maps, const void* V,
 
 hipError_t launch_adj_legendre_cols(const modal_ctx* c, const void* lam, const void* Gh, int ncol, void* Z,
                                     hipStream_t st) {
-  dim3 grid((c->lmax + 1 + 63) / 64, c->lmax + 1, (ncol + NC - 1) / NC);
-  if (is_f64(c))
+  if (is_f64(c)) {
+    dim3 grid((c->lmax + 1 + 63) / 64, c->lmax + 1, (ncol + NC - 1) / NC);
     hipLaunchKernelGGL(k_adj_legendre_cols<double>, grid, dim3(64), 0, st, c->lmax, c->ntheta, c->nrp, ncol, c->nalm,
                        (const double*)lam, (const double2*)Gh, (double2*)Z);
-  else
-    hipLaunchKernelGGL(k_adj_legendre_cols<float>, grid, dim3(64), 0, st, c->lmax, c->ntheta, c->nrp, ncol, c->nalm,
-                       (const float*)lam, (const float2*)Gh, (float2*)Z);
+  } else {
+    dim3 grid((c->lmax + 1 + 63) / 64, c->lmax + 1, (ncol + AL_NC - 1) / AL_NC);
+    hipLaunchKernelGGL(k_adj_legendre_mfma, grid, dim3(256), 0, st, c->lmax, c->ntheta, c->nrp, ncol, c->nalm,
+                       (const float*)lam, (const float2*)Gh, (float*)Z);
+  }
   return hipGetLastError();
 }
 
