@@ -105,6 +105,9 @@ __global__ __launch_bounds__(256) void k_pair_adjoint(int P, int npairs, int npi
 // accumulator register r is D[4 (l / 16) + r][l % 16]).  A = K of a 64-pair chunk (FP32,
 // in LDS), B = the pair product of the lane's pixel and pair, formed on the fly.  Each
 // chunk is a chain of 16 MFMAs from zero, added to the running sums with a vector add.
+// The S skies of one pixel block are consecutive workgroups on one XCD (workgroups are
+// dealt to the 8 XCDs round-robin), so the pair means V, the same for every sky, come
+// from HBM once per block and from that XCD's L2 for the other skies.
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 constexpr int kMx = 128;  // pixels per workgroup (32 per wave: two 16-column tiles)
 constexpr int kMc = 64;   // pairs per staged chunk (16 MFMA steps of 4)
@@ -116,8 +119,12 @@ __global__ __launch_bounds__(256) void k_pair_adjoint_mfma(int P, int npairs, in
                                                            const int* __restrict__ pair_b,
                                                            const float* __restrict__ maps,
                                                            const float* __restrict__ V, const float* __restrict__ w,
-                                                           const double* __restrict__ K, float* __restrict__ G) {
-  const int s = blockIdx.y, x0 = blockIdx.x * kMx;
+                                                           const double* __restrict__ K, float* __restrict__ G,
+                                                           int S, int nblk) {
+  const int i8 = blockIdx.x >> 3;
+  const int blk = (blockIdx.x & 7) + 8 * (i8 / S);
+  if (blk >= nblk) return;   // whole workgroup, before any barrier
+  const int s = i8 % S, x0 = blk * kMx;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int l16 = lane & 15, kq = lane >> 4;
   const int xl0 = wv * 32 + l16, xl1 = xl0 + 16;   // this lane's pixels within the block
@@ -233,13 +240,16 @@ hipError_t launch_pair_adjoint(const modal_ctx* c, const void* maps, const void*
     if (V) LAUNCH(double, true, 1, c->t.w64);
     else LAUNCH(double, false, 1, c->t.w64);
   } else if (c->P <= kMt * 16) {
-    const dim3 grid((c->npix + kMx - 1) / kMx, S);
+    const int nblk = (c->npix + kMx - 1) / kMx;
+    const dim3 grid(8 * ((nblk + 7) / 8) * S);
     if (V)
       hipLaunchKernelGGL(k_pair_adjoint_mfma<true>, grid, dim3(256), 0, st, c->P, c->npairs, c->npix, c->t.pair_a,
-                         c->t.pair_b, (const float*)maps, (const float*)V, c->t.w32, (const double*)K, (float*)G);
+                         c->t.pair_b, (const float*)maps, (const float*)V, c->t.w32, (const double*)K, (float*)G, S,
+                         nblk);
     else
       hipLaunchKernelGGL(k_pair_adjoint_mfma<false>, grid, dim3(256), 0, st, c->P, c->npairs, c->npix, c->t.pair_a,
-                         c->t.pair_b, (const float*)maps, (const float*)V, c->t.w32, (const double*)K, (float*)G);
+                         c->t.pair_b, (const float*)maps, (const float*)V, c->t.w32, (const double*)K, (float*)G, S,
+                         nblk);
   } else {
     if (V) LAUNCH(float, true, 2, c->t.w32);
     else LAUNCH(float, false, 2, c->t.w32);

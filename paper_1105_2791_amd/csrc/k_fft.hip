@@ -531,6 +531,77 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int 
   }
 }
 
+// r2c, register passes (the adjoint of k_fft_c2r_rg): same persistent ring-group order,
+// one wave per ring.  z_n = G_{2n} + i G_{2n+1} goes into the ring buffer conjugated, so
+// the e^{+i} passes above give conj of Z_m = sum_n z_n e^{-2 pi i m n / K}; after a
+// workgroup barrier every thread forms Gh_m of one (m, ring) of the four rings from
+// Z_m and Z_{K-m} (see the top of the file), and consecutive threads write the four
+// rings of one m, the contiguous run of the [seq][m][ring] layout.
+template <int PTS>
+__global__ __launch_bounds__(64 * RG_RINGS) void k_fft_r2c_rg(FftPlan plan, int lmax, int ntheta, int nseq,
+                                                              const float* __restrict__ G, float2* __restrict__ Gh,
+                                                              const float2* __restrict__ twg,
+                                                              const float2* __restrict__ twpg) {
+  extern __shared__ __attribute__((aligned(16))) float2 rbuf[];
+  const int K = plan.K;
+  const int KP = padr(K) + 1;
+  float2* tw = rbuf + RG_RINGS * KP;
+  float2* twp = tw + K / 2 + 1;
+  const int nrb8 = f_ring_blocks(ntheta);
+  const int units = nseq * nrb8;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int t = tid; t <= K / 2; t += 64 * RG_RINGS) tw[t] = twg[t];
+  for (int t = tid; t < K - 1; t += 64 * RG_RINGS) twp[t] = twpg[t];
+  const int b = blockIdx.x;
+  const int xcd = b & 7, half = (b >> 3) & 1, slot = b >> 4;
+  const int nslot = gridDim.x >> 4;
+  for (int unit = xcd + 8 * slot; unit < units; unit += 8 * nslot) {
+    const int seq = unit / nrb8, rb = unit - seq * nrb8;
+    // the previous unit's reads of all four buffers (and the twiddle tables) are settled
+    lds_barrier();
+    const int jb = rb * 8 + RG_RINGS * half;
+    const int j = jb + w;
+    float2* bw = rbuf + w * KP;
+    if (j < ntheta) {   // wave-uniform
+      const float2* src = reinterpret_cast<const float2*>(G + ((size_t)seq * ntheta + j) * plan.N);
+      for (int n = lane; n < K; n += 64) {
+        const float2 v = src[n];
+        bw[padr(n)] = make_float2(v.x, -v.y);
+      }
+      int Ns = 1;
+      const float2* tf = twp;
+      for (int f = 0; f < plan.nf; ++f) {
+        const int R = plan.radix[f];
+        if (R == 24) rg_pass<24, PTS>(bw, K, Ns, lane, tf);
+        else if (R == 8) rg_pass<8, PTS>(bw, K, Ns, lane, tf);
+        else if (R == 4) rg_pass<4, PTS>(bw, K, Ns, lane, tf);
+        else if (R == 2) rg_pass<2, PTS>(bw, K, Ns, lane, tf);
+        else if (R == 3) rg_pass<3, PTS>(bw, K, Ns, lane, tf);
+        else rg_pass<5, PTS>(bw, K, Ns, lane, tf);
+        tf += (R - 1) * Ns;
+        Ns *= R;
+      }
+    }
+    lds_barrier();   // the four rings' spectra are in LDS
+    float2* dst = Gh + (size_t)seq * (lmax + 1) * ntheta;
+    for (int e = tid; e < (lmax + 1) * RG_RINGS; e += 64 * RG_RINGS) {
+      const int m = e / RG_RINGS, r = e - m * RG_RINGS;
+      if (jb + r >= ntheta) continue;
+      const float2* br = rbuf + r * KP;
+      const float2 cz = br[padr(m)], cw = br[padr((K - m) % K)];   // conj Z_m, conj Z_{K-m}
+      const float2 zk = make_float2(cz.x, -cz.y);
+      const float2 a = make_float2(zk.x + cw.x, zk.y + cw.y);   // Z_m + conj Z_{K-m}
+      const float2 d = make_float2(zk.x - cw.x, zk.y - cw.y);   // Z_m - conj Z_{K-m}
+      const float2 ew = (m <= K / 2) ? tw[m] : make_float2(-tw[K - m].x, tw[K - m].y);   // e^{2 pi i m / N}
+      float2 g;
+      g.x = 0.5f * (a.x + (ew.x * d.y - ew.y * d.x));
+      g.y = 0.5f * (a.y - (ew.x * d.x + ew.y * d.y));
+      dst[(size_t)m * ntheta + j - w + r] = g;
+    }
+  }
+}
+
 }  // namespace
 
 int fft_rings_max(const modal_ctx* c) {
@@ -609,6 +680,10 @@ hipError_t fft_rg_set_lds(size_t bytes) {
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_fft_c2r_rg<24>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_fft_c2r_rg<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_fft_c2r_rg<48>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  const void* r2c[] = {(const void*)k_fft_r2c_rg<16>, (const void*)k_fft_r2c_rg<24>, (const void*)k_fft_r2c_rg<32>,
+                       (const void*)k_fft_r2c_rg<48>};
+  for (const void* f : r2c)
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   return e;
 }
 
@@ -660,6 +735,22 @@ hipError_t launch_fft_r2c(const modal_ctx* c, const void* G, int S, void* Gh, hi
 
 // nseq sequences of ntheta ring rows each
 hipError_t launch_fft_r2c_rows(const modal_ctx* c, const void* G, size_t nseq, void* Gh, hipStream_t st) {
+  if (c->fft_rg) {
+    const int units = (int)nseq * f_ring_blocks(c->ntheta);
+    int blocks = 16 * ((units + 7) / 8);
+    blocks = std::min(blocks, 16 * 64);
+    const int pts = fft_rg_points(c->fft_rg_plan);
+#define LAUNCH(PT)                                                                                                \
+  hipLaunchKernelGGL(k_fft_r2c_rg<PT>, dim3(blocks), dim3(64 * RG_RINGS), fft_rg_lds(c), st, c->fft_rg_plan,        \
+                     c->lmax, c->ntheta, (int)nseq, (const float*)G, (float2*)Gh, (const float2*)c->t.tw32,       \
+                     (const float2*)c->t.twp32)
+    if (pts <= 16) LAUNCH(16);
+    else if (pts <= 24) LAUNCH(24);
+    else if (pts <= 32) LAUNCH(32);
+    else LAUNCH(48);
+#undef LAUNCH
+    return hipGetLastError();
+  }
   const int R = fft_rings_per_block(c);
   const size_t blocks = nseq * ((c->ntheta + R - 1) / R);
   const size_t lds = (size_t)R * 2 * c->fft.K * 2 * real_bytes(c);

@@ -106,7 +106,7 @@ __global__ __launch_bounds__(64) void k_adj_legendre_cols(int lmax, int ntheta, 
   }
 }
 
-// The same sums on the matrix cores for FP32 operands: per m a GEMM
+// The same sums on the matrix cores for the split-precision contexts: per m a GEMM
 //   Z[l][c] = sum_j lambda[m][j][l] H_{(l - m) mod 2}[j][c],  H_0 = Gh_N + Gh_S, H_1 = Gh_N - Gh_S,
 // with K = the northern rings and the real and imaginary parts of the columns as
 // separate GEMM columns.  v_mfma_f32_32x32x2f32 (lane l holds A[l % 32][l / 32],
@@ -116,7 +116,11 @@ __global__ __launch_bounds__(64) void k_adj_legendre_cols(int lmax, int ntheta, 
 // lane reads the even and odd lambda of its row from the table row of its ring; the
 // folded ring values of 32 rings are staged in LDS for all four waves.  The MFMAs of a
 // staged chunk accumulate from zero and the chunk joins the running FP32 sum with a
-// round-to-nearest add.
+// round-to-nearest add.  The matrix core's FP32 accumulation raised the FP32-context
+// linear term's error against the oracle from 2.7e-6 to 6.5e-6 of rms (its bound is
+// 1e-5; a running FP64 sum did not lower it and cost 25 %), so FP32 contexts keep the
+// FP64 vector sums above; the split contexts, whose operands carry 2^-16 (bf16x3) or
+// 2^-22 (f16x3), take this kernel.
 constexpr int AL_RC = 32;   // rings per staged chunk
 constexpr int AL_NC = 64;   // complex columns per workgroup
 
@@ -316,6 +320,10 @@ hipError_t launch_adj_legendre_cols(const modal_ctx* c, const void* lam, const v
     dim3 grid((c->lmax + 1 + 63) / 64, c->lmax + 1, (ncol + NC - 1) / NC);
     hipLaunchKernelGGL(k_adj_legendre_cols<double>, grid, dim3(64), 0, st, c->lmax, c->ntheta, c->nrp, ncol, c->nalm,
                        (const double*)lam, (const double2*)Gh, (double2*)Z);
+  } else if (c->prec == MODAL_F32) {
+    dim3 grid((c->lmax + 1 + 63) / 64, c->lmax + 1, (ncol + NC - 1) / NC);
+    hipLaunchKernelGGL(k_adj_legendre_cols<float>, grid, dim3(64), 0, st, c->lmax, c->ntheta, c->nrp, ncol, c->nalm,
+                       (const float*)lam, (const float2*)Gh, (float2*)Z);
   } else {
     dim3 grid((c->lmax + 1 + 63) / 64, c->lmax + 1, (ncol + AL_NC - 1) / AL_NC);
     hipLaunchKernelGGL(k_adj_legendre_mfma, grid, dim3(256), 0, st, c->lmax, c->ntheta, c->nrp, ncol, c->nalm,

@@ -4,168 +4,104 @@
 //   zeta = L L^T, y = L^-1 alpha, z_s = L^-1 beta_s          (eq. Cholrot)
 //   E_s = y.z_s / y.y,  sigma^2 = 6 / y.y                    (eqs. modalest, modalvariance)
 //
-// MI355X runs FP64 FMA on the vector ALUs at the same rate as its FP64 matrix
-// cores (78.6 TFLOP/s each), so these kernels are register-tiled VALU code:
-// 64x64 output tiles, 4x4 per thread, k-chunks of 16 staged in LDS.
-// The Cholesky is right-looking with 64-wide panels: diagonal block factored in
-// LDS by one workgroup, panel solved row-per-thread, trailing lower triangle
-// updated tile by tile.  A non-positive (or NaN) pivot is recorded in flag[0]
-// as 1 + its index; later steps then carry NaN and the host reports ENOTPD.
+// The products run on the FP64 matrix cores (v_mfma_f64_16x16x4_f64: lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16], accumulator register r is
+// D[4 r + l / 16][l % 16], checked on the device).  The sample covariance and the Cholesky's trailing update
+// are one lower-triangle tile kernel (64 x 64 tiles, four waves of 32 x 32, 16 k per
+// LDS stage).  The Cholesky is right-looking with 64-wide panels: the diagonal block is
+// factored in LDS by one workgroup, which also inverts it (W = L_kk^-1, kept in the
+// block's unused upper triangle); the panel is then the product A_panel W^T on the matrix
+// cores instead of a row-by-row substitution.  A non-positive (or NaN) pivot is recorded
+// in flag[0] as 1 + its index; later steps then carry NaN and the host reports ENOTPD.
 #include "common.h"
 
 namespace modal {
 namespace {
 
 constexpr int NB = 64;
-constexpr int KC = 16;
 
-// C[i][j] = alpha * sum_k X[k][i] X[k][j] over rows k of X [N][n], for the
-// tile (bi, bj), bi >= bj; mirrored into the upper triangle.
-__global__ __launch_bounds__(256) void k_syrk_t(int n, int N, const double* __restrict__ X, double alpha,
-                                                double* __restrict__ C) {
-  const int bi = blockIdx.y, bj = blockIdx.x;
-  if (bj > bi) return;
-  const int i0 = bi * NB, j0 = bj * NB;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  __shared__ double Xi[KC][NB + 1];
-  __shared__ double Xj[KC][NB + 1];
-  double acc[4][4] = {};
-  for (int k0 = 0; k0 < N; k0 += KC) {
-    for (int e = threadIdx.x; e < KC * NB; e += 256) {
-      const int kk = e / NB, c = e - kk * NB;
-      const int k = k0 + kk;
-      Xi[kk][c] = (k < N && i0 + c < n) ? X[(size_t)k * n + i0 + c] : 0.0;
-      Xj[kk][c] = (k < N && j0 + c < n) ? X[(size_t)k * n + j0 + c] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < KC; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a[u] = Xi[kk][ty * 4 + u];
-        b[u] = Xj[kk][tx * 4 + u];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = i0 + ty * 4 + u, j = j0 + tx * 4 + v;
-      if (i < n && j < n) {
-        C[(size_t)i * n + j] = alpha * acc[u][v];
-        C[(size_t)j * n + i] = alpha * acc[u][v];
-      }
-    }
-}
-
-// Factor the diagonal block A[k0:k0+kb, k0:k0+kb] in place (lower triangle).
+// Factor the diagonal block A[k0:k0+kb, k0:k0+kb] in place (lower triangle) and invert it.
+// 256 threads: thread (i, q) holds the columns c = 4 cc + q (cc < 16) of row i in
+// registers.  Step j: the owner of a_jj publishes the pivot, the owners of column j scale
+// it and publish it (LDS, double-buffered by the parity of j), and every thread updates
+// its elements a_ic -= a_ij a_cj (j < c <= i).  Then W = L^-1 by columns, four threads per
+// column (W and L in LDS):
+//   W[c][c] = 1 / L_cc,  W[q][c] = -(sum_{c <= k < q} L_qk W[k][c]) / L_qq  (q > c);
+// W's strictly lower part goes to the block's upper triangle, transposed
+// (A[k0 + c][k0 + q] = W[q][c]).  Rows and columns past kb are an identity block.
 __global__ __launch_bounds__(256) void k_potrf_diag(int n, double* __restrict__ A, int k0, int kb, int* flag) {
-  __shared__ double a[NB][NB + 1];
-  for (int e = threadIdx.x; e < NB * NB; e += 256) {
-    const int i = e / NB, j = e - i * NB;
-    a[i][j] = (i < kb && j < kb) ? A[(size_t)(k0 + i) * n + k0 + j] : 0.0;
+  __shared__ double piv[2];
+  __shared__ double colj[2][NB];
+  __shared__ double Ls[NB][NB + 1];
+  __shared__ double Ws[NB][NB + 1];
+  const int t = threadIdx.x, i = t >> 2, q = t & 3;
+  double r[NB / 4];
+  // loads unconditional (indices clamped into the block, values selected after), so that
+  // they are all in flight together
+  const double* arow = A + (size_t)(k0 + min(i, kb - 1)) * n + k0;
+#pragma unroll
+  for (int cc = 0; cc < NB / 4; ++cc) {
+    const int c = 4 * cc + q;
+    const double v = arow[min(c, kb - 1)];
+    r[cc] = (i < kb && c < kb && c <= i) ? v : (c == i ? 1.0 : 0.0);
+  }
+  for (int j = 0; j < NB; ++j) {
+    const int jb = j & 1, jc = j >> 2;
+    const bool owns_col = q == (j & 3);
+    double aij = 0.0;   // this thread's a_ij when it owns column j
+#pragma unroll
+    for (int cc = 0; cc < NB / 4; ++cc)
+      if (cc == jc) aij = r[cc];
+    if (owns_col && i == j) {
+      const bool ok = aij > 0.0;
+      if (!ok && j < kb) atomicCAS(flag, 0, k0 + j + 1);
+      piv[jb] = ok ? sqrt(aij) : __builtin_nan("");
+    }
+    __syncthreads();
+    if (owns_col) {
+      const double d = piv[jb];
+      const double l = i > j ? aij / d : (i == j ? d : 0.0);
+#pragma unroll
+      for (int cc = 0; cc < NB / 4; ++cc)
+        if (cc == jc) r[cc] = l;
+      colj[jb][i] = l;
+    }
+    __syncthreads();
+    const double lij = colj[jb][i];
+    double lc[NB / 4];   // read first, all at once; the update is selected after
+#pragma unroll
+    for (int cc = 0; cc < NB / 4; ++cc) lc[cc] = colj[jb][4 * cc + q];
+#pragma unroll
+    for (int cc = 0; cc < NB / 4; ++cc) {
+      const int c = 4 * cc + q;
+      const double upd = r[cc] - lij * lc[cc];
+      r[cc] = (c > j && c <= i) ? upd : r[cc];
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < NB / 4; ++cc) {
+    const int c = 4 * cc + q;
+    Ls[i][c] = c <= i ? r[cc] : 0.0;
+    if (i < kb && c < kb && c <= i) A[(size_t)(k0 + i) * n + k0 + c] = r[cc];
   }
   __syncthreads();
-  for (int j = 0; j < kb; ++j) {
-    if (threadIdx.x == 0) {
-      const double d = a[j][j];
-      if (!(d > 0.0)) {
-        atomicCAS(flag, 0, k0 + j + 1);
-        a[j][j] = __builtin_nan("");
-      } else {
-        a[j][j] = sqrt(d);
-      }
+  // four threads per column c = t / 4 (one wave holds 16 columns), thread part t % 4
+  // summing k = part mod 4; the sum is combined across the four lanes
+  const int c = t >> 2, part = t & 3;
+  for (int qq = 0; qq < NB; ++qq) {
+    double v = 0.0;
+#pragma unroll 4
+    for (int k = part; k < qq; k += 4) {
+      const double term = Ls[qq][k] * Ws[k][c];
+      v += k >= c ? term : 0.0;
     }
-    __syncthreads();
-    const double djj = a[j][j];
-    for (int i = j + 1 + threadIdx.x; i < kb; i += 256) a[i][j] /= djj;
-    __syncthreads();
-    // trailing update inside the block: a[i][c] -= a[i][j] a[c][j], j < c <= i
-    for (int e = threadIdx.x; e < kb * kb; e += 256) {
-      const int i = e / kb, c = e - i * kb;
-      if (c > j && i >= c) a[i][c] -= a[i][j] * a[c][j];
-    }
-    __syncthreads();
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    const double inv = 1.0 / Ls[qq][qq];
+    if (part == 0) Ws[qq][c] = qq > c ? -v * inv : (qq == c ? inv : 0.0);
   }
-  for (int e = threadIdx.x; e < kb * kb; e += 256) {
-    const int i = e / kb, j = e - i * kb;
-    if (j <= i) A[(size_t)(k0 + i) * n + k0 + j] = a[i][j];
-  }
-}
-
-// Panel: rows i >= k0 + kb, A[i, k0:k0+kb] <- A[i, k0:k0+kb] L_kk^-T (one row per thread).
-__global__ __launch_bounds__(64) void k_trsm_panel(int n, double* __restrict__ A, int k0, int kb) {
-  __shared__ double L[NB][NB + 1];
-  for (int e = threadIdx.x; e < NB * NB; e += 64) {
-    const int i = e / NB, j = e - i * NB;
-    L[i][j] = (i < kb && j < kb) ? A[(size_t)(k0 + i) * n + k0 + j] : (i == j ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  const int i = k0 + kb + blockIdx.x * 64 + threadIdx.x;
-  if (i >= n) return;
-  double x[NB];
-  double* row = A + (size_t)i * n + k0;
-#pragma unroll
-  for (int c = 0; c < NB; ++c) x[c] = c < kb ? row[c] : 0.0;
-#pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    double v = x[c];
-#pragma unroll
-    for (int cp = 0; cp < c; ++cp) v -= x[cp] * L[c][cp];
-    x[c] = v / L[c][c];
-  }
-#pragma unroll
-  for (int c = 0; c < NB; ++c)
-    if (c < kb) row[c] = x[c];
-}
-
-// Trailing update of the lower triangle: A[i][j] -= sum_c A[i][k0+c] A[j][k0+c], i >= j >= k1.
-__global__ __launch_bounds__(256) void k_chol_update(int n, double* __restrict__ A, int k0, int kb) {
-  const int bi = blockIdx.y, bj = blockIdx.x;
-  if (bj > bi) return;
-  const int k1 = k0 + kb;
-  const int i0 = k1 + bi * NB, j0 = k1 + bj * NB;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  __shared__ double Pi[KC][NB + 1];
-  __shared__ double Pj[KC][NB + 1];
-  double acc[4][4] = {};
-  for (int c0 = 0; c0 < kb; c0 += KC) {
-    for (int e = threadIdx.x; e < KC * NB; e += 256) {
-      const int r = e / KC, cc = e - r * KC;
-      const int c = c0 + cc;
-      Pi[cc][r] = (c < kb && i0 + r < n) ? A[(size_t)(i0 + r) * n + k0 + c] : 0.0;
-      Pj[cc][r] = (c < kb && j0 + r < n) ? A[(size_t)(j0 + r) * n + k0 + c] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int cc = 0; cc < KC; ++cc) {
-      double a[4], b[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a[u] = Pi[cc][ty * 4 + u];
-        b[u] = Pj[cc][tx * 4 + u];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = i0 + ty * 4 + u, j = j0 + tx * 4 + v;
-      if (i < n && j < n && j <= i) A[(size_t)i * n + j] -= acc[u][v];
-    }
+  if (c < kb)
+    for (int qq = c + 1 + part; qq < kb; qq += 4) A[(size_t)(k0 + c) * n + k0 + qq] = Ws[qq][c];
 }
 
 // Forward substitution on the diagonal block for every right-hand side row.
@@ -231,6 +167,158 @@ __global__ __launch_bounds__(256) void k_dots(int n, const double* __restrict__ 
   if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int TK = 16;     // k per LDS stage of the matrix-core update kernel
+
+// Lower-triangle tile update on the matrix cores, tile (bi, bj), bi >= bj:
+//   C[i][j] = alpha sum_k P(i, k) P(j, k) (+ C[i][j] when ACCUM),
+// with P(i, k) = X[k][i] (COLS: rows of X [K][n] are the samples) or
+// P(i, k) = X[(r0 + i) ld + k] (rows of a panel).  Rows and columns start at r0 for C.
+// MIRROR: the upper triangle gets the same values (a symmetric result).
+template <int TT, bool COLS, bool ACCUM, bool MIRROR>
+__global__ __launch_bounds__(256) void k_tile_update(int n, int K, int r0, const double* __restrict__ X, int ld,
+                                                     double alpha, double* __restrict__ C) {
+  constexpr int WT = TT / 2, MT = WT / 16;   // wave tile, 16 x 16 MFMA tiles per wave side
+  constexpr int NL = TK * TT / 256;           // staged values per thread and operand
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  if (bj > bi) return;   // whole workgroup, before any barrier
+  const int i0 = r0 + bi * TT, j0 = r0 + bj * TT;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int wr = wv >> 1, wc = wv & 1, l16 = lane & 15, kq = lane >> 4;
+  __shared__ double Pi[TK][TT + 1];
+  __shared__ double Pj[TK][TT + 1];
+  // this thread's outputs; with ACCUM their old values are loaded first and stay in flight
+  // through the contraction (indices clamped, the loads unconditional)
+  double cold[MT][MT][4];
+#pragma unroll
+  for (int ta = 0; ta < MT; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < MT; ++tb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = min(i0 + WT * wr + 16 * ta + 4 * r + kq, n - 1), j = min(j0 + WT * wc + 16 * tb + l16, n - 1);
+        cold[ta][tb][r] = ACCUM ? C[(size_t)i * n + j] : 0.0;
+      }
+  d4 acc[MT][MT];
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < MT; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  // the next stage's operands are loaded into registers while this stage multiplies
+  double pi[NL], pj[NL];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int e = tid + 256 * u;
+      int kk, c;
+      if (COLS) { kk = e / TT; c = e - kk * TT; }   // consecutive threads: consecutive columns of X
+      else { c = e / TK; kk = e - c * TK; }          // consecutive threads: consecutive k of a row
+      const int k = k0 + kk, kc = min(k, K - 1), ic = min(i0 + c, n - 1), jc = min(j0 + c, n - 1);
+      const double vi = COLS ? X[(size_t)kc * ld + ic] : X[(size_t)ic * ld + kc];
+      const double vj = COLS ? X[(size_t)kc * ld + jc] : X[(size_t)jc * ld + kc];
+      pi[u] = (k < K && i0 + c < n) ? vi : 0.0;
+      pj[u] = (k < K && j0 + c < n) ? vj : 0.0;
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += TK) {
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int e = tid + 256 * u;
+      int kk, c;
+      if (COLS) { kk = e / TT; c = e - kk * TT; }
+      else { c = e / TK; kk = e - c * TK; }
+      Pi[kk][c] = pi[u];
+      Pj[kk][c] = pj[u];
+    }
+    __syncthreads();
+    if (k0 + TK < K) load(k0 + TK);
+#pragma unroll
+    for (int ks = 0; ks < TK / 4; ++ks) {
+      const int kk = 4 * ks + kq;
+      double a[MT], b[MT];
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        a[t] = Pi[kk][WT * wr + 16 * t + l16];
+        b[t] = Pj[kk][WT * wc + 16 * t + l16];
+      }
+#pragma unroll
+      for (int ta = 0; ta < MT; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < MT; ++tb)
+          acc[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ta = 0; ta < MT; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < MT; ++tb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + WT * wr + 16 * ta + 4 * r + kq, j = j0 + WT * wc + 16 * tb + l16;
+        if (i < n && j < n && j <= i) {
+          const double v = cold[ta][tb][r] + alpha * acc[ta][tb][r];
+          C[(size_t)i * n + j] = v;
+          if (MIRROR && j < i) C[(size_t)j * n + i] = v;
+        }
+      }
+}
+
+// Panel: rows i >= k0 + kb, A[i, k0:k0+kb] <- A[i, k0:k0+kb] W^T with W = L_kk^-1, whose
+// strictly lower part k_potrf_diag left transposed in the block's upper triangle and
+// whose diagonal is 1 / L_jj.  64 rows per workgroup, four waves of 32 x 32.
+__global__ __launch_bounds__(256) void k_panel_mfma(int n, double* __restrict__ A, int k0, int kb) {
+  __shared__ double Ar[NB][NB + 1];   // the workgroup's panel rows
+  __shared__ double Wt[NB][NB + 1];   // Wt[k][c] = W[c][k]
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int rbase = k0 + kb + blockIdx.x * NB;
+  // loads unconditional (clamped indices, values selected after); kb == NB for a panel
+#pragma unroll
+  for (int u = 0; u < NB * NB / 256; ++u) {
+    const int e = tid + 256 * u;
+    const int r = e / NB, c = e - r * NB;
+    const double av = A[(size_t)min(rbase + r, n - 1) * n + k0 + c];
+    // Wt[k][c] = W[c][k]: W[c][k] for k < c sits at A[k0 + k][k0 + c]; W[c][c] = 1 / L_cc
+    const int k = r;
+    const double wv_ = A[(size_t)(k0 + min(k, c)) * n + k0 + c];
+    Ar[r][c] = rbase + r < n ? av : 0.0;
+    Wt[k][c] = k == c ? 1.0 / wv_ : (k < c ? wv_ : 0.0);
+  }
+  __syncthreads();
+  const int wr = wv >> 1, wc = wv & 1;
+  d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int ks = 0; ks < NB / 4; ++ks) {
+    const int kk = 4 * ks + kq;
+    double a[2], b[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      a[t] = Ar[32 * wr + 16 * t + l16][kk];
+      b[t] = Wt[kk][32 * wc + 16 * t + l16];
+    }
+#pragma unroll
+    for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+      for (int tb = 0; tb < 2; ++tb) acc[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
+  }
+  // every read of the rows is done (the stores below overwrite them)
+#pragma unroll
+  for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = rbase + 32 * wr + 16 * ta + 4 * r + kq, c = 32 * wc + 16 * tb + l16;
+        if (i < n && c < kb) A[(size_t)i * n + k0 + c] = acc[ta][tb][r];
+      }
+}
+
 __global__ void k_copy_lower(int n, const double* __restrict__ src, double* __restrict__ dst) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (size_t)n * n) return;
@@ -257,8 +345,9 @@ hipError_t launch_center_rows(int n, int N, const double* B, double* C, hipStrea
 }
 
 hipError_t launch_syrk(int n, int N, const double* B, double scale, double* Z, hipStream_t st) {
-  const int nb = (n + NB - 1) / NB;
-  hipLaunchKernelGGL(k_syrk_t, dim3(nb, nb), dim3(256), 0, st, n, N, B, scale, Z);
+  constexpr int T = 64;
+  const int nb = (n + T - 1) / T;
+  hipLaunchKernelGGL((k_tile_update<T, true, false, true>), dim3(nb, nb), dim3(256), 0, st, n, N, 0, B, n, scale, Z);
   return hipGetLastError();
 }
 
@@ -274,9 +363,12 @@ hipError_t launch_cholesky(int n, double* A, int* flag, hipStream_t st) {
     hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, n, A, k0, kb, flag);
     const int rem = n - k0 - kb;
     if (rem > 0) {
-      hipLaunchKernelGGL(k_trsm_panel, dim3((rem + 63) / 64), dim3(64), 0, st, n, A, k0, kb);
-      const int nb = (rem + NB - 1) / NB;
-      hipLaunchKernelGGL(k_chol_update, dim3(nb, nb), dim3(256), 0, st, n, A, k0, kb);
+      hipLaunchKernelGGL(k_panel_mfma, dim3((rem + NB - 1) / NB), dim3(256), 0, st, n, A, k0, kb);
+      constexpr int T = 64;
+      const int nb = (rem + T - 1) / T;
+      // A[i][j] -= sum_c A[i][k0 + c] A[j][k0 + c] over the trailing lower triangle
+      hipLaunchKernelGGL((k_tile_update<T, false, true, false>), dim3(nb, nb), dim3(256), 0, st, n, kb, k0 + kb,
+                         A + k0, n, -1.0, A);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
