@@ -147,35 +147,61 @@ __global__ __launch_bounds__(256) void k_adj_legendre_mfma(int lmax, int ntheta,
   const bool ok0 = li < L, ok1 = li + 1 < L;
   const int bc = 16 * wv + (row >> 1);       // this lane's B (and D) column: complex column, part
   const int part = row & 1;
-  for (int j0 = 0; j0 < nrp; j0 += AL_RC) {
+  // software pipeline: the next chunk's lambda values and folded ring values are loaded
+  // into registers (unconditionally, indices clamped) while this chunk's MFMAs run
+  constexpr int NE = AL_RC * AL_NC / 256;   // staged ring values per thread
+  float la0[AL_RC / 2], la1[AL_RC / 2];     // this lane's A values of one chunk
+  float2 gn[NE], gs[NE];
+  auto load_chunk = [&](int j0) {
+#pragma unroll
+    for (int k2 = 0; k2 < AL_RC / 2; ++k2) {
+      const int j = min(j0 + 2 * k2 + kh, nrp - 1);
+      const float* lp = lrow + (size_t)j * L + min(li, L - 1);
+      la0[k2] = lp[0];
+      la1[k2] = lp[ok1 ? 1 : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {   // consecutive threads: consecutive rings of one column
+      const int e = tid + 256 * u, jj = e % AL_RC, q = e / AL_RC;
+      const int col = min(c0 + q, ncol - 1), j = min(j0 + jj, nrp - 1);
+      const float2* g = Gh + ((size_t)col * (lmax + 1) + m) * ntheta;   // Gh[col][m][ring]
+      gn[u] = g[j];
+      gs[u] = g[ntheta - 1 - j];
+    }
+  };
+  auto store_chunk = [&](int j0) {
     const int nj = min(AL_RC, nrp - j0);
-    __syncthreads();
-    for (int e = tid; e < AL_RC * AL_NC; e += 256) {   // consecutive threads: consecutive rings
-      const int jj = e % AL_RC, q = e / AL_RC;
-      float2 vn = make_float2(0.f, 0.f), vs = make_float2(0.f, 0.f);
-      const int col = c0 + q, j = j0 + jj;
-      if (jj < nj && col < ncol) {
-        const float2* g = Gh + ((size_t)col * (lmax + 1) + m) * ntheta;   // Gh[col][m][ring]
-        vn = g[j];
-        const int js = ntheta - 1 - j;
-        if (js != j) vs = g[js];
-      }
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = tid + 256 * u, jj = e % AL_RC, q = e / AL_RC;
+      const int j = j0 + jj;
+      const bool in = jj < nj && c0 + q < ncol;
+      const float2 vn = in ? gn[u] : make_float2(0.f, 0.f);
+      const float2 vs = (in && ntheta - 1 - j != j) ? gs[u] : make_float2(0.f, 0.f);   // the equator ring once
       hp[jj][q] = make_float2(vn.x + vs.x, vn.y + vs.y);
       hm[jj][q] = make_float2(vn.x - vs.x, vn.y - vs.y);
     }
-    __syncthreads();
-#pragma unroll 4
+  };
+  load_chunk(0);
+  store_chunk(0);
+  for (int j0 = 0; j0 < nrp; j0 += AL_RC) {
+    const int nj = min(AL_RC, nrp - j0);
+    float a0c[AL_RC / 2], a1c[AL_RC / 2];
+#pragma unroll
+    for (int k2 = 0; k2 < AL_RC / 2; ++k2) {
+      const bool in = 2 * k2 + kh < nj;
+      a0c[k2] = (in && ok0) ? la0[k2] : 0.f;
+      a1c[k2] = (in && ok1) ? la1[k2] : 0.f;
+    }
+    __syncthreads();   // hp, hm of this chunk are in LDS
+    const bool more = j0 + AL_RC < nrp;
+    if (more) load_chunk(j0 + AL_RC);
+#pragma unroll
     for (int k2 = 0; k2 < AL_RC / 2; ++k2) {
       const int jj = 2 * k2 + kh;
-      float a0 = 0.f, a1 = 0.f;
-      if (jj < nj) {
-        const float* lp = lrow + (size_t)(j0 + jj) * L + li;
-        if (ok0) a0 = lp[0];
-        if (ok1) a1 = lp[1];
-      }
       const float2 he = hp[jj][bc], ho = hm[jj][bc];
-      cha[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, part ? he.y : he.x, cha[0], 0, 0, 0);
-      cha[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, part ? ho.y : ho.x, cha[1], 0, 0, 0);
+      cha[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0c[k2], part ? he.y : he.x, cha[0], 0, 0, 0);
+      cha[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1c[k2], part ? ho.y : ho.x, cha[1], 0, 0, 0);
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
@@ -183,6 +209,8 @@ __global__ __launch_bounds__(256) void k_adj_legendre_mfma(int lmax, int ntheta,
 #pragma unroll
       for (int r = 0; r < 16; ++r) cha[t][r] = 0.f;
     }
+    __syncthreads();   // every wave is done with this chunk's hp, hm
+    if (more) store_chunk(j0 + AL_RC);
   }
   const int col = c0 + bc;
   if (col >= ncol) return;
