@@ -86,6 +86,9 @@ struct modal_ctx {
   struct Mark { int stage; hipEvent_t a, b; };
   std::vector<Mark> marks;
   std::vector<hipEvent_t> event_pool;
+  // second stream and events of the Cholesky's look-ahead (created on first use)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_a = nullptr, ev_p = nullptr;
   double stage_ms[MODAL_NSTAGES] = {};
   long long stage_n[MODAL_NSTAGES] = {};
   // linear-term state bookkeeping (the device state holds the pair planes)
@@ -194,9 +197,16 @@ hipError_t launch_syrk(int n, int N, const double* B, double scale, double* Z, h
 hipError_t launch_center_rows(int n, int N, const double* B, double* C, hipStream_t st);
 hipError_t launch_copy_lower(int n, const double* src, double* dst, hipStream_t st);
 // in-place Cholesky of the lower triangle of A (row-major, n x n); flag[0] = 1 + first bad pivot
-hipError_t launch_cholesky(int n, double* A, int* flag, hipStream_t st);
+// blocked right-looking Cholesky with look-ahead: the next diagonal block and panel run on
+// side while the rest of the trailing update runs on st (ev_a, ev_p order them); st is
+// joined with side when it returns
+hipError_t launch_cholesky_lookahead(int n, double* A, int* flag, hipStream_t st, hipStream_t side, hipEvent_t ev_a,
+                                     hipEvent_t ev_p);
 // solve L Y = B in place for nrhs right-hand sides stored as rows of B [nrhs][n]
 hipError_t launch_trsm_rows(int n, const double* L, int nrhs, double* B, hipStream_t st);
+// the same solve after launch_cholesky (which leaves the inverted diagonal blocks in the
+// upper triangles); the solution goes to Y, B is overwritten below the blocks
+hipError_t launch_trsm_rows_inv(int n, const double* L, int nrhs, double* B, double* Y, hipStream_t st);
 hipError_t launch_estimator(int n, const double* y, const double* Z, int S, double* out, hipStream_t st);
 
 // low-rank covariance I + sum b b^T: noise vectors, Woodbury estimator, closed-form rotation

@@ -191,7 +191,7 @@ size_t ws_size(const modal_ctx* c, int op, int S) {
       break;
     case MODAL_OP_FNL:
       cv.take((size_t)c->nmax * c->nmax * 8); cv.take((size_t)(S + 1) * c->nmax * 8); cv.take((size_t)(S + 1) * 8);
-      cv.take(16);
+      cv.take(16); cv.take((size_t)(S + 1) * c->nmax * 8);
       break;
     case MODAL_OP_NOISE_VECTORS: cv.take(noise_ws_bytes(S)); break;
     case MODAL_OP_FNL_LOWRANK: cv.take(lowrank_ws_bytes(S)); break;
@@ -215,13 +215,13 @@ size_t ws_size(const modal_ctx* c, int op, int S) {
       break;
     case MODAL_OP_POWER_FNL:
       cv.take((size_t)c->P * c->P * 8); cv.take((size_t)(S + 1) * c->P * 8); cv.take((size_t)(S + 1) * 8);
-      cv.take(16);
+      cv.take(16); cv.take((size_t)(S + 1) * c->P * 8);
       break;
     case MODAL_OP_FRAME: cv.take(frame_ws_bytes(c->nmax)); break;
     case MODAL_OP_FNL_FRAME:
       cv.take((size_t)c->nmax * c->nmax * 8); cv.take((size_t)(S + 1) * c->nmax * 8);
       cv.take((size_t)c->nmax * c->nmax * 8); cv.take((size_t)(S + 1) * c->nmax * 8); cv.take((size_t)(S + 1) * 8);
-      cv.take(16);
+      cv.take(16); cv.take((size_t)(S + 1) * c->nmax * 8);
       break;
     case MODAL_OP_IDEAL_COVARIANCE: {
       const size_t nmu = shapes_nmu(c->lmax), L = c->lmax + 1;
@@ -655,6 +655,12 @@ void modal_destroy(modal_ctx* c) {
     (void)hipEventDestroy(mk.b);
   }
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+    (void)hipEventDestroy(c->ev_a);
+    (void)hipEventDestroy(c->ev_p);
+  }
   delete c;   // the tables live in the caller's buffer
 }
 
@@ -934,6 +940,7 @@ modal_status estimate(modal_ctx* c, int op, int n, double factor, const double* 
   double* rows = (double*)cv.take((size_t)(S + 1) * n * 8);
   double* dots = (double*)cv.take((size_t)(S + 1) * 8);
   int* flag = (int*)cv.take(16);
+  double* sol = (double*)cv.take((size_t)(S + 1) * n * 8);
   HIPTRY(launch_zero(flag, 16, st));
   HIPTRY(hipMemcpyAsync(L, zeta, (size_t)n * n * 8, hipMemcpyDeviceToDevice, st));
   HIPTRY(hipMemcpyAsync(rows, alpha, (size_t)n * 8, hipMemcpyDeviceToDevice, st));
@@ -942,9 +949,14 @@ modal_status estimate(modal_ctx* c, int op, int n, double factor, const double* 
                             hipMemcpyDeviceToDevice, st));
   {
     StageTimer _t(c, MODAL_STAGE_CHOLESKY, st);
-    HIPTRY(launch_cholesky(n, L, flag, st));
-    HIPTRY(launch_trsm_rows(n, L, S + 1, rows, st));
-    HIPTRY(launch_estimator(n, rows, nullptr, S, dots, st));
+    if (!c->side) {
+      HIPTRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+      HIPTRY(hipEventCreateWithFlags(&c->ev_a, hipEventDisableTiming));
+      HIPTRY(hipEventCreateWithFlags(&c->ev_p, hipEventDisableTiming));
+    }
+    HIPTRY(launch_cholesky_lookahead(n, L, flag, st, c->side, c->ev_a, c->ev_p));
+    HIPTRY(launch_trsm_rows_inv(n, L, S + 1, rows, sol, st));
+    HIPTRY(launch_estimator(n, sol, nullptr, S, dots, st));
   }
   if (L_dev) HIPTRY(launch_copy_lower(n, L, L_dev, st));
   std::vector<double> h(S + 1);

@@ -30,7 +30,7 @@ constexpr int NB = 64;
 // W's strictly lower part goes to the block's upper triangle, transposed
 // (A[k0 + c][k0 + q] = W[q][c]).  Rows and columns past kb are an identity block.
 __global__ __launch_bounds__(256) void k_potrf_diag(int n, double* __restrict__ A, int k0, int kb, int* flag) {
-  __shared__ double piv[2];
+  __shared__ double piv[2], rpiv[2];
   __shared__ double colj[2][NB];
   __shared__ double Ls[NB][NB + 1];
   __shared__ double Ws[NB][NB + 1];
@@ -55,12 +55,14 @@ __global__ __launch_bounds__(256) void k_potrf_diag(int n, double* __restrict__ 
     if (owns_col && i == j) {
       const bool ok = aij > 0.0;
       if (!ok && j < kb) atomicCAS(flag, 0, k0 + j + 1);
-      piv[jb] = ok ? sqrt(aij) : __builtin_nan("");
+      const double d = ok ? sqrt(aij) : __builtin_nan("");
+      piv[jb] = d;
+      rpiv[jb] = 1.0 / d;
     }
     __syncthreads();
     if (owns_col) {
       const double d = piv[jb];
-      const double l = i > j ? aij / d : (i == j ? d : 0.0);
+      const double l = i > j ? aij * rpiv[jb] : (i == j ? d : 0.0);
 #pragma unroll
       for (int cc = 0; cc < NB / 4; ++cc)
         if (cc == jc) r[cc] = l;
@@ -143,6 +145,60 @@ __global__ __launch_bounds__(256) void k_trsv_update(int n, const double* __rest
   const double* row = A + (size_t)i * n + k0;
 #pragma unroll
   for (int c = 0; c < NB; ++c) l[c] = c < kb ? row[c] : 0.0;
+  for (int r = 0; r < nr; ++r) {
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) acc += l[c] * y[r][c];
+    B[(size_t)(r0 + r) * n + i] -= acc;
+  }
+}
+
+// One step of the blocked forward substitution with the inverted diagonal blocks that
+// k_potrf_diag leaves in the upper triangles: for the right-hand sides r (rows of B
+// [nrhs][n]), y_r = W b_r[k0:k0+kb] (W = L_kk^-1), written to Y by workgroup 0; the other
+// workgroups each form the same y (a 64 x 64 product, cheaper than a second launch) and
+// update their 256 rows below: B[r][i] -= sum_c L[i][k0 + c] y_r[c].  B's block rows are
+// only read, so no workgroup writes what another still reads.
+constexpr int TRS_R = 16;   // right-hand sides per workgroup
+__global__ __launch_bounds__(256) void k_trsv_inv_step(int n, const double* __restrict__ A, int k0, int kb, int nrhs,
+                                                       double* __restrict__ B, double* __restrict__ Y) {
+  __shared__ double W[NB][NB + 1];
+  __shared__ double b[TRS_R][NB];
+  __shared__ double y[TRS_R][NB];
+  const int tid = threadIdx.x;
+  const int r0 = blockIdx.y * TRS_R, nr = min(TRS_R, nrhs - r0);
+#pragma unroll
+  for (int u = 0; u < NB * NB / 256; ++u) {
+    const int e = tid + 256 * u, i = e / NB, k = e - i * NB;   // W[i][k], k <= i
+    const int ic = min(i, kb - 1), kc = min(k, kb - 1);   // clamped into the block
+    const double v = A[(size_t)(k0 + min(kc, ic)) * n + k0 + max(kc, ic)];   // L_ii on the diagonal
+    W[i][k] = (i < kb && k < kb) ? (k == i ? 1.0 / v : (k < i ? v : 0.0)) : 0.0;
+  }
+  for (int e = tid; e < TRS_R * NB; e += 256) {
+    const int r = e / NB, c = e - r * NB;
+    b[r][c] = (r < nr && c < kb) ? B[(size_t)(r0 + r) * n + k0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < TRS_R * NB; e += 256) {
+    const int r = e / NB, i = e - r * NB;
+    double v = 0.0;
+    for (int k = 0; k <= i; ++k) v += W[i][k] * b[r][k];
+    y[r][i] = v;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int e = tid; e < TRS_R * NB; e += 256) {
+      const int r = e / NB, c = e - r * NB;
+      if (r < nr && c < kb) Y[(size_t)(r0 + r) * n + k0 + c] = y[r][c];
+    }
+    return;
+  }
+  const int i = k0 + kb + (blockIdx.x - 1) * 256 + tid;
+  if (i >= n) return;
+  const double* row = A + (size_t)i * n + k0;
+  double l[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) l[c] = row[c];   // kb == NB whenever rows remain below
   for (int r = 0; r < nr; ++r) {
     double acc = 0.0;
 #pragma unroll
@@ -357,23 +413,35 @@ hipError_t launch_copy_lower(int n, const double* src, double* dst, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_cholesky(int n, double* A, int* flag, hipStream_t st) {
-  for (int k0 = 0; k0 < n; k0 += NB) {
-    const int kb = n - k0 < NB ? n - k0 : NB;
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, n, A, k0, kb, flag);
-    const int rem = n - k0 - kb;
-    if (rem > 0) {
-      hipLaunchKernelGGL(k_panel_mfma, dim3((rem + NB - 1) / NB), dim3(256), 0, st, n, A, k0, kb);
-      constexpr int T = 64;
-      const int nb = (rem + T - 1) / T;
-      // A[i][j] -= sum_c A[i][k0 + c] A[j][k0 + c] over the trailing lower triangle
-      hipLaunchKernelGGL((k_tile_update<T, false, true, false>), dim3(nb, nb), dim3(256), 0, st, n, kb, k0 + kb,
-                         A + k0, n, -1.0, A);
-    }
-    hipError_t e = hipGetLastError();
+hipError_t launch_cholesky_lookahead(int n, double* A, int* flag, hipStream_t st, hipStream_t side, hipEvent_t ev_a,
+                                     hipEvent_t ev_p) {
+  constexpr int T = 64;
+  // A[i][j] -= sum_c A[i][k0 + c] A[j][k0 + c], i >= j >= r0, tile columns [bj0, ...) of the
+  // (n - r0)-square trailing grid; nbx tile columns
+  auto update = [&](int k0, int kb, int r0, int nbx, hipStream_t s) {
+    const int nb = (n - r0 + T - 1) / T;
+    hipLaunchKernelGGL((k_tile_update<T, false, true, false>), dim3(nbx, nb), dim3(256), 0, s, n, kb, r0, A + k0, n,
+                       -1.0, A);
+  };
+  hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, n, A, 0, n < NB ? n : NB, flag);
+  if (n > NB) hipLaunchKernelGGL(k_panel_mfma, dim3((n - NB + NB - 1) / NB), dim3(256), 0, st, n, A, 0, NB);
+  for (int k0 = 0; k0 + NB < n; k0 += NB) {
+    const int k1 = k0 + NB;              // the next diagonal block
+    const int kb1 = n - k1 < NB ? n - k1 : NB;
+    // the next block's columns first (its diagonal block and panel rows), then the rest
+    update(k0, NB, k1, 1, st);
+    hipError_t e = hipEventRecord(ev_a, st);
     if (e != hipSuccess) return e;
+    if (n - k1 > NB) update(k0, NB, k1 + NB, (n - k1 - NB + T - 1) / T, st);
+    if ((e = hipStreamWaitEvent(side, ev_a, 0)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, side, n, A, k1, kb1, flag);
+    const int rem = n - k1 - kb1;
+    if (rem > 0) hipLaunchKernelGGL(k_panel_mfma, dim3((rem + NB - 1) / NB), dim3(256), 0, side, n, A, k1, kb1);
+    if ((e = hipEventRecord(ev_p, side)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(st, ev_p, 0)) != hipSuccess) return e;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  return hipSuccess;
+  return hipGetLastError();
 }
 
 hipError_t launch_trsm_rows(int n, const double* L, int nrhs, double* B, hipStream_t st) {
@@ -384,6 +452,18 @@ hipError_t launch_trsm_rows(int n, const double* L, int nrhs, double* B, hipStre
     if (rem > 0)
       hipLaunchKernelGGL(k_trsv_update, dim3((rem + 255) / 256, (nrhs + 63) / 64), dim3(256), 0, st, n, L, k0, kb,
                          nrhs, B);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_trsm_rows_inv(int n, const double* L, int nrhs, double* B, double* Y, hipStream_t st) {
+  for (int k0 = 0; k0 < n; k0 += NB) {
+    const int kb = n - k0 < NB ? n - k0 : NB;
+    const int rem = n - k0 - kb;
+    hipLaunchKernelGGL(k_trsv_inv_step, dim3(1 + (rem + 255) / 256, (nrhs + TRS_R - 1) / TRS_R), dim3(256), 0, st, n,
+                       L, k0, kb, nrhs, B, Y);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
