@@ -1,7 +1,8 @@
 #!/usr/bin/env python3
-"""Write the oracle's beta, linear term and beta^hat for full-spectrum skies at the two
-full-resolution shapes, l_max 1000 and l_max 1024 on the Gauss-Legendre 1536 x 3072
-grid with P = 40 modes (n_max = 11,480), for the GPU parity test at those shapes.
+"""Write the oracle's beta, linear term and beta^hat for full-spectrum skies at the
+workload shapes: l_max 1000 and l_max 1024 on the Gauss-Legendre 1536 x 3072 grid with
+P = 40 modes (n_max = 11,480), and l_max 500 on 768 x 1536 with P = 30 (n_max = 4,960),
+for the GPU parity test at those shapes.
 
 Calls only ``oracle`` (FP64, ring-chunked pixel sums) and ``modal_inputs`` (seeded
 inputs).  The sky recipe is the benchmark's: isotropic Gaussian a_lm drawn with the
@@ -11,8 +12,8 @@ pixel weights, and the linear term's pair means from four further Monte-Carlo sk
 of the same recipe.  It also writes the sums of the terms' magnitudes (the scale of
 rounding errors in a sum, for the condition-scaled error of the test).
 
-Usage: python tests/golden/make_fullsize_golden.py [metric1000|precision1024 ...]
-Writes tests/golden/fullsize_<name>.npz (about 0.6 MB each); takes minutes per shape.
+Usage: python tests/golden/make_fullsize_golden.py [metric1000|precision1024|wmap500 ...]
+Writes tests/golden/fullsize_<name>.npz (0.2-0.9 MB each); takes minutes per shape.
 """
 from __future__ import annotations
 
@@ -60,5 +61,5 @@ def make(name: str) -> str:
 
 
 if __name__ == "__main__":
-    for n in (sys.argv[1:] or ["metric1000", "precision1024"]):
+    for n in (sys.argv[1:] or ["metric1000", "precision1024", "wmap500"]):
         make(n)

@@ -1,6 +1,7 @@
 """Element-by-element parity at the full resolution of the throughput workload (l_max 1000)
 and of the precision study (l_max 1024), Gauss-Legendre 1536 x 3072 rings, P = 40 modes
-(n_max = 11,480), against the FP64 oracle.
+(n_max = 11,480), and of the WMAP-size estimator workload (l_max 500, 768 x 1536 rings,
+P = 30, n_max = 4,960), against the FP64 oracle.
 
 The expected beta, linear term and beta^hat of two full-spectrum skies (WMAP-like filter
 spectrum with a 13' beam and white noise, the |lat| < 10 deg cut in the pixel weights,
@@ -60,7 +61,7 @@ def _errs(got, ref, scale):
     return e_inf, e_2, e_sc
 
 
-@pytest.mark.parametrize("name", ["metric1000", "precision1024"])
+@pytest.mark.parametrize("name", ["metric1000", "precision1024", "wmap500"])
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16x3", "bf16x3"])
 def test_fullsize_golden(name, prec):
     from paper_1105_2791_amd import ModalContext
