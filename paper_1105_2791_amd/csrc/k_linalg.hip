@@ -20,90 +20,133 @@ namespace {
 
 constexpr int NB = 64;
 
-// Factor the diagonal block A[k0:k0+kb, k0:k0+kb] in place (lower triangle) and invert it.
-// 256 threads: thread (i, q) holds the columns c = 4 cc + q (cc < 16) of row i in
-// registers.  Step j: the owner of a_jj publishes the pivot, the owners of column j scale
-// it and publish it (LDS, double-buffered by the parity of j), and every thread updates
-// its elements a_ic -= a_ij a_cj (j < c <= i).  Then W = L^-1 by columns, four threads per
-// column (W and L in LDS):
-//   W[c][c] = 1 / L_cc,  W[q][c] = -(sum_{c <= k < q} L_qk W[k][c]) / L_qq  (q > c);
-// W's strictly lower part goes to the block's upper triangle, transposed
-// (A[k0 + c][k0 + q] = W[q][c]).  Rows and columns past kb are an identity block.
+// Factor the diagonal block A[k0:k0+kb, k0:k0+kb] in place (lower triangle) and invert it,
+// blocked by 16 so that the dependent chain is 4 x 16 short steps instead of 64 long ones.
+// The block is in LDS; for each 16-column sub-block:
+//   1. wave 0 factors its 16 x 16 diagonal block D (lane r holds row r in registers; the
+//      pivot and the column of each step are broadcast by shuffles, no barrier) and inverts
+//      it (lane c forms column c of D^-1);
+//   2. the rows below it in the block become A_panel D^-T;
+//   3. the trailing rows and columns of the block are updated.
+// Then W = L^-1 from the four inverted diagonal blocks, by block distance:
+//   W_IJ = -D_I^-1 (sum_{J <= K < I} L_IK W_KJ).
+// L goes back to the lower triangle and W's strictly lower part, transposed, to the
+// block's upper triangle (A[k0 + c][k0 + q] = W[q][c]).  Rows and columns past kb are an
+// identity block.  A non-positive pivot is recorded in flag and turns into NaN.
+constexpr int SB = 16;   // sub-block
+
 __global__ __launch_bounds__(256) void k_potrf_diag(int n, double* __restrict__ A, int k0, int kb, int* flag) {
-  __shared__ double piv[2], rpiv[2];
-  __shared__ double colj[2][NB];
-  __shared__ double Ls[NB][NB + 1];
-  __shared__ double Ws[NB][NB + 1];
-  const int t = threadIdx.x, i = t >> 2, q = t & 3;
-  double r[NB / 4];
-  // loads unconditional (indices clamped into the block, values selected after), so that
-  // they are all in flight together
-  const double* arow = A + (size_t)(k0 + min(i, kb - 1)) * n + k0;
-#pragma unroll
-  for (int cc = 0; cc < NB / 4; ++cc) {
-    const int c = 4 * cc + q;
-    const double v = arow[min(c, kb - 1)];
-    r[cc] = (i < kb && c < kb && c <= i) ? v : (c == i ? 1.0 : 0.0);
-  }
-  for (int j = 0; j < NB; ++j) {
-    const int jb = j & 1, jc = j >> 2;
-    const bool owns_col = q == (j & 3);
-    double aij = 0.0;   // this thread's a_ij when it owns column j
-#pragma unroll
-    for (int cc = 0; cc < NB / 4; ++cc)
-      if (cc == jc) aij = r[cc];
-    if (owns_col && i == j) {
-      const bool ok = aij > 0.0;
-      if (!ok && j < kb) atomicCAS(flag, 0, k0 + j + 1);
-      const double d = ok ? sqrt(aij) : __builtin_nan("");
-      piv[jb] = d;
-      rpiv[jb] = 1.0 / d;
-    }
-    __syncthreads();
-    if (owns_col) {
-      const double d = piv[jb];
-      const double l = i > j ? aij * rpiv[jb] : (i == j ? d : 0.0);
-#pragma unroll
-      for (int cc = 0; cc < NB / 4; ++cc)
-        if (cc == jc) r[cc] = l;
-      colj[jb][i] = l;
-    }
-    __syncthreads();
-    const double lij = colj[jb][i];
-    double lc[NB / 4];   // read first, all at once; the update is selected after
-#pragma unroll
-    for (int cc = 0; cc < NB / 4; ++cc) lc[cc] = colj[jb][4 * cc + q];
-#pragma unroll
-    for (int cc = 0; cc < NB / 4; ++cc) {
-      const int c = 4 * cc + q;
-      const double upd = r[cc] - lij * lc[cc];
-      r[cc] = (c > j && c <= i) ? upd : r[cc];
-    }
-  }
-#pragma unroll
-  for (int cc = 0; cc < NB / 4; ++cc) {
-    const int c = 4 * cc + q;
-    Ls[i][c] = c <= i ? r[cc] : 0.0;
-    if (i < kb && c < kb && c <= i) A[(size_t)(k0 + i) * n + k0 + c] = r[cc];
+  __shared__ double a[NB][NB + 1];
+  __shared__ double Wf[NB][NB + 1];   // W = L^-1 (diagonal blocks first, then the rest)
+  __shared__ double T[NB][NB + 1];    // block products of the inverse
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  for (int e = t; e < NB * NB; e += 256) {
+    const int r = e / NB, c = e - r * NB;
+    const double v = A[(size_t)(k0 + min(r, kb - 1)) * n + k0 + min(c, kb - 1)];
+    a[r][c] = (r < kb && c < kb && c <= r) ? v : (c == r ? 1.0 : 0.0);
+    Wf[r][c] = 0.0;
   }
   __syncthreads();
-  // four threads per column c = t / 4 (one wave holds 16 columns), thread part t % 4
-  // summing k = part mod 4; the sum is combined across the four lanes
-  const int c = t >> 2, part = t & 3;
-  for (int qq = 0; qq < NB; ++qq) {
-    double v = 0.0;
-#pragma unroll 4
-    for (int k = part; k < qq; k += 4) {
-      const double term = Ls[qq][k] * Ws[k][c];
-      v += k >= c ? term : 0.0;
+  for (int kk = 0; kk < NB / SB; ++kk) {
+    const int c0 = SB * kk;
+    if (wv == 0) {   // 1. factor and invert the 16 x 16 diagonal block (lanes 0..15 own rows)
+      const int r = lane & (SB - 1);
+      double d[SB];
+#pragma unroll
+      for (int c = 0; c < SB; ++c) d[c] = a[c0 + r][c0 + c];
+#pragma unroll
+      for (int j = 0; j < SB; ++j) {
+        const double p = __shfl(d[j], j);
+        const bool ok = p > 0.0;
+        if (lane == 0 && !ok && c0 + j < kb) atomicCAS(flag, 0, k0 + c0 + j + 1);
+        const double sd = ok ? sqrt(p) : __builtin_nan("");
+        const double l = r > j ? d[j] / sd : (r == j ? sd : 0.0);
+        d[j] = l;
+#pragma unroll
+        for (int c = j + 1; c < SB; ++c) d[c] -= l * __shfl(l, c);   // entries past the diagonal are never read
+      }
+      if (lane < SB) {
+#pragma unroll
+        for (int c = 0; c < SB; ++c)
+          if (c <= r) a[c0 + r][c0 + c] = d[c];
+      }
+      // column c = r of D^-1: w_q = -(sum_{c <= k < q} L_qk w_k) / L_qq
+      double Ld[SB];   // this lane's row of L (for broadcasting L_qk below)
+#pragma unroll
+      for (int c = 0; c < SB; ++c) Ld[c] = d[c];
+      double w[SB];
+#pragma unroll
+      for (int q = 0; q < SB; ++q) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < q; ++k) {
+          const double lqk = __shfl(Ld[k], q);
+          v += k >= r ? lqk * w[k] : 0.0;
+        }
+        const double lqq = __shfl(Ld[q], q);
+        w[q] = q > r ? -v / lqq : (q == r ? 1.0 / lqq : 0.0);
+      }
+      if (lane < SB) {
+#pragma unroll
+        for (int q = 0; q < SB; ++q) Wf[c0 + q][c0 + r] = w[q];
+      }
     }
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    const double inv = 1.0 / Ls[qq][qq];
-    if (part == 0) Ws[qq][c] = qq > c ? -v * inv : (qq == c ? inv : 0.0);
+    __syncthreads();
+    // 2. panel rows below: X[i][j] = sum_{k <= j} a[i][c0 + k] W_D[j][k]
+    const int r0 = c0 + SB, nr = NB - r0;
+    double xo[3];
+    for (int u = 0; u < 3; ++u) {
+      const int e = t + 256 * u;
+      xo[u] = 0.0;
+      if (e < nr * SB) {
+        const int i = r0 + e / SB, j = e % SB;
+        double v = 0.0;
+        for (int k = 0; k <= j; ++k) v += a[i][c0 + k] * Wf[c0 + j][c0 + k];
+        xo[u] = v;
+      }
+    }
+    __syncthreads();
+    for (int u = 0; u < 3; ++u) {
+      const int e = t + 256 * u;
+      if (e < nr * SB) a[r0 + e / SB][c0 + e % SB] = xo[u];
+    }
+    __syncthreads();
+    // 3. trailing update inside the block: a[i][j] -= sum_k a[i][c0 + k] a[j][c0 + k], r0 <= j <= i
+    for (int e = t; e < nr * nr; e += 256) {
+      const int i = r0 + e / nr, j = r0 + e % nr;
+      if (j <= i) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < SB; ++k) v += a[i][c0 + k] * a[j][c0 + k];
+        a[i][j] -= v;
+      }
+    }
+    __syncthreads();
   }
-  if (c < kb)
-    for (int qq = c + 1 + part; qq < kb; qq += 4) A[(size_t)(k0 + c) * n + k0 + qq] = Ws[qq][c];
+  // the off-diagonal blocks of W, by block distance
+  for (int dist = 1; dist < NB / SB; ++dist) {
+    const int nbk = NB / SB - dist;   // blocks (I, J = I - dist)
+    for (int e = t; e < nbk * SB * SB; e += 256) {   // T_IJ = sum_{J <= K < I} L_IK W_KJ
+      const int b = e / (SB * SB), rc = e - b * SB * SB, I = b + dist, J = b;
+      const int i = SB * I + rc / SB, j = SB * J + rc % SB;
+      double v = 0.0;
+      for (int k = SB * J; k < SB * I; ++k) v += a[i][k] * Wf[k][j];
+      T[i][j] = v;
+    }
+    __syncthreads();
+    for (int e = t; e < nbk * SB * SB; e += 256) {   // W_IJ = -D_I^-1 T_IJ
+      const int b = e / (SB * SB), rc = e - b * SB * SB, I = b + dist, J = b;
+      const int i = SB * I + rc / SB, j = SB * J + rc % SB;
+      double v = 0.0;
+      for (int k = SB * I; k <= i; ++k) v += Wf[i][k] * T[k][j];
+      Wf[i][j] = -v;
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < NB * NB; e += 256) {
+    const int r = e / NB, c = e - r * NB;
+    if (r < kb && c < kb) A[(size_t)(k0 + r) * n + k0 + c] = c <= r ? a[r][c] : Wf[c][r];
+  }
 }
 
 // Forward substitution on the diagonal block for every right-hand side row.
