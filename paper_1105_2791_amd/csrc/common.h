@@ -187,8 +187,9 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 
 // adjoint
 hipError_t launch_slot_matrix(const modal_ctx* c, const double* cot, int S, void* K, hipStream_t st);
-hipError_t launch_pair_adjoint(const modal_ctx* c, const void* maps, const void* V, const void* K, int S,
-                               void* G, hipStream_t st);
+hipError_t launch_pair_adjoint(const modal_ctx* c, const void* maps, const void* K, int S, void* G, hipStream_t st);
+hipError_t launch_lin_vjp(const modal_ctx* c, const double* K, const void* Z, int S, void* H, void* grad,
+                          hipStream_t st);
 hipError_t launch_lambda_table(const modal_ctx* c, void* lam, hipStream_t st);
 hipError_t launch_adj_combine(const modal_ctx* c, const void* Z, int S, void* grad, hipStream_t st);
 

@@ -3,9 +3,13 @@
 // For L = sum_n c_n beta^hat_n, beta^hat_prs = sum_x w (M_p M_r M_s - V_pr M_s - V_ps M_r - V_rs M_p),
 //   dL/dM_u(x) = w(x) sum_{(ab)} K_{u,(ab)} (M_a M_b - V_ab)(x),
 // where K_{u,(ab)} = c_{sort(u,a,b)} times the number of legs of that triple equal
-// to u (each leg of the product differentiates to the other two).  The pair map
-// contraction over (ab) is done per pixel; the result then goes through the
-// r2c ring FFT and the adjoint Legendre contraction (k_fft.hip, k_legendre.hip).
+// to u (each leg of the product differentiates to the other two).  The pair-mean part
+// - w sum K V is linear in the state, and its image in harmonic space is a contraction
+// of the state's Z with K folded by the filters (k_lin_harm.hip); so the kernels here
+// form only the cubic part
+//   G_u(x) = w(x) sum_{(ab)} K_{u,(ab)} M_a(x) M_b(x)
+// per pixel.  G then goes through the r2c ring FFT and the adjoint Legendre
+// contraction (k_fft.hip, k_fisher.hip).
 #include "common.h"
 
 namespace modal {
@@ -23,14 +27,14 @@ __global__ void k_slot(int P, int npairs, int nmax, int S, const int* __restrict
 constexpr int kPx = 64;
 constexpr int kPc = 16;
 
-// One workgroup: 64 pixels of SK skies (SK = 2 for float maps, 1 for double); the pair
-// means of each 16-pair chunk are staged in LDS once for the SK skies with coalesced loads,
-// so the inner loop reads LDS only.  Thread (px, ug) accumulates the modes u = ug + 4 i.
-template <typename T, bool LIN, int SK>
+// One workgroup: 64 pixels of SK skies (SK = 2 for float maps, 1 for double); the slot
+// coefficients of each 16-pair chunk are staged in LDS once for the SK skies, so the inner
+// loop reads LDS only.  Thread (px, ug) accumulates the modes u = ug + 4 i.
+template <typename T, int SK>
 __global__ __launch_bounds__(256) void k_pair_adjoint(int P, int npairs, int npix, int S,
                                                       const int* __restrict__ pair_a, const int* __restrict__ pair_b,
-                                                      const T* __restrict__ maps, const T* __restrict__ V,
-                                                      const T* __restrict__ w, const double* __restrict__ K,
+                                                      const T* __restrict__ maps, const T* __restrict__ w,
+                                                      const double* __restrict__ K,
                                                       T* __restrict__ G) {
   const int s0 = blockIdx.y * SK;
   const int x0 = blockIdx.x * kPx;
@@ -38,7 +42,6 @@ __global__ __launch_bounds__(256) void k_pair_adjoint(int P, int npairs, int npi
   const int x = x0 + px;
   __shared__ T Mt[SK][kMaxP][kPx];
   __shared__ double Ks[SK][kMaxP][kPc];
-  __shared__ T Vs[kPc][kPx];
   __shared__ int sa[kPc], sb[kPc];
   for (int e = threadIdx.x; e < SK * P * kPx; e += 256) {
     const int sk = e / (P * kPx), rem = e - sk * P * kPx, p = rem / kPx, xx = rem - p * kPx;
@@ -58,11 +61,6 @@ __global__ __launch_bounds__(256) void k_pair_adjoint(int P, int npairs, int npi
       const int s = s0 + sk;
       Ks[sk][u][pc] = (s < S && pc < nc) ? K[((size_t)s * P + u) * npairs + c0 + pc] : 0.0;
     }
-    if (LIN)
-      for (int e = threadIdx.x; e < kPc * kPx; e += 256) {
-        const int pc = e / kPx, xx = e - pc * kPx;
-        Vs[pc][xx] = (pc < nc && x0 + xx < npix) ? V[(size_t)(c0 + pc) * npix + x0 + xx] : T(0);
-      }
     if (threadIdx.x < kPc) {
       sa[threadIdx.x] = threadIdx.x < nc ? pair_a[c0 + threadIdx.x] : 0;
       sb[threadIdx.x] = threadIdx.x < nc ? pair_b[c0 + threadIdx.x] : 0;
@@ -70,11 +68,10 @@ __global__ __launch_bounds__(256) void k_pair_adjoint(int P, int npairs, int npi
     __syncthreads();
     if (x < npix) {
       for (int pc = 0; pc < nc; ++pc) {
-        const double v = LIN ? (double)Vs[pc][px] : 0.0;
         const int a = sa[pc], b = sb[pc];
 #pragma unroll
         for (int sk = 0; sk < SK; ++sk) {
-          const double A = (double)Mt[sk][a][px] * (double)Mt[sk][b][px] - v;
+          const double A = (double)Mt[sk][a][px] * (double)Mt[sk][b][px];
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
             const int u = ug + 4 * i;
@@ -99,26 +96,23 @@ __global__ __launch_bounds__(256) void k_pair_adjoint(int P, int npairs, int npi
 }
 
 // Float maps, P <= 48: the same contraction on the matrix cores in FP32,
-//   G[u][x] = w(x) sum_pairs K[u][pair] (M_a M_b - V_ab)(x),
+//   G[u][x] = w(x) sum_pairs K[u][pair] M_a(x) M_b(x),
 // a GEMM with rows = modes u (three 16-row tiles), columns = pixels, inner index = pairs,
 // on v_mfma_f32_16x16x4_f32 (lane l holds A[l % 16][l / 16], B[l / 16][l % 16], and
 // accumulator register r is D[4 (l / 16) + r][l % 16]).  A = K of a 64-pair chunk (FP32,
 // in LDS), B = the pair product of the lane's pixel and pair, formed on the fly.  Each
 // chunk is a chain of 16 MFMAs from zero, added to the running sums with a vector add.
 // The S skies of one pixel block are consecutive workgroups on one XCD (workgroups are
-// dealt to the 8 XCDs round-robin), so the pair means V, the same for every sky, come
-// from HBM once per block and from that XCD's L2 for the other skies.
+// dealt to the 8 XCDs round-robin).
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 constexpr int kMx = 128;  // pixels per workgroup (32 per wave: two 16-column tiles)
 constexpr int kMc = 64;   // pairs per staged chunk (16 MFMA steps of 4)
 constexpr int kMt = 3;    // 16-mode tiles (P <= 48)
 
-template <bool LIN>
 __global__ __launch_bounds__(256) void k_pair_adjoint_mfma(int P, int npairs, int npix,
                                                            const int* __restrict__ pair_a,
                                                            const int* __restrict__ pair_b,
-                                                           const float* __restrict__ maps,
-                                                           const float* __restrict__ V, const float* __restrict__ w,
+                                                           const float* __restrict__ maps, const float* __restrict__ w,
                                                            const double* __restrict__ K, float* __restrict__ G,
                                                            int S, int nblk) {
   const int i8 = blockIdx.x >> 3;
@@ -130,7 +124,6 @@ __global__ __launch_bounds__(256) void k_pair_adjoint_mfma(int P, int npairs, in
   const int xl0 = wv * 32 + l16, xl1 = xl0 + 16;   // this lane's pixels within the block
   __shared__ float Mt[kMaxP][kMx];
   __shared__ float Ks[kMt * 16][kMc + 1];
-  __shared__ float Vs[kMc][kMx];
   __shared__ int sab[kMc];        // a | b << 8 of each pair of the chunk
   const float* Ms = maps + (size_t)s * P * npix;
   for (int e = tid; e < P * kMx; e += 256) {
@@ -143,11 +136,10 @@ __global__ __launch_bounds__(256) void k_pair_adjoint_mfma(int P, int npairs, in
 #pragma unroll
     for (int t = 0; t < kMt; ++t) acc[c][t] = f32x4{0.f, 0.f, 0.f, 0.f};
   const double* Kslab = K + (size_t)s * P * npairs;
-  // the next chunk's K, pair means and pair modes are loaded into registers before this
-  // chunk's MFMAs, so that their latency is hidden behind them
-  constexpr int NK = kMt * 16 * kMc / 256, NV = kMc * kMx / 256;
+  // the next chunk's K and pair modes are loaded into registers before this chunk's
+  // MFMAs, so that their latency is hidden behind them
+  constexpr int NK = kMt * 16 * kMc / 256;
   double pk[NK];
-  float pv[NV];
   int pab = 0;
   auto load_chunk = [&](int c0) {
     const int nc = min(kMc, npairs - c0);
@@ -155,11 +147,6 @@ __global__ __launch_bounds__(256) void k_pair_adjoint_mfma(int P, int npairs, in
     for (int i = 0; i < NK; ++i) {
       const int e = tid + 256 * i, u = e / kMc, pc = e - u * kMc;
       pk[i] = (u < P && pc < nc) ? Kslab[(size_t)u * npairs + c0 + pc] : 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      const int e = tid + 256 * i, pc = e / kMx, xx = e - pc * kMx;
-      pv[i] = (LIN && pc < nc && x0 + xx < npix) ? V[(size_t)(c0 + pc) * npix + x0 + xx] : 0.f;
     }
     if (tid < kMc) pab = tid < nc ? (pair_a[c0 + tid] | (pair_b[c0 + tid] << 8)) : 0;
   };
@@ -170,11 +157,6 @@ __global__ __launch_bounds__(256) void k_pair_adjoint_mfma(int P, int npairs, in
     for (int i = 0; i < NK; ++i) {
       const int e = tid + 256 * i, u = e / kMc, pc = e - u * kMc;
       Ks[u][pc] = (float)pk[i];
-    }
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      const int e = tid + 256 * i, pc = e / kMx, xx = e - pc * kMx;
-      Vs[pc][xx] = pv[i];
     }
     if (tid < kMc) sab[tid] = pab;
     __syncthreads();
@@ -189,11 +171,7 @@ __global__ __launch_bounds__(256) void k_pair_adjoint_mfma(int P, int npairs, in
     for (int ks = 0; ks < kMc / 4; ++ks) {
       const int pc = 4 * ks + kq;
       const int ab = sab[pc], a = ab & 0xff, b2 = (ab >> 8) & 0xff;
-      float b0 = Mt[a][xl0] * Mt[b2][xl0], b1 = Mt[a][xl1] * Mt[b2][xl1];
-      if (LIN) {
-        b0 -= Vs[pc][xl0];
-        b1 -= Vs[pc][xl1];
-      }
+      const float b0 = Mt[a][xl0] * Mt[b2][xl0], b1 = Mt[a][xl1] * Mt[b2][xl1];
 #pragma unroll
       for (int t = 0; t < kMt; ++t) {
         const float av = Ks[16 * t + l16][pc];
@@ -230,31 +208,21 @@ hipError_t launch_slot_matrix(const modal_ctx* c, const double* cot, int S, void
   return hipGetLastError();
 }
 
-hipError_t launch_pair_adjoint(const modal_ctx* c, const void* maps, const void* V, const void* K, int S, void* G,
-                               hipStream_t st) {
-#define LAUNCH(T, L, SKN, W)                                                                                     \
-  hipLaunchKernelGGL((k_pair_adjoint<T, L, SKN>), dim3((c->npix + kPx - 1) / kPx, (S + SKN - 1) / SKN), dim3(256), \
-                     0, st, c->P, c->npairs, c->npix, S, c->t.pair_a, c->t.pair_b, (const T*)maps, (const T*)V,   \
-                     (const T*)W, (const double*)K, (T*)G)
+hipError_t launch_pair_adjoint(const modal_ctx* c, const void* maps, const void* K, int S, void* G, hipStream_t st) {
   if (is_f64(c)) {
-    if (V) LAUNCH(double, true, 1, c->t.w64);
-    else LAUNCH(double, false, 1, c->t.w64);
+    hipLaunchKernelGGL((k_pair_adjoint<double, 1>), dim3((c->npix + kPx - 1) / kPx, S), dim3(256), 0, st, c->P,
+                       c->npairs, c->npix, S, c->t.pair_a, c->t.pair_b, (const double*)maps, c->t.w64,
+                       (const double*)K, (double*)G);
   } else if (c->P <= kMt * 16) {
     const int nblk = (c->npix + kMx - 1) / kMx;
-    const dim3 grid(8 * ((nblk + 7) / 8) * S);
-    if (V)
-      hipLaunchKernelGGL(k_pair_adjoint_mfma<true>, grid, dim3(256), 0, st, c->P, c->npairs, c->npix, c->t.pair_a,
-                         c->t.pair_b, (const float*)maps, (const float*)V, c->t.w32, (const double*)K, (float*)G, S,
-                         nblk);
-    else
-      hipLaunchKernelGGL(k_pair_adjoint_mfma<false>, grid, dim3(256), 0, st, c->P, c->npairs, c->npix, c->t.pair_a,
-                         c->t.pair_b, (const float*)maps, (const float*)V, c->t.w32, (const double*)K, (float*)G, S,
-                         nblk);
+    hipLaunchKernelGGL(k_pair_adjoint_mfma, dim3(8 * ((nblk + 7) / 8) * S), dim3(256), 0, st, c->P, c->npairs,
+                       c->npix, c->t.pair_a, c->t.pair_b, (const float*)maps, c->t.w32, (const double*)K, (float*)G,
+                       S, nblk);
   } else {
-    if (V) LAUNCH(float, true, 2, c->t.w32);
-    else LAUNCH(float, false, 2, c->t.w32);
+    hipLaunchKernelGGL((k_pair_adjoint<float, 2>), dim3((c->npix + kPx - 1) / kPx, (S + 1) / 2), dim3(256), 0, st,
+                       c->P, c->npairs, c->npix, S, c->t.pair_a, c->t.pair_b, (const float*)maps, c->t.w32,
+                       (const double*)K, (float*)G);
   }
-#undef LAUNCH
   return hipGetLastError();
 }
 

@@ -136,6 +136,91 @@ __global__ __launch_bounds__(64) void k_lin_l(int lmax, int npairs, int P, const
   if (t < P) L[((size_t)s * npairs + pair) * P + t] = acc;
 }
 
+// The adjoint of the linear term with respect to a_lm.  With the slot matrix K of the
+// adjoint (K[s][u][pair]: dL/dlin summed onto the leg u of each triple),
+//   dL/da^s_lm (linear part) = - sum_pair H_{s,pair}(l) Z_pair,lm,
+//   H_{s,pair}(l) = sum_u K[s][u][pair] qw_u(l),
+// the transpose of the X contraction above: the same reordering of finite sums, so the
+// pixel-space adjoint needs only the cubic part w sum K M_a M_b.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lin_vjp_h(int lmax, int P, int npairs, const double* __restrict__ qw,
+                                                   const double* __restrict__ K, T* __restrict__ H) {
+  const int l = blockIdx.x * 256 + threadIdx.x;
+  const int pair = blockIdx.y, s = blockIdx.z;
+  if (l > lmax) return;
+  const double* k = K + (size_t)s * P * npairs + pair;
+  double acc = 0.0;
+  for (int u = 0; u < P; ++u) acc = fma(k[(size_t)u * npairs], qw[(size_t)u * (lmax + 1) + l], acc);
+  H[((size_t)s * npairs + pair) * (lmax + 1) + l] = T(acc);
+}
+
+// grad[s][lm] -= sum_pair H[s][pair][l] Z[pair][lm], FP64 sums.  A workgroup covers VL
+// consecutive l (one per lane) x VW VM consecutive m x VS maps; wave w takes the m
+// m0 + w + VW j.  Each Z element is read once; lanes with l < m read a valid element
+// and add nothing.
+constexpr int VL = 64;
+constexpr int VW = 4;
+constexpr int VM = 4;
+constexpr int VS = 8;
+
+template <typename T>
+__global__ __launch_bounds__(VL * VW) void k_lin_vjp(int lmax, int nalm, int npairs, int S, const T* __restrict__ H,
+                                                     const typename vec2<T>::type* __restrict__ Z,
+                                                     typename vec2<T>::type* __restrict__ grad) {
+  using T2 = typename vec2<T>::type;
+  const int lane = threadIdx.x % VL, w = threadIdx.x / VL;
+  const int l = blockIdx.x * VL + lane;
+  const int lc = min(l, lmax);
+  const int m0 = blockIdx.y * (VW * VM);
+  const int s0 = blockIdx.z * VS;
+  if (m0 > min((int)blockIdx.x * VL + VL - 1, lmax)) return;   // no l >= m in the tile (no barrier below)
+  size_t idx[VM];
+  bool on[VM];
+#pragma unroll
+  for (int j = 0; j < VM; ++j) {
+    const int m = min(m0 + w + VW * j, lmax);
+    on[j] = m0 + w + VW * j <= l && l <= lmax;
+    idx[j] = (size_t)m * (2 * lmax + 3 - m) / 2 + (max(lc, m) - m);   // m-major packing
+  }
+  double ar[VM][VS], ai[VM][VS];
+#pragma unroll
+  for (int j = 0; j < VM; ++j)
+#pragma unroll
+    for (int q = 0; q < VS; ++q) ar[j][q] = ai[j][q] = 0.0;
+  const T* hr[VS];
+#pragma unroll
+  for (int q = 0; q < VS; ++q) hr[q] = H + (size_t)min(s0 + q, S - 1) * npairs * (lmax + 1) + lc;
+  for (int pair = 0; pair < npairs; ++pair) {
+    double h[VS];
+#pragma unroll
+    for (int q = 0; q < VS; ++q) h[q] = (double)hr[q][(size_t)pair * (lmax + 1)];
+    const T2* zp = Z + (size_t)pair * nalm;
+#pragma unroll
+    for (int j = 0; j < VM; ++j) {
+      const T2 z = zp[idx[j]];
+      const double zx = on[j] ? (double)z.x : 0.0, zy = on[j] ? (double)z.y : 0.0;
+#pragma unroll
+      for (int q = 0; q < VS; ++q) {
+        ar[j][q] = fma(h[q], zx, ar[j][q]);
+        ai[j][q] = fma(h[q], zy, ai[j][q]);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < VM; ++j) {
+    if (!on[j]) continue;
+#pragma unroll
+    for (int q = 0; q < VS; ++q) {
+      if (s0 + q >= S) break;
+      T2* g = grad + (size_t)(s0 + q) * nalm + idx[j];
+      T2 v = *g;
+      v.x = T((double)v.x - ar[j][q]);
+      v.y = T((double)v.y - ai[j][q]);
+      *g = v;
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_weight_planes(const modal_ctx* c, const void* V, int nk, void* G, hipStream_t st) {
@@ -163,6 +248,24 @@ hipError_t launch_lin_harmonic(const modal_ctx* c, const void* Z, const void* al
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_lin_l, dim3(c->npairs, S), dim3(64), 0, st, c->lmax, c->npairs, c->P, c->t.qw64, X, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_lin_vjp(const modal_ctx* c, const double* K, const void* Z, int S, void* H, void* grad,
+                          hipStream_t st) {
+  const dim3 gh((c->lmax + 256) / 256, c->npairs, S);
+  const dim3 gv((c->lmax + VL) / VL, (c->lmax + VW * VM) / (VW * VM), (S + VS - 1) / VS);
+  if (is_f64(c)) {
+    hipLaunchKernelGGL(k_lin_vjp_h<double>, gh, dim3(256), 0, st, c->lmax, c->P, c->npairs, c->t.qw64, K,
+                       (double*)H);
+    hipLaunchKernelGGL(k_lin_vjp<double>, gv, dim3(VL * VW), 0, st, c->lmax, c->nalm, c->npairs, S,
+                       (const double*)H, (const double2*)Z, (double2*)grad);
+  } else {
+    hipLaunchKernelGGL(k_lin_vjp_h<float>, gh, dim3(256), 0, st, c->lmax, c->P, c->npairs, c->t.qw64, K,
+                       (float*)H);
+    hipLaunchKernelGGL(k_lin_vjp<float>, gv, dim3(VL * VW), 0, st, c->lmax, c->nalm, c->npairs, S,
+                       (const float*)H, (const float2*)Z, (float2*)grad);
+  }
   return hipGetLastError();
 }
 
