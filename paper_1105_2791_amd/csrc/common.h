@@ -187,7 +187,10 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 
 // adjoint
 hipError_t launch_slot_matrix(const modal_ctx* c, const double* cot, int S, void* K, hipStream_t st);
-hipError_t launch_pair_adjoint(const modal_ctx* c, const void* maps, const void* K, int S, void* G, hipStream_t st);
+// workspace of launch_pair_adjoint (the split operands of the slot coefficients; 0 when unused)
+size_t pair_adjoint_ws_bytes(const modal_ctx* c, int S);
+hipError_t launch_pair_adjoint(const modal_ctx* c, const void* maps, const void* K, int S, void* G, void* ws,
+                               hipStream_t st);
 hipError_t launch_lin_vjp(const modal_ctx* c, const double* K, const void* Z, int S, void* H, void* grad,
                           hipStream_t st);
 hipError_t launch_lambda_table(const modal_ctx* c, void* lam, hipStream_t st);

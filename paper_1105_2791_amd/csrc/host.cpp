@@ -180,6 +180,7 @@ size_t ws_size(const modal_ctx* c, int op, int S) {
       cv.take(F_bytes(c, S)); cv.take(maps_bytes(c, S)); cv.take((size_t)S * c->P * c->npairs * 8);
       cv.take(maps_bytes(c, S)); cv.take(F_bytes(c, S)); cv.take(lam_bytes(c));
       cv.take((size_t)S * c->P * alm_bytes(c)); cv.take((size_t)S * c->npairs * (c->lmax + 1) * real_bytes(c));
+      cv.take(pair_adjoint_ws_bytes(c, S));
       break;
     case MODAL_OP_COVARIANCE_SAMPLE: cv.take(256); break;
     case MODAL_OP_COVARIANCE_CENTERED: cv.take((size_t)S * c->nmax * 8); break;
@@ -861,10 +862,11 @@ modal_status modal_beta_vjp(modal_ctx* c, const void* alm, int S, const void* st
   void* lam = cv.take(lam_bytes(c));
   void* Zc = cv.take((size_t)S * c->P * alm_bytes(c));   // per (sky, mode) column
   void* H = cv.take((size_t)S * c->npairs * (c->lmax + 1) * real_bytes(c));
+  void* Kw = cv.take(pair_adjoint_ws_bytes(c, S));
   if ((s = run_maps(c, alm, S, F, maps, st)) != MODAL_OK) return s;
   STAGE(MODAL_STAGE_ADJ_PAIR, launch_slot_matrix(c, cot, S, K, st));
   // the cubic part in pixel space; the pair-mean part is added in harmonic space below
-  STAGE(MODAL_STAGE_ADJ_PAIR, launch_pair_adjoint(c, maps, K, S, G, st));
+  STAGE(MODAL_STAGE_ADJ_PAIR, launch_pair_adjoint(c, maps, K, S, G, Kw, st));
   STAGE(MODAL_STAGE_ADJ_FFT, launch_fft_r2c(c, G, S, Gh, st));
   STAGE(MODAL_STAGE_ADJ_LEGENDRE, launch_lambda_table(c, lam, st));
   STAGE(MODAL_STAGE_ADJ_LEGENDRE, launch_adj_legendre_cols(c, lam, Gh, S * c->P, Zc, st));

@@ -70,4 +70,8 @@ CASES = {
     # nphi = 94: a prime half-length ring transform (K = 47), the radix that the l_max 2000
     # grid (nphi 6016 = 128 x 47) needs, in the generic transform kernels (c2r and r2c)
     "prime": Case("prime", 32, 48, 94, 8, 2, "wmap", 41),
+    # the headline mode count, P = 40 (two 32-mode tiles in the split adjoint), and the largest
+    # the split adjoint takes, P = 48 (168 eight-pair groups), on the l_max = 32 grid
+    "wide": Case("wide", 32, 48, 96, 40, 2, "wmap", 51),
+    "wide48": Case("wide48", 32, 48, 96, 48, 2, "wmap", 61),
 }

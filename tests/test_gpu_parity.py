@@ -160,6 +160,33 @@ def test_vjp_matches_oracle_gradient(name, prec):
         assert err < MAP_TOL[prec], err
 
 
+@pytest.mark.parametrize("name,prec", [("wide", "bf16x3"), ("wide", "f32"), ("wide", "f16x3"), ("wide", "f64"),
+                                       ("wide48", "bf16x3"), ("wide48", "f32")])
+def test_vjp_wide_modes(name, prec):
+    """The adjoint at 33..48 modes: two 32-row mode tiles of the split contraction."""
+    case = CASES[name]
+    c = ctx_for(case, prec)
+    o = oracle_for(case)
+    print(f"[case] vjp {name} {prec}", flush=True)
+    st = c.linear_state()
+    c.linear_reset(st)
+    c.linear_accumulate(st, o["mc"])
+    c.linear_finalize(st)
+    rng = np.random.default_rng(19)
+    cot = rng.standard_normal((2, mi.ntriples(case.P)))
+    g = c.beta_vjp(o["alms"][:2], cot, state=st).cpu().numpy()
+    gn = c.beta_vjp(o["alms"][:2], cot).cpu().numpy()   # no state: the cubic part alone
+    for i in range(2):
+        ref = om.vjp(o["alms"][i], case.cl, case.q, case.grid, o["V"], cot[i])[0]
+        err = np.linalg.norm(g[i] - ref) / np.linalg.norm(ref)
+        log_err(f"vjp {name} {prec} sim{i}", err)
+        assert err < MAP_TOL[prec], err
+        ref0 = om.vjp(o["alms"][i], case.cl, case.q, case.grid, None, cot[i])[0]
+        err0 = np.linalg.norm(gn[i] - ref0) / np.linalg.norm(ref0)
+        log_err(f"vjp {name} {prec} no state sim{i}", err0)
+        assert err0 < MAP_TOL[prec], err0
+
+
 def test_sample_covariance_and_estimator():
     case = CASES["tiny"]
     c = ctx_for(case, "f64")
