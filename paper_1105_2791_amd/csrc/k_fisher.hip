@@ -224,6 +224,175 @@ __global__ __launch_bounds__(256) void k_adj_legendre_mfma(int lmax, int ntheta,
     }
 }
 
+// bf16x3 contexts: the same sums on the bf16 matrix cores with split operands.  Per m,
+//   Z^T[c][l] = sum_j H_{(l - m) mod 2}^T[c][j] lambda[m][j][l]   (K = the northern rings),
+// on v_mfma_f32_32x32x16_bf16: A = H^T (rows = 32 real columns, K = 16 rings), B = lambda
+// (K = 16 rings, N = 32 l of one parity); lane l holds A[l % 32][8 (l / 32) + i] and
+// B[8 (l / 32) + i][l % 32]; accumulator register r is D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+// Both operands are split into bf16 hi + lo and each product is Ah Bh + Ah Bl + Al Bh.
+// Workgroup: 4 waves, one m, 128 consecutive l - m (wave w: the 32 l of parity w / 2 in
+// the half w % 2), 64 complex columns (4 tiles of 32 real columns).  The folded ring values
+// of a 32-ring chunk are split and staged in LDS, double buffered; each lane loads the
+// lambda of its l at 8 rings from the FP32 table one K step ahead and splits them in
+// registers.  The workgroups of one m (l blocks x column blocks) run back to back on one
+// XCD, so lambda[m] and the ring values of m come from HBM about once.  An output takes
+// 3 nrp / 16 accumulations (144 at 768 rings); the truncation of the matrix core's
+// accumulation stays below the operand split error.
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
+constexpr int AS_L = 128;         // l per workgroup (32 of one parity per wave)
+constexpr int AS_NC = 64;         // complex columns per workgroup
+constexpr int AS_RC = 32;         // rings per staged chunk (two K steps)
+constexpr int AS_RS = AS_RC + 8;  // LDS row stride of a staged column (16-bit words): 16-byte reads of 16 lanes on distinct banks
+
+struct AsLds {
+  uint16_t h[2][2][2 * AS_NC][AS_RS];   // [buffer][parity][real column][ring of the chunk]
+  uint16_t l[2][2][2 * AS_NC][AS_RS];
+};
+
+__device__ inline uint32_t as_bf16x2(float a, float b) {
+  typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
+  bf16x2 v;
+  v[0] = (__bf16)a;
+  v[1] = (__bf16)b;
+  return __builtin_bit_cast(uint32_t, v);
+}
+
+// bf16 hi/lo words of two values (RNE each; the split starts from the rounded FP32 value)
+__device__ inline void as_split2(float v0, float v1, uint32_t& hi, uint32_t& lo) {
+  asm("" : "+v"(v0), "+v"(v1));
+  uint32_t hb = as_bf16x2(v0, v1);
+  asm("" : "+v"(hb));
+  hi = hb;
+  lo = as_bf16x2(v0 - __builtin_bit_cast(float, hb << 16), v1 - __builtin_bit_cast(float, hb & 0xffff0000u));
+}
+
+__global__ __launch_bounds__(256) void k_adj_legendre_split(int lmax, int ntheta, int nrp, int ncol, int nalm, int nlb,
+                                                            int ncb, const float* __restrict__ lam,
+                                                            const float2* __restrict__ Gh, float* __restrict__ Z) {
+  typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+  const int xcd = blockIdx.x & 7, i8 = blockIdx.x >> 3, per = nlb * ncb;
+  const int m = xcd + 8 * (i8 / per);
+  const int lb = (i8 % per) / ncb, cb = (i8 % per) % ncb;
+  const int L = lmax + 1 - m;
+  if (m > lmax || lb * AS_L >= L) return;   // whole workgroup, before any barrier
+  const int c0 = cb * AS_NC;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, n = lane & 31, h = lane >> 5;
+  const size_t off = (size_t)m * (2 * lmax + 3 - m) / 2;
+  const float* lrow = lam + off * nrp;
+  __shared__ AsLds S;
+  const int par = wv >> 1;                        // the parity of l - m of this wave's rows
+  const int li = lb * AS_L + 64 * (wv & 1) + 2 * n + par;   // this lane's B column (l - m)
+  const int lcl = min(li, L - 1);
+  // lambda at rings 16 t + 8 h + i of the lane's l (valid addresses for every t)
+  float lv[8];
+  auto load_lam = [&](int t) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) lv[i] = lrow[(size_t)min(16 * t + 8 * h + i, nrp - 1) * L + lcl];
+  };
+  // ring values of a chunk: thread (column q, ring pair jp) for four (q, jp), north and south
+  constexpr int NU = AS_NC * AS_RC / 2 / 256;
+  float2 gn[NU][2], gs[NU][2];
+  auto load_g = [&](int r0) {
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int e = tid + 256 * u, jp = e % (AS_RC / 2), q = e / (AS_RC / 2);
+      const float2* g = Gh + ((size_t)min(c0 + q, ncol - 1) * (lmax + 1) + m) * ntheta;   // Gh[col][m][ring]
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int j = min(r0 + 2 * jp + k, nrp - 1);
+        gn[u][k] = g[j];
+        gs[u][k] = g[ntheta - 1 - j];
+      }
+    }
+  };
+  auto store_g = [&](int r0, int buf) {
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int e = tid + 256 * u, jp = e % (AS_RC / 2), q = e / (AS_RC / 2);
+      float hp[2][2], hm[2][2];   // [part][ring of the pair]
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int j = r0 + 2 * jp + k;
+        const bool in = j < nrp && c0 + q < ncol;
+        const float2 vn = in ? gn[u][k] : make_float2(0.f, 0.f);
+        const float2 vs = (in && ntheta - 1 - j != j) ? gs[u][k] : make_float2(0.f, 0.f);   // the equator ring once
+        hp[0][k] = vn.x + vs.x;
+        hp[1][k] = vn.y + vs.y;
+        hm[0][k] = vn.x - vs.x;
+        hm[1][k] = vn.y - vs.y;
+      }
+#pragma unroll
+      for (int part = 0; part < 2; ++part) {
+        uint32_t hi, lo;
+        as_split2(hp[part][0], hp[part][1], hi, lo);
+        *reinterpret_cast<uint32_t*>(&S.h[buf][0][2 * q + part][2 * jp]) = hi;
+        *reinterpret_cast<uint32_t*>(&S.l[buf][0][2 * q + part][2 * jp]) = lo;
+        as_split2(hm[part][0], hm[part][1], hi, lo);
+        *reinterpret_cast<uint32_t*>(&S.h[buf][1][2 * q + part][2 * jp]) = hi;
+        *reinterpret_cast<uint32_t*>(&S.l[buf][1][2 * q + part][2 * jp]) = lo;
+      }
+    }
+  };
+  f32x16 acc[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[ct][r] = 0.f;
+  const int nch = (nrp + AS_RC - 1) / AS_RC;
+  load_g(0);
+  store_g(0, 0);
+  load_g(AS_RC);
+  load_lam(0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    // chunk ch + 1 into the other buffer (last read in chunk ch - 1, before the barrier
+    // that ended it), then the loads of chunk ch + 2
+    if (ch + 1 < nch) {
+      store_g((ch + 1) * AS_RC, buf ^ 1);
+      load_g((ch + 2) * AS_RC);
+    }
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      const int t = 2 * ch + kk;
+      bf16x8 bh, bl;
+      {
+        u32x4 hv, lo4;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          uint32_t hw, lw2;
+          as_split2(lv[2 * k], lv[2 * k + 1], hw, lw2);
+          hv[k] = hw;
+          lo4[k] = lw2;
+        }
+        bh = __builtin_bit_cast(bf16x8, hv);
+        bl = __builtin_bit_cast(bf16x8, lo4);
+      }
+      load_lam(t + 1);   // one K step ahead (clamped past the last ring: unused)
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&S.h[buf][par][32 * ct + n][16 * kk + 8 * h]));
+        const bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&S.l[buf][par][32 * ct + n][16 * kk + 8 * h]));
+        acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[ct], 0, 0, 0);
+        acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[ct], 0, 0, 0);
+        acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[ct], 0, 0, 0);
+      }
+    }
+    __syncthreads();   // chunk ch read by all waves; chunk ch + 1 visible
+  }
+  if (li >= L) return;
+  const float cm = (m == 0) ? 1.f : 2.f;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int rc = 32 * ct + 8 * (r >> 2) + 4 * h + (r & 3);
+      const int col = c0 + (rc >> 1), part = rc & 1;
+      if (col < ncol) Z[((size_t)col * nalm + off + li) * 2 + part] = (m == 0 && part) ? 0.f : cm * acc[ct][r];
+    }
+}
+
 // X[l][a][b] += C_l [Re Za Re Zb (m=0) + 1/2 sum_{m>=1} (Re Za Re Zb + Im Za Im Zb)], 64x64 tiles, lower tiles only.
 constexpr int XT = 64;
 constexpr int MC = 16;
@@ -352,6 +521,11 @@ hipError_t launch_adj_legendre_cols(const modal_ctx* c, const void* lam, const v
     dim3 grid((c->lmax + 1 + 63) / 64, c->lmax + 1, (ncol + NC - 1) / NC);
     hipLaunchKernelGGL(k_adj_legendre_cols<float>, grid, dim3(64), 0, st, c->lmax, c->ntheta, c->nrp, ncol, c->nalm,
                        (const float*)lam, (const float2*)Gh, (float2*)Z);
+  } else if (c->prec == MODAL_BF16X3) {
+    const int nlb = (c->lmax + AS_L) / AS_L, ncb = (ncol + AS_NC - 1) / AS_NC;
+    const dim3 grid(8 * ((c->lmax + 8) / 8) * nlb * ncb);
+    hipLaunchKernelGGL(k_adj_legendre_split, grid, dim3(256), 0, st, c->lmax, c->ntheta, c->nrp, ncol, c->nalm, nlb,
+                       ncb, (const float*)lam, (const float2*)Gh, (float*)Z);
   } else {
     dim3 grid((c->lmax + 1 + 63) / 64, c->lmax + 1, (ncol + AL_NC - 1) / AL_NC);
     hipLaunchKernelGGL(k_adj_legendre_mfma, grid, dim3(256), 0, st, c->lmax, c->ntheta, c->nrp, ncol, c->nalm,
