@@ -155,42 +155,43 @@ __global__ __launch_bounds__(256) void k_lin_vjp_h(int lmax, int P, int npairs, 
 }
 
 // grad[s][lm] -= sum_pair H[s][pair][l] Z[pair][lm], FP64 sums.  A workgroup covers VL
-// consecutive l (one per lane) x VW VM consecutive m x VS maps; wave w takes the m
-// m0 + w + VW j.  Each Z element is read once; lanes with l < m read a valid element
-// and add nothing.
+// consecutive l (one per lane) x VM consecutive m x VS maps; its VW waves take the pairs
+// in turn (pair = w, w + VW, ...) and their partial sums are added through LDS, so that
+// every wave runs a short loop and many waves are in flight.  Each Z element is read
+// once; lanes with l < m read a valid element and add nothing.
 constexpr int VL = 64;
 constexpr int VW = 4;
 constexpr int VM = 4;
 constexpr int VS = 8;
+constexpr int VRED = 16;   // accumulators per LDS reduction round
 
 template <typename T>
 __global__ __launch_bounds__(VL * VW) void k_lin_vjp(int lmax, int nalm, int npairs, int S, const T* __restrict__ H,
                                                      const typename vec2<T>::type* __restrict__ Z,
                                                      typename vec2<T>::type* __restrict__ grad) {
   using T2 = typename vec2<T>::type;
+  __shared__ double red[VW - 1][VRED][VL];
   const int lane = threadIdx.x % VL, w = threadIdx.x / VL;
   const int l = blockIdx.x * VL + lane;
   const int lc = min(l, lmax);
-  const int m0 = blockIdx.y * (VW * VM);
+  const int m0 = blockIdx.y * VM;
   const int s0 = blockIdx.z * VS;
-  if (m0 > min((int)blockIdx.x * VL + VL - 1, lmax)) return;   // no l >= m in the tile (no barrier below)
+  if (m0 > min((int)blockIdx.x * VL + VL - 1, lmax)) return;   // whole workgroup: no l >= m in the tile
   size_t idx[VM];
   bool on[VM];
 #pragma unroll
   for (int j = 0; j < VM; ++j) {
-    const int m = min(m0 + w + VW * j, lmax);
-    on[j] = m0 + w + VW * j <= l && l <= lmax;
+    const int m = min(m0 + j, lmax);
+    on[j] = m0 + j <= l && l <= lmax;
     idx[j] = (size_t)m * (2 * lmax + 3 - m) / 2 + (max(lc, m) - m);   // m-major packing
   }
-  double ar[VM][VS], ai[VM][VS];
+  double acc[2 * VM * VS];   // [re/im][j][q]
 #pragma unroll
-  for (int j = 0; j < VM; ++j)
-#pragma unroll
-    for (int q = 0; q < VS; ++q) ar[j][q] = ai[j][q] = 0.0;
+  for (int k = 0; k < 2 * VM * VS; ++k) acc[k] = 0.0;
   const T* hr[VS];
 #pragma unroll
   for (int q = 0; q < VS; ++q) hr[q] = H + (size_t)min(s0 + q, S - 1) * npairs * (lmax + 1) + lc;
-  for (int pair = 0; pair < npairs; ++pair) {
+  for (int pair = w; pair < npairs; pair += VW) {
     double h[VS];
 #pragma unroll
     for (int q = 0; q < VS; ++q) h[q] = (double)hr[q][(size_t)pair * (lmax + 1)];
@@ -201,11 +202,28 @@ __global__ __launch_bounds__(VL * VW) void k_lin_vjp(int lmax, int nalm, int npa
       const double zx = on[j] ? (double)z.x : 0.0, zy = on[j] ? (double)z.y : 0.0;
 #pragma unroll
       for (int q = 0; q < VS; ++q) {
-        ar[j][q] = fma(h[q], zx, ar[j][q]);
-        ai[j][q] = fma(h[q], zy, ai[j][q]);
+        acc[(0 * VM + j) * VS + q] = fma(h[q], zx, acc[(0 * VM + j) * VS + q]);
+        acc[(1 * VM + j) * VS + q] = fma(h[q], zy, acc[(1 * VM + j) * VS + q]);
       }
     }
   }
+  // add the partial sums of waves 1 .. VW-1 into wave 0, VRED accumulators at a time
+#pragma unroll
+  for (int r0 = 0; r0 < 2 * VM * VS; r0 += VRED) {
+    __syncthreads();
+    if (w > 0) {
+#pragma unroll
+      for (int i = 0; i < VRED; ++i) red[w - 1][i][lane] = acc[r0 + i];
+    }
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+      for (int i = 0; i < VRED; ++i)
+#pragma unroll
+        for (int v = 0; v < VW - 1; ++v) acc[r0 + i] += red[v][i][lane];
+    }
+  }
+  if (w != 0) return;
 #pragma unroll
   for (int j = 0; j < VM; ++j) {
     if (!on[j]) continue;
@@ -214,8 +232,8 @@ __global__ __launch_bounds__(VL * VW) void k_lin_vjp(int lmax, int nalm, int npa
       if (s0 + q >= S) break;
       T2* g = grad + (size_t)(s0 + q) * nalm + idx[j];
       T2 v = *g;
-      v.x = T((double)v.x - ar[j][q]);
-      v.y = T((double)v.y - ai[j][q]);
+      v.x = T((double)v.x - acc[(0 * VM + j) * VS + q]);
+      v.y = T((double)v.y - acc[(1 * VM + j) * VS + q]);
       *g = v;
     }
   }
@@ -254,7 +272,7 @@ hipError_t launch_lin_harmonic(const modal_ctx* c, const void* Z, const void* al
 hipError_t launch_lin_vjp(const modal_ctx* c, const double* K, const void* Z, int S, void* H, void* grad,
                           hipStream_t st) {
   const dim3 gh((c->lmax + 256) / 256, c->npairs, S);
-  const dim3 gv((c->lmax + VL) / VL, (c->lmax + VW * VM) / (VW * VM), (S + VS - 1) / VS);
+  const dim3 gv((c->lmax + VL) / VL, (c->lmax + VM) / VM, (S + VS - 1) / VS);
   if (is_f64(c)) {
     hipLaunchKernelGGL(k_lin_vjp_h<double>, gh, dim3(256), 0, st, c->lmax, c->P, c->npairs, c->t.qw64, K,
                        (double*)H);
