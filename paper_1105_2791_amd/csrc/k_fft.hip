@@ -565,9 +565,28 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_r2c_rg(FftPlan plan, int 
     float2* bw = rbuf + w * KP;
     if (j < ntheta) {   // wave-uniform
       const float2* src = reinterpret_cast<const float2*>(G + ((size_t)seq * ntheta + j) * plan.N);
-      for (int n = lane; n < K; n += 64) {
-        const float2 v = src[n];
-        bw[padr(n)] = make_float2(v.x, -v.y);
+      if constexpr (PTS <= 24) {
+        // the row in rounds of 8 loads per lane issued before their stores (64 PTS >= K):
+        // a round trip per 512 points instead of per 64 (at more points per lane the extra
+        // registers would cost the second wave per SIMD)
+        const float2* srcl = src + lane;
+        float2* dstb = bw + padr(lane);   // padr(n + 64) = padr(n) + 72: constant offsets
+        constexpr int RL = 8;
+#pragma unroll
+        for (int i0 = 0; i0 < PTS; i0 += RL) {
+          float2 v[RL];
+#pragma unroll
+          for (int i = 0; i < RL; ++i)
+            if (i0 + i < PTS && lane + 64 * (i0 + i) < K) v[i] = srcl[64 * (i0 + i)];
+#pragma unroll
+          for (int i = 0; i < RL; ++i)
+            if (i0 + i < PTS && lane + 64 * (i0 + i) < K) dstb[72 * (i0 + i)] = make_float2(v[i].x, -v[i].y);
+        }
+      } else {
+        for (int n = lane; n < K; n += 64) {
+          const float2 v = src[n];
+          bw[padr(n)] = make_float2(v.x, -v.y);
+        }
       }
       int Ns = 1;
       const float2* tf = twp;
