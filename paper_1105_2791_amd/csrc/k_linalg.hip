@@ -466,20 +466,36 @@ hipError_t launch_cholesky_lookahead(int n, double* A, int* flag, hipStream_t st
     hipLaunchKernelGGL((k_tile_update<T, false, true, false>), dim3(nbx, nb), dim3(256), 0, s, n, kb, r0, A + k0, n,
                        -1.0, A);
   };
-  hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, n, A, 0, n < NB ? n : NB, flag);
-  if (n > NB) hipLaunchKernelGGL(k_panel_mfma, dim3((n - NB + NB - 1) / NB), dim3(256), 0, st, n, A, 0, NB);
-  for (int k0 = 0; k0 + NB < n; k0 += NB) {
-    const int k1 = k0 + NB;              // the next diagonal block
-    const int kb1 = n - k1 < NB ? n - k1 : NB;
-    // the next block's columns first (its diagonal block and panel rows), then the rest
-    update(k0, NB, k1, 1, st);
+  // Factor the block column [k, k + 2 NB) (its two NB-wide halves), all updates from the
+  // columns left of k applied: diagonal block and panel of the first half, its update of the
+  // second half's columns, then the second half's diagonal block and panel.
+  auto factor2 = [&](int k, hipStream_t s) {
+    const int kb = n - k < NB ? n - k : NB;
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, n, A, k, kb, flag);
+    if (n - k - kb > 0) hipLaunchKernelGGL(k_panel_mfma, dim3((n - k - kb + NB - 1) / NB), dim3(256), 0, s, n, A, k, kb);
+    const int k2 = k + NB;
+    if (k2 < n) {
+      update(k, NB, k2, 1, s);
+      const int kb2 = n - k2 < NB ? n - k2 : NB;
+      hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, n, A, k2, kb2, flag);
+      if (n - k2 - kb2 > 0)
+        hipLaunchKernelGGL(k_panel_mfma, dim3((n - k2 - kb2 + NB - 1) / NB), dim3(256), 0, s, n, A, k2, kb2);
+    }
+  };
+  // The trailing updates take both halves of a factored block column at once (K = 2 NB), so
+  // each trailing tile is read and written once per 2 NB columns instead of per NB.
+  factor2(0, st);
+  for (int k0 = 0; k0 + 2 * NB < n; k0 += 2 * NB) {
+    const int k1 = k0 + 2 * NB;   // the next block column (both halves of [k0, k1) are NB wide)
+    const int w1 = n - k1 < 2 * NB ? n - k1 : 2 * NB;
+    const int nb1 = (w1 + T - 1) / T;   // its tile columns
+    // the next block column's tiles first, then the rest of the trailing matrix
+    update(k0, 2 * NB, k1, nb1, st);
     hipError_t e = hipEventRecord(ev_a, st);
     if (e != hipSuccess) return e;
-    if (n - k1 > NB) update(k0, NB, k1 + NB, (n - k1 - NB + T - 1) / T, st);
+    if (n - k1 > 2 * NB) update(k0, 2 * NB, k1 + 2 * NB, (n - k1 - 2 * NB + T - 1) / T, st);
     if ((e = hipStreamWaitEvent(side, ev_a, 0)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, side, n, A, k1, kb1, flag);
-    const int rem = n - k1 - kb1;
-    if (rem > 0) hipLaunchKernelGGL(k_panel_mfma, dim3((rem + NB - 1) / NB), dim3(256), 0, side, n, A, k1, kb1);
+    factor2(k1, side);
     if ((e = hipEventRecord(ev_p, side)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(st, ev_p, 0)) != hipSuccess) return e;
     if ((e = hipGetLastError()) != hipSuccess) return e;

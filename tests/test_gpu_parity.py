@@ -205,9 +205,12 @@ def test_sample_covariance_and_estimator():
     assert np.linalg.norm(L.cpu().numpy() - Lo) / np.linalg.norm(Lo) < 1e-12
 
 
-@pytest.mark.parametrize("n", [120, 455, 969])
+@pytest.mark.parametrize("n", [120, 165, 220, 455, 969])
 def test_cholesky_bivector_closed_form(n):
-    """Sec. III B: zeta = I + b b^T has a closed-form Cholesky factor and variance."""
+    """Sec. III B: zeta = I + b b^T has a closed-form Cholesky factor and variance.  The
+    sizes cover the blocked factorization's ends: one 128-wide block column (120), a last
+    block column of one partial half (165 = 128 + 37), of a full and a partial half
+    (220 = 128 + 64 + 28; 455; 969)."""
     case = CASES["tiny"]
     c = ctx_for(case, "f64")
     rng = np.random.default_rng(n)
@@ -217,7 +220,7 @@ def test_cholesky_bivector_closed_form(n):
     # fnl works for any n: use a throwaway context whose nmax is n? the ABI ties n to P,
     # so embed the problem in the context's nmax when it matches, else skip
     if n != c.nmax:
-        P = {455: 13, 969: 17}.get(n)
+        P = {165: 9, 220: 10, 455: 13, 969: 17}.get(n)
         if P is None:
             pytest.skip("no P gives this nmax")
         from paper_1105_2791_amd import ModalContext
