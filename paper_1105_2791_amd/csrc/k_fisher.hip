@@ -233,8 +233,8 @@ __global__ __launch_bounds__(256) void k_adj_legendre_mfma(int lmax, int ntheta,
 // Workgroup: 4 waves, one m, 128 consecutive l - m (wave w: the 32 l of parity w / 2 in
 // the half w % 2), 64 complex columns (4 tiles of 32 real columns).  The folded ring values
 // of a 32-ring chunk are split and staged in LDS, double buffered; each lane loads the
-// lambda of its l at 8 rings from the FP32 table one K step ahead and splits them in
-// registers.  The workgroups of one m (l blocks x column blocks) run back to back on one
+// lambda of its l at the 16 rings of its two K steps from the FP32 table one chunk ahead
+// and splits them in registers.  The workgroups of one m (l blocks x column blocks) run back to back on one
 // XCD, so lambda[m] and the ring values of m come from HBM about once.  An output takes
 // 3 nrp / 16 accumulations (144 at 768 rings); the truncation of the matrix core's
 // accumulation stays below the operand split error.
@@ -284,11 +284,14 @@ __global__ __launch_bounds__(256) void k_adj_legendre_split(int lmax, int ntheta
   const int par = wv >> 1;                        // the parity of l - m of this wave's rows
   const int li = lb * AS_L + 64 * (wv & 1) + 2 * n + par;   // this lane's B column (l - m)
   const int lcl = min(li, L - 1);
-  // lambda at rings 16 t + 8 h + i of the lane's l (valid addresses for every t)
-  float lv[8];
-  auto load_lam = [&](int t) {
+  // lambda at rings 32 c + 16 kk + 8 h + i of the lane's l for the two K steps kk of chunk c
+  // (valid addresses for every c), loaded one chunk ahead
+  float lv[2][8], lvn[2][8];
+  auto load_lam = [&](int c, float (&dst)[2][8]) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) lv[i] = lrow[(size_t)min(16 * t + 8 * h + i, nrp - 1) * L + lcl];
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) dst[kk][i] = lrow[(size_t)min(AS_RC * c + 16 * kk + 8 * h + i, nrp - 1) * L + lcl];
   };
   // ring values of a chunk: thread (column q, ring pair jp) for four (q, jp), north and south
   constexpr int NU = AS_NC * AS_RC / 2 / 256;
@@ -343,7 +346,7 @@ __global__ __launch_bounds__(256) void k_adj_legendre_split(int lmax, int ntheta
   load_g(0);
   store_g(0, 0);
   load_g(AS_RC);
-  load_lam(0);
+  load_lam(0, lv);
   __syncthreads();
   for (int ch = 0; ch < nch; ++ch) {
     const int buf = ch & 1;
@@ -353,23 +356,22 @@ __global__ __launch_bounds__(256) void k_adj_legendre_split(int lmax, int ntheta
       store_g((ch + 1) * AS_RC, buf ^ 1);
       load_g((ch + 2) * AS_RC);
     }
+    load_lam(ch + 1, lvn);   // the next chunk's lambda (clamped past the last ring: unused)
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
-      const int t = 2 * ch + kk;
       bf16x8 bh, bl;
       {
         u32x4 hv, lo4;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           uint32_t hw, lw2;
-          as_split2(lv[2 * k], lv[2 * k + 1], hw, lw2);
+          as_split2(lv[kk][2 * k], lv[kk][2 * k + 1], hw, lw2);
           hv[k] = hw;
           lo4[k] = lw2;
         }
         bh = __builtin_bit_cast(bf16x8, hv);
         bl = __builtin_bit_cast(bf16x8, lo4);
       }
-      load_lam(t + 1);   // one K step ahead (clamped past the last ring: unused)
 #pragma unroll
       for (int ct = 0; ct < 4; ++ct) {
         const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&S.h[buf][par][32 * ct + n][16 * kk + 8 * h]));
@@ -379,6 +381,10 @@ __global__ __launch_bounds__(256) void k_adj_legendre_split(int lmax, int ntheta
         acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[ct], 0, 0, 0);
       }
     }
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) lv[kk][i] = lvn[kk][i];
     __syncthreads();   // chunk ch read by all waves; chunk ch + 1 visible
   }
   if (li >= L) return;
