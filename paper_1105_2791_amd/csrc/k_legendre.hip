@@ -181,25 +181,37 @@ __global__ __launch_bounds__(64) void k_legendre(int lmax, int ntheta, int nrp, 
 }
 
 // ---------------------------------------------------------------------------
-// lambda table for the adjoint: lam[m][j][l - m] (north rings), T precision
+// lambda table for the adjoint: lam[m][j][l - m] (north rings), T precision.  A workgroup
+// runs the recurrences of 64 rings (one per thread) 64 steps at a time into LDS and writes
+// each ring's run of 64 l back as one contiguous row segment, so the stores are coalesced
+// (a thread writing its own ring's row would touch 64 rows per store instruction).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_lambda_table(int lmax, int nrp, const double* __restrict__ x, const double* __restrict__ rec,
-                               const double* __restrict__ seed, const int* __restrict__ lstart,
-                               T* __restrict__ lam) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(64) void k_lambda_table(int lmax, int nrp, const double* __restrict__ x,
+                                                     const double* __restrict__ rec, const double* __restrict__ seed,
+                                                     const int* __restrict__ lstart, T* __restrict__ lam) {
+  __shared__ T buf[64][65];
+  const int t = threadIdx.x, j0 = blockIdx.x * 64;
+  const int jc = min(j0 + t, nrp - 1);   // rings past nrp run a valid recurrence, not stored
   const int m = blockIdx.y;
-  if (j >= nrp) return;
+  const int L = lmax + 1 - m;
   Rec r;
   r.l1 = r.l2 = 0.0;
-  r.ls = lstart[(size_t)m * nrp + j];
-  r.s0 = seed[2 * ((size_t)m * nrp + j)];
-  r.s1 = seed[2 * ((size_t)m * nrp + j) + 1];
-  const double xx = x[j];
+  r.ls = lstart[(size_t)m * nrp + jc];
+  r.s0 = seed[2 * ((size_t)m * nrp + jc)];
+  r.s1 = seed[2 * ((size_t)m * nrp + jc) + 1];
+  const double xx = x[jc];
   const size_t off = (size_t)m * (2 * lmax + 3 - m) / 2;
-  // table base for this m: rows j of length L_m = lmax + 1 - m
-  T* out = lam + off * nrp + (size_t)j * (lmax + 1 - m);
-  for (int l = m; l <= lmax; ++l) out[l - m] = T(r.step(l, xx, rec + 2 * (off + (l - m))));
+  T* out = lam + off * nrp;   // rows j of length L
+  const int nr = min(64, nrp - j0);
+  for (int l0 = 0; l0 < L; l0 += 64) {
+    const int nl = min(64, L - l0);
+    for (int i = 0; i < nl; ++i) buf[t][i] = T(r.step(m + l0 + i, xx, rec + 2 * (off + l0 + i)));
+    __syncthreads();
+    if (t < nl)
+      for (int rr = 0; rr < nr; ++rr) out[(size_t)(j0 + rr) * L + l0 + t] = buf[rr][t];
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
