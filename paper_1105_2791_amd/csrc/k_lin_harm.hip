@@ -35,8 +35,8 @@ __global__ __launch_bounds__(256) void k_weight_planes(int npix, int nk, const T
 }
 
 // X[s][pair][l] = sum_{m <= l} (Re a Re Z + Im a Im Z) at index (l, m), FP64 sums.
-// A workgroup covers LT consecutive l (one per lane) x PT pairs x ST maps, so that every
-// Z and a_lm element it loads feeds PT or ST products; its MW waves take the m of the
+// A workgroup covers LT consecutive l (one per lane) x PT pairs x ST maps (grid x: the pair
+// group, y: the l tile), so that every Z and a_lm element it loads feeds PT or ST products; its MW waves take the m of the
 // sum in turn (m = w, w + MW, ...) and their partial sums are added through LDS.  The
 // lanes of a wave read consecutive l of one m row of the m-major packing: coalesced.
 constexpr int PT = 8;
@@ -53,10 +53,10 @@ __global__ __launch_bounds__(LT * MW) void k_lin_x(int lmax, int nalm, int npair
   using T2 = typename vec2<T>::type;
   __shared__ double red[MW - 1][RED][LT];
   const int lane = threadIdx.x % LT, w = threadIdx.x / LT;
-  const int l = blockIdx.x * LT + lane;
+  const int l = blockIdx.y * LT + lane;
   const int lc = min(l, lmax);
-  const int mend = min((int)blockIdx.x * LT + LT - 1, lmax);   // largest l of the workgroup
-  const int p0 = blockIdx.y * PT, s0 = blockIdx.z * ST;
+  const int mend = min((int)blockIdx.y * LT + LT - 1, lmax);   // largest l of the workgroup
+  const int p0 = blockIdx.x * PT, s0 = blockIdx.z * ST;
   double acc[PT][ST];
 #pragma unroll
   for (int k = 0; k < PT; ++k)
@@ -256,7 +256,8 @@ hipError_t launch_weight_planes(const modal_ctx* c, const void* V, int nk, void*
 hipError_t launch_lin_harmonic(const modal_ctx* c, const void* Z, const void* alm, int S, double* X, double* L,
                                hipStream_t st) {
   if (c->P > 64) return hipErrorInvalidValue;
-  dim3 gx((c->lmax + LT) / LT, (c->npairs + PT - 1) / PT, (S + ST - 1) / ST);
+  // pair groups fastest: the workgroups running together share one l tile of a_lm in L2
+  dim3 gx((c->npairs + PT - 1) / PT, (c->lmax + LT) / LT, (S + ST - 1) / ST);
   if (is_f64(c))
     hipLaunchKernelGGL(k_lin_x<double>, gx, dim3(LT * MW), 0, st, c->lmax, c->nalm, c->npairs, S, (const double2*)Z,
                        (const double2*)alm, X);
