@@ -403,9 +403,13 @@ __device__ inline void dft_plus(float2* x) {
 // PTS: the most points a lane holds in any pass of the plan (register budget)
 // OUT: the last pass writes its (natural-order) output to the global row out instead
 // of back to b (nothing when out is null: a padding ring)
-template <int R, int PTS, bool OUT = false>
-__device__ inline void rg_pass(float2* b, int K, int Ns, int lane, const float2* twp, float2* out = nullptr) {
+// KC, NSC: the ring length and the pass's stride when known at compile time (0: from
+// the arguments), so that the index arithmetic of a specialised plan folds to constants
+template <int R, int PTS, bool OUT = false, int KC = 0, int NSC = 0>
+__device__ inline void rg_pass(float2* b, int K_, int Ns_, int lane, const float2* twp, float2* out = nullptr) {
   constexpr int NB = (PTS + R - 1) / R;
+  const int K = KC ? KC : K_;
+  const int Ns = NSC ? NSC : Ns_;
   const int KR = K / R;
   float2 v[NB][R];
 #pragma unroll
@@ -438,13 +442,12 @@ __device__ inline void rg_pass(float2* b, int K, int Ns, int lane, const float2*
   }
 }
 
-template <int PTS>
-__global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int lmax, int ntheta, int nseq,
-                                                              const float2* __restrict__ F, float* __restrict__ maps,
-                                                              const float2* __restrict__ twg,
-                                                              const float2* __restrict__ twpg) {
+template <int PTS, int KC>
+__device__ __forceinline__ void c2r_rg_body(FftPlan plan, int lmax, int ntheta, int nseq,
+                                            const float2* __restrict__ F, float* __restrict__ maps,
+                                            const float2* __restrict__ twg, const float2* __restrict__ twpg) {
   extern __shared__ __attribute__((aligned(16))) float2 rbuf[];
-  const int K = plan.K;
+  const int K = KC ? KC : plan.K;   // KC: the plan 24 x 8 x 8 of K = 1536, compiled in
   const int KP = padr(K) + 1;
   float2* tw = rbuf + RG_RINGS * KP;   // e^{2 pi i t / N}, t <= K / 2, shared by the workgroup's rings
   float2* twp = tw + K / 2 + 1;          // the passes' twiddle tables, K - 1 entries in all
@@ -508,27 +511,50 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int 
     // M_{2n} = Re z_n, M_{2n+1} = Im z_n
     const int j = rb * 8 + RG_RINGS * half + w;
     float2* dst = (j < ntheta) ? reinterpret_cast<float2*>(maps + ((size_t)seq * ntheta + j) * plan.N) : nullptr;
-    int Ns = 1;
-    const float2* tf = twp;
-    // (a last pass of radix 8, the common case, stores straight to the row; other plans
-    // finish in LDS and copy the row out)
-    const bool direct = plan.radix[plan.nf - 1] == 8;
-    for (int f = 0; f < plan.nf; ++f) {
-      const int R = plan.radix[f];
-      if (direct && f == plan.nf - 1) rg_pass<8, PTS, true>(bw, K, Ns, lane, tf, dst);
-      else if (R == 24) rg_pass<24, PTS>(bw, K, Ns, lane, tf);
-      else if (R == 8) rg_pass<8, PTS>(bw, K, Ns, lane, tf);
-      else if (R == 4) rg_pass<4, PTS>(bw, K, Ns, lane, tf);
-      else if (R == 2) rg_pass<2, PTS>(bw, K, Ns, lane, tf);
-      else if (R == 3) rg_pass<3, PTS>(bw, K, Ns, lane, tf);
-      else rg_pass<5, PTS>(bw, K, Ns, lane, tf);
-      tf += (R - 1) * Ns;
-      Ns *= R;
-    }
-    if (!direct && dst) {
-      for (int n = lane; n < K; n += 64) dst[n] = bw[padr(n)];
+    if constexpr (KC == 1536) {
+      // passes 24, 8, 8 (strides 1, 24, 192; twiddle tables at 0, 23, 23 + 7 * 24)
+      rg_pass<24, PTS, false, KC, 1>(bw, K, 1, lane, twp);
+      rg_pass<8, PTS, false, KC, 24>(bw, K, 24, lane, twp + 23);
+      rg_pass<8, PTS, true, KC, 192>(bw, K, 192, lane, twp + 23 + 7 * 24, dst);
+    } else {
+      int Ns = 1;
+      const float2* tf = twp;
+      // (a last pass of radix 8, the common case, stores straight to the row; other plans
+      // finish in LDS and copy the row out)
+      const bool direct = plan.radix[plan.nf - 1] == 8;
+      for (int f = 0; f < plan.nf; ++f) {
+        const int R = plan.radix[f];
+        if (direct && f == plan.nf - 1) rg_pass<8, PTS, true>(bw, K, Ns, lane, tf, dst);
+        else if (R == 24) rg_pass<24, PTS>(bw, K, Ns, lane, tf);
+        else if (R == 8) rg_pass<8, PTS>(bw, K, Ns, lane, tf);
+        else if (R == 4) rg_pass<4, PTS>(bw, K, Ns, lane, tf);
+        else if (R == 2) rg_pass<2, PTS>(bw, K, Ns, lane, tf);
+        else if (R == 3) rg_pass<3, PTS>(bw, K, Ns, lane, tf);
+        else rg_pass<5, PTS>(bw, K, Ns, lane, tf);
+        tf += (R - 1) * Ns;
+        Ns *= R;
+      }
+      if (!direct && dst) {
+        for (int n = lane; n < K; n += 64) dst[n] = bw[padr(n)];
+      }
     }
   }
+}
+
+template <int PTS>
+__global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int lmax, int ntheta, int nseq,
+                                                              const float2* __restrict__ F, float* __restrict__ maps,
+                                                              const float2* __restrict__ twg,
+                                                              const float2* __restrict__ twpg) {
+  c2r_rg_body<PTS, 0>(plan, lmax, ntheta, nseq, F, maps, twg, twpg);
+}
+
+// the plan 24 x 8 x 8 of K = 1536 compiled in (the constant index arithmetic lets the
+// compiler keep more in registers: held to two waves per SIMD)
+__global__ __launch_bounds__(64 * RG_RINGS) __attribute__((amdgpu_waves_per_eu(2))) void k_fft_c2r_rg_k1536(
+    FftPlan plan, int lmax, int ntheta, int nseq, const float2* __restrict__ F, float* __restrict__ maps,
+    const float2* __restrict__ twg, const float2* __restrict__ twpg) {
+  c2r_rg_body<24, 1536>(plan, lmax, ntheta, nseq, F, maps, twg, twpg);
 }
 
 // r2c, register passes (the adjoint of k_fft_c2r_rg): same persistent ring-group order,
@@ -537,13 +563,13 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg(FftPlan plan, int 
 // workgroup barrier every thread forms Gh_m of one (m, ring) of the four rings from
 // Z_m and Z_{K-m} (see the top of the file), and consecutive threads write the four
 // rings of one m, the contiguous run of the [seq][m][ring] layout.
-template <int PTS>
+template <int PTS, int KC = 0>
 __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_r2c_rg(FftPlan plan, int lmax, int ntheta, int nseq,
                                                               const float* __restrict__ G, float2* __restrict__ Gh,
                                                               const float2* __restrict__ twg,
                                                               const float2* __restrict__ twpg) {
   extern __shared__ __attribute__((aligned(16))) float2 rbuf[];
-  const int K = plan.K;
+  const int K = KC ? KC : plan.K;   // KC: the plan 24 x 8 x 8 of K = 1536, compiled in
   const int KP = padr(K) + 1;
   float2* tw = rbuf + RG_RINGS * KP;
   float2* twp = tw + K / 2 + 1;
@@ -588,18 +614,24 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_r2c_rg(FftPlan plan, int 
           bw[padr(n)] = make_float2(v.x, -v.y);
         }
       }
-      int Ns = 1;
-      const float2* tf = twp;
-      for (int f = 0; f < plan.nf; ++f) {
-        const int R = plan.radix[f];
-        if (R == 24) rg_pass<24, PTS>(bw, K, Ns, lane, tf);
-        else if (R == 8) rg_pass<8, PTS>(bw, K, Ns, lane, tf);
-        else if (R == 4) rg_pass<4, PTS>(bw, K, Ns, lane, tf);
-        else if (R == 2) rg_pass<2, PTS>(bw, K, Ns, lane, tf);
-        else if (R == 3) rg_pass<3, PTS>(bw, K, Ns, lane, tf);
-        else rg_pass<5, PTS>(bw, K, Ns, lane, tf);
-        tf += (R - 1) * Ns;
-        Ns *= R;
+      if constexpr (KC == 1536) {
+        rg_pass<24, PTS, false, KC, 1>(bw, K, 1, lane, twp);
+        rg_pass<8, PTS, false, KC, 24>(bw, K, 24, lane, twp + 23);
+        rg_pass<8, PTS, false, KC, 192>(bw, K, 192, lane, twp + 23 + 7 * 24);
+      } else {
+        int Ns = 1;
+        const float2* tf = twp;
+        for (int f = 0; f < plan.nf; ++f) {
+          const int R = plan.radix[f];
+          if (R == 24) rg_pass<24, PTS>(bw, K, Ns, lane, tf);
+          else if (R == 8) rg_pass<8, PTS>(bw, K, Ns, lane, tf);
+          else if (R == 4) rg_pass<4, PTS>(bw, K, Ns, lane, tf);
+          else if (R == 2) rg_pass<2, PTS>(bw, K, Ns, lane, tf);
+          else if (R == 3) rg_pass<3, PTS>(bw, K, Ns, lane, tf);
+          else rg_pass<5, PTS>(bw, K, Ns, lane, tf);
+          tf += (R - 1) * Ns;
+          Ns *= R;
+        }
       }
     }
     lds_barrier();   // the four rings' spectra are in LDS
@@ -699,8 +731,10 @@ hipError_t fft_rg_set_lds(size_t bytes) {
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_fft_c2r_rg<24>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_fft_c2r_rg<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_fft_c2r_rg<48>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_fft_c2r_rg_k1536, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   const void* r2c[] = {(const void*)k_fft_r2c_rg<16>, (const void*)k_fft_r2c_rg<24>, (const void*)k_fft_r2c_rg<32>,
-                       (const void*)k_fft_r2c_rg<48>};
+                       (const void*)k_fft_r2c_rg<48>, (const void*)k_fft_r2c_rg<24, 1536>};
   for (const void* f : r2c)
     if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   return e;
@@ -711,6 +745,11 @@ bool plan_has_radix(const FftPlan& p, int r) {
   for (int f = 0; f < p.nf; ++f)
     if (p.radix[f] == r) return true;
   return false;
+}
+
+// the register plan compiled in (K = 1536: the rings of nphi 3072, the l_max 1000 grid)
+bool plan_is_k1536(const FftPlan& p) {
+  return p.K == 1536 && p.nf == 3 && p.radix[0] == 24 && p.radix[1] == 8 && p.radix[2] == 8;
 }
 }  // namespace
 
@@ -726,7 +765,11 @@ hipError_t launch_fft_c2r(const modal_ctx* c, const void* F, int S, void* maps, 
   hipLaunchKernelGGL(k_fft_c2r_rg<PT>, dim3(blocks), dim3(64 * RG_RINGS), fft_rg_lds(c), st, c->fft_rg_plan,        \
                      c->lmax, c->ntheta, nseq, (const float2*)F, (float*)maps, (const float2*)c->t.tw32,        \
                      (const float2*)c->t.twp32)
-    if (pts <= 16) LAUNCH(16);
+    if (plan_is_k1536(c->fft_rg_plan) && pts == 24)
+      hipLaunchKernelGGL(k_fft_c2r_rg_k1536, dim3(blocks), dim3(64 * RG_RINGS), fft_rg_lds(c), st,
+                         c->fft_rg_plan, c->lmax, c->ntheta, nseq, (const float2*)F, (float*)maps,
+                         (const float2*)c->t.tw32, (const float2*)c->t.twp32);
+    else if (pts <= 16) LAUNCH(16);
     else if (pts <= 24) LAUNCH(24);
     else if (pts <= 32) LAUNCH(32);
     else LAUNCH(48);
@@ -763,7 +806,11 @@ hipError_t launch_fft_r2c_rows(const modal_ctx* c, const void* G, size_t nseq, v
   hipLaunchKernelGGL(k_fft_r2c_rg<PT>, dim3(blocks), dim3(64 * RG_RINGS), fft_rg_lds(c), st, c->fft_rg_plan,        \
                      c->lmax, c->ntheta, (int)nseq, (const float*)G, (float2*)Gh, (const float2*)c->t.tw32,       \
                      (const float2*)c->t.twp32)
-    if (pts <= 16) LAUNCH(16);
+    if (plan_is_k1536(c->fft_rg_plan) && pts == 24)
+      hipLaunchKernelGGL((k_fft_r2c_rg<24, 1536>), dim3(blocks), dim3(64 * RG_RINGS), fft_rg_lds(c), st,
+                         c->fft_rg_plan, c->lmax, c->ntheta, (int)nseq, (const float*)G, (float2*)Gh,
+                         (const float2*)c->t.tw32, (const float2*)c->t.twp32);
+    else if (pts <= 16) LAUNCH(16);
     else if (pts <= 24) LAUNCH(24);
     else if (pts <= 32) LAUNCH(32);
     else LAUNCH(48);
