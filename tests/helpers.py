@@ -74,4 +74,6 @@ CASES = {
     # the split adjoint takes, P = 48 (168 eight-pair groups), on the l_max = 32 grid
     "wide": Case("wide", 32, 48, 96, 40, 2, "wmap", 51),
     "wide48": Case("wide48", 32, 48, 96, 48, 2, "wmap", 61),
+    # past the split adjoint's 48 modes: the vector pair contraction takes over
+    "wide50": Case("wide50", 32, 48, 96, 50, 2, "wmap", 71),
 }

@@ -161,7 +161,8 @@ def test_vjp_matches_oracle_gradient(name, prec):
 
 
 @pytest.mark.parametrize("name,prec", [("wide", "bf16x3"), ("wide", "f32"), ("wide", "f16x3"), ("wide", "f64"),
-                                       ("wide48", "bf16x3"), ("wide48", "f32")])
+                                       ("wide48", "bf16x3"), ("wide48", "f32"), ("wide50", "bf16x3"),
+                                       ("wide50", "f32")])
 def test_vjp_wide_modes(name, prec):
     """The adjoint at 33..48 modes: two 32-row mode tiles of the split contraction."""
     case = CASES[name]
@@ -185,6 +186,29 @@ def test_vjp_wide_modes(name, prec):
         err0 = np.linalg.norm(gn[i] - ref0) / np.linalg.norm(ref0)
         log_err(f"vjp {name} {prec} no state sim{i}", err0)
         assert err0 < MAP_TOL[prec], err0
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "f64"])
+def test_vjp_more_skies_than_a_block(prec):
+    """Ten skies in one call: the harmonic pair-mean part takes eight maps per workgroup,
+    so the last two run in a second block; every sky against the oracle's gradient."""
+    case = CASES["tiny"]
+    c = ctx_for(case, prec)
+    o = oracle_for(case)
+    print(f"[case] vjp 10 skies tiny {prec}", flush=True)
+    st = c.linear_state()
+    c.linear_reset(st)
+    c.linear_accumulate(st, o["mc"])
+    c.linear_finalize(st)
+    alms = case.alms(100, 10)
+    rng = np.random.default_rng(29)
+    cot = rng.standard_normal((10, mi.ntriples(case.P)))
+    g = c.beta_vjp(alms, cot, state=st).cpu().numpy()
+    for i in range(10):
+        ref = om.vjp(alms[i], case.cl, case.q, case.grid, o["V"], cot[i])[0]
+        err = np.linalg.norm(g[i] - ref) / np.linalg.norm(ref)
+        log_err(f"vjp 10 skies tiny {prec} sim{i}", err)
+        assert err < MAP_TOL[prec], (i, err)
 
 
 def test_sample_covariance_and_estimator():
