@@ -203,14 +203,14 @@ hipError_t launch_copy_lower(int n, const double* src, double* dst, hipStream_t 
 // in-place Cholesky of the lower triangle of A (row-major, n x n); flag[0] = 1 + first bad pivot
 // blocked right-looking Cholesky with look-ahead: the next diagonal block and panel run on
 // side while the rest of the trailing update runs on st (ev_a, ev_p order them); st is
-// joined with side when it returns
+// joined with side when it returns.  With nrhs > 0 the solves L Y = B of nrhs right-hand
+// sides stored as rows of B [nrhs][n] run too, each block's step right after the block is
+// factored (the inverted diagonal block and its panel); Y gets the solution, B is
+// overwritten below the blocks
 hipError_t launch_cholesky_lookahead(int n, double* A, int* flag, hipStream_t st, hipStream_t side, hipEvent_t ev_a,
-                                     hipEvent_t ev_p);
+                                     hipEvent_t ev_p, int nrhs = 0, double* B = nullptr, double* Y = nullptr);
 // solve L Y = B in place for nrhs right-hand sides stored as rows of B [nrhs][n]
 hipError_t launch_trsm_rows(int n, const double* L, int nrhs, double* B, hipStream_t st);
-// the same solve after launch_cholesky (which leaves the inverted diagonal blocks in the
-// upper triangles); the solution goes to Y, B is overwritten below the blocks
-hipError_t launch_trsm_rows_inv(int n, const double* L, int nrhs, double* B, double* Y, hipStream_t st);
 hipError_t launch_estimator(int n, const double* y, const double* Z, int S, double* out, hipStream_t st);
 
 // low-rank covariance I + sum b b^T: noise vectors, Woodbury estimator, closed-form rotation

@@ -959,8 +959,8 @@ modal_status estimate(modal_ctx* c, int op, int n, double factor, const double* 
       HIPTRY(hipEventCreateWithFlags(&c->ev_a, hipEventDisableTiming));
       HIPTRY(hipEventCreateWithFlags(&c->ev_p, hipEventDisableTiming));
     }
-    HIPTRY(launch_cholesky_lookahead(n, L, flag, st, c->side, c->ev_a, c->ev_p));
-    HIPTRY(launch_trsm_rows_inv(n, L, S + 1, rows, sol, st));
+    // the factorization with the solves of the S + 1 right-hand sides folded in
+    HIPTRY(launch_cholesky_lookahead(n, L, flag, st, c->side, c->ev_a, c->ev_p, S + 1, rows, sol));
     HIPTRY(launch_estimator(n, sol, nullptr, S, dots, st));
   }
   if (L_dev) HIPTRY(launch_copy_lower(n, L, L_dev, st));

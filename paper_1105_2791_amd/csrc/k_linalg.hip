@@ -457,7 +457,7 @@ hipError_t launch_copy_lower(int n, const double* src, double* dst, hipStream_t 
 }
 
 hipError_t launch_cholesky_lookahead(int n, double* A, int* flag, hipStream_t st, hipStream_t side, hipEvent_t ev_a,
-                                     hipEvent_t ev_p) {
+                                     hipEvent_t ev_p, int nrhs, double* B, double* Y) {
   constexpr int T = 64;
   // A[i][j] -= sum_c A[i][k0 + c] A[j][k0 + c], i >= j >= r0, tile columns [bj0, ...) of the
   // (n - r0)-square trailing grid; nbx tile columns
@@ -482,9 +482,21 @@ hipError_t launch_cholesky_lookahead(int n, double* A, int* flag, hipStream_t st
         hipLaunchKernelGGL(k_panel_mfma, dim3((n - k2 - kb2 + NB - 1) / NB), dim3(256), 0, s, n, A, k2, kb2);
     }
   };
+  // The solve steps of a factored block column (Y_k = W_kk B_k, and the rows below updated
+  // with its panel): they need only that block column, so they run on the stream that
+  // factored it, after the event that releases the main stream, and overlap the trailing
+  // updates instead of following the whole factorization.
+  auto solve2 = [&](int k, hipStream_t s) {
+    for (int kk = k; kk < k + 2 * NB && kk < n; kk += NB) {
+      const int kb = n - kk < NB ? n - kk : NB, rem = n - kk - kb;
+      hipLaunchKernelGGL(k_trsv_inv_step, dim3(1 + (rem + 255) / 256, (nrhs + TRS_R - 1) / TRS_R), dim3(256), 0, s, n,
+                         A, kk, kb, nrhs, B, Y);
+    }
+  };
   // The trailing updates take both halves of a factored block column at once (K = 2 NB), so
   // each trailing tile is read and written once per 2 NB columns instead of per NB.
   factor2(0, st);
+  if (nrhs > 0) solve2(0, st);
   for (int k0 = 0; k0 + 2 * NB < n; k0 += 2 * NB) {
     const int k1 = k0 + 2 * NB;   // the next block column (both halves of [k0, k1) are NB wide)
     const int w1 = n - k1 < 2 * NB ? n - k1 : 2 * NB;
@@ -498,7 +510,13 @@ hipError_t launch_cholesky_lookahead(int n, double* A, int* flag, hipStream_t st
     factor2(k1, side);
     if ((e = hipEventRecord(ev_p, side)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(st, ev_p, 0)) != hipSuccess) return e;
+    if (nrhs > 0) solve2(k1, side);   // in order on the side stream, after ev_p
     if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (nrhs > 0 && n > 2 * NB) {   // the last solve steps ran on the side stream
+    hipError_t e = hipEventRecord(ev_p, side);
+    if (e != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(st, ev_p, 0)) != hipSuccess) return e;
   }
   return hipGetLastError();
 }
@@ -511,18 +529,6 @@ hipError_t launch_trsm_rows(int n, const double* L, int nrhs, double* B, hipStre
     if (rem > 0)
       hipLaunchKernelGGL(k_trsv_update, dim3((rem + 255) / 256, (nrhs + 63) / 64), dim3(256), 0, st, n, L, k0, kb,
                          nrhs, B);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
-hipError_t launch_trsm_rows_inv(int n, const double* L, int nrhs, double* B, double* Y, hipStream_t st) {
-  for (int k0 = 0; k0 < n; k0 += NB) {
-    const int kb = n - k0 < NB ? n - k0 : NB;
-    const int rem = n - k0 - kb;
-    hipLaunchKernelGGL(k_trsv_inv_step, dim3(1 + (rem + 255) / 256, (nrhs + TRS_R - 1) / TRS_R), dim3(256), 0, st, n,
-                       L, k0, kb, nrhs, B, Y);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
