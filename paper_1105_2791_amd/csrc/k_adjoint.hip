@@ -222,6 +222,7 @@ __global__ __launch_bounds__(256) void k_pair_adjoint_mfma(int P, int npairs, in
 // MFMAs of step t (software pipeline).  The A operands of SG_KC steps are staged in LDS, double
 // buffered; the MFMAs of SG_CH staged chunks accumulate from zero into a chain that is then
 // added to the running FP32 sums (the matrix core truncates the addend of a long accumulation).
+// A workgroup is 4 waves and 256 pixels of one sky (70 KB of LDS: two workgroups per CU).
 typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
 typedef __attribute__((__vector_size__(2 * sizeof(_Float16)))) _Float16 f16x2;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
@@ -339,8 +340,7 @@ __global__ __launch_bounds__(64 * SG_NW) void k_pair_adjoint_split(int P, int np
   const int c = lane & 31, h = lane >> 5;
   const float* Ms = maps + (size_t)s * P * npix;
   // the scaled maps as fp16 pairs: thread (xx = tid, modes 2i, 2i + 1), coalesced along pixels.
-  // All loads are issued before the first is used (one round trip, not 24: the workgroup
-  // holds the CU alone, so nothing else hides the staging).
+  // All loads are issued before the first is used: one round trip instead of 24.
   {
     constexpr int NS = SG_PP / 2;
     const int xx = tid;

@@ -119,8 +119,8 @@ __global__ __launch_bounds__(64) void k_adj_legendre_cols(int lmax, int ntheta, 
 // round-to-nearest add.  The matrix core's FP32 accumulation raised the FP32-context
 // linear term's error against the oracle from 2.7e-6 to 6.5e-6 of rms (its bound is
 // 1e-5; a running FP64 sum did not lower it and cost 25 %), so FP32 contexts keep the
-// FP64 vector sums above; the split contexts, whose operands carry 2^-16 (bf16x3) or
-// 2^-22 (f16x3), take this kernel.
+// FP64 vector sums above; f16x3 contexts, whose operands carry 2^-22, take this kernel, and
+// bf16x3 contexts the split-operand kernel below.
 constexpr int AL_RC = 32;   // rings per staged chunk
 constexpr int AL_NC = 64;   // complex columns per workgroup
 
@@ -234,8 +234,8 @@ __global__ __launch_bounds__(256) void k_adj_legendre_mfma(int lmax, int ntheta,
 // the half w % 2), 64 complex columns (4 tiles of 32 real columns).  The folded ring values
 // of a 32-ring chunk are split and staged in LDS, double buffered; each lane loads the
 // lambda of its l at the 16 rings of its two K steps from the FP32 table one chunk ahead
-// and splits them in registers.  The workgroups of one m (l blocks x column blocks) run back to back on one
-// XCD, so lambda[m] and the ring values of m come from HBM about once.  An output takes
+// and splits them in registers.  The workgroups of one m (l blocks x column blocks) run
+// back to back on one XCD, so lambda[m] and the ring values of m come from HBM about once.  An output takes
 // 3 nrp / 16 accumulations (144 at 768 rings); the truncation of the matrix core's
 // accumulation stays below the operand split error.
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
