@@ -39,8 +39,8 @@ __device__ inline T2 cmul(T2 a, T2 b) {
 // w = exp(sign 2 pi i / R), whose powers are held in registers (the indices j q mod R are
 // compile-time).  R^2 / 2 complex multiply-adds per butterfly, no LDS re-reads.
 template <typename T2, int SIGN, int R>
-__device__ inline void prime_stage(const T2* __restrict__ in, T2* __restrict__ out, int K, int Ns,
-                                   const T2* __restrict__ tw) {
+__device__ inline void prime_stage(const T2* __restrict__ in0, T2* __restrict__ out0, int K, int Ns,
+                                   const T2* __restrict__ tw, int nring) {
   constexpr int H = (R - 1) / 2;
   const int KR = K / R;
   const int step = K / (Ns * R);
@@ -50,7 +50,12 @@ __device__ inline void prime_stage(const T2* __restrict__ in, T2* __restrict__ o
     wr[m] = tw[2 * m * KR];                 // exp(2 pi i m / R) = exp(2 pi i m KR / K)
     if (SIGN < 0) wr[m].y = -wr[m].y;
   }
-  for (int b = threadIdx.x; b < KR; b += blockDim.x) {
+  // the butterflies of all nring rings are dealt to the threads together (a ring alone has
+  // K / R of them: 64 for R = 47 at K = 3008, a quarter of the workgroup)
+  for (int bb = threadIdx.x; bb < nring * KR; bb += blockDim.x) {
+    const int ring = bb / KR, b = bb - ring * KR;
+    const T2* in = in0 + (size_t)ring * K;
+    T2* out = out0 + (size_t)ring * K;
     const int k = b % Ns;
     const int obase = (b / Ns) * Ns * R + k;
     const int dt = k * step;                // < K: the stage twiddle of input r is exp(2 pi i r dt / K)
@@ -90,18 +95,21 @@ __device__ inline void prime_stage(const T2* __restrict__ in, T2* __restrict__ o
 // e^{+i}, -1 for e^{-i}.  Twiddle exp(sign 2 pi i t / K) = tw[2 t] (conjugated for sign -1).
 // PR: a large prime radix with its own compiled stage (0: none).
 template <typename T2, int SIGN, int PR>
-__device__ inline void stockham_stage(const T2* __restrict__ in, T2* __restrict__ out, int K, int Ns, int R,
-                                      const T2* __restrict__ tw) {
+__device__ inline void stockham_stage(const T2* __restrict__ in0, T2* __restrict__ out0, int K, int Ns, int R,
+                                      const T2* __restrict__ tw, int nring) {
   if constexpr (sizeof(T2) == 8) {   // float data: compiled odd-prime stages
-    if (R == 3) return prime_stage<T2, SIGN, 3>(in, out, K, Ns, tw);
-    if (R == 5) return prime_stage<T2, SIGN, 5>(in, out, K, Ns, tw);
-    if (R == 7) return prime_stage<T2, SIGN, 7>(in, out, K, Ns, tw);
+    if (R == 3) return prime_stage<T2, SIGN, 3>(in0, out0, K, Ns, tw, nring);
+    if (R == 5) return prime_stage<T2, SIGN, 5>(in0, out0, K, Ns, tw, nring);
+    if (R == 7) return prime_stage<T2, SIGN, 7>(in0, out0, K, Ns, tw, nring);
     if constexpr (PR > 7)
-      if (R == PR) return prime_stage<T2, SIGN, PR>(in, out, K, Ns, tw);
+      if (R == PR) return prime_stage<T2, SIGN, PR>(in0, out0, K, Ns, tw, nring);
   }
   const int KR = K / R;
   const int step = K / (Ns * R);  // exp(2 pi i u / (Ns R)) = exp(2 pi i u step / K)
-  for (int b = threadIdx.x; b < KR; b += blockDim.x) {
+  for (int bb = threadIdx.x; bb < nring * KR; bb += blockDim.x) {
+    const int ring = bb / KR, b = bb - ring * KR;
+    const T2* in = in0 + (size_t)ring * K;
+    T2* out = out0 + (size_t)ring * K;
     const int k = b % Ns;
     const int obase = (b / Ns) * Ns * R + k;
     if (R == 2) {
@@ -174,7 +182,7 @@ __device__ inline void stockham_stage(const T2* __restrict__ in, T2* __restrict_
 template <typename T2, int SIGN, int PR>
 __device__ inline void stockham_stage_multi(const T2* __restrict__ in, T2* __restrict__ out, int K, int R, int Ns,
                                             int Rf, const T2* __restrict__ tw) {
-  for (int r = 0; r < R; ++r) stockham_stage<T2, SIGN, PR>(in + (size_t)r * K, out + (size_t)r * K, K, Ns, Rf, tw);
+  stockham_stage<T2, SIGN, PR>(in, out, K, Ns, Rf, tw, R);
 }
 
 // c2r, generic radices: one workgroup per (sequence, block of R consecutive rings),
