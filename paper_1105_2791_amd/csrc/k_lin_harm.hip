@@ -27,11 +27,12 @@ template <> struct vec2<double> { using type = double2; };
 template <typename T>
 __global__ __launch_bounds__(256) void k_weight_planes(int npix, int nk, const T* __restrict__ V,
                                                        const T* __restrict__ w, T* __restrict__ G) {
-  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  const size_t n = (size_t)nk * npix;
-  if (i >= n) return;
-  const int x = (int)(i % (size_t)npix);
-  G[i] = T((double)V[i] * (double)w[x]);
+  // grid-stride (the launch is capped below the 2^32 work-items of one dispatch dimension)
+  const size_t n = (size_t)nk * npix, step = (size_t)gridDim.x * 256;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += step) {
+    const int x = (int)(i % (size_t)npix);
+    G[i] = T((double)V[i] * (double)w[x]);
+  }
 }
 
 // X[s][pair][l] = sum_{m <= l} (Re a Re Z + Im a Im Z) at index (l, m), FP64 sums.
@@ -243,7 +244,8 @@ __global__ __launch_bounds__(VL * VW) void k_lin_vjp(int lmax, int nalm, int npa
 
 hipError_t launch_weight_planes(const modal_ctx* c, const void* V, int nk, void* G, hipStream_t st) {
   const size_t n = (size_t)nk * c->npix;
-  const size_t blocks = (n + 255) / 256;
+  if (n == 0) return hipSuccess;
+  const size_t blocks = std::min((n + 255) / 256, (size_t)65536);
   if (is_f64(c))
     hipLaunchKernelGGL(k_weight_planes<double>, dim3(blocks), dim3(256), 0, st, c->npix, nk, (const double*)V,
                        c->t.w64, (double*)G);

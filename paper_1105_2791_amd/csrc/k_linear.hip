@@ -105,15 +105,21 @@ void lin_acc_launch(const modal_ctx* c, const void* maps, int S, void* U, hipStr
                      nblk, ntiles, c->t.pair_of, (const T*)maps, (T*)U);
 }
 
+// Element-wise kernels over whole state buffers loop with the grid's stride: one dispatch
+// holds fewer than 2^32 work-items per dimension, and the pair planes of a state exceed
+// that (4.7e9 words at l_max 1000, P 40; 6.0e9 elements at P 50).
+constexpr size_t kStrideBlocks = 65536;
+inline unsigned stride_blocks(size_t n) { return (unsigned)std::min((n + 255) / 256, kStrideBlocks); }
+
 template <typename T>
 __global__ void k_scale(size_t n, T* __restrict__ U, double s) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) U[i] = T((double)U[i] * s);
+  const size_t step = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) U[i] = T((double)U[i] * s);
 }
 
 __global__ void k_zero(size_t n, uint32_t* __restrict__ p) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
+  const size_t step = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) p[i] = 0u;
 }
 
 }  // namespace
@@ -132,10 +138,11 @@ hipError_t launch_lin_accumulate(const modal_ctx* c, const void* maps, int S, vo
 
 hipError_t launch_lin_scale(const modal_ctx* c, void* U, double s, hipStream_t st) {
   const size_t n = (size_t)c->npairs * c->npix;
+  if (n == 0) return hipSuccess;
   if (is_f64(c))
-    hipLaunchKernelGGL(k_scale<double>, dim3((n + 255) / 256), dim3(256), 0, st, n, (double*)U, s);
+    hipLaunchKernelGGL(k_scale<double>, dim3(stride_blocks(n)), dim3(256), 0, st, n, (double*)U, s);
   else
-    hipLaunchKernelGGL(k_scale<float>, dim3((n + 255) / 256), dim3(256), 0, st, n, (float*)U, s);
+    hipLaunchKernelGGL(k_scale<float>, dim3(stride_blocks(n)), dim3(256), 0, st, n, (float*)U, s);
   return hipGetLastError();
 }
 
@@ -143,7 +150,7 @@ hipError_t launch_lin_scale(const modal_ctx* c, void* U, double s, hipStream_t s
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
   const size_t n = bytes / 4;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero, dim3((n + 255) / 256), dim3(256), 0, st, n, (uint32_t*)p);
+  hipLaunchKernelGGL(k_zero, dim3(stride_blocks(n)), dim3(256), 0, st, n, (uint32_t*)p);
   return hipGetLastError();
 }
 

@@ -169,6 +169,9 @@ def test_fullsize_beta_and_linear_term_gaunt(prec):
     log_err(f"fullsize beta gaunt {prec}", eb)
     print(f"[case] fullsize linear term {prec}", flush=True)
     st = c.linear_state()
+    # NaN bytes first: RESET must clear the whole state, whose 4.7e9 words exceed what one
+    # dispatch dimension can address one work-item per word
+    st.fill_(255)
     c.linear_reset(st)
     c.linear_accumulate(st, mc)
     c.linear_finalize(st)
