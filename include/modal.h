@@ -195,7 +195,8 @@ int modal_nmax(const modal_ctx* ctx);
 int modal_npairs(const modal_ctx* ctx);
 
 /* Contraction kernel the context dispatches for the cubic reduction:
- * 0 = vector-ALU with FP64 accumulation, 1 = FP32 MFMA (16x16x4 tiles),
+ * 0 = vector-ALU with FP64 accumulation (FP64 contexts, and FP32 contexts with P > 48),
+ * 1 = FP32 MFMA (16x16x4 tiles, P <= 48),
  * 2 = split bf16/fp16 MFMA (32x32x16 tiles, modes t >= b only). */
 int modal_cubic_path(const modal_ctx* ctx);
 /* Multiply-adds the cubic contraction issues per pixel and map, counting tile

@@ -679,7 +679,7 @@ int modal_cubic_path(const modal_ctx* c) {
 double modal_cubic_issued_macs(const modal_ctx* c) {
   if (!c) return 0.0;
   if (c->prec == MODAL_BF16X3 || c->prec == MODAL_F16X3) return (double)c->t.nitems * 32 * 4 * 32 * 3;
-  if (c->prec == MODAL_F32) return (double)c->t.nblk * 8 * 48;
+  if (c->prec == MODAL_F32 && cubic_mfma_available(c)) return (double)c->t.nblk * 8 * 48;
   return (double)c->npairs * c->P;
 }
 

@@ -345,8 +345,11 @@ int cubic_mfma_nchunk_max(const modal_ctx* c) {
   return (c->npix + px - 1) / px;
 }
 
+// The FP32 tiles cover the modes t < 48 (three 16-row tiles per wave); more modes in an
+// FP32 context take the vector-ALU contraction.  The split precisions' own contraction
+// covers every P <= kMaxP (this flag also picks their chunking).
 bool cubic_mfma_available(const modal_ctx* c) {
-  return c->prec == MODAL_F32 || c->prec == MODAL_BF16X3 || c->prec == MODAL_F16X3;
+  return (c->prec == MODAL_F32 && c->P <= 48) || c->prec == MODAL_BF16X3 || c->prec == MODAL_F16X3;
 }
 
 int cubic_mfma_nchunk(const modal_ctx* c) {

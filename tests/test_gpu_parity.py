@@ -110,6 +110,49 @@ def test_beta_no_linear_term(name, prec):
     assert err < TOL[prec]
 
 
+def _nan_workspace(c, op, S):
+    """Fill the context's workspace for (op, S) with NaN bytes (0xff): a kernel that reads
+    workspace memory no kernel of the call wrote then shows as a non-finite result."""
+    from paper_1105_2791_amd import _lib as L
+    c.workspace(getattr(L, op), S).fill_(255)
+
+
+# max-relative bounds at 40..50 modes on l_max 32: the highest modes oscillate at the band
+# limit and their beta are sums with more cancellation, so map rounding shows about 1.5x
+# larger than at the other cases' 6..12 modes (measured: FP32 1.0e-5..1.6e-5 on both
+# contraction paths, bf16x3 0.7e-3..1.3e-3, f16x3 1.3e-5..2.5e-5)
+WIDE_TOL = {"f64": 1e-10, "f32": 3e-5, "bf16x3": 3e-3, "f16x3": 1e-4}
+
+
+@pytest.mark.parametrize("name,prec", [(n, p) for n in ("wide", "wide48", "wide50")
+                                       for p in ("f64", "f32", "bf16x3", "f16x3")])
+def test_beta_wide_modes(name, prec):
+    """beta and beta^hat at 40, 48 and 50 modes: the FP32 matrix-core contraction covers 48
+    modes (three 16-mode tiles), past which FP32 runs the vector-ALU contraction; the split
+    contraction tiles modes by 32.  Workspace and state start as NaN bytes."""
+    case = CASES[name]
+    c = ctx_for(case, prec)
+    o = oracle_for(case)
+    print(f"[case] beta wide {name} {prec}", flush=True)
+    _nan_workspace(c, "OP_BETA", case.S)
+    got = c.beta(o["alms"]).cpu().numpy()
+    err = max(rel_inf(got[i], o["beta"][i]) for i in range(case.S))
+    log_err(f"beta wide {name} {prec}", err)
+    assert np.all(np.isfinite(got)) and err < WIDE_TOL[prec], err
+    st = c.linear_state()
+    st.fill_(255)
+    c.linear_reset(st)
+    _nan_workspace(c, "OP_LINEAR_ACCUMULATE", len(o["mc"]))
+    c.linear_accumulate(st, o["mc"])
+    _nan_workspace(c, "OP_LINEAR_FINALIZE", 1)
+    c.linear_finalize(st)
+    _nan_workspace(c, "OP_BETA", case.S)
+    bh = c.beta(o["alms"], state=st).cpu().numpy()
+    e_bh = max(rel_inf(bh[i], o["beta"][i] - o["lin"][i]) for i in range(case.S))
+    log_err(f"beta_hat wide {name} {prec}", e_bh)
+    assert np.all(np.isfinite(bh)) and e_bh < WIDE_TOL[prec], e_bh
+
+
 @pytest.mark.parametrize("name,prec", CASE_PREC)
 def test_linear_term_and_beta_hat(name, prec):
     case = CASES[name]
