@@ -74,7 +74,7 @@ struct modal_ctx {
   int tune_fft_rings = 0;       // rings per FFT workgroup
   float wscale = 1.f;           // power of two ~ npix / 4pi (split-fp16 contraction)
   modal::FftPlan fft{};
-  bool fft_rg = false;          // register-pass c2r kernel (float maps, radices 8/4/2/3/5)
+  bool fft_rg = false;          // register-pass ring FFTs (float maps, radices 24/8/4/2/3/5; 47 x 8 x 8 at K 3008)
   modal::FftPlan fft_rg_plan{};
   modal::Tables t{};
   std::vector<double> x_host, wgl_host;

@@ -415,7 +415,7 @@ __device__ inline void dft_plus(float2* x) {
 // the arguments), so that the index arithmetic of a specialised plan folds to constants
 template <int R, int PTS, bool OUT = false, int KC = 0, int NSC = 0>
 __device__ inline void rg_pass(float2* b, int K_, int Ns_, int lane, const float2* twp, float2* out = nullptr) {
-  constexpr int NB = (PTS + R - 1) / R;
+  constexpr int NB = KC ? (KC / R + 63) / 64 : (PTS + R - 1) / R;
   const int K = KC ? KC : K_;
   const int Ns = NSC ? NSC : Ns_;
   const int KR = K / R;
@@ -433,8 +433,10 @@ __device__ inline void rg_pass(float2* b, int K_, int Ns_, int lane, const float
     const int bi = lane + 64 * i;
     if (bi < KR) {
       const int k = bi % Ns;
+      if (NSC != 1) {   // (the first pass's twiddles are all 1)
 #pragma unroll
-      for (int q = 1; q < R; ++q) v[i][q] = cmulf(v[i][q], twp[(q - 1) * Ns + k]);
+        for (int q = 1; q < R; ++q) v[i][q] = cmulf(v[i][q], twp[(q - 1) * Ns + k]);
+      }
       dft_plus<R>(v[i]);
       const int ob = (bi / Ns) * Ns * R + k;
       if (OUT) {
@@ -450,12 +452,70 @@ __device__ inline void rg_pass(float2* b, int K_, int Ns_, int lane, const float
   }
 }
 
+// cos and sin of 2 pi j / 47, j < 47, rounded to float
+__device__ constexpr float kC47[47] = {
+    1.0f, 0.991077488f, 0.964469175f, 0.920649887f, 0.860401579f, 0.784799385f, 0.695192428f,
+    0.593179745f, 0.480581755f, 0.359407773f, 0.23182015f, 0.100095692f, -0.033414977f, -0.166329355f,
+    -0.296275581f, -0.420934762f, -0.538082353f, -0.645627852f, -0.741652106f, -0.82444156f, -0.892518836f,
+    -0.944669092f, -0.979961705f, -0.997766879f, -0.997766879f, -0.979961705f, -0.944669092f, -0.892518836f,
+    -0.82444156f, -0.741652106f, -0.645627852f, -0.538082353f, -0.420934762f, -0.296275581f, -0.166329355f,
+    -0.033414977f, 0.100095692f, 0.23182015f, 0.359407773f, 0.480581755f, 0.593179745f, 0.695192428f,
+    0.784799385f, 0.860401579f, 0.920649887f, 0.964469175f, 0.991077488f};
+__device__ constexpr float kS47[47] = {
+    0.0f, 0.133286955f, 0.264195402f, 0.390389275f, 0.509616643f, 0.619749889f, 0.718823684f,
+    0.805070053f, 0.876949928f, 0.933180611f, 0.972758664f, 0.994977815f, 0.999441564f, 0.986070254f,
+    0.955102497f, 0.907090914f, 0.842892271f, 0.763652197f, 0.67078473f, 0.565947094f, 0.451010119f,
+    0.328024858f, 0.199185985f, 0.0667926337f, -0.0667926337f, -0.199185985f, -0.328024858f, -0.451010119f,
+    -0.565947094f, -0.67078473f, -0.763652197f, -0.842892271f, -0.907090914f, -0.955102497f, -0.986070254f,
+    -0.999441564f, -0.994977815f, -0.972758664f, -0.933180611f, -0.876949928f, -0.805070053f, -0.718823684f,
+    -0.619749889f, -0.509616643f, -0.390389275f, -0.264195402f, -0.133286955f};
+
+// The first pass of a ring of K = 47 x 64 points (stride 1, so no twiddles): one
+// 47-point DFT per lane, y_q = sum_r x_r e^{+2 pi i r q / 47} of x_r = b[lane + 64 r],
+// into b[47 lane + q].  The inputs r and 47 - r are paired, s_r = x_r + x_{47-r},
+// d_r = x_r - x_{47-r} (r = 1..23), so that one cosine sum and one sine sum give two
+// outputs:
+//   y_q = A_q + i B_q,  y_{47-q} = A_q - i B_q,
+//   A_q = x_0 + sum_r s_r cos(2 pi r q / 47),  B_q = sum_r d_r sin(2 pi r q / 47),
+// each pair stored as soon as it is formed.  All the wave's loads precede its stores in
+// program order, and LDS accesses of one wave complete in order, so the pass is in place.
+__device__ inline void rg_pass47_first(float2* b, int lane) {
+  float2 x[47];
+#pragma unroll
+  for (int r = 0; r < 47; ++r) x[r] = b[padr(lane + 64 * r)];
+#pragma unroll
+  for (int r = 1; r < 24; ++r) {
+    const float2 sr = cadd(x[r], x[47 - r]), dr = csub(x[r], x[47 - r]);
+    x[r] = sr;
+    x[47 - r] = dr;
+  }
+  const int ob = 47 * lane;
+  float2 y0 = x[0];
+#pragma unroll
+  for (int r = 1; r < 24; ++r) y0 = cadd(y0, x[r]);
+  b[padr(ob)] = y0;
+#pragma unroll
+  for (int q = 1; q < 24; ++q) {
+    float2 A = x[0], B = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int r = 1; r < 24; ++r) {
+      const int j = (r * q) % 47;
+      A.x = fmaf(x[r].x, kC47[j], A.x);
+      A.y = fmaf(x[r].y, kC47[j], A.y);
+      B.x = fmaf(x[47 - r].x, kS47[j], B.x);
+      B.y = fmaf(x[47 - r].y, kS47[j], B.y);
+    }
+    b[padr(ob + q)] = make_float2(A.x - B.y, A.y + B.x);
+    b[padr(ob + 47 - q)] = make_float2(A.x + B.y, A.y - B.x);
+  }
+}
+
 template <int PTS, int KC>
 __device__ __forceinline__ void c2r_rg_body(FftPlan plan, int lmax, int ntheta, int nseq,
                                             const float2* __restrict__ F, float* __restrict__ maps,
                                             const float2* __restrict__ twg, const float2* __restrict__ twpg) {
   extern __shared__ __attribute__((aligned(16))) float2 rbuf[];
-  const int K = KC ? KC : plan.K;   // KC: the plan 24 x 8 x 8 of K = 1536, compiled in
+  const int K = KC ? KC : plan.K;   // KC: a plan compiled in (24 x 8 x 8 of K = 1536, 47 x 8 x 8 of 3008)
   const int KP = padr(K) + 1;
   float2* tw = rbuf + RG_RINGS * KP;   // e^{2 pi i t / N}, t <= K / 2, shared by the workgroup's rings
   float2* twp = tw + K / 2 + 1;          // the passes' twiddle tables, K - 1 entries in all
@@ -524,6 +584,11 @@ __device__ __forceinline__ void c2r_rg_body(FftPlan plan, int lmax, int ntheta, 
       rg_pass<24, PTS, false, KC, 1>(bw, K, 1, lane, twp);
       rg_pass<8, PTS, false, KC, 24>(bw, K, 24, lane, twp + 23);
       rg_pass<8, PTS, true, KC, 192>(bw, K, 192, lane, twp + 23 + 7 * 24, dst);
+    } else if constexpr (KC == 3008) {
+      // passes 47, 8, 8 (strides 1, 47, 376; twiddle tables at 46, 46 + 7 * 47)
+      rg_pass47_first(bw, lane);
+      rg_pass<8, PTS, false, KC, 47>(bw, K, 47, lane, twp + 46);
+      rg_pass<8, PTS, true, KC, 376>(bw, K, 376, lane, twp + 46 + 7 * 47, dst);
     } else {
       int Ns = 1;
       const float2* tf = twp;
@@ -565,6 +630,14 @@ __global__ __launch_bounds__(64 * RG_RINGS) __attribute__((amdgpu_waves_per_eu(2
   c2r_rg_body<24, 1536>(plan, lmax, ntheta, nseq, F, maps, twg, twpg);
 }
 
+// the plan 47 x 8 x 8 of K = 3008 (the rings of nphi 6016, the l_max 2000 grid): its
+// LDS (about 141 KB) holds one workgroup per CU, so registers are not limited
+__global__ __launch_bounds__(64 * RG_RINGS) void k_fft_c2r_rg_k3008(
+    FftPlan plan, int lmax, int ntheta, int nseq, const float2* __restrict__ F, float* __restrict__ maps,
+    const float2* __restrict__ twg, const float2* __restrict__ twpg) {
+  c2r_rg_body<48, 3008>(plan, lmax, ntheta, nseq, F, maps, twg, twpg);
+}
+
 // r2c, register passes (the adjoint of k_fft_c2r_rg): same persistent ring-group order,
 // one wave per ring.  z_n = G_{2n} + i G_{2n+1} goes into the ring buffer conjugated, so
 // the e^{+i} passes above give conj of Z_m = sum_n z_n e^{-2 pi i m n / K}; after a
@@ -577,7 +650,7 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_r2c_rg(FftPlan plan, int 
                                                               const float2* __restrict__ twg,
                                                               const float2* __restrict__ twpg) {
   extern __shared__ __attribute__((aligned(16))) float2 rbuf[];
-  const int K = KC ? KC : plan.K;   // KC: the plan 24 x 8 x 8 of K = 1536, compiled in
+  const int K = KC ? KC : plan.K;   // KC: a plan compiled in (24 x 8 x 8 of K = 1536, 47 x 8 x 8 of 3008)
   const int KP = padr(K) + 1;
   float2* tw = rbuf + RG_RINGS * KP;
   float2* twp = tw + K / 2 + 1;
@@ -626,6 +699,10 @@ __global__ __launch_bounds__(64 * RG_RINGS) void k_fft_r2c_rg(FftPlan plan, int 
         rg_pass<24, PTS, false, KC, 1>(bw, K, 1, lane, twp);
         rg_pass<8, PTS, false, KC, 24>(bw, K, 24, lane, twp + 23);
         rg_pass<8, PTS, false, KC, 192>(bw, K, 192, lane, twp + 23 + 7 * 24);
+      } else if constexpr (KC == 3008) {
+        rg_pass47_first(bw, lane);
+        rg_pass<8, PTS, false, KC, 47>(bw, K, 47, lane, twp + 46);
+        rg_pass<8, PTS, false, KC, 376>(bw, K, 376, lane, twp + 46 + 7 * 47);
       } else {
         int Ns = 1;
         const float2* tf = twp;
@@ -685,6 +762,12 @@ bool fft_plan_rg(int N, FftPlan& p) {
   p.N = N;
   p.K = N / 2;
   p.nf = 0;
+  if (p.K == 3008) {   // 47 x 8 x 8, compiled in (the one plan with a radix-47 pass)
+    p.radix[0] = 47;
+    p.radix[1] = p.radix[2] = 8;
+    p.nf = 3;
+    return true;
+  }
   if (p.K > RG_KMAX || p.K < 1) return false;
   int K = p.K;
   // a first radix-24 pass (a 24-point DFT in registers) saves one LDS round trip when a
@@ -741,8 +824,11 @@ hipError_t fft_rg_set_lds(size_t bytes) {
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_fft_c2r_rg<48>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_fft_c2r_rg_k1536, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  const void* r2c[] = {(const void*)k_fft_r2c_rg<16>, (const void*)k_fft_r2c_rg<24>, (const void*)k_fft_r2c_rg<32>,
-                       (const void*)k_fft_r2c_rg<48>, (const void*)k_fft_r2c_rg<24, 1536>};
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_fft_c2r_rg_k3008, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  const void* r2c[] = {(const void*)k_fft_r2c_rg<16>,       (const void*)k_fft_r2c_rg<24>,
+                       (const void*)k_fft_r2c_rg<32>,       (const void*)k_fft_r2c_rg<48>,
+                       (const void*)k_fft_r2c_rg<24, 1536>, (const void*)k_fft_r2c_rg<48, 3008>};
   for (const void* f : r2c)
     if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   return e;
@@ -758,6 +844,11 @@ bool plan_has_radix(const FftPlan& p, int r) {
 // the register plan compiled in (K = 1536: the rings of nphi 3072, the l_max 1000 grid)
 bool plan_is_k1536(const FftPlan& p) {
   return p.K == 1536 && p.nf == 3 && p.radix[0] == 24 && p.radix[1] == 8 && p.radix[2] == 8;
+}
+
+// K = 3008 (nphi 6016, the l_max 2000 grid); the register kernels run it only compiled in
+bool plan_is_k3008(const FftPlan& p) {
+  return p.K == 3008 && p.nf == 3 && p.radix[0] == 47 && p.radix[1] == 8 && p.radix[2] == 8;
 }
 }  // namespace
 
@@ -775,6 +866,10 @@ hipError_t launch_fft_c2r(const modal_ctx* c, const void* F, int S, void* maps, 
                      (const float2*)c->t.twp32)
     if (plan_is_k1536(c->fft_rg_plan) && pts == 24)
       hipLaunchKernelGGL(k_fft_c2r_rg_k1536, dim3(blocks), dim3(64 * RG_RINGS), fft_rg_lds(c), st,
+                         c->fft_rg_plan, c->lmax, c->ntheta, nseq, (const float2*)F, (float*)maps,
+                         (const float2*)c->t.tw32, (const float2*)c->t.twp32);
+    else if (plan_is_k3008(c->fft_rg_plan))   // one workgroup per CU: 256 of them
+      hipLaunchKernelGGL(k_fft_c2r_rg_k3008, dim3(std::min(blocks, 256)), dim3(64 * RG_RINGS), fft_rg_lds(c), st,
                          c->fft_rg_plan, c->lmax, c->ntheta, nseq, (const float2*)F, (float*)maps,
                          (const float2*)c->t.tw32, (const float2*)c->t.twp32);
     else if (pts <= 16) LAUNCH(16);
@@ -817,6 +912,10 @@ hipError_t launch_fft_r2c_rows(const modal_ctx* c, const void* G, size_t nseq, v
     if (plan_is_k1536(c->fft_rg_plan) && pts == 24)
       hipLaunchKernelGGL((k_fft_r2c_rg<24, 1536>), dim3(blocks), dim3(64 * RG_RINGS), fft_rg_lds(c), st,
                          c->fft_rg_plan, c->lmax, c->ntheta, (int)nseq, (const float*)G, (float2*)Gh,
+                         (const float2*)c->t.tw32, (const float2*)c->t.twp32);
+    else if (plan_is_k3008(c->fft_rg_plan))
+      hipLaunchKernelGGL((k_fft_r2c_rg<48, 3008>), dim3(std::min(blocks, 256)), dim3(64 * RG_RINGS), fft_rg_lds(c),
+                         st, c->fft_rg_plan, c->lmax, c->ntheta, (int)nseq, (const float*)G, (float2*)Gh,
                          (const float2*)c->t.tw32, (const float2*)c->t.twp32);
     else if (pts <= 16) LAUNCH(16);
     else if (pts <= 24) LAUNCH(24);
