@@ -197,11 +197,26 @@ int modal_npairs(const modal_ctx* ctx);
 /* Contraction kernel the context dispatches for the cubic reduction:
  * 0 = vector-ALU with FP64 accumulation (FP64 contexts, and FP32 contexts with P > 48),
  * 1 = FP32 MFMA (16x16x4 tiles, P <= 48),
- * 2 = split bf16/fp16 MFMA (32x32x16 tiles, modes t >= b only). */
+ * 2 = split bf16/fp16 MFMA (32x32x16 tiles over a cover of the triples, see
+ *     modal_cubic_plan). */
 int modal_cubic_path(const modal_ctx* ctx);
 /* Multiply-adds the cubic contraction issues per pixel and map, counting tile
  * padding and every product of a split (for roofline reports; host only). */
 double modal_cubic_issued_macs(const modal_ctx* ctx);
+/* Work plan of the split contraction for P modes (host only, no device; Sec. II,
+ * eq. (bbispect): beta_prs is the pixel sum of the triple product, so it may be read
+ * from the product of any two of the three maps against the third).  Each work item
+ * is 32 blocks of 2 x 2 pairs {a0, a0+1} x {b0, b0+1} against a window of 32
+ * consecutive modes; it writes the cell (pair (a, b), mode t) for a <= b < P and t in
+ * [zlo, zhi).  Outputs, each optional (NULL skips it):
+ *   items [2 * nitems]: first slot, window base s0 (the window is [s0, s0 + 32));
+ *   slots [4 * 32 * nitems]: a0, b0, zlo, zhi (unused slots have a0 = b0 = 64);
+ *   cell  [nmax]: pair index * P + mode of the cell holding beta_n, triples n in the
+ *         order p <= r <= s, pair index in the order a <= b;
+ *   mult: waves of a workgroup that share one item (1, 2, 4 or 8).
+ * max_items bounds items and slots.  Returns the item count, or -MODAL_EINVAL for P
+ * outside 1..64 or max_items too small. */
+int modal_cubic_plan(int P, int max_items, int* items, int* slots, int* cell, int* mult);
 
 /* The context's quadrature: x_host[ntheta] = cos theta_j (descending),
  * w_host[ntheta] = Gauss-Legendre weights (sum 2).  Either may be NULL. */

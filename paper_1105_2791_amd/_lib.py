@@ -65,6 +65,7 @@ _SIGS = {
     "modal_profile_enable": (ip, [vp, ip]),
     "modal_cubic_path": (ip, [vp]),
     "modal_cubic_issued_macs": (C.c_double, [vp]),
+    "modal_cubic_plan": (ip, [ip, ip, vp, vp, vp, vp]),
     "modal_beta_graph_create": (ip, [ip, vp, vp, vp, vp, vp, vp, vp, vp]),
     "modal_graph_launch": (ip, [vp, vp]),
     "modal_graph_destroy": (None, [vp]),

@@ -54,8 +54,12 @@ struct Tables {
   int* flag = nullptr;         // [4] device status words (Cholesky pivot)
   int2* blk = nullptr;         // [nblk] (a0, b0) of the 2 x 4 pair blocks of the MFMA contraction
   int nblk = 0;
-  int2* items = nullptr;       // [nitems] (first block, mode tile) work items of the split contraction
+  int2* items = nullptr;       // [nitems] (first slot, window base s0) work items of the split contraction
   int nitems = 0;
+  int4* cslot = nullptr;       // [ncslot] (a0, b0, zlo, zhi) blocks of the split contraction's items, 32 per item
+  int ncslot = 0;
+  int cmult = 1;               // waves per item of the split contraction (1, 2, 4 or 8)
+  int* cell = nullptr;         // [nmax] pair * P + mode of the partial-sum cell holding beta_n (split contraction)
   float* mscale = nullptr;     // [P] exact powers of two ~ 1/sigma_p (split-fp16 contraction)
   uint4* lamtab = nullptr;     // split synthesis: lambda operand words per (m, wave of rings, chunk)
   long long* lamtab_off = nullptr;   // [lmax+1] first record of each m
@@ -165,7 +169,9 @@ hipError_t launch_reduce_symm(const modal_ctx* c, const double* partials, int S,
 void make_pair_blocks(int P, std::vector<int2>& out);
 // split-precision contraction on 32x32 tiles (k_cubic_split.hip): 2 x 2 pair blocks
 // sorted by b0; writes the partial sums of the needed modes t >= b only
-void make_pair_blocks22(int P, std::vector<int2>& blocks, std::vector<int2>& items);
+// cover of the triples by (block, window) cells of the split contraction; false if the plan fails
+bool make_cubic_cover(int P, const std::vector<int>& pair_of, std::vector<int4>& slots, std::vector<int2>& items,
+                      std::vector<int>& cell, int* mult);
 size_t cubic_split_lds();
 hipError_t cubic_split_set_lds(size_t bytes);
 hipError_t launch_cubic_split(const modal_ctx* c, const void* maps, int S, int nchunk, int chunk_px, double* part,

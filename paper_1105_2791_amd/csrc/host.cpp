@@ -552,11 +552,20 @@ modal_status place_tables(modal_ctx* c, const double* q_host, const double* cl_h
   Tables& t = c->t;
   if (!ok(pl.put(&t.mscale, mscale))) return MODAL_EDEVICE;
   std::vector<int2> blocks, items;
-  if (prec == MODAL_BF16X3 || prec == MODAL_F16X3) make_pair_blocks22(P, blocks, items);
-  else make_pair_blocks(P, blocks);
+  std::vector<int4> cslots;
+  std::vector<int> cell;
+  if (prec == MODAL_BF16X3 || prec == MODAL_F16X3) {
+    if (!make_cubic_cover(P, pair_of, cslots, items, cell, &t.cmult))
+      return fail(c, MODAL_EINVAL, "no cover of the triples by the split contraction's items");
+  } else {
+    make_pair_blocks(P, blocks);
+  }
   t.nblk = (int)blocks.size();
   t.nitems = (int)items.size();
-  if (!ok(pl.put(&t.blk, blocks)) || !ok(pl.put(&t.items, items))) return MODAL_EDEVICE;
+  t.ncslot = (int)cslots.size();
+  if (!ok(pl.put(&t.blk, blocks)) || !ok(pl.put(&t.items, items)) || !ok(pl.put(&t.cslot, cslots)) ||
+      !ok(pl.put(&t.cell, cell)))
+    return MODAL_EDEVICE;
   if (c->fft_rg && !ok(pl.put(&t.twp32, fft_rg_twiddles(c->fft_rg_plan)))) return MODAL_EDEVICE;
   std::vector<double> xs(c->x_host);
   if (!ok(pl.put(&t.x, xs)) || !ok(pl.put(&t.ringw, ringw)) || !ok(pl.put(&t.w64, w64)) || !ok(pl.put(&t.w32, w32)) ||
@@ -674,6 +683,34 @@ int modal_cubic_path(const modal_ctx* c) {
   if (!c) return -1;
   if (!cubic_mfma_available(c)) return 0;
   return c->prec == MODAL_F32 ? 1 : 2;
+}
+
+int modal_cubic_plan(int P, int max_items, int* items_out, int* slots_out, int* cell_out, int* mult_out) {
+  if (P < 1 || P > kMaxP) return -MODAL_EINVAL;
+  std::vector<int> pair_of((size_t)P * P, -1);
+  int np = 0;
+  for (int p = 0; p < P; ++p)
+    for (int r = p; r < P; ++r) pair_of[(size_t)p * P + r] = pair_of[(size_t)r * P + p] = np++;
+  std::vector<int4> slots;
+  std::vector<int2> items;
+  std::vector<int> cell;
+  int mult = 1;
+  if (!make_cubic_cover(P, pair_of, slots, items, cell, &mult)) return -MODAL_EINVAL;
+  const int n = (int)items.size();
+  if (n > max_items) return -MODAL_EINVAL;
+  for (int i = 0; i < n && items_out; ++i) {
+    items_out[2 * i] = items[i].x;
+    items_out[2 * i + 1] = items[i].y;
+  }
+  for (size_t i = 0; i < slots.size() && slots_out; ++i) {
+    slots_out[4 * i] = slots[i].x;
+    slots_out[4 * i + 1] = slots[i].y;
+    slots_out[4 * i + 2] = slots[i].z;
+    slots_out[4 * i + 3] = slots[i].w;
+  }
+  if (cell_out) std::copy(cell.begin(), cell.end(), cell_out);
+  if (mult_out) *mult_out = mult;
+  return n;
 }
 
 double modal_cubic_issued_macs(const modal_ctx* c) {

@@ -95,24 +95,26 @@ __global__ void k_symm(int nmax, int npairs, int P, int S, double scale, const i
   out[(size_t)s * nmax + n] = v;
 }
 
-// out_n = scale * sum_c part[s][c][pair(pr)][s] + scale2 * (three pairings of E2): beta_prs
-// is the single pairing E_{(pr),s} (the contraction writes the modes t >= b only)
+// out_n = scale * sum_c part[s][c][cell_n] + scale2 * (three pairings of E2): beta_prs is
+// the one cell (pair, mode) of the split contraction that holds it (any of the three
+// pairings of the triple; the table of cells comes with the contraction's plan)
 __global__ void k_reduce_single(int nmax, int npairs, int P, int nchunk, const int* __restrict__ tri,
-                                const double* __restrict__ part, double scale, double scale2,
-                                const double* __restrict__ E2, double* __restrict__ out) {
+                                const int* __restrict__ cell, const double* __restrict__ part, double scale,
+                                double scale2, const double* __restrict__ E2, double* __restrict__ out) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
   if (n >= nmax) return;
   const int* tr = tri + 6 * n;
   const size_t per = (size_t)npairs * P;
-  const size_t i1 = (size_t)tr[3] * P + tr[2];
+  const size_t i1 = (size_t)cell[n];
   const double* src = part + (size_t)s * nchunk * per + i1;
   double v = 0.0;
   for (int c = 0; c < nchunk; ++c) v += src[(size_t)c * per];
   v *= scale;
   if (E2) {
     const size_t o = (size_t)s * per;
-    v += scale2 * (E2[o + i1] + E2[o + (size_t)tr[4] * P + tr[1]] + E2[o + (size_t)tr[5] * P + tr[0]]);
+    v += scale2 * (E2[o + (size_t)tr[3] * P + tr[2]] + E2[o + (size_t)tr[4] * P + tr[1]] +
+                   E2[o + (size_t)tr[5] * P + tr[0]]);
   }
   out[(size_t)s * nmax + n] = v;
 }
@@ -121,8 +123,9 @@ __global__ void k_reduce_single(int nmax, int npairs, int P, int nchunk, const i
 
 hipError_t launch_reduce_single(const modal_ctx* c, const double* part, int S, int nchunk, double scale,
                                 const double* E2, double scale2, double* out, hipStream_t st) {
+  if (!c->t.cell) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_reduce_single, dim3((c->nmax + 255) / 256, S), dim3(256), 0, st, c->nmax, c->npairs, c->P,
-                     nchunk, c->t.tri, part, scale, scale2, E2, out);
+                     nchunk, c->t.tri, c->t.cell, part, scale, scale2, E2, out);
   return hipGetLastError();
 }
 

@@ -12,10 +12,17 @@
 //   * lane-row i of a wave owns a 2 x 2 block of pairs (a0, a0+1) x (b0, b0+1); the
 //     four 32-row tiles of a wave are the four positions in the block, so a K step
 //     reads 4 map rows per lane for 4 pair products;
-//   * blocks are sorted by b0 and taken 32 at a time; a work item is such a group of
-//     32 blocks with one 32-mode tile: the last 32 modes [P-32, P) always, and the
-//     32 before them only when the group's smallest b0 is below P - 32 (for P = 40
-//     that is one extra item; every wave runs one item);
+//   * a work item is 32 such blocks with one 32-mode window [s0, s0 + 32), and each
+//     block carries the range [zlo, zhi) of window modes it writes.  The host covers
+//     the triples with few items (make_cubic_cover): beta_{abz} is the cell of pair
+//     (a, b) at mode z for any of the three ways to split the triple, so the pairs need
+//     not be the two smallest modes.  The modes are grouped in two-mode vertices split
+//     into two classes; pairs inside a class take the window that holds the modes of
+//     the class, and by pigeonhole two modes of every triple share a class (for P 40:
+//     4 items instead of the 8 that pairs (a <= b) with modes z >= b take);
+//   * with fewer than eight items the waves of a workgroup share them: MULT waves run
+//     one item, each on its own substeps of every staged step, and their sums are
+//     added through LDS at the end;
 //   * maps and the split B operand of a 128-pixel step are staged in LDS, double
 //     buffered, with the next step's global loads issued before this step's MFMAs
 //     (a step is long enough to cover the load latency).
@@ -70,6 +77,8 @@ struct Lds {
   uint16_t bh[2][BROWS][BSS];
   uint16_t bl[2][BROWS][BSS];
 };
+// the sums of the waves that share an item pass through the staging area (up to 7 waves)
+static_assert(sizeof(Lds) >= (size_t)(NW - 1) * 64 * 64 * sizeof(float), "LDS too small for the wave sums");
 
 // The value a split starts from must be one rounded FP32 number (see the bf16 path).
 __device__ inline float rounded(float x) {
@@ -156,14 +165,16 @@ __device__ inline f32x16 mfma32(const V& a, const V& b, const f32x16& c) {
                                                    0);
 }
 
-template <int PREC>
+template <int PREC, int MULT>
 __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix, int S, int nchunk, int chunk_px,
-                                                    int nblk, int nitems, int ngroups, const int2* __restrict__ blocks,
+                                                    int nblk, int nitems, int ngroups, const int4* __restrict__ blocks,
                                                     const int2* __restrict__ items, const int* __restrict__ pair_of,
                                                     const float* __restrict__ maps, const float* __restrict__ w,
                                                     const float* __restrict__ mscale, float wscale, int vec,
                                                     double* __restrict__ part) {
   constexpr bool F16 = PREC == MODAL_F16X3;
+  constexpr int NWI = NW / MULT;          // items per workgroup
+  constexpr int NSUB = KS / 16 / MULT;    // substeps of a staged step per wave
   typedef typename std::conditional<F16, f16x8, bf16x8>::type vec8;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   Lds& L = *reinterpret_cast<Lds*>(lds_raw);
@@ -193,19 +204,22 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
     }
   }
 
-  // this wave's work item (wave-uniform): 32 blocks from wfirst, mode tile ct
-  const int item = group * NW + wv;
+  // this wave's work item (wave-uniform): 32 blocks from wfirst, window [s0, s0 + 32);
+  // the MULT waves wi, wi + NWI, ... of an item take the substeps sub NSUB .. + NSUB - 1
+  // of every staged step
+  const int wi = wv % NWI, sub = wv / NWI;
+  const int item = group * NWI + wi;
   const bool wave_on = item < nitems;
-  int wfirst = 0, ct = 1;
+  int wfirst = 0, s0 = P - 32;
   if (wave_on) {
     const int2 it = items[item];
     wfirst = __builtin_amdgcn_readfirstlane(it.x);
-    ct = __builtin_amdgcn_readfirstlane(it.y);
+    s0 = __builtin_amdgcn_readfirstlane(it.y);
   }
   const int myblk = wfirst + lrow;
   int a0 = 0, b0 = 0;
   if (myblk < nblk) {
-    const int2 bb = blocks[myblk];
+    const int4 bb = blocks[myblk];
     a0 = bb.x;
     b0 = bb.y;
   }
@@ -285,7 +299,7 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
   for (int j = 0; j < 4; ++j)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[j][r] = cha[j][r] = 0.f;
-  const int brow = 32 * ct + lrow;   // this lane's B row (mode P - 64 + brow)
+  const int brow = s0 - (P - BROWS) + lrow;   // this lane's B row (mode s0 + lrow)
 
   __syncthreads();   // msc and the zero rows
   load_step(x_begin);
@@ -337,7 +351,8 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
         // so that consecutive MFMAs feed different accumulators (measured faster than the
         // pipelined order for bf16, whose split is twice the vector work of the fp16 one)
 #pragma unroll
-        for (int ks = 0; ks < KS / 16; ++ks) {
+        for (int i = 0; i < NSUB; ++i) {
+          const int ks = sub * NSUB + i;
           const int kx = 16 * ks + 8 * kh;
           const vec8 bh = *reinterpret_cast<const vec8*>(&L.bh[st][brow][kx]);
           const vec8 bl = *reinterpret_cast<const vec8*>(&L.bl[st][brow][kx]);
@@ -357,17 +372,18 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
       vec8 ah[4], al[4];
       {
         Rows R0;
-        load_rows(0, R0);
+        load_rows(sub * NSUB, R0);
 #pragma unroll
         for (int j = 0; j < 4; ++j) split_tile(R0, j, ah[j], al[j]);
       }
 #pragma unroll
-      for (int ks = 0; ks < KS / 16; ++ks) {
+      for (int i = 0; i < NSUB; ++i) {
+        const int ks = sub * NSUB + i;
         const int kx = 16 * ks + 8 * kh;
         const vec8 bh = *reinterpret_cast<const vec8*>(&L.bh[st][brow][kx]);
         const vec8 bl = *reinterpret_cast<const vec8*>(&L.bl[st][brow][kx]);
         Rows Rn;
-        if (ks + 1 < KS / 16) load_rows(ks + 1, Rn);
+        if (i + 1 < NSUB) load_rows(ks + 1, Rn);
         // tile by tile: its three products, then the next substep's split of the same tile
         // into the registers they have just read (issued among the following MFMAs)
 #pragma unroll
@@ -375,7 +391,7 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
           cha[j] = mfma32<PREC>(al[j], bh, cha[j]);
           cha[j] = mfma32<PREC>(ah[j], bl, cha[j]);
           cha[j] = mfma32<PREC>(ah[j], bh, cha[j]);
-          if (ks + 1 < KS / 16) split_tile(Rn, j, ah[j], al[j]);
+          if (i + 1 < NSUB) split_tile(Rn, j, ah[j], al[j]);
         }
       }
       }
@@ -393,20 +409,44 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
     __syncthreads();
     st ^= 1;
   }
+  if constexpr (MULT > 1) {
+    // the item's other waves hand their sums to wave sub 0 through LDS (the staging
+    // buffers are free after the loop's last barrier), added in the order of sub
+    float* red = reinterpret_cast<float*>(lds_raw);
+    if (sub > 0) {
+      float* mine = red + (size_t)((sub - 1) * NWI + wi) * (64 * 64) + lane;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) mine[(16 * j + r) * 64] = acc[j][r];
+    }
+    __syncthreads();
+    if (sub > 0) return;
+#pragma unroll 1
+    for (int u = 1; u < MULT; ++u) {
+      const float* theirs = red + (size_t)((u - 1) * NWI + wi) * (64 * 64) + lane;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[j][r] += theirs[(16 * j + r) * 64];
+    }
+  }
   if (!wave_on) return;
 
-  // partial sums: acc[j][r] = E[pair j of block wfirst + 8 (r/4) + 4 kh + r % 4][mode P - 64 + brow]
-  const int t = P - 64 + brow;
+  // partial sums: acc[j][r] = E[pair j of block wfirst + 8 (r/4) + 4 kh + r % 4][mode s0 + lrow];
+  // each block writes the modes [zlo, zhi) of the window (a cell is written by one item)
+  const int t = s0 + lrow;
   double* dst = part + ((size_t)s * nchunk + chunk) * npairs * P;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int ob = wfirst + 8 * (r >> 2) + 4 * kh + (r & 3);
     if (ob >= nblk) continue;
-    const int2 bb = blocks[ob];
+    const int4 bb = blocks[ob];
+    if (t < bb.z || t >= bb.w) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int a = bb.x + (j >> 1), b = bb.y + (j & 1);
-      if (a >= P || b >= P || a > b || t < b) continue;   // needed modes only: t >= b (>= 0)
+      if (a >= P || b >= P || a > b) continue;
       double v = (double)acc[j][r];
       if (F16) v *= 1.0 / ((double)mscale[a] * (double)mscale[b] * (double)mscale[t] * (double)wscale);   // powers of two
       dst[(size_t)pair_of[a * P + b] * P + t] = v;
@@ -416,42 +456,161 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
 
 }  // namespace
 
-// 2 x 2 pair blocks (a0, b0 even, a0 <= b0) sorted by b0, then a0, and the work items
-// (first block of a group of 32, mode tile).
-void make_pair_blocks22(int P, std::vector<int2>& blocks, std::vector<int2>& items) {
-  blocks.clear();
+// Cover of the triples p <= r <= s by the cells (pair, mode) that the work items write.
+// A vertex v is the mode pair {2v, 2v + 1}; block (u, v), u <= v, holds the pairs of
+// {2u, 2u + 1} x {2v, 2v + 1} with a <= b.  Windows: [P - 32, P) when P <= 32, else
+// A = [0, 32) and B = [P - 32, P).  With L the vertices holding a mode below P - 32 and
+// H those holding a mode from 32 on, the vertices are split into classes C_B = [0, k)
+// (holding L) and C_A = [k, V) (holding H).  Blocks inside C_A take window A, blocks
+// inside C_B window B.  A triple has two modes in one class (pigeonhole); their pair's
+// window misses the third mode only when that mode lies in L (class B) or H (class A),
+// i.e. in the same class, and then another pair of the triple works, unless all three
+// modes are in L (or all in H).  Those triples take the blocks inside L with window A
+// (inside H with window B); there the blocks of two halves suffice, since two of any
+// three vertices fall in one half.  Within a single window (P <= 32) the same two
+// halves cover everything.  A block in two windows writes each mode once: [zlo, zhi).
+// For P = 40 this takes 122 blocks in 4 items (61 per window).
+namespace {
+struct BlockWin {
+  int u, v, s0, zlo, zhi;
+};
+void add_clique(std::vector<BlockWin>& bw, int v0, int v1, int s0, int zlo, int zhi) {
+  for (int v = v0; v < v1; ++v)
+    for (int u = v0; u <= v; ++u) bw.push_back({u, v, s0, zlo, zhi});
+}
+void add_halves(std::vector<BlockWin>& bw, int v0, int v1, int s0, int zlo, int zhi) {
+  const int h = v0 + (v1 - v0 + 1) / 2;
+  add_clique(bw, v0, h, s0, zlo, zhi);
+  add_clique(bw, h, v1, s0, zlo, zhi);
+}
+int clique_blocks(int n) { return n * (n + 1) / 2; }
+int halves_blocks(int n) { return clique_blocks((n + 1) / 2) + clique_blocks(n / 2); }
+int ceil32(int n) { return (n + BPW - 1) / BPW; }
+}  // namespace
+
+bool make_cubic_cover(int P, const std::vector<int>& pair_of, std::vector<int4>& slots, std::vector<int2>& items,
+                      std::vector<int>& cell, int* mult) {
+  slots.clear();
   items.clear();
-  for (int b = 0; b < P; b += 2)
-    for (int a = 0; a <= b; a += 2) blocks.push_back(make_int2(a, b));
-  for (int g = 0; g < (int)blocks.size(); g += BPW) {
-    items.push_back(make_int2(g, 1));
-    if (P - blocks[g].y > 32) items.push_back(make_int2(g, 0));
+  cell.clear();
+  if (P < 1 || P > kMaxP) return false;
+  const int V = (P + 1) / 2;
+  std::vector<BlockWin> bw;
+  if (P <= 32) {
+    add_halves(bw, 0, V, P - 32, 0, P);
+  } else {
+    const int nL = (P - 31) / 2, hv = 16;   // L = [0, nL), H = [16, V)
+    int best_k = nL, best = 1 << 30, best_imb = 1 << 30;
+    for (int k = nL; k <= hv; ++k) {   // the class boundary with the fewest items, then the most even
+      const int nA = clique_blocks(V - k) + halves_blocks(nL), nB = clique_blocks(k) + halves_blocks(V - hv);
+      const int n = ceil32(nA) + ceil32(nB), imb = std::abs(nA - nB);
+      if (n < best || (n == best && imb < best_imb)) {
+        best = n;
+        best_imb = imb;
+        best_k = k;
+      }
+    }
+    add_clique(bw, best_k, V, 0, 0, 32);
+    add_halves(bw, 0, nL, 0, 0, P - 32);
+    add_clique(bw, 0, best_k, P - 32, P - 32, P);
+    add_halves(bw, hv, V, P - 32, 32, P);
   }
+  // items: the blocks of one window, 32 at a time, in the order added
+  std::vector<std::vector<int>> lists;
+  for (int w = 0; w < 2; ++w) {
+    const int s0 = w == 0 ? std::min(0, P - 32) : P - 32;
+    if (w == 1 && s0 == std::min(0, P - 32)) break;
+    std::vector<int> mine;
+    for (int i = 0; i < (int)bw.size(); ++i)
+      if (bw[i].s0 == s0) mine.push_back(i);
+    for (size_t f = 0; f < mine.size(); f += BPW)
+      lists.emplace_back(mine.begin() + f, mine.begin() + std::min(mine.size(), f + BPW));
+  }
+  // fewer than eight items: split the largest until the count divides the eight waves
+  int n = (int)lists.size();
+  int target = n;
+  if (n <= 8) {
+    target = 1;
+    while (target < n) target *= 2;
+  }
+  while ((int)lists.size() < target) {
+    size_t big = 0;
+    for (size_t i = 1; i < lists.size(); ++i)
+      if (lists[i].size() > lists[big].size()) big = i;
+    if (lists[big].size() < 2) break;
+    std::vector<int> tail(lists[big].begin() + lists[big].size() / 2, lists[big].end());
+    lists[big].resize(lists[big].size() / 2);
+    lists.push_back(tail);
+  }
+  n = (int)lists.size();
+  *mult = (n <= 8 && 8 % n == 0) ? 8 / n : 1;
+  for (const auto& li : lists) {
+    items.push_back(make_int2((int)slots.size(), bw[li[0]].s0));
+    for (int i : li) slots.push_back(make_int4(2 * bw[i].u, 2 * bw[i].v, bw[i].zlo, bw[i].zhi));
+    while (slots.size() % BPW) slots.push_back(make_int4(kMaxP, kMaxP, 0, 0));
+  }
+  // written cells: block (u, v) -> modes, each written once
+  std::vector<unsigned long long> wmask((size_t)V * V, 0ull);
+  for (const auto& b : bw)
+    for (int z = std::max(b.zlo, 0); z < std::min(b.zhi, P); ++z) {
+      if (z < b.s0 || z >= b.s0 + 32) return false;
+      unsigned long long& m = wmask[(size_t)b.u * V + b.v];
+      if (m >> z & 1ull) return false;   // two items would write one cell
+      m |= 1ull << z;
+    }
+  auto written = [&](int x, int y, int z) {
+    return (wmask[(size_t)(x >> 1) * V + (y >> 1)] >> z & 1ull) != 0;
+  };
+  for (int p = 0; p < P; ++p)
+    for (int r = p; r < P; ++r)
+      for (int s = r; s < P; ++s) {
+        int c = -1;
+        if (written(p, r, s)) c = pair_of[(size_t)p * P + r] * P + s;
+        else if (written(p, s, r)) c = pair_of[(size_t)p * P + s] * P + r;
+        else if (written(r, s, p)) c = pair_of[(size_t)r * P + s] * P + p;
+        if (c < 0) return false;
+        cell.push_back(c);
+      }
+  return true;
 }
 
 size_t cubic_split_lds() { return sizeof(Lds); }
 
 hipError_t cubic_split_set_lds(size_t bytes) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_cubic_split<MODAL_BF16X3>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_cubic_split<MODAL_F16X3>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)bytes);
+  const void* fns[] = {(const void*)k_cubic_split<MODAL_BF16X3, 1>, (const void*)k_cubic_split<MODAL_BF16X3, 2>,
+                       (const void*)k_cubic_split<MODAL_BF16X3, 4>, (const void*)k_cubic_split<MODAL_BF16X3, 8>,
+                       (const void*)k_cubic_split<MODAL_F16X3, 1>,  (const void*)k_cubic_split<MODAL_F16X3, 2>,
+                       (const void*)k_cubic_split<MODAL_F16X3, 4>,  (const void*)k_cubic_split<MODAL_F16X3, 8>};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_cubic_split(const modal_ctx* c, const void* maps, int S, int nchunk, int chunk_px, double* part,
                               hipStream_t st) {
   if (c->P > kMaxP || chunk_px % KS != 0 || (long long)nchunk * chunk_px < c->npix) return hipErrorInvalidValue;
-  const int ngroups = (c->t.nitems + NW - 1) / NW;
+  const int mult = c->t.cmult;
+  if (mult != 1 && mult != 2 && mult != 4 && mult != 8) return hipErrorInvalidValue;
+  if (mult > 1 && c->t.nitems * mult != NW) return hipErrorInvalidValue;
+  const int ngroups = (c->t.nitems * mult + NW - 1) / NW;
   const int nslots = 8 * ((nchunk + 7) / 8);
   const size_t grid = (size_t)nslots * ngroups * S;
   const size_t lds = sizeof(Lds);
-#define LAUNCH(PR)                                                                                              \
-  hipLaunchKernelGGL((k_cubic_split<PR>), dim3(grid), dim3(NT), lds, st, c->P, c->npairs, c->npix, S, nchunk,     \
-                     chunk_px, c->t.nblk, c->t.nitems, ngroups, c->t.blk, c->t.items, c->t.pair_of,               \
+#define LAUNCH(PR, M)                                                                                           \
+  hipLaunchKernelGGL((k_cubic_split<PR, M>), dim3(grid), dim3(NT), lds, st, c->P, c->npairs, c->npix, S, nchunk, \
+                     chunk_px, c->t.ncslot, c->t.nitems, ngroups, c->t.cslot, c->t.items, c->t.pair_of,          \
                      (const float*)maps, c->t.w32, c->t.mscale, c->wscale, c->npix % 4 == 0 ? 1 : 0, part)
-  if (c->prec == MODAL_F16X3) LAUNCH(MODAL_F16X3);
-  else LAUNCH(MODAL_BF16X3);
+#define BY_MULT(PR)              \
+  switch (mult) {                \
+    case 1: LAUNCH(PR, 1); break; \
+    case 2: LAUNCH(PR, 2); break; \
+    case 4: LAUNCH(PR, 4); break; \
+    default: LAUNCH(PR, 8); break; \
+  }
+  if (c->prec == MODAL_F16X3) BY_MULT(MODAL_F16X3) else BY_MULT(MODAL_BF16X3)
+#undef BY_MULT
 #undef LAUNCH
   return hipGetLastError();
 }

@@ -95,3 +95,67 @@ def test_ctx_bytes_size_query(lib):
     # the pixel weights alone: FP64 and FP32 planes of npix values
     assert f(1000, 1536, 3072, 40, L.BF16X3, 0) > 12 * 1536 * 3072
     assert f(150, 199, 400, 13, L.F32, 0) < f(150, 399, 800, 13, L.F32, 0)
+
+
+def _plan(lib, P):
+    """The split contraction's plan for P modes, through the C ABI (host only)."""
+    nmax = P * (P + 1) * (P + 2) // 6
+    max_items = 64
+    items = (ctypes.c_int * (2 * max_items))()
+    slots = (ctypes.c_int * (4 * 32 * max_items))()
+    cell = (ctypes.c_int * nmax)()
+    mult = ctypes.c_int(0)
+    n = lib.modal_cubic_plan(P, max_items, items, slots, cell, ctypes.byref(mult))
+    assert n > 0, (P, n)
+    return n, list(items)[:2 * n], list(slots)[:4 * 32 * n], list(cell), mult.value
+
+
+@pytest.mark.parametrize("P", list(range(1, 65)))
+def test_cubic_plan_writes_every_triple_once(lib, P):
+    """The cells the split contraction writes, emulated from the plan as the kernel's
+    write-out reads it, cover every triple p <= r <= s exactly through the cell the
+    reduction reads; no cell is written by two items (Sec. II, eq. (bbispect): the
+    triple product is symmetric, so beta_prs is any pairing of the three maps)."""
+    n, items, slots, cell, mult = _plan(lib, P)
+    pair = {}
+    for a in range(P):
+        for b in range(a, P):
+            pair[(a, b)] = len(pair)
+    written = {}
+    for i in range(n):
+        first, s0 = items[2 * i], items[2 * i + 1]
+        assert first == 32 * i
+        assert P - 64 <= s0 <= max(0, P - 32)   # the window lies in the staged B rows
+        for k in range(32):
+            a0, b0, zlo, zhi = slots[4 * (first + k): 4 * (first + k) + 4]
+            for j in range(4):
+                a, b = a0 + j // 2, b0 + j % 2
+                if a >= P or b >= P or a > b:
+                    continue
+                for t in range(max(s0, zlo, 0), min(s0 + 32, zhi, P)):
+                    key = pair[(a, b)] * P + t
+                    assert key not in written, (P, a, b, t)
+                    written[key] = i
+    tris = [(p, r, s) for p in range(P) for r in range(p, P) for s in range(r, P)]
+    assert len(cell) == len(tris)
+    inv = {v: k for k, v in pair.items()}
+    for (p, r, s), c in zip(tris, cell):
+        assert c in written, (P, p, r, s)
+        a, b = inv[c // P]
+        assert sorted((a, b, c % P)) == [p, r, s]
+    assert mult in (1, 2, 4, 8)
+    assert n * mult == 8 if mult > 1 else n >= 5
+
+
+@pytest.mark.parametrize("P,items,mult", [(8, 1, 8), (30, 2, 4), (40, 4, 2), (50, 8, 1)])
+def test_cubic_plan_item_counts(lib, P, items, mult):
+    """Work of the split contraction at the configured mode counts: for P 40 the two
+    classes take 61 blocks per window (4 items; 8 with pairs a <= b against modes t >= b)."""
+    n, _, _, _, m = _plan(lib, P)
+    assert (n, m) == (items, mult)
+
+
+def test_cubic_plan_rejects_bad_P(lib):
+    assert lib.modal_cubic_plan(0, 64, None, None, None, None) < 0
+    assert lib.modal_cubic_plan(65, 64, None, None, None, None) < 0
+    assert lib.modal_cubic_plan(40, 1, None, None, None, None) < 0
