@@ -210,7 +210,7 @@ double modal_cubic_issued_macs(const modal_ctx* ctx);
  * consecutive modes; it writes the cell (pair (a, b), mode t) for a <= b < P and t in
  * [zlo, zhi).  Outputs, each optional (NULL skips it):
  *   items [2 * nitems]: first slot, window base s0 (the window is [s0, s0 + 32));
- *   slots [4 * 32 * nitems]: a0, b0, zlo, zhi (unused slots have a0 = b0 = 64);
+ *   slots [4 * 32 * nitems]: a0, b0, zlo, zhi (unused slots have zlo = zhi = 0);
  *   cell  [nmax]: pair index * P + mode of the cell holding beta_n, triples n in the
  *         order p <= r <= s, pair index in the order a <= b;
  *   mult: waves of a workgroup that share one item (1, 2, 4 or 8).

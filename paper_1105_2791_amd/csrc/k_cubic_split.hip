@@ -43,7 +43,8 @@
 // split, twice the vector work, 3% slower, so bf16 keeps split-then-MFMA per substep).
 // The matrix core drops addend bits below the largest term of an accumulation, which
 // against a long running sum biases every step; so the MFMAs accumulate a short
-// chain of CHAIN staged steps from zero, and each chain joins the running FP32 sum
+// chain of CHAIN x MULT staged steps from zero (48 MFMAs per tile whatever the number of
+// waves sharing an item), and each chain joins the running FP32 sum
 // with a round-to-nearest vector add.
 #include "common.h"
 
@@ -65,7 +66,7 @@ constexpr int MSS = KS + 4;        // map row stride in LDS (floats)
 constexpr int BSS = KS + 8;        // B row stride in LDS (16-bit)
 constexpr int BROWS = 64;          // B rows: row r <-> mode P - 64 + r (rows of negative modes are zero)
 constexpr int QSTEP = kMaxP * KS / (4 * NT);   // staged pixel quads per thread per step (4)
-constexpr int CHAIN = 2;           // staged steps per MFMA accumulation chain (48 MFMAs per tile)
+constexpr int CHAIN = 2;           // staged steps per MFMA accumulation chain with one wave per item
 
 // LDS slot of map row r: even rows first, then odd rows.  The lane-rows of a wave
 // read rows a0 (even, consecutive blocks) and a0 + 1, so consecutive even rows land
@@ -395,7 +396,7 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
         }
       }
       }
-      if (++link == CHAIN || !more) {   // wave-uniform
+      if (++link == CHAIN * MULT || !more) {   // wave-uniform
         link = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -510,21 +511,54 @@ bool make_cubic_cover(int P, const std::vector<int>& pair_of, std::vector<int4>&
         best_k = k;
       }
     }
-    add_clique(bw, best_k, V, 0, 0, 32);
+    // the low and high blocks first: the item halves they open are then filled with the
+    // class blocks whose vertices share no LDS bank group with them
     add_halves(bw, 0, nL, 0, 0, P - 32);
-    add_clique(bw, 0, best_k, P - 32, P - 32, P);
+    add_clique(bw, best_k, V, 0, 0, 32);
     add_halves(bw, hv, V, P - 32, 32, P);
+    add_clique(bw, 0, best_k, P - 32, P - 32, P);
   }
-  // items: the blocks of one window, 32 at a time, in the order added
+  // items: the blocks of one window, 32 at a time.  The map row of vertex u sits in the
+  // 16-byte LDS bank group u mod 16 (even and odd rows alike, row stride 33 groups), so
+  // each half item (the 16 lanes of one LDS read cycle) is filled greedily with the blocks
+  // that add the fewest vertices sharing a group with a different vertex already there
   std::vector<std::vector<int>> lists;
   for (int w = 0; w < 2; ++w) {
     const int s0 = w == 0 ? std::min(0, P - 32) : P - 32;
     if (w == 1 && s0 == std::min(0, P - 32)) break;
-    std::vector<int> mine;
+    std::vector<int> left;
     for (int i = 0; i < (int)bw.size(); ++i)
-      if (bw[i].s0 == s0) mine.push_back(i);
-    for (size_t f = 0; f < mine.size(); f += BPW)
-      lists.emplace_back(mine.begin() + f, mine.begin() + std::min(mine.size(), f + BPW));
+      if (bw[i].s0 == s0) left.push_back(i);
+    std::vector<int> order;
+    while (!left.empty()) {
+      unsigned long long seen_u = 0, seen_v = 0;   // vertices present in this half
+      for (int k = 0; k < BPW / 2 && !left.empty(); ++k) {
+        size_t best = 0;
+        int best_cost = 1 << 30;
+        for (size_t q = 0; q < left.size(); ++q) {
+          const BlockWin& b = bw[left[q]];
+          auto clash = [](unsigned long long seen, int x) {
+            if (seen >> x & 1ull) return 0;   // the same row: one address
+            for (int y = x % 16; y < 64; y += 16)
+              if (seen >> y & 1ull) return 1;
+            return 0;
+          };
+          const int cost = clash(seen_u, b.u) + clash(seen_v, b.v);
+          if (cost < best_cost) {
+            best_cost = cost;
+            best = q;
+          }
+          if (cost == 0) break;
+        }
+        const BlockWin& b = bw[left[best]];
+        seen_u |= 1ull << b.u;
+        seen_v |= 1ull << b.v;
+        order.push_back(left[best]);
+        left.erase(left.begin() + best);
+      }
+    }
+    for (size_t f = 0; f < order.size(); f += BPW)
+      lists.emplace_back(order.begin() + f, order.begin() + std::min(order.size(), f + BPW));
   }
   // fewer than eight items: split the largest until the count divides the eight waves
   int n = (int)lists.size();
@@ -547,7 +581,9 @@ bool make_cubic_cover(int P, const std::vector<int>& pair_of, std::vector<int4>&
   for (const auto& li : lists) {
     items.push_back(make_int2((int)slots.size(), bw[li[0]].s0));
     for (int i : li) slots.push_back(make_int4(2 * bw[i].u, 2 * bw[i].v, bw[i].zlo, bw[i].zhi));
-    while (slots.size() % BPW) slots.push_back(make_int4(kMaxP, kMaxP, 0, 0));
+    // unused slots repeat the rows of the item's last block (one LDS address) and write nothing
+    const int4 last = slots.back();
+    while (slots.size() % BPW) slots.push_back(make_int4(last.x, last.y, 0, 0));
   }
   // written cells: block (u, v) -> modes, each written once
   std::vector<unsigned long long> wmask((size_t)V * V, 0ull);
