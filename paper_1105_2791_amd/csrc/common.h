@@ -60,6 +60,7 @@ struct Tables {
   int ncslot = 0;
   int cmult = 1;               // waves per item of the split contraction (1, 2, 4 or 8)
   int* cell = nullptr;         // [nmax] pair * P + mode of the partial-sum cell holding beta_n (split contraction)
+  int* cell_order = nullptr;   // [nmax] the triples sorted by their cell
   float* mscale = nullptr;     // [P] exact powers of two ~ 1/sigma_p (split-fp16 contraction)
   uint4* lamtab = nullptr;     // split synthesis: lambda operand words per (m, wave of rings, chunk)
   long long* lamtab_off = nullptr;   // [lmax+1] first record of each m

@@ -563,8 +563,11 @@ modal_status place_tables(modal_ctx* c, const double* q_host, const double* cl_h
   t.nblk = (int)blocks.size();
   t.nitems = (int)items.size();
   t.ncslot = (int)cslots.size();
+  std::vector<int> cell_order(cell.size());
+  for (size_t n = 0; n < cell.size(); ++n) cell_order[n] = (int)n;
+  std::sort(cell_order.begin(), cell_order.end(), [&](int x, int y) { return cell[x] < cell[y]; });
   if (!ok(pl.put(&t.blk, blocks)) || !ok(pl.put(&t.items, items)) || !ok(pl.put(&t.cslot, cslots)) ||
-      !ok(pl.put(&t.cell, cell)))
+      !ok(pl.put(&t.cell, cell)) || !ok(pl.put(&t.cell_order, cell_order)))
     return MODAL_EDEVICE;
   if (c->fft_rg && !ok(pl.put(&t.twp32, fft_rg_twiddles(c->fft_rg_plan)))) return MODAL_EDEVICE;
   std::vector<double> xs(c->x_host);

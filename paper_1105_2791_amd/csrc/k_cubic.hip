@@ -97,13 +97,17 @@ __global__ void k_symm(int nmax, int npairs, int P, int S, double scale, const i
 
 // out_n = scale * sum_c part[s][c][cell_n] + scale2 * (three pairings of E2): beta_prs is
 // the one cell (pair, mode) of the split contraction that holds it (any of the three
-// pairings of the triple; the table of cells comes with the contraction's plan)
+// pairings of the triple; the table of cells comes with the contraction's plan).  Thread i
+// takes triple n = order[i], the triples sorted by cell, so that a wave reads runs of
+// neighbouring cells of each chunk's partial sums.
 __global__ void k_reduce_single(int nmax, int npairs, int P, int nchunk, const int* __restrict__ tri,
-                                const int* __restrict__ cell, const double* __restrict__ part, double scale,
-                                double scale2, const double* __restrict__ E2, double* __restrict__ out) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+                                const int* __restrict__ cell, const int* __restrict__ order,
+                                const double* __restrict__ part, double scale, double scale2,
+                                const double* __restrict__ E2, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
-  if (n >= nmax) return;
+  if (i >= nmax) return;
+  const int n = order[i];
   const int* tr = tri + 6 * n;
   const size_t per = (size_t)npairs * P;
   const size_t i1 = (size_t)cell[n];
@@ -123,9 +127,9 @@ __global__ void k_reduce_single(int nmax, int npairs, int P, int nchunk, const i
 
 hipError_t launch_reduce_single(const modal_ctx* c, const double* part, int S, int nchunk, double scale,
                                 const double* E2, double scale2, double* out, hipStream_t st) {
-  if (!c->t.cell) return hipErrorInvalidValue;
+  if (!c->t.cell || !c->t.cell_order) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_reduce_single, dim3((c->nmax + 255) / 256, S), dim3(256), 0, st, c->nmax, c->npairs, c->P,
-                     nchunk, c->t.tri, c->t.cell, part, scale, scale2, E2, out);
+                     nchunk, c->t.tri, c->t.cell, c->t.cell_order, part, scale, scale2, E2, out);
   return hipGetLastError();
 }
 
