@@ -195,10 +195,9 @@ int modal_nmax(const modal_ctx* ctx);
 int modal_npairs(const modal_ctx* ctx);
 
 /* Contraction kernel the context dispatches for the cubic reduction:
- * 0 = vector-ALU with FP64 accumulation (FP64 contexts, and FP32 contexts with P > 48),
- * 1 = FP32 MFMA (16x16x4 tiles, P <= 48),
- * 2 = split bf16/fp16 MFMA (32x32x16 tiles over a cover of the triples, see
- *     modal_cubic_plan). */
+ * 0 = vector-ALU with FP64 accumulation (FP64 contexts),
+ * 1 = FP32 MFMA (32x32x2 tiles over a cover of the triples, see modal_cubic_plan),
+ * 2 = split bf16/fp16 MFMA (32x32x16 tiles over the same cover). */
 int modal_cubic_path(const modal_ctx* ctx);
 /* Multiply-adds the cubic contraction issues per pixel and map, counting tile
  * padding and every product of a split (for roofline reports; host only). */

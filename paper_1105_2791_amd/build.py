@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmodal.so")
 
-SOURCES = ["host.cpp", "k_legendre.hip", "k_fft.hip", "k_cubic.hip", "k_cubic_mfma.hip",
+SOURCES = ["host.cpp", "k_legendre.hip", "k_fft.hip", "k_cubic.hip",
            "k_linear.hip", "k_linalg.hip", "k_adjoint.hip", "k_fisher.hip", "k_legendre_mfma.hip", "k_lin_harm.hip", "k_cubic_split.hip", "k_legendre_split.hip", "k_lowrank.hip", "k_shapes.hip", "k_power.hip", "k_trispectrum.hip", "k_frame.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

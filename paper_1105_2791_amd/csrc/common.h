@@ -52,8 +52,6 @@ struct Tables {
   int* tri_of = nullptr;       // [P][npairs] triple index of sort(u, a, b)
   int* tri_mult = nullptr;     // [P][npairs] multiplicity of u in that triple
   int* flag = nullptr;         // [4] device status words (Cholesky pivot)
-  int2* blk = nullptr;         // [nblk] (a0, b0) of the 2 x 4 pair blocks of the MFMA contraction
-  int nblk = 0;
   int2* items = nullptr;       // [nitems] (first slot, window base s0) work items of the split contraction
   int nitems = 0;
   int4* cslot = nullptr;       // [ncslot] (a0, b0, zlo, zhi) blocks of the split contraction's items, 32 per item
@@ -159,7 +157,6 @@ hipError_t launch_fisher_assemble(const modal_ctx* c, const double* X, double sc
 // partials[S][nchunk][npairs][P] float64 (VALU FP64 path / matrix-core paths)
 int cubic_nchunk(const modal_ctx* c);
 hipError_t launch_cubic_valu(const modal_ctx* c, const void* maps, int S, double* partials, hipStream_t st);
-hipError_t launch_cubic_mfma(const modal_ctx* c, const void* maps, int S, double* partials, hipStream_t st);
 bool cubic_mfma_available(const modal_ctx* c);
 int cubic_mfma_nchunk(const modal_ctx* c);
 int cubic_mfma_nchunk_max(const modal_ctx* c);
@@ -167,7 +164,6 @@ int cubic_mfma_nchunk_max(const modal_ctx* c);
 // pairings of E2[S][npairs][P]); partials or E2 may be null
 hipError_t launch_reduce_symm(const modal_ctx* c, const double* partials, int S, int nchunk, double scale,
                               double* E, const double* E2, double scale2, double* out, hipStream_t st);
-void make_pair_blocks(int P, std::vector<int2>& out);
 // split-precision contraction on 32x32 tiles (k_cubic_split.hip): 2 x 2 pair blocks
 // sorted by b0; writes the partial sums of the needed modes t >= b only
 // cover of the triples by (block, window) cells of the split contraction; false if the plan fails

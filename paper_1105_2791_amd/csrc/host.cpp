@@ -309,9 +309,9 @@ modal_status run_maps(modal_ctx* c, const void* alm, int S, void* F, void* maps,
 modal_status run_beta(modal_ctx* c, const void* maps, const void* alm, const void* state, int S, double* part,
                       double* E, double* X, double* L, double* out, hipStream_t st, double sb = 1.0,
                       double sl = -1.0) {
-  const bool split = c->prec == MODAL_BF16X3 || c->prec == MODAL_F16X3;
+  // the matrix cores over the triple cover (split and FP32 contexts), the vector ALUs in FP64
+  const bool split = cubic_mfma_available(c);
   if (split) STAGE(MODAL_STAGE_CUBIC, launch_cubic_split(c, maps, S, nchunk_for(c), cubic_chunk_px(c), part, st));
-  else if (cubic_mfma_available(c)) STAGE(MODAL_STAGE_CUBIC, launch_cubic_mfma(c, maps, S, part, st));
   else STAGE(MODAL_STAGE_CUBIC, launch_cubic_valu(c, maps, S, part, st));
   if (state) STAGE(MODAL_STAGE_LINEAR, launch_lin_harmonic(c, lin_Z(c, state), alm, S, X, L, st));
   if (split)
@@ -551,22 +551,19 @@ modal_status place_tables(modal_ctx* c, const double* q_host, const double* cl_h
   c->wscale = (float)std::ldexp(1.0, (int)std::lround(std::log2((double)c->npix / (4.0 * kPi))));
   Tables& t = c->t;
   if (!ok(pl.put(&t.mscale, mscale))) return MODAL_EDEVICE;
-  std::vector<int2> blocks, items;
+  std::vector<int2> items;
   std::vector<int4> cslots;
   std::vector<int> cell;
-  if (prec == MODAL_BF16X3 || prec == MODAL_F16X3) {
+  if (prec == MODAL_BF16X3 || prec == MODAL_F16X3 || prec == MODAL_F32) {
     if (!make_cubic_cover(P, pair_of, cslots, items, cell, &t.cmult))
-      return fail(c, MODAL_EINVAL, "no cover of the triples by the split contraction's items");
-  } else {
-    make_pair_blocks(P, blocks);
+      return fail(c, MODAL_EINVAL, "no cover of the triples by the contraction's items");
   }
-  t.nblk = (int)blocks.size();
   t.nitems = (int)items.size();
   t.ncslot = (int)cslots.size();
   std::vector<int> cell_order(cell.size());
   for (size_t n = 0; n < cell.size(); ++n) cell_order[n] = (int)n;
   std::sort(cell_order.begin(), cell_order.end(), [&](int x, int y) { return cell[x] < cell[y]; });
-  if (!ok(pl.put(&t.blk, blocks)) || !ok(pl.put(&t.items, items)) || !ok(pl.put(&t.cslot, cslots)) ||
+  if (!ok(pl.put(&t.items, items)) || !ok(pl.put(&t.cslot, cslots)) ||
       !ok(pl.put(&t.cell, cell)) || !ok(pl.put(&t.cell_order, cell_order)))
     return MODAL_EDEVICE;
   if (c->fft_rg && !ok(pl.put(&t.twp32, fft_rg_twiddles(c->fft_rg_plan)))) return MODAL_EDEVICE;
@@ -719,7 +716,7 @@ int modal_cubic_plan(int P, int max_items, int* items_out, int* slots_out, int* 
 double modal_cubic_issued_macs(const modal_ctx* c) {
   if (!c) return 0.0;
   if (c->prec == MODAL_BF16X3 || c->prec == MODAL_F16X3) return (double)c->t.nitems * 32 * 4 * 32 * 3;
-  if (c->prec == MODAL_F32 && cubic_mfma_available(c)) return (double)c->t.nblk * 8 * 48;
+  if (c->prec == MODAL_F32 && cubic_mfma_available(c)) return (double)c->t.nitems * 32 * 4 * 32;
   return (double)c->npairs * c->P;
 }
 

@@ -10,7 +10,8 @@
 //
 // This kernel is the FP64 path (and any precision's reference-grade path): one
 // workgroup per (pixel chunk, block of 64 pairs, map) accumulating in FP64.
-// The MFMA paths live in k_cubic_mfma.hip and share the reduction below.
+// The matrix-core path (FP32 and the splits) lives in k_cubic_split.hip and uses the
+// reduction k_reduce_single below.
 #include "common.h"
 
 namespace modal {

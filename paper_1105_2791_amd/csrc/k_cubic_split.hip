@@ -1,10 +1,12 @@
-// Cubic pixel reduction on the matrix cores with split 16-bit operands, 32x32 tiles.
+// Cubic pixel reduction on the matrix cores, 32x32 tiles over a cover of the triples:
+// split 16-bit operands (32x32x16) for the bf16x3 and f16x3 contexts, FP32 operands
+// (32x32x2) for FP32 contexts.
 //
 //   E_{(ab),t} = sum_x A_ab(x) B_t(x),  A_ab = M_a M_b,  B_t = w M_t,
 //
 // a GEMM with M = pairs, N = modes, K = pixels (chunked; FP32 partial sums are
-// reduced in FP64 by k_cubic.hip).  beta_prs = E_{(pr),s} for p <= r <= s, so only
-// the modes t >= b of a pair (a, b) are needed.
+// reduced in FP64 by k_cubic.hip).  beta_prs is the cell of any one of its three
+// pairings, so only the cells of the cover are computed.
 //
 // Tiling (v_mfma_f32_32x32x16_{bf16,f16}; lane l holds A[l % 32][8 (l / 32) + i],
 // B[8 (l / 32) + i][l % 32], and accumulator register j is D[8 (j / 4) + 4 (l / 32)
@@ -27,6 +29,9 @@
 //     buffered, with the next step's global loads issued before this step's MFMAs
 //     (a step is long enough to cover the load latency).
 // Precisions
+//   FP32  : A formed in FP32 per lane, B = w M_t in FP32 in LDS; v_mfma_f32_32x32x2_f32 with
+//           pixel 8 kh + i of a substep in MFMA i; each substep's 8 MFMAs start from zero
+//           and join the running FP32 sum.
 //   BF16X3: maps staged in FP32; A = M_a M_b in FP32 split as hi = RNE bf16, lo = RNE bf16
 //           of the exact residual; Ah Bh + Ah Bl + Al Bh.
 //   F16X3 : maps scaled by exact powers of two (s_p ~ 1/sigma_p, s_w ~ npix/4pi) and staged
@@ -65,6 +70,7 @@ constexpr int BPW = 32;            // pair blocks per wave (one per lane-row)
 constexpr int MSS = KS + 4;        // map row stride in LDS (floats)
 constexpr int BSS = KS + 8;        // B row stride in LDS (16-bit)
 constexpr int BROWS = 64;          // B rows: row r <-> mode P - 64 + r (rows of negative modes are zero)
+constexpr int BSF = KS + 4;        // FP32 contexts: B row stride (floats) of the FP32 operand in the bh/bl area
 constexpr int QSTEP = kMaxP * KS / (4 * NT);   // staged pixel quads per thread per step (4)
 constexpr int CHAIN = 2;           // staged steps per MFMA accumulation chain with one wave per item
 
@@ -78,6 +84,8 @@ struct Lds {
   uint16_t bh[2][BROWS][BSS];
   uint16_t bl[2][BROWS][BSS];
 };
+// FP32 contexts keep B as floats [2][BROWS][BSF] in the bh and bl arrays
+static_assert((size_t)2 * BROWS * BSF * sizeof(float) <= 2 * sizeof(uint16_t[2][BROWS][BSS]), "FP32 B operand");
 // the sums of the waves that share an item pass through the staging area (up to 7 waves)
 static_assert(sizeof(Lds) >= (size_t)(NW - 1) * 64 * 64 * sizeof(float), "LDS too small for the wave sums");
 
@@ -166,6 +174,11 @@ __device__ inline f32x16 mfma32(const V& a, const V& b, const f32x16& c) {
                                                    0);
 }
 
+// FP32 contexts: v_mfma_f32_32x32x2_f32, lane l holding A[l % 32][l / 32] and B[l / 32][l % 32]
+__device__ inline f32x16 mfma32_f32(float a, float b, const f32x16& c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
 template <int PREC, int MULT>
 __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix, int S, int nchunk, int chunk_px,
                                                     int nblk, int nitems, int ngroups, const int4* __restrict__ blocks,
@@ -174,6 +187,10 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
                                                     const float* __restrict__ mscale, float wscale, int vec,
                                                     double* __restrict__ part) {
   constexpr bool F16 = PREC == MODAL_F16X3;
+  constexpr bool F32 = PREC == MODAL_F32;
+  // MFMA accumulation chain in staged steps: 48 MFMAs per tile for the splits (FP32
+  // contexts chain one 16-pixel substep, 8 MFMAs of K = 2, inside the substep loop)
+  constexpr int CHAIN_STEPS = CHAIN * MULT;
   constexpr int NWI = NW / MULT;          // items per workgroup
   constexpr int NSUB = KS / 16 / MULT;    // substeps of a staged step per wave
   typedef typename std::conditional<F16, f16x8, bf16x8>::type vec8;
@@ -197,11 +214,17 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
 
   if (tid < kMaxP) msc[tid] = (F16 && tid < P) ? mscale[tid] : 1.f;
   // rows of negative modes stay zero in both stages
-  for (int e = tid; e < 2 * BROWS * BSS; e += NT) {
-    const int st = e / (BROWS * BSS), r = (e / BSS) % BROWS, xx = e % BSS;
-    if (r < BROWS - P) {
-      L.bh[st][r][xx] = 0;
-      L.bl[st][r][xx] = 0;
+  float* const bf = reinterpret_cast<float*>(&L.bh[0][0][0]);   // FP32 contexts: B as [2][BROWS][BSF]
+  if constexpr (F32) {
+    for (int e = tid; e < 2 * BROWS * BSF; e += NT)
+      if ((e / BSF) % BROWS < BROWS - P) bf[e] = 0.f;
+  } else {
+    for (int e = tid; e < 2 * BROWS * BSS; e += NT) {
+      const int st = e / (BROWS * BSS), r = (e / BSS) % BROWS, xx = e % BSS;
+      if (r < BROWS - P) {
+        L.bh[st][r][xx] = 0;
+        L.bl[st][r][xx] = 0;
+      }
     }
   }
 
@@ -287,6 +310,11 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
         } else {
           *reinterpret_cast<float4*>(&L.ms[st][ms_slot(t)][sq4]) = pre[i];
         }
+        if constexpr (F32) {
+          *reinterpret_cast<float4*>(bf + ((size_t)st * BROWS + BROWS - P + t) * BSF + sq4) =
+              make_float4(wpre.x * pre[i].x, wpre.y * pre[i].y, wpre.z * pre[i].z, wpre.w * pre[i].w);
+          continue;
+        }
         split_pair<PREC>(wpre.x * sc * pre[i].x, wpre.y * sc * pre[i].y, h0, l0);
         split_pair<PREC>(wpre.z * sc * pre[i].z, wpre.w * sc * pre[i].w, h1, l1);
         *reinterpret_cast<uint2*>(&L.bh[st][BROWS - P + t][sq4]) = make_uint2(h0, h1);
@@ -347,7 +375,33 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
         else
           split_bf16(R.v[j >> 1], R.v[2 + (j & 1)], *reinterpret_cast<bf16x8*>(&ah), *reinterpret_cast<bf16x8*>(&al));
       };
-      if constexpr (!F16) {
+      if constexpr (F32) {
+        // FP32: per substep the lane's 8 pixels as 8 MFMAs of K = 2 per tile (pixel 8 kh + i
+        // in MFMA i, in A and B alike), the four tiles in turn.  Each substep's chain starts
+        // from zero and joins the running sum (twice the accumulation steps per pixel of the
+        // split forms' K = 16 tiles, so shorter chains keep the truncation of the addends
+        // small)
+#pragma unroll
+        for (int i = 0; i < NSUB; ++i) {
+          const int ks = sub * NSUB + i;
+          const float* brw = bf + ((size_t)st * BROWS + brow) * BSF + 16 * ks + 8 * kh;
+          const float4 b0 = reinterpret_cast<const float4*>(brw)[0];
+          const float4 b1 = reinterpret_cast<const float4*>(brw)[1];
+          const float bv[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+          Rows R;
+          load_rows(ks, R);
+          f32x16 ch[4];
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const float a = R.v[j >> 1][k] * R.v[2 + (j & 1)][k];
+              ch[j] = mfma32_f32(a, bv[k], k == 0 ? f32x16{} : ch[j]);
+            }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[j] += ch[j];
+        }
+      } else if constexpr (!F16) {
         // bf16: per substep, all four tiles' operands first, then the MFMAs product by product,
         // so that consecutive MFMAs feed different accumulators (measured faster than the
         // pipelined order for bf16, whose split is twice the vector work of the fp16 one)
@@ -396,7 +450,7 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
         }
       }
       }
-      if (++link == CHAIN * MULT || !more) {   // wave-uniform
+      if (!F32 && (++link == CHAIN_STEPS || !more)) {   // wave-uniform
         link = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -610,13 +664,53 @@ bool make_cubic_cover(int P, const std::vector<int>& pair_of, std::vector<int4>&
   return true;
 }
 
+namespace {
+// Pixel chunks of the contraction: a multiple of 8 of them (one chunk stream per XCD), of
+// about target pixels, in whole staged steps.
+int chunk_px_for(const modal_ctx* c, int target) {
+  int nchunk = 8 * ((c->npix + 8 * target - 1) / (8 * target));
+  int px = (c->npix + nchunk - 1) / nchunk;
+  px = (px + KS - 1) / KS * KS;
+  return px;
+}
+
+}  // namespace
+
+// FP32 accumulates its exact products in FP32, so it uses short chunks; the split
+// precisions carry a larger operand error and use long chunks (fewer partials).
+// (defaults: the autotuner's choice at lmax 1000, P 40 on MI355X)
+int chunk_target_default(const modal_ctx* c) { return c->prec == MODAL_F32 ? 4096 : 16384; }
+int chunk_target_min(const modal_ctx* c) { return c->prec == MODAL_F32 ? 2048 : 8192; }
+
+int cubic_chunk_px(const modal_ctx* c) {
+  return chunk_px_for(c, c->tune_chunk_px > 0 ? c->tune_chunk_px : chunk_target_default(c));
+}
+
+int cubic_mfma_nchunk_max(const modal_ctx* c) {
+  const int px = chunk_px_for(c, chunk_target_min(c));
+  return (c->npix + px - 1) / px;
+}
+
+// The matrix-core contraction over the triple cover serves the split and FP32 contexts
+// for every P <= kMaxP (this flag also picks their chunking); FP64 runs on the vector ALUs.
+bool cubic_mfma_available(const modal_ctx* c) {
+  return (c->prec == MODAL_F32 || c->prec == MODAL_BF16X3 || c->prec == MODAL_F16X3) && c->P <= kMaxP;
+}
+
+int cubic_mfma_nchunk(const modal_ctx* c) {
+  const int px = chunk_px_for(c, c->tune_chunk_px > 0 ? c->tune_chunk_px : chunk_target_default(c));
+  return (c->npix + px - 1) / px;
+}
+
 size_t cubic_split_lds() { return sizeof(Lds); }
 
 hipError_t cubic_split_set_lds(size_t bytes) {
   const void* fns[] = {(const void*)k_cubic_split<MODAL_BF16X3, 1>, (const void*)k_cubic_split<MODAL_BF16X3, 2>,
                        (const void*)k_cubic_split<MODAL_BF16X3, 4>, (const void*)k_cubic_split<MODAL_BF16X3, 8>,
                        (const void*)k_cubic_split<MODAL_F16X3, 1>,  (const void*)k_cubic_split<MODAL_F16X3, 2>,
-                       (const void*)k_cubic_split<MODAL_F16X3, 4>,  (const void*)k_cubic_split<MODAL_F16X3, 8>};
+                       (const void*)k_cubic_split<MODAL_F16X3, 4>,  (const void*)k_cubic_split<MODAL_F16X3, 8>,
+                       (const void*)k_cubic_split<MODAL_F32, 1>,    (const void*)k_cubic_split<MODAL_F32, 2>,
+                       (const void*)k_cubic_split<MODAL_F32, 4>,    (const void*)k_cubic_split<MODAL_F32, 8>};
   for (const void* f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
@@ -645,7 +739,7 @@ hipError_t launch_cubic_split(const modal_ctx* c, const void* maps, int S, int n
     case 4: LAUNCH(PR, 4); break; \
     default: LAUNCH(PR, 8); break; \
   }
-  if (c->prec == MODAL_F16X3) BY_MULT(MODAL_F16X3) else BY_MULT(MODAL_BF16X3)
+  if (c->prec == MODAL_F16X3) BY_MULT(MODAL_F16X3) else if (c->prec == MODAL_F32) BY_MULT(MODAL_F32) else BY_MULT(MODAL_BF16X3)
 #undef BY_MULT
 #undef LAUNCH
   return hipGetLastError();
