@@ -41,11 +41,14 @@
 //             product fits in fp16), L = fma(l_a, h_b, fma(h_a, l_b, r)),
 //           so A = H + L carries about 21 bits (the l_a l_b term, 2^-22, is dropped): four
 //           packed instructions per two products.
-// For F16X3 the substeps of 16 pixels are software-pipelined: the next substep's map rows
+// For F16X3 with one wave per item the substeps of 16 pixels are software-pipelined: the next substep's map rows
 // are read and its pair products split while this substep's MFMAs run, so that the vector
 // work issues between matrix-core instructions instead of after them (8.7 -> 8.0 ms per
 // 8-sky batch at l_max 1000, P 40 with the packed products; the same order made the bf16
 // split, twice the vector work, 3% slower, so bf16 keeps split-then-MFMA per substep).
+// With waves sharing an item (four substeps each per staged step) the pipelined registers
+// spilled (80 bytes per lane) and split-then-MFMA was faster for F16X3 too (5.35 -> 4.88 ms
+// per 8-sky batch at l_max 1000, P 40, same box).
 // The matrix core drops addend bits below the largest term of an accumulation, which
 // against a long running sum biases every step; so the MFMAs accumulate a short
 // chain of CHAIN x MULT staged steps from zero (48 MFMAs per tile whatever the number of
@@ -401,7 +404,7 @@ __global__ __launch_bounds__(NT) void k_cubic_split(int P, int npairs, int npix,
 #pragma unroll
           for (int j = 0; j < 4; ++j) acc[j] += ch[j];
         }
-      } else if constexpr (!F16) {
+      } else if constexpr (!F16 || MULT >= 2) {
         // bf16: per substep, all four tiles' operands first, then the MFMAs product by product,
         // so that consecutive MFMAs feed different accumulators (measured faster than the
         // pipelined order for bf16, whose split is twice the vector work of the fp16 one)
