@@ -164,9 +164,9 @@ int cubic_mfma_nchunk_max(const modal_ctx* c);
 // pairings of E2[S][npairs][P]); partials or E2 may be null
 hipError_t launch_reduce_symm(const modal_ctx* c, const double* partials, int S, int nchunk, double scale,
                               double* E, const double* E2, double scale2, double* out, hipStream_t st);
-// split-precision contraction on 32x32 tiles (k_cubic_split.hip): 2 x 2 pair blocks
-// sorted by b0; writes the partial sums of the needed modes t >= b only
-// cover of the triples by (block, window) cells of the split contraction; false if the plan fails
+// matrix-core contraction on 32x32 tiles (k_cubic_split.hip; FP32 and split contexts): work
+// items of 32 blocks of 2 x 2 pairs against a 32-mode window, over a cover of the triples by
+// (block, window) cells; make_cubic_cover builds it (false if the plan fails)
 bool make_cubic_cover(int P, const std::vector<int>& pair_of, std::vector<int4>& slots, std::vector<int2>& items,
                       std::vector<int>& cell, int* mult);
 size_t cubic_split_lds();
