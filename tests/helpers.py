@@ -76,4 +76,7 @@ CASES = {
     "wide48": Case("wide48", 32, 48, 96, 48, 2, "wmap", 61),
     # past the split adjoint's 48 modes: the vector pair contraction takes over
     "wide50": Case("wide50", 32, 48, 96, 50, 2, "wmap", 71),
+    # the largest mode count, P = 64: the contraction's cover takes 14 work items, two
+    # workgroup groups of 8 waves with two waves idle
+    "wide64": Case("wide64", 32, 48, 96, 64, 2, "wmap", 81),
 }
