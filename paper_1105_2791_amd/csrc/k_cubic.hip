@@ -8,7 +8,7 @@
 // lin_prs (eq. bbispect with the three pairings of the "3 C a" linear term of
 // eq. bispectrumest).
 //
-// This kernel is the FP64 path (and any precision's reference-grade path): one
+// This kernel is the FP64 path: one
 // workgroup per (pixel chunk, block of 64 pairs, map) accumulating in FP64.
 // The matrix-core path (FP32 and the splits) lives in k_cubic_split.hip and uses the
 // reduction k_reduce_single below.
@@ -137,14 +137,12 @@ hipError_t launch_reduce_single(const modal_ctx* c, const double* part, int S, i
 int cubic_nchunk(const modal_ctx* c) { return (c->npix + kChunk - 1) / kChunk; }
 
 hipError_t launch_cubic_valu(const modal_ctx* c, const void* maps, int S, double* part, hipStream_t st) {
+  // FP64 contexts only: the others contract on the matrix cores (k_cubic_split.hip)
+  if (!is_f64(c)) return hipErrorInvalidValue;
   const int nchunk = cubic_nchunk(c);
   dim3 grid(nchunk, (c->npairs + 63) / 64, S);
-  if (is_f64(c))
-    hipLaunchKernelGGL(k_cubic_valu<double>, grid, dim3(256), 0, st, c->P, c->npairs, c->npix, nchunk, c->t.pair_a,
-                       c->t.pair_b, (const double*)maps, c->t.w64, part);
-  else
-    hipLaunchKernelGGL(k_cubic_valu<float>, grid, dim3(256), 0, st, c->P, c->npairs, c->npix, nchunk, c->t.pair_a,
-                       c->t.pair_b, (const float*)maps, c->t.w32, part);
+  hipLaunchKernelGGL(k_cubic_valu<double>, grid, dim3(256), 0, st, c->P, c->npairs, c->npix, nchunk, c->t.pair_a,
+                     c->t.pair_b, (const double*)maps, c->t.w64, part);
   return hipGetLastError();
 }
 
